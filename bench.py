@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: primes tested per second at p ~ 1e11 on one MI355X.
+
+Workload (the paper's search ceiling): the primes in [1e11 - 1e6, 1e11), all
+below 2^37, each tested for both residues B_{p-3} mod p and E_{p-3} mod p with
+the congruences eqnBB30 (Section 3) and eqnEE33 (Section 5).  A step is one
+pass of the whole path over the next sub-window of `--window` consecutive
+integers of that range (about window / 25.3 primes): segmented sieve, plan,
+term sums, reductions, finalize, results copied to the host.  Warm-up steps
+take the sub-windows before the timed ones, so no step repeats work.
+
+Prints one JSON line.  `roofline` describes the term-sum kernel (the dominant
+kernel): 32-bit integer multiplies it must issue per term (two 64-bit
+Montgomery products of 40-bit operands, ten 32x32-bit products each) times the
+terms it summed, over its own HIP-event time, against the chip's int32
+multiply issue rate (256 CUs x 64 lanes x 2.4 GHz).  `cpu_baseline` is the
+plain CPU oracle timed on this host on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PAPER_V100_PRIMES_PER_S = 1.0 / (25.3e-3 + 34.1e-3)   # Section 3 and Section 5 timings at 1e11
+PEAK_INT32_MUL = 256 * 64 * 2.4e9                       # lane multiplies per second
+MULS_PER_TERM = 20                                      # 2 Montgomery products x 10 32-bit products
+
+CONFIGS = {
+    "1e11": (10 ** 11 - 10 ** 6, 10 ** 11, 8192),
+    "1e9": (10 ** 9, 10 ** 9 + 10 ** 7, 1 << 18),
+    "1e5": (5, 10 ** 5, 10 ** 5),
+}
+
+
+def cpu_threads():
+    for k in ("OMP_NUM_THREADS",):
+        v = os.environ.get(k)
+        if v and v.isdigit() and int(v) > 0:
+            return int(v)
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(primes, nthreads):
+    """The oracle as it stands: eqnBB30 + eqnEE33 evaluated plainly, one prime
+    at a time with each sum's range split over threads."""
+    import oracle
+    oracle.lib()
+    t0 = time.perf_counter()
+    for p in primes:
+        oracle.residue_one_parallel(p, method="table", nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return len(primes) / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="1e11", choices=sorted(CONFIGS))
+    ap.add_argument("--window", type=int, default=0, help="integers per step (0: config default)")
+    ap.add_argument("--chunk", type=int, default=0, help="terms per lane chunk (0: automatic)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-primes", type=int, default=1, help="primes in the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(primes shard across GPUs with no communication; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_2101_11157_amd as wv
+
+    lo0, hi0, wdef = CONFIGS[args.config]
+    W = args.window or wdef
+    nwin = args.warmup + args.steps
+    if lo0 + nwin * W > hi0 and args.config != "1e5":
+        print(f"bench.py: {nwin} windows of {W} do not fit in [{lo0}, {hi0})", file=sys.stderr)
+        sys.exit(2)
+    wins = [(lo0 + k * W, min(hi0, lo0 + (k + 1) * W)) for k in range(nwin)]
+    if args.config == "1e5":
+        wins = [(lo0, hi0)] * nwin
+
+    ctx = wv.Context(0)
+    if args.chunk:
+        ctx.set_chunk_terms(args.chunk)
+    for k in range(args.warmup):
+        ctx.search_range(*wins[k])
+        print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
+
+    primes = terms = 0
+    ms_sum = ms_dev = 0.0
+    first_timed = None
+    t0 = time.perf_counter()
+    for k in range(args.warmup, nwin):
+        res, hits = ctx.search_range(*wins[k])
+        st = ctx.stats()
+        primes += len(res)
+        terms += st["n_terms"]
+        ms_sum += st["ms_sum"]
+        ms_dev += st["ms_total"]
+        if first_timed is None and len(res):
+            first_timed = [int(res["p"][0])]
+        print(f"step {k - args.warmup}: {len(res)} primes, {st['n_terms']:.3e} terms, "
+              f"sum kernel {st['ms_sum']:.1f} ms, device {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    ctx.close()
+
+    value = primes / wall
+    achieved = MULS_PER_TERM * terms / (ms_sum * 1e-3) / 1e12
+    peak = PEAK_INT32_MUL / 1e12
+    line = {
+        "metric": "primes tested/sec at p~1e11 (1 GPU), both B_{p-3} and E_{p-3} mod p",
+        "value": value,
+        "unit": "primes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": value / PAPER_V100_PRIMES_PER_S if args.config == "1e11" else None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"primes in [{lo0}, {hi0}), sub-windows of {W} integers per step",
+            "tables": "eqnBB30+eqnEE33",
+            "primes_timed": primes,
+            "terms_timed": terms,
+            "terms_per_s": terms / wall,
+            "sum_kernel_ms": ms_sum,
+            "device_ms": ms_dev,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "Tops/s (int32 multiplies)",
+            "frac": achieved / peak,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline and first_timed:
+        sample = first_timed[: max(1, args.cpu_primes)]
+        nt = cpu_threads()
+        v, dt = cpu_baseline(sample, nt)
+        line["cpu_baseline"] = {
+            "value": v, "unit": "primes/s", "cores": nt, "kind": "oracle",
+            "sample": f"{len(sample)} prime(s) of the first timed window ({sample[0]}), "
+                      f"eqnBB30+eqnEE33 evaluated plainly, {dt:.1f} s",
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * wvprime.h -- C ABI of libwvprime.so: B_{p-3} mod p and E_{p-3} mod p for
+ * primes p on an AMD MI355X (gfx950).
+ *
+ * Method (Booker, Hathi, Mossinghoff, Trudgian, "Wolstenholme and Vandiver
+ * primes", arXiv:2101.11157):
+ *   - A prime p >= 5 is a Wolstenholme prime iff p divides the numerator of
+ *     B_{p-3} (Section 1, eqnGlaisher and the sentence after it) and a
+ *     Vandiver prime iff p divides E_{p-3} (Section 1; Euler numbers from the
+ *     EGF sec z).
+ *   - Each residue is a linear combination of sums
+ *         S(x, y) = sum_{x p < s < y p} s^-3   (Bernoulli side, Section 3)
+ *         S(x, y) = sum_{x p < s < y p} s^-2   (Euler side, Section 5)
+ *     given by one of the paper's specialised congruences (eqnBB1 ... eqnBB30,
+ *     eqnEE3 ... eqnEE33), with each sum computed as c1/c0 of
+ *     prod (z + s^3) or prod (z + s^2) (Section 3, eqnComputeS) and partial
+ *     products joined by eqnCombinePairs.
+ *
+ * Every call returns an int status: WV_OK (0) or a negative error code.  No
+ * C++ exception crosses this interface.  Calls on one context are not
+ * thread-safe: use one context per host thread, or serialise.
+ */
+#ifndef WVPRIME_H
+#define WVPRIME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define WV_OK         0
+#define WV_EINVAL    -1  /* NULL pointer where one is required, lo > hi, bad id  */
+#define WV_EDOMAIN   -2  /* p < 5 or p >= WV_P_MAX                              */
+#define WV_ENOTPRIME -3  /* a non-prime in wv_eval_primes                       */
+#define WV_ETRUNC    -4  /* caller's buffer too small; *n_out holds the need    */
+#define WV_ENOMEM    -5  /* device allocation failed (context stays valid)      */
+#define WV_EHIP      -6  /* a HIP runtime call failed (context stays valid)     */
+
+/* Largest supported prime bound (exclusive): 2^40.  The sums are computed with
+ * 64-bit Montgomery arithmetic whose intermediate bounds assume p < 2^40. */
+#define WV_P_MAX (1ULL << 40)
+
+/* Result flags. */
+#define WV_FLAG_WOLSTENHOLME 1u  /* b == 0: p | B_{p-3} */
+#define WV_FLAG_VANDIVER     2u  /* e == 0: p | E_{p-3} */
+
+/* One prime's residues.  b = B_{p-3} mod p and e = E_{p-3} mod p (Euler numbers
+ * in the secant convention), both canonical in [0, p).  The paper reports the
+ * symmetric representative in (-p/2, p/2] (Section 3, notation before Table 2);
+ * wv_symmetric() converts. */
+typedef struct {
+    uint64_t p;
+    uint64_t b;
+    uint64_t e;
+    uint32_t flags;
+    uint32_t reserved;
+} wv_result;
+
+static inline int64_t wv_symmetric(uint64_t r, uint64_t p) {
+    return r > (p - 1) / 2 ? (int64_t)r - (int64_t)p : (int64_t)r;
+}
+
+/* Congruence identifiers.  Bernoulli side (Section 3): eqnBB1, eqnBB2, eqnBB6,
+ * eqnBB9, eqnBB16, eqnBB22, eqnBB30.  Euler side (Section 5): eqnEE3, eqnEE5,
+ * eqnEE9, eqnEE16, eqnEE24, eqnEE33.  Root forms used for p = 5 and 7, where the
+ * specialised tables' left sides vanish: eqnV12 (Section 2, at k=(p-3)/2 its
+ * left side is 5 B_{p-3}) and eqnE1 (Section 4, at k=1 its left side is
+ * -4 E_{p-3}, sign read as (-1)^k). */
+enum {
+    WV_TABLE_BB1 = 0, WV_TABLE_BB2, WV_TABLE_BB6, WV_TABLE_BB9, WV_TABLE_BB16,
+    WV_TABLE_BB22, WV_TABLE_BB30,
+    WV_TABLE_EE3, WV_TABLE_EE5, WV_TABLE_EE9, WV_TABLE_EE16, WV_TABLE_EE24,
+    WV_TABLE_EE33,
+    WV_TABLE_V12, WV_TABLE_E1,
+    WV_TABLE_COUNT
+};
+
+/* Opaque context: owns device buffers, one HIP stream, events and the
+ * tuning cache.  Device memory grows on demand and is freed by wv_destroy. */
+typedef struct wv_ctx wv_ctx;
+
+/* Timings (milliseconds, HIP events on the context stream) and sizes of the
+ * most recent wv_search_range / wv_eval_primes call. */
+typedef struct {
+    double ms_total;     /* first to last event of the call (device time)        */
+    double ms_sieve;     /* segmented sieve and prime compaction (search only)   */
+    double ms_plan;      /* per-prime plan: endpoints, coefficients, chunk scan  */
+    double ms_sum;       /* term-sum kernel (the hot loop)                      */
+    double ms_reduce;    /* per-sum reduction of chunk pairs                    */
+    double ms_finalize;  /* per-prime combination, inverse, flags               */
+    uint64_t n_primes;
+    uint64_t n_sums;     /* (prime, sum) pairs                                  */
+    uint64_t n_chunks;
+    uint64_t n_terms;    /* total number of s values summed (both residues)     */
+    uint64_t n_terms_b;  /* of which Bernoulli-side terms                       */
+    uint64_t chunk_terms;/* terms per chunk used                                */
+    uint32_t block_k;    /* terms per block in the hot loop                     */
+    uint32_t grid;       /* workgroups of the term-sum launch                   */
+} wv_stats;
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle.
+ * Errors: WV_EINVAL (out NULL or bad device), WV_EHIP, WV_ENOMEM. */
+int wv_create(int hip_device, wv_ctx **out);
+
+/* Release every resource of ctx (NULL is accepted). */
+int wv_destroy(wv_ctx *ctx);
+
+/* Choose the congruences used for primes p >= 11: b_table one of the BB ids,
+ * e_table one of the EE ids.  Default: WV_TABLE_BB30 and WV_TABLE_EE33 (the
+ * cheapest printed ones, cost 227p/6480 and 27p/512).  Every valid choice gives
+ * identical residues; only the work changes.  Errors: WV_EINVAL. */
+int wv_set_tables(wv_ctx *ctx, int b_table, int e_table);
+
+/* Set the number of terms each lane sums per chunk (0 = automatic).  Must be a
+ * multiple of 64 when nonzero.  Results do not depend on it. */
+int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
+
+/* Number of primes p with 5 <= p and lo <= p < hi (segmented sieve on the
+ * device).  Errors: WV_EINVAL (n NULL, lo > hi), WV_EDOMAIN (hi > WV_P_MAX). */
+int wv_count_primes(wv_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *n);
+
+/* Every prime p with max(lo,5) <= p < hi: sieve, then residues.  out[0..n)
+ * receives the results in ascending p, where n = *n_out; if cap < n the call
+ * writes nothing, sets *n_out = n and returns WV_ETRUNC.  hits (may be NULL
+ * when hit_cap == 0) receives up to hit_cap primes whose flags are nonzero,
+ * ascending; *n_hits (may be NULL) receives their total number.  All buffers
+ * are host memory owned by the caller and not retained.
+ * Errors: WV_EINVAL, WV_EDOMAIN (hi > WV_P_MAX), WV_ETRUNC, WV_ENOMEM, WV_EHIP. */
+int wv_search_range(wv_ctx *ctx, uint64_t lo, uint64_t hi,
+                    wv_result *out, size_t cap, size_t *n_out,
+                    uint64_t *hits, size_t hit_cap, size_t *n_hits);
+
+/* Residues for n given primes (host memory), results in input order.  Each
+ * p must satisfy 5 <= p < WV_P_MAX (else WV_EDOMAIN) and be prime (checked on
+ * the host by deterministic Miller-Rabin; else WV_ENOTPRIME).  n == 0 is a
+ * no-op. */
+int wv_eval_primes(wv_ctx *ctx, const uint64_t *primes, size_t n, wv_result *out);
+
+/* Device-pointer variant: d_primes and d_out are device memory (e.g. torch
+ * tensors) of n entries; the work is enqueued on hip_stream (a hipStream_t;
+ * NULL = the legacy default stream) and the call returns without waiting.
+ * The primes are not validated: each must be a prime in [5, WV_P_MAX); a
+ * value outside that range yields a result with flags = 0xFFFFFFFF.  The
+ * caller keeps both buffers alive until the stream has passed this work.
+ * Internal buffers of ctx are in use until then: do not issue another call on
+ * ctx before synchronising hip_stream. */
+int wv_eval_primes_async(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
+                         wv_result *d_out, void *hip_stream);
+
+/* Testing aid: the individual sums S_j = sum_{x_j p < s < y_j p} s^-deg mod p
+ * (Section 2, eqnDefnS; deg 3 on the Bernoulli side, 2 on the Euler side) of
+ * the congruences the context uses for each prime, computed by the same
+ * kernels as wv_eval_primes.  out_b[i*nb + j] receives the j-th Bernoulli
+ * sum of primes[i] and out_e[i*ne + j] the j-th Euler sum, canonical in
+ * [0, p); nb and ne are the numbers of sums of the configured congruences
+ * (wv_table_info), and slots beyond the congruence used for a prime (p = 5, 7
+ * use one-sum root forms) hold 0.  Same validation as wv_eval_primes. */
+int wv_eval_sums(wv_ctx *ctx, const uint64_t *primes, size_t n, uint64_t *out_b, uint64_t *out_e);
+
+/* Statistics of the last search/eval call (synchronous calls only). */
+int wv_get_stats(const wv_ctx *ctx, wv_stats *out);
+
+/* Describe congruence `id`: number of sums, left-side multiplier and the exact
+ * cost numerator/denominator (sum of y_i - x_i).  For tests. */
+int wv_table_info(int id, int *n_sums, int64_t *lhs, uint64_t *cost_num, uint64_t *cost_den);
+
+/* Term i of congruence `id`: coefficient and the endpoints x = xa/xb, y = ya/yb. */
+int wv_table_term(int id, int i, int64_t *coef, uint32_t *xa, uint32_t *xb,
+                  uint32_t *ya, uint32_t *yb);
+
+/* Message for a status code (static storage). */
+const char *wv_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WVPRIME_H */

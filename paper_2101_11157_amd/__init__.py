@@ -1,0 +1,222 @@
+"""wvprime: B_{p-3} mod p and E_{p-3} mod p on an AMD MI355X.
+
+A thin ctypes binding over ``libwvprime.so`` (C ABI in ``include/wvprime.h``);
+every step of the computation runs in the library's HIP kernels.  The binding
+only marshals arguments.  Importing this package does not load the library:
+the first call that needs it does, and raises ``WvError`` when the built
+library is missing (build it with ``paper_2101_11157_amd.build.build()``).
+
+Method: Booker, Hathi, Mossinghoff, Trudgian, "Wolstenholme and Vandiver
+primes", arXiv:2101.11157 -- specialised congruences (Sections 3 and 5) whose
+sums of s^-3 / s^-2 are evaluated as c1/c0 of prod(z + s^k) (eqnComputeS).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwvprime.so")
+
+WV_OK = 0
+WV_EINVAL = -1
+WV_EDOMAIN = -2
+WV_ENOTPRIME = -3
+WV_ETRUNC = -4
+WV_ENOMEM = -5
+WV_EHIP = -6
+WV_P_MAX = 1 << 40
+WV_FLAG_WOLSTENHOLME = 1
+WV_FLAG_VANDIVER = 2
+
+TABLE_NAMES = ["BB1", "BB2", "BB6", "BB9", "BB16", "BB22", "BB30",
+               "EE3", "EE5", "EE9", "EE16", "EE24", "EE33", "V12", "E1"]
+TABLE_ID = {n: i for i, n in enumerate(TABLE_NAMES)}
+
+# wv_result as a numpy record (32 bytes)
+RESULT_DTYPE = np.dtype([("p", "<u8"), ("b", "<u8"), ("e", "<u8"), ("flags", "<u4"), ("reserved", "<u4")])
+
+
+class WvStats(ctypes.Structure):
+    _fields_ = [
+        ("ms_total", ctypes.c_double), ("ms_sieve", ctypes.c_double), ("ms_plan", ctypes.c_double),
+        ("ms_sum", ctypes.c_double), ("ms_reduce", ctypes.c_double), ("ms_finalize", ctypes.c_double),
+        ("n_primes", ctypes.c_uint64), ("n_sums", ctypes.c_uint64), ("n_chunks", ctypes.c_uint64),
+        ("n_terms", ctypes.c_uint64), ("n_terms_b", ctypes.c_uint64), ("chunk_terms", ctypes.c_uint64),
+        ("block_k", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class WvError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        msg = _strerror(status) if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+_lib = None
+U64 = ctypes.c_uint64
+P_U64 = ctypes.POINTER(ctypes.c_uint64)
+VP = ctypes.c_void_p
+SZ = ctypes.c_size_t
+
+
+def lib():
+    """The loaded C library (raises WvError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise WvError(WV_EHIP, f"{LIB_PATH} not built; run paper_2101_11157_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "wv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "wv_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(VP)]),
+            "wv_destroy": (ctypes.c_int, [VP]),
+            "wv_set_tables": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int]),
+            "wv_set_chunk_terms": (ctypes.c_int, [VP, U64]),
+            "wv_count_primes": (ctypes.c_int, [VP, U64, U64, P_U64]),
+            "wv_search_range": (ctypes.c_int, [VP, U64, U64, VP, SZ, ctypes.POINTER(SZ), P_U64, SZ,
+                                               ctypes.POINTER(SZ)]),
+            "wv_eval_primes": (ctypes.c_int, [VP, P_U64, SZ, VP]),
+            "wv_eval_primes_async": (ctypes.c_int, [VP, VP, SZ, VP, VP]),
+            "wv_eval_sums": (ctypes.c_int, [VP, P_U64, SZ, P_U64, P_U64]),
+            "wv_get_stats": (ctypes.c_int, [VP, ctypes.POINTER(WvStats)]),
+            "wv_table_info": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_int64), P_U64, P_U64]),
+            "wv_table_term": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                             ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _strerror(status):
+    return lib().wv_strerror(status).decode()
+
+
+def _check(status, what):
+    if status != WV_OK:
+        raise WvError(status, what)
+
+
+def table_info(name_or_id):
+    """(n_sums, lhs, cost_num, cost_den) of a congruence compiled into the library."""
+    i = TABLE_ID[name_or_id] if isinstance(name_or_id, str) else int(name_or_id)
+    n = ctypes.c_int()
+    lhs = ctypes.c_int64()
+    cn, cd = U64(), U64()
+    _check(lib().wv_table_info(i, ctypes.byref(n), ctypes.byref(lhs), ctypes.byref(cn), ctypes.byref(cd)),
+           "wv_table_info")
+    return n.value, lhs.value, cn.value, cd.value
+
+
+def table_terms(name_or_id):
+    """[(coef, xa, xb, ya, yb)] of a congruence compiled into the library."""
+    i = TABLE_ID[name_or_id] if isinstance(name_or_id, str) else int(name_or_id)
+    n = table_info(i)[0]
+    out = []
+    for j in range(n):
+        c = ctypes.c_int64()
+        v = [ctypes.c_uint32() for _ in range(4)]
+        _check(lib().wv_table_term(i, j, ctypes.byref(c), *[ctypes.byref(x) for x in v]), "wv_table_term")
+        out.append((c.value, *[x.value for x in v]))
+    return out
+
+
+def symmetric(r, p):
+    """Representative of r mod p in (-p/2, p/2]."""
+    r = int(r) % int(p)
+    return r - int(p) if r > (int(p) - 1) // 2 else r
+
+
+class Context:
+    """One wv_ctx: device buffers, a HIP stream and tuning state on one GPU."""
+
+    def __init__(self, device=0):
+        h = VP()
+        _check(lib().wv_create(int(device), ctypes.byref(h)), "wv_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wv_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_tables(self, b_table="BB30", e_table="EE33"):
+        b = TABLE_ID[b_table] if isinstance(b_table, str) else int(b_table)
+        e = TABLE_ID[e_table] if isinstance(e_table, str) else int(e_table)
+        _check(lib().wv_set_tables(self._h, b, e), "wv_set_tables")
+
+    def set_chunk_terms(self, n):
+        _check(lib().wv_set_chunk_terms(self._h, int(n)), "wv_set_chunk_terms")
+
+    def count_primes(self, lo, hi):
+        n = U64()
+        _check(lib().wv_count_primes(self._h, int(lo), int(hi), ctypes.byref(n)), "wv_count_primes")
+        return n.value
+
+    def search_range(self, lo, hi, cap=None, hit_cap=1024):
+        """Results (numpy RESULT_DTYPE, ascending p) and the hit list for [lo, hi)."""
+        if cap is None:
+            cap = self.count_primes(lo, hi)
+        out = np.zeros(max(1, cap), dtype=RESULT_DTYPE)
+        hits = np.zeros(max(1, hit_cap), dtype=np.uint64)
+        n_out, n_hits = SZ(), SZ()
+        st = lib().wv_search_range(self._h, int(lo), int(hi), out.ctypes.data_as(VP), cap, ctypes.byref(n_out),
+                                   hits.ctypes.data_as(P_U64), hit_cap, ctypes.byref(n_hits))
+        _check(st, "wv_search_range")
+        return out[:n_out.value], hits[:min(n_hits.value, hit_cap)]
+
+    def eval_primes(self, primes):
+        """Results (numpy RESULT_DTYPE) for the given primes, input order."""
+        arr = np.ascontiguousarray(np.asarray(primes, dtype=np.uint64))
+        out = np.zeros(max(1, arr.size), dtype=RESULT_DTYPE)
+        st = lib().wv_eval_primes(self._h, arr.ctypes.data_as(P_U64), arr.size, out.ctypes.data_as(VP))
+        _check(st, "wv_eval_primes")
+        return out[:arr.size]
+
+    def eval_sums(self, primes, nb, ne):
+        """Per-sum values S_j for the configured congruences: arrays (n, nb) and (n, ne)."""
+        arr = np.ascontiguousarray(np.asarray(primes, dtype=np.uint64))
+        ob = np.zeros((max(1, arr.size), nb), dtype=np.uint64)
+        oe = np.zeros((max(1, arr.size), ne), dtype=np.uint64)
+        st = lib().wv_eval_sums(self._h, arr.ctypes.data_as(P_U64), arr.size, ob.ctypes.data_as(P_U64),
+                                oe.ctypes.data_as(P_U64))
+        _check(st, "wv_eval_sums")
+        return ob[:arr.size], oe[:arr.size]
+
+    def eval_primes_async(self, d_primes_ptr, n, d_out_ptr, stream_ptr=0):
+        """Enqueue on a HIP stream with device pointers (e.g. torch tensor data_ptr())."""
+        st = lib().wv_eval_primes_async(self._h, VP(d_primes_ptr), int(n), VP(d_out_ptr),
+                                        VP(stream_ptr) if stream_ptr else None)
+        _check(st, "wv_eval_primes_async")
+
+    def stats(self):
+        s = WvStats()
+        _check(lib().wv_get_stats(self._h, ctypes.byref(s)), "wv_get_stats")
+        return s.as_dict()

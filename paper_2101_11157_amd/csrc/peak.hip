@@ -1,0 +1,114 @@
+// peak.hip -- instruction-rate microbenchmark for the roofline of the term-sum
+// kernel (libwvpeak.so, C ABI: wv_peak_rates).
+//
+// Each kernel runs NCHAIN independent dependency chains of one VALU
+// instruction class per lane, so issue rate (not latency) bounds it.  The
+// instruction each loop body compiles to is checked in the gfx950 assembly of
+// this file (v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32, v_mul_u32_u24,
+// v_add_u32, v_lshl_add_u64, v_fma_f64).
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace {
+
+constexpr int NCHAIN = 8;
+constexpr int UNROLL = 16;
+
+// Each loop body issues exactly one instance of the measured instruction per
+// chain (inline asm, so the compiler can neither fold nor reorder the chain).
+#define WV_PEAK_KERNEL(NAME, T, INIT, ASM, ...)                                        \
+    __global__ void __launch_bounds__(256) NAME(uint64_t *out, uint32_t a, int iters) { \
+        T x[NCHAIN];                                                                   \
+        const T b = (T)(a | 1u) + (T)threadIdx.x;                                      \
+        for (int c = 0; c < NCHAIN; c++) x[c] = INIT;                                  \
+        for (int it = 0; it < iters; it++) {                                           \
+            _Pragma("unroll") for (int u = 0; u < UNROLL; u++)                         \
+            _Pragma("unroll") for (int c = 0; c < NCHAIN; c++) {                       \
+                asm volatile(ASM : __VA_ARGS__);                                       \
+            }                                                                          \
+        }                                                                              \
+        uint64_t s = 0;                                                                \
+        for (int c = 0; c < NCHAIN; c++) s ^= (uint64_t)x[c];                          \
+        out[blockIdx.x * blockDim.x + threadIdx.x] = s;                                \
+    }
+
+WV_PEAK_KERNEL(k_mullo, uint32_t, threadIdx.x + c + 1, "v_mul_lo_u32 %0, %0, %1", "+v"(x[c]) : "v"(b))
+WV_PEAK_KERNEL(k_mulhi, uint32_t, threadIdx.x * 2654435761u + c, "v_mul_hi_u32 %0, %0, %1", "+v"(x[c]) : "v"(b))
+WV_PEAK_KERNEL(k_mul24, uint32_t, threadIdx.x + c + 1, "v_mul_u32_u24 %0, %0, %1", "+v"(x[c]) : "v"(b))
+WV_PEAK_KERNEL(k_add32, uint32_t, threadIdx.x + c, "v_add_u32 %0, %0, %1", "+v"(x[c]) : "v"(b))
+WV_PEAK_KERNEL(k_add64, uint64_t, threadIdx.x + c, "v_lshl_add_u64 %0, %0, 0, %1", "+v"(x[c]) : "v"(b))
+
+__global__ void __launch_bounds__(256) k_mad64(uint64_t *out, uint32_t a, int iters) {
+    uint64_t x[NCHAIN];
+    const uint32_t b = (a | 1u) + threadIdx.x;
+    for (int c = 0; c < NCHAIN; c++) x[c] = threadIdx.x + c;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; u++)
+#pragma unroll
+            for (int c = 0; c < NCHAIN; c++) x[c] = (uint64_t)(uint32_t)x[c] * b + x[c];
+    }
+    uint64_t s = 0;
+    for (int c = 0; c < NCHAIN; c++) s ^= x[c];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_fma64(uint64_t *out, uint32_t a, int iters) {
+    double x[NCHAIN];
+    const double m = 1.0 + 1e-9 * (double)(a & 7), d = 1e-7;
+    for (int c = 0; c < NCHAIN; c++) x[c] = (double)(threadIdx.x + c);
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; u++)
+#pragma unroll
+            for (int c = 0; c < NCHAIN; c++) x[c] = fma(x[c], m, d);
+    }
+    double s = 0;
+    for (int c = 0; c < NCHAIN; c++) s += x[c];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = (uint64_t)s;
+}
+
+typedef void (*kfn)(uint64_t *, uint32_t, int);
+
+}  // namespace
+
+extern "C" {
+
+// Measures lane-operations per second for each instruction class on device
+// `dev`: rates[0..6] = v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32,
+// v_mul_u32_u24, v_add_u32, 64-bit add, v_fma_f64.  Each rate counts one
+// instruction per lane as one operation.  Returns 0 on success.
+int wv_peak_rates(int dev, double *rates) {
+    if (!rates) return -1;
+    if (hipSetDevice(dev) != hipSuccess) return -6;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -6;
+    const int blocks = prop.multiProcessorCount * 16;
+    const int threads = 256;
+    const int iters = 2048;
+    uint64_t *buf = nullptr;
+    if (hipMalloc(&buf, (size_t)blocks * threads * sizeof(uint64_t)) != hipSuccess) return -5;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -6;
+    kfn ks[7] = {k_mad64, k_mullo, k_mulhi, k_mul24, k_add32, k_add64, k_fma64};
+    // instructions of the measured class per lane per loop-body instance
+    const double per[7] = {1, 1, 1, 1, 1, 1, 1};
+    int rc = 0;
+    for (int k = 0; k < 7 && rc == 0; k++) {
+        hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(threads), 0, 0, buf, 12345u, 16);   // warm-up
+        (void)hipEventRecord(e0, 0);
+        hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(threads), 0, 0, buf, 12345u, iters);
+        (void)hipEventRecord(e1, 0);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = -6; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double ops = (double)blocks * threads * iters * UNROLL * NCHAIN * per[k];
+        rates[k] = ops / (ms * 1e-3);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Host-side unit test of the device arithmetic (mont.hpp) and of the per-lane
+// hot loop (sum_core.hpp) against unsigned __int128 products and %.
+// Prints "OK <checks>" or the first failure.
+#include <cstdint>
+#include <cstdio>
+#include <random>
+#include <vector>
+#include "mont.hpp"
+#include "sum_core.hpp"
+
+using u128 = unsigned __int128;
+using namespace wv;
+
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((u128)a * b % p); }
+static uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
+    uint64_t r = 1;
+    a %= p;
+    while (e) { if (e & 1) r = mulmod(r, a, p); a = mulmod(a, a, p); e >>= 1; }
+    return r;
+}
+
+int main() {
+    std::mt19937_64 rng(12345);
+    // odd moduli (primality is not needed for the Montgomery identities)
+    std::vector<uint64_t> ps = {11, 13, 101, 65537, 1000003, 998244353, 4294967291ull, 4294967311ull,
+                                99999999977ull, 100000000003ull, (1ull << 40) - 87, (1ull << 40) - 1,
+                                (1ull << 39) + 1, (1ull << 32) + 15, (1ull << 20) + 7, (1ull << 19) + 21};
+    for (int i = 0; i < 40; i++) ps.push_back((rng() % ((1ull << 40) - 11)) | 1ull);
+    long checks = 0;
+    for (uint64_t p : ps) {
+        if (p < 11) continue;
+        Mont m = make_mont(p);
+        if ((uint32_t)(m.ninv * (uint32_t)p) != 0xFFFFFFFFu) { printf("FAIL ninv p=%llu\n", (unsigned long long)p); return 1; }
+        const uint64_t Rm = (uint64_t)(((u128)1 << 64) % p);
+        const uint64_t R2 = mulmod(Rm, Rm, p);
+        if (r_mod(p) != Rm || r2_mod(p) != R2) { printf("FAIL R p=%llu\n", (unsigned long long)p); return 1; }
+        // R^-1 mod p via the extended identity: mmul(x, 1) == x R^-1
+        auto check = [&](uint64_t a, uint64_t b) {
+            // lazy inputs up to 4p
+            uint64_t r = mmul(a, b, m);
+            // r * R == a * b (mod p) and r < 2p
+            uint64_t lhs = mulmod(r % p, Rm, p), rhs = mulmod(a % p, b % p, p);
+            if (lhs != rhs || r >= 2 * p) {
+                printf("FAIL mmul p=%llu a=%llu b=%llu r=%llu\n", (unsigned long long)p, (unsigned long long)a,
+                       (unsigned long long)b, (unsigned long long)r);
+                return false;
+            }
+            checks++;
+            return true;
+        };
+        const uint64_t edge[] = {0, 1, 2, p - 1, p, p + 1, 2 * p - 1, 2 * p, 3 * p, 4 * p - 1, Rm, R2};
+        for (uint64_t a : edge)
+            for (uint64_t b : edge)
+                if (!check(a, b)) return 1;
+        for (int k = 0; k < 20000; k++) {
+            uint64_t a = rng() % (4 * p), b = rng() % (4 * p);
+            if (!check(a, b)) return 1;
+        }
+        // addm / subm / to_mont / from_mont / mpow
+        for (int k = 0; k < 2000; k++) {
+            uint64_t a = rng() % p, b = rng() % p;
+            if (addm(a, b, p) != (uint64_t)(((u128)a + b) % p)) { printf("FAIL addm\n"); return 1; }
+            if (subm(a, b, p) != (uint64_t)(((u128)a + p - b) % p)) { printf("FAIL subm\n"); return 1; }
+            uint64_t aR = to_mont(a, R2, m);
+            if (aR != mulmod(a, Rm, p)) { printf("FAIL to_mont\n"); return 1; }
+            if (from_mont(aR, m) != a) { printf("FAIL from_mont\n"); return 1; }
+            uint64_t e = rng() % p;
+            uint64_t pw = mpow(aR, e, Rm, m) % p;
+            if (pw != mulmod(powmod(a, e, p), Rm, p)) { printf("FAIL mpow\n"); return 1; }
+            checks += 5;
+        }
+        // pair product: ratio c1/c0 of a product equals the sum of the ratios
+        for (int k = 0; k < 500; k++) {
+            uint64_t c0 = 1 + rng() % (p - 1), c1 = rng() % (4 * p), d0 = 1 + rng() % (p - 1), d1 = rng() % (4 * p);
+            uint64_t e0 = c0, e1 = c1;
+            pair_mul(e0, e1, d0, d1, m);
+            // e0 R == c0 d0, e1 R == c0 d1 + c1 d0
+            if (mulmod(e0 % p, Rm, p) != mulmod(c0, d0, p) ||
+                mulmod(e1 % p, Rm, p) != (mulmod(c0, d1 % p, p) + mulmod(c1 % p, d0, p)) % p ||
+                e0 >= 2 * p || e1 >= 4 * p) {
+                printf("FAIL pair_mul p=%llu\n", (unsigned long long)p);
+                return 1;
+            }
+            checks++;
+        }
+    }
+    // the hot loop: (c0, c1) of prod (z + s^deg) over s0 .. s0+n-1, written out
+    for (uint64_t p : ps) {
+        if (p < 11) continue;
+        Mont m = make_mont(p);
+        const uint64_t R2 = r2_mod(p), Rm = r_mod(p);
+        for (int k = 0; k < 12; k++) {
+            uint64_t s0 = 1 + rng() % (p - 1);
+            uint64_t n = rng() % 300;
+            if (k == 0) n = 0;
+            if (k == 1) { s0 = p - 1; n = 1; }
+            if (k == 2 && p > 1000) { s0 = p - 200; n = 199; }
+            if (s0 + n > p) n = p - s0;   // keep every s in (0, p)
+            for (int deg = 2; deg <= 3; deg++) {
+                uint64_t c0, c1;
+                if (deg == 3) run_chunk<3>(s0, n, m, R2, Rm, c0, c1);
+                else run_chunk<2>(s0, n, m, R2, Rm, c0, c1);
+                uint64_t e0 = 1, e1 = 0;
+                for (uint64_t s = s0; s < s0 + n; s++) {
+                    uint64_t u = powmod(s, deg, p);
+                    e1 = (mulmod(e1, u, p) + e0) % p;
+                    e0 = mulmod(e0, u, p);
+                }
+                if (c0 % p != e0 || c1 % p != e1 || c0 >= 2 * p || c1 >= 4 * p) {
+                    printf("FAIL run_chunk<%d> p=%llu s0=%llu n=%llu\n", deg, (unsigned long long)p,
+                           (unsigned long long)s0, (unsigned long long)n);
+                    return 1;
+                }
+                checks++;
+            }
+        }
+    }
+    // chunk -> sum lookup skips empty sums
+    {
+        const uint64_t off[] = {0, 0, 3, 3, 3, 7, 8, 8};   // 7 sums, total 8 chunks
+        const uint32_t want[] = {1, 1, 1, 4, 4, 4, 4, 5};
+        for (uint64_t c = 0; c < 8; c++)
+            if (find_seg(off, 7, c) != want[c]) { printf("FAIL find_seg %llu\n", (unsigned long long)c); return 1; }
+        checks += 8;
+    }
+    printf("OK %ld\n", checks);
+    return 0;
+}

@@ -1,0 +1,348 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle and the
+paper's printed values.  Bit-exact: every residue is an integer in [0, p)."""
+import json
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2101_11157_amd as wv
+import oracle
+from oracle import exact
+from conftest import GOLDEN, read_golden
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not os.path.exists(wv.LIB_PATH):
+        pytest.fail("libwvprime.so is not built: the HIP path must be present on a GPU box")
+    c = wv.Context(0)
+    yield c
+    c.close()
+
+
+def golden_json(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def as_pairs(res):
+    return [(int(r["b"]), int(r["e"])) for r in res]
+
+
+def check_against_oracle(res, method="root"):
+    ps = [int(p) for p in res["p"]]
+    want = oracle.residues(ps, method=method)
+    got = as_pairs(res)
+    bad = [(p, g, w) for p, g, w in zip(ps, got, want) if g != w]
+    assert not bad, f"{len(bad)} mismatches, first {bad[:5]}"
+    for r, (b, e) in zip(res, want):
+        f = (1 if b == 0 else 0) | (2 if e == 0 else 0)
+        assert int(r["flags"]) == f
+
+
+def test_small_window_all_primes(ctx):
+    """All primes 5 <= p < 1e5 (9590 primes) against the oracle, and the hits."""
+    say("case: search_range(5, 1e5)")
+    res, hits = ctx.search_range(5, 10 ** 5)
+    assert len(res) == 9590
+    assert list(res["p"]) == oracle.primes(5, 10 ** 5)
+    check_against_oracle(res)
+    assert list(hits) == [149, 241, 16843]
+    st = ctx.stats()
+    assert st["n_primes"] == 9590 and st["ms_sum"] > 0
+
+
+def test_paper_tables_2_and_3(ctx):
+    """Printed symmetric residues of Tables 2 and 3 (43 primes up to 7.8e10)."""
+    say("case: Tables 2 and 3")
+    for name, key in (("near_miss_B.txt", "b"), ("near_miss_E.txt", "e")):
+        rows = [(int(p), int(r)) for p, r in read_golden(name)]
+        res = ctx.eval_primes([p for p, _ in rows])
+        for (p, r), out in zip(rows, res):
+            assert int(out["p"]) == p
+            assert wv.symmetric(out[key], p) == r, (name, p, int(out[key]))
+
+
+def test_theorem_1_1_hits(ctx):
+    say("case: Theorem 1.1 primes")
+    rows = read_golden("known_primes.txt")
+    ps = sorted({int(p) for _, p in rows})
+    res = {int(r["p"]): r for r in ctx.eval_primes(ps)}
+    for kind, p in rows:
+        f = int(res[int(p)]["flags"])
+        if kind == "wolstenholme":
+            assert f & wv.WV_FLAG_WOLSTENHOLME, p
+        elif kind == "vandiver":
+            assert f & wv.WV_FLAG_VANDIVER, p
+        elif kind == "not_vandiver":
+            assert not f & wv.WV_FLAG_VANDIVER, p
+
+
+def test_smallest_primes_and_edges(ctx):
+    say("case: p = 5 .. 101 and argument edges")
+    ps = oracle.primes(5, 102)
+    res = ctx.eval_primes(ps)
+    assert as_pairs(res) == [(oracle.bernoulli_rec(p), oracle.euler_rec(p)) for p in ps]
+    assert as_pairs(res[:2]) == [(1, 1), (3, 5)]
+    r, _ = ctx.search_range(0, 20)
+    assert list(r["p"]) == [5, 7, 11, 13, 17, 19]
+    assert len(ctx.search_range(24, 29)[0]) == 0        # no prime in [24, 29)
+    assert len(ctx.search_range(5, 5)[0]) == 0
+    assert len(ctx.eval_primes([])) == 0
+    # short output buffer
+    with pytest.raises(wv.WvError) as ei:
+        ctx.search_range(5, 100, cap=3)
+    assert ei.value.status == wv.WV_ETRUNC
+    for bad, code in (([3], wv.WV_EDOMAIN), ([2 ** 40 + 15], wv.WV_EDOMAIN), ([9], wv.WV_ENOTPRIME),
+                      ([1000003 * 1000033], wv.WV_ENOTPRIME)):
+        with pytest.raises(wv.WvError) as ei:
+            ctx.eval_primes(bad)
+        assert ei.value.status == code
+    with pytest.raises(wv.WvError) as ei:
+        ctx.count_primes(10, 5)
+    assert ei.value.status == wv.WV_EINVAL
+    with pytest.raises(wv.WvError) as ei:
+        ctx.count_primes(0, 2 ** 40 + 1)
+    assert ei.value.status == wv.WV_EDOMAIN
+
+
+def test_ragged_batches(ctx):
+    """Batch sizes that leave partial waves and workgroups; input order kept."""
+    say("case: ragged batches")
+    pool = oracle.primes(10 ** 6, 10 ** 6 + 40000)
+    rng = random.Random(3)
+    for n in (1, 63, 65, 257, 1000):
+        ps = rng.sample(pool, n)
+        res = ctx.eval_primes(ps)
+        assert [int(x) for x in res["p"]] == ps
+        check_against_oracle(res)
+
+
+@pytest.mark.parametrize("chunk", [64, 192, 4096, 1 << 20])
+def test_chunk_size_invariance(ctx, chunk):
+    say(f"case: chunk {chunk}")
+    ps = oracle.primes(10 ** 7, 10 ** 7 + 3000) + [1025793739, 73607557631]
+    ref = ctx.eval_primes(ps)
+    try:
+        ctx.set_chunk_terms(chunk)
+        got = ctx.eval_primes(ps)
+    finally:
+        ctx.set_chunk_terms(0)
+    assert as_pairs(got) == as_pairs(ref)
+
+
+def test_first_sum_spans_many_waves(ctx):
+    """Regression: a batch whose very first sum covers far more than 64 chunks
+    (every wave of it takes the single-sum butterfly path from chunk 0 on).
+    The term-sum loop once read its wave-uniform chunk base through a vector
+    shuffle, and the compiler's per-lane loop split then left lanes 1..63
+    re-reading a stale base from the parked lane 0 forever."""
+    say("case: first sum of 14k chunks")
+    ps = [1000000007, 1000000009]
+    try:
+        ctx.set_chunk_terms(64)
+        got = ctx.eval_primes(ps)
+        st = ctx.stats()
+    finally:
+        ctx.set_chunk_terms(0)
+    assert st["chunk_terms"] == 64 and st["n_chunks"] > 64 * 63
+    assert as_pairs(got) == oracle.residues(ps, method="table")
+
+
+def test_cross_table_agreement(ctx):
+    """Every Bernoulli table with every Euler table gives the same residues."""
+    say("case: cross-table agreement")
+    ps = oracle.primes(11, 3000)[::7] + oracle.primes(10 ** 8, 10 ** 8 + 2000)[:40] + [16843, 2124679]
+    ref = None
+    try:
+        for b in ("BB1", "BB2", "BB6", "BB9", "BB16", "BB22", "BB30"):
+            for e in ("EE3", "EE5", "EE9", "EE16", "EE24", "EE33"):
+                ctx.set_tables(b, e)
+                got = as_pairs(ctx.eval_primes(ps))
+                if ref is None:
+                    ref = got
+                assert got == ref, (b, e)
+    finally:
+        ctx.set_tables("BB30", "EE33")
+    assert ref == oracle.residues(ps)
+
+
+def test_window_1e9_sample(ctx):
+    """Seeded sample of the primes in [1e9, 1e9 + 1e7) against stored oracle values."""
+    g = golden_json("window_1e9.json")
+    say(f"case: window 1e9, {len(g['rows'])} sampled primes")
+    ps = [r["p"] for r in g["rows"]]
+    res = ctx.eval_primes(ps)
+    assert as_pairs(res) == [(r["b"], r["e"]) for r in g["rows"]]
+    assert ctx.count_primes(g["lo"], g["hi"]) == g["n_primes"]
+
+
+def test_window_1e9_search_subwindow(ctx):
+    """The sieve and the whole path on [1e9, 1e9 + 2^19): primes equal the plain
+    sieve's, stored samples inside it match, and a fresh oracle sample matches."""
+    lo, hi = 10 ** 9, 10 ** 9 + (1 << 19)
+    say(f"case: search_range({lo}, {hi})")
+    res, _ = ctx.search_range(lo, hi)
+    assert [int(p) for p in res["p"]] == oracle.primes(lo, hi)
+    g = golden_json("window_1e9.json")
+    by_p = {int(r["p"]): r for r in res}
+    inside = [r for r in g["rows"] if r["p"] < hi]
+    assert inside
+    for r in inside:
+        assert (int(by_p[r["p"]]["b"]), int(by_p[r["p"]]["e"])) == (r["b"], r["e"])
+    pick = random.Random(5).sample(list(range(len(res))), 6)
+    check_against_oracle(res[sorted(pick)], method="table")
+
+
+def test_window_1e11_sample(ctx):
+    """Seeded sample of [1e11 - 1e6, 1e11) (p < 2^37) against stored oracle values."""
+    g = golden_json("window_1e11.json")
+    say(f"case: window 1e11, {len(g['rows'])} sampled primes")
+    ps = [r["p"] for r in g["rows"]]
+    res = ctx.eval_primes(ps)
+    assert as_pairs(res) == [(r["b"], r["e"]) for r in g["rows"]]
+    assert ctx.count_primes(g["lo"], g["hi"]) == g["n_primes"]
+
+
+def test_top_of_range_sums(ctx):
+    """Largest primes below 2^40: single sums against stored oracle values."""
+    g = golden_json("sums_2p40.json")
+    ps = sorted({r["p"] for r in g["rows"]})
+    say(f"case: sums at {ps}")
+    nb, ne = wv.table_info("BB30")[0], wv.table_info("EE33")[0]
+    sb, se = ctx.eval_sums(ps, nb, ne)
+    for r in g["rows"]:
+        i = ps.index(r["p"])
+        got = sb[i, r["term"]] if r["table"] == "BB30" else se[i, r["term"]]
+        assert int(got) == r["S"], r
+
+
+def test_sums_small_primes_direct(ctx):
+    """Per-sum values for small primes against sums of inverses written out."""
+    ps = oracle.primes(11, 400) + [10007, 65537]
+    nb, ne = wv.table_info("BB30")[0], wv.table_info("EE33")[0]
+    sb, se = ctx.eval_sums(ps, nb, ne)
+    from oracle import congruences as C
+    for i, p in enumerate(ps):
+        for cong, arr in ((C.BB30, sb), (C.EE33, se)):
+            for j, (_, x, y) in enumerate(cong.terms):
+                lo, hi = oracle.interval(p, x, y)
+                assert int(arr[i, j]) == oracle.sum_direct(p, lo, hi, -cong.ell), (p, cong.name, j)
+
+
+class Hip:
+    """Minimal HIP runtime calls through ctypes (the runtime the library already loaded)."""
+
+    def __init__(self):
+        import ctypes
+        self.ct = ctypes
+        wv.lib()
+        self.h = ctypes.CDLL("libamdhip64.so.7")
+        self.h.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+        self.h.hipFree.argtypes = [ctypes.c_void_p]
+        self.h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        self.h.hipStreamCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.h.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+        self.h.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+
+    def malloc(self, n):
+        p = self.ct.c_void_p()
+        assert self.h.hipMalloc(self.ct.byref(p), n) == 0
+        return p.value
+
+    def h2d(self, dst, arr):
+        assert self.h.hipMemcpy(dst, arr.ctypes.data, arr.nbytes, 1) == 0
+
+    def d2h(self, arr, src):
+        assert self.h.hipMemcpy(arr.ctypes.data, src, arr.nbytes, 2) == 0
+
+
+def test_async_device_pointers(ctx):
+    """Device-pointer entry point on a caller's stream equals the host entry point,
+    including a rejected input (flags 0xFFFFFFFF) in the middle of the batch."""
+    hip = Hip()
+    ps = oracle.primes(3 * 10 ** 6, 3 * 10 ** 6 + 20000)
+    ref = ctx.eval_primes(ps)
+    arr = np.array(ps[:100] + [4] + ps[100:], dtype=np.uint64)
+    d_in = hip.malloc(arr.nbytes)
+    d_out = hip.malloc(arr.size * wv.RESULT_DTYPE.itemsize)
+    st = hip.ct.c_void_p()
+    assert hip.h.hipStreamCreate(hip.ct.byref(st)) == 0
+    try:
+        hip.h2d(d_in, arr)
+        ctx.eval_primes_async(d_in, arr.size, d_out, st.value)
+        assert hip.h.hipStreamSynchronize(st) == 0
+        got = np.zeros(arr.size, dtype=wv.RESULT_DTYPE)
+        hip.d2h(got, d_out)
+    finally:
+        hip.h.hipStreamDestroy(st)
+        hip.h.hipFree(d_in)
+        hip.h.hipFree(d_out)
+    assert int(got[100]["flags"]) == 0xFFFFFFFF
+    got = np.concatenate([got[:100], got[101:]])
+    assert [int(x) for x in got["p"]] == ps
+    assert as_pairs(got) == as_pairs(ref)
+    assert list(got["flags"]) == list(ref["flags"])
+
+
+TORCH_INTEROP = r"""
+import sys, numpy as np
+import torch                      # torch first: one HIP runtime in the process
+assert torch.cuda.is_available(), "torch sees no GPU"
+sys.path.insert(0, sys.argv[1])
+import paper_2101_11157_amd as wv, oracle
+ps = oracle.primes(3 * 10 ** 6, 3 * 10 ** 6 + 5000)
+with wv.Context(0) as ctx:
+    ref = ctx.eval_primes(ps)
+    d_in = torch.tensor(np.array(ps, dtype=np.int64), device="cuda:0")
+    d_out = torch.zeros((len(ps), 4), dtype=torch.int64, device="cuda:0")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx.eval_primes_async(d_in.data_ptr(), len(ps), d_out.data_ptr(), s.cuda_stream)
+    s.synchronize()
+    got = d_out.cpu().numpy().view(np.uint64)
+    assert [int(x) for x in got[:, 0]] == ps
+    assert [(int(b), int(e)) for b, e in got[:, 1:3]] == [(int(r["b"]), int(r["e"])) for r in ref]
+print("torch interop ok")
+"""
+
+
+def test_torch_stream_interop():
+    """torch tensors and a torch stream as the async entry point's memory and stream
+    (a fresh process that imports torch before the library)."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    probe = subprocess.run([sys.executable, "-c", "import torch; print(torch.cuda.is_available())"],
+                           capture_output=True, text=True, timeout=300)
+    if probe.stdout.strip() != "True":
+        pytest.skip("torch does not see the GPU in this environment: " + (probe.stdout + probe.stderr)[-300:])
+    r = subprocess.run([sys.executable, "-c", TORCH_INTEROP, root], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "torch interop ok" in r.stdout
+
+
+def test_determinism_repeat(ctx):
+    ps = oracle.primes(10 ** 10, 10 ** 10 + 1500)
+    a = ctx.eval_primes(ps)
+    b = ctx.eval_primes(ps)
+    assert as_pairs(a) == as_pairs(b)
+
+
+def test_paper_prime_count(ctx):
+    """Section 3, Results: 4118054811 primes p with 5 <= p < 1e11."""
+    say("case: count_primes(5, 1e11)")
+    assert ctx.count_primes(5, 10 ** 11) == 4118054811
+    c = golden_json("counts.json")
+    for k, v in c.items():
+        lo, hi = map(int, k.split(","))
+        assert ctx.count_primes(lo, hi) == v, k
