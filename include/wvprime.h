@@ -97,8 +97,10 @@ typedef struct {
     uint64_t n_terms;    /* total number of s values summed (both residues)     */
     uint64_t n_terms_b;  /* of which Bernoulli-side terms                       */
     uint64_t chunk_terms;/* terms per chunk used                                */
-    uint32_t block_k;    /* terms per block in the hot loop                     */
+    uint32_t block_k_b;  /* terms per block in the hot loop, Bernoulli side    */
+    uint32_t block_k_e;  /* terms per block in the hot loop, Euler side        */
     uint32_t grid;       /* workgroups of the term-sum launch                   */
+    uint32_t reserved;
 } wv_stats;
 
 /* Create a context on HIP device `hip_device`.  *out receives the handle.
@@ -117,6 +119,14 @@ int wv_set_tables(wv_ctx *ctx, int b_table, int e_table);
 /* Set the number of terms each lane sums per chunk (0 = automatic).  Must be a
  * multiple of 64 when nonzero.  Results do not depend on it. */
 int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
+
+/* Choose the block shape of the term-sum kernel: kb terms per block on the
+ * Bernoulli side and ke on the Euler side (compiled shapes: 1/1, 4/4, 8/8,
+ * 8/16, 16/8, 16/16; default 8/8).  Each block of k consecutive s is folded
+ * into the running pair as one factor of eqnCombinePairs whose two members
+ * are stepped by finite differences.  Results do not depend on the shape.
+ * Errors: WV_EINVAL for a shape that is not compiled. */
+int wv_set_block(wv_ctx *ctx, int kb, int ke);
 
 /* Number of primes p with 5 <= p and lo <= p < hi (segmented sieve on the
  * device).  Errors: WV_EINVAL (n NULL, lo > hi), WV_EDOMAIN (hi > WV_P_MAX). */

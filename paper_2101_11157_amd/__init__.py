@@ -43,11 +43,12 @@ class WvStats(ctypes.Structure):
         ("ms_sum", ctypes.c_double), ("ms_reduce", ctypes.c_double), ("ms_finalize", ctypes.c_double),
         ("n_primes", ctypes.c_uint64), ("n_sums", ctypes.c_uint64), ("n_chunks", ctypes.c_uint64),
         ("n_terms", ctypes.c_uint64), ("n_terms_b", ctypes.c_uint64), ("chunk_terms", ctypes.c_uint64),
-        ("block_k", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+        ("block_k_b", ctypes.c_uint32), ("block_k_e", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class WvError(RuntimeError):
@@ -77,6 +78,7 @@ def lib():
             "wv_destroy": (ctypes.c_int, [VP]),
             "wv_set_tables": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int]),
             "wv_set_chunk_terms": (ctypes.c_int, [VP, U64]),
+            "wv_set_block": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int]),
             "wv_count_primes": (ctypes.c_int, [VP, U64, U64, P_U64]),
             "wv_search_range": (ctypes.c_int, [VP, U64, U64, VP, SZ, ctypes.POINTER(SZ), P_U64, SZ,
                                                ctypes.POINTER(SZ)]),
@@ -174,6 +176,9 @@ class Context:
 
     def set_chunk_terms(self, n):
         _check(lib().wv_set_chunk_terms(self._h, int(n)), "wv_set_chunk_terms")
+
+    def set_block(self, kb, ke):
+        _check(lib().wv_set_block(self._h, int(kb), int(ke)), "wv_set_block")
 
     def count_primes(self, lo, hi):
         n = U64()

@@ -12,11 +12,13 @@
 #include <cstdint>
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
+#define WV_UNROLL _Pragma("unroll")
 #else
 // Plain C++ build of the same arithmetic, for host-side unit tests.
 #define __host__
 #define __device__
 #define __forceinline__ inline
+#define WV_UNROLL
 #endif
 
 namespace wv {

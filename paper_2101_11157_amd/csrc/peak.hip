@@ -37,6 +37,13 @@ WV_PEAK_KERNEL(k_mulhi, uint32_t, threadIdx.x * 2654435761u + c, "v_mul_hi_u32 %
 WV_PEAK_KERNEL(k_mul24, uint32_t, threadIdx.x + c + 1, "v_mul_u32_u24 %0, %0, %1", "+v"(x[c]) : "v"(b))
 WV_PEAK_KERNEL(k_add32, uint32_t, threadIdx.x + c, "v_add_u32 %0, %0, %1", "+v"(x[c]) : "v"(b))
 WV_PEAK_KERNEL(k_add64, uint64_t, threadIdx.x + c, "v_lshl_add_u64 %0, %0, 0, %1", "+v"(x[c]) : "v"(b))
+WV_PEAK_KERNEL(k_addco, uint32_t, threadIdx.x + c, "v_add_co_u32 %0, vcc, %0, %1", "+v"(x[c]) : "v"(b) : "vcc")
+WV_PEAK_KERNEL(k_addc, uint32_t, threadIdx.x + c, "v_addc_co_u32 %0, vcc, %0, %1, vcc", "+v"(x[c]) : "v"(b) : "vcc")
+WV_PEAK_KERNEL(k_cndmask, uint32_t, threadIdx.x + c, "v_cndmask_b32 %0, %0, %1, vcc", "+v"(x[c]) : "v"(b) : "vcc")
+WV_PEAK_KERNEL(k_cmp, uint32_t, threadIdx.x + c, "v_cmp_gt_u32 vcc, %0, %1", "+v"(x[c]) : "v"(b) : "vcc")
+WV_PEAK_KERNEL(k_min32, uint32_t, threadIdx.x + c, "v_min_u32 %0, %0, %1", "+v"(x[c]) : "v"(b))
+WV_PEAK_KERNEL(k_mov32, uint32_t, threadIdx.x + c, "v_mov_b32 %0, %1", "+v"(x[c]) : "v"(b))
+WV_PEAK_KERNEL(k_subrev, uint32_t, threadIdx.x + c, "v_sub_u32 %0, %1, %0", "+v"(x[c]) : "v"(b))
 
 __global__ void __launch_bounds__(256) k_mad64(uint64_t *out, uint32_t a, int iters) {
     uint64_t x[NCHAIN];
@@ -75,9 +82,14 @@ typedef void (*kfn)(uint64_t *, uint32_t, int);
 extern "C" {
 
 // Measures lane-operations per second for each instruction class on device
-// `dev`: rates[0..6] = v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32,
-// v_mul_u32_u24, v_add_u32, 64-bit add, v_fma_f64.  Each rate counts one
-// instruction per lane as one operation.  Returns 0 on success.
+// `dev`: rates[0..13] = v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32,
+// v_mul_u32_u24, v_add_u32, v_lshl_add_u64, v_fma_f64, v_add_co_u32,
+// v_addc_co_u32, v_cndmask_b32, v_cmp_gt_u32, v_min_u32, v_mov_b32,
+// v_sub_u32.  Each rate counts one instruction per lane as one operation.
+// Returns 0 on success.
+#define WV_PEAK_N 14
+int wv_peak_count(void) { return WV_PEAK_N; }
+
 int wv_peak_rates(int dev, double *rates) {
     if (!rates) return -1;
     if (hipSetDevice(dev) != hipSuccess) return -6;
@@ -90,11 +102,10 @@ int wv_peak_rates(int dev, double *rates) {
     if (hipMalloc(&buf, (size_t)blocks * threads * sizeof(uint64_t)) != hipSuccess) return -5;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -6;
-    kfn ks[7] = {k_mad64, k_mullo, k_mulhi, k_mul24, k_add32, k_add64, k_fma64};
-    // instructions of the measured class per lane per loop-body instance
-    const double per[7] = {1, 1, 1, 1, 1, 1, 1};
+    kfn ks[WV_PEAK_N] = {k_mad64, k_mullo, k_mulhi, k_mul24, k_add32, k_add64, k_fma64,
+                         k_addco, k_addc, k_cndmask, k_cmp, k_min32, k_mov32, k_subrev};
     int rc = 0;
-    for (int k = 0; k < 7 && rc == 0; k++) {
+    for (int k = 0; k < WV_PEAK_N && rc == 0; k++) {
         hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(threads), 0, 0, buf, 12345u, 16);   // warm-up
         (void)hipEventRecord(e0, 0);
         hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(threads), 0, 0, buf, 12345u, iters);
@@ -102,7 +113,7 @@ int wv_peak_rates(int dev, double *rates) {
         if (hipEventSynchronize(e1) != hipSuccess) { rc = -6; break; }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        const double ops = (double)blocks * threads * iters * UNROLL * NCHAIN * per[k];
+        const double ops = (double)blocks * threads * iters * UNROLL * NCHAIN;
         rates[k] = ops / (ms * 1e-3);
     }
     (void)hipEventDestroy(e0);

@@ -42,6 +42,111 @@ __device__ __forceinline__ void run_chunk(uint64_t s0, uint64_t n, const Mont &m
     c1 = a1;
 }
 
+// x < 4p -> x mod p
+__host__ __device__ __forceinline__ uint64_t canon4(uint64_t x, uint64_t p) {
+    x = x >= 2 * p ? x - 2 * p : x;
+    return x >= p ? x - p : x;
+}
+
+// a, b in [0, p), negp = 2^64 - p: a + b mod p with one 64-bit add, one
+// 64-bit add of -p, a sign test of the high word and two selects.
+__host__ __device__ __forceinline__ uint64_t addm_n(uint64_t a, uint64_t b, uint64_t negp) {
+    const uint64_t s = a + b;
+    const uint64_t t = s + negp;
+    return (int32_t)(uint32_t)(t >> 32) < 0 ? s : t;
+}
+
+// u = s^DEG R mod p for one s < p (canonical).
+template <int DEG>
+__host__ __device__ __forceinline__ uint64_t pow_mont(uint64_t s, const Mont &m, uint64_t r2) {
+    const uint64_t sR = to_mont(s, r2, m);
+    uint64_t u = red1(mmul(sR, sR, m), m.p);
+    if (DEG == 3) u = red1(mmul(u, sR, m), m.p);
+    return u;
+}
+
+// Blocked form of eqnComputeS.  For a block of K consecutive s starting at x,
+//   prod_{j<K} (z + (x+j)^DEG) = P(x) + Q(x) z + O(z^2),
+//   P(x) = prod_j (x+j)^DEG,   Q(x) = sum_j prod_{i != j} (x+i)^DEG,
+// and P, Q are polynomials in x of degrees DEG*K and DEG*(K-1).  Along the
+// blocks x = s0, s0+K, s0+2K, ... they are stepped by forward differences
+// (DEG*K + DEG*(K-1) modular additions per block) and each block is folded
+// into the running pair with the pair product of eqnCombinePairs:
+//   (c0, c1) <- (c0 P, c0 Q + c1 P)      (three Montgomery products per block).
+// The difference tables start from P, Q evaluated directly at the first
+// DEG*K + 1 block points.  Terms beyond the last full block are folded one by
+// one.  The result is the same (c0, c1) as run_chunk up to rounding order,
+// which exact arithmetic does not have: bit-identical residues.
+template <int DEG, int K>
+__host__ __device__ __forceinline__ void run_chunk_blocked(uint64_t s0, uint64_t n, const Mont &m, uint64_t r2,
+                                                           uint64_t one, uint64_t &c0, uint64_t &c1) {
+    constexpr int DP = DEG * K;
+    constexpr int DQ = DEG * (K - 1);
+    const uint64_t p = m.p;
+    const uint64_t negp = 0 - p;
+    const uint64_t nb = n / K;
+    uint64_t a0 = 1, a1 = 0;
+    if (nb > 0) {
+        uint64_t Pd[DP + 1] = {}, Qd[DQ + 1] = {};
+        // direct values at x = s0 + b K, b = 0..DP, with u = s^DEG R stepped
+        // over consecutive s by forward differences
+        const uint64_t sR = to_mont(s0, r2, m);
+        const uint64_t s2R = red1(mmul(sR, sR, m), p);
+        uint64_t u, d1, d2 = 0, d3 = 0;
+        if (DEG == 3) {
+            u = red1(mmul(s2R, sR, m), p);
+            const uint64_t t3s = addm(addm(sR, sR, p), sR, p);
+            d1 = addm(addm(addm(addm(s2R, s2R, p), s2R, p), t3s, p), one, p);
+            const uint64_t six = addm(addm(addm(one, one, p), addm(one, one, p), p), addm(one, one, p), p);
+            d2 = addm(addm(t3s, t3s, p), six, p);
+            d3 = six;
+        } else {
+            u = s2R;
+            d1 = addm(addm(sR, sR, p), one, p);
+            d2 = addm(one, one, p);
+        }
+WV_UNROLL
+        for (int b = 0; b <= DP; b++) {
+            uint64_t P = one, Q = 0;
+            for (int j = 0; j < K; j++) {
+                Q = mmul(Q, u, m) + P;
+                P = mmul(P, u, m);
+                u = addm(u, d1, p);
+                d1 = addm(d1, d2, p);
+                if (DEG == 3) d2 = addm(d2, d3, p);
+            }
+            Pd[b] = canon4(P, p);
+            if (b <= DQ) Qd[b] = canon4(Q, p);
+        }
+        // forward differences at b = 0: entry i becomes Delta^i
+WV_UNROLL
+        for (int lev = 1; lev <= DP; lev++) {
+WV_UNROLL
+            for (int i = DP; i >= lev; i--) Pd[i] = subm(Pd[i], Pd[i - 1], p);
+        }
+WV_UNROLL
+        for (int lev = 1; lev <= DQ; lev++) {
+WV_UNROLL
+            for (int i = DQ; i >= lev; i--) Qd[i] = subm(Qd[i], Qd[i - 1], p);
+        }
+        for (uint64_t b = 0; b < nb; b++) {
+            a1 = mmul(a0, Qd[0], m) + mmul(a1, Pd[0], m);
+            a0 = mmul(a0, Pd[0], m);
+WV_UNROLL
+            for (int i = 0; i < DP; i++) Pd[i] = addm_n(Pd[i], Pd[i + 1], negp);
+WV_UNROLL
+            for (int i = 0; i < DQ; i++) Qd[i] = addm_n(Qd[i], Qd[i + 1], negp);
+        }
+    }
+    for (uint64_t t = nb * K; t < n; t++) {
+        const uint64_t u = pow_mont<DEG>(s0 + t, m, r2);
+        a1 = mmul(a1, u, m) + a0;
+        a0 = mmul(a0, u, m);
+    }
+    c0 = a0;
+    c1 = a1;
+}
+
 __device__ __forceinline__ uint32_t find_seg(const uint64_t *__restrict__ off, uint32_t nseg, uint64_t chunk) {
     // largest j in [0, nseg) with off[j] <= chunk
     uint32_t lo = 0, hi = nseg;   // invariant: off[lo] <= chunk < off[hi] (off[nseg] = total)

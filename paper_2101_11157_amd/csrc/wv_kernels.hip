@@ -412,10 +412,22 @@ __global__ void k_zero_u64(uint64_t *p, int n) {
 // term-sum kernel
 // --------------------------------------------------------------------------
 
+// Per-lane work of one chunk: the blocked loop with K terms per block when
+// the chunk is long enough to amortise the difference tables, else one term
+// per iteration.
+template <int DEG, int K>
+__device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont &m, uint64_t r2, uint64_t one,
+                                           uint64_t &c0, uint64_t &c1) {
+    if (K > 1 && cnt >= (uint64_t)4 * (DEG * K + 1) * K) run_chunk_blocked<DEG, K>(s0, cnt, m, r2, one, c0, c1);
+    else run_chunk<DEG>(s0, cnt, m, r2, one, c0, c1);
+}
+
 // Persistent: each wave takes 64 consecutive chunks at a time from `counter`
 // until every chunk is done.  A wave whose chunks all belong to one sum stores
 // their butterfly product at partials[first chunk]; any other wave stores one
-// pair per chunk at partials[chunk].
+// pair per chunk at partials[chunk].  KB / KE: terms per block on the
+// Bernoulli (s^3) and Euler (s^2) sides.
+template <int KB, int KE>
 __global__ void __launch_bounds__(256) k_sum(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
                                              uint32_t nseg, const PrimeRec *__restrict__ pr,
                                              const uint64_t *__restrict__ chunk_ptr, Pair *__restrict__ partials,
@@ -444,8 +456,8 @@ __global__ void __launch_bounds__(256) k_sum(const SegRec *__restrict__ segs, co
             const uint64_t o = (chunk - off[seg]) * C;
             const uint64_t s0 = sr.lo + o;
             const uint64_t cnt = min(C, sr.len - o);
-            if (sr.deg == 3) run_chunk<3>(s0, cnt, m, P.r2, P.one, c0, c1);
-            else run_chunk<2>(s0, cnt, m, P.r2, P.one, c0, c1);
+            if (sr.deg == 3) chunk_pair<3, KB>(s0, cnt, m, P.r2, P.one, c0, c1);
+            else chunk_pair<2, KE>(s0, cnt, m, P.r2, P.one, c0, c1);
         }
         const uint32_t seg0 = __builtin_amdgcn_readlane(seg, 0);
         const uint32_t segl = __builtin_amdgcn_readlane(seg, 63);
@@ -458,6 +470,21 @@ __global__ void __launch_bounds__(256) k_sum(const SegRec *__restrict__ segs, co
         }
     }
 }
+
+typedef void (*SumKernel)(const SegRec *, const uint64_t *, uint32_t, const PrimeRec *, const uint64_t *, Pair *,
+                          unsigned long long *);
+
+struct SumVariant {
+    int kb, ke;
+    SumKernel fn;
+};
+
+// Compiled block shapes (terms per block, Bernoulli side / Euler side).
+static const SumVariant kSumVariants[] = {
+    {1, 1, k_sum<1, 1>},   {4, 4, k_sum<4, 4>},   {8, 8, k_sum<8, 8>},
+    {8, 16, k_sum<8, 16>}, {16, 8, k_sum<16, 8>}, {16, 16, k_sum<16, 16>},
+};
+constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants[0]));
 
 // --------------------------------------------------------------------------
 // per-sum reduction and finalize
@@ -584,7 +611,8 @@ struct wv_ctx {
     int tb = WV_TABLE_BB30, te = WV_TABLE_EE33;
     uint64_t chunk_cfg = 0;
     int num_cus = 0;
-    int sum_blocks = 0;
+    int variant = 2;                    // index into kSumVariants
+    int sum_blocks[16] = {};            // persistent grid per variant
     uint32_t n_base = 0;
     DevBuf base_primes, primes, pr, segs, terms, cnt, off, tiles, scal, partials, seg_pairs, results,
         seg_counts, seg_bits, seg_off;
@@ -744,7 +772,8 @@ int run_batch(wv_ctx *c, const uint64_t *d_primes, uint32_t n, wv_result *d_out,
     WV_HIP(hipGetLastError());
     if (timed) WV_HIP(hipEventRecord(c->ev[EV_PLAN], st));
 
-    hipLaunchKernelGGL(k_sum, dim3(c->sum_blocks), dim3(256), 0, st, (const SegRec *)as<SegRec>(c->segs),
+    hipLaunchKernelGGL(kSumVariants[c->variant].fn, dim3(c->sum_blocks[c->variant]), dim3(256), 0, st,
+                       (const SegRec *)as<SegRec>(c->segs),
                        (const uint64_t *)toff, (uint32_t)nseg, (const PrimeRec *)as<PrimeRec>(c->pr),
                        (const uint64_t *)(scal + 1), as<Pair>(c->partials),
                        (unsigned long long *)(scal + 2));
@@ -795,8 +824,9 @@ int collect_stats(wv_ctx *c, uint32_t n, bool with_sieve) {
     s.n_terms += host[0];
     s.n_terms_b += host[3];
     s.chunk_terms = host[1];
-    s.block_k = 1;
-    s.grid = (uint32_t)c->sum_blocks;
+    s.block_k_b = (uint32_t)kSumVariants[c->variant].kb;
+    s.block_k_e = (uint32_t)kSumVariants[c->variant].ke;
+    s.grid = (uint32_t)c->sum_blocks[c->variant];
     return WV_OK;
 }
 
@@ -864,10 +894,13 @@ int wv_create(int hip_device, wv_ctx **out) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { rc = WV_EHIP; break; }
         c->num_cus = prop.multiProcessorCount;
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sum, 256, 0) != hipSuccess || per_cu < 1)
-            per_cu = 2;
-        c->sum_blocks = c->num_cus * per_cu;
+        for (int v = 0; v < kNumSumVariants; v++) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kSumVariants[v].fn, 256, 0) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            c->sum_blocks[v] = c->num_cus * per_cu;
+        }
         if ((rc = upload_tables()) != WV_OK) break;
         if ((rc = ensure(c->base_primes, kBaseLimit / 2 * sizeof(uint32_t))) != WV_OK) break;
         if ((rc = ensure(c->scal, 8 * sizeof(uint64_t))) != WV_OK) break;
@@ -916,6 +949,17 @@ int wv_set_chunk_terms(wv_ctx *c, uint64_t chunk_terms) {
     if (!c || (chunk_terms % 64) != 0) return WV_EINVAL;
     c->chunk_cfg = chunk_terms;
     return WV_OK;
+}
+
+int wv_set_block(wv_ctx *c, int kb, int ke) {
+    if (!c) return WV_EINVAL;
+    for (int v = 0; v < kNumSumVariants; v++) {
+        if (kSumVariants[v].kb == kb && kSumVariants[v].ke == ke) {
+            c->variant = v;
+            return WV_OK;
+        }
+    }
+    return WV_EINVAL;
 }
 
 int wv_get_stats(const wv_ctx *c, wv_stats *out) {

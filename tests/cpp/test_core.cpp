@@ -115,6 +115,49 @@ int main() {
             }
         }
     }
+    // the blocked hot loop gives the same pair as the one-term loop
+    for (uint64_t p : ps) {
+        if (p < 11) continue;
+        Mont m = make_mont(p);
+        const uint64_t R2 = r2_mod(p), Rm = r_mod(p);
+        for (int k = 0; k < 6; k++) {
+            uint64_t s0 = 1 + rng() % (p - 1);
+            uint64_t n = rng() % 700;
+            if (k == 0) n = 0;
+            if (k == 1) n = 5;
+            if (s0 + n > p) n = p - s0;
+            uint64_t r0, r1;
+            auto cmp = [&](uint64_t x0, uint64_t x1, const char *what) {
+                if (x0 % p != r0 % p || x1 % p != r1 % p || x0 >= 2 * p || x1 >= 4 * p) {
+                    printf("FAIL %s p=%llu s0=%llu n=%llu\n", what, (unsigned long long)p, (unsigned long long)s0,
+                           (unsigned long long)n);
+                    return false;
+                }
+                checks++;
+                return true;
+            };
+            uint64_t x0, x1;
+            run_chunk<3>(s0, n, m, R2, Rm, r0, r1);
+            run_chunk_blocked<3, 1>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k1")) return 1;
+            run_chunk_blocked<3, 2>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k2")) return 1;
+            run_chunk_blocked<3, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k4")) return 1;
+            run_chunk_blocked<3, 8>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k8")) return 1;
+            run_chunk_blocked<3, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k16")) return 1;
+            run_chunk<2>(s0, n, m, R2, Rm, r0, r1);
+            run_chunk_blocked<2, 1>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k1")) return 1;
+            run_chunk_blocked<2, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k4")) return 1;
+            run_chunk_blocked<2, 8>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k8")) return 1;
+            run_chunk_blocked<2, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k16")) return 1;
+        }
+        // addm_n, canon4
+        for (int k = 0; k < 1000; k++) {
+            uint64_t a = rng() % p, b = rng() % p;
+            if (addm_n(a, b, 0 - p) != (uint64_t)(((u128)a + b) % p)) { printf("FAIL addm_n\n"); return 1; }
+            uint64_t x = rng() % (4 * p);
+            if (canon4(x, p) != x % p) { printf("FAIL canon4\n"); return 1; }
+            checks += 2;
+        }
+    }
     // chunk -> sum lookup skips empty sums
     {
         const uint64_t off[] = {0, 0, 3, 3, 3, 7, 8, 8};   // 7 sums, total 8 chunks

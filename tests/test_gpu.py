@@ -159,6 +159,38 @@ def test_first_sum_spans_many_waves(ctx):
     assert as_pairs(got) == oracle.residues(ps, method="table")
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (4, 4), (8, 8), (8, 16), (16, 8), (16, 16)])
+def test_block_shape_invariance(ctx, shape):
+    """Every compiled block shape of the term-sum kernel gives the same residues
+    (long chunks take the blocked path, segment tails the one-term path)."""
+    say(f"case: block shape {shape}")
+    ps = oracle.primes(10 ** 8, 10 ** 8 + 400)[:20] + [11, 101, 1000003, 9999999967, 73607557631]
+    want = oracle.residues(ps[:22]) 
+    try:
+        ctx.set_block(*shape)
+        got = ctx.eval_primes(ps)
+        st = ctx.stats()
+        ctx.set_chunk_terms(4096)
+        got2 = ctx.eval_primes(ps)
+    finally:
+        ctx.set_block(8, 8)
+        ctx.set_chunk_terms(0)
+    assert (st["block_k_b"], st["block_k_e"]) == shape
+    assert as_pairs(got)[:22] == want
+    assert as_pairs(got2) == as_pairs(got)
+    ref = golden_residues_paper()
+    for (p, key, r) in ref:
+        if p in ps:
+            assert wv.symmetric(got[ps.index(p)][key], p) == r
+
+
+def golden_residues_paper():
+    out = []
+    for name, key in (("near_miss_B.txt", "b"), ("near_miss_E.txt", "e")):
+        out += [(int(p), key, int(r)) for p, r in read_golden(name)]
+    return out
+
+
 def test_cross_table_agreement(ctx):
     """Every Bernoulli table with every Euler table gives the same residues."""
     say("case: cross-table agreement")
