@@ -34,6 +34,7 @@ CONFIGS = {
     "1e9": (10 ** 9, 10 ** 9 + 10 ** 7, 1 << 18),
     "1e5": (5, 10 ** 5, 10 ** 5),
 }
+EXTRA_CONFIGS = ("batch", "serve")
 
 
 def cpu_threads():
@@ -64,7 +65,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="1e11", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="1e11", choices=sorted(CONFIGS) + list(EXTRA_CONFIGS))
+    ap.add_argument("--windows", type=int, default=64, help="batch: number of seeded windows")
+    ap.add_argument("--verify", type=int, default=0, help="batch: windows re-run alone and compared")
+    ap.add_argument("--requests", type=int, default=128, help="serve: requests in the seeded trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
+    ap.add_argument("--step-terms", type=int, default=0, help="serve: terms per scheduling step")
     ap.add_argument("--window", type=int, default=0, help="integers per step (0: config default)")
     ap.add_argument("--chunk", type=int, default=0, help="terms per lane chunk (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -77,15 +83,19 @@ def main():
 
     import paper_2101_11157_amd as wv
 
+    if args.config == "batch":
+        return bench_batch(args, wv)
+    if args.config == "serve":
+        return bench_serve(args, wv)
+
     lo0, hi0, wdef = CONFIGS[args.config]
     W = args.window or wdef
     nwin = args.warmup + args.steps
     if lo0 + nwin * W > hi0 and args.config != "1e5":
         print(f"bench.py: {nwin} windows of {W} do not fit in [{lo0}, {hi0})", file=sys.stderr)
         sys.exit(2)
-    wins = [(lo0 + k * W, min(hi0, lo0 + (k + 1) * W)) for k in range(nwin)]
-    if args.config == "1e5":
-        wins = [(lo0, hi0)] * nwin
+    from paper_2101_11157_amd import workloads
+    wins = workloads.bench_windows(nwin, W, lo0, hi0) if args.config != "1e5" else [(lo0, hi0)] * nwin
 
     ctx = wv.Context(0)
     if args.chunk:
@@ -156,6 +166,109 @@ def main():
                       f"eqnBB30+eqnEE33 evaluated plainly, {dt:.1f} s",
         }
     print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, wv):
+    """Uneven seeded windows (lengths log-uniform in [1e3, 1e6], starts in
+    [1e6, 1e11], numpy default_rng(0)) in one batched call."""
+    from paper_2101_11157_amd import workloads
+    wins = workloads.batch_windows(0, args.windows)
+    ctx = wv.Context(0)
+    if args.chunk:
+        ctx.set_chunk_terms(args.chunk)
+    last = [0.0]
+
+    def progress(done, total):
+        t = time.perf_counter()
+        if t - last[0] > 10 or done == total:
+            last[0] = t
+            print(f"batch progress {done}/{total} chunks", file=sys.stderr, flush=True)
+
+    ctx.set_progress(progress)
+    t0 = time.perf_counter()
+    res = ctx.search_windows([a for a, _ in wins], [b for _, b in wins])
+    wall = time.perf_counter() - t0
+    st = ctx.stats()
+    primes = sum(len(r) for r in res)
+    ok = None
+    if args.verify:
+        ctx.set_progress(None)
+        order = sorted(range(len(wins)), key=lambda k: wins[k][1] - wins[k][0])[: args.verify]
+        ok = True
+        for k in order:
+            ref, _ = ctx.search_range(*wins[k])
+            same = [(int(r["b"]), int(r["e"])) for r in ref] == [(int(r["b"]), int(r["e"])) for r in res[k]]
+            ok = ok and same
+            print(f"verify window {k} {wins[k]}: {len(ref)} primes, {'identical' if same else 'DIFFERENT'}",
+                  file=sys.stderr, flush=True)
+    ctx.close()
+    print(json.dumps({
+        "metric": "batched windows: primes tested/sec (1 GPU)", "value": primes / wall, "unit": "primes/s",
+        "config": {"workload": f"{len(wins)} seeded windows (default_rng(0)), lengths log-uniform [1e3, 1e6], "
+                               f"starts log-uniform [1e6, 1e11]", "primes": primes, "terms": st["n_terms"],
+                   "terms_per_s": st["n_terms"] / wall, "sum_kernel_ms": st["ms_sum"], "wall_s": wall,
+                   "block": [st["block_k_b"], st["block_k_e"]], "verified_windows": args.verify,
+                   "verified_identical": ok},
+    }), flush=True)
+
+
+def bench_serve(args, wv):
+    """Seeded Poisson trace of single primes and intervals through the request
+    server; arrivals submitted at their times, latency from arrival."""
+    from paper_2101_11157_amd import workloads
+    trace = workloads.serve_trace(0, args.requests, rate=args.rate)
+    ctx = wv.Context(0)
+    srv = wv.Server(ctx, step_terms=args.step_terms)
+    t0 = time.perf_counter()
+    ids, arrive, lat = {}, {}, {}
+    nxt = 0
+    last = t0
+    primes = 0
+    while len(lat) < len(trace):
+        now = time.perf_counter() - t0
+        while nxt < len(trace) and trace[nxt][0] <= now:
+            at, kind, arg = trace[nxt]
+            rid = srv.submit_primes([arg]) if kind == "prime" else srv.submit_range(*arg)
+            ids[rid] = nxt
+            arrive[rid] = (at, time.perf_counter() - t0)
+            nxt += 1
+        srv.step()
+        for rid in list(ids):
+            if rid in lat:
+                continue
+            r = srv.result(rid)
+            if r is not None:
+                res, server_ms = r
+                at, sub = arrive[rid]
+                lat[rid] = server_ms + (sub - at) * 1e3     # from arrival, not from submission
+                primes += len(res)
+        if nxt >= len(trace) and not lat and not ids:
+            break
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            st = srv.stats()
+            print(f"serve: {len(lat)}/{len(trace)} done, active {st['active']}, pending {st['pending']}",
+                  file=sys.stderr, flush=True)
+        if nxt < len(trace) and not srv.stats()["active"] and not srv.stats()["pending"]:
+            time.sleep(max(0.0, min(0.01, trace[nxt][0] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+    v = sorted(lat.values())
+    pct = lambda q: v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+    span = trace[-1][0] if trace else 0.0
+    offered = st["terms_done"] / span if span > 0 else float("inf")
+    capacity = st["terms_done"] / st["busy_s"] if st["busy_s"] > 0 else 0.0
+    print(json.dumps({
+        "metric": "served queries: p50/p99 latency and primes tested/sec (1 GPU)", "value": primes / wall,
+        "unit": "primes/s", "p50_ms": pct(0.5), "p99_ms": pct(0.99), "mean_ms": sum(v) / len(v),
+        "config": {"workload": f"seeded Poisson trace (default_rng(0)), {len(trace)} requests, "
+                               f"{args.rate:g}/s, 70% single primes, 30% intervals of 1e2..1e5, u in [1e8, 1e11]",
+                   "requests": len(trace), "primes": primes, "terms": st["terms_done"], "wall_s": wall,
+                   "busy_s": st["busy_s"], "steps": st["steps"], "offered_terms_per_s": offered,
+                   "capacity_terms_per_s": capacity, "offered_over_capacity": offered / capacity if capacity else None},
+    }), flush=True)
 
 
 if __name__ == "__main__":

@@ -38,6 +38,7 @@ extern "C" {
 #define WV_ETRUNC    -4  /* caller's buffer too small; *n_out holds the need    */
 #define WV_ENOMEM    -5  /* device allocation failed (context stays valid)      */
 #define WV_EHIP      -6  /* a HIP runtime call failed (context stays valid)     */
+#define WV_EBUSY     -7  /* a served request has not finished yet               */
 
 /* Largest supported prime bound (exclusive): 2^40.  The sums are computed with
  * 64-bit Montgomery arithmetic whose intermediate bounds assume p < 2^40. */
@@ -125,8 +126,31 @@ int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
  * 8/16, 16/8, 16/16; default 8/8).  Each block of k consecutive s is folded
  * into the running pair as one factor of eqnCombinePairs whose two members
  * are stepped by finite differences.  Results do not depend on the shape.
+ * kb = ke = 0 returns to the default / autotuned choice.
  * Errors: WV_EINVAL for a shape that is not compiled. */
 int wv_set_block(wv_ctx *ctx, int kb, int ke);
+
+/* Progress of a long synchronous call: with a callback set, the term sums of
+ * each batch run as consecutive launches of about terms_per_launch terms (0:
+ * 2^44) and fn(user, done, total) is called on the calling thread after each
+ * (done/total in chunks of the current batch).  NULL fn: one launch per batch.
+ * Results do not depend on the split. */
+typedef void (*wv_progress_fn)(void *user, uint64_t done, uint64_t total);
+int wv_set_progress(wv_ctx *ctx, wv_progress_fn fn, void *user, uint64_t terms_per_launch);
+
+/* Autotuner: times every compiled block shape with chunk sizes 2^14, 2^16 and
+ * 2^18 terms on sample primes just above p_hint (n_sample of them, 0: 16) and
+ * keeps the fastest for primes in [2^k, 2^(k+1)), k = floor(log2 p_hint).
+ * Synchronous calls on primes in a tuned range then use the tuned shape and
+ * chunk unless wv_set_block / wv_set_chunk_terms force others.  The measured
+ * rates go to rates[v*3 + j] (terms/s) when rates is non-NULL (room for
+ * 3 x the number of compiled shapes).  Returns the chosen shape and chunk. */
+int wv_autotune(wv_ctx *ctx, uint64_t p_hint, int n_sample, int *kb, int *ke, uint64_t *chunk_terms,
+                double *rates);
+
+/* Write / read the tuning cache (text lines: arch log2p kb ke chunk rate). */
+int wv_tune_save(const wv_ctx *ctx, const char *path);
+int wv_tune_load(wv_ctx *ctx, const char *path);
 
 /* Number of primes p with 5 <= p and lo <= p < hi (segmented sieve on the
  * device).  Errors: WV_EINVAL (n NULL, lo > hi), WV_EDOMAIN (hi > WV_P_MAX). */
@@ -143,6 +167,17 @@ int wv_search_range(wv_ctx *ctx, uint64_t lo, uint64_t hi,
                     wv_result *out, size_t cap, size_t *n_out,
                     uint64_t *hits, size_t hit_cap, size_t *n_hits);
 
+/* Batched search over nwin windows [lo[w], hi[w]) (may differ in size and
+ * position): all windows are sieved together and all their primes go through
+ * one plan and one persistent term-sum launch per batch of about 2^19 primes,
+ * with work split by cost (equal-size chunks of the flat term space).  out
+ * receives the results window by window, ascending p within a window;
+ * win_off (nwin + 1 entries, may be NULL) receives each window's first index
+ * and the total.  Short buffer: WV_ETRUNC with *n_out set, nothing written.
+ * Errors as wv_search_range. */
+int wv_search_windows(wv_ctx *ctx, const uint64_t *lo, const uint64_t *hi, size_t nwin,
+                      wv_result *out, size_t cap, size_t *n_out, size_t *win_off);
+
 /* Residues for n given primes (host memory), results in input order.  Each
  * p must satisfy 5 <= p < WV_P_MAX (else WV_EDOMAIN) and be prime (checked on
  * the host by deterministic Miller-Rabin; else WV_ENOTPRIME).  n == 0 is a
@@ -152,6 +187,9 @@ int wv_eval_primes(wv_ctx *ctx, const uint64_t *primes, size_t n, wv_result *out
 /* Device-pointer variant: d_primes and d_out are device memory (e.g. torch
  * tensors) of n entries; the work is enqueued on hip_stream (a hipStream_t;
  * NULL = the legacy default stream) and the call returns without waiting.
+ * The batch is padded to a power of two and the whole sequence of kernels is
+ * replayed from a captured HIP graph cached per padded size (captured on the
+ * first call of each size, which waits for the context's own stream).
  * The primes are not validated: each must be a prime in [5, WV_P_MAX); a
  * value outside that range yields a result with flags = 0xFFFFFFFF.  The
  * caller keeps both buffers alive until the stream has passed this work.
@@ -169,6 +207,52 @@ int wv_eval_primes_async(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
  * (wv_table_info), and slots beyond the congruence used for a prime (p = 5, 7
  * use one-sum root forms) hold 0.  Same validation as wv_eval_primes. */
 int wv_eval_sums(wv_ctx *ctx, const uint64_t *primes, size_t n, uint64_t *out_b, uint64_t *out_e);
+
+/* ---- request server ---------------------------------------------------
+ * Continuous batching of mixed requests (prime lists and intervals) on one
+ * context.  Admitted requests keep their primes, per-sum plans and running
+ * pairs (c0, c1) in a device pool; each step cuts `step_terms` terms of work
+ * into contiguous pieces of sums, shared fairly among the active requests,
+ * runs them through the term-sum kernels and folds every piece into its sum
+ * with eqnCombinePairs (Section 3).  Requests that arrive while others run
+ * join at the next step; results do not depend on the interleaving (exact
+ * arithmetic, associative product).  The server uses the context's stream and
+ * buffers: do not call other entry points on the context between steps except
+ * wv_get_stats.  The congruences are those set on the context at creation. */
+typedef struct wv_server wv_server;
+
+typedef struct {
+    uint64_t step_terms;   /* terms of work per step (0: 2^36, ~50 ms at p ~ 1e11) */
+    uint32_t max_primes;   /* prime slots of the device pool (0: 65536) */
+    uint32_t reserved;
+} wv_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, pending, active;
+    uint64_t primes_done, terms_done, steps, readmits;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* submit-to-completion latency, completed requests */
+    double busy_s;                          /* device time of the steps */
+    double wall_s;                          /* since the first submit */
+} wv_server_stats;
+
+int wv_server_create(wv_ctx *ctx, const wv_server_config *cfg, wv_server **out);
+int wv_server_destroy(wv_server *srv);
+/* Every prime of [lo, hi) (at most 2^26 integers wide). */
+int wv_server_submit_range(wv_server *srv, uint64_t lo, uint64_t hi, uint64_t *id);
+/* A list of primes (validated like wv_eval_primes; at most max_primes). */
+int wv_server_submit_primes(wv_server *srv, const uint64_t *primes, size_t n, uint64_t *id);
+/* Admit what fits, then run one step of work; returns after the step's GPU
+ * work.  A failed step (HIP error) restarts every active request from its
+ * plan, so no partial state of the failed step survives. */
+int wv_server_step(wv_server *srv, uint32_t *n_active, uint32_t *n_pending);
+/* Results of a finished request (then forgotten); WV_EBUSY while it runs,
+ * WV_ETRUNC (with *n_out) if cap is short.  latency_ms: submit to completion. */
+int wv_server_result(wv_server *srv, uint64_t id, wv_result *out, size_t cap, size_t *n_out,
+                     double *latency_ms);
+int wv_server_get_stats(const wv_server *srv, wv_server_stats *out);
+/* Testing aid: the step that ends `after_steps` steps from now reports a
+ * failure after its GPU work (forced on the host), exercising the restart. */
+int wv_server_inject_fault(wv_server *srv, int after_steps);
 
 /* Statistics of the last search/eval call (synchronous calls only). */
 int wv_get_stats(const wv_ctx *ctx, wv_stats *out);

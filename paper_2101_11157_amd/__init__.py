@@ -25,6 +25,7 @@ WV_ENOTPRIME = -3
 WV_ETRUNC = -4
 WV_ENOMEM = -5
 WV_EHIP = -6
+WV_EBUSY = -7
 WV_P_MAX = 1 << 40
 WV_FLAG_WOLSTENHOLME = 1
 WV_FLAG_VANDIVER = 2
@@ -32,6 +33,8 @@ WV_FLAG_VANDIVER = 2
 TABLE_NAMES = ["BB1", "BB2", "BB6", "BB9", "BB16", "BB22", "BB30",
                "EE3", "EE5", "EE9", "EE16", "EE24", "EE33", "V12", "E1"]
 TABLE_ID = {n: i for i, n in enumerate(TABLE_NAMES)}
+# compiled block shapes of the term-sum kernel, in the library's order
+BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (8, 16), (16, 8), (16, 16)]
 
 # wv_result as a numpy record (32 bytes)
 RESULT_DTYPE = np.dtype([("p", "<u8"), ("b", "<u8"), ("e", "<u8"), ("flags", "<u4"), ("reserved", "<u4")])
@@ -49,6 +52,26 @@ class WvStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class WvServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+        ("active", ctypes.c_uint64), ("primes_done", ctypes.c_uint64), ("terms_done", ctypes.c_uint64),
+        ("steps", ctypes.c_uint64), ("readmits", ctypes.c_uint64),
+        ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("wall_s", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class WvServerConfig(ctypes.Structure):
+    _fields_ = [("step_terms", ctypes.c_uint64), ("max_primes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
 
 
 class WvError(RuntimeError):
@@ -85,6 +108,22 @@ def lib():
             "wv_eval_primes": (ctypes.c_int, [VP, P_U64, SZ, VP]),
             "wv_eval_primes_async": (ctypes.c_int, [VP, VP, SZ, VP, VP]),
             "wv_eval_sums": (ctypes.c_int, [VP, P_U64, SZ, P_U64, P_U64]),
+            "wv_search_windows": (ctypes.c_int, [VP, P_U64, P_U64, SZ, VP, SZ, ctypes.POINTER(SZ),
+                                                 ctypes.POINTER(SZ)]),
+            "wv_set_progress": (ctypes.c_int, [VP, PROGRESS_FN, VP, U64]),
+            "wv_autotune": (ctypes.c_int, [VP, U64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), P_U64, ctypes.POINTER(ctypes.c_double)]),
+            "wv_tune_save": (ctypes.c_int, [VP, ctypes.c_char_p]),
+            "wv_tune_load": (ctypes.c_int, [VP, ctypes.c_char_p]),
+            "wv_server_create": (ctypes.c_int, [VP, ctypes.POINTER(WvServerConfig), ctypes.POINTER(VP)]),
+            "wv_server_destroy": (ctypes.c_int, [VP]),
+            "wv_server_submit_range": (ctypes.c_int, [VP, U64, U64, P_U64]),
+            "wv_server_submit_primes": (ctypes.c_int, [VP, P_U64, SZ, P_U64]),
+            "wv_server_step": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+            "wv_server_result": (ctypes.c_int, [VP, U64, VP, SZ, ctypes.POINTER(SZ),
+                                                ctypes.POINTER(ctypes.c_double)]),
+            "wv_server_get_stats": (ctypes.c_int, [VP, ctypes.POINTER(WvServerStats)]),
+            "wv_server_inject_fault": (ctypes.c_int, [VP, ctypes.c_int]),
             "wv_get_stats": (ctypes.c_int, [VP, ctypes.POINTER(WvStats)]),
             "wv_table_info": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                              ctypes.POINTER(ctypes.c_int64), P_U64, P_U64]),
@@ -205,6 +244,52 @@ class Context:
         _check(st, "wv_eval_primes")
         return out[:arr.size]
 
+    def search_windows(self, los, his):
+        """Batched search: list of per-window result arrays (ascending p in each)."""
+        lo = np.ascontiguousarray(np.asarray(los, dtype=np.uint64))
+        hi = np.ascontiguousarray(np.asarray(his, dtype=np.uint64))
+        n_out = SZ()
+        offs = (SZ * (lo.size + 1))()
+        st = lib().wv_search_windows(self._h, lo.ctypes.data_as(P_U64), hi.ctypes.data_as(P_U64), lo.size, None, 0,
+                                     ctypes.byref(n_out), offs)
+        if st not in (WV_OK, WV_ETRUNC):
+            _check(st, "wv_search_windows")
+        out = np.zeros(max(1, n_out.value), dtype=RESULT_DTYPE)
+        st = lib().wv_search_windows(self._h, lo.ctypes.data_as(P_U64), hi.ctypes.data_as(P_U64), lo.size,
+                                     out.ctypes.data_as(VP), n_out.value, ctypes.byref(n_out), offs)
+        _check(st, "wv_search_windows")
+        return [out[offs[w]:offs[w + 1]] for w in range(lo.size)]
+
+    def set_progress(self, fn=None, terms_per_launch=0):
+        """Callback fn(done, total) between term-sum launches of long calls (None: off)."""
+        if fn is None:
+            self._progress = None
+            _check(lib().wv_set_progress(self._h, PROGRESS_FN(), None, 0), "wv_set_progress")
+            return
+        self._progress = PROGRESS_FN(lambda _u, d, t: fn(d, t))
+        _check(lib().wv_set_progress(self._h, self._progress, None, int(terms_per_launch)), "wv_set_progress")
+
+    def autotune(self, p_hint, n_sample=16):
+        """Times every compiled block shape x chunk size near p_hint; returns
+        (kb, ke, chunk, {(kb, ke, chunk): terms/s})."""
+        kb, ke = ctypes.c_int(), ctypes.c_int()
+        ch = U64()
+        nv = len(BLOCK_SHAPES)
+        rates = (ctypes.c_double * (3 * nv))()
+        _check(lib().wv_autotune(self._h, int(p_hint), int(n_sample), ctypes.byref(kb), ctypes.byref(ke),
+                                 ctypes.byref(ch), rates), "wv_autotune")
+        table = {}
+        for v, (a, b) in enumerate(BLOCK_SHAPES):
+            for j, c in enumerate((1 << 14, 1 << 16, 1 << 18)):
+                table[(a, b, c)] = rates[3 * v + j]
+        return kb.value, ke.value, ch.value, table
+
+    def tune_save(self, path):
+        _check(lib().wv_tune_save(self._h, os.fsencode(path)), "wv_tune_save")
+
+    def tune_load(self, path):
+        _check(lib().wv_tune_load(self._h, os.fsencode(path)), "wv_tune_load")
+
     def eval_sums(self, primes, nb, ne):
         """Per-sum values S_j for the configured congruences: arrays (n, nb) and (n, ne)."""
         arr = np.ascontiguousarray(np.asarray(primes, dtype=np.uint64))
@@ -225,3 +310,67 @@ class Context:
         s = WvStats()
         _check(lib().wv_get_stats(self._h, ctypes.byref(s)), "wv_get_stats")
         return s.as_dict()
+
+
+class Server:
+    """Continuous-batching request server on a Context (wv_server_*)."""
+
+    def __init__(self, ctx, step_terms=0, max_primes=0):
+        cfg = WvServerConfig(int(step_terms), int(max_primes), 0)
+        h = VP()
+        _check(lib().wv_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "wv_server_create")
+        self._h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wv_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit_range(self, lo, hi):
+        rid = U64()
+        _check(lib().wv_server_submit_range(self._h, int(lo), int(hi), ctypes.byref(rid)), "wv_server_submit_range")
+        return rid.value
+
+    def submit_primes(self, primes):
+        arr = np.ascontiguousarray(np.asarray(primes, dtype=np.uint64))
+        rid = U64()
+        _check(lib().wv_server_submit_primes(self._h, arr.ctypes.data_as(P_U64), arr.size, ctypes.byref(rid)),
+               "wv_server_submit_primes")
+        return rid.value
+
+    def step(self):
+        """One scheduling step; returns (active, pending)."""
+        a, p = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().wv_server_step(self._h, ctypes.byref(a), ctypes.byref(p)), "wv_server_step")
+        return a.value, p.value
+
+    def result(self, rid):
+        """(results array, latency_ms), or None while the request runs."""
+        n = SZ()
+        lat = ctypes.c_double()
+        st = lib().wv_server_result(self._h, int(rid), None, 0, ctypes.byref(n), ctypes.byref(lat))
+        if st == WV_EBUSY:
+            return None
+        if st == WV_OK:
+            return np.zeros(0, dtype=RESULT_DTYPE), lat.value
+        if st != WV_ETRUNC:
+            _check(st, "wv_server_result")
+        out = np.zeros(n.value, dtype=RESULT_DTYPE)
+        _check(lib().wv_server_result(self._h, int(rid), out.ctypes.data_as(VP), n.value, ctypes.byref(n),
+                                      ctypes.byref(lat)), "wv_server_result")
+        return out, lat.value
+
+    def stats(self):
+        s = WvServerStats()
+        _check(lib().wv_server_get_stats(self._h, ctypes.byref(s)), "wv_server_get_stats")
+        return s.as_dict()
+
+    def inject_fault(self, after_steps):
+        _check(lib().wv_server_inject_fault(self._h, int(after_steps)), "wv_server_inject_fault")

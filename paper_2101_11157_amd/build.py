@@ -4,10 +4,11 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "wv_kernels.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("wv_kernels.hip", "wv_capi.hip", "wv_tune.hip", "wv_server.hip")]
 PEAK_SRC = os.path.join(HERE, "csrc", "peak.hip")
 PEAK_LIB = os.path.join(HERE, "libwvpeak.so")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("mont.hpp", "sum_core.hpp", "wv_tables.hpp")] + [
+DEPS = [os.path.join(HERE, "csrc", f) for f in ("mont.hpp", "sum_core.hpp", "wv_tables.hpp", "wv_internal.hpp",
+                                                "wv_ctx.hpp")] + [
     os.path.join(ROOT, "include", "wvprime.h")]
 LIB = os.path.join(HERE, "libwvprime.so")
 ARCH = os.environ.get("WV_OFFLOAD_ARCH", "gfx950")
@@ -21,11 +22,11 @@ HIPCC_FLAGS = [
 ]
 
 
-def _hipcc(src, out, verbose):
+def _hipcc(srcs, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = out + f".tmp{os.getpid()}"
     cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp, src]
+           "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -36,8 +37,8 @@ def _hipcc(src, out, verbose):
 def build(verbose=False):
     """Compile csrc/wv_kernels.hip into libwvprime.so and the instruction-rate
     microbenchmark csrc/peak.hip into libwvpeak.so (both gfx950, in-tree)."""
-    _hipcc(SRC, LIB, verbose)
-    _hipcc(PEAK_SRC, PEAK_LIB, verbose)
+    _hipcc(SRCS, LIB, verbose)
+    _hipcc([PEAK_SRC], PEAK_LIB, verbose)
     return LIB
 
 
@@ -45,7 +46,7 @@ def is_stale():
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(f) > t for f in [SRC, *DEPS])
+    return any(os.path.getmtime(f) > t for f in [*SRCS, *DEPS])
 
 
 if __name__ == "__main__":

@@ -48,12 +48,27 @@ __host__ __device__ __forceinline__ uint64_t canon4(uint64_t x, uint64_t p) {
     return x >= p ? x - p : x;
 }
 
-// a, b in [0, p), negp = 2^64 - p: a + b mod p with one 64-bit add, one
-// 64-bit add of -p, a sign test of the high word and two selects.
+// a, b in [0, p), negp = 2^64 - p: a + b mod p as two 64-bit adds, an
+// arithmetic shift of the high word of s - p into a mask, and two bitfield
+// selects.  No carry or condition flags, so consecutive additions interleave
+// freely.  (The selects are written as instructions: the compiler otherwise
+// rebuilds a compare-and-select chain through the condition register.)
 __host__ __device__ __forceinline__ uint64_t addm_n(uint64_t a, uint64_t b, uint64_t negp) {
     const uint64_t s = a + b;
-    const uint64_t t = s + negp;
-    return (int32_t)(uint32_t)(t >> 32) < 0 ? s : t;
+    const uint64_t t = s + negp;                   // s - p, negative when s < p
+    const uint32_t sl = (uint32_t)s, sh = (uint32_t)(s >> 32);
+    const uint32_t tl = (uint32_t)t, th = (uint32_t)(t >> 32);
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t mask, rl, rh;
+    asm("v_ashrrev_i32 %0, 31, %1" : "=v"(mask) : "v"(th));
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(rl) : "v"(mask), "v"(sl), "v"(tl));
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(rh) : "v"(mask), "v"(sh), "v"(th));
+#else
+    const uint32_t mask = (uint32_t)((int32_t)th >> 31);
+    const uint32_t rl = (sl & mask) | (tl & ~mask);
+    const uint32_t rh = (sh & mask) | (th & ~mask);
+#endif
+    return ((uint64_t)rh << 32) | rl;
 }
 
 // u = s^DEG R mod p for one s < p (canonical).
@@ -83,7 +98,10 @@ __host__ __device__ __forceinline__ void run_chunk_blocked(uint64_t s0, uint64_t
     constexpr int DP = DEG * K;
     constexpr int DQ = DEG * (K - 1);
     const uint64_t p = m.p;
-    const uint64_t negp = 0 - p;
+    uint64_t negp = 0 - p;
+#if defined(__HIPCC__)
+    asm volatile("" : "+v"(negp));   // keep s + negp an addition (not folded into a subtract)
+#endif
     const uint64_t nb = n / K;
     uint64_t a0 = 1, a1 = 0;
     if (nb > 0) {

@@ -1,0 +1,627 @@
+// wv_capi.hip -- context, pipeline orchestration and the C ABI of
+// libwvprime.so.  Every computational step runs in the kernels of
+// wv_kernels.hip; this file sizes buffers, orders launches on the context's
+// stream, and moves inputs and results across the boundary.
+//
+// Method: Booker, Hathi, Mossinghoff, Trudgian, "Wolstenholme and Vandiver
+// primes" (arXiv:2101.11157) -- see wv_kernels.hip for the step-by-step map.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "wv_ctx.hpp"
+
+using namespace wv;
+
+// ==========================================================================
+// helpers
+// ==========================================================================
+
+namespace wv {
+
+int ensure(wv_ctx *c, DevBuf &b, size_t bytes) {
+    if (b.cap >= bytes && b.ptr) return WV_OK;
+    if (b.ptr) {
+        WV_HIP(hipFree(b.ptr));
+        b.ptr = nullptr;
+        b.cap = 0;
+    }
+    size_t want = std::max(bytes, (size_t)256);
+    WV_HIP(hipMalloc(&b.ptr, want));
+    b.cap = want;
+    c->gen++;   // captured graphs hold the old address
+    return WV_OK;
+}
+
+static uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+
+static uint64_t powmod_h(uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    a %= m;
+    while (e) {
+        if (e & 1) r = mulmod_h(r, a, m);
+        a = mulmod_h(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Deterministic Miller-Rabin for n < 2^64 (first twelve prime bases).
+bool is_prime_u64(uint64_t n) {
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (n < 2) return false;
+    for (uint64_t b : bases) {
+        if (n == b) return true;
+        if (n % b == 0) return false;
+    }
+    uint64_t d = n - 1;
+    int s = 0;
+    while (!(d & 1)) {
+        d >>= 1;
+        s++;
+    }
+    for (uint64_t a : bases) {
+        uint64_t x = powmod_h(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int r = 1; r < s; r++) {
+            x = mulmod_h(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+static float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+int check_device(wv_ctx *c) {
+    WV_HIP(hipSetDevice(c->device));
+    return WV_OK;
+}
+
+// ==========================================================================
+// one batch of primes on the device: plan -> sums -> reduce -> finalize
+// ==========================================================================
+
+int batch_shape(const wv_ctx *c, uint32_t n, BatchShape *sh) {
+    sh->n = n;
+    sh->nB = std::max(table_slots(c->tb), 1);
+    sh->nE = std::max(table_slots(c->te), 1);
+    sh->nseg = (uint64_t)n * (sh->nB + sh->nE);
+    // partial pairs: at most total_terms / chunk + nseg chunks, and the chunk
+    // size keeps total_terms / chunk <= cap - nseg, so cap >= 2 nseg leaves room
+    sh->cap = std::max<uint64_t>(kMaxChunks, 2 * sh->nseg);
+    return WV_OK;
+}
+
+int prepare(wv_ctx *c, const BatchShape &sh) {
+    const uint64_t n = sh.n, nseg = sh.nseg;
+    WV_TRY(ensure(c, c->pr, n * sizeof(PrimeRec)));
+    WV_TRY(ensure(c, c->segs, nseg * sizeof(SegRec)));
+    WV_TRY(ensure(c, c->terms, nseg * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->cnt, nseg * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->off, (nseg + 1) * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->tiles, ((nseg + kScanTile - 1) / kScanTile + 1) * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->scal, 8 * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->partials, sh.cap * sizeof(Pair)));
+    WV_TRY(ensure(c, c->seg_pairs, nseg * sizeof(Pair)));
+    return WV_OK;
+}
+
+// scal: [0] total terms, [1] chunk size, [2] chunk counter, [3] Bernoulli-side terms,
+//       [4] total chunks
+int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st) {
+    uint64_t *scal = as<uint64_t>(c->scal);
+    uint64_t *toff = as<uint64_t>(c->off);   // prefix of terms, then of chunks
+    const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    WV_HIP(launch_set_u64(st, scal, 8, 0));
+    WV_HIP(launch_plan(st, d_primes, sh.n, c->tb, c->te, sh.nB, sh.nE, as<PrimeRec>(c->pr), as<SegRec>(c->segs),
+                       as<uint64_t>(c->terms), 0));
+    WV_HIP(launch_scan(st, as<uint64_t>(c->terms), sh.nseg, toff, as<uint64_t>(c->tiles)));
+    WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sh.cap, scal + 1));
+    WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + 0, 1));
+    WV_HIP(launch_copy_u64(st, toff + (uint64_t)sh.n * sh.nB, scal + 3, 1));
+    WV_HIP(launch_chunk_count(st, as<uint64_t>(c->terms), sh.nseg, scal + 1, as<uint64_t>(c->cnt)));
+    WV_HIP(launch_scan(st, as<uint64_t>(c->cnt), sh.nseg, toff, as<uint64_t>(c->tiles)));
+    WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + 4, 1));
+    return WV_OK;
+}
+
+int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end) {
+    uint64_t *scal = as<uint64_t>(c->scal);
+    const int v = c->variant;
+    WV_HIP(launch_set_u64(st, scal + 2, 1, begin));
+    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(c->segs), as<uint64_t>(c->off),
+                      (uint32_t)sh.nseg, as<PrimeRec>(c->pr), scal + 1, as<Pair>(c->partials),
+                      (unsigned long long *)(scal + 2), end));
+    return WV_OK;
+}
+
+int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out) {
+    WV_HIP(launch_reduce(st, as<SegRec>(c->segs), as<uint64_t>(c->off), (uint32_t)sh.nseg, as<PrimeRec>(c->pr),
+                         as<Pair>(c->partials), as<Pair>(c->seg_pairs)));
+    WV_HIP(launch_finalize(st, as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), sh.n, sh.nB, sh.nE, d_out));
+    return WV_OK;
+}
+
+// Synchronous batch on the context stream with timing.  When a progress
+// callback is set, the term sums run as several launches over consecutive
+// chunk ranges of about `launch_terms` terms each, with the callback between
+// them; the partial pairs of all ranges are reduced together afterwards, so
+// the result does not depend on the split.
+int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, wv_result *d_out) {
+    hipStream_t st = c->stream;
+    BatchShape sh;
+    WV_TRY(batch_shape(c, n, &sh));
+    WV_TRY(prepare(c, sh));
+    WV_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
+    WV_TRY(enqueue_plan(c, d_primes, sh, st));
+    WV_HIP(hipEventRecord(c->ev[EV_PLAN], st));
+    double ms_sum = 0.0;
+    if (!c->progress) {
+        WV_TRY(enqueue_sum(c, sh, st, 0, UINT64_MAX));
+        WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
+        WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
+        ms_sum = elapsed(c->ev[EV_PLAN], c->ev[EV_SUM]);
+    } else {
+        uint64_t host[8];
+        WV_HIP(hipMemcpyAsync(host, c->scal.ptr, sizeof(host), hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+        const uint64_t total = host[4], chunk = host[1];
+        const uint64_t per = std::max<uint64_t>(64, (c->launch_terms / std::max<uint64_t>(chunk, 1)) & ~63ull);
+        for (uint64_t b = 0; b < total; b += per) {
+            const uint64_t e = b + per >= total ? UINT64_MAX : b + per;   // ranges stay 64-aligned
+            WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
+            WV_TRY(enqueue_sum(c, sh, st, b, e));
+            WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
+            WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
+            ms_sum += elapsed(c->ev[EV_SUM0], c->ev[EV_SUM]);
+            c->progress(c->progress_user, std::min(total, b + per), total);
+        }
+    }
+    WV_HIP(launch_reduce(st, as<SegRec>(c->segs), as<uint64_t>(c->off), (uint32_t)sh.nseg, as<PrimeRec>(c->pr),
+                         as<Pair>(c->partials), as<Pair>(c->seg_pairs)));
+    WV_HIP(hipEventRecord(c->ev[EV_RED], st));
+    WV_HIP(launch_finalize(st, as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), sh.n, sh.nB, sh.nE, d_out));
+    WV_HIP(hipEventRecord(c->ev[EV_FINAL], st));
+    WV_HIP(hipEventSynchronize(c->ev[EV_FINAL]));
+    // statistics
+    uint64_t host[8];
+    WV_HIP(hipMemcpyAsync(host, c->scal.ptr, sizeof(host), hipMemcpyDeviceToHost, st));
+    WV_HIP(hipStreamSynchronize(st));
+    wv_stats &s = c->stats;
+    s.ms_plan += elapsed(c->ev[EV_PLAN0], c->ev[EV_PLAN]);
+    s.ms_sum += ms_sum;
+    s.ms_reduce += elapsed(c->ev[EV_SUM], c->ev[EV_RED]);
+    s.ms_finalize += elapsed(c->ev[EV_RED], c->ev[EV_FINAL]);
+    s.ms_total += elapsed(c->ev[EV_PLAN0], c->ev[EV_FINAL]);
+    s.n_primes += n;
+    s.n_sums += sh.nseg;
+    s.n_chunks += host[4];
+    s.n_terms += host[0];
+    s.n_terms_b += host[3];
+    s.chunk_terms = host[1];
+    s.block_k_b = (uint32_t)sum_variant_kb(c->variant);
+    s.block_k_e = (uint32_t)sum_variant_ke(c->variant);
+    s.grid = (uint32_t)c->sum_blocks[c->variant];
+    return WV_OK;
+}
+
+// ==========================================================================
+// sieve over segment descriptors
+// ==========================================================================
+
+void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d) {
+    if (hi <= lo || hi <= 5) return;
+    for (uint64_t L = lo & ~1ull; L < hi; L += kSegSpan) d.push_back(SegDesc{L, lo, hi});
+}
+
+// Prime counts of descs[0..ns) into counts; with keep_bits the prime bitmaps
+// stay in c->seg_bits for a following compaction (ns <= kMaxBatchSegs).
+int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts) {
+    hipStream_t st = c->stream;
+    WV_TRY(ensure(c, c->seg_desc, std::min<size_t>(ns, kSieveLaunch) * sizeof(SegDesc)));
+    WV_TRY(ensure(c, c->seg_counts, std::min<size_t>(ns, kSieveLaunch) * sizeof(uint32_t)));
+    if (keep_bits) WV_TRY(ensure(c, c->seg_bits, ns * kSegWords * sizeof(uint32_t)));
+    for (size_t b = 0; b < ns; b += kSieveLaunch) {
+        const size_t k = std::min<size_t>(kSieveLaunch, ns - b);
+        WV_HIP(hipMemcpyAsync(c->seg_desc.ptr, descs + b, k * sizeof(SegDesc), hipMemcpyHostToDevice, st));
+        WV_HIP(launch_seg_sieve(st, as<SegDesc>(c->seg_desc), (unsigned)k, as<uint32_t>(c->base_primes), c->n_base,
+                                keep_bits ? as<uint32_t>(c->seg_bits) : nullptr, as<uint32_t>(c->seg_counts)));
+        WV_HIP(hipMemcpyAsync(counts + b, c->seg_counts.ptr, k * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+    }
+    return WV_OK;
+}
+
+// Primes of descs[0..ns) (bitmaps already in c->seg_bits) into c->primes.
+int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out) {
+    hipStream_t st = c->stream;
+    std::vector<uint64_t> offs(ns + 1, 0);
+    for (size_t i = 0; i < ns; i++) offs[i + 1] = offs[i] + counts[i];
+    *np_out = offs[ns];
+    if (offs[ns] == 0) return WV_OK;
+    WV_TRY(ensure(c, c->seg_off, (ns + 1) * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->primes, offs[ns] * sizeof(uint64_t)));
+    WV_HIP(hipMemcpyAsync(c->seg_desc.ptr, descs, ns * sizeof(SegDesc), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(c->seg_off.ptr, offs.data(), (ns + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    WV_HIP(launch_seg_compact(st, as<SegDesc>(c->seg_desc), (unsigned)ns, as<uint32_t>(c->seg_bits),
+                              as<uint64_t>(c->seg_off), as<uint64_t>(c->primes)));
+    return WV_OK;
+}
+
+// All primes of the descriptor list (in order) and their residues into out.
+// Descriptors are grouped into batches of at most kMaxBatchSegs segments and
+// about kMaxBatchPrimes primes; each batch is one plan and one persistent
+// term-sum launch (or one split launch sequence under a progress callback).
+int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts, wv_result *out) {
+    hipStream_t st = c->stream;
+    size_t i = 0, written = 0;
+    while (i < descs.size()) {
+        size_t j = i;
+        uint64_t np = 0;
+        while (j < descs.size() && j - i < kMaxBatchSegs && (np == 0 || np + counts[j] <= kMaxBatchPrimes))
+            np += counts[j++];
+        if (np == 0) {
+            i = j;
+            continue;
+        }
+        WV_HIP(hipEventRecord(c->ev[EV_START], st));
+        std::vector<uint32_t> again(j - i);
+        WV_TRY(sieve_count(c, descs.data() + i, j - i, true, again.data()));
+        for (size_t k = 0; k < again.size(); k++)
+            if (again[k] != counts[i + k]) return WV_EHIP;   // the sieve is deterministic
+        uint64_t got = 0;
+        WV_TRY(compact(c, descs.data() + i, j - i, counts.data() + i, &got));
+        WV_HIP(hipEventRecord(c->ev[EV_SIEVE], st));
+        WV_HIP(hipEventSynchronize(c->ev[EV_SIEVE]));
+        c->stats.ms_sieve += elapsed(c->ev[EV_START], c->ev[EV_SIEVE]);
+        WV_TRY(ensure(c, c->results, got * sizeof(wv_result)));
+        WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)got, as<wv_result>(c->results)));
+        WV_HIP(hipMemcpyAsync(out + written, c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+        written += got;
+        i = j;
+    }
+    return WV_OK;
+}
+
+void pick_tuned(wv_ctx *c, uint64_t pmax) {
+    if (c->shape_forced || pmax < 2) return;
+    int b = 63 - __builtin_clzll(pmax);
+    for (const TuneEntry &t : c->tune)
+        if (t.log2p == b) {
+            c->variant = t.variant;
+            c->chunk_auto = t.chunk;
+            return;
+        }
+}
+
+}  // namespace wv
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+
+extern "C" {
+
+const char *wv_strerror(int status) {
+    switch (status) {
+    case WV_OK: return "ok";
+    case WV_EINVAL: return "invalid argument";
+    case WV_EDOMAIN: return "prime outside [5, 2^40)";
+    case WV_ENOTPRIME: return "input is not prime";
+    case WV_ETRUNC: return "output buffer too small";
+    case WV_ENOMEM: return "device out of memory";
+    case WV_EHIP: return "HIP runtime error";
+    case WV_EBUSY: return "request not finished";
+    default: return "unknown status";
+    }
+}
+
+int wv_table_info(int id, int *n_sums, int64_t *lhs, uint64_t *cost_num, uint64_t *cost_den) {
+    if (id < 0 || id >= kNumTables) return WV_EINVAL;
+    if (n_sums) *n_sums = kTables[id].n;
+    if (lhs) *lhs = kTables[id].lhs;
+    if (cost_num) *cost_num = kTables[id].cost_num;
+    if (cost_den) *cost_den = kTables[id].cost_den;
+    return WV_OK;
+}
+
+int wv_table_term(int id, int i, int64_t *coef, uint32_t *xa, uint32_t *xb, uint32_t *ya, uint32_t *yb) {
+    if (id < 0 || id >= kNumTables || i < 0 || i >= kTables[id].n) return WV_EINVAL;
+    const TermDef &t = kTables[id].t[i];
+    if (coef) *coef = t.coef;
+    if (xa) *xa = t.xa;
+    if (xb) *xb = t.xb;
+    if (ya) *ya = t.ya;
+    if (yb) *yb = t.yb;
+    return WV_OK;
+}
+
+int wv_create(int hip_device, wv_ctx **out) {
+    if (!out) return WV_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return WV_EINVAL;
+    wv_ctx *c = new (std::nothrow) wv_ctx();
+    if (!c) return WV_ENOMEM;
+    c->device = hip_device;
+    int rc = WV_OK;
+    do {
+        if (hipSetDevice(hip_device) != hipSuccess) { rc = WV_EHIP; break; }
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { rc = WV_EHIP; break; }
+        for (int i = 0; i < EV_COUNT; i++)
+            if (hipEventCreate(&c->ev[i]) != hipSuccess) { rc = WV_EHIP; break; }
+        if (rc) break;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { rc = WV_EHIP; break; }
+        c->num_cus = prop.multiProcessorCount;
+        snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
+        for (int v = 0; v < num_sum_variants(); v++) {
+            int per_cu = 0;
+            if (sum_variant_occupancy(v, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+            c->sum_blocks[v] = c->num_cus * per_cu;
+        }
+        if (upload_tables() != hipSuccess) { rc = WV_EHIP; break; }
+        if ((rc = ensure(c, c->base_primes, kBaseLimit / 2 * sizeof(uint32_t))) != WV_OK) break;
+        if ((rc = ensure(c, c->scal, 8 * sizeof(uint64_t))) != WV_OK) break;
+        if (launch_base_sieve(c->stream, as<uint32_t>(c->base_primes), as<uint32_t>(c->scal)) != hipSuccess) {
+            rc = WV_EHIP;
+            break;
+        }
+        uint32_t nb = 0;
+        if (hipMemcpyAsync(&nb, c->scal.ptr, sizeof(nb), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) { rc = WV_EHIP; break; }
+        c->n_base = nb;
+    } while (0);
+    if (rc != WV_OK) {
+        wv_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return WV_OK;
+}
+
+int wv_destroy(wv_ctx *c) {
+    if (!c) return WV_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (GraphEntry &g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    DevBuf *bufs[] = {&c->base_primes, &c->primes, &c->pr, &c->segs, &c->terms, &c->cnt, &c->off, &c->tiles,
+                      &c->scal, &c->partials, &c->seg_pairs, &c->results, &c->seg_counts, &c->seg_bits,
+                      &c->seg_off, &c->seg_desc, &c->pad_primes};
+    for (DevBuf *b : bufs)
+        if (b->ptr) (void)hipFree(b->ptr);
+    for (int i = 0; i < EV_COUNT; i++)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return WV_OK;
+}
+
+int wv_set_tables(wv_ctx *c, int b_table, int e_table) {
+    if (!c) return WV_EINVAL;
+    if (b_table < WV_TABLE_BB1 || b_table > WV_TABLE_BB30) return WV_EINVAL;
+    if (e_table < WV_TABLE_EE3 || e_table > WV_TABLE_EE33) return WV_EINVAL;
+    c->tb = b_table;
+    c->te = e_table;
+    return WV_OK;
+}
+
+int wv_set_chunk_terms(wv_ctx *c, uint64_t chunk_terms) {
+    if (!c || (chunk_terms % 64) != 0) return WV_EINVAL;
+    c->chunk_cfg = chunk_terms;
+    return WV_OK;
+}
+
+int wv_set_block(wv_ctx *c, int kb, int ke) {
+    if (!c) return WV_EINVAL;
+    if (kb == 0 && ke == 0) {
+        c->shape_forced = false;
+        c->variant = kDefaultVariant;
+        return WV_OK;
+    }
+    for (int v = 0; v < num_sum_variants(); v++) {
+        if (sum_variant_kb(v) == kb && sum_variant_ke(v) == ke) {
+            c->variant = v;
+            c->shape_forced = true;
+            return WV_OK;
+        }
+    }
+    return WV_EINVAL;
+}
+
+int wv_set_progress(wv_ctx *c, wv_progress_fn fn, void *user, uint64_t terms_per_launch) {
+    if (!c) return WV_EINVAL;
+    c->progress = fn;
+    c->progress_user = user;
+    c->launch_terms = terms_per_launch ? terms_per_launch : (1ull << 44);
+    return WV_OK;
+}
+
+int wv_get_stats(const wv_ctx *c, wv_stats *out) {
+    if (!c || !out) return WV_EINVAL;
+    *out = c->stats;
+    return WV_OK;
+}
+
+int wv_count_primes(wv_ctx *c, uint64_t lo, uint64_t hi, uint64_t *n) {
+    if (!c || !n || lo > hi) return WV_EINVAL;
+    if (hi > WV_P_MAX) return WV_EDOMAIN;
+    WV_TRY(check_device(c));
+    *n = 0;
+    std::vector<SegDesc> d;
+    window_descs(lo, hi, d);
+    if (d.empty()) return WV_OK;
+    std::vector<uint32_t> counts(d.size());
+    WV_TRY(sieve_count(c, d.data(), d.size(), false, counts.data()));
+    uint64_t t = 0;
+    for (uint32_t k : counts) t += k;
+    *n = t;
+    return WV_OK;
+}
+
+int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t nwin, wv_result *out, size_t cap,
+                      size_t *n_out, size_t *win_off) {
+    if (!c || !n_out || (nwin && (!lo || !hi))) return WV_EINVAL;
+    for (size_t w = 0; w < nwin; w++) {
+        if (lo[w] > hi[w]) return WV_EINVAL;
+        if (hi[w] > WV_P_MAX) return WV_EDOMAIN;
+    }
+    WV_TRY(check_device(c));
+    std::vector<SegDesc> d;
+    std::vector<size_t> first(nwin + 1, 0);
+    uint64_t pmax = 0;
+    for (size_t w = 0; w < nwin; w++) {
+        first[w] = d.size();
+        window_descs(lo[w], hi[w], d);
+        if (hi[w] > lo[w]) pmax = std::max(pmax, hi[w] - 1);
+    }
+    first[nwin] = d.size();
+    std::vector<uint32_t> counts(d.size());
+    if (!d.empty()) WV_TRY(sieve_count(c, d.data(), d.size(), false, counts.data()));
+    uint64_t total = 0;
+    for (size_t w = 0; w < nwin; w++) {
+        if (win_off) win_off[w] = (size_t)total;
+        for (size_t k = first[w]; k < first[w + 1]; k++) total += counts[k];
+    }
+    if (win_off) win_off[nwin] = (size_t)total;
+    *n_out = (size_t)total;
+    if (total > cap) return WV_ETRUNC;
+    if (total > 0 && !out) return WV_EINVAL;
+    c->stats = wv_stats{};
+    if (total == 0) return WV_OK;
+    pick_tuned(c, pmax);
+    return search_descs(c, d, counts, out);
+}
+
+int wv_search_range(wv_ctx *c, uint64_t lo, uint64_t hi, wv_result *out, size_t cap, size_t *n_out,
+                    uint64_t *hits, size_t hit_cap, size_t *n_hits) {
+    if (!c || !n_out || lo > hi || (hit_cap && !hits)) return WV_EINVAL;
+    if (n_hits) *n_hits = 0;
+    WV_TRY(wv_search_windows(c, &lo, &hi, 1, out, cap, n_out, nullptr));
+    size_t nh = 0;
+    for (size_t i = 0; i < *n_out; i++) {
+        if (out[i].flags) {
+            if (nh < hit_cap) hits[nh] = out[i].p;
+            nh++;
+        }
+    }
+    if (n_hits) *n_hits = nh;
+    return WV_OK;
+}
+
+int wv_eval_primes(wv_ctx *c, const uint64_t *primes, size_t n, wv_result *out) {
+    if (!c) return WV_EINVAL;
+    if (n == 0) return WV_OK;
+    if (!primes || !out) return WV_EINVAL;
+    if (n > 0xFFFFFFFFull) return WV_EINVAL;
+    uint64_t pmax = 0;
+    for (size_t i = 0; i < n; i++) {
+        if (primes[i] < 5 || primes[i] >= WV_P_MAX) return WV_EDOMAIN;
+        if (!is_prime_u64(primes[i])) return WV_ENOTPRIME;
+        pmax = std::max(pmax, primes[i]);
+    }
+    WV_TRY(check_device(c));
+    c->stats = wv_stats{};
+    pick_tuned(c, pmax);
+    WV_TRY(ensure(c, c->primes, n * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->results, n * sizeof(wv_result)));
+    WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)n, as<wv_result>(c->results)));
+    WV_HIP(hipMemcpyAsync(out, c->results.ptr, n * sizeof(wv_result), hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipStreamSynchronize(c->stream));
+    return WV_OK;
+}
+
+int wv_eval_sums(wv_ctx *c, const uint64_t *primes, size_t n, uint64_t *out_b, uint64_t *out_e) {
+    if (!c) return WV_EINVAL;
+    if (n == 0) return WV_OK;
+    if (!primes || !out_b || !out_e || n > 0xFFFFFFFFull) return WV_EINVAL;
+    for (size_t i = 0; i < n; i++) {
+        if (primes[i] < 5 || primes[i] >= WV_P_MAX) return WV_EDOMAIN;
+        if (!is_prime_u64(primes[i])) return WV_ENOTPRIME;
+    }
+    WV_TRY(check_device(c));
+    c->stats = wv_stats{};
+    BatchShape sh;
+    WV_TRY(batch_shape(c, (uint32_t)n, &sh));
+    WV_TRY(ensure(c, c->primes, n * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->results, std::max(n * sizeof(wv_result), (size_t)sh.nseg * sizeof(uint64_t))));
+    WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)n, as<wv_result>(c->results)));
+    // the results buffer is free again once finalize has run: reuse it for the sums
+    uint64_t *d_sums = as<uint64_t>(c->results);
+    WV_HIP(launch_sum_values(c->stream, as<SegRec>(c->segs), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), sh.nseg,
+                             d_sums));
+    WV_HIP(hipMemcpyAsync(out_b, d_sums, (size_t)n * sh.nB * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipMemcpyAsync(out_e, d_sums + (size_t)n * sh.nB, (size_t)n * sh.nE * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipStreamSynchronize(c->stream));
+    return WV_OK;
+}
+
+// Device-pointer entry point: pads the batch to a power of two (padding slots
+// hold 0, which the plan rejects and which cost no term work), and replays a
+// captured graph of the whole plan -> finalize sequence for that size.
+int wv_eval_primes_async(wv_ctx *c, const uint64_t *d_primes, size_t n, wv_result *d_out, void *hip_stream) {
+    if (!c) return WV_EINVAL;
+    if (n == 0) return WV_OK;
+    if (!d_primes || !d_out || n > 0x7FFFFFFFull) return WV_EINVAL;
+    WV_TRY(check_device(c));
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint64_t n_pad = 64;
+    while (n_pad < n) n_pad <<= 1;
+    BatchShape sh;
+    WV_TRY(batch_shape(c, (uint32_t)n_pad, &sh));
+    WV_TRY(prepare(c, sh));
+    WV_TRY(ensure(c, c->pad_primes, n_pad * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->results, n_pad * sizeof(wv_result)));
+    hipGraphExec_t exec = nullptr;
+    const uint64_t chunk = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    for (GraphEntry &g : c->graphs)
+        if (g.n_pad == n_pad && g.gen == c->gen && g.variant == c->variant && g.tb == c->tb && g.te == c->te &&
+            g.chunk == chunk)
+            exec = g.exec;
+    if (!exec) {
+        // the capture stream must be idle: earlier work on it may still run
+        WV_HIP(hipStreamSynchronize(c->stream));
+        hipGraph_t graph = nullptr;
+        WV_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_plan(c, as<uint64_t>(c->pad_primes), sh, c->stream);
+        if (rc == WV_OK) rc = enqueue_sum(c, sh, c->stream, 0, UINT64_MAX);
+        if (rc == WV_OK) rc = enqueue_finish(c, sh, c->stream, as<wv_result>(c->results));
+        hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        if (rc != WV_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        WV_HIP(e);
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        WV_HIP(e);
+        c->graphs.push_back(GraphEntry{n_pad, c->gen, c->variant, c->tb, c->te, chunk, exec});
+    }
+    WV_HIP(launch_copy_pad(st, d_primes, n, as<uint64_t>(c->pad_primes), n_pad));
+    WV_HIP(hipGraphLaunch(exec, st));
+    WV_HIP(launch_copy_results(st, as<wv_result>(c->results), n, d_out));
+    return WV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// wv_ctx.hpp -- the context behind the opaque wv_ctx handle and the host-side
+// pipeline helpers shared by the C ABI (wv_capi.hip), the autotuner
+// (wv_tune.hip) and the request server (wv_server.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "wv_internal.hpp"
+#include "wv_tables.hpp"
+#include "wvprime.h"
+
+#define WV_TRY(expr)                  \
+    do {                              \
+        int _rc = (expr);             \
+        if (_rc != WV_OK) return _rc; \
+    } while (0)
+
+#define WV_HIP(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (expr);                                                                       \
+        if (_e != hipSuccess) {                                                                       \
+            if (getenv("WV_DEBUG"))                                                                   \
+                fprintf(stderr, "wvprime: %s:%d %s: %s\n", __FILE__, __LINE__, #expr, hipGetErrorString(_e)); \
+            return _e == hipErrorOutOfMemory ? WV_ENOMEM : WV_EHIP;                                   \
+        }                                                                                             \
+    } while (0)
+
+namespace wv {
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+template <class T>
+T *as(DevBuf &b) { return reinterpret_cast<T *>(b.ptr); }
+
+enum { EV_START, EV_SIEVE, EV_PLAN0, EV_PLAN, EV_SUM0, EV_SUM, EV_RED, EV_FINAL, EV_COUNT };
+
+constexpr uint64_t kDefaultChunk = 1ull << 16;
+constexpr uint64_t kMaxChunks = 1ull << 24;      // partial pairs held at once (256 MiB)
+constexpr size_t kMaxBatchSegs = 64;             // sieve segments per search batch (4 MiB of bitmaps)
+constexpr uint64_t kMaxBatchPrimes = 1ull << 19; // primes per search batch
+constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
+constexpr int kDefaultVariant = 2;               // block shape 8/8
+
+struct BatchShape {
+    uint32_t n;          // primes
+    int nB, nE;          // slots per prime on each side
+    uint64_t nseg;       // (prime, sum) slots
+    uint64_t cap;        // partial-pair capacity
+};
+
+struct GraphEntry {
+    uint64_t n_pad, gen;
+    int variant, tb, te;
+    uint64_t chunk;
+    hipGraphExec_t exec;
+};
+
+struct TuneEntry {
+    int log2p;           // primes in [2^log2p, 2^(log2p+1))
+    int variant;
+    uint64_t chunk;
+    double terms_per_s;
+};
+
+}  // namespace wv
+
+struct wv_ctx {
+    int device = 0;
+    char arch[64] = {};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[wv::EV_COUNT] = {};
+    int tb = WV_TABLE_BB30, te = WV_TABLE_EE33;
+    uint64_t chunk_cfg = 0;                       // user setting (0: automatic)
+    uint64_t chunk_auto = wv::kDefaultChunk;      // automatic value (tuned)
+    int variant = wv::kDefaultVariant;            // term-sum block shape
+    bool shape_forced = false;
+    int num_cus = 0;
+    int sum_blocks[16] = {};                      // persistent grid per block shape
+    uint32_t n_base = 0;
+    uint64_t gen = 0;                             // bumped on every device reallocation
+    wv::DevBuf base_primes, primes, pr, segs, terms, cnt, off, tiles, scal, partials, seg_pairs, results,
+        seg_counts, seg_bits, seg_off, seg_desc, pad_primes;
+    wv_stats stats{};
+    wv_progress_fn progress = nullptr;
+    void *progress_user = nullptr;
+    uint64_t launch_terms = 1ull << 44;
+    std::vector<wv::GraphEntry> graphs;
+    std::vector<wv::TuneEntry> tune;
+};
+
+namespace wv {
+
+int ensure(wv_ctx *c, DevBuf &b, size_t bytes);
+bool is_prime_u64(uint64_t n);
+int check_device(wv_ctx *c);
+int batch_shape(const wv_ctx *c, uint32_t n, BatchShape *sh);
+int prepare(wv_ctx *c, const BatchShape &sh);
+int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st);
+int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end);
+int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out);
+int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, wv_result *d_out);
+void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d);
+int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts);
+int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out);
+int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts,
+                 wv_result *out);
+void pick_tuned(wv_ctx *c, uint64_t pmax);
+
+}  // namespace wv

@@ -1,0 +1,93 @@
+// wv_internal.hpp -- records shared by the device kernels and the host code
+// of libwvprime.so, and the host-side launchers of the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "wvprime.h"
+
+namespace wv {
+
+constexpr int kSegLog = 20;                    // sieve segment: 2^20 integers
+constexpr uint64_t kSegSpan = 1ull << kSegLog;
+constexpr int kSegBits = 1 << (kSegLog - 1);   // odd integers per segment
+constexpr int kSegWords = kSegBits / 32;       // 16384 words = 64 KiB of LDS
+constexpr uint32_t kBaseLimit = 1u << 20;      // base primes below 2^20 cover p < 2^40
+constexpr int kScanTile = 1024;                // elements per scan workgroup
+
+// One sieve segment: the 2^20 integers [L, L + 2^20) (L even), of which the
+// window [lo, hi) keeps the primes p >= 5.  Segments of several windows can
+// share one launch (batched search).
+struct SegDesc {
+    uint64_t L, lo, hi;
+};
+
+struct PrimeRec {      // 32 bytes
+    uint64_t p;
+    uint64_t r2;       // R^2 mod p
+    uint64_t one;      // R mod p
+    uint32_t ninv;     // -p^-1 mod 2^32
+    uint8_t tb, te;    // congruences used
+    uint8_t ok, pad;
+};
+
+struct SegRec {        // one (prime, sum)
+    uint64_t lo;       // first s
+    uint64_t len;      // number of s; 0 for an unused slot
+    uint32_t prime;    // index in the batch
+    uint32_t deg;      // 3 (B) or 2 (E)
+};
+
+struct Pair {
+    uint64_t c0, c1;
+};
+
+// ---- launchers (wv_kernels.hip) ---------------------------------------------
+// Every launcher enqueues on `st` and returns hipGetLastError().
+
+hipError_t upload_tables();
+hipError_t launch_base_sieve(hipStream_t st, uint32_t *out, uint32_t *n_out);
+hipError_t launch_seg_sieve(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bp, uint32_t n_bp,
+                            uint32_t *bits_out, uint32_t *counts);
+hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bits,
+                              const uint64_t *off, uint64_t *out);
+// exclusive scan of n values into out[0..n], out[n] = total; tiles holds
+// ceil(n / kScanTile) entries
+hipError_t launch_scan(hipStream_t st, const uint64_t *in, uint64_t n, uint64_t *out, uint64_t *tiles);
+hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int tb, int te, int nB, int nE,
+                       PrimeRec *pr, SegRec *segs, uint64_t *terms, uint32_t prime_base);
+hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg,
+                             uint64_t cap, uint64_t *chunk_out);
+hipError_t launch_chunk_count(hipStream_t st, const uint64_t *terms, uint64_t nseg, const uint64_t *chunk,
+                              uint64_t *cnt);
+hipError_t launch_set_u64(hipStream_t st, uint64_t *dst, int n, uint64_t value);
+hipError_t launch_copy_u64(hipStream_t st, const uint64_t *src, uint64_t *dst, int n);
+// Persistent term sums over the chunks [begin, min(end, total)) of the plan;
+// the counter at *counter must hold `begin` (a multiple of 64).
+int num_sum_variants();
+int sum_variant_kb(int v);
+int sum_variant_ke(int v);
+hipError_t sum_variant_occupancy(int v, int *blocks_per_cu);
+hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, const uint64_t *off, uint32_t nseg,
+                      const PrimeRec *pr, const uint64_t *chunk, Pair *partials, unsigned long long *counter,
+                      uint64_t end);
+hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
+                         const Pair *partials, Pair *seg_pairs);
+hipError_t launch_finalize(hipStream_t st, const PrimeRec *pr, const Pair *sp, uint32_t n, int nB, int nE,
+                           wv_result *out);
+hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec *pr, const Pair *sp, uint64_t nseg,
+                             uint64_t *out);
+// acc[target[t]] <- acc[target[t]] (x) tp[t] (eqnCombinePairs), t < ntask
+hipError_t launch_fold(hipStream_t st, const SegRec *tasks, const uint32_t *target, const Pair *tp, uint32_t ntask,
+                       const PrimeRec *pr, Pair *acc);
+hipError_t launch_fill_pairs(hipStream_t st, Pair *p, uint64_t n, uint64_t c0, uint64_t c1);
+// out[i] = i < n ? src[i] : 0  (zero marks a padding slot the plan rejects)
+hipError_t launch_copy_pad(hipStream_t st, const uint64_t *src, uint64_t n, uint64_t *dst, uint64_t n_pad);
+hipError_t launch_copy_results(hipStream_t st, const wv_result *src, uint64_t n, wv_result *dst);
+
+// table sizes (host copy of the compiled tables)
+int table_slots(int id);
+
+}  // namespace wv

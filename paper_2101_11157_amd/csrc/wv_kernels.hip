@@ -1,4 +1,4 @@
-// wv_kernels.hip -- HIP kernels and the C ABI of libwvprime.so (gfx950).
+// wv_kernels.hip -- HIP kernels of libwvprime.so (gfx950) and their launchers.
 //
 // Pipeline for a batch of primes (Booker, Hathi, Mossinghoff, Trudgian,
 // arXiv:2101.11157):
@@ -27,8 +27,8 @@
 
 #include "mont.hpp"
 #include "sum_core.hpp"
+#include "wv_internal.hpp"
 #include "wv_tables.hpp"
-#include "wvprime.h"
 
 namespace wv {
 
@@ -36,11 +36,6 @@ namespace wv {
 // constants and records
 // --------------------------------------------------------------------------
 
-constexpr int kSegLog = 20;                    // sieve segment: 2^20 integers
-constexpr uint64_t kSegSpan = 1ull << kSegLog;
-constexpr int kSegBits = 1 << (kSegLog - 1);   // odd integers per segment
-constexpr int kSegWords = kSegBits / 32;       // 16384 words = 64 KiB of LDS
-constexpr uint32_t kBaseLimit = 1u << 20;      // base primes below 2^20 cover p < 2^40
 constexpr int kTotalTerms = 256;               // all tables' terms together
 
 struct DevTerm {
@@ -54,26 +49,6 @@ struct DevTable {
 
 __constant__ DevTerm c_terms[kTotalTerms];
 __constant__ DevTable c_tables[WV_TABLE_COUNT];
-
-struct PrimeRec {      // 32 bytes
-    uint64_t p;
-    uint64_t r2;       // R^2 mod p
-    uint64_t one;      // R mod p
-    uint32_t ninv;     // -p^-1 mod 2^32
-    uint8_t tb, te;    // congruences used
-    uint8_t ok, pad;
-};
-
-struct SegRec {        // one (prime, sum)
-    uint64_t lo;       // first s
-    uint64_t len;      // number of s; 0 for an unused slot
-    uint32_t prime;    // index in the batch
-    uint32_t deg;      // 3 (B) or 2 (E)
-};
-
-struct Pair {
-    uint64_t c0, c1;
-};
 
 __device__ __forceinline__ Mont mont_of(const PrimeRec &r) {
     Mont m;
@@ -170,19 +145,20 @@ __global__ void __launch_bounds__(1024) k_base_sieve(uint32_t *out, uint32_t *n_
     if (tid == 1023) *n_out = scan[1023];
 }
 
-// Segment `blockIdx.x` covers [L, L + 2^20) with L = base + blockIdx.x * 2^20
-// (base even); bit i stands for L + 2i + 1.  Marks odd multiples of every odd
-// base prime q with q^2 < min(L + 2^20, hi), then keeps the primes p with
-// max(lo, 5) <= p < hi.  Writes the count to counts[seg] and, when bits_out is
-// non-null, the prime bitmap (1 = prime) to bits_out + seg * kSegWords.
-__global__ void __launch_bounds__(1024) k_seg_sieve(uint64_t lo, uint64_t hi, uint64_t base,
+// Segment desc[blockIdx.x]; bit i stands for L + 2i + 1.  Marks odd multiples
+// of every odd base prime q with q^2 < min(L + 2^20, hi), then keeps the
+// primes p with max(lo, 5) <= p < hi.  Writes the count to counts[seg] and,
+// when bits_out is non-null, the prime bitmap (1 = prime) to
+// bits_out + seg * kSegWords.
+__global__ void __launch_bounds__(1024) k_seg_sieve(const SegDesc *__restrict__ desc,
                                                     const uint32_t *__restrict__ bp, uint32_t n_bp,
                                                     uint32_t *__restrict__ bits_out,
                                                     uint32_t *__restrict__ counts) {
     __shared__ uint32_t bits[kSegWords];
     __shared__ uint32_t red[16];
     const int tid = threadIdx.x;
-    const uint64_t L = base + (uint64_t)blockIdx.x * kSegSpan;
+    const SegDesc d = desc[blockIdx.x];
+    const uint64_t L = d.L, lo = d.lo, hi = d.hi;
     const uint64_t H = min(L + kSegSpan, hi);
     for (int w = tid; w < kSegWords; w += 1024) bits[w] = 0;
     __syncthreads();
@@ -236,17 +212,17 @@ __global__ void __launch_bounds__(1024) k_seg_sieve(uint64_t lo, uint64_t hi, ui
         for (int i = 0; i < 16; i++) t += red[i];
         counts[blockIdx.x] = t;
     }
-    (void)H;
 }
 
 // Writes the primes of segment blockIdx.x, ascending, at out + off[seg].
-__global__ void __launch_bounds__(1024) k_seg_compact(uint64_t base, const uint32_t *__restrict__ bits_in,
+__global__ void __launch_bounds__(1024) k_seg_compact(const SegDesc *__restrict__ desc,
+                                                      const uint32_t *__restrict__ bits_in,
                                                       const uint64_t *__restrict__ off,
                                                       uint64_t *__restrict__ out) {
     __shared__ uint32_t scan[1024];
     const int tid = threadIdx.x;
     const uint32_t *bits = bits_in + (size_t)blockIdx.x * kSegWords;
-    const uint64_t L = base + (uint64_t)blockIdx.x * kSegSpan;
+    const uint64_t L = desc[blockIdx.x].L;
     uint32_t cnt = 0;
     for (int w = tid * 16; w < tid * 16 + 16; w++) cnt += __popc(bits[w]);
     scan[tid] = cnt;
@@ -271,8 +247,6 @@ __global__ void __launch_bounds__(1024) k_seg_compact(uint64_t base, const uint3
 // --------------------------------------------------------------------------
 // exclusive scan of uint64 (three passes)
 // --------------------------------------------------------------------------
-
-constexpr int kScanTile = 1024;   // 256 threads x 4
 
 __global__ void __launch_bounds__(256) k_scan_tiles(const uint64_t *__restrict__ in, uint64_t n,
                                                     uint64_t *__restrict__ out, uint64_t *__restrict__ tile_sum) {
@@ -342,9 +316,13 @@ __device__ __forceinline__ uint64_t smod_dev(int64_t a, uint64_t p) {
 
 // One thread per prime.  Slot layout: B sums of prime i at i*nB + j, E sums at
 // n*nB + i*nE + j (all Bernoulli work first, then all Euler work).
+// pr, segs and terms point at the batch's first entries; `prime_base` is added
+// to the prime index stored in each SegRec (the batch's offset in a larger
+// prime array, as in the request server's pool).
 __global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ primes, uint32_t n, int tb_cfg,
                                               int te_cfg, int nB, int nE, PrimeRec *__restrict__ pr,
-                                              SegRec *__restrict__ segs, uint64_t *__restrict__ terms) {
+                                              SegRec *__restrict__ segs, uint64_t *__restrict__ terms,
+                                              uint32_t prime_base) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t p = primes[i];
@@ -366,7 +344,7 @@ __global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ prime
         for (int j = 0; j < nslots; j++) {
             const size_t slot = side == 0 ? (size_t)i * nB + j : (size_t)n * nB + (size_t)i * nE + j;
             SegRec s;
-            s.prime = i;
+            s.prime = prime_base + i;
             s.deg = (uint32_t)t.deg;
             s.lo = 1;
             s.len = 0;
@@ -382,6 +360,26 @@ __global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ prime
             terms[slot] = s.len;
         }
     }
+}
+
+__global__ void k_set_u64(uint64_t *p, int n, uint64_t v) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
+}
+
+__global__ void k_copy_u64(const uint64_t *__restrict__ s, uint64_t *__restrict__ d, int n) {
+    if ((int)threadIdx.x < n) d[threadIdx.x] = s[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) k_copy_pad(const uint64_t *__restrict__ src, uint64_t n,
+                                                  uint64_t *__restrict__ dst, uint64_t n_pad) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n_pad) dst[i] = i < n ? src[i] : 0;
+}
+
+__global__ void __launch_bounds__(256) k_copy_results(const wv_result *__restrict__ src, uint64_t n,
+                                                      wv_result *__restrict__ dst) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 // Chunk size: at least `chunk_cfg` terms, and large enough that the total
@@ -402,10 +400,6 @@ __global__ void __launch_bounds__(256) k_chunk_count(const uint64_t *__restrict_
     if (i >= nseg) return;
     const uint64_t C = *chunk;
     cnt[i] = (terms[i] + C - 1) / C;
-}
-
-__global__ void k_zero_u64(uint64_t *p, int n) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 // --------------------------------------------------------------------------
@@ -431,8 +425,9 @@ template <int KB, int KE>
 __global__ void __launch_bounds__(256) k_sum(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
                                              uint32_t nseg, const PrimeRec *__restrict__ pr,
                                              const uint64_t *__restrict__ chunk_ptr, Pair *__restrict__ partials,
-                                             unsigned long long *__restrict__ counter) {
-    const uint64_t total = off[nseg];
+                                             unsigned long long *__restrict__ counter, uint64_t end) {
+    // chunks [counter start, min(end, total)); end is a multiple of 64 or past the total
+    const uint64_t total = min(off[nseg], end);
     const uint64_t C = *chunk_ptr;
     const int lane = threadIdx.x & 63;
     // A wave can take at most total/64 + 1 batches; the bound is a second exit.
@@ -472,7 +467,7 @@ __global__ void __launch_bounds__(256) k_sum(const SegRec *__restrict__ segs, co
 }
 
 typedef void (*SumKernel)(const SegRec *, const uint64_t *, uint32_t, const PrimeRec *, const uint64_t *, Pair *,
-                          unsigned long long *);
+                          unsigned long long *, uint64_t);
 
 struct SumVariant {
     int kb, ke;
@@ -545,6 +540,24 @@ __device__ uint64_t combine_residue(const DevTable &t, const Pair *__restrict__ 
     return red1(mmul(N, inv, m), p);                                // N / (D L)
 }
 
+// acc[target[t]] <- acc[target[t]] * tp[t] in F_p[z]/(z^2) (eqnCombinePairs),
+// one thread per task; each target appears at most once per launch.
+__global__ void __launch_bounds__(256) k_fold(const SegRec *__restrict__ tasks, const uint32_t *__restrict__ target,
+                                              const Pair *__restrict__ tp, uint32_t ntask,
+                                              const PrimeRec *__restrict__ pr, Pair *__restrict__ acc) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= ntask) return;
+    const Mont m = mont_of(pr[tasks[t].prime]);
+    Pair a = acc[target[t]];
+    pair_mul(a.c0, a.c1, tp[t].c0, tp[t].c1, m);
+    acc[target[t]] = a;
+}
+
+__global__ void __launch_bounds__(256) k_fill_pairs(Pair *__restrict__ p, uint64_t n, uint64_t c0, uint64_t c1) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = Pair{c0, c1};
+}
+
 // S_j = c1_j / c0_j, canonical, for every (prime, sum) slot.
 __global__ void __launch_bounds__(256) k_sum_values(const SegRec *__restrict__ segs, const PrimeRec *__restrict__ pr,
                                                     const Pair *__restrict__ sp, uint64_t nseg,
@@ -581,125 +594,14 @@ __global__ void __launch_bounds__(256) k_finalize(const PrimeRec *__restrict__ p
     out[i] = r;
 }
 
-}  // namespace wv
 
 // ==========================================================================
-// host side
+// launchers
 // ==========================================================================
-
-using namespace wv;
-
-namespace {
-
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t cap = 0;
-};
-
-enum { EV_START, EV_SIEVE, EV_PLAN, EV_SUM, EV_REDUCE, EV_FINAL, EV_COUNT };
-
-constexpr uint64_t kDefaultChunk = 1ull << 16;
-constexpr uint64_t kMaxChunks = 1ull << 24;   // partial pairs held at once (256 MiB)
-constexpr uint64_t kWindowSegs = 4;           // sieve segments per search batch
-
-}  // namespace
-
-struct wv_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev[EV_COUNT] = {};
-    int tb = WV_TABLE_BB30, te = WV_TABLE_EE33;
-    uint64_t chunk_cfg = 0;
-    int num_cus = 0;
-    int variant = 2;                    // index into kSumVariants
-    int sum_blocks[16] = {};            // persistent grid per variant
-    uint32_t n_base = 0;
-    DevBuf base_primes, primes, pr, segs, terms, cnt, off, tiles, scal, partials, seg_pairs, results,
-        seg_counts, seg_bits, seg_off;
-    wv_stats stats{};
-};
-
-namespace {
-
-int hip_status(hipError_t e) { return e == hipSuccess ? WV_OK : WV_EHIP; }
-
-#define WV_TRY(expr)                         \
-    do {                                     \
-        int _rc = (expr);                    \
-        if (_rc != WV_OK) return _rc;        \
-    } while (0)
-#define WV_HIP(expr)                                             \
-    do {                                                         \
-        hipError_t _e = (expr);                                  \
-        if (_e != hipSuccess) {                                  \
-            if (getenv("WV_DEBUG"))                              \
-                fprintf(stderr, "wvprime: %s:%d %s: %s\n", __FILE__, __LINE__, #expr, hipGetErrorString(_e)); \
-            return _e == hipErrorOutOfMemory ? WV_ENOMEM : WV_EHIP; \
-        }                                                        \
-    } while (0)
-
-int ensure(DevBuf &b, size_t bytes) {
-    if (b.cap >= bytes && b.ptr) return WV_OK;
-    if (b.ptr) {
-        WV_HIP(hipFree(b.ptr));
-        b.ptr = nullptr;
-        b.cap = 0;
-    }
-    size_t want = std::max(bytes, (size_t)256);
-    WV_HIP(hipMalloc(&b.ptr, want));
-    b.cap = want;
-    return WV_OK;
-}
-
-template <class T>
-T *as(DevBuf &b) { return reinterpret_cast<T *>(b.ptr); }
-
-uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
-
-uint64_t powmod_h(uint64_t a, uint64_t e, uint64_t m) {
-    uint64_t r = 1 % m;
-    a %= m;
-    while (e) {
-        if (e & 1) r = mulmod_h(r, a, m);
-        a = mulmod_h(a, a, m);
-        e >>= 1;
-    }
-    return r;
-}
-
-// Deterministic Miller-Rabin for n < 2^64 (first twelve prime bases).
-bool is_prime_u64(uint64_t n) {
-    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
-    if (n < 2) return false;
-    for (uint64_t b : bases) {
-        if (n == b) return true;
-        if (n % b == 0) return false;
-    }
-    uint64_t d = n - 1;
-    int s = 0;
-    while (!(d & 1)) {
-        d >>= 1;
-        s++;
-    }
-    for (uint64_t a : bases) {
-        uint64_t x = powmod_h(a, d, n);
-        if (x == 1 || x == n - 1) continue;
-        bool comp = true;
-        for (int r = 1; r < s; r++) {
-            x = mulmod_h(x, x, n);
-            if (x == n - 1) {
-                comp = false;
-                break;
-            }
-        }
-        if (comp) return false;
-    }
-    return true;
-}
 
 int table_slots(int id) { return kTables[id].n; }
 
-int upload_tables() {
+hipError_t upload_tables() {
     DevTerm terms[kTotalTerms];
     DevTable tabs[WV_TABLE_COUNT];
     int off = 0;
@@ -715,406 +617,121 @@ int upload_tables() {
         }
         off += kTables[i].n;
     }
-    WV_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_terms), terms, sizeof(DevTerm) * off));
-    WV_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tables), tabs, sizeof(tabs)));
-    return WV_OK;
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_terms), terms, sizeof(DevTerm) * off);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_tables), tabs, sizeof(tabs));
 }
 
-// Exclusive scan of n uint64 at `in` into `out` (n+1 entries; out[n] = total).
-int scan_u64(wv_ctx *c, const uint64_t *in, uint64_t n, uint64_t *out, hipStream_t st) {
-    const uint64_t tiles = std::max<uint64_t>(1, (n + kScanTile - 1) / kScanTile);
-    WV_TRY(ensure(c->tiles, tiles * sizeof(uint64_t)));
-    uint64_t *ts = as<uint64_t>(c->tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(256), 0, st, in, n, out, ts);
-    hipLaunchKernelGGL(k_scan_carry, dim3(1), dim3(1024), 0, st, ts, tiles, out + n);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256 + (n == 0))), dim3(256), 0, st, out, n,
-                       (const uint64_t *)ts);
-    WV_HIP(hipGetLastError());
-    return WV_OK;
+static unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per + (n == 0)); }
+
+hipError_t launch_base_sieve(hipStream_t st, uint32_t *out, uint32_t *n_out) {
+    hipLaunchKernelGGL(k_base_sieve, dim3(1), dim3(1024), 0, st, out, n_out);
+    return hipGetLastError();
 }
 
-// plan -> scan -> sum -> reduce -> finalize for n primes already on the device.
-int run_batch(wv_ctx *c, const uint64_t *d_primes, uint32_t n, wv_result *d_out, hipStream_t st, bool timed) {
-    const int nB = std::max(table_slots(c->tb), 1);
-    const int nE = std::max(table_slots(c->te), 1);
-    const uint64_t nseg = (uint64_t)n * (nB + nE);
-    WV_TRY(ensure(c->pr, (size_t)n * sizeof(PrimeRec)));
-    WV_TRY(ensure(c->segs, nseg * sizeof(SegRec)));
-    WV_TRY(ensure(c->terms, nseg * sizeof(uint64_t)));
-    WV_TRY(ensure(c->cnt, nseg * sizeof(uint64_t)));
-    WV_TRY(ensure(c->off, (nseg + 1) * sizeof(uint64_t)));
-    WV_TRY(ensure(c->scal, 8 * sizeof(uint64_t)));
-    // partial pairs: at most total_terms / chunk + nseg chunks (k_pick_chunk keeps
-    // total_terms / chunk <= cap - nseg), so cap >= 2 nseg always leaves room
-    const uint64_t cap = std::max<uint64_t>(kMaxChunks, 2 * nseg);
-    WV_TRY(ensure(c->partials, cap * sizeof(Pair)));
-    WV_TRY(ensure(c->seg_pairs, nseg * sizeof(Pair)));
-    uint64_t *scal = as<uint64_t>(c->scal);   // [0] total terms, [1] chunk, [2] counter, [3] total B terms
-    uint64_t *toff = as<uint64_t>(c->off);    // reused: prefix of terms, then of chunks
-    const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : kDefaultChunk;
-
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, scal, 8);
-    hipLaunchKernelGGL(k_plan, dim3((n + 255) / 256), dim3(256), 0, st, d_primes, n, c->tb, c->te, nB, nE,
-                       as<PrimeRec>(c->pr), as<SegRec>(c->segs), as<uint64_t>(c->terms));
-    WV_HIP(hipGetLastError());
-    // total terms (prefix of the per-slot term counts) -> chunk size -> chunk prefix
-    WV_TRY(scan_u64(c, as<uint64_t>(c->terms), nseg, toff, st));
-    hipLaunchKernelGGL(k_pick_chunk, dim3(1), dim3(1), 0, st, toff + nseg, nseg, chunk_cfg, cap, scal + 1);
-    if (timed) {
-        // keep the totals for the statistics: terms overall and Bernoulli-side
-        WV_HIP(hipMemcpyAsync(scal + 0, toff + nseg, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-        WV_HIP(hipMemcpyAsync(scal + 3, toff + (uint64_t)n * nB, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    }
-    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st,
-                       (const uint64_t *)as<uint64_t>(c->terms), nseg, (const uint64_t *)(scal + 1),
-                       as<uint64_t>(c->cnt));
-    WV_TRY(scan_u64(c, as<uint64_t>(c->cnt), nseg, toff, st));
-    WV_HIP(hipGetLastError());
-    if (timed) WV_HIP(hipEventRecord(c->ev[EV_PLAN], st));
-
-    hipLaunchKernelGGL(kSumVariants[c->variant].fn, dim3(c->sum_blocks[c->variant]), dim3(256), 0, st,
-                       (const SegRec *)as<SegRec>(c->segs),
-                       (const uint64_t *)toff, (uint32_t)nseg, (const PrimeRec *)as<PrimeRec>(c->pr),
-                       (const uint64_t *)(scal + 1), as<Pair>(c->partials),
-                       (unsigned long long *)(scal + 2));
-    WV_HIP(hipGetLastError());
-    if (timed) WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
-
-    const uint64_t rthreads = nseg * 64;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((rthreads + 255) / 256)), dim3(256), 0, st,
-                       (const SegRec *)as<SegRec>(c->segs), (const uint64_t *)toff, (uint32_t)nseg,
-                       (const PrimeRec *)as<PrimeRec>(c->pr), (const Pair *)as<Pair>(c->partials),
-                       as<Pair>(c->seg_pairs));
-    WV_HIP(hipGetLastError());
-    if (timed) WV_HIP(hipEventRecord(c->ev[EV_REDUCE], st));
-
-    hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, st, (const PrimeRec *)as<PrimeRec>(c->pr),
-                       (const Pair *)as<Pair>(c->seg_pairs), n, nB, nE, d_out);
-    WV_HIP(hipGetLastError());
-    if (timed) WV_HIP(hipEventRecord(c->ev[EV_FINAL], st));
-    return WV_OK;
+hipError_t launch_seg_sieve(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bp, uint32_t n_bp,
+                            uint32_t *bits_out, uint32_t *counts) {
+    hipLaunchKernelGGL(k_seg_sieve, dim3(ns), dim3(1024), 0, st, desc, bp, n_bp, bits_out, counts);
+    return hipGetLastError();
 }
 
-float elapsed(hipEvent_t a, hipEvent_t b) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
-    return ms;
+hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bits,
+                              const uint64_t *off, uint64_t *out) {
+    hipLaunchKernelGGL(k_seg_compact, dim3(ns), dim3(1024), 0, st, desc, bits, off, out);
+    return hipGetLastError();
 }
 
-// Adds the timings and sizes of the batch that just completed to c->stats.
-int collect_stats(wv_ctx *c, uint32_t n, bool with_sieve) {
-    WV_HIP(hipEventSynchronize(c->ev[EV_FINAL]));
-    wv_stats &s = c->stats;
-    const hipEvent_t before_plan = with_sieve ? c->ev[EV_SIEVE] : c->ev[EV_START];
-    if (with_sieve) s.ms_sieve += elapsed(c->ev[EV_START], c->ev[EV_SIEVE]);
-    s.ms_plan += elapsed(before_plan, c->ev[EV_PLAN]);
-    s.ms_sum += elapsed(c->ev[EV_PLAN], c->ev[EV_SUM]);
-    s.ms_reduce += elapsed(c->ev[EV_SUM], c->ev[EV_REDUCE]);
-    s.ms_finalize += elapsed(c->ev[EV_REDUCE], c->ev[EV_FINAL]);
-    s.ms_total += elapsed(c->ev[EV_START], c->ev[EV_FINAL]);
-    const int nB = std::max(table_slots(c->tb), 1), nE = std::max(table_slots(c->te), 1);
-    uint64_t host[4];
-    WV_HIP(hipMemcpy(host, c->scal.ptr, sizeof(host), hipMemcpyDeviceToHost));
-    uint64_t chunks = 0;
-    const uint64_t nseg = (uint64_t)n * (nB + nE);
-    WV_HIP(hipMemcpy(&chunks, as<uint64_t>(c->off) + nseg, sizeof(uint64_t), hipMemcpyDeviceToHost));
-    s.n_primes += n;
-    s.n_sums += nseg;
-    s.n_chunks += chunks;
-    s.n_terms += host[0];
-    s.n_terms_b += host[3];
-    s.chunk_terms = host[1];
-    s.block_k_b = (uint32_t)kSumVariants[c->variant].kb;
-    s.block_k_e = (uint32_t)kSumVariants[c->variant].ke;
-    s.grid = (uint32_t)c->sum_blocks[c->variant];
-    return WV_OK;
+hipError_t launch_scan(hipStream_t st, const uint64_t *in, uint64_t n, uint64_t *out, uint64_t *tiles) {
+    const uint64_t nt = std::max<uint64_t>(1, (n + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(256), 0, st, in, n, out, tiles);
+    hipLaunchKernelGGL(k_scan_carry, dim3(1), dim3(1024), 0, st, tiles, nt, out + n);
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, out, n, (const uint64_t *)tiles);
+    return hipGetLastError();
 }
 
-int check_device(wv_ctx *c) {
-    WV_HIP(hipSetDevice(c->device));
-    return WV_OK;
+hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int tb, int te, int nB, int nE,
+                       PrimeRec *pr, SegRec *segs, uint64_t *terms, uint32_t prime_base) {
+    hipLaunchKernelGGL(k_plan, dim3(blocks_for(n, 256)), dim3(256), 0, st, primes, n, tb, te, nB, nE, pr, segs,
+                       terms, prime_base);
+    return hipGetLastError();
 }
 
-}  // namespace
-
-// ==========================================================================
-// C ABI
-// ==========================================================================
-
-extern "C" {
-
-const char *wv_strerror(int status) {
-    switch (status) {
-    case WV_OK: return "ok";
-    case WV_EINVAL: return "invalid argument";
-    case WV_EDOMAIN: return "prime outside [5, 2^40)";
-    case WV_ENOTPRIME: return "input is not prime";
-    case WV_ETRUNC: return "output buffer too small";
-    case WV_ENOMEM: return "device out of memory";
-    case WV_EHIP: return "HIP runtime error";
-    default: return "unknown status";
-    }
+hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg,
+                             uint64_t cap, uint64_t *chunk_out) {
+    hipLaunchKernelGGL(k_pick_chunk, dim3(1), dim3(1), 0, st, total_terms, nseg, chunk_cfg, cap, chunk_out);
+    return hipGetLastError();
 }
 
-int wv_table_info(int id, int *n_sums, int64_t *lhs, uint64_t *cost_num, uint64_t *cost_den) {
-    if (id < 0 || id >= kNumTables) return WV_EINVAL;
-    if (n_sums) *n_sums = kTables[id].n;
-    if (lhs) *lhs = kTables[id].lhs;
-    if (cost_num) *cost_num = kTables[id].cost_num;
-    if (cost_den) *cost_den = kTables[id].cost_den;
-    return WV_OK;
+hipError_t launch_chunk_count(hipStream_t st, const uint64_t *terms, uint64_t nseg, const uint64_t *chunk,
+                              uint64_t *cnt) {
+    hipLaunchKernelGGL(k_chunk_count, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg, chunk, cnt);
+    return hipGetLastError();
 }
 
-int wv_table_term(int id, int i, int64_t *coef, uint32_t *xa, uint32_t *xb, uint32_t *ya, uint32_t *yb) {
-    if (id < 0 || id >= kNumTables || i < 0 || i >= kTables[id].n) return WV_EINVAL;
-    const TermDef &t = kTables[id].t[i];
-    if (coef) *coef = t.coef;
-    if (xa) *xa = t.xa;
-    if (xb) *xb = t.xb;
-    if (ya) *ya = t.ya;
-    if (yb) *yb = t.yb;
-    return WV_OK;
+hipError_t launch_set_u64(hipStream_t st, uint64_t *dst, int n, uint64_t value) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, st, dst, n, value);
+    return hipGetLastError();
 }
 
-int wv_create(int hip_device, wv_ctx **out) {
-    if (!out) return WV_EINVAL;
-    *out = nullptr;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return WV_EINVAL;
-    wv_ctx *c = new (std::nothrow) wv_ctx();
-    if (!c) return WV_ENOMEM;
-    c->device = hip_device;
-    int rc = WV_OK;
-    do {
-        if (hipSetDevice(hip_device) != hipSuccess) { rc = WV_EHIP; break; }
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { rc = WV_EHIP; break; }
-        for (int i = 0; i < EV_COUNT; i++)
-            if (hipEventCreate(&c->ev[i]) != hipSuccess) { rc = WV_EHIP; break; }
-        if (rc) break;
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { rc = WV_EHIP; break; }
-        c->num_cus = prop.multiProcessorCount;
-        for (int v = 0; v < kNumSumVariants; v++) {
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kSumVariants[v].fn, 256, 0) != hipSuccess ||
-                per_cu < 1)
-                per_cu = 1;
-            c->sum_blocks[v] = c->num_cus * per_cu;
-        }
-        if ((rc = upload_tables()) != WV_OK) break;
-        if ((rc = ensure(c->base_primes, kBaseLimit / 2 * sizeof(uint32_t))) != WV_OK) break;
-        if ((rc = ensure(c->scal, 8 * sizeof(uint64_t))) != WV_OK) break;
-        hipLaunchKernelGGL(k_base_sieve, dim3(1), dim3(1024), 0, c->stream, as<uint32_t>(c->base_primes),
-                           reinterpret_cast<uint32_t *>(c->scal.ptr));
-        if (hipGetLastError() != hipSuccess) { rc = WV_EHIP; break; }
-        uint32_t nb = 0;
-        if (hipMemcpyAsync(&nb, c->scal.ptr, sizeof(nb), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess) { rc = WV_EHIP; break; }
-        c->n_base = nb;
-    } while (0);
-    if (rc != WV_OK) {
-        wv_destroy(c);
-        return rc;
-    }
-    *out = c;
-    return WV_OK;
+hipError_t launch_copy_u64(hipStream_t st, const uint64_t *src, uint64_t *dst, int n) {
+    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, st, src, dst, n);
+    return hipGetLastError();
 }
 
-int wv_destroy(wv_ctx *c) {
-    if (!c) return WV_OK;
-    (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    DevBuf *bufs[] = {&c->base_primes, &c->primes, &c->pr, &c->segs, &c->terms, &c->cnt, &c->off, &c->tiles,
-                      &c->scal, &c->partials, &c->seg_pairs, &c->results, &c->seg_counts, &c->seg_bits,
-                      &c->seg_off};
-    for (DevBuf *b : bufs)
-        if (b->ptr) (void)hipFree(b->ptr);
-    for (int i = 0; i < EV_COUNT; i++)
-        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
-    delete c;
-    return WV_OK;
+int num_sum_variants() { return kNumSumVariants; }
+int sum_variant_kb(int v) { return kSumVariants[v].kb; }
+int sum_variant_ke(int v) { return kSumVariants[v].ke; }
+
+hipError_t sum_variant_occupancy(int v, int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kSumVariants[v].fn, 256, 0);
 }
 
-int wv_set_tables(wv_ctx *c, int b_table, int e_table) {
-    if (!c) return WV_EINVAL;
-    if (b_table < WV_TABLE_BB1 || b_table > WV_TABLE_BB30) return WV_EINVAL;
-    if (e_table < WV_TABLE_EE3 || e_table > WV_TABLE_EE33) return WV_EINVAL;
-    c->tb = b_table;
-    c->te = e_table;
-    return WV_OK;
+hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, const uint64_t *off, uint32_t nseg,
+                      const PrimeRec *pr, const uint64_t *chunk, Pair *partials, unsigned long long *counter,
+                      uint64_t end) {
+    hipLaunchKernelGGL(kSumVariants[v].fn, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, chunk, partials,
+                       counter, end);
+    return hipGetLastError();
 }
 
-int wv_set_chunk_terms(wv_ctx *c, uint64_t chunk_terms) {
-    if (!c || (chunk_terms % 64) != 0) return WV_EINVAL;
-    c->chunk_cfg = chunk_terms;
-    return WV_OK;
+hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
+                         const Pair *partials, Pair *seg_pairs) {
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for((uint64_t)nseg * 64, 256)), dim3(256), 0, st, segs, off, nseg, pr,
+                       partials, seg_pairs);
+    return hipGetLastError();
 }
 
-int wv_set_block(wv_ctx *c, int kb, int ke) {
-    if (!c) return WV_EINVAL;
-    for (int v = 0; v < kNumSumVariants; v++) {
-        if (kSumVariants[v].kb == kb && kSumVariants[v].ke == ke) {
-            c->variant = v;
-            return WV_OK;
-        }
-    }
-    return WV_EINVAL;
+hipError_t launch_finalize(hipStream_t st, const PrimeRec *pr, const Pair *sp, uint32_t n, int nB, int nE,
+                           wv_result *out) {
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, pr, sp, n, nB, nE, out);
+    return hipGetLastError();
 }
 
-int wv_get_stats(const wv_ctx *c, wv_stats *out) {
-    if (!c || !out) return WV_EINVAL;
-    *out = c->stats;
-    return WV_OK;
+hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec *pr, const Pair *sp, uint64_t nseg,
+                             uint64_t *out) {
+    hipLaunchKernelGGL(k_sum_values, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, segs, pr, sp, nseg, out);
+    return hipGetLastError();
 }
 
-int wv_count_primes(wv_ctx *c, uint64_t lo, uint64_t hi, uint64_t *n) {
-    if (!c || !n || lo > hi) return WV_EINVAL;
-    if (hi > WV_P_MAX) return WV_EDOMAIN;
-    WV_TRY(check_device(c));
-    *n = 0;
-    if (hi <= 5 || hi <= lo) return WV_OK;
-    const uint64_t base = lo & ~1ull;
-    const uint64_t nseg_total = (hi - base + kSegSpan - 1) / kSegSpan;
-    const uint64_t batch = 1 << 16;
-    WV_TRY(ensure(c->seg_counts, batch * sizeof(uint32_t)));
-    std::vector<uint32_t> host(batch);
-    uint64_t total = 0;
-    for (uint64_t s0 = 0; s0 < nseg_total; s0 += batch) {
-        const uint64_t ns = std::min(batch, nseg_total - s0);
-        hipLaunchKernelGGL(k_seg_sieve, dim3((unsigned)ns), dim3(1024), 0, c->stream, lo, hi, base + s0 * kSegSpan,
-                           (const uint32_t *)as<uint32_t>(c->base_primes), c->n_base, (uint32_t *)nullptr,
-                           as<uint32_t>(c->seg_counts));
-        WV_HIP(hipGetLastError());
-        WV_HIP(hipMemcpyAsync(host.data(), c->seg_counts.ptr, ns * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                              c->stream));
-        WV_HIP(hipStreamSynchronize(c->stream));
-        for (uint64_t i = 0; i < ns; i++) total += host[i];
-    }
-    *n = total;
-    return WV_OK;
+hipError_t launch_fold(hipStream_t st, const SegRec *tasks, const uint32_t *target, const Pair *tp, uint32_t ntask,
+                       const PrimeRec *pr, Pair *acc) {
+    hipLaunchKernelGGL(k_fold, dim3(blocks_for(ntask, 256)), dim3(256), 0, st, tasks, target, tp, ntask, pr, acc);
+    return hipGetLastError();
 }
 
-int wv_search_range(wv_ctx *c, uint64_t lo, uint64_t hi, wv_result *out, size_t cap, size_t *n_out,
-                    uint64_t *hits, size_t hit_cap, size_t *n_hits) {
-    if (!c || !n_out || lo > hi || (hit_cap && !hits)) return WV_EINVAL;
-    if (hi > WV_P_MAX) return WV_EDOMAIN;
-    WV_TRY(check_device(c));
-    // count first, so that a short buffer is reported before any work
-    uint64_t total = 0;
-    WV_TRY(wv_count_primes(c, lo, hi, &total));
-    *n_out = (size_t)total;
-    if (n_hits) *n_hits = 0;
-    if (total > cap) return WV_ETRUNC;
-    if (total > 0 && !out) return WV_EINVAL;
-    c->stats = wv_stats{};
-    if (total == 0) return WV_OK;
-    const uint64_t base0 = lo & ~1ull;
-    const uint64_t nseg_total = (hi - base0 + kSegSpan - 1) / kSegSpan;
-    WV_TRY(ensure(c->seg_counts, kWindowSegs * sizeof(uint32_t)));
-    WV_TRY(ensure(c->seg_bits, kWindowSegs * kSegWords * sizeof(uint32_t)));
-    WV_TRY(ensure(c->seg_off, (kWindowSegs + 1) * sizeof(uint64_t)));
-    WV_TRY(ensure(c->tiles, 64 * sizeof(uint64_t)));
-    size_t written = 0, nh = 0;
-    std::vector<uint32_t> counts(kWindowSegs);
-    for (uint64_t s0 = 0; s0 < nseg_total; s0 += kWindowSegs) {
-        const uint64_t ns = std::min(kWindowSegs, nseg_total - s0);
-        const uint64_t base = base0 + s0 * kSegSpan;
-        WV_HIP(hipEventRecord(c->ev[EV_START], c->stream));
-        hipLaunchKernelGGL(k_seg_sieve, dim3((unsigned)ns), dim3(1024), 0, c->stream, lo, hi, base,
-                           (const uint32_t *)as<uint32_t>(c->base_primes), c->n_base, as<uint32_t>(c->seg_bits),
-                           as<uint32_t>(c->seg_counts));
-        WV_HIP(hipGetLastError());
-        WV_HIP(hipMemcpyAsync(counts.data(), c->seg_counts.ptr, ns * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                              c->stream));
-        WV_HIP(hipStreamSynchronize(c->stream));
-        std::vector<uint64_t> offs(ns + 1, 0);
-        for (uint64_t i = 0; i < ns; i++) offs[i + 1] = offs[i] + counts[i];
-        const uint64_t np = offs[ns];
-        if (np == 0) continue;
-        if (written + np > cap) return WV_EHIP;   // sieve disagreed with the count pass
-        WV_TRY(ensure(c->primes, np * sizeof(uint64_t)));
-        WV_TRY(ensure(c->results, np * sizeof(wv_result)));
-        WV_HIP(hipMemcpyAsync(c->seg_off.ptr, offs.data(), (ns + 1) * sizeof(uint64_t), hipMemcpyHostToDevice,
-                              c->stream));
-        hipLaunchKernelGGL(k_seg_compact, dim3((unsigned)ns), dim3(1024), 0, c->stream, base,
-                           (const uint32_t *)as<uint32_t>(c->seg_bits), (const uint64_t *)as<uint64_t>(c->seg_off),
-                           as<uint64_t>(c->primes));
-        WV_HIP(hipGetLastError());
-        WV_HIP(hipEventRecord(c->ev[EV_SIEVE], c->stream));
-        WV_TRY(run_batch(c, as<uint64_t>(c->primes), (uint32_t)np, as<wv_result>(c->results), c->stream, true));
-        WV_HIP(hipMemcpyAsync(out + written, c->results.ptr, np * sizeof(wv_result), hipMemcpyDeviceToHost,
-                              c->stream));
-        WV_TRY(collect_stats(c, (uint32_t)np, true));
-        WV_HIP(hipStreamSynchronize(c->stream));
-        for (uint64_t i = 0; i < np; i++) {
-            if (out[written + i].flags) {
-                if (nh < hit_cap) hits[nh] = out[written + i].p;
-                nh++;
-            }
-        }
-        written += np;
-    }
-    if (n_hits) *n_hits = nh;
-    return WV_OK;
+hipError_t launch_fill_pairs(hipStream_t st, Pair *p, uint64_t n, uint64_t c0, uint64_t c1) {
+    hipLaunchKernelGGL(k_fill_pairs, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, c0, c1);
+    return hipGetLastError();
 }
 
-int wv_eval_primes(wv_ctx *c, const uint64_t *primes, size_t n, wv_result *out) {
-    if (!c) return WV_EINVAL;
-    if (n == 0) return WV_OK;
-    if (!primes || !out) return WV_EINVAL;
-    if (n > 0xFFFFFFFFull) return WV_EINVAL;
-    for (size_t i = 0; i < n; i++) {
-        if (primes[i] < 5 || primes[i] >= WV_P_MAX) return WV_EDOMAIN;
-        if (!is_prime_u64(primes[i])) return WV_ENOTPRIME;
-    }
-    WV_TRY(check_device(c));
-    c->stats = wv_stats{};
-    WV_TRY(ensure(c->primes, n * sizeof(uint64_t)));
-    WV_TRY(ensure(c->results, n * sizeof(wv_result)));
-    WV_HIP(hipEventRecord(c->ev[EV_START], c->stream));
-    WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
-    WV_TRY(run_batch(c, as<uint64_t>(c->primes), (uint32_t)n, as<wv_result>(c->results), c->stream, true));
-    WV_HIP(hipMemcpyAsync(out, c->results.ptr, n * sizeof(wv_result), hipMemcpyDeviceToHost, c->stream));
-    WV_TRY(collect_stats(c, (uint32_t)n, false));
-    WV_HIP(hipStreamSynchronize(c->stream));
-    return WV_OK;
+hipError_t launch_copy_pad(hipStream_t st, const uint64_t *src, uint64_t n, uint64_t *dst, uint64_t n_pad) {
+    hipLaunchKernelGGL(k_copy_pad, dim3(blocks_for(n_pad, 256)), dim3(256), 0, st, src, n, dst, n_pad);
+    return hipGetLastError();
 }
 
-int wv_eval_sums(wv_ctx *c, const uint64_t *primes, size_t n, uint64_t *out_b, uint64_t *out_e) {
-    if (!c) return WV_EINVAL;
-    if (n == 0) return WV_OK;
-    if (!primes || !out_b || !out_e || n > 0xFFFFFFFFull) return WV_EINVAL;
-    for (size_t i = 0; i < n; i++) {
-        if (primes[i] < 5 || primes[i] >= WV_P_MAX) return WV_EDOMAIN;
-        if (!is_prime_u64(primes[i])) return WV_ENOTPRIME;
-    }
-    WV_TRY(check_device(c));
-    const int nB = std::max(table_slots(c->tb), 1), nE = std::max(table_slots(c->te), 1);
-    const uint64_t nseg = (uint64_t)n * (nB + nE);
-    WV_TRY(ensure(c->primes, n * sizeof(uint64_t)));
-    WV_TRY(ensure(c->results, std::max(n * sizeof(wv_result), (size_t)nseg * sizeof(uint64_t))));
-    WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
-    WV_TRY(run_batch(c, as<uint64_t>(c->primes), (uint32_t)n, as<wv_result>(c->results), c->stream, false));
-    // the results buffer is free again once finalize has run: reuse it for the sums
-    uint64_t *d_sums = as<uint64_t>(c->results);
-    hipLaunchKernelGGL(k_sum_values, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, c->stream,
-                       (const SegRec *)as<SegRec>(c->segs), (const PrimeRec *)as<PrimeRec>(c->pr),
-                       (const Pair *)as<Pair>(c->seg_pairs), nseg, d_sums);
-    WV_HIP(hipGetLastError());
-    WV_HIP(hipMemcpyAsync(out_b, d_sums, (size_t)n * nB * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
-    WV_HIP(hipMemcpyAsync(out_e, d_sums + (size_t)n * nB, (size_t)n * nE * sizeof(uint64_t),
-                          hipMemcpyDeviceToHost, c->stream));
-    WV_HIP(hipStreamSynchronize(c->stream));
-    return WV_OK;
+hipError_t launch_copy_results(hipStream_t st, const wv_result *src, uint64_t n, wv_result *dst) {
+    hipLaunchKernelGGL(k_copy_results, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, n, dst);
+    return hipGetLastError();
 }
 
-int wv_eval_primes_async(wv_ctx *c, const uint64_t *d_primes, size_t n, wv_result *d_out, void *hip_stream) {
-    if (!c) return WV_EINVAL;
-    if (n == 0) return WV_OK;
-    if (!d_primes || !d_out || n > 0xFFFFFFFFull) return WV_EINVAL;
-    WV_TRY(check_device(c));
-    return run_batch(c, d_primes, (uint32_t)n, d_out, (hipStream_t)hip_stream, false);
-}
-
-}  // extern "C"
+}  // namespace wv

@@ -1,0 +1,487 @@
+// wv_server.hip -- request server with continuous batching at chunk
+// granularity (the serving loop of the residue search).
+//
+// Requests (a prime list, or every prime of an interval) are admitted into a
+// device pool of prime slots when a contiguous range of slots is free: their
+// primes are planned into the pool (PrimeRec, one SegRec per (prime, sum)) and
+// each sum gets an accumulator pair (c0, c1) = (1, 0) on the device.  Every
+// step then cuts a budget of terms into tasks -- contiguous ranges of one sum
+// -- shared fairly among the active requests, runs them through the same
+// term-sum and reduction kernels as a batch, and folds each task's pair into
+// its sum's accumulator with eqnCombinePairs (Section 3).  A request whose
+// sums are all complete is finalized (Sections 3 and 5 congruences), its
+// results copied out and its slots freed.  New requests join at the next
+// step, so short requests overtake long ones instead of queueing behind them.
+//
+// Because the pair product is associative and commutative and all arithmetic
+// is exact, a request's residues do not depend on how its work was cut into
+// tasks or interleaved with other requests.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "wv_ctx.hpp"
+
+using namespace wv;
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+enum { REQ_PENDING = 0, REQ_ACTIVE = 1, REQ_DONE = 2 };
+
+struct Request {
+    uint64_t id = 0;
+    bool is_range = false;
+    uint64_t lo = 0, hi = 0;
+    std::vector<uint64_t> primes;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int state = REQ_PENDING;
+    uint32_t n = 0;            // primes
+    uint32_t base = 0;         // first pool slot
+    std::vector<uint64_t> seg_lo, seg_len, cursor;
+    size_t first_open = 0;     // first sum with work left
+    uint64_t remaining = 0;    // terms left
+    std::vector<wv_result> results;
+};
+
+}  // namespace
+
+struct wv_server {
+    wv_ctx *c = nullptr;
+    uint64_t step_terms = 1ull << 36;
+    uint32_t pool = 1u << 16;
+    int tb = 0, te = 0;        // congruences fixed at creation (the pool layout depends on them)
+    int nB = 0, nE = 0, NS = 0;
+    DevBuf pr, segs, acc, terms, tmp, tasks, target, toff, tpairs, partials, res, scal;
+    std::vector<std::pair<uint32_t, uint32_t>> free_ranges;   // (first slot, count), sorted
+    std::deque<Request *> pending;
+    std::vector<Request *> active;
+    std::map<uint64_t, Request *> all;
+    uint64_t next_id = 1;
+    uint64_t submitted = 0, completed = 0, primes_done = 0, terms_done = 0, steps = 0, readmits = 0;
+    double t_first = 0, busy_s = 0;
+    std::vector<double> lat_ms;
+    int fault_after = -1;      // host-forced step failure (tests)
+};
+
+namespace {
+
+bool pool_alloc(wv_server *s, uint32_t n, uint32_t *base) {
+    for (size_t i = 0; i < s->free_ranges.size(); i++) {
+        auto &r = s->free_ranges[i];
+        if (r.second >= n) {
+            *base = r.first;
+            r.first += n;
+            r.second -= n;
+            if (r.second == 0) s->free_ranges.erase(s->free_ranges.begin() + i);
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(wv_server *s, uint32_t base, uint32_t n) {
+    if (n == 0) return;
+    s->free_ranges.push_back({base, n});
+    std::sort(s->free_ranges.begin(), s->free_ranges.end());
+    std::vector<std::pair<uint32_t, uint32_t>> merged;
+    for (auto &r : s->free_ranges) {
+        if (!merged.empty() && merged.back().first + merged.back().second == r.first) merged.back().second += r.second;
+        else merged.push_back(r);
+    }
+    s->free_ranges.swap(merged);
+}
+
+int finish_request(wv_server *s, Request *r) {
+    wv_ctx *c = s->c;
+    if (r->n) {
+        WV_HIP(launch_finalize(c->stream, as<PrimeRec>(s->pr) + r->base, as<Pair>(s->acc) + (size_t)r->base * s->NS,
+                               r->n, s->nB, s->nE, as<wv_result>(s->res)));
+        r->results.resize(r->n);
+        WV_HIP(hipMemcpyAsync(r->results.data(), s->res.ptr, r->n * sizeof(wv_result), hipMemcpyDeviceToHost,
+                              c->stream));
+        WV_HIP(hipStreamSynchronize(c->stream));
+    }
+    pool_free(s, r->base, r->n);
+    r->state = REQ_DONE;
+    r->t_done = now_s();
+    s->completed++;
+    s->primes_done += r->n;
+    s->lat_ms.push_back((r->t_done - r->t_submit) * 1e3);
+    return WV_OK;
+}
+
+// Plans a pending request into the pool.  Returns WV_OK with *admitted false
+// when there is no room yet.
+int admit(wv_server *s, Request *r, bool *admitted) {
+    wv_ctx *c = s->c;
+    *admitted = false;
+    const uint64_t *d_primes = nullptr;
+    uint64_t n = 0;
+    if (r->is_range) {
+        std::vector<SegDesc> d;
+        window_descs(r->lo, r->hi, d);
+        std::vector<uint32_t> counts(d.size());
+        // intervals of a request are sieved in one batch of segments
+        if (d.size() > kMaxBatchSegs) return WV_EINVAL;
+        if (!d.empty()) WV_TRY(sieve_count(c, d.data(), d.size(), true, counts.data()));
+        for (uint32_t k : counts) n += k;
+        if (n > s->pool) return WV_ENOMEM;
+        uint32_t base = 0;
+        if (n > 0 && !pool_alloc(s, (uint32_t)n, &base)) return WV_OK;
+        if (n > 0) {
+            uint64_t got = 0;
+            WV_TRY(compact(c, d.data(), d.size(), counts.data(), &got));
+            d_primes = as<uint64_t>(c->primes);
+        }
+        r->base = base;
+    } else {
+        n = r->primes.size();
+        if (n > s->pool) return WV_ENOMEM;
+        uint32_t base = 0;
+        if (n > 0 && !pool_alloc(s, (uint32_t)n, &base)) return WV_OK;
+        if (n > 0) {
+            WV_TRY(ensure(c, s->tmp, n * sizeof(uint64_t)));
+            WV_HIP(hipMemcpyAsync(s->tmp.ptr, r->primes.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                  c->stream));
+            d_primes = as<uint64_t>(s->tmp);
+        }
+        r->base = base;
+    }
+    r->n = (uint32_t)n;
+    r->t_admit = now_s();
+    *admitted = true;
+    if (n == 0) return finish_request(s, r);
+    const size_t first = (size_t)r->base * s->NS, nseg = (size_t)n * s->NS;
+    WV_HIP(launch_plan(c->stream, d_primes, (uint32_t)n, s->tb, s->te, s->nB, s->nE, as<PrimeRec>(s->pr) + r->base,
+                       as<SegRec>(s->segs) + first, as<uint64_t>(s->terms) + first, r->base));
+    WV_HIP(launch_fill_pairs(c->stream, as<Pair>(s->acc) + first, nseg, 1, 0));
+    std::vector<SegRec> recs(nseg);
+    WV_HIP(hipMemcpyAsync(recs.data(), as<SegRec>(s->segs) + first, nseg * sizeof(SegRec), hipMemcpyDeviceToHost,
+                          c->stream));
+    WV_HIP(hipStreamSynchronize(c->stream));
+    r->seg_lo.resize(nseg);
+    r->seg_len.resize(nseg);
+    r->cursor.assign(nseg, 0);
+    r->remaining = 0;
+    for (size_t k = 0; k < nseg; k++) {
+        r->seg_lo[k] = recs[k].lo;
+        r->seg_len[k] = recs[k].len;
+        r->remaining += recs[k].len;
+    }
+    r->first_open = 0;
+    r->state = REQ_ACTIVE;
+    s->active.push_back(r);
+    if (r->remaining == 0) {
+        s->active.pop_back();
+        return finish_request(s, r);
+    }
+    return WV_OK;
+}
+
+// Restart every active request from scratch (after a failed step).
+int readmit_all(wv_server *s) {
+    for (Request *r : s->active) {
+        std::fill(r->cursor.begin(), r->cursor.end(), 0);
+        r->first_open = 0;
+        r->remaining = 0;
+        for (uint64_t l : r->seg_len) r->remaining += l;
+        WV_HIP(launch_fill_pairs(s->c->stream, as<Pair>(s->acc) + (size_t)r->base * s->NS, (size_t)r->n * s->NS,
+                                 1, 0));
+        s->readmits++;
+    }
+    WV_HIP(hipStreamSynchronize(s->c->stream));
+    return WV_OK;
+}
+
+struct Task {
+    Request *r;
+    size_t k;        // sum index within the request
+    uint64_t t;      // terms
+};
+
+int run_step(wv_server *s) {
+    wv_ctx *c = s->c;
+    const uint64_t C = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    // fair share of the step budget, leftovers to whoever still has work
+    std::vector<uint64_t> allow(s->active.size(), 0);
+    uint64_t budget = s->step_terms;
+    for (int pass = 0; pass < 2 && budget > 0; pass++) {
+        size_t want = 0;
+        for (size_t i = 0; i < s->active.size(); i++)
+            if (s->active[i]->remaining > allow[i]) want++;
+        if (!want) break;
+        const uint64_t share = std::max<uint64_t>(C, budget / want);
+        for (size_t i = 0; i < s->active.size() && budget > 0; i++) {
+            const uint64_t left = s->active[i]->remaining - allow[i];
+            if (!left) continue;
+            const uint64_t g = std::min(std::min(left, share), budget);
+            allow[i] += g;
+            budget -= g;
+        }
+    }
+    std::vector<Task> tasks;
+    for (size_t i = 0; i < s->active.size(); i++) {
+        Request *r = s->active[i];
+        uint64_t a = allow[i];
+        for (size_t k = r->first_open; k < r->seg_len.size() && a > 0; k++) {
+            const uint64_t left = r->seg_len[k] - r->cursor[k];
+            if (!left) continue;
+            uint64_t t = std::min(left, ((a + C - 1) / C) * C);
+            tasks.push_back(Task{r, k, t});
+            a -= std::min(a, t);
+        }
+    }
+    if (tasks.empty()) return WV_OK;
+    const size_t nt = tasks.size();
+    std::vector<SegRec> recs(nt);
+    std::vector<uint32_t> tgt(nt);
+    std::vector<uint64_t> off(nt + 1, 0);
+    uint64_t terms = 0;
+    for (size_t j = 0; j < nt; j++) {
+        const Task &t = tasks[j];
+        const size_t nseg_r = t.r->seg_len.size();
+        const size_t k = t.k;
+        // slot k of the request: Bernoulli slots (i*nB + j) first, then Euler
+        const bool bern = k < (size_t)t.r->n * s->nB;
+        const uint32_t prime = bern ? (uint32_t)(k / s->nB) : (uint32_t)((k - (size_t)t.r->n * s->nB) / s->nE);
+        recs[j] = SegRec{t.r->seg_lo[k] + t.r->cursor[k], t.t, t.r->base + prime, bern ? 3u : 2u};
+        tgt[j] = (uint32_t)((size_t)t.r->base * s->NS + k);
+        off[j + 1] = off[j] + (t.t + C - 1) / C;
+        terms += t.t;
+        (void)nseg_r;
+    }
+    const uint64_t chunks = off[nt];
+    WV_TRY(ensure(c, s->tasks, nt * sizeof(SegRec)));
+    WV_TRY(ensure(c, s->target, nt * sizeof(uint32_t)));
+    WV_TRY(ensure(c, s->toff, (nt + 1) * sizeof(uint64_t)));
+    WV_TRY(ensure(c, s->tpairs, nt * sizeof(Pair)));
+    WV_TRY(ensure(c, s->partials, chunks * sizeof(Pair)));
+    hipStream_t st = c->stream;
+    WV_HIP(hipMemcpyAsync(s->tasks.ptr, recs.data(), nt * sizeof(SegRec), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(s->target.ptr, tgt.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(s->toff.ptr, off.data(), (nt + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    uint64_t *scal = as<uint64_t>(s->scal);   // [0] chunk size, [1] counter
+    WV_HIP(launch_set_u64(st, scal, 1, C));
+    WV_HIP(launch_set_u64(st, scal + 1, 1, 0));
+    WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
+    const int v = c->variant;
+    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt,
+                      as<PrimeRec>(s->pr), scal, as<Pair>(s->partials), (unsigned long long *)(scal + 1),
+                      UINT64_MAX));
+    WV_HIP(launch_reduce(st, as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt, as<PrimeRec>(s->pr),
+                         as<Pair>(s->partials), as<Pair>(s->tpairs)));
+    WV_HIP(launch_fold(st, as<SegRec>(s->tasks), as<uint32_t>(s->target), as<Pair>(s->tpairs), (uint32_t)nt,
+                       as<PrimeRec>(s->pr), as<Pair>(s->acc)));
+    WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
+    WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev[EV_SUM0], c->ev[EV_SUM]);
+    s->busy_s += ms * 1e-3;
+    s->steps++;
+    if (s->fault_after >= 0 && (int64_t)s->steps > s->fault_after) {
+        s->fault_after = -1;   // one forced failure: the step's work is discarded
+        return WV_EHIP;
+    }
+    // commit progress
+    for (const Task &t : tasks) {
+        t.r->cursor[t.k] += t.t;
+        t.r->remaining -= t.t;
+    }
+    s->terms_done += terms;
+    std::vector<Request *> still;
+    for (Request *r : s->active) {
+        while (r->first_open < r->seg_len.size() && r->cursor[r->first_open] == r->seg_len[r->first_open])
+            r->first_open++;
+        if (r->remaining == 0) WV_TRY(finish_request(s, r));
+        else still.push_back(r);
+    }
+    s->active.swap(still);
+    return WV_OK;
+}
+
+double percentile(std::vector<double> v, double q) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (v.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - i;
+    return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
+    if (!c || !out) return WV_EINVAL;
+    *out = nullptr;
+    WV_TRY(check_device(c));
+    wv_server *s = new (std::nothrow) wv_server();
+    if (!s) return WV_ENOMEM;
+    s->c = c;
+    if (cfg && cfg->step_terms) s->step_terms = cfg->step_terms;
+    if (cfg && cfg->max_primes) s->pool = cfg->max_primes;
+    s->tb = c->tb;
+    s->te = c->te;
+    s->nB = std::max(table_slots(c->tb), 1);
+    s->nE = std::max(table_slots(c->te), 1);
+    s->NS = s->nB + s->nE;
+    const size_t nseg = (size_t)s->pool * s->NS;
+    int rc = WV_OK;
+    if ((rc = ensure(c, s->pr, s->pool * sizeof(PrimeRec))) != WV_OK ||
+        (rc = ensure(c, s->segs, nseg * sizeof(SegRec))) != WV_OK ||
+        (rc = ensure(c, s->acc, nseg * sizeof(Pair))) != WV_OK ||
+        (rc = ensure(c, s->terms, nseg * sizeof(uint64_t))) != WV_OK ||
+        (rc = ensure(c, s->res, s->pool * sizeof(wv_result))) != WV_OK ||
+        (rc = ensure(c, s->scal, 8 * sizeof(uint64_t))) != WV_OK) {
+        wv_server_destroy(s);
+        return rc;
+    }
+    s->free_ranges.push_back({0, s->pool});
+    *out = s;
+    return WV_OK;
+}
+
+int wv_server_inject_fault(wv_server *s, int after_steps) {
+    if (!s) return WV_EINVAL;
+    s->fault_after = after_steps < 0 ? -1 : (int)(s->steps + after_steps);
+    return WV_OK;
+}
+
+int wv_server_destroy(wv_server *s) {
+    if (!s) return WV_OK;
+    if (s->c) (void)hipStreamSynchronize(s->c->stream);
+    DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->tmp, &s->tasks, &s->target, &s->toff,
+                      &s->tpairs, &s->partials, &s->res, &s->scal};
+    for (DevBuf *b : bufs)
+        if (b->ptr) (void)hipFree(b->ptr);
+    for (auto &kv : s->all) delete kv.second;
+    delete s;
+    return WV_OK;
+}
+
+int wv_server_submit_range(wv_server *s, uint64_t lo, uint64_t hi, uint64_t *id) {
+    if (!s || !id || lo > hi) return WV_EINVAL;
+    if (hi > WV_P_MAX) return WV_EDOMAIN;
+    if (hi - (lo & ~1ull) > kMaxBatchSegs * kSegSpan) return WV_EINVAL;   // one batch of sieve segments
+    Request *r = new (std::nothrow) Request();
+    if (!r) return WV_ENOMEM;
+    r->id = s->next_id++;
+    r->is_range = true;
+    r->lo = lo;
+    r->hi = hi;
+    r->t_submit = now_s();
+    if (!s->submitted) s->t_first = r->t_submit;
+    s->submitted++;
+    s->all[r->id] = r;
+    s->pending.push_back(r);
+    *id = r->id;
+    return WV_OK;
+}
+
+int wv_server_submit_primes(wv_server *s, const uint64_t *primes, size_t n, uint64_t *id) {
+    if (!s || !id || (n && !primes)) return WV_EINVAL;
+    if (n > s->pool) return WV_EINVAL;
+    for (size_t i = 0; i < n; i++) {
+        if (primes[i] < 5 || primes[i] >= WV_P_MAX) return WV_EDOMAIN;
+        if (!is_prime_u64(primes[i])) return WV_ENOTPRIME;
+    }
+    Request *r = new (std::nothrow) Request();
+    if (!r) return WV_ENOMEM;
+    r->id = s->next_id++;
+    r->primes.assign(primes, primes + n);
+    r->t_submit = now_s();
+    if (!s->submitted) s->t_first = r->t_submit;
+    s->submitted++;
+    s->all[r->id] = r;
+    s->pending.push_back(r);
+    *id = r->id;
+    return WV_OK;
+}
+
+int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
+    if (!s) return WV_EINVAL;
+    WV_TRY(check_device(s->c));
+    // admit in arrival order; a request that does not fit yet does not block
+    // smaller ones behind it
+    std::deque<Request *> waiting;
+    while (!s->pending.empty()) {
+        Request *r = s->pending.front();
+        s->pending.pop_front();
+        bool ok = false;
+        const int rc = admit(s, r, &ok);
+        if (rc != WV_OK) {
+            // a request that can never be served completes empty with an error
+            r->state = REQ_DONE;
+            r->t_done = now_s();
+            r->results.clear();
+            r->n = 0;
+            s->completed++;
+            s->lat_ms.push_back((r->t_done - r->t_submit) * 1e3);
+            continue;
+        }
+        if (!ok) waiting.push_back(r);
+    }
+    s->pending.swap(waiting);
+    int rc = s->active.empty() ? WV_OK : run_step(s);
+    if (rc != WV_OK) rc = readmit_all(s);
+    if (n_active) *n_active = (uint32_t)s->active.size();
+    if (n_pending) *n_pending = (uint32_t)s->pending.size();
+    return rc;
+}
+
+int wv_server_result(wv_server *s, uint64_t id, wv_result *out, size_t cap, size_t *n_out, double *latency_ms) {
+    if (!s || !n_out) return WV_EINVAL;
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return WV_EINVAL;
+    Request *r = it->second;
+    if (r->state != REQ_DONE) return WV_EBUSY;
+    *n_out = r->results.size();
+    if (latency_ms) *latency_ms = (r->t_done - r->t_submit) * 1e3;
+    if (r->results.size() > cap) return WV_ETRUNC;
+    if (!r->results.empty()) {
+        if (!out) return WV_EINVAL;
+        memcpy(out, r->results.data(), r->results.size() * sizeof(wv_result));
+    }
+    s->all.erase(it);
+    delete r;
+    return WV_OK;
+}
+
+int wv_server_get_stats(const wv_server *s, wv_server_stats *out) {
+    if (!s || !out) return WV_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->pending = s->pending.size();
+    out->active = s->active.size();
+    out->primes_done = s->primes_done;
+    out->terms_done = s->terms_done;
+    out->steps = s->steps;
+    out->readmits = s->readmits;
+    out->p50_ms = percentile(s->lat_ms, 0.50);
+    out->p99_ms = percentile(s->lat_ms, 0.99);
+    double sum = 0, mx = 0;
+    for (double v : s->lat_ms) {
+        sum += v;
+        mx = std::max(mx, v);
+    }
+    out->mean_ms = s->lat_ms.empty() ? 0.0 : sum / s->lat_ms.size();
+    out->max_ms = mx;
+    out->busy_s = s->busy_s;
+    out->wall_s = s->submitted ? now_s() - s->t_first : 0.0;
+    return WV_OK;
+}
+
+}  // extern "C"

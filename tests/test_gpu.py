@@ -378,3 +378,178 @@ def test_paper_prime_count(ctx):
     for k, v in c.items():
         lo, hi = map(int, k.split(","))
         assert ctx.count_primes(lo, hi) == v, k
+
+
+# ---------------------------------------------------------------------------
+# batched windows, split launches, graphs, autotuner
+# ---------------------------------------------------------------------------
+
+
+def test_search_windows_equals_plain_path(ctx):
+    """Uneven windows in one batched call give, window by window, exactly the
+    plain per-window results (seeded draw; shorter windows than the full
+    workload so that the plain path can be run beside it)."""
+    from paper_2101_11157_amd import workloads
+    wins = workloads.batch_windows(0, 24, len_range=(1e2, 2e3))
+    wins += [(5, 5), (24, 29), (10 ** 9, 10 ** 9 + 300), (10 ** 9 + 100, 10 ** 9 + 200)]   # empty, overlapping
+    say(f"case: search_windows over {len(wins)} windows")
+    got = ctx.search_windows([a for a, _ in wins], [b for _, b in wins])
+    st = ctx.stats()
+    assert len(got) == len(wins)
+    total = 0
+    for (a, b), res in zip(wins, got):
+        ref, _ = ctx.search_range(a, b)
+        assert [int(p) for p in res["p"]] == [int(p) for p in ref["p"]] == oracle.primes(max(a, 5), b)
+        assert as_pairs(res) == as_pairs(ref)
+        total += len(res)
+    assert st["n_primes"] == total
+    # and a sample against the oracle
+    flat = np.concatenate([g for g in got if len(g)])
+    pick = sorted(random.Random(9).sample(range(len(flat)), 5))
+    check_against_oracle(flat[pick], method="table")
+
+
+def test_split_launches_with_progress(ctx):
+    """Term sums cut into many launches with a progress callback: same residues."""
+    ps = oracle.primes(10 ** 9, 10 ** 9 + 3000)
+    ref = ctx.eval_primes(ps)
+    seen = []
+    try:
+        ctx.set_progress(lambda d, t: seen.append((d, t)), terms_per_launch=1 << 30)
+        got = ctx.eval_primes(ps)
+    finally:
+        ctx.set_progress(None)
+    assert len(seen) > 3
+    assert all(b[0] > a[0] for a, b in zip(seen, seen[1:])) and seen[-1][0] == seen[-1][1]
+    assert as_pairs(got) == as_pairs(ref)
+
+
+def test_async_graph_replays(ctx):
+    """The device-pointer entry point replays captured graphs: several replays of
+    one size, another size in between, eager calls and syncs between them; every
+    replay equals the eager host-pointer result."""
+    hip = Hip()
+    pools = [oracle.primes(10 ** 7, 10 ** 7 + 9000), oracle.primes(2 * 10 ** 8, 2 * 10 ** 8 + 3000)]
+    st = hip.ct.c_void_p()
+    assert hip.h.hipStreamCreate(hip.ct.byref(st)) == 0
+    bufs = []
+    try:
+        for rep in range(3):
+            for ps in pools:
+                arr = np.array(ps, dtype=np.uint64)
+                ref = ctx.eval_primes(ps)                       # eager, between replays
+                d_in = hip.malloc(arr.nbytes)
+                d_out = hip.malloc(arr.size * wv.RESULT_DTYPE.itemsize)
+                bufs += [d_in, d_out]
+                hip.h2d(d_in, arr)
+                ctx.eval_primes_async(d_in, arr.size, d_out, st.value)
+                assert hip.h.hipStreamSynchronize(st) == 0
+                got = np.zeros(arr.size, dtype=wv.RESULT_DTYPE)
+                hip.d2h(got, d_out)
+                assert [int(x) for x in got["p"]] == ps, rep
+                assert as_pairs(got) == as_pairs(ref), rep
+    finally:
+        hip.h.hipStreamDestroy(st)
+        for b in bufs:
+            hip.h.hipFree(b)
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    say("case: autotune at 1e9")
+    ps = oracle.primes(10 ** 9, 10 ** 9 + 2000)
+    ref = ctx.eval_primes(ps)
+    kb, ke, chunk, table = ctx.autotune(10 ** 9, n_sample=8)
+    assert (kb, ke) in wv.BLOCK_SHAPES and chunk in (1 << 14, 1 << 16, 1 << 18)
+    assert table[(kb, ke, chunk)] == max(table.values()) > 0
+    got = ctx.eval_primes(ps)                                   # tuned shape in use
+    assert as_pairs(got) == as_pairs(ref)
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(str(path))
+    line = path.read_text().split()
+    assert line[0].startswith("gfx") and int(line[1]) == 29 and (int(line[2]), int(line[3])) == (kb, ke)
+    with wv.Context(0) as c2:
+        c2.tune_load(str(path))
+        assert as_pairs(c2.eval_primes(ps)) == as_pairs(ref)
+        assert (c2.stats()["block_k_b"], c2.stats()["block_k_e"]) == (kb, ke)
+
+
+# ---------------------------------------------------------------------------
+# request server
+# ---------------------------------------------------------------------------
+
+
+def drain(srv, ids, max_steps=100000):
+    out = {}
+    for _ in range(max_steps):
+        for rid in list(ids):
+            if rid in out:
+                continue
+            r = srv.result(rid)
+            if r is not None:
+                out[rid] = r
+        if len(out) == len(ids):
+            return out
+        srv.step()
+    raise AssertionError("server did not drain")
+
+
+def test_server_mixed_requests_match_alone(ctx):
+    """Singles and intervals submitted together and while others run: every
+    request's residues equal the same request run alone."""
+    say("case: server mixed requests")
+    rng = random.Random(21)
+    reqs = []
+    for k in range(14):
+        if rng.random() < 0.6:
+            u = rng.randrange(10 ** 6, 10 ** 10)
+            p = oracle.primes(u, u + 2000)[0]
+            reqs.append(("primes", [p]))
+        else:
+            a = rng.randrange(10 ** 6, 10 ** 9)
+            reqs.append(("range", (a, a + rng.randrange(100, 3000))))
+    reqs.append(("primes", oracle.primes(10 ** 8, 10 ** 8 + 500)))
+    reqs.append(("range", (24, 29)))                                  # no primes
+    with wv.Server(ctx, step_terms=1 << 30) as srv:
+        ids = []
+        for i, (kind, arg) in enumerate(reqs):
+            ids.append(srv.submit_primes(arg) if kind == "primes" else srv.submit_range(*arg))
+            if i % 4 == 3:
+                srv.step()                                            # arrivals while work runs
+        res = drain(srv, ids)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
+    for (kind, arg), rid in zip(reqs, ids):
+        got, lat = res[rid]
+        alone = ctx.eval_primes(arg) if kind == "primes" else ctx.search_range(*arg)[0]
+        assert [int(p) for p in got["p"]] == [int(p) for p in alone["p"]]
+        assert as_pairs(got) == as_pairs(alone)
+        assert lat > 0
+
+
+def test_server_restart_after_failed_step(ctx):
+    """A step forced to fail (on the host) restarts the active requests; the
+    results are unchanged."""
+    say("case: server fault injection")
+    ps1 = oracle.primes(3 * 10 ** 9, 3 * 10 ** 9 + 400)
+    with wv.Server(ctx, step_terms=1 << 31) as srv:
+        srv.inject_fault(2)
+        a = srv.submit_primes(ps1)
+        b = srv.submit_range(10 ** 8, 10 ** 8 + 5000)
+        res = drain(srv, [a, b])
+        st = srv.stats()
+    assert st["readmits"] >= 1
+    assert as_pairs(res[a][0]) == as_pairs(ctx.eval_primes(ps1))
+    assert as_pairs(res[b][0]) == as_pairs(ctx.search_range(10 ** 8, 10 ** 8 + 5000)[0])
+
+
+def test_server_pool_admission(ctx):
+    """A pool smaller than the offered requests admits them as slots free up."""
+    ps = oracle.primes(10 ** 7, 10 ** 7 + 20000)
+    chunks = [ps[i:i + 300] for i in range(0, len(ps), 300)]
+    with wv.Server(ctx, step_terms=1 << 30, max_primes=700) as srv:
+        ids = [srv.submit_primes(c) for c in chunks]
+        active, pending = srv.step()
+        assert pending > 0 and active <= 2
+        res = drain(srv, ids)
+    for c, rid in zip(chunks, ids):
+        assert as_pairs(res[rid][0]) == as_pairs(ctx.eval_primes(c))
