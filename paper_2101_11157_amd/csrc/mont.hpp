@@ -33,10 +33,13 @@ __host__ __device__ __forceinline__ uint64_t mul32w(uint32_t a, uint32_t b) {
     return (uint64_t)a * (uint64_t)b;
 }
 
-// a * b * 2^-64 mod p, output in [0, 2p).
-// Precondition: a, b < 4p with p < 2^40 odd.  Then the high limbs a1, b1 are
-// < 2^10, a1*b1 < 2^20 fits one 32-bit product, the round-0 value is < 2^43,
-// the round-1 value < 2^53, and the result (ab + Mp)/2^64 < p + 16p^2/2^64 <= 2p.
+// a * b * 2^-64 mod p (Montgomery product), output in [0, 2p).
+// Preconditions (p < 2^40 odd): a < 4p, so a1 = a >> 32 < 2^10; b < 2^62; and
+// a * b < p * 2^64.  Then the round-0 value is < 2^43, the round-1 value
+// T1 = T0 + a0*b1 < 2^63, a1*b1 enters after the second division, and the
+// result (ab + Mp)/2^64 < p + ab/2^64 < 2p.  With b < 4p as well this is the
+// plain lazy Montgomery product; b may also be a value up to p * 2^21 that is
+// only known modulo p (a finite-difference accumulator between reductions).
 __host__ __device__ __forceinline__ uint64_t mmul(uint64_t a, uint64_t b, const Mont &m) {
     const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
     const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
@@ -45,11 +48,12 @@ __host__ __device__ __forceinline__ uint64_t mmul(uint64_t a, uint64_t b, const 
     uint32_t q = (uint32_t)t * m.ninv;
     uint64_t x = mul32w(q, m.p0) + (uint32_t)t;          // == 0 mod 2^32, < 2^64
     uint64_t T = (t >> 32) + (x >> 32) + mul32w(a1, b0) + mul32w(q, m.p1);
-    // round 1: T += a*b1 (a1*b1 < 2^20, a 32-bit product), same reduction
-    T += mul32w(a0, b1) + ((uint64_t)(a1 * b1) << 32);
+    // round 1: the a0*b1 part shares the low word; a1*b1 sits one word higher
+    // and is added after the division
+    T += mul32w(a0, b1);
     q = (uint32_t)T * m.ninv;
     x = mul32w(q, m.p0) + (uint32_t)T;
-    return (T >> 32) + (x >> 32) + mul32w(q, m.p1);
+    return (T >> 32) + (x >> 32) + mul32w(q, m.p1) + mul32w(a1, b1);
 }
 
 // x < 2p -> x mod p

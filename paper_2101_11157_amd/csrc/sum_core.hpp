@@ -84,24 +84,50 @@ __host__ __device__ __forceinline__ uint64_t pow_mont(uint64_t s, const Mont &m,
 //   prod_{j<K} (z + (x+j)^DEG) = P(x) + Q(x) z + O(z^2),
 //   P(x) = prod_j (x+j)^DEG,   Q(x) = sum_j prod_{i != j} (x+i)^DEG,
 // and P, Q are polynomials in x of degrees DEG*K and DEG*(K-1).  Along the
-// blocks x = s0, s0+K, s0+2K, ... they are stepped by forward differences
-// (DEG*K + DEG*(K-1) modular additions per block) and each block is folded
-// into the running pair with the pair product of eqnCombinePairs:
+// blocks x = s0, s0+K, s0+2K, ... they are stepped by forward differences and
+// each block is folded into the running pair with the pair product of
+// eqnCombinePairs:
 //   (c0, c1) <- (c0 P, c0 Q + c1 P)      (three Montgomery products per block).
 // The difference tables start from P, Q evaluated directly at the first
-// DEG*K + 1 block points.  Terms beyond the last full block are folded one by
-// one.  The result is the same (c0, c1) as run_chunk up to rounding order,
-// which exact arithmetic does not have: bit-identical residues.
+// DEG*K + 1 block points, in [0, p).  Between reductions the differences are
+// stepped as plain 64-bit sums: n steps from entries below 2p leave every entry
+// below 2p * 2^n (entry i becomes sum_j C(n, j) D_{i+j}), and the Montgomery
+// product accepts such a second operand for n <= 20 (mont.hpp).  So the tables
+// are brought back below 2p only every kRenorm blocks, by reduce_f64.  Each
+// sum passes through opaque(): the compiler otherwise recognises the chain of
+// additions as a polynomial recurrence and rewrites the values after the loop
+// as closed forms with binomial coefficients, which costs hundreds of
+// registers.  Terms
+// beyond the last full block are folded one by one.  The result is the same
+// (c0, c1) as run_chunk up to rounding order, which exact arithmetic does not
+// have: bit-identical residues.
+// x < p * 2^24, p < 2^40 -> r == x (mod p), r in [0, 2p).  The quotient is
+// estimated in double precision: xd * pinv carries a relative error below
+// 2^-51 on a value below 2^24, so y = x/p - 1/2 is known to within 2^-26 and
+// its truncation is floor(x/p) or one less (0 when y < 0).  The remainder is
+// formed modulo 2^64 as x + q (2^64 - p).
+__host__ __device__ __forceinline__ uint64_t reduce_f64(uint64_t x, uint64_t negp, double pinv) {
+    const double y = (double)x * pinv - 0.5;
+    const uint32_t q = y > 0.0 ? (uint32_t)y : 0u;
+    return x + mul32w(q, (uint32_t)negp) + ((uint64_t)(q * (uint32_t)(negp >> 32)) << 32);
+}
+
+constexpr int kRenorm = 20;
+
+// x unchanged, but hidden from the optimiser's recurrence analysis
+__host__ __device__ __forceinline__ uint64_t opaque(uint64_t x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("" : "+v"(x));
+#endif
+    return x;
+}
+
 template <int DEG, int K>
 __host__ __device__ __forceinline__ void run_chunk_blocked(uint64_t s0, uint64_t n, const Mont &m, uint64_t r2,
                                                            uint64_t one, uint64_t &c0, uint64_t &c1) {
     constexpr int DP = DEG * K;
     constexpr int DQ = DEG * (K - 1);
     const uint64_t p = m.p;
-    uint64_t negp = 0 - p;
-#if defined(__HIPCC__)
-    asm volatile("" : "+v"(negp));   // keep s + negp an addition (not folded into a subtract)
-#endif
     const uint64_t nb = n / K;
     uint64_t a0 = 1, a1 = 0;
     if (nb > 0) {
@@ -147,13 +173,25 @@ WV_UNROLL
 WV_UNROLL
             for (int i = DQ; i >= lev; i--) Qd[i] = subm(Qd[i], Qd[i - 1], p);
         }
-        for (uint64_t b = 0; b < nb; b++) {
-            a1 = mmul(a0, Qd[0], m) + mmul(a1, Pd[0], m);
-            a0 = mmul(a0, Pd[0], m);
+        const uint64_t negp = 0 - p;
+        const double pinv = 1.0 / (double)p;
+        uint64_t b = 0;
+        for (;;) {
+            const uint64_t steps = nb - b < (uint64_t)kRenorm ? nb - b : (uint64_t)kRenorm;
+            for (uint64_t k = 0; k < steps; k++) {
+                a1 = mmul(a0, Qd[0], m) + mmul(a1, Pd[0], m);
+                a0 = mmul(a0, Pd[0], m);
 WV_UNROLL
-            for (int i = 0; i < DP; i++) Pd[i] = addm_n(Pd[i], Pd[i + 1], negp);
+                for (int i = 0; i < DP; i++) Pd[i] = opaque(Pd[i] + Pd[i + 1]);
 WV_UNROLL
-            for (int i = 0; i < DQ; i++) Qd[i] = addm_n(Qd[i], Qd[i + 1], negp);
+                for (int i = 0; i < DQ; i++) Qd[i] = opaque(Qd[i] + Qd[i + 1]);
+            }
+            b += steps;
+            if (b >= nb) break;
+WV_UNROLL
+            for (int i = 0; i < DP; i++) Pd[i] = reduce_f64(Pd[i], negp, pinv);
+WV_UNROLL
+            for (int i = 0; i < DQ; i++) Qd[i] = reduce_f64(Qd[i], negp, pinv);
         }
     }
     for (uint64_t t = nb * K; t < n; t++) {

@@ -56,6 +56,16 @@ int main() {
             uint64_t a = rng() % (4 * p), b = rng() % (4 * p);
             if (!check(a, b)) return 1;
         }
+        // second operand up to p * 2^21 (unreduced difference accumulators)
+        const uint64_t big = p << 21;
+        const uint64_t bigs[] = {big - 1, big - p, (p << 15) + 12345, p << 8};
+        for (uint64_t b : bigs)
+            for (uint64_t a : edge)
+                if (!check(a, b)) return 1;
+        for (int k = 0; k < 20000; k++) {
+            uint64_t a = rng() % (4 * p), b = rng() % big;
+            if (!check(a, b)) return 1;
+        }
         // addm / subm / to_mont / from_mont / mpow
         for (int k = 0; k < 2000; k++) {
             uint64_t a = rng() % p, b = rng() % p;
@@ -125,6 +135,8 @@ int main() {
             uint64_t n = rng() % 700;
             if (k == 0) n = 0;
             if (k == 1) n = 5;
+            if (k == 2) n = 16 * 20 * 3 + 77;   // several reduction periods of the tables
+            if (k == 3) n = 8 * 20 + 8;         // a period boundary at K = 8
             if (s0 + n > p) n = p - s0;
             uint64_t r0, r1;
             auto cmp = [&](uint64_t x0, uint64_t x1, const char *what) {
@@ -148,6 +160,33 @@ int main() {
             run_chunk_blocked<2, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k4")) return 1;
             run_chunk_blocked<2, 8>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k8")) return 1;
             run_chunk_blocked<2, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k16")) return 1;
+        }
+        // reduce_f64: x < p 2^24 -> r == x mod p, r < 2p, at quotient boundaries
+        {
+            const uint64_t negp = 0 - p;
+            const double pinv = 1.0 / (double)p;
+            auto chk = [&](uint64_t x) {
+                const uint64_t r = reduce_f64(x, negp, pinv);
+                if (r % p != x % p || r >= 2 * p) {
+                    printf("FAIL reduce_f64 p=%llu x=%llu r=%llu\n", (unsigned long long)p, (unsigned long long)x,
+                           (unsigned long long)r);
+                    return false;
+                }
+                checks++;
+                return true;
+            };
+            const uint64_t top = (p << 24) - 1;
+            for (uint64_t x : {(uint64_t)0, (uint64_t)1, p - 1, p, p + 1, 2 * p - 1, 2 * p, top, top - p, top / p * p,
+                               top / p * p - 1, (p << 21) - 1, (p << 21), (p << 21) + 1})
+                if (!chk(x)) return 1;
+            for (int k = 0; k < 20000; k++) {
+                const uint64_t q = rng() % ((top / p) + 1);
+                const uint64_t e = rng() % 5;
+                const uint64_t x = q * p + e;
+                if (x <= top && !chk(x)) return 1;
+                if (q > 0 && !chk(q * p - 1 - e)) return 1;
+                if (!chk(rng() % (top + 1))) return 1;
+            }
         }
         // addm_n, canon4
         for (int k = 0; k < 1000; k++) {
