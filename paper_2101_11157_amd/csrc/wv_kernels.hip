@@ -476,8 +476,8 @@ struct SumVariant {
 
 // Compiled block shapes (terms per block, Bernoulli side / Euler side).
 static const SumVariant kSumVariants[] = {
-    {1, 1, k_sum<1, 1>},   {4, 4, k_sum<4, 4>},   {8, 8, k_sum<8, 8>},
-    {8, 16, k_sum<8, 16>}, {16, 8, k_sum<16, 8>}, {16, 16, k_sum<16, 16>},
+    {1, 1, k_sum<1, 1>},     {4, 4, k_sum<4, 4>},     {8, 8, k_sum<8, 8>},    {8, 16, k_sum<8, 16>},
+    {12, 12, k_sum<12, 12>}, {12, 16, k_sum<12, 16>}, {16, 16, k_sum<16, 16>},
 };
 constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants[0]));
 

@@ -159,7 +159,7 @@ def test_first_sum_spans_many_waves(ctx):
     assert as_pairs(got) == oracle.residues(ps, method="table")
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (4, 4), (8, 8), (8, 16), (16, 8), (16, 16)])
+@pytest.mark.parametrize("shape", wv.BLOCK_SHAPES)
 def test_block_shape_invariance(ctx, shape):
     """Every compiled block shape of the term-sum kernel gives the same residues
     (long chunks take the blocked path, segment tails the one-term path)."""
