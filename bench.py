@@ -87,10 +87,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="1e11", choices=sorted(CONFIGS) + list(EXTRA_CONFIGS))
     ap.add_argument("--windows", type=int, default=64, help="batch: number of seeded windows")
-    ap.add_argument("--verify", type=int, default=0, help="batch: windows re-run alone and compared")
+    ap.add_argument("--verify", type=int, default=0,
+                    help="batch: windows re-run alone and compared (smallest first); serve: nonzero compares "
+                         "every request with the same request run alone")
     ap.add_argument("--requests", type=int, default=128, help="serve: requests in the seeded trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
     ap.add_argument("--step-terms", type=int, default=0, help="serve: terms per scheduling step")
+    ap.add_argument("--load", type=float, default=0.0,
+                    help="serve: also replay the trace at this fraction of the measured capacity")
     ap.add_argument("--window", type=int, default=0, help="integers per step (0: config default)")
     ap.add_argument("--chunk", type=int, default=0, help="terms per lane chunk (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -233,7 +237,7 @@ def bench_batch(args, wv):
         ok = True
         for k in order:
             ref, _ = ctx.search_range(*wins[k])
-            same = [(int(r["b"]), int(r["e"])) for r in ref] == [(int(r["b"]), int(r["e"])) for r in res[k]]
+            same = as_pairs(ref) == as_pairs(res[k])
             ok = ok and same
             print(f"verify window {k} {wins[k]}: {len(ref)} primes, {'identical' if same else 'DIFFERENT'}",
                   file=sys.stderr, flush=True)
@@ -248,15 +252,12 @@ def bench_batch(args, wv):
     }), flush=True)
 
 
-def bench_serve(args, wv):
-    """Seeded Poisson trace of single primes and intervals through the request
-    server; arrivals submitted at their times, latency from arrival."""
-    from paper_2101_11157_amd import workloads
-    trace = workloads.serve_trace(0, args.requests, rate=args.rate)
-    ctx = wv.Context(0)
-    srv = wv.Server(ctx, step_terms=args.step_terms)
+def run_trace(wv, ctx, trace, step_terms):
+    """Submit each request at its arrival time, step the server, collect
+    results; latency is measured from arrival."""
+    srv = wv.Server(ctx, step_terms=step_terms)
     t0 = time.perf_counter()
-    ids, arrive, lat = {}, {}, {}
+    ids, arrive, lat, out = {}, {}, {}, {}
     nxt = 0
     last = t0
     primes = 0
@@ -277,9 +278,8 @@ def bench_serve(args, wv):
                 res, server_ms = r
                 at, sub = arrive[rid]
                 lat[rid] = server_ms + (sub - at) * 1e3     # from arrival, not from submission
+                out[ids[rid]] = res
                 primes += len(res)
-        if nxt >= len(trace) and not lat and not ids:
-            break
         if time.perf_counter() - last > 10:
             last = time.perf_counter()
             st = srv.stats()
@@ -290,21 +290,58 @@ def bench_serve(args, wv):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    ctx.close()
     v = sorted(lat.values())
     pct = lambda q: v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
     span = trace[-1][0] if trace else 0.0
-    offered = st["terms_done"] / span if span > 0 else float("inf")
     capacity = st["terms_done"] / st["busy_s"] if st["busy_s"] > 0 else 0.0
-    print(json.dumps({
-        "metric": "served queries: p50/p99 latency and primes tested/sec (1 GPU)", "value": primes / wall,
-        "unit": "primes/s", "p50_ms": pct(0.5), "p99_ms": pct(0.99), "mean_ms": sum(v) / len(v),
-        "config": {"workload": f"seeded Poisson trace (default_rng(0)), {len(trace)} requests, "
-                               f"{args.rate:g}/s, 70% single primes, 30% intervals of 1e2..1e5, u in [1e8, 1e11]",
-                   "requests": len(trace), "primes": primes, "terms": st["terms_done"], "wall_s": wall,
-                   "busy_s": st["busy_s"], "steps": st["steps"], "offered_terms_per_s": offered,
-                   "capacity_terms_per_s": capacity, "offered_over_capacity": offered / capacity if capacity else None},
-    }), flush=True)
+    offered = st["terms_done"] / span if span > 0 else float("inf")
+    summary = {"value": primes / wall, "p50_ms": pct(0.5), "p99_ms": pct(0.99), "mean_ms": sum(v) / len(v),
+               "max_ms": v[-1], "requests": len(trace), "primes": primes, "terms": st["terms_done"],
+               "wall_s": wall, "busy_s": st["busy_s"], "steps": st["steps"], "offered_terms_per_s": offered,
+               "capacity_terms_per_s": capacity, "offered_over_capacity": offered / capacity if capacity else None}
+    return summary, out
+
+
+def bench_serve(args, wv):
+    """Seeded Poisson trace of single primes and intervals through the request
+    server; arrivals submitted at their times, latency from arrival.  With
+    --load f the same trace is replayed with its arrival times stretched so
+    that the offered load is f x the capacity measured on the first run."""
+    from paper_2101_11157_amd import workloads
+    trace = workloads.serve_trace(0, args.requests, rate=args.rate)
+    ctx = wv.Context(0)
+    main_run, out = run_trace(wv, ctx, trace, args.step_terms)
+    ok = None
+    if args.verify:
+        ok = True
+        for k, (at, kind, arg) in enumerate(trace):
+            alone = ctx.eval_primes([arg]) if kind == "prime" else ctx.search_range(*arg)[0]
+            same = as_pairs(alone) == as_pairs(out[k])
+            ok = ok and same
+            if not same:
+                print(f"verify request {k} ({kind} {arg}): DIFFERENT", file=sys.stderr, flush=True)
+        print(f"verify: {len(trace)} requests against the same request alone: "
+              f"{'identical' if ok else 'DIFFERENT'}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "served queries: p50/p99 latency and primes tested/sec (1 GPU)", "value": main_run["value"],
+        "unit": "primes/s", "p50_ms": main_run["p50_ms"], "p99_ms": main_run["p99_ms"],
+        "mean_ms": main_run["mean_ms"],
+        "config": dict({"workload": f"seeded Poisson trace (default_rng(0)), {len(trace)} requests, "
+                                    f"{args.rate:g}/s, 70% single primes, 30% intervals of 1e2..1e5, "
+                                    f"u in [1e8, 1e11]", "verified_identical": ok}, **main_run),
+    }
+    if args.load:
+        per_req = main_run["terms"] / len(trace)
+        rate = args.load * main_run["capacity_terms_per_s"] / per_req
+        print(f"supplementary run: {rate:.3f} requests/s ({args.load:g} x capacity)", file=sys.stderr, flush=True)
+        sup, _ = run_trace(wv, ctx, workloads.serve_trace(0, args.requests, rate=rate), args.step_terms)
+        line["supplementary"] = dict({"rate_per_s": rate, "load": args.load}, **sup)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def as_pairs(res):
+    return [(int(r["p"]), int(r["b"]), int(r["e"])) for r in res]
 
 
 if __name__ == "__main__":

@@ -167,6 +167,37 @@ int wv_search_range(wv_ctx *ctx, uint64_t lo, uint64_t hi,
                     wv_result *out, size_t cap, size_t *n_out,
                     uint64_t *hits, size_t hit_cap, size_t *n_hits);
 
+/* A prime whose symmetric residue is small (a "near miss"): the results of
+ * Section 3 list the primes in (1e9, 1e11) with |<B_{p-3}>_p| < 50 (Table 2),
+ * those of Section 5 the primes with |<E_{p-3}>_p| < 50 (Table 3); a hit
+ * (residue 0) is the limiting case. */
+typedef struct {
+    uint64_t p;
+    int64_t r;          /* symmetric residue in (-p/2, p/2] */
+    uint32_t which;     /* WV_NEAR_B (Bernoulli) or WV_NEAR_E (Euler) */
+    uint32_t reserved;
+} wv_near;
+
+enum { WV_NEAR_B = 1, WV_NEAR_E = 2 };
+
+#define WV_MAX_BINS 65536u
+
+/* Residue statistics over every prime p with max(lo,5) <= p < hi, without
+ * returning the per-prime results (the distributions the histograms of
+ * Sections 3 and 5 show: 2000 equal bins of <r>_p / p over (-1/2, 1/2]).
+ * hist_b / hist_e (bins entries each, 1 <= bins <= WV_MAX_BINS) receive the
+ * number of primes whose symmetric residue s of B_{p-3} (resp. E_{p-3}) falls
+ * in bin k = floor((s/p + 1/2) * bins) = floor((2s + p) * bins / (2p)).
+ * near receives the near misses |s| < near_bound (none for near_bound = 0)
+ * sorted by (p, which); *n_near receives their total number; if it exceeds
+ * near_cap, the first near_cap are written and the call returns WV_ETRUNC
+ * after completing (histograms and *n_primes are then still valid).
+ * *n_primes (may be NULL) receives the number of primes.  Host buffers owned
+ * by the caller.  Errors: WV_EINVAL, WV_EDOMAIN, WV_ETRUNC, WV_ENOMEM, WV_EHIP. */
+int wv_range_stats(wv_ctx *ctx, uint64_t lo, uint64_t hi, uint32_t bins, uint64_t near_bound,
+                   uint64_t *hist_b, uint64_t *hist_e, wv_near *near, size_t near_cap, size_t *n_near,
+                   uint64_t *n_primes);
+
 /* Batched search over nwin windows [lo[w], hi[w]) (may differ in size and
  * position): all windows are sieved together and all their primes go through
  * one plan and one persistent term-sum launch per batch of about 2^19 primes,

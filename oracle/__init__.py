@@ -254,3 +254,28 @@ def residue_one_parallel(p, method="table", nthreads=None):
         cb, ce = congruences.SV, congruences.E1
     return (congruence_residue(p, cb, nthreads=nthreads),
             congruence_residue(p, ce, nthreads=nthreads))
+
+
+# ---------------------------------------------------------------------------
+# Residue statistics (results of Sections 3 and 5)
+# ---------------------------------------------------------------------------
+
+def residue_stats(rows, bins=2000, bound=50):
+    """Histograms and near misses of a list of (p, b, e) residues.
+
+    The histograms of Sections 3 and 5 use `bins` equal bins of <r>_p / p over
+    (-1/2, 1/2]; a value falls in bin k when -1/2 + k/bins <= <r>_p/p <
+    -1/2 + (k+1)/bins, i.e. k = floor((<r>_p/p + 1/2) bins), computed here with
+    exact rationals.  Near misses (Tables 2 and 3): |<r>_p| < bound, as
+    (p, <r>_p, which) with which 1 for B_{p-3}, 2 for E_{p-3}, sorted.
+    """
+    hist = [[0] * bins, [0] * bins]
+    near = []
+    for p, b, e in rows:
+        for w, r in enumerate((b, e)):
+            s = exact.symmetric(r, p)
+            k = int((Fraction(s, p) + Fraction(1, 2)) * bins // 1)
+            hist[w][k] += 1
+            if abs(s) < bound:
+                near.append((p, s, w + 1))
+    return hist[0], hist[1], sorted(near)

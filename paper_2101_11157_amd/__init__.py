@@ -38,6 +38,10 @@ BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (8, 16), (12, 12), (12, 16), (16, 16)]
 
 # wv_result as a numpy record (32 bytes)
 RESULT_DTYPE = np.dtype([("p", "<u8"), ("b", "<u8"), ("e", "<u8"), ("flags", "<u4"), ("reserved", "<u4")])
+# wv_near (24 bytes): a prime with a small symmetric residue; which = 1 (B) or 2 (E)
+NEAR_DTYPE = np.dtype([("p", "<u8"), ("r", "<i8"), ("which", "<u4"), ("reserved", "<u4")])
+NEAR_B, NEAR_E = 1, 2
+MAX_BINS = 65536
 
 
 class WvStats(ctypes.Structure):
@@ -111,6 +115,8 @@ def lib():
             "wv_search_windows": (ctypes.c_int, [VP, P_U64, P_U64, SZ, VP, SZ, ctypes.POINTER(SZ),
                                                  ctypes.POINTER(SZ)]),
             "wv_set_progress": (ctypes.c_int, [VP, PROGRESS_FN, VP, U64]),
+            "wv_range_stats": (ctypes.c_int, [VP, U64, U64, ctypes.c_uint32, U64, P_U64, P_U64, VP, SZ,
+                                              ctypes.POINTER(SZ), P_U64]),
             "wv_autotune": (ctypes.c_int, [VP, U64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), P_U64, ctypes.POINTER(ctypes.c_double)]),
             "wv_tune_save": (ctypes.c_int, [VP, ctypes.c_char_p]),
@@ -259,6 +265,25 @@ class Context:
                                      out.ctypes.data_as(VP), n_out.value, ctypes.byref(n_out), offs)
         _check(st, "wv_search_windows")
         return [out[offs[w]:offs[w + 1]] for w in range(lo.size)]
+
+    def range_stats(self, lo, hi, bins=2000, near=50, near_cap=4096):
+        """Residue statistics of [lo, hi) computed on the device: (hist_b,
+        hist_e, near misses (NEAR_DTYPE, sorted by p then which), n_primes).
+        Bin k of the symmetric residue s counts floor((s/p + 1/2) bins) == k."""
+        hb = np.zeros(bins, dtype=np.uint64)
+        he = np.zeros(bins, dtype=np.uint64)
+        nr = np.zeros(max(1, near_cap), dtype=NEAR_DTYPE)
+        n_near, n_primes = SZ(), U64()
+        st = lib().wv_range_stats(self._h, int(lo), int(hi), int(bins), int(near), hb.ctypes.data_as(P_U64),
+                                  he.ctypes.data_as(P_U64), nr.ctypes.data_as(VP), near_cap, ctypes.byref(n_near),
+                                  ctypes.byref(n_primes))
+        if st == WV_ETRUNC:
+            nr = np.zeros(n_near.value, dtype=NEAR_DTYPE)
+            st = lib().wv_range_stats(self._h, int(lo), int(hi), int(bins), int(near), hb.ctypes.data_as(P_U64),
+                                      he.ctypes.data_as(P_U64), nr.ctypes.data_as(VP), n_near.value,
+                                      ctypes.byref(n_near), ctypes.byref(n_primes))
+        _check(st, "wv_range_stats")
+        return hb, he, nr[:n_near.value], n_primes.value
 
     def set_progress(self, fn=None, terms_per_launch=0):
         """Callback fn(done, total) between term-sum launches of long calls (None: off)."""

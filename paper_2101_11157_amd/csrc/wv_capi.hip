@@ -268,7 +268,8 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
 // Descriptors are grouped into batches of at most kMaxBatchSegs segments and
 // about kMaxBatchPrimes primes; each batch is one plan and one persistent
 // term-sum launch (or one split launch sequence under a progress callback).
-int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts, wv_result *out) {
+int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts, wv_result *out,
+                 StatsSink *sink) {
     hipStream_t st = c->stream;
     size_t i = 0, written = 0;
     while (i < descs.size()) {
@@ -292,7 +293,26 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
         c->stats.ms_sieve += elapsed(c->ev[EV_START], c->ev[EV_SIEVE]);
         WV_TRY(ensure(c, c->results, got * sizeof(wv_result)));
         WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)got, as<wv_result>(c->results)));
-        WV_HIP(hipMemcpyAsync(out + written, c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
+        if (out)
+            WV_HIP(hipMemcpyAsync(out + written, c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
+        if (sink) {
+            // near-miss slots: a counter, then room for two entries per prime
+            WV_TRY(ensure(c, c->stats_near, 64 + 2 * got * sizeof(wv_near)));
+            auto *cnt = as<unsigned long long>(c->stats_near);
+            auto *near = reinterpret_cast<wv_near *>(as<char>(c->stats_near) + 64);
+            WV_HIP(launch_set_u64(st, reinterpret_cast<uint64_t *>(cnt), 1, 0));
+            WV_HIP(launch_stats(st, as<wv_result>(c->results), (uint32_t)got, sink->bins, sink->bound,
+                                as<unsigned long long>(c->stats_hist), near, cnt));
+            unsigned long long nn = 0;
+            WV_HIP(hipMemcpyAsync(&nn, cnt, sizeof(nn), hipMemcpyDeviceToHost, st));
+            WV_HIP(hipStreamSynchronize(st));
+            if (nn > 2 * got) return WV_EHIP;   // cannot happen: two residues per prime
+            const size_t base = sink->near.size();
+            sink->near.resize(base + nn);
+            if (nn)
+                WV_HIP(hipMemcpyAsync(sink->near.data() + base, near, nn * sizeof(wv_near), hipMemcpyDeviceToHost,
+                                      st));
+        }
         WV_HIP(hipStreamSynchronize(st));
         written += got;
         i = j;
@@ -509,6 +529,40 @@ int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t 
     if (total == 0) return WV_OK;
     pick_tuned(c, pmax);
     return search_descs(c, d, counts, out);
+}
+
+int wv_range_stats(wv_ctx *c, uint64_t lo, uint64_t hi, uint32_t bins, uint64_t near_bound, uint64_t *hist_b,
+                   uint64_t *hist_e, wv_near *near, size_t near_cap, size_t *n_near, uint64_t *n_primes) {
+    if (!c || lo > hi || bins == 0 || bins > WV_MAX_BINS || !hist_b || !hist_e || !n_near || (near_cap && !near))
+        return WV_EINVAL;
+    if (hi > WV_P_MAX) return WV_EDOMAIN;
+    WV_TRY(check_device(c));
+    std::vector<SegDesc> d;
+    window_descs(lo, hi, d);
+    std::vector<uint32_t> counts(d.size());
+    if (!d.empty()) WV_TRY(sieve_count(c, d.data(), d.size(), false, counts.data()));
+    uint64_t total = 0;
+    for (uint32_t k : counts) total += k;
+    c->stats = wv_stats{};
+    StatsSink sink{bins, near_bound, {}};
+    WV_TRY(ensure(c, c->stats_hist, 2 * (size_t)bins * sizeof(uint64_t)));
+    WV_HIP(launch_fill_pairs(c->stream, as<Pair>(c->stats_hist), bins, 0, 0));   // 2 * bins zero words
+    if (total > 0) {
+        pick_tuned(c, hi - 1);
+        WV_TRY(search_descs(c, d, counts, nullptr, &sink));
+    }
+    WV_HIP(hipMemcpyAsync(hist_b, c->stats_hist.ptr, bins * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipMemcpyAsync(hist_e, as<uint64_t>(c->stats_hist) + bins, bins * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipStreamSynchronize(c->stream));
+    std::sort(sink.near.begin(), sink.near.end(), [](const wv_near &a, const wv_near &b) {
+        return a.p != b.p ? a.p < b.p : a.which < b.which;
+    });
+    *n_near = sink.near.size();
+    if (n_primes) *n_primes = total;
+    const size_t nw = std::min(near_cap, sink.near.size());
+    if (nw) std::copy(sink.near.begin(), sink.near.begin() + nw, near);
+    return sink.near.size() > near_cap ? WV_ETRUNC : WV_OK;
 }
 
 int wv_search_range(wv_ctx *c, uint64_t lo, uint64_t hi, wv_result *out, size_t cap, size_t *n_out,

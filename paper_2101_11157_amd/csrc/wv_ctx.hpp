@@ -62,6 +62,14 @@ struct GraphEntry {
     hipGraphExec_t exec;
 };
 
+// Per-batch consumer of device results that never go to the host: residue
+// histograms accumulated on the device, near misses gathered per batch.
+struct StatsSink {
+    uint32_t bins;
+    uint64_t bound;
+    std::vector<wv_near> near;   // host copy, all batches
+};
+
 struct TuneEntry {
     int log2p;           // primes in [2^log2p, 2^(log2p+1))
     int variant;
@@ -86,7 +94,7 @@ struct wv_ctx {
     uint32_t n_base = 0;
     uint64_t gen = 0;                             // bumped on every device reallocation
     wv::DevBuf base_primes, primes, pr, segs, terms, cnt, off, tiles, scal, partials, seg_pairs, results,
-        seg_counts, seg_bits, seg_off, seg_desc, pad_primes;
+        seg_counts, seg_bits, seg_off, seg_desc, pad_primes, stats_hist, stats_near;
     wv_stats stats{};
     wv_progress_fn progress = nullptr;
     void *progress_user = nullptr;
@@ -109,8 +117,9 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, wv_result *d
 void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d);
 int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts);
 int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out);
+// out: host results (may be NULL when sink is set); sink: device statistics
 int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts,
-                 wv_result *out);
+                 wv_result *out, StatsSink *sink = nullptr);
 void pick_tuned(wv_ctx *c, uint64_t pmax);
 
 }  // namespace wv

@@ -86,6 +86,11 @@ hipError_t launch_fill_pairs(hipStream_t st, Pair *p, uint64_t n, uint64_t c0, u
 // out[i] = i < n ? src[i] : 0  (zero marks a padding slot the plan rejects)
 hipError_t launch_copy_pad(hipStream_t st, const uint64_t *src, uint64_t n, uint64_t *dst, uint64_t n_pad);
 hipError_t launch_copy_results(hipStream_t st, const wv_result *src, uint64_t n, wv_result *dst);
+// hist[w * bins + k] += primes whose symmetric residue (w = 0: b, 1: e) falls
+// in bin k; residues with |s| < bound appended at near[atomic (*near_n)++]
+// (room for 2n entries)
+hipError_t launch_stats(hipStream_t st, const wv_result *res, uint32_t n, uint32_t bins, uint64_t bound,
+                        unsigned long long *hist, wv_near *near, unsigned long long *near_n);
 
 // table sizes (host copy of the compiled tables)
 int table_slots(int id);

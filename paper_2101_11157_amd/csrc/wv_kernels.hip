@@ -729,6 +729,38 @@ hipError_t launch_copy_pad(hipStream_t st, const uint64_t *src, uint64_t n, uint
     return hipGetLastError();
 }
 
+// Residue statistics of Sections 3 and 5: bin k = floor((2s + p) bins / (2p))
+// of the symmetric residue s in (-p/2, p/2] (2s + p in [1, 2p - 1], so k is in
+// [0, bins); the product is below 2^57 for p < 2^40, bins <= 2^16), and the
+// near misses |s| < bound.
+__global__ void __launch_bounds__(256) k_stats(const wv_result *__restrict__ res, uint32_t n, uint32_t bins,
+                                               uint64_t bound, unsigned long long *__restrict__ hist,
+                                               wv_near *__restrict__ near, unsigned long long *__restrict__ near_n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const wv_result r = res[i];
+    const uint64_t p = r.p;
+    const uint64_t half = (p - 1) / 2;
+    for (int w = 0; w < 2; w++) {
+        const uint64_t v = w == 0 ? r.b : r.e;
+        const int64_t s = v > half ? (int64_t)v - (int64_t)p : (int64_t)v;
+        const uint64_t k = (uint64_t)(2 * s + (int64_t)p) * bins / (2 * p);
+        atomicAdd(&hist[(uint64_t)w * bins + k], 1ull);
+        const uint64_t a = s < 0 ? (uint64_t)(-s) : (uint64_t)s;
+        if (a < bound) {
+            const unsigned long long slot = atomicAdd(near_n, 1ull);
+            if (slot < 2ull * n) near[slot] = wv_near{p, s, (uint32_t)(w == 0 ? WV_NEAR_B : WV_NEAR_E), 0u};
+        }
+    }
+}
+
+hipError_t launch_stats(hipStream_t st, const wv_result *res, uint32_t n, uint32_t bins, uint64_t bound,
+                        unsigned long long *hist, wv_near *near, unsigned long long *near_n) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stats, dim3(blocks_for(n, 256)), dim3(256), 0, st, res, n, bins, bound, hist, near, near_n);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy_results(hipStream_t st, const wv_result *src, uint64_t n, wv_result *dst) {
     hipLaunchKernelGGL(k_copy_results, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, n, dst);
     return hipGetLastError();

@@ -14,6 +14,14 @@ of the paper-scale workloads:
 * sums_2p40.json    single sums S(x, y) for the largest primes below 2^40
                     (the top of the supported range), for the narrowest
                     intervals of eqnBB30 and eqnEE33.
+* batch_seed0.json  the 64 uneven windows of workloads.batch_windows(seed 0):
+                    prime count of every window, and residues (eqnBB30 /
+                    eqnEE33) of its first and last prime and of 2 more drawn
+                    with random.Random(window index).
+* serve_seed0.json  the 128 requests of workloads.serve_trace(seed 0): for a
+                    single prime its residues, for an interval its prime count
+                    and the residues of one prime drawn with
+                    random.Random(request index).
 
 Usage: python tests/golden/make_golden.py [which ...]   (default: all)
 """
@@ -96,8 +104,48 @@ def sums_2p40():
     _write("sums_2p40.json", {"rows": rows})
 
 
+def _residue_rows(ps, nt):
+    rows = []
+    for p in ps:
+        b, e = both(p, C.BB30, C.EE33, nt)
+        rows.append({"p": p, "b": b, "e": e})
+    return rows
+
+
+def batch_seed0():
+    from paper_2101_11157_amd import workloads
+    t0 = time.time()
+    nt = oracle.max_threads()
+    out = []
+    for i, (lo, hi) in enumerate(workloads.batch_windows(0, 64)):
+        ps = oracle.primes(lo, hi)
+        pick = sorted(set([ps[0], ps[-1]] + random.Random(i).sample(ps, 2)))
+        out.append({"lo": lo, "hi": hi, "n_primes": len(ps), "rows": _residue_rows(pick, nt)})
+        print(f"batch window {i}: [{lo}, {hi}) {len(ps)} primes ({time.time() - t0:.0f}s)", flush=True)
+    _write("batch_seed0.json", {"windows": out, "method": "eqnBB30+eqnEE33",
+                                "sample": "first, last and 2 by random.Random(window index)"})
+
+
+def serve_seed0():
+    from paper_2101_11157_amd import workloads
+    t0 = time.time()
+    nt = oracle.max_threads()
+    out = []
+    for i, (t, kind, arg) in enumerate(workloads.serve_trace(0, 128)):
+        if kind == "prime":
+            out.append({"kind": kind, "p": arg, "rows": _residue_rows([arg], nt)})
+        else:
+            ps = oracle.primes(*arg)
+            pick = random.Random(i).sample(ps, 1) if ps else []
+            out.append({"kind": kind, "lo": arg[0], "hi": arg[1], "n_primes": len(ps),
+                        "rows": _residue_rows(pick, nt)})
+        print(f"serve request {i}: {kind} ({time.time() - t0:.0f}s)", flush=True)
+    _write("serve_seed0.json", {"requests": out, "method": "eqnBB30+eqnEE33",
+                                "sample": "single primes; one prime per interval by random.Random(request index)"})
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["counts", "sums", "w9", "w11"]
+    which = sys.argv[1:] or ["counts", "sums", "w9", "w11", "batch", "serve"]
     if "counts" in which:
         counts()
     if "sums" in which:
@@ -106,3 +154,7 @@ if __name__ == "__main__":
         window(10 ** 9, 10 ** 9 + 10 ** 7, 8, 8, 256, 32, "window_1e9.json")
     if "w11" in which:
         window(10 ** 11 - 10 ** 6, 10 ** 11, 2, 2, 12, 4, "window_1e11.json")
+    if "batch" in which:
+        batch_seed0()
+    if "serve" in which:
+        serve_seed0()

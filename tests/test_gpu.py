@@ -526,6 +526,69 @@ def test_server_mixed_requests_match_alone(ctx):
         assert lat > 0
 
 
+def test_batch_windows_seed0_oracle_sample(ctx):
+    """The 64 uneven windows of the batched workload (seed 0): every window's
+    prime count, the oracle's residues of 4 primes per window, and the windows
+    below 1e8 (the cheap ones) through one batched call."""
+    from paper_2101_11157_amd import workloads
+    g = golden_json("batch_seed0.json")
+    wins = workloads.batch_windows(0, 64)
+    assert [(w["lo"], w["hi"]) for w in g["windows"]] == wins
+    say("case: batch seed 0, prime counts of 64 windows")
+    for w in g["windows"]:
+        assert ctx.count_primes(w["lo"], w["hi"]) == w["n_primes"], (w["lo"], w["hi"])
+    rows = [r for w in g["windows"] for r in w["rows"]]
+    say(f"case: batch seed 0, {len(rows)} sampled primes")
+    res = ctx.eval_primes([r["p"] for r in rows])
+    assert as_pairs(res) == [(r["b"], r["e"]) for r in rows]
+    small = [k for k, (a, b) in enumerate(wins) if b < 10 ** 8]
+    say(f"case: batch seed 0, {len(small)} windows below 1e8 batched")
+    assert len(small) >= 8
+    got = ctx.search_windows([wins[k][0] for k in small], [wins[k][1] for k in small])
+    for k, res in zip(small, got):
+        w = g["windows"][k]
+        assert len(res) == w["n_primes"]
+        by_p = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in res}
+        for r in w["rows"]:
+            assert by_p[r["p"]] == (r["b"], r["e"]), r["p"]
+
+
+def test_serve_seed0_oracle_sample(ctx):
+    """The 128-request serving trace (seed 0): the single primes and the
+    cheaper intervals through the request server (results against the
+    oracle's sample), every interval's prime count, and the oracle's sampled
+    prime of each of the other intervals."""
+    from paper_2101_11157_amd import workloads
+    g = golden_json("serve_seed0.json")
+    trace = workloads.serve_trace(0, 128)
+    assert len(g["requests"]) == len(trace)
+    served, rest = [], []
+    for (t, kind, arg), q in zip(trace, g["requests"]):
+        assert q["kind"] == kind
+        if kind == "prime":
+            assert q["p"] == arg
+            served.append((kind, arg, q))
+        else:
+            assert (q["lo"], q["hi"]) == arg
+            assert ctx.count_primes(*arg) == q["n_primes"], arg
+            cost = 0.0878 * (arg[1] - arg[0]) * arg[0] / max(1.0, np.log(arg[0]))
+            (served if cost < 2e12 else rest).append((kind, arg, q))
+    say(f"case: serve seed 0, {len(served)} requests through the server, {len(rest)} sampled alone")
+    with wv.Server(ctx, step_terms=1 << 36) as srv:
+        ids = [srv.submit_primes([arg]) if kind == "prime" else srv.submit_range(*arg) for kind, arg, _ in served]
+        res = drain(srv, ids)
+    for (kind, arg, q), rid in zip(served, ids):
+        got, _ = res[rid]
+        if kind == "range":
+            assert len(got) == q["n_primes"]
+        by_p = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in got}
+        for r in q["rows"]:
+            assert by_p[r["p"]] == (r["b"], r["e"]), r["p"]
+    rows = [r for _, _, q in rest for r in q["rows"]]
+    alone = ctx.eval_primes([r["p"] for r in rows])
+    assert as_pairs(alone) == [(r["b"], r["e"]) for r in rows]
+
+
 def test_server_restart_after_failed_step(ctx):
     """A step forced to fail (on the host) restarts the active requests; the
     results are unchanged."""
@@ -553,3 +616,90 @@ def test_server_pool_admission(ctx):
         res = drain(srv, ids)
     for c, rid in zip(chunks, ids):
         assert as_pairs(res[rid][0]) == as_pairs(ctx.eval_primes(c))
+
+
+# ---------------------------------------------------------------------------
+# residue statistics on the device (histograms of Sections 3 and 5, Tables 2-3)
+# ---------------------------------------------------------------------------
+
+def _table_rows(name):
+    return [(int(p), int(r)) for p, r in read_golden(name)]
+
+
+def test_range_stats_small_window_vs_oracle(ctx):
+    """All primes 5 <= p < 1e5: device histograms (2000 bins and 7 bins) and
+    near misses equal the oracle's, computed from the oracle's residues."""
+    say("case: range_stats(5, 1e5)")
+    ps = oracle.primes(5, 10 ** 5)
+    rows = [(p, b, e) for p, (b, e) in zip(ps, oracle.residues(ps))]
+    for bins, bound in ((2000, 50), (7, 1000)):
+        hb, he, near, n = ctx.range_stats(5, 10 ** 5, bins=bins, near=bound)
+        wb, we, wnear = oracle.residue_stats(rows, bins=bins, bound=bound)
+        assert n == len(ps)
+        assert list(hb) == wb and list(he) == we
+        assert [(int(x["p"]), int(x["r"]), int(x["which"])) for x in near] == wnear
+
+
+def test_range_stats_reproduces_tables_2_and_3(ctx):
+    """Tables 2 and 3 list every prime in (1e9, 1e11) with |<r>_p| < 50, so a
+    window around a printed prime has exactly the printed near misses."""
+    tb = _table_rows("near_miss_B.txt")
+    te = _table_rows("near_miss_E.txt")
+    printed = sorted([(p, r, 1) for p, r in tb] + [(p, r, 2) for p, r in te])
+    centres = [p for p, _ in tb[:4]] + [p for p, _ in te[:5]]
+    for c in centres:
+        lo, hi = c - 4000, c + 4000
+        say(f"case: range_stats near {c}")
+        hb, he, near, n = ctx.range_stats(lo, hi, bins=2000, near=50)
+        assert int(hb.sum()) == int(he.sum()) == n == ctx.count_primes(lo, hi)
+        got = [(int(x["p"]), int(x["r"]), int(x["which"])) for x in near]
+        assert got == [t for t in printed if lo <= t[0] < hi]
+
+
+def test_range_stats_equals_host_statistics_of_search(ctx):
+    """At 1e9 (about 10^4 primes): the device statistics equal the same
+    statistics taken on the host from wv_search_range's results, and a
+    sample of those results equals the oracle."""
+    lo, hi = 10 ** 9, 10 ** 9 + 2 * 10 ** 5
+    say(f"case: range_stats({lo}, {hi})")
+    hb, he, near, n = ctx.range_stats(lo, hi, bins=2000, near=10 ** 6)
+    res, _ = ctx.search_range(lo, hi)
+    rows = [(int(r["p"]), int(r["b"]), int(r["e"])) for r in res]
+    wb, we, wnear = oracle.residue_stats(rows, bins=2000, bound=10 ** 6)
+    assert n == len(rows)
+    assert list(hb) == wb and list(he) == we
+    assert [(int(x["p"]), int(x["r"]), int(x["which"])) for x in near] == wnear
+    pick = sorted(random.Random(4).sample(range(len(res)), 3))
+    check_against_oracle(res[pick], method="table")
+
+
+def test_range_stats_edges(ctx):
+    """Empty range, one bin, the largest bin count, truncated near list, bad
+    arguments."""
+    say("case: range_stats edges")
+    hb, he, near, n = ctx.range_stats(24, 29, bins=5, near=50)
+    assert n == 0 and not hb.any() and not he.any() and len(near) == 0
+    hb, he, near, n = ctx.range_stats(5, 3000, bins=1, near=0)
+    assert list(hb) == list(he) == [n] and n == len(oracle.primes(5, 3000)) and len(near) == 0
+    hb, he, _, n = ctx.range_stats(5, 3000, bins=wv.MAX_BINS, near=0)
+    ps = oracle.primes(5, 3000)
+    wb, we, _ = oracle.residue_stats([(p, b, e) for p, (b, e) in zip(ps, oracle.residues(ps))],
+                                     bins=wv.MAX_BINS, bound=0)
+    assert list(hb) == wb and list(he) == we
+    # truncation: the binding retries with the reported size; the C call itself says ETRUNC
+    import ctypes
+    b0 = np.zeros(4, dtype=np.uint64)
+    b1 = np.zeros(4, dtype=np.uint64)
+    buf = np.zeros(2, dtype=wv.NEAR_DTYPE)
+    nn, npr = ctypes.c_size_t(), ctypes.c_uint64()
+    st = wv.lib().wv_range_stats(ctx._h, 5, 3000, 4, 3000, b0.ctypes.data_as(wv.P_U64), b1.ctypes.data_as(wv.P_U64),
+                                 buf.ctypes.data_as(wv.VP), 2, ctypes.byref(nn), ctypes.byref(npr))
+    assert st == wv.WV_ETRUNC and nn.value == 2 * npr.value == 2 * len(ps) and int(b0.sum()) == len(ps)
+    _, _, near, _ = ctx.range_stats(5, 3000, bins=4, near=3000, near_cap=2)
+    assert len(near) == 2 * len(ps)
+    assert list(near[:2]) == list(buf)
+    for bins in (0, wv.MAX_BINS + 1):
+        with pytest.raises(wv.WvError):
+            ctx.range_stats(5, 100, bins=bins)
+    with pytest.raises(wv.WvError):
+        ctx.range_stats(2 ** 40 - 10, 2 ** 40 + 10)

@@ -361,3 +361,49 @@ def test_residues_dispatch_small_and_large_agree():
     assert oracle.residues(big, "root") == oracle.residues(big, "table")
     assert via_table == small
     assert oracle.residues([5, 7]) == [(1, 1), (3, 5)]
+
+
+# ---------------------------------------------------------------------------
+# residue statistics (histograms of Sections 3 and 5, Tables 2 and 3)
+# ---------------------------------------------------------------------------
+
+def test_residue_stats_bins_equal_p_is_a_bijection():
+    """With bins = p, floor((s/p + 1/2) p) = s + (p-1)/2: every residue has its
+    own bin, in order, so an offset, sign or scaling slip moves some bin."""
+    for p in (11, 13, 101, 997):
+        rows = [(p, r, (p - r) % p) for r in range(p)]
+        hb, he, _ = oracle.residue_stats(rows, bins=p, bound=0)
+        assert hb == [1] * p and he == [1] * p
+        for r in range(p):
+            s = exact.symmetric(r, p)
+            one, _, _ = oracle.residue_stats([(p, r, 0)], bins=p, bound=0)
+            assert one.index(1) == s + (p - 1) // 2
+
+
+def test_residue_stats_small_bin_counts():
+    """bins = 1 puts everything in bin 0; bins = 2 splits at <r> < 0; the
+    extremes +-(p-1)/2 land in the first and last bins."""
+    p = 1000003
+    rows = [(p, 0, 1), (p, p - 1, (p - 1) // 2), (p, (p + 1) // 2, 5)]
+    hb, he, near = oracle.residue_stats(rows, bins=1, bound=0)
+    assert hb == [3] and he == [3] and near == []
+    hb, he, _ = oracle.residue_stats(rows, bins=2, bound=0)
+    assert hb == [2, 1] and he == [0, 3]
+    hb, he, _ = oracle.residue_stats(rows, bins=2000, bound=0)
+    assert hb[0] == 1 and he[1999] == 1 and hb[1000] == 1
+
+
+def test_residue_stats_near_misses_from_table_2_and_3():
+    """The printed near misses come back with their printed signed values."""
+    rows_b = [(int(p), int(r)) for p, r in read_golden("near_miss_B.txt")]
+    rows_e = [(int(p), int(r)) for p, r in read_golden("near_miss_E.txt")]
+    for rows, which in ((rows_b, 1), (rows_e, 2)):
+        data = []
+        for p, r in rows[:4]:
+            far = (p - 1) // 2                      # the other residue: far from 0
+            data.append((p, r % p, far) if which == 1 else (p, far, r % p))
+        _, _, near = oracle.residue_stats(data, bins=2000, bound=50)
+        assert near == sorted((p, r, which) for p, r in rows[:4])
+        cut = sorted(abs(r) for _, r in rows[:4])[2]
+        _, _, near = oracle.residue_stats(data, bins=2000, bound=cut)
+        assert near == sorted((p, r, which) for p, r in rows[:4] if abs(r) < cut)
