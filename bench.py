@@ -35,6 +35,11 @@ OPS_ADDM = 3        # one modular addition: add, subtract, select
 OPS_REDUCE = 9      # one table reduction: u64->f64 (3), quotient fma, clamp, f64->u32, q(2^64-p) (2), add
 RENORM = 20         # blocks between table reductions
 
+# HBM bytes (read + written) of one term-sum launch on the first timed window,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
+# (profiles/k_sum_window_1e11_14_20.md); only valid for that kernel and workload.
+MEASURED_TRAFFIC = {("1e11", 14, 20, 8192): 5006297 + 36025887}
+
 
 def ops_per_term(d, k):
     """Full-rate VALU operations per term of a sum of s^-d with blocks of k terms."""
@@ -97,6 +102,7 @@ def main():
                     help="serve: also replay the trace at this fraction of the measured capacity")
     ap.add_argument("--window", type=int, default=0, help="integers per step (0: config default)")
     ap.add_argument("--chunk", type=int, default=0, help="terms per lane chunk (0: automatic)")
+    ap.add_argument("--block", default="", help="term-sum block shape KB,KE (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primes", type=int, default=1, help="primes in the oracle sample")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -135,6 +141,8 @@ def main():
     ctx = wv.Context(0)
     if args.chunk:
         ctx.set_chunk_terms(args.chunk)
+    if args.block:
+        ctx.set_block(*[int(v) for v in args.block.split(",")])
     for k in range(args.warmup):
         ctx.search_range(*wins[k])
         print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
@@ -193,7 +201,7 @@ def main():
             "peak": peak,
             "unit": "Tops/s (full-rate VALU lane ops)",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": MEASURED_TRAFFIC.get((args.config, block[0], block[1], W)) if block else None,
         },
     }
     if not args.no_cpu_baseline and first_timed:

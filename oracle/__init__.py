@@ -267,7 +267,8 @@ def residue_stats(rows, bins=2000, bound=50):
     (-1/2, 1/2]; a value falls in bin k when -1/2 + k/bins <= <r>_p/p <
     -1/2 + (k+1)/bins, i.e. k = floor((<r>_p/p + 1/2) bins), computed here with
     exact rationals.  Near misses (Tables 2 and 3): |<r>_p| < bound, as
-    (p, <r>_p, which) with which 1 for B_{p-3}, 2 for E_{p-3}, sorted.
+    (p, <r>_p, which) with which 1 for B_{p-3}, 2 for E_{p-3}, ordered by p,
+    then which.
     """
     hist = [[0] * bins, [0] * bins]
     near = []
@@ -278,4 +279,4 @@ def residue_stats(rows, bins=2000, bound=50):
             hist[w][k] += 1
             if abs(s) < bound:
                 near.append((p, s, w + 1))
-    return hist[0], hist[1], sorted(near)
+    return hist[0], hist[1], sorted(near, key=lambda t: (t[0], t[2]))

@@ -34,7 +34,7 @@ TABLE_NAMES = ["BB1", "BB2", "BB6", "BB9", "BB16", "BB22", "BB30",
                "EE3", "EE5", "EE9", "EE16", "EE24", "EE33", "V12", "E1"]
 TABLE_ID = {n: i for i, n in enumerate(TABLE_NAMES)}
 # compiled block shapes of the term-sum kernel, in the library's order
-BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (8, 16), (12, 12), (12, 16), (16, 16)]
+BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (8, 16), (12, 12), (12, 16), (12, 20), (14, 20), (16, 16)]
 
 # wv_result as a numpy record (32 bytes)
 RESULT_DTYPE = np.dtype([("p", "<u8"), ("b", "<u8"), ("e", "<u8"), ("flags", "<u4"), ("reserved", "<u4")])

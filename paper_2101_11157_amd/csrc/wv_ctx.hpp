@@ -46,7 +46,7 @@ constexpr uint64_t kMaxChunks = 1ull << 24;      // partial pairs held at once (
 constexpr size_t kMaxBatchSegs = 64;             // sieve segments per search batch (4 MiB of bitmaps)
 constexpr uint64_t kMaxBatchPrimes = 1ull << 19; // primes per search batch
 constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
-constexpr int kDefaultVariant = 3;               // block shape 8/16
+constexpr int kDefaultVariant = 7;               // block shape 14/20
 
 struct BatchShape {
     uint32_t n;          // primes

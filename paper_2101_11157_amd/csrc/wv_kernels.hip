@@ -477,7 +477,8 @@ struct SumVariant {
 // Compiled block shapes (terms per block, Bernoulli side / Euler side).
 static const SumVariant kSumVariants[] = {
     {1, 1, k_sum<1, 1>},     {4, 4, k_sum<4, 4>},     {8, 8, k_sum<8, 8>},    {8, 16, k_sum<8, 16>},
-    {12, 12, k_sum<12, 12>}, {12, 16, k_sum<12, 16>}, {16, 16, k_sum<16, 16>},
+    {12, 12, k_sum<12, 12>}, {12, 16, k_sum<12, 16>}, {12, 20, k_sum<12, 20>}, {14, 20, k_sum<14, 20>},
+    {16, 16, k_sum<16, 16>},
 };
 constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants[0]));
 

@@ -645,7 +645,7 @@ def test_range_stats_reproduces_tables_2_and_3(ctx):
     window around a printed prime has exactly the printed near misses."""
     tb = _table_rows("near_miss_B.txt")
     te = _table_rows("near_miss_E.txt")
-    printed = sorted([(p, r, 1) for p, r in tb] + [(p, r, 2) for p, r in te])
+    printed = sorted([(p, r, 1) for p, r in tb] + [(p, r, 2) for p, r in te], key=lambda t: (t[0], t[2]))
     centres = [p for p, _ in tb[:4]] + [p for p, _ in te[:5]]
     for c in centres:
         lo, hi = c - 4000, c + 4000

@@ -403,7 +403,7 @@ def test_residue_stats_near_misses_from_table_2_and_3():
             far = (p - 1) // 2                      # the other residue: far from 0
             data.append((p, r % p, far) if which == 1 else (p, far, r % p))
         _, _, near = oracle.residue_stats(data, bins=2000, bound=50)
-        assert near == sorted((p, r, which) for p, r in rows[:4])
+        assert near == sorted(((p, r, which) for p, r in rows[:4]), key=lambda t: (t[0], t[2]))
         cut = sorted(abs(r) for _, r in rows[:4])[2]
         _, _, near = oracle.residue_stats(data, bins=2000, bound=cut)
-        assert near == sorted((p, r, which) for p, r in rows[:4] if abs(r) < cut)
+        assert near == sorted(((p, r, which) for p, r in rows[:4] if abs(r) < cut), key=lambda t: (t[0], t[2]))
