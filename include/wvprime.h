@@ -117,7 +117,10 @@ int wv_destroy(wv_ctx *ctx);
  * identical residues; only the work changes.  Errors: WV_EINVAL. */
 int wv_set_tables(wv_ctx *ctx, int b_table, int e_table);
 
-/* Set the number of terms each lane sums per chunk (0 = automatic).  Must be a
+/* Set the number of terms each lane sums per chunk (0 = automatic: about
+ * sqrt(2 * 4096 * T / (lanes + sums)) for a batch of T terms, between 2^12
+ * and 2^22, which balances the set-up of each chunk against lanes idling
+ * behind the short last chunk of each sum and of each lane).  Must be a
  * multiple of 64 when nonzero.  Results do not depend on it. */
 int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
 
@@ -138,8 +141,8 @@ int wv_set_block(wv_ctx *ctx, int kb, int ke);
 typedef void (*wv_progress_fn)(void *user, uint64_t done, uint64_t total);
 int wv_set_progress(wv_ctx *ctx, wv_progress_fn fn, void *user, uint64_t terms_per_launch);
 
-/* Autotuner: times every compiled block shape with chunk sizes 2^14, 2^16 and
- * 2^18 terms on sample primes just above p_hint (n_sample of them, 0: 16) and
+/* Autotuner: times every compiled block shape with chunk sizes 2^16, 2^18 and
+ * automatic (reported as 0) on sample primes just above p_hint (n_sample of them, 0: 16) and
  * keeps the fastest for primes in [2^k, 2^(k+1)), k = floor(log2 p_hint).
  * Synchronous calls on primes in a tuned range then use the tuned shape and
  * chunk unless wv_set_block / wv_set_chunk_terms force others.  The measured

@@ -305,7 +305,7 @@ class Context:
                                  ctypes.byref(ch), rates), "wv_autotune")
         table = {}
         for v, (a, b) in enumerate(BLOCK_SHAPES):
-            for j, c in enumerate((1 << 14, 1 << 16, 1 << 18)):
+            for j, c in enumerate((1 << 16, 1 << 18, 0)):   # 0: automatic per batch
                 table[(a, b, c)] = rates[3 * v + j]
         return kb.value, ke.value, ch.value, table
 

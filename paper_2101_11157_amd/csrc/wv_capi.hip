@@ -97,14 +97,25 @@ int check_device(wv_ctx *c) {
 // one batch of primes on the device: plan -> sums -> reduce -> finalize
 // ==========================================================================
 
-int batch_shape(const wv_ctx *c, uint32_t n, BatchShape *sh) {
+int batch_shape(const wv_ctx *c, uint32_t n, uint64_t pmax, BatchShape *sh) {
     sh->n = n;
     sh->nB = std::max(table_slots(c->tb), 1);
     sh->nE = std::max(table_slots(c->te), 1);
     sh->nseg = (uint64_t)n * (sh->nB + sh->nE);
-    // partial pairs: at most total_terms / chunk + nseg chunks, and the chunk
-    // size keeps total_terms / chunk <= cap - nseg, so cap >= 2 nseg leaves room
-    sh->cap = std::max<uint64_t>(kMaxChunks, 2 * sh->nseg);
+    // partial pairs: the plan picks chunk >= total_terms / (cap - nseg), so
+    // cap > nseg always; with room for total_terms / chunk_cfg + nseg chunks
+    // the configured chunk size is kept.  total_terms <= n (pmax cost + sums).
+    const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    const double cost = (double)kTables[c->tb].cost_num / kTables[c->tb].cost_den +
+                        (double)kTables[c->te].cost_num / kTables[c->te].cost_den;
+    const double t_max = (double)n * ((double)pmax * cost + sh->nB + sh->nE);
+    // the adaptive chunk grows with T, so T / chunk is largest at the bound
+    const double chunk = chunk_cfg ? (double)chunk_cfg
+                                   : (double)adaptive_chunk((uint64_t)std::min(t_max, 1.8e19),
+                                                            sum_lanes(c) + sh->nseg);
+    const double want = t_max / chunk + 2.0 * sh->nseg;
+    sh->cap = (uint64_t)std::min<double>(std::max<double>(want, (double)kMinChunks), (double)kMaxChunks);
+    sh->cap = std::max<uint64_t>(sh->cap, 2 * sh->nseg);
     return WV_OK;
 }
 
@@ -132,7 +143,7 @@ int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipS
     WV_HIP(launch_plan(st, d_primes, sh.n, c->tb, c->te, sh.nB, sh.nE, as<PrimeRec>(c->pr), as<SegRec>(c->segs),
                        as<uint64_t>(c->terms), 0));
     WV_HIP(launch_scan(st, as<uint64_t>(c->terms), sh.nseg, toff, as<uint64_t>(c->tiles)));
-    WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sh.cap, scal + 1));
+    WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sum_lanes(c), sh.cap, scal + 1));
     WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + 0, 1));
     WV_HIP(launch_copy_u64(st, toff + (uint64_t)sh.n * sh.nB, scal + 3, 1));
     WV_HIP(launch_chunk_count(st, as<uint64_t>(c->terms), sh.nseg, scal + 1, as<uint64_t>(c->cnt)));
@@ -163,10 +174,10 @@ int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d
 // chunk ranges of about `launch_terms` terms each, with the callback between
 // them; the partial pairs of all ranges are reduced together afterwards, so
 // the result does not depend on the split.
-int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, wv_result *d_out) {
+int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pmax, wv_result *d_out) {
     hipStream_t st = c->stream;
     BatchShape sh;
-    WV_TRY(batch_shape(c, n, &sh));
+    WV_TRY(batch_shape(c, n, pmax, &sh));
     WV_TRY(prepare(c, sh));
     WV_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
     WV_TRY(enqueue_plan(c, d_primes, sh, st));
@@ -269,7 +280,8 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
 // about kMaxBatchPrimes primes; each batch is one plan and one persistent
 // term-sum launch (or one split launch sequence under a progress callback).
 int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts, wv_result *out,
-                 StatsSink *sink) {
+                 StatsSink *sink, const uint64_t *dest) {
+    std::vector<wv_result> staging;
     hipStream_t st = c->stream;
     size_t i = 0, written = 0;
     while (i < descs.size()) {
@@ -292,9 +304,21 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
         WV_HIP(hipEventSynchronize(c->ev[EV_SIEVE]));
         c->stats.ms_sieve += elapsed(c->ev[EV_START], c->ev[EV_SIEVE]);
         WV_TRY(ensure(c, c->results, got * sizeof(wv_result)));
-        WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)got, as<wv_result>(c->results)));
-        if (out)
+        uint64_t pmax = 0;
+        for (size_t k = i; k < j; k++) pmax = std::max(pmax, std::min(descs[k].hi, descs[k].L + kSegSpan));
+        WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)got, pmax, as<wv_result>(c->results)));
+        if (out && !dest)
             WV_HIP(hipMemcpyAsync(out + written, c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
+        if (out && dest) {
+            staging.resize(got);
+            WV_HIP(hipMemcpyAsync(staging.data(), c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
+            WV_HIP(hipStreamSynchronize(st));
+            uint64_t o = 0;
+            for (size_t k = i; k < j; k++) {
+                std::memcpy(out + dest[k], staging.data() + o, counts[k] * sizeof(wv_result));
+                o += counts[k];
+            }
+        }
         if (sink) {
             // near-miss slots: a counter, then room for two entries per prime
             WV_TRY(ensure(c, c->stats_near, 64 + 2 * got * sizeof(wv_near)));
@@ -528,7 +552,27 @@ int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t 
     c->stats = wv_stats{};
     if (total == 0) return WV_OK;
     pick_tuned(c, pmax);
-    return search_descs(c, d, counts, out);
+    // Batch the segments in ascending position, so that a batch holds primes of
+    // one size (chunk sizes then fit every sum of the batch), and place each
+    // segment's primes at its window's offset.
+    std::vector<uint64_t> dest(d.size());
+    uint64_t o = 0;
+    for (size_t k = 0; k < d.size(); k++) {
+        dest[k] = o;
+        o += counts[k];
+    }
+    std::vector<size_t> ord(d.size());
+    for (size_t k = 0; k < ord.size(); k++) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return d[a].L < d[b].L; });
+    std::vector<SegDesc> ds(d.size());
+    std::vector<uint32_t> cs(d.size());
+    std::vector<uint64_t> dst(d.size());
+    for (size_t k = 0; k < ord.size(); k++) {
+        ds[k] = d[ord[k]];
+        cs[k] = counts[ord[k]];
+        dst[k] = dest[ord[k]];
+    }
+    return search_descs(c, ds, cs, out, nullptr, dst.data());
 }
 
 int wv_range_stats(wv_ctx *c, uint64_t lo, uint64_t hi, uint32_t bins, uint64_t near_bound, uint64_t *hist_b,
@@ -598,7 +642,7 @@ int wv_eval_primes(wv_ctx *c, const uint64_t *primes, size_t n, wv_result *out) 
     WV_TRY(ensure(c, c->primes, n * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->results, n * sizeof(wv_result)));
     WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
-    WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)n, as<wv_result>(c->results)));
+    WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)n, pmax + 1, as<wv_result>(c->results)));
     WV_HIP(hipMemcpyAsync(out, c->results.ptr, n * sizeof(wv_result), hipMemcpyDeviceToHost, c->stream));
     WV_HIP(hipStreamSynchronize(c->stream));
     return WV_OK;
@@ -608,18 +652,20 @@ int wv_eval_sums(wv_ctx *c, const uint64_t *primes, size_t n, uint64_t *out_b, u
     if (!c) return WV_EINVAL;
     if (n == 0) return WV_OK;
     if (!primes || !out_b || !out_e || n > 0xFFFFFFFFull) return WV_EINVAL;
+    uint64_t pmax = 0;
     for (size_t i = 0; i < n; i++) {
         if (primes[i] < 5 || primes[i] >= WV_P_MAX) return WV_EDOMAIN;
         if (!is_prime_u64(primes[i])) return WV_ENOTPRIME;
+        pmax = std::max(pmax, primes[i]);
     }
     WV_TRY(check_device(c));
     c->stats = wv_stats{};
     BatchShape sh;
-    WV_TRY(batch_shape(c, (uint32_t)n, &sh));
+    WV_TRY(batch_shape(c, (uint32_t)n, pmax + 1, &sh));
     WV_TRY(ensure(c, c->primes, n * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->results, std::max(n * sizeof(wv_result), (size_t)sh.nseg * sizeof(uint64_t))));
     WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
-    WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)n, as<wv_result>(c->results)));
+    WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)n, pmax + 1, as<wv_result>(c->results)));
     // the results buffer is free again once finalize has run: reuse it for the sums
     uint64_t *d_sums = as<uint64_t>(c->results);
     WV_HIP(launch_sum_values(c->stream, as<SegRec>(c->segs), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), sh.nseg,
@@ -643,7 +689,7 @@ int wv_eval_primes_async(wv_ctx *c, const uint64_t *d_primes, size_t n, wv_resul
     uint64_t n_pad = 64;
     while (n_pad < n) n_pad <<= 1;
     BatchShape sh;
-    WV_TRY(batch_shape(c, (uint32_t)n_pad, &sh));
+    WV_TRY(batch_shape(c, (uint32_t)n_pad, WV_P_MAX, &sh));   // the primes are not seen on the host
     WV_TRY(prepare(c, sh));
     WV_TRY(ensure(c, c->pad_primes, n_pad * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->results, n_pad * sizeof(wv_result)));

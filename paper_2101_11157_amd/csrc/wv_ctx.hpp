@@ -41,8 +41,9 @@ T *as(DevBuf &b) { return reinterpret_cast<T *>(b.ptr); }
 
 enum { EV_START, EV_SIEVE, EV_PLAN0, EV_PLAN, EV_SUM0, EV_SUM, EV_RED, EV_FINAL, EV_COUNT };
 
-constexpr uint64_t kDefaultChunk = 1ull << 16;
-constexpr uint64_t kMaxChunks = 1ull << 24;      // partial pairs held at once (256 MiB)
+constexpr uint64_t kDefaultChunk = 0;            // 0: adaptive_chunk per batch
+constexpr uint64_t kMaxChunks = 1ull << 26;      // partial pairs held at once (1 GiB)
+constexpr uint64_t kMinChunks = 1ull << 16;
 constexpr size_t kMaxBatchSegs = 64;             // sieve segments per search batch (4 MiB of bitmaps)
 constexpr uint64_t kMaxBatchPrimes = 1ull << 19; // primes per search batch
 constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
@@ -86,7 +87,7 @@ struct wv_ctx {
     hipEvent_t ev[wv::EV_COUNT] = {};
     int tb = WV_TABLE_BB30, te = WV_TABLE_EE33;
     uint64_t chunk_cfg = 0;                       // user setting (0: automatic)
-    uint64_t chunk_auto = wv::kDefaultChunk;      // automatic value (tuned)
+    uint64_t chunk_auto = wv::kDefaultChunk;      // automatic value (tuned; 0: adaptive)
     int variant = wv::kDefaultVariant;            // term-sum block shape
     bool shape_forced = false;
     int num_cus = 0;
@@ -105,21 +106,27 @@ struct wv_ctx {
 
 namespace wv {
 
+// lanes of the persistent term-sum grid of the current block shape
+inline uint64_t sum_lanes(const wv_ctx *c) { return (uint64_t)c->sum_blocks[c->variant] * 256; }
+
 int ensure(wv_ctx *c, DevBuf &b, size_t bytes);
 bool is_prime_u64(uint64_t n);
 int check_device(wv_ctx *c);
-int batch_shape(const wv_ctx *c, uint32_t n, BatchShape *sh);
+// pmax: an upper bound on the batch's primes (sizes the partial-pair buffer)
+int batch_shape(const wv_ctx *c, uint32_t n, uint64_t pmax, BatchShape *sh);
 int prepare(wv_ctx *c, const BatchShape &sh);
 int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st);
 int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end);
 int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out);
-int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, wv_result *d_out);
+int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pmax, wv_result *d_out);
 void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d);
 int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts);
 int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out);
-// out: host results (may be NULL when sink is set); sink: device statistics
+// out: host results (may be NULL when sink is set), written contiguously in
+// desc order, or, with dest, the primes of descs[k] at out + dest[k];
+// sink: device statistics
 int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts,
-                 wv_result *out, StatsSink *sink = nullptr);
+                 wv_result *out, StatsSink *sink = nullptr, const uint64_t *dest = nullptr);
 void pick_tuned(wv_ctx *c, uint64_t pmax);
 
 }  // namespace wv

@@ -20,6 +20,18 @@ constexpr int kScanTile = 1024;                // elements per scan workgroup
 // One sieve segment: the 2^20 integers [L, L + 2^20) (L even), of which the
 // window [lo, hi) keeps the primes p >= 5.  Segments of several windows can
 // share one launch (batched search).
+constexpr uint64_t kChunkSetup = 4096;         // set-up work of one chunk, in terms
+constexpr uint64_t kChunkMin = 1ull << 12;
+constexpr uint64_t kChunkMax = 1ull << 22;
+
+// Automatic chunk size for T terms: sqrt(2 S T / w), clamped, where w counts
+// the lanes of the grid plus the sums (see k_pick_chunk).
+__host__ __device__ inline uint64_t adaptive_chunk(uint64_t T, uint64_t w) {
+    const double c = sqrt(2.0 * (double)kChunkSetup * (double)T / (double)(w ? w : 1));
+    const uint64_t k = (uint64_t)c;
+    return k < kChunkMin ? kChunkMin : (k > kChunkMax ? kChunkMax : k);
+}
+
 struct SegDesc {
     uint64_t L, lo, hi;
 };
@@ -58,7 +70,7 @@ hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, 
 hipError_t launch_scan(hipStream_t st, const uint64_t *in, uint64_t n, uint64_t *out, uint64_t *tiles);
 hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int tb, int te, int nB, int nE,
                        PrimeRec *pr, SegRec *segs, uint64_t *terms, uint32_t prime_base);
-hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg,
+hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg, uint64_t lanes,
                              uint64_t cap, uint64_t *chunk_out);
 hipError_t launch_chunk_count(hipStream_t st, const uint64_t *terms, uint64_t nseg, const uint64_t *chunk,
                               uint64_t *cnt);

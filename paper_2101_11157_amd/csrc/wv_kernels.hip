@@ -384,13 +384,22 @@ __global__ void __launch_bounds__(256) k_copy_results(const wv_result *__restric
 
 // Chunk size: at least `chunk_cfg` terms, and large enough that the total
 // number of chunks stays within `max_chunks` (the partial-pair buffer).
+// Terms per lane chunk.  chunk_cfg > 0 is used as given; 0 picks
+// sqrt(2 S T / (lanes + nseg)) (S = kChunkSetup), which minimises the
+// per-chunk set-up of the blocked loop (about S terms of work per chunk) plus
+// the idle lanes behind short chunks (on average half a chunk per sum, at the
+// sum's ragged end, and per lane in the last round), clamped to
+// [kChunkMin, kChunkMax].  Either way at least T / (max_chunks - nseg), so
+// the partial pairs fit, rounded up to a multiple of 64.
 __global__ void k_pick_chunk(const uint64_t *__restrict__ total_terms, uint64_t nseg, uint64_t chunk_cfg,
-                             uint64_t max_chunks, uint64_t *__restrict__ chunk_out) {
+                             uint64_t max_chunks, uint64_t lanes, uint64_t *__restrict__ chunk_out) {
     const uint64_t T = *total_terms;
+    uint64_t want = chunk_cfg ? chunk_cfg : adaptive_chunk(T, lanes + nseg);
     uint64_t room = max_chunks > nseg ? max_chunks - nseg : 1;
     uint64_t c = (T + room - 1) / room;
+    c = max(c, want);
     c = (c + 63) & ~63ull;
-    *chunk_out = max(chunk_cfg, max(c, (uint64_t)64));
+    *chunk_out = max(c, (uint64_t)64);
 }
 
 __global__ void __launch_bounds__(256) k_chunk_count(const uint64_t *__restrict__ terms, uint64_t nseg,
@@ -657,9 +666,9 @@ hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int t
     return hipGetLastError();
 }
 
-hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg,
+hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg, uint64_t lanes,
                              uint64_t cap, uint64_t *chunk_out) {
-    hipLaunchKernelGGL(k_pick_chunk, dim3(1), dim3(1), 0, st, total_terms, nseg, chunk_cfg, cap, chunk_out);
+    hipLaunchKernelGGL(k_pick_chunk, dim3(1), dim3(1), 0, st, total_terms, nseg, chunk_cfg, cap, lanes, chunk_out);
     return hipGetLastError();
 }
 

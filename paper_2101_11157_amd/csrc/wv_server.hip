@@ -212,7 +212,9 @@ struct Task {
 
 int run_step(wv_server *s) {
     wv_ctx *c = s->c;
-    const uint64_t C = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    const uint64_t C = c->chunk_cfg   ? c->chunk_cfg
+                       : c->chunk_auto ? c->chunk_auto
+                                       : (adaptive_chunk(s->step_terms, sum_lanes(c)) + 63) & ~63ull;
     // fair share of the step budget, leftovers to whoever still has work
     std::vector<uint64_t> allow(s->active.size(), 0);
     uint64_t budget = s->step_terms;

@@ -39,6 +39,7 @@ int wv_autotune(wv_ctx *c, uint64_t p_hint, int n_sample, int *kb, int *ke, uint
         width <<= 1;
     }
     if (np == 0 || d.size() > kMaxBatchSegs) return WV_EINVAL;
+    const uint64_t sample_hi = std::min<uint64_t>(WV_P_MAX, p_hint + width);
     uint64_t got = 0;
     WV_TRY(compact(c, d.data(), d.size(), counts.data(), &got));
     const uint32_t n = (uint32_t)std::min<uint64_t>(got, (uint64_t)n_sample);
@@ -51,21 +52,23 @@ int wv_autotune(wv_ctx *c, uint64_t p_hint, int n_sample, int *kb, int *ke, uint
     const int saved_variant = c->variant;
     const bool saved_forced = c->shape_forced;
     const uint64_t saved_chunk = c->chunk_cfg;
-    const uint64_t chunks[3] = {1ull << 14, 1ull << 16, 1ull << 18};
+    const uint64_t chunks[3] = {1ull << 16, 1ull << 18, 0};   // 0: adaptive per batch
     int best_v = kDefaultVariant;
     uint64_t best_c = kDefaultChunk;
     double best = -1.0;
     int rc = WV_OK;
+    const uint64_t saved_auto = c->chunk_auto;
+    c->chunk_auto = 0;
     c->variant = kDefaultVariant;
     c->chunk_cfg = kDefaultChunk;
     c->stats = wv_stats{};
-    rc = run_batch_sync(c, as<uint64_t>(sample), n, as<wv_result>(c->results));   // warm-up
+    rc = run_batch_sync(c, as<uint64_t>(sample), n, sample_hi, as<wv_result>(c->results));   // warm-up
     for (int v = 0; v < num_sum_variants() && rc == WV_OK; v++) {
         for (int j = 0; j < 3 && rc == WV_OK; j++) {
             c->variant = v;
             c->chunk_cfg = chunks[j];
             c->stats = wv_stats{};
-            rc = run_batch_sync(c, as<uint64_t>(sample), n, as<wv_result>(c->results));
+            rc = run_batch_sync(c, as<uint64_t>(sample), n, sample_hi, as<wv_result>(c->results));
             if (rc != WV_OK) break;
             const double r = c->stats.ms_sum > 0 ? (double)c->stats.n_terms / (c->stats.ms_sum * 1e-3) : 0.0;
             if (rates) rates[v * 3 + j] = r;
@@ -79,6 +82,7 @@ int wv_autotune(wv_ctx *c, uint64_t p_hint, int n_sample, int *kb, int *ke, uint
     c->variant = saved_forced ? saved_variant : best_v;
     c->shape_forced = saved_forced;
     c->chunk_cfg = saved_chunk;
+    c->chunk_auto = saved_auto;
     (void)hipFree(sample.ptr);
     if (rc != WV_OK) return rc;
     const int lg = 63 - __builtin_clzll(p_hint);
@@ -118,7 +122,7 @@ int wv_tune_load(wv_ctx *c, const char *path) {
     unsigned long long chunk;
     double rate;
     while (fscanf(f, "%63s %d %d %d %llu %lf", arch, &lg, &kb, &ke, &chunk, &rate) == 6) {
-        if (strcmp(arch, c->arch) != 0 || lg < 0 || lg > 40 || chunk % 64 != 0 || chunk == 0) continue;
+        if (strcmp(arch, c->arch) != 0 || lg < 0 || lg > 40 || chunk % 64 != 0) continue;   // 0: adaptive
         int v = -1;
         for (int k = 0; k < num_sum_variants(); k++)
             if (sum_variant_kb(k) == kb && sum_variant_ke(k) == ke) v = k;
