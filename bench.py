@@ -226,11 +226,13 @@ def bench_batch(args, wv):
         ctx.set_chunk_terms(args.chunk)
     last = [0.0]
 
+    t_start = time.perf_counter()
+
     def progress(done, total):
         t = time.perf_counter()
         if t - last[0] > 10 or done == total:
             last[0] = t
-            print(f"batch progress {done}/{total} chunks", file=sys.stderr, flush=True)
+            print(f"batch progress {done}/{total} chunks at {t - t_start:.1f} s", file=sys.stderr, flush=True)
 
     ctx.set_progress(progress)
     t0 = time.perf_counter()

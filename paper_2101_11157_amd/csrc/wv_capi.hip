@@ -285,10 +285,21 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
     hipStream_t st = c->stream;
     size_t i = 0, written = 0;
     while (i < descs.size()) {
+        // a batch ends at kMaxBatchSegs segments, kMaxBatchPrimes primes or
+        // about kMaxBatchTerms terms (bounded by count * largest p * cost):
+        // with the partial pairs capped, a bigger batch would force chunks
+        // longer than its sums
+        const double cost = (double)kTables[c->tb].cost_num / kTables[c->tb].cost_den +
+                            (double)kTables[c->te].cost_num / kTables[c->te].cost_den;
         size_t j = i;
         uint64_t np = 0;
-        while (j < descs.size() && j - i < kMaxBatchSegs && (np == 0 || np + counts[j] <= kMaxBatchPrimes))
+        double est = 0.0;
+        while (j < descs.size() && j - i < kMaxBatchSegs) {
+            const double e = (double)counts[j] * (double)std::min(descs[j].hi, descs[j].L + kSegSpan) * cost;
+            if (np > 0 && (np + counts[j] > kMaxBatchPrimes || est + e > kMaxBatchTerms)) break;
             np += counts[j++];
+            est += e;
+        }
         if (np == 0) {
             i = j;
             continue;

@@ -42,10 +42,11 @@ T *as(DevBuf &b) { return reinterpret_cast<T *>(b.ptr); }
 enum { EV_START, EV_SIEVE, EV_PLAN0, EV_PLAN, EV_SUM0, EV_SUM, EV_RED, EV_FINAL, EV_COUNT };
 
 constexpr uint64_t kDefaultChunk = 0;            // 0: adaptive_chunk per batch
-constexpr uint64_t kMaxChunks = 1ull << 26;      // partial pairs held at once (1 GiB)
+constexpr uint64_t kMaxChunks = 1ull << 27;      // partial pairs held at once (2 GiB)
 constexpr uint64_t kMinChunks = 1ull << 16;
 constexpr size_t kMaxBatchSegs = 64;             // sieve segments per search batch (4 MiB of bitmaps)
 constexpr uint64_t kMaxBatchPrimes = 1ull << 19; // primes per search batch
+constexpr double kMaxBatchTerms = 70368744177664.0;   // 2^46 terms per search batch (~20 s)
 constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
 constexpr int kDefaultVariant = 7;               // block shape 14/20
 
