@@ -152,6 +152,25 @@ def congruence_residue(p, cong, method="poly", nthreads=1):
     return None if r == 2 ** 64 - 1 else r
 
 
+def congruence_residue_exact(p, cong, nthreads=1):
+    """lhs^-1 * sum_i c_i S(x_i, y_i) mod p (Section 2, eqnDefnS) for a
+    congruence whose integers and endpoints may have any size (derived
+    congruences): endpoints by exact integer floors of the open interval,
+    coefficients reduced mod p, each sum by eqnComputeS (orc_sum_poly).
+    None when p divides the left side."""
+    L = cong.lhs % p
+    if L == 0:
+        return None
+    acc = 0
+    for c, x, y in cong.terms:
+        lo = x.numerator * p // x.denominator + 1
+        hi = (y.numerator * p - 1) // y.denominator
+        if hi < lo:
+            continue
+        acc = (acc + (c % p) * sum_poly(p, lo, hi, -cong.ell, cong.alt, nthreads=nthreads)) % p
+    return acc * pow(L, -1, p) % p
+
+
 def congruence_residues(primes, cong, method="poly", nthreads=None):
     """congruence_residue over a list of primes, one prime per thread."""
     if isinstance(cong, str):

@@ -1,0 +1,318 @@
+"""Derivation of congruences for B_{p-3} and E_{p-3} mod p.
+
+Host-side generator of the tables the term-sum kernels evaluate (the step
+before the hot path).  Implements, in exact rational arithmetic:
+
+* the three transformations of Proposition propTW (Section 2): separation,
+  reflection S_l(x, y) == (-1)^l S_l(1-y, 1-x), and subdivision
+  S_l(x, y) == d^l sum_{i<d} S_l((x+i)/d, (y+i)/d) for p not dividing d;
+* the exhaustive search of Section 2.1 (every sequence of at most L
+  subdivisions, the i-th with 2 <= d <= d_i) and the greedy search of
+  Section 2.2 (lambda subdivisions with d <= D per round, keep a cheapest
+  result, repeat);
+* the starting congruences of Sections 2 and 4, specialised to the index the
+  searches need: for B_{p-3}, k = (p-3)/2 and l = p - 4 == -3 (mod p - 1), so
+  d^l == d^-3 and C_k(a, b, c) == (c^3 - a^3 - b^3 + 1)/6 (Section 3); for
+  E_{p-3}, k = 1 and l = p - 3 == -2, so d^l == d^-2 and reflection keeps the
+  sign.
+
+A congruence is held as  lhs * X == sum_i c_i S(x_i, y_i)  with X = B_{p-3} or
+E_{p-3}, the right side as a piecewise-constant coefficient function on
+[0, 1/2] (every interval reflected below 1/2, which the reflection property
+allows; p/2 is never an integer, so splitting at 1/2 is a valid separation).
+Each maximal interval of constant nonzero coefficient is one sum; the cost is
+p times their total length (Section 2).
+
+The congruences derived here hold for every prime p >= 11 that divides no
+subdivision factor (factors are at most 8 here, so every p >= 11), as long as
+the starting congruence holds and p does not divide lhs.
+"""
+from bisect import bisect_left, bisect_right
+from fractions import Fraction as Q
+from math import gcd
+import itertools
+import json
+
+HALF = Q(1, 2)
+
+# (name, side, lhs, [(coef, x, y)]) at the index p-3, Sections 2-4
+#   Vandiver:  C_k(2,5,6) = (216 - 8 - 125 + 1)/6 = 14
+#   SV:        C_k(3,4,6) = (216 - 27 - 64 + 1)/6 = 21
+#   V12:       C_k(2,3,4) = (64 - 8 - 27 + 1)/6 = 5
+#   V10:       C_k(4,5,8) = (512 - 64 - 125 + 1)/6 = 54
+#   E1:        (-1)^k 4^(2k-1) with k = 1: -4
+#   EMac2:     (-1)^k 4^(k-1) (9^k + 1) with k = 1: -10, right side 2^t (...) = (1/4)(...)
+STARTS = {
+    "Vandiver": ("B", 14, [(1, Q(1, 6), Q(1, 5)), (1, Q(1, 3), Q(2, 5))]),
+    "SV": ("B", 21, [(1, Q(1, 6), Q(1, 4))]),
+    "V12": ("B", 5, [(1, Q(1, 4), Q(1, 3))]),
+    "V10": ("B", 54, [(1, Q(1, 8), Q(1, 5)), (1, Q(3, 8), Q(2, 5))]),
+    "E1": ("E", -4, [(1, Q(0), Q(1, 4))]),
+    "EMac2": ("E", -10, [(Q(1, 4), Q(0), Q(1, 12)), (Q(-1, 4), Q(5, 12), HALF)]),
+}
+
+SIDES = {"B": (3, -1), "E": (2, 1)}   # side -> (power k in d^-k, reflection sign)
+
+
+def tw1(b):
+    """eqnTW1 at the index p-3: C_k(2, b, b+1) = ((b+1)^3 - 8 - b^3 + 1)/6, right
+    side sum_{m=1}^{floor(b/2)} S(m/(b+1), m/b)."""
+    lhs = Q((b + 1) ** 3 - 8 - b ** 3 + 1, 6)
+    return ("B", lhs, [(1, Q(m, b + 1), Q(m, b)) for m in range(1, b // 2 + 1)])
+
+
+class Congruence:
+    """lhs * X == sum over pieces c * S(x, y), pieces disjoint in [0, 1/2]."""
+
+    def __init__(self, side, lhs, terms=()):
+        if side not in SIDES:
+            raise ValueError("side is 'B' or 'E'")
+        self.side = side
+        self.power, self.refl = SIDES[side]
+        self.lhs = Q(lhs)
+        self.bp = []   # breakpoints, ascending
+        self.cf = []   # cf[j]: coefficient on (bp[j], bp[j+1]); len(cf) == len(bp) - 1 (or both empty)
+        for c, x, y in terms:
+            self.add(Q(x), Q(y), Q(c))
+
+    @classmethod
+    def start(cls, name):
+        side, lhs, terms = tw1(int(name[3:])) if name.startswith("TW1") else STARTS[name]
+        return cls(side, lhs, terms)
+
+    def copy(self):
+        o = Congruence.__new__(Congruence)
+        o.side, o.power, o.refl, o.lhs = self.side, self.power, self.refl, self.lhs
+        o.bp, o.cf = list(self.bp), list(self.cf)
+        return o
+
+    # ---- the coefficient function ----------------------------------------
+    def _cut(self, t):
+        """Make t a breakpoint (inside or at the ends of the support)."""
+        if not self.bp:
+            self.bp = [t]
+            return
+        if t < self.bp[0]:
+            self.bp.insert(0, t)
+            self.cf.insert(0, Q(0))
+            return
+        if t > self.bp[-1]:
+            self.bp.append(t)
+            self.cf.append(Q(0))
+            return
+        j = bisect_left(self.bp, t)
+        if self.bp[j] != t:
+            self.bp.insert(j, t)
+            self.cf.insert(j, self.cf[j - 1])
+
+    def _raw_add(self, x, y, c):
+        if not (0 <= x < y <= HALF):
+            raise ValueError("interval outside [0, 1/2]")
+        self._cut(x)
+        self._cut(y)
+        i, j = bisect_left(self.bp, x), bisect_left(self.bp, y)
+        for k in range(i, j):
+            self.cf[k] += c
+        self._tidy(max(i - 1, 0), min(j + 1, len(self.bp)))
+
+    def _tidy(self, lo, hi):
+        """Drop breakpoints in bp[lo:hi] that separate equal coefficients, and
+        zero-coefficient ends."""
+        k = max(lo, 1)
+        while k < min(hi, len(self.bp) - 1):
+            if self.cf[k - 1] == self.cf[k]:
+                del self.bp[k]
+                del self.cf[k]
+                hi -= 1
+            else:
+                k += 1
+        while self.cf and self.cf[0] == 0:
+            del self.bp[0]
+            del self.cf[0]
+        while self.cf and self.cf[-1] == 0:
+            del self.bp[-1]
+            del self.cf[-1]
+        if not self.cf:
+            self.bp = []
+
+    def add(self, x, y, c):
+        """c * S(x, y) for any 0 <= x < y <= 1, reflected into [0, 1/2]."""
+        if c == 0 or x == y:
+            return
+        if y <= HALF:
+            self._raw_add(x, y, c)
+        elif x >= HALF:
+            self._raw_add(1 - y, 1 - x, self.refl * c)
+        else:
+            self._raw_add(x, HALF, c)
+            self._raw_add(1 - y, HALF, self.refl * c)
+
+    # ---- transformations ------------------------------------------------
+    def pieces(self):
+        """[(c, x, y)]: the sums, ascending."""
+        return [(c, self.bp[j], self.bp[j + 1]) for j, c in enumerate(self.cf) if c != 0]
+
+    def subdivide(self, x, y, d):
+        """Replace the sum on (x, y) (an existing piece) by d^-k times its d images."""
+        c = self._coef_of(x, y)
+        self.add(x, y, -c)
+        w = c / Q(d) ** self.power
+        for i in range(d):
+            self.add((x + i) / d, (y + i) / d, w)
+        return self
+
+    def _coef_of(self, x, y):
+        j = bisect_left(self.bp, x)
+        if j >= len(self.cf) or self.bp[j] != x or self.bp[j + 1] != y or self.cf[j] == 0:
+            raise KeyError(f"({x}, {y}) is not a sum of this congruence")
+        return self.cf[j]
+
+    # ---- measures -------------------------------------------------------
+    def cost(self):
+        """Total length of the sums (cost / p)."""
+        return sum((self.bp[j + 1] - self.bp[j] for j, c in enumerate(self.cf) if c != 0), Q(0))
+
+    def n_sums(self):
+        return sum(1 for c in self.cf if c != 0)
+
+    def value_at(self, t):
+        """Coefficient at a point t in (0, 1/2) that is not a breakpoint."""
+        j = bisect_right(self.bp, t) - 1
+        return self.cf[j] if 0 <= j < len(self.cf) else Q(0)
+
+    def cost_after(self, x, y, d):
+        """cost() after subdivide(x, y, d), without changing the congruence."""
+        c = self._coef_of(x, y)
+        w = c / Q(d) ** self.power
+        delta = [(x, y, -c)]
+        for i in range(d):
+            a, b = (x + i) / d, (y + i) / d
+            if b <= HALF:
+                delta.append((a, b, w))
+            elif a >= HALF:
+                delta.append((1 - b, 1 - a, self.refl * w))
+            else:
+                delta.append((a, HALF, w))
+                delta.append((1 - b, HALF, self.refl * w))
+        pts = set()
+        for a, b, _ in delta:
+            pts.add(a)
+            pts.add(b)
+            lo, hi = bisect_right(self.bp, a), bisect_left(self.bp, b)
+            pts.update(self.bp[lo:hi])
+        pts = sorted(pts)
+        change = Q(0)
+        for a, b in zip(pts, pts[1:]):
+            mid = (a + b) / 2
+            dv = sum((c2 for a2, b2, c2 in delta if a2 <= a and b <= b2), Q(0))
+            if dv == 0:
+                continue
+            old = self.value_at(mid)
+            change += (b - a) * ((old + dv != 0) - (old != 0))
+        return self.cost() + change
+
+    # ---- output ---------------------------------------------------------
+    def integer_form(self):
+        """(L, [(N_i, x_i, y_i)]) with L * X == sum N_i S(x_i, y_i), all integers,
+        the common content divided out and L > 0."""
+        ps = self.pieces()
+        den = self.lhs.denominator
+        for c, _, _ in ps:
+            den = den * c.denominator // gcd(den, c.denominator)
+        L = self.lhs * den
+        Ns = [c * den for c, _, _ in ps]
+        g = abs(int(L))
+        for n in Ns:
+            g = gcd(g, abs(int(n)))
+        sgn = -1 if L < 0 else 1
+        L = int(L) // g * sgn
+        return L, [(int(n) // g * sgn, x, y) for n, (_, x, y) in zip(Ns, ps)]
+
+    def to_json(self, name):
+        L, terms = self.integer_form()
+        return {"name": name, "side": self.side, "lhs": str(L), "n": len(terms),
+                "cost": [self.cost().numerator, self.cost().denominator],
+                "terms": [[str(n), x.numerator, x.denominator, y.numerator, y.denominator] for n, x, y in terms]}
+
+
+def load_json(obj):
+    """A Congruence from to_json output."""
+    c = Congruence(obj["side"], int(obj["lhs"]))
+    for n, xa, xb, ya, yb in obj["terms"]:
+        c.add(Q(xa, xb), Q(ya, yb), Q(int(n)))
+    return c
+
+
+# ---------------------------------------------------------------------------
+# searches
+# ---------------------------------------------------------------------------
+
+def exhaustive(start, ds):
+    """Section 2.1: every sequence of at most len(ds) subdivisions, the i-th
+    with 2 <= d <= ds[i].  Returns {m: (cost, steps)} with the cheapest
+    congruence found for each number of sums m (first found on ties)."""
+    best = {}
+
+    def visit(cong, depth, steps):
+        m, cost = cong.n_sums(), cong.cost()
+        if m not in best or cost < best[m][0]:
+            best[m] = (cost, list(steps))
+        if depth == len(ds):
+            return
+        for c, x, y in cong.pieces():
+            for d in range(2, ds[depth] + 1):
+                nxt = cong.copy().subdivide(x, y, d)
+                steps.append((x, y, d))
+                visit(nxt, depth + 1, steps)
+                steps.pop()
+
+    visit(start.copy(), 0, [])
+    return best
+
+
+def greedy(start, D=8, rounds=100, lam=1, log=None):
+    """Section 2.2: each round tries every sequence of lam subdivisions with
+    d <= D and moves to a cheapest result (first in piece order, then d, on
+    ties); returns (final congruence, cheapest congruence seen, its round)."""
+    cur = start.copy()
+    best, best_round = cur.copy(), 0
+    for r in range(1, rounds + 1):
+        choice = None
+        if lam == 1:
+            for c, x, y in cur.pieces():
+                for d in range(2, D + 1):
+                    cost = cur.cost_after(x, y, d)
+                    if choice is None or cost < choice[0]:
+                        choice = (cost, [(x, y, d)])
+        else:
+            for seq in _sequences(cur, D, lam):
+                cand = cur.copy()
+                for x, y, d in seq:
+                    cand.subdivide(x, y, d)
+                if choice is None or cand.cost() < choice[0]:
+                    choice = (cand.cost(), seq)
+        if choice is None:
+            break
+        for x, y, d in choice[1]:
+            cur.subdivide(x, y, d)
+        if cur.cost() < best.cost():
+            best, best_round = cur.copy(), r
+        if log:
+            log(r, cur)
+    return cur, best, best_round
+
+
+def _sequences(cong, D, lam):
+    if lam == 0:
+        yield []
+        return
+    for c, x, y in cong.pieces():
+        for d in range(2, D + 1):
+            nxt = cong.copy().subdivide(x, y, d)
+            for rest in _sequences(nxt, D, lam - 1):
+                yield [(x, y, d)] + rest
+
+
+def save_tables(path, tables):
+    with open(path, "w") as f:
+        json.dump(tables, f, indent=0)

@@ -1,0 +1,158 @@
+"""The congruence-derivation engine (paper_2101_11157_amd.derive) against the
+paper: its recipes must rebuild the printed congruences exactly, its searches
+must reach the printed minimal costs, and whatever it derives must give the
+residues of the recurrences (the oracle)."""
+from fractions import Fraction as Q
+from math import gcd
+
+import pytest
+
+import oracle
+from oracle import congruences as C
+from paper_2101_11157_amd import derive as D
+
+
+def normal_form(L, terms):
+    """(L, terms) divided by the content, L > 0: a congruence up to a scalar."""
+    g = abs(int(L))
+    for n, _, _ in terms:
+        g = gcd(g, abs(int(n)))
+    s = -1 if L < 0 else 1
+    return int(L) // g * s, [(int(n) // g * s, Q(x), Q(y)) for n, x, y in terms]
+
+
+def assert_same(cong, table):
+    assert cong.integer_form() == normal_form(table.lhs, table.terms)
+    assert cong.cost() == table.exact_cost() == table.cost
+
+
+def test_starting_congruences_and_costs():
+    """Section 2: costs p/10 (Vandiver, V10), p/12 (SV, V12); Section 4: E1 p/4."""
+    assert D.Congruence.start("Vandiver").cost() == Q(1, 10)
+    assert D.Congruence.start("V10").cost() == Q(1, 10)
+    assert D.Congruence.start("SV").cost() == Q(1, 12)
+    assert D.Congruence.start("V12").cost() == Q(1, 12)
+    assert D.Congruence.start("E1").cost() == Q(1, 4)
+    assert D.Congruence.start("EMac2").cost() == Q(1, 6)
+    for b in range(2, 14):
+        want = Q((b // 2) * (b // 2 + 1), 2 * b * (b + 1))
+        assert D.Congruence.start(f"TW1{b}").cost() == want
+
+
+def test_transformations_on_tiny_intervals():
+    """Reflection across 1/2 with the sign (-1)^l (l odd for B, even for E),
+    splitting at 1/2, merging equal neighbours, and subdivision weights d^-3 /
+    d^-2."""
+    b = D.Congruence("B", 1, [(1, Q(3, 5), Q(4, 5))])        # reflected: -S(1/5, 2/5)
+    assert b.pieces() == [(-1, Q(1, 5), Q(2, 5))]
+    e = D.Congruence("E", 1, [(1, Q(2, 5), Q(3, 5))])        # straddles 1/2: 2 S(2/5, 1/2)
+    assert e.pieces() == [(2, Q(2, 5), Q(1, 2))]
+    m = D.Congruence("B", 1, [(1, Q(1, 7), Q(1, 5)), (1, Q(1, 5), Q(1, 4))])
+    assert m.pieces() == [(1, Q(1, 7), Q(1, 4))] and m.n_sums() == 1
+    z = D.Congruence("B", 1, [(1, Q(1, 7), Q(1, 5)), (-1, Q(1, 7), Q(1, 5))])
+    assert z.pieces() == [] and z.cost() == 0
+    s = D.Congruence("E", 1, [(1, Q(0), Q(1, 4))]).subdivide(Q(0), Q(1, 4), 3)
+    # images (0, 1/12), (1/3, 5/12), (2/3, 3/4) -> reflected (1/4, 1/3), weight 1/9 each
+    assert s.pieces() == [(Q(1, 9), Q(0), Q(1, 12)), (Q(1, 9), Q(1, 4), Q(5, 12))]
+    with pytest.raises(KeyError):
+        s.subdivide(Q(0), Q(1, 13), 2)
+
+
+def test_recipe_b2_and_b6():
+    """eqnB2 from eqnVandiver (d = 2 on S(1/3, 2/5)), specialised as eqnBB2;
+    then the four d = 2 subdivisions of Section 2.1 give eqnBB6."""
+    c = D.Congruence.start("Vandiver").subdivide(Q(1, 3), Q(2, 5), 2)
+    assert_same(c, C.BB2)
+    for x, y in [(Q(3, 10), Q(1, 3)), (Q(1, 3), Q(7, 20)), (Q(13, 40), Q(1, 3)), (Q(1, 3), Q(27, 80))]:
+        c.subdivide(x, y, 2)
+    assert_same(c, C.BB6)
+
+
+def test_recipes_e3_e5_e9_e16():
+    """Section 4's derivations from eqnE1 rebuild eqnEE3, EE5, EE9 and EE16."""
+    e = D.Congruence.start("E1").subdivide(Q(0), Q(1, 4), 2).subdivide(Q(0), Q(1, 8), 2)
+    assert_same(e, C.EE3)
+    e.subdivide(Q(0), Q(1, 16), 2).subdivide(Q(0), Q(1, 32), 2)
+    assert_same(e, C.EE5)
+    e.subdivide(Q(0), Q(1, 64), 2).subdivide(Q(3, 8), Q(7, 16), 3)
+    assert_same(e, C.EE9)
+    for x, y, d in [(Q(3, 16), Q(5, 24), 3), (Q(7, 16), Q(11, 24), 3), (Q(0), Q(1, 128), 2),
+                    (Q(1, 8), Q(7, 48), 2), (Q(11, 24), Q(15, 32), 2)]:
+        e.subdivide(x, y, d)
+    assert_same(e, C.EE16)
+
+
+def test_recipe_e33_from_emac2():
+    """The sixteen subdivision steps listed in Section 4 turn eqnEMac2 into
+    eqnE33, specialised as eqnEE33 (33 sums, cost 27/512)."""
+    m = D.Congruence.start("EMac2")
+    steps = [(Q(0), Q(1, 2 ** k * 3), 2) for k in range(2, 9)]
+    steps += [(Q(5, 12), Q(11, 24), 3), (Q(11, 24), Q(17, 36), 3), (Q(17, 36), Q(23, 48), 3),
+              (Q(23, 48), Q(35, 72), 3)]
+    steps += [(Q(5, 36), Q(11, 72), 2), (Q(5, 72), Q(11, 144), 2)]
+    steps += [(Q(61, 144), Q(31, 72), 3), (Q(133, 288), Q(67, 144), 3), (Q(205, 432), Q(103, 216), 3)]
+    for x, y, d in steps:
+        m.subdivide(x, y, d)
+    assert m.n_sums() == 33
+    assert_same(m, C.EE33)
+
+
+def test_exhaustive_search_reaches_table_1():
+    """Section 2.1, Table 1: starting from eqnVandiver, sequences of up to seven
+    d = 2 subdivisions reach the printed minimal costs p/r_m for m = 1..8
+    (r_1 = 12 belongs to eqnSV, not reachable from Vandiver with one sum)."""
+    best = D.exhaustive(D.Congruence.start("Vandiver"), [2] * 7)
+    r = {m: 1 / c for m, (c, _) in best.items()}
+    assert r[2] == 15 and r[3] == 15
+    assert r[4] == Q(120, 7) and r[5] == Q(240, 13) and r[6] == Q(96, 5)
+    assert r[7] == Q(960, 49) and r[8] == Q(1920, 97)
+
+
+def test_greedy_search_lowers_cost_and_cost_after_is_exact():
+    """Section 2.2 with lambda = 1, D = 8 from eqnEMac2: the cost falls, and the
+    incremental cost used to rank candidates equals the cost after applying
+    the subdivision."""
+    start = D.Congruence.start("EMac2")
+    seen = []
+    cur, best, r = D.greedy(start, D=8, rounds=12, log=lambda k, c: seen.append(c.cost()))
+    assert best.cost() < Q(1, 16) < start.cost() and len(seen) == 12 and best.cost() == min(seen)
+    for c, x, y in cur.pieces()[:6]:
+        for d in (2, 3, 5, 8):
+            assert cur.cost_after(x, y, d) == cur.copy().subdivide(x, y, d).cost()
+
+
+def _as_oracle_congruence(cong, name):
+    L, terms = cong.integer_form()
+    kind, ell = ("B", -3) if cong.side == "B" else ("E", -2)
+    return C.Congruence(name, kind, ell, L, terms, cong.cost(), "derived", min_p=11)
+
+
+@pytest.mark.parametrize("start,rounds", [("Vandiver", 25), ("EMac2", 25), ("E1", 15), ("SV", 10)])
+def test_derived_congruences_give_the_recurrence_residues(start, rounds):
+    """Whatever the greedy search derives is a valid congruence: evaluated
+    plainly by the oracle, it gives B_{p-3} / E_{p-3} mod p of the recurrence for
+    every prime 11 <= p < 1200 (p divides no subdivision factor) and the root
+    forms' residues on primes near 1e6."""
+    _, best, _ = D.greedy(D.Congruence.start(start), D=8, rounds=rounds)
+    cong = _as_oracle_congruence(best, f"greedy-{start}")
+    ps = [p for p in oracle.primes(11, 1200) if cong.lhs % p]
+    got = [oracle.congruence_residue_exact(p, cong) for p in ps]
+    want = [oracle.bernoulli_rec(p) if cong.kind == "B" else oracle.euler_rec(p) for p in ps]
+    assert got == want
+    big = oracle.primes(10 ** 6, 10 ** 6 + 400)[:12]
+    root = C.SV if cong.kind == "B" else C.E1
+    assert [oracle.congruence_residue_exact(p, cong) for p in big] == oracle.congruence_residues(big, root)
+
+
+def test_exact_evaluator_matches_the_printed_tables():
+    """The oracle's arbitrary-size evaluator agrees with its C evaluator on the
+    printed eqnBB30 / eqnEE33 (primes near 1e5)."""
+    ps = oracle.primes(10 ** 5, 10 ** 5 + 300)
+    for t in (C.BB30, C.EE33):
+        assert [oracle.congruence_residue_exact(p, t) for p in ps] == oracle.congruence_residues(ps, t)
+
+
+def test_json_round_trip():
+    _, best, _ = D.greedy(D.Congruence.start("EMac2"), D=8, rounds=6)
+    again = D.load_json(best.to_json("t"))
+    assert again.integer_form() == best.integer_form() and again.cost() == best.cost()
