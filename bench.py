@@ -38,7 +38,7 @@ RENORM = 20         # blocks between table reductions
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
 # (profiles/k_sum_window_1e11_14_20.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {("1e11", 14, 20, 8192): 4285157 + 26352736}
+MEASURED_TRAFFIC = {("1e11", "printed", 14, 20, 8192): 4285157 + 26352736}
 
 
 def ops_per_term(d, k):
@@ -47,6 +47,19 @@ def ops_per_term(d, k):
         return 2 * OPS_MONT + 1 + d * OPS_ADDM
     table = d * k + d * (k - 1)   # difference-table entries of P and Q
     return (3 * OPS_MONT + 1 + table * (1 + OPS_REDUCE / RENORM)) / k
+
+
+def muls_per_term(d, k):
+    """int32 multiply instructions (v_mad_u64_u32, v_mul_lo_u32) per term: ten
+    per Montgomery product, two per table-entry reduction."""
+    if k == 1:
+        return 2 * 10
+    return (3 * 10 + (d * k + d * (k - 1)) * 2 / RENORM) / k
+
+
+def sum_kernel_muls(st):
+    nb = st["n_terms_b"]
+    return nb * muls_per_term(3, st["block_k_b"]) + (st["n_terms"] - nb) * muls_per_term(2, st["block_k_e"])
 
 
 def sum_kernel_ops(st):
@@ -60,6 +73,17 @@ CONFIGS = {
     "1e5": (5, 10 ** 5, 10 ** 5),
 }
 EXTRA_CONFIGS = ("batch", "serve")
+
+
+def use_tables(ctx, which):
+    """Select the congruences; returns their description."""
+    if which == "derived":
+        import paper_2101_11157_amd as wv
+        ctx.use_derived_tables()
+        jb, je = wv.derived_table("B"), wv.derived_table("E")
+        return (f"derived: {jb['n']}-sum B (cost {jb['cost'][0]}/{jb['cost'][1]}) and {je['n']}-sum E "
+                f"(cost {je['cost'][0]}/{je['cost'][1]}) for p >= 2^30, eqnBB30+eqnEE33 below")
+    return "eqnBB30+eqnEE33"
 
 
 def cpu_threads():
@@ -103,6 +127,9 @@ def main():
     ap.add_argument("--window", type=int, default=0, help="integers per step (0: config default)")
     ap.add_argument("--chunk", type=int, default=0, help="terms per lane chunk (0: automatic)")
     ap.add_argument("--block", default="", help="term-sum block shape KB,KE (default: the library's)")
+    ap.add_argument("--tables", default="derived", choices=["derived", "printed"],
+                    help="derived: the package's greedy-derived congruences (Section 2.2) above 2^30, "
+                         "printed: eqnBB30 + eqnEE33")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primes", type=int, default=1, help="primes in the oracle sample")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -143,12 +170,14 @@ def main():
         ctx.set_chunk_terms(args.chunk)
     if args.block:
         ctx.set_block(*[int(v) for v in args.block.split(",")])
+    tables = use_tables(ctx, args.tables)
     for k in range(args.warmup):
         ctx.search_range(*wins[k])
         print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
 
     primes = terms = 0
     ops = 0.0
+    muls = 0.0
     block = None
     ms_sum = ms_dev = 0.0
     first_timed = None
@@ -159,6 +188,7 @@ def main():
         primes += len(res)
         terms += st["n_terms"]
         ops += sum_kernel_ops(st)
+        muls += sum_kernel_muls(st)
         block = [st["block_k_b"], st["block_k_e"]]
         ms_sum += st["ms_sum"]
         ms_dev += st["ms_total"]
@@ -172,6 +202,7 @@ def main():
     value = primes / wall
     achieved = ops / (ms_sum * 1e-3) / 1e12
     peak = PEAK_VALU / 1e12
+    mul_rate = muls / (ms_sum * 1e-3) / 1e12
     line = {
         "metric": "primes tested/sec at p~1e11 (1 GPU), both B_{p-3} and E_{p-3} mod p",
         "value": value,
@@ -187,7 +218,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"primes in [{lo0}, {hi0}), sub-windows of {W} integers per step",
-            "tables": "eqnBB30+eqnEE33",
+            "tables": tables,
             "primes_timed": primes,
             "terms_timed": terms,
             "terms_per_s": terms / wall,
@@ -201,9 +232,12 @@ def main():
             "peak": peak,
             "unit": "Tops/s (full-rate VALU lane ops)",
             "frac": achieved / peak,
-            "traffic": MEASURED_TRAFFIC.get((args.config, block[0], block[1], W)) if block else None,
+            "traffic": MEASURED_TRAFFIC.get((args.config, args.tables, block[0], block[1], W)) if block else None,
         },
     }
+    # the int32-multiply view: the blocked loop needs few multiplies per term,
+    # so this fraction is low although the kernel is bound by VALU issue
+    line["int32_mul"] = {"achieved": mul_rate, "peak": peak, "unit": "Tops/s", "frac": mul_rate / peak}
     if not args.no_cpu_baseline and first_timed:
         sample = first_timed[: max(1, args.cpu_primes)]
         nt = cpu_threads()
@@ -224,6 +258,7 @@ def bench_batch(args, wv):
     ctx = wv.Context(0)
     if args.chunk:
         ctx.set_chunk_terms(args.chunk)
+    tables = use_tables(ctx, args.tables)
     last = [0.0]
 
     t_start = time.perf_counter()
@@ -257,7 +292,7 @@ def bench_batch(args, wv):
         "config": {"workload": f"{len(wins)} seeded windows (default_rng(0)), lengths log-uniform [1e3, 1e6], "
                                f"starts log-uniform [1e6, 1e11]", "primes": primes, "terms": st["n_terms"],
                    "terms_per_s": st["n_terms"] / wall, "sum_kernel_ms": st["ms_sum"], "wall_s": wall,
-                   "block": [st["block_k_b"], st["block_k_e"]], "verified_windows": args.verify,
+                   "block": [st["block_k_b"], st["block_k_e"]], "tables": tables, "verified_windows": args.verify,
                    "verified_identical": ok},
     }), flush=True)
 
@@ -320,6 +355,7 @@ def bench_serve(args, wv):
     from paper_2101_11157_amd import workloads
     trace = workloads.serve_trace(0, args.requests, rate=args.rate)
     ctx = wv.Context(0)
+    tables = use_tables(ctx, args.tables)
     main_run, out = run_trace(wv, ctx, trace, args.step_terms)
     ok = None
     if args.verify:
@@ -338,7 +374,7 @@ def bench_serve(args, wv):
         "mean_ms": main_run["mean_ms"],
         "config": dict({"workload": f"seeded Poisson trace (default_rng(0)), {len(trace)} requests, "
                                     f"{args.rate:g}/s, 70% single primes, 30% intervals of 1e2..1e5, "
-                                    f"u in [1e8, 1e11]", "verified_identical": ok}, **main_run),
+                                    f"u in [1e8, 1e11]", "tables": tables, "verified_identical": ok}, **main_run),
     }
     if args.load:
         per_req = main_run["terms"] / len(trace)

@@ -111,11 +111,28 @@ int wv_create(int hip_device, wv_ctx **out);
 /* Release every resource of ctx (NULL is accepted). */
 int wv_destroy(wv_ctx *ctx);
 
-/* Choose the congruences used for primes p >= 11: b_table one of the BB ids,
- * e_table one of the EE ids.  Default: WV_TABLE_BB30 and WV_TABLE_EE33 (the
+/* Choose the congruences used for primes p >= 11: b_table one of the BB ids
+ * or a Bernoulli table defined with wv_define_table, e_table one of the EE ids
+ * or a defined Euler table.  Default: WV_TABLE_BB30 and WV_TABLE_EE33 (the
  * cheapest printed ones, cost 227p/6480 and 27p/512).  Every valid choice gives
  * identical residues; only the work changes.  Errors: WV_EINVAL. */
 int wv_set_tables(wv_ctx *ctx, int b_table, int e_table);
+
+/* Define a congruence at run time (for instance one derived from eqnVandiver
+ * or eqnEMac2 with the transformations of Proposition propTW, Section 2):
+ *     lhs * X_{p-3} == sum_{i<n} coef[i] * S(xa[i]/xb[i], ya[i]/yb[i])  (mod p),
+ * S(x, y) = sum_{x p < s < y p} s^-deg, deg 3 for X = B, 2 for X = E.
+ * Integers are decimal strings of any length (optional leading '-'; lhs
+ * nonzero); endpoints 0 <= x < y <= 1 with denominators below 2^63; n <= 65536.
+ * The table serves the primes p >= min_p (min_p >= 11, above every prime the
+ * derivation must avoid, such as subdivision factors) that do not divide lhs;
+ * every other prime of a batch uses eqnBB30 / eqnEE33.  The congruence itself
+ * is trusted, not checked.  *id
+ * receives the id for wv_set_tables (at most 64 tables per context).
+ * Errors: WV_EINVAL (malformed input), WV_ENOMEM, WV_EHIP. */
+int wv_define_table(wv_ctx *ctx, int deg, const char *lhs, size_t n, const char *const *coef,
+                    const uint64_t *xa, const uint64_t *xb, const uint64_t *ya, const uint64_t *yb,
+                    uint64_t min_p, int *id);
 
 /* Set the number of terms each lane sums per chunk (0 = automatic: about
  * sqrt(2 * 4096 * T / (lanes + sums)) for a batch of T terms, between 2^12

@@ -33,6 +33,23 @@ WV_FLAG_VANDIVER = 2
 TABLE_NAMES = ["BB1", "BB2", "BB6", "BB9", "BB16", "BB22", "BB30",
                "EE3", "EE5", "EE9", "EE16", "EE24", "EE33", "V12", "E1"]
 TABLE_ID = {n: i for i, n in enumerate(TABLE_NAMES)}
+# derived congruences shipped with the package (tables/make_tables.py)
+DERIVED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tables")
+DERIVED_MIN_P = 1 << 30     # below this the printed tables' fewer, longer sums are cheaper overall
+
+
+def derived_table(side):
+    """The JSON congruence of tables/derived_<side>.json (side 'B' or 'E')."""
+    import json
+    with open(os.path.join(DERIVED_DIR, f"derived_{side}.json")) as f:
+        return json.load(f)
+
+
+def Fraction_(a, b):
+    from fractions import Fraction
+    return Fraction(int(a), int(b))
+
+
 # compiled block shapes of the term-sum kernel, in the library's order
 BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (8, 16), (12, 12), (12, 16), (12, 20), (14, 20), (16, 16)]
 
@@ -115,6 +132,8 @@ def lib():
             "wv_search_windows": (ctypes.c_int, [VP, P_U64, P_U64, SZ, VP, SZ, ctypes.POINTER(SZ),
                                                  ctypes.POINTER(SZ)]),
             "wv_set_progress": (ctypes.c_int, [VP, PROGRESS_FN, VP, U64]),
+            "wv_define_table": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_char_p, SZ, ctypes.POINTER(ctypes.c_char_p),
+                                               P_U64, P_U64, P_U64, P_U64, U64, ctypes.POINTER(ctypes.c_int)]),
             "wv_range_stats": (ctypes.c_int, [VP, U64, U64, ctypes.c_uint32, U64, P_U64, P_U64, VP, SZ,
                                               ctypes.POINTER(SZ), P_U64]),
             "wv_autotune": (ctypes.c_int, [VP, U64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -218,6 +237,38 @@ class Context:
         b = TABLE_ID[b_table] if isinstance(b_table, str) else int(b_table)
         e = TABLE_ID[e_table] if isinstance(e_table, str) else int(e_table)
         _check(lib().wv_set_tables(self._h, b, e), "wv_set_tables")
+
+    def define_table(self, deg, lhs, terms, min_p=11):
+        """Register  lhs * X_{p-3} == sum c S(x, y)  (terms: (c, x, y) with
+        integer c and fractions 0 <= x < y <= 1; deg 3: X = B, 2: X = E) for
+        primes p >= min_p; returns the table id for set_tables."""
+        from fractions import Fraction
+        n = len(terms)
+        coef = (ctypes.c_char_p * n)(*[str(int(c)).encode() for c, _, _ in terms])
+        xs = [Fraction(x) for _, x, _ in terms]
+        ys = [Fraction(y) for _, _, y in terms]
+        arr = lambda v: np.ascontiguousarray(np.array(v, dtype=np.uint64))
+        xa, xb = arr([x.numerator for x in xs]), arr([x.denominator for x in xs])
+        ya, yb = arr([y.numerator for y in ys]), arr([y.denominator for y in ys])
+        out = ctypes.c_int()
+        _check(lib().wv_define_table(self._h, int(deg), str(int(lhs)).encode(), n, coef, xa.ctypes.data_as(P_U64),
+                                     xb.ctypes.data_as(P_U64), ya.ctypes.data_as(P_U64), yb.ctypes.data_as(P_U64),
+                                     int(min_p), ctypes.byref(out)), "wv_define_table")
+        return out.value
+
+    def define_derived_table(self, obj, min_p=DERIVED_MIN_P):
+        """Register a congruence written by derive.Congruence.to_json."""
+        terms = [(int(n), Fraction_(xa, xb), Fraction_(ya, yb)) for n, xa, xb, ya, yb in obj["terms"]]
+        return self.define_table(3 if obj["side"] == "B" else 2, int(obj["lhs"]), terms, min_p)
+
+    def use_derived_tables(self, min_p=DERIVED_MIN_P):
+        """Define the package's derived congruences (tables/*.json, built by
+        tables/make_tables.py with the greedy search of Section 2.2) and use
+        them for primes >= min_p; returns (b_id, e_id)."""
+        b = self.define_derived_table(derived_table("B"), min_p)
+        e = self.define_derived_table(derived_table("E"), min_p)
+        self.set_tables(b, e)
+        return b, e
 
     def set_chunk_terms(self, n):
         _check(lib().wv_set_chunk_terms(self._h, int(n)), "wv_set_chunk_terms")

@@ -99,15 +99,14 @@ int check_device(wv_ctx *c) {
 
 int batch_shape(const wv_ctx *c, uint32_t n, uint64_t pmax, BatchShape *sh) {
     sh->n = n;
-    sh->nB = std::max(table_slots(c->tb), 1);
-    sh->nE = std::max(table_slots(c->te), 1);
+    sh->nB = side_slots(c, c->tb);
+    sh->nE = side_slots(c, c->te);
     sh->nseg = (uint64_t)n * (sh->nB + sh->nE);
     // partial pairs: the plan picks chunk >= total_terms / (cap - nseg), so
     // cap > nseg always; with room for total_terms / chunk_cfg + nseg chunks
     // the configured chunk size is kept.  total_terms <= n (pmax cost + sums).
     const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
-    const double cost = (double)kTables[c->tb].cost_num / kTables[c->tb].cost_den +
-                        (double)kTables[c->te].cost_num / kTables[c->te].cost_den;
+    const double cost = side_cost(c, c->tb) + side_cost(c, c->te);
     const double t_max = (double)n * ((double)pmax * cost + sh->nB + sh->nE);
     // the adaptive chunk grows with T, so T / chunk is largest at the bound
     const double chunk = chunk_cfg ? (double)chunk_cfg
@@ -130,6 +129,8 @@ int prepare(wv_ctx *c, const BatchShape &sh) {
     WV_TRY(ensure(c, c->scal, 8 * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->partials, sh.cap * sizeof(Pair)));
     WV_TRY(ensure(c, c->seg_pairs, nseg * sizeof(Pair)));
+    WV_TRY(ensure(c, c->coefs, nseg * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->lhsmod, 2 * n * sizeof(uint64_t)));
     return WV_OK;
 }
 
@@ -140,8 +141,9 @@ int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipS
     uint64_t *toff = as<uint64_t>(c->off);   // prefix of terms, then of chunks
     const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
     WV_HIP(launch_set_u64(st, scal, 8, 0));
-    WV_HIP(launch_plan(st, d_primes, sh.n, c->tb, c->te, sh.nB, sh.nE, as<PrimeRec>(c->pr), as<SegRec>(c->segs),
-                       as<uint64_t>(c->terms), 0));
+    WV_HIP(launch_plan(st, d_primes, sh.n, c->tb, c->te, table_fallback(c, c->tb), table_fallback(c, c->te), sh.nB,
+                       sh.nE, table_store(c), as<PrimeRec>(c->pr), as<SegRec>(c->segs), as<uint64_t>(c->terms),
+                       as<uint64_t>(c->coefs), as<uint64_t>(c->lhsmod), 0));
     WV_HIP(launch_scan(st, as<uint64_t>(c->terms), sh.nseg, toff, as<uint64_t>(c->tiles)));
     WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sum_lanes(c), sh.cap, scal + 1));
     WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + 0, 1));
@@ -165,7 +167,8 @@ int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin,
 int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out) {
     WV_HIP(launch_reduce(st, as<SegRec>(c->segs), as<uint64_t>(c->off), (uint32_t)sh.nseg, as<PrimeRec>(c->pr),
                          as<Pair>(c->partials), as<Pair>(c->seg_pairs)));
-    WV_HIP(launch_finalize(st, as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), sh.n, sh.nB, sh.nE, d_out));
+    WV_HIP(launch_finalize(st, table_store(c), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), as<uint64_t>(c->coefs),
+                           as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out));
     return WV_OK;
 }
 
@@ -207,7 +210,8 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
     WV_HIP(launch_reduce(st, as<SegRec>(c->segs), as<uint64_t>(c->off), (uint32_t)sh.nseg, as<PrimeRec>(c->pr),
                          as<Pair>(c->partials), as<Pair>(c->seg_pairs)));
     WV_HIP(hipEventRecord(c->ev[EV_RED], st));
-    WV_HIP(launch_finalize(st, as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), sh.n, sh.nB, sh.nE, d_out));
+    WV_HIP(launch_finalize(st, table_store(c), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), as<uint64_t>(c->coefs),
+                           as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out));
     WV_HIP(hipEventRecord(c->ev[EV_FINAL], st));
     WV_HIP(hipEventSynchronize(c->ev[EV_FINAL]));
     // statistics
@@ -289,8 +293,7 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
         // about kMaxBatchTerms terms (bounded by count * largest p * cost):
         // with the partial pairs capped, a bigger batch would force chunks
         // longer than its sums
-        const double cost = (double)kTables[c->tb].cost_num / kTables[c->tb].cost_den +
-                            (double)kTables[c->te].cost_num / kTables[c->te].cost_den;
+        const double cost = side_cost(c, c->tb) + side_cost(c, c->te);
         size_t j = i;
         uint64_t np = 0;
         double est = 0.0;
@@ -354,6 +357,130 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
     }
     return WV_OK;
 }
+
+// ---- congruence registry ---------------------------------------------------
+
+static std::vector<uint32_t> limbs_of(uint64_t v) {
+    std::vector<uint32_t> l;
+    while (v) {
+        l.push_back((uint32_t)v);
+        v >>= 32;
+    }
+    return l;
+}
+
+// Decimal string (optional leading '-') -> magnitude limbs and sign.
+static bool parse_int(const char *str, std::vector<uint32_t> *mag, bool *neg) {
+    if (!str) return false;
+    mag->clear();
+    *neg = false;
+    const char *q = str;
+    if (*q == '-' || *q == '+') *neg = *q++ == '-';
+    if (!*q || std::strlen(q) > 20000) return false;
+    for (; *q; q++) {
+        if (*q < '0' || *q > '9') return false;
+        uint64_t carry = (uint64_t)(*q - '0');
+        for (uint32_t &w : *mag) {
+            const uint64_t t = (uint64_t)w * 10 + carry;
+            w = (uint32_t)t;
+            carry = t >> 32;
+        }
+        if (carry) mag->push_back((uint32_t)carry);
+    }
+    if (mag->empty()) *neg = false;   // zero
+    return true;
+}
+
+static int upload_tables(wv_ctx *c) {
+    WV_TRY(ensure(c, c->tbl_head, c->t_head.size() * sizeof(TableHead)));
+    WV_TRY(ensure(c, c->tbl_term, c->t_term.size() * sizeof(TableTerm)));
+    WV_TRY(ensure(c, c->tbl_limb, std::max<size_t>(1, c->t_limb.size()) * sizeof(uint32_t)));
+    WV_HIP(hipMemcpyAsync(c->tbl_head.ptr, c->t_head.data(), c->t_head.size() * sizeof(TableHead),
+                          hipMemcpyHostToDevice, c->stream));
+    WV_HIP(hipMemcpyAsync(c->tbl_term.ptr, c->t_term.data(), c->t_term.size() * sizeof(TableTerm),
+                          hipMemcpyHostToDevice, c->stream));
+    if (!c->t_limb.empty())
+        WV_HIP(hipMemcpyAsync(c->tbl_limb.ptr, c->t_limb.data(), c->t_limb.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, c->stream));
+    WV_HIP(hipStreamSynchronize(c->stream));
+    return WV_OK;
+}
+
+int table_add(wv_ctx *c, int deg, const std::vector<uint32_t> &lhs_mag, bool lhs_neg,
+              const std::vector<std::vector<uint32_t>> &coef_mag, const std::vector<bool> &coef_neg,
+              const uint64_t *xa, const uint64_t *xb, const uint64_t *ya, const uint64_t *yb, uint64_t min_p,
+              int *id) {
+    TableHead h{};
+    h.deg = deg;
+    h.n = (int32_t)coef_mag.size();
+    h.term_off = (uint32_t)c->t_term.size();
+    h.lhs_off = (uint32_t)c->t_limb.size();
+    h.lhs_nlimb = (uint16_t)lhs_mag.size();
+    h.lhs_neg = lhs_neg ? 1 : 0;
+    h.min_p = min_p;
+    c->t_limb.insert(c->t_limb.end(), lhs_mag.begin(), lhs_mag.end());
+    double cost = 0.0;
+    for (size_t i = 0; i < coef_mag.size(); i++) {
+        TableTerm t{};
+        t.xa = xa[i];
+        t.xb = xb[i];
+        t.ya = ya[i];
+        t.yb = yb[i];
+        t.limb_off = (uint32_t)c->t_limb.size();
+        t.nlimb = (uint16_t)coef_mag[i].size();
+        t.neg = coef_neg[i] ? 1 : 0;
+        c->t_limb.insert(c->t_limb.end(), coef_mag[i].begin(), coef_mag[i].end());
+        c->t_term.push_back(t);
+        cost += (double)ya[i] / (double)yb[i] - (double)xa[i] / (double)xb[i];
+    }
+    c->t_head.push_back(h);
+    c->t_cost.push_back(cost);
+    *id = (int)c->t_head.size() - 1;
+    return upload_tables(c);
+}
+
+// The compiled tables, from wv_tables.hpp, become registry entries 0..WV_TABLE_COUNT-1.
+int tables_init(wv_ctx *c) {
+    c->t_head.clear();
+    c->t_term.clear();
+    c->t_limb.clear();
+    c->t_cost.clear();
+    for (int i = 0; i < kNumTables; i++) {
+        const TableDef &d = kTables[i];
+        std::vector<std::vector<uint32_t>> mag(d.n);
+        std::vector<bool> neg(d.n);
+        std::vector<uint64_t> xa(d.n), xb(d.n), ya(d.n), yb(d.n);
+        for (int j = 0; j < d.n; j++) {
+            const TermDef &t = d.t[j];
+            mag[j] = limbs_of(t.coef < 0 ? (uint64_t)(-t.coef) : (uint64_t)t.coef);
+            neg[j] = t.coef < 0;
+            xa[j] = t.xa;
+            xb[j] = t.xb;
+            ya[j] = t.ya;
+            yb[j] = t.yb;
+        }
+        int id = 0;
+        WV_TRY(table_add(c, d.deg, limbs_of(d.lhs < 0 ? (uint64_t)(-d.lhs) : (uint64_t)d.lhs), d.lhs < 0, mag, neg,
+                         xa.data(), xb.data(), ya.data(), yb.data(), 5, &id));
+        if (id != i) return WV_EHIP;
+    }
+    return WV_OK;
+}
+
+TableStore table_store(wv_ctx *c) {
+    return TableStore{as<TableHead>(c->tbl_head), as<TableTerm>(c->tbl_term), as<uint32_t>(c->tbl_limb)};
+}
+
+int table_fallback(const wv_ctx *c, int id) {
+    if (id < WV_TABLE_COUNT) return id;
+    return c->t_head[id].deg == 3 ? WV_TABLE_BB30 : WV_TABLE_EE33;
+}
+
+int side_slots(const wv_ctx *c, int id) {
+    return std::max({c->t_head[id].n, c->t_head[table_fallback(c, id)].n, 1});
+}
+
+double side_cost(const wv_ctx *c, int id) { return std::max(c->t_cost[id], c->t_cost[table_fallback(c, id)]); }
 
 void pick_tuned(wv_ctx *c, uint64_t pmax) {
     if (c->shape_forced || pmax < 2) return;
@@ -432,7 +559,7 @@ int wv_create(int hip_device, wv_ctx **out) {
             if (sum_variant_occupancy(v, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
             c->sum_blocks[v] = c->num_cus * per_cu;
         }
-        if (upload_tables() != hipSuccess) { rc = WV_EHIP; break; }
+        if ((rc = tables_init(c)) != WV_OK) break;
         if ((rc = ensure(c, c->base_primes, kBaseLimit / 2 * sizeof(uint32_t))) != WV_OK) break;
         if ((rc = ensure(c, c->scal, 8 * sizeof(uint64_t))) != WV_OK) break;
         if (launch_base_sieve(c->stream, as<uint32_t>(c->base_primes), as<uint32_t>(c->scal)) != hipSuccess) {
@@ -460,7 +587,8 @@ int wv_destroy(wv_ctx *c) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     DevBuf *bufs[] = {&c->base_primes, &c->primes, &c->pr, &c->segs, &c->terms, &c->cnt, &c->off, &c->tiles,
                       &c->scal, &c->partials, &c->seg_pairs, &c->results, &c->seg_counts, &c->seg_bits,
-                      &c->seg_off, &c->seg_desc, &c->pad_primes};
+                      &c->seg_off, &c->seg_desc, &c->pad_primes, &c->stats_hist, &c->stats_near, &c->coefs,
+                      &c->lhsmod, &c->tbl_head, &c->tbl_term, &c->tbl_limb};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (int i = 0; i < EV_COUNT; i++)
@@ -470,10 +598,39 @@ int wv_destroy(wv_ctx *c) {
     return WV_OK;
 }
 
+int wv_define_table(wv_ctx *c, int deg, const char *lhs, size_t n, const char *const *coef, const uint64_t *xa,
+                    const uint64_t *xb, const uint64_t *ya, const uint64_t *yb, uint64_t min_p, int *id) {
+    if (!c || !id || (deg != 2 && deg != 3) || n == 0 || n > kMaxTableTerms || !coef || !xa || !xb || !ya || !yb)
+        return WV_EINVAL;
+    if (min_p < 11 || min_p > WV_P_MAX) return WV_EINVAL;
+    if ((int)c->t_head.size() >= WV_TABLE_COUNT + kMaxDefinedTables) return WV_EINVAL;
+    std::vector<uint32_t> lmag;
+    bool lneg = false;
+    if (!parse_int(lhs, &lmag, &lneg) || lmag.empty() || lmag.size() > 0xFFFF) return WV_EINVAL;
+    std::vector<std::vector<uint32_t>> mag(n);
+    std::vector<bool> neg(n);
+    for (size_t i = 0; i < n; i++) {
+        bool ng = false;
+        if (!parse_int(coef[i], &mag[i], &ng) || mag[i].size() > 0xFFFF) return WV_EINVAL;
+        neg[i] = ng;
+        // 0 <= x < y <= 1, denominators below 2^63
+        if (xb[i] == 0 || yb[i] == 0 || xb[i] >> 63 || yb[i] >> 63) return WV_EINVAL;
+        if (xa[i] > xb[i] || ya[i] > yb[i]) return WV_EINVAL;
+        if ((unsigned __int128)xa[i] * yb[i] >= (unsigned __int128)ya[i] * xb[i]) return WV_EINVAL;
+    }
+    WV_TRY(check_device(c));
+    WV_TRY(table_add(c, deg, lmag, lneg, mag, neg, xa, xb, ya, yb, min_p, id));
+    c->gen++;   // captured graphs hold the old table ids' shapes
+    return WV_OK;
+}
+
 int wv_set_tables(wv_ctx *c, int b_table, int e_table) {
     if (!c) return WV_EINVAL;
-    if (b_table < WV_TABLE_BB1 || b_table > WV_TABLE_BB30) return WV_EINVAL;
-    if (e_table < WV_TABLE_EE3 || e_table > WV_TABLE_EE33) return WV_EINVAL;
+    const int nt = (int)c->t_head.size();
+    if (b_table < 0 || b_table >= nt || e_table < 0 || e_table >= nt) return WV_EINVAL;
+    if (c->t_head[b_table].deg != 3 || c->t_head[e_table].deg != 2) return WV_EINVAL;
+    // the root forms eqnV12 / eqnE1 serve p = 5, 7 only
+    if (b_table == WV_TABLE_V12 || e_table == WV_TABLE_E1) return WV_EINVAL;
     c->tb = b_table;
     c->te = e_table;
     return WV_OK;

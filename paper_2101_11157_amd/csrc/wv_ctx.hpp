@@ -96,7 +96,14 @@ struct wv_ctx {
     uint32_t n_base = 0;
     uint64_t gen = 0;                             // bumped on every device reallocation
     wv::DevBuf base_primes, primes, pr, segs, terms, cnt, off, tiles, scal, partials, seg_pairs, results,
-        seg_counts, seg_bits, seg_off, seg_desc, pad_primes, stats_hist, stats_near;
+        seg_counts, seg_bits, seg_off, seg_desc, pad_primes, stats_hist, stats_near, coefs, lhsmod, tbl_head,
+        tbl_term, tbl_limb;
+    // congruence registry: the compiled tables (ids < WV_TABLE_COUNT), then
+    // those defined at run time; device copy in tbl_* (TableStore)
+    std::vector<wv::TableHead> t_head;
+    std::vector<wv::TableTerm> t_term;
+    std::vector<uint32_t> t_limb;
+    std::vector<double> t_cost;
     wv_stats stats{};
     wv_progress_fn progress = nullptr;
     void *progress_user = nullptr;
@@ -109,6 +116,22 @@ namespace wv {
 
 // lanes of the persistent term-sum grid of the current block shape
 inline uint64_t sum_lanes(const wv_ctx *c) { return (uint64_t)c->sum_blocks[c->variant] * 256; }
+
+constexpr int kMaxDefinedTables = 64;
+constexpr size_t kMaxTableTerms = 1 << 16;
+
+// table registry (wv_capi.hip)
+int tables_init(wv_ctx *c);
+int table_add(wv_ctx *c, int deg, const std::vector<uint32_t> &lhs_mag, bool lhs_neg,
+              const std::vector<std::vector<uint32_t>> &coef_mag, const std::vector<bool> &coef_neg,
+              const uint64_t *xa, const uint64_t *xb, const uint64_t *ya, const uint64_t *yb, uint64_t min_p,
+              int *id);
+TableStore table_store(wv_ctx *c);
+// the table used where `id` does not apply (p < min_p or p | lhs)
+int table_fallback(const wv_ctx *c, int id);
+// slots and cost per p of a side that uses `id` (fallback included)
+int side_slots(const wv_ctx *c, int id);
+double side_cost(const wv_ctx *c, int id);
 
 int ensure(wv_ctx *c, DevBuf &b, size_t bytes);
 bool is_prime_u64(uint64_t n);

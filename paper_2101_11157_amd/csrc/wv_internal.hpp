@@ -56,10 +56,34 @@ struct Pair {
     uint64_t c0, c1;
 };
 
+// A congruence  lhs * X_{p-3} == sum_i coef_i S(x_i, y_i)  (mod p) in device
+// memory (compiled tables and tables defined at run time alike).  Integers of
+// any size are little-endian base-2^32 limbs of the magnitude plus a sign.
+struct TableTerm {      // 40 bytes
+    uint64_t xa, xb, ya, yb;   // x = xa/xb < y = ya/yb
+    uint32_t limb_off;         // coefficient magnitude: limbs[limb_off .. limb_off + nlimb)
+    uint16_t nlimb;
+    int16_t neg;
+};
+
+struct TableHead {      // 32 bytes
+    int32_t deg, n;            // 3: s^-3 (B), 2: s^-2 (E); number of sums
+    uint32_t term_off, lhs_off;
+    uint16_t lhs_nlimb;
+    int16_t lhs_neg;
+    uint32_t pad;
+    uint64_t min_p;            // used for p >= min_p (and p not dividing lhs)
+};
+
+struct TableStore {
+    const TableHead *head;
+    const TableTerm *term;
+    const uint32_t *limb;
+};
+
 // ---- launchers (wv_kernels.hip) ---------------------------------------------
 // Every launcher enqueues on `st` and returns hipGetLastError().
 
-hipError_t upload_tables();
 hipError_t launch_base_sieve(hipStream_t st, uint32_t *out, uint32_t *n_out);
 hipError_t launch_seg_sieve(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bp, uint32_t n_bp,
                             uint32_t *bits_out, uint32_t *counts);
@@ -68,8 +92,14 @@ hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, 
 // exclusive scan of n values into out[0..n], out[n] = total; tiles holds
 // ceil(n / kScanTile) entries
 hipError_t launch_scan(hipStream_t st, const uint64_t *in, uint64_t n, uint64_t *out, uint64_t *tiles);
-hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int tb, int te, int nB, int nE,
-                       PrimeRec *pr, SegRec *segs, uint64_t *terms, uint32_t prime_base);
+// Plan of a batch of n primes with tables tb / te (per prime: fb / fe where
+// p < min_p or p divides the table's lhs; the compiled root forms for p = 5, 7):
+// PrimeRec, SegRec and term count per (prime, sum) slot, each slot's
+// coefficient mod p (coefs, same layout as segs) and each prime's two lhs
+// residues (lhsmod[2i], lhsmod[2i + 1]).
+hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int tb, int te, int fb, int fe, int nB,
+                       int nE, TableStore ts, PrimeRec *pr, SegRec *segs, uint64_t *terms, uint64_t *coefs,
+                       uint64_t *lhsmod, uint32_t prime_base);
 hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg, uint64_t lanes,
                              uint64_t cap, uint64_t *chunk_out);
 hipError_t launch_chunk_count(hipStream_t st, const uint64_t *terms, uint64_t nseg, const uint64_t *chunk,
@@ -87,8 +117,8 @@ hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, 
                       uint64_t end);
 hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
                          const Pair *partials, Pair *seg_pairs);
-hipError_t launch_finalize(hipStream_t st, const PrimeRec *pr, const Pair *sp, uint32_t n, int nB, int nE,
-                           wv_result *out);
+hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *sp, const uint64_t *coefs,
+                           const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out);
 hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec *pr, const Pair *sp, uint64_t nseg,
                              uint64_t *out);
 // acc[target[t]] <- acc[target[t]] (x) tp[t] (eqnCombinePairs), t < ntask
@@ -104,7 +134,6 @@ hipError_t launch_copy_results(hipStream_t st, const wv_result *src, uint64_t n,
 hipError_t launch_stats(hipStream_t st, const wv_result *res, uint32_t n, uint32_t bins, uint64_t bound,
                         unsigned long long *hist, wv_near *near, unsigned long long *near_n);
 
-// table sizes (host copy of the compiled tables)
-int table_slots(int id);
+
 
 }  // namespace wv

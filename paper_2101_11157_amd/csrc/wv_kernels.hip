@@ -28,27 +28,12 @@
 #include "mont.hpp"
 #include "sum_core.hpp"
 #include "wv_internal.hpp"
-#include "wv_tables.hpp"
 
 namespace wv {
 
 // --------------------------------------------------------------------------
 // constants and records
 // --------------------------------------------------------------------------
-
-constexpr int kTotalTerms = 256;               // all tables' terms together
-
-struct DevTerm {
-    int64_t coef;
-    uint32_t xa, xb, ya, yb;
-};
-struct DevTable {
-    int32_t deg, n, off, pad;
-    int64_t lhs;
-};
-
-__constant__ DevTerm c_terms[kTotalTerms];
-__constant__ DevTable c_tables[WV_TABLE_COUNT];
 
 __device__ __forceinline__ Mont mont_of(const PrimeRec &r) {
     Mont m;
@@ -309,28 +294,39 @@ __global__ void __launch_bounds__(256) k_scan_add(uint64_t *__restrict__ out, ui
 // plan
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ uint64_t smod_dev(int64_t a, uint64_t p) {
-    int64_t r = a % (int64_t)p;
-    return (uint64_t)(r < 0 ? r + (int64_t)p : r);
+// A signed integer of any size (limbs of its magnitude, base 2^32, least
+// significant first) mod p, canonical.
+__device__ uint64_t limbs_mod(const uint32_t *__restrict__ limb, uint32_t off, int nlimb, bool neg, uint64_t p) {
+    uint64_t r = 0;
+    for (int k = nlimb - 1; k >= 0; k--) r = (uint64_t)((((unsigned __int128)r << 32) | limb[off + k]) % p);
+    return neg && r ? p - r : r;
 }
 
-// One thread per prime.  Slot layout: B sums of prime i at i*nB + j, E sums at
-// n*nB + i*nE + j (all Bernoulli work first, then all Euler work).
-// pr, segs and terms point at the batch's first entries; `prime_base` is added
-// to the prime index stored in each SegRec (the batch's offset in a larger
-// prime array, as in the request server's pool).
-__global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ primes, uint32_t n, int tb_cfg,
-                                              int te_cfg, int nB, int nE, PrimeRec *__restrict__ pr,
-                                              SegRec *__restrict__ segs, uint64_t *__restrict__ terms,
-                                              uint32_t prime_base) {
+// Table of one side for prime p: the configured one where it applies, else
+// the fallback; the root forms for p = 5 and 7 (readings of the paper: the
+// specialised tables need p >= 11).
+__device__ int pick_table(TableStore ts, int side, uint64_t p, int cfg, int fb) {
+    if (side == 0 && p == 5) return WV_TABLE_BB1;
+    if (side == 0 && p == 7) return WV_TABLE_V12;
+    if (side == 1 && p < 11) return WV_TABLE_E1;
+    const TableHead h = ts.head[cfg];
+    if (p < h.min_p || limbs_mod(ts.limb, h.lhs_off, h.lhs_nlimb, false, p) == 0) return fb;
+    return cfg;
+}
+
+// One thread per prime: PrimeRec, the table of each side and the residues of
+// their left sides.
+__global__ void __launch_bounds__(256) k_plan_primes(const uint64_t *__restrict__ primes, uint32_t n, int tb_cfg,
+                                                     int te_cfg, int fb, int fe, TableStore ts,
+                                                     PrimeRec *__restrict__ pr, uint64_t *__restrict__ lhsmod) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t p = primes[i];
     const bool ok = p >= 5 && p < WV_P_MAX && (p & 1);
     PrimeRec r;
     r.p = ok ? p : 11;   // keep the arithmetic defined for rejected inputs
-    r.tb = (uint8_t)(p == 5 ? WV_TABLE_BB1 : p == 7 ? WV_TABLE_V12 : tb_cfg);
-    r.te = (uint8_t)(p < 11 ? WV_TABLE_E1 : te_cfg);
+    r.tb = (uint8_t)pick_table(ts, 0, r.p, tb_cfg, fb);
+    r.te = (uint8_t)pick_table(ts, 1, r.p, te_cfg, fe);
     Mont m = make_mont(r.p);
     r.ninv = m.ninv;
     r.one = r_mod(r.p);
@@ -339,27 +335,49 @@ __global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ prime
     r.pad = 0;
     pr[i] = r;
     for (int side = 0; side < 2; side++) {
-        const DevTable t = c_tables[side == 0 ? r.tb : r.te];
-        const int nslots = side == 0 ? nB : nE;
-        for (int j = 0; j < nslots; j++) {
-            const size_t slot = side == 0 ? (size_t)i * nB + j : (size_t)n * nB + (size_t)i * nE + j;
-            SegRec s;
-            s.prime = prime_base + i;
-            s.deg = (uint32_t)t.deg;
-            s.lo = 1;
-            s.len = 0;
-            if (ok && j < t.n) {
-                const DevTerm d = c_terms[t.off + j];
-                // open interval (xa/xb) p < s < (ya/yb) p
-                const uint64_t lo = (d.xa * p) / d.xb + 1;
-                const uint64_t hi = (d.ya * p - 1) / d.yb;
-                s.lo = lo;
-                s.len = hi >= lo ? hi - lo + 1 : 0;
-            }
-            segs[slot] = s;
-            terms[slot] = s.len;
-        }
+        const TableHead h = ts.head[side == 0 ? r.tb : r.te];
+        lhsmod[2 * (size_t)i + side] = limbs_mod(ts.limb, h.lhs_off, h.lhs_nlimb, h.lhs_neg != 0, r.p);
     }
+}
+
+// One thread per (prime, sum) slot.  Slot layout: B sums of prime i at
+// i*nB + j, E sums at n*nB + i*nE + j (all Bernoulli work first, then all Euler
+// work).  pr, segs, terms and coefs point at the batch's first entries;
+// `prime_base` is added to the prime index stored in each SegRec (the batch's
+// offset in a larger prime array, as in the request server's pool).  Open
+// interval (xa/xb) p < s < (ya/yb) p, in 128-bit products (eqnDefnS).
+__global__ void __launch_bounds__(256) k_plan_slots(uint32_t n, int nB, int nE, TableStore ts,
+                                                    const PrimeRec *__restrict__ pr, SegRec *__restrict__ segs,
+                                                    uint64_t *__restrict__ terms, uint64_t *__restrict__ coefs,
+                                                    uint32_t prime_base) {
+    const uint64_t slot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nb_slots = (uint64_t)n * nB;
+    if (slot >= nb_slots + (uint64_t)n * nE) return;
+    const int side = slot < nb_slots ? 0 : 1;
+    const uint64_t k = side == 0 ? slot : slot - nb_slots;
+    const int per = side == 0 ? nB : nE;
+    const uint32_t i = (uint32_t)(k / per);
+    const int j = (int)(k % per);
+    const PrimeRec r = pr[i];
+    const TableHead h = ts.head[side == 0 ? r.tb : r.te];
+    SegRec s;
+    s.prime = prime_base + i;
+    s.deg = (uint32_t)h.deg;
+    s.lo = 1;
+    s.len = 0;
+    uint64_t c = 0;
+    if (r.ok && j < h.n) {
+        const TableTerm d = ts.term[h.term_off + j];
+        const uint64_t p = r.p;
+        const uint64_t lo = (uint64_t)((unsigned __int128)d.xa * p / d.xb) + 1;
+        const uint64_t hi = (uint64_t)(((unsigned __int128)d.ya * p - 1) / d.yb);
+        s.lo = lo;
+        s.len = hi >= lo ? hi - lo + 1 : 0;
+        c = limbs_mod(ts.limb, d.limb_off, d.nlimb, d.neg != 0, p);
+    }
+    segs[slot] = s;
+    terms[slot] = s.len;
+    coefs[slot] = c;
 }
 
 __global__ void k_set_u64(uint64_t *p, int n, uint64_t v) {
@@ -530,20 +548,21 @@ __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs,
     if (lane == 0) seg_pairs[j] = Pair{c0, c1};
 }
 
-// L^-1 sum_i coef_i c1_i / c0_i mod p for one congruence; pairs at
-// seg_pairs[first + j].  Running fraction N/D in Montgomery values.
-__device__ uint64_t combine_residue(const DevTable &t, const Pair *__restrict__ sp, size_t first, const Mont &m,
-                                    uint64_t r2, uint64_t one) {
+// L^-1 sum_i coef_i c1_i / c0_i mod p for one congruence of n sums; pairs at
+// sp[first + j], coefficients mod p at coef[first + j], L mod p in lhs.
+// Running fraction N/D in Montgomery values.
+__device__ uint64_t combine_residue(int n, const Pair *__restrict__ sp, const uint64_t *__restrict__ coef,
+                                    size_t first, uint64_t lhs, const Mont &m, uint64_t r2, uint64_t one) {
     const uint64_t p = m.p;
     uint64_t N = 0, D = one;
-    for (int j = 0; j < t.n; j++) {
+    for (int j = 0; j < n; j++) {
         const Pair q = sp[first + j];
-        const uint64_t cR = to_mont(smod_dev(c_terms[t.off + j].coef, p), r2, m);
+        const uint64_t cR = to_mont(coef[first + j], r2, m);
         const uint64_t num = mmul(mmul(cR, q.c1, m), D, m);       // coef c1 D / R
         N = mmul(N, q.c0, m) + num;                                 // (N c0 + coef c1 D) / R
         D = mmul(D, q.c0, m);                                       // D c0 / R
     }
-    const uint64_t LR = to_mont(smod_dev(t.lhs, p), r2, m);
+    const uint64_t LR = to_mont(lhs, r2, m);
     const uint64_t X = mmul(D, LR, m);                              // D L
     const uint64_t XR = mmul(X, r2, m);                             // D L R
     const uint64_t inv = mpow(XR, p - 2, one, m);                   // (D L)^-1 R
@@ -581,8 +600,10 @@ __global__ void __launch_bounds__(256) k_sum_values(const SegRec *__restrict__ s
     out[j] = P.ok ? red1(mmul(q.c1, inv, m), P.p) : 0;
 }
 
-__global__ void __launch_bounds__(256) k_finalize(const PrimeRec *__restrict__ pr, const Pair *__restrict__ sp,
-                                                  uint32_t n, int nB, int nE, wv_result *__restrict__ out) {
+__global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec *__restrict__ pr,
+                                                  const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
+                                                  const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
+                                                  wv_result *__restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const PrimeRec P = pr[i];
@@ -598,8 +619,9 @@ __global__ void __launch_bounds__(256) k_finalize(const PrimeRec *__restrict__ p
     }
     const Mont m = mont_of(P);
     r.p = P.p;
-    r.b = combine_residue(c_tables[P.tb], sp, (size_t)i * nB, m, P.r2, P.one);
-    r.e = combine_residue(c_tables[P.te], sp, (size_t)n * nB + (size_t)i * nE, m, P.r2, P.one);
+    r.b = combine_residue(ts.head[P.tb].n, sp, coefs, (size_t)i * nB, lhsmod[2 * (size_t)i], m, P.r2, P.one);
+    r.e = combine_residue(ts.head[P.te].n, sp, coefs, (size_t)n * nB + (size_t)i * nE, lhsmod[2 * (size_t)i + 1], m,
+                          P.r2, P.one);
     r.flags = (r.b == 0 ? WV_FLAG_WOLSTENHOLME : 0u) | (r.e == 0 ? WV_FLAG_VANDIVER : 0u);
     out[i] = r;
 }
@@ -608,29 +630,6 @@ __global__ void __launch_bounds__(256) k_finalize(const PrimeRec *__restrict__ p
 // ==========================================================================
 // launchers
 // ==========================================================================
-
-int table_slots(int id) { return kTables[id].n; }
-
-hipError_t upload_tables() {
-    DevTerm terms[kTotalTerms];
-    DevTable tabs[WV_TABLE_COUNT];
-    int off = 0;
-    for (int i = 0; i < kNumTables; i++) {
-        tabs[i].deg = kTables[i].deg;
-        tabs[i].n = kTables[i].n;
-        tabs[i].off = off;
-        tabs[i].pad = 0;
-        tabs[i].lhs = kTables[i].lhs;
-        for (int j = 0; j < kTables[i].n; j++) {
-            const TermDef &t = kTables[i].t[j];
-            terms[off + j] = DevTerm{t.coef, t.xa, t.xb, t.ya, t.yb};
-        }
-        off += kTables[i].n;
-    }
-    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_terms), terms, sizeof(DevTerm) * off);
-    if (e != hipSuccess) return e;
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_tables), tabs, sizeof(tabs));
-}
 
 static unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per + (n == 0)); }
 
@@ -659,10 +658,14 @@ hipError_t launch_scan(hipStream_t st, const uint64_t *in, uint64_t n, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int tb, int te, int nB, int nE,
-                       PrimeRec *pr, SegRec *segs, uint64_t *terms, uint32_t prime_base) {
-    hipLaunchKernelGGL(k_plan, dim3(blocks_for(n, 256)), dim3(256), 0, st, primes, n, tb, te, nB, nE, pr, segs,
-                       terms, prime_base);
+hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int tb, int te, int fb, int fe, int nB,
+                       int nE, TableStore ts, PrimeRec *pr, SegRec *segs, uint64_t *terms, uint64_t *coefs,
+                       uint64_t *lhsmod, uint32_t prime_base) {
+    hipLaunchKernelGGL(k_plan_primes, dim3(blocks_for(n, 256)), dim3(256), 0, st, primes, n, tb, te, fb, fe, ts, pr,
+                       lhsmod);
+    const uint64_t nseg = (uint64_t)n * (nB + nE);
+    hipLaunchKernelGGL(k_plan_slots, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, n, nB, nE, ts, pr, segs, terms,
+                       coefs, prime_base);
     return hipGetLastError();
 }
 
@@ -711,9 +714,10 @@ hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t st, const PrimeRec *pr, const Pair *sp, uint32_t n, int nB, int nE,
-                           wv_result *out) {
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, pr, sp, n, nB, nE, out);
+hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *sp, const uint64_t *coefs,
+                           const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out) {
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, ts, pr, sp, coefs, lhsmod, n, nB, nE,
+                       out);
     return hipGetLastError();
 }
 

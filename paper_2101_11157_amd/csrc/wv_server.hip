@@ -62,7 +62,7 @@ struct wv_server {
     uint32_t pool = 1u << 16;
     int tb = 0, te = 0;        // congruences fixed at creation (the pool layout depends on them)
     int nB = 0, nE = 0, NS = 0;
-    DevBuf pr, segs, acc, terms, tmp, tasks, target, toff, tpairs, partials, res, scal;
+    DevBuf pr, segs, acc, terms, tmp, tasks, target, toff, tpairs, partials, res, scal, coefs, lhsmod;
     std::vector<std::pair<uint32_t, uint32_t>> free_ranges;   // (first slot, count), sorted
     std::deque<Request *> pending;
     std::vector<Request *> active;
@@ -105,8 +105,11 @@ void pool_free(wv_server *s, uint32_t base, uint32_t n) {
 int finish_request(wv_server *s, Request *r) {
     wv_ctx *c = s->c;
     if (r->n) {
-        WV_HIP(launch_finalize(c->stream, as<PrimeRec>(s->pr) + r->base, as<Pair>(s->acc) + (size_t)r->base * s->NS,
-                               r->n, s->nB, s->nE, as<wv_result>(s->res)));
+        WV_HIP(launch_finalize(c->stream, table_store(c), as<PrimeRec>(s->pr) + r->base,
+                               as<Pair>(s->acc) + (size_t)r->base * s->NS,
+                               as<uint64_t>(s->coefs) + (size_t)r->base * s->NS,
+                               as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->n, s->nB, s->nE,
+                               as<wv_result>(s->res)));
         r->results.resize(r->n);
         WV_HIP(hipMemcpyAsync(r->results.data(), s->res.ptr, r->n * sizeof(wv_result), hipMemcpyDeviceToHost,
                               c->stream));
@@ -163,8 +166,10 @@ int admit(wv_server *s, Request *r, bool *admitted) {
     *admitted = true;
     if (n == 0) return finish_request(s, r);
     const size_t first = (size_t)r->base * s->NS, nseg = (size_t)n * s->NS;
-    WV_HIP(launch_plan(c->stream, d_primes, (uint32_t)n, s->tb, s->te, s->nB, s->nE, as<PrimeRec>(s->pr) + r->base,
-                       as<SegRec>(s->segs) + first, as<uint64_t>(s->terms) + first, r->base));
+    WV_HIP(launch_plan(c->stream, d_primes, (uint32_t)n, s->tb, s->te, table_fallback(c, s->tb),
+                       table_fallback(c, s->te), s->nB, s->nE, table_store(c), as<PrimeRec>(s->pr) + r->base,
+                       as<SegRec>(s->segs) + first, as<uint64_t>(s->terms) + first, as<uint64_t>(s->coefs) + first,
+                       as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->base));
     WV_HIP(launch_fill_pairs(c->stream, as<Pair>(s->acc) + first, nseg, 1, 0));
     std::vector<SegRec> recs(nseg);
     WV_HIP(hipMemcpyAsync(recs.data(), as<SegRec>(s->segs) + first, nseg * sizeof(SegRec), hipMemcpyDeviceToHost,
@@ -336,8 +341,8 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
     if (cfg && cfg->max_primes) s->pool = cfg->max_primes;
     s->tb = c->tb;
     s->te = c->te;
-    s->nB = std::max(table_slots(c->tb), 1);
-    s->nE = std::max(table_slots(c->te), 1);
+    s->nB = side_slots(c, c->tb);
+    s->nE = side_slots(c, c->te);
     s->NS = s->nB + s->nE;
     const size_t nseg = (size_t)s->pool * s->NS;
     int rc = WV_OK;
@@ -345,6 +350,8 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
         (rc = ensure(c, s->segs, nseg * sizeof(SegRec))) != WV_OK ||
         (rc = ensure(c, s->acc, nseg * sizeof(Pair))) != WV_OK ||
         (rc = ensure(c, s->terms, nseg * sizeof(uint64_t))) != WV_OK ||
+        (rc = ensure(c, s->coefs, nseg * sizeof(uint64_t))) != WV_OK ||
+        (rc = ensure(c, s->lhsmod, 2 * (size_t)s->pool * sizeof(uint64_t))) != WV_OK ||
         (rc = ensure(c, s->res, s->pool * sizeof(wv_result))) != WV_OK ||
         (rc = ensure(c, s->scal, 8 * sizeof(uint64_t))) != WV_OK) {
         wv_server_destroy(s);
@@ -365,7 +372,7 @@ int wv_server_destroy(wv_server *s) {
     if (!s) return WV_OK;
     if (s->c) (void)hipStreamSynchronize(s->c->stream);
     DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->tmp, &s->tasks, &s->target, &s->toff,
-                      &s->tpairs, &s->partials, &s->res, &s->scal};
+                      &s->tpairs, &s->partials, &s->res, &s->scal, &s->coefs, &s->lhsmod};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &kv : s->all) delete kv.second;

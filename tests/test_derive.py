@@ -156,3 +156,28 @@ def test_json_round_trip():
     _, best, _ = D.greedy(D.Congruence.start("EMac2"), D=8, rounds=6)
     again = D.load_json(best.to_json("t"))
     assert again.integer_form() == best.integer_form() and again.cost() == best.cost()
+
+
+@pytest.mark.parametrize("side", ["B", "E"])
+def test_shipped_derived_tables(side):
+    """The congruences the package ships (tables/make_tables.py) are valid:
+    the oracle evaluates them plainly and gets the recurrence residues for all
+    11 <= p < 600 and the root forms' residues near 1e6.  The Euler one is the
+    paper's 100-round greedy search from eqnEMac2: 438 sums, cost below p/30.4
+    (end of Section 4)."""
+    import paper_2101_11157_amd as wv
+    obj = wv.derived_table(side)
+    cong = D.load_json(obj)
+    assert cong.n_sums() == obj["n"] and cong.cost() == Q(*obj["cost"])
+    if side == "E":
+        assert obj["n"] == 438 and cong.cost() < 1 / Q(304, 10)
+    else:
+        assert cong.cost() < C.BB30.cost and obj["n"] > 300
+    oc = _as_oracle_congruence(cong, f"shipped-{side}")
+    ps = [p for p in oracle.primes(11, 600) if oc.lhs % p]
+    got = [oracle.congruence_residue_exact(p, oc) for p in ps]
+    want = [oracle.bernoulli_rec(p) if side == "B" else oracle.euler_rec(p) for p in ps]
+    assert got == want
+    big = oracle.primes(10 ** 6, 10 ** 6 + 200)[:6]
+    root = C.SV if side == "B" else C.E1
+    assert [oracle.congruence_residue_exact(p, oc) for p in big] == oracle.congruence_residues(big, root)

@@ -703,3 +703,96 @@ def test_range_stats_edges(ctx):
             ctx.range_stats(5, 100, bins=bins)
     with pytest.raises(wv.WvError):
         ctx.range_stats(2 ** 40 - 10, 2 ** 40 + 10)
+
+
+# ---------------------------------------------------------------------------
+# congruences defined at run time (derivation engine, Section 2)
+# ---------------------------------------------------------------------------
+
+def _derived(start, rounds):
+    from paper_2101_11157_amd import derive
+    _, best, _ = derive.greedy(derive.Congruence.start(start), D=8, rounds=rounds)
+    return best.to_json(f"{start}-{rounds}")
+
+
+def test_defined_tables_all_small_primes():
+    """Greedy-derived Bernoulli and Euler congruences, used from p = 11 on, give
+    the residues of the printed tables (oracle-pinned above) for every prime
+    below 3000, and the oracle's plain evaluation of the same congruences."""
+    from oracle import congruences as C
+    from paper_2101_11157_amd import derive
+    say("case: derived tables from 11")
+    jb, je = _derived("Vandiver", 20), _derived("EMac2", 20)
+    ps = oracle.primes(5, 3000)
+    with wv.Context(0) as c:
+        ref = c.eval_primes(ps)
+        b = c.define_derived_table(jb, min_p=11)
+        e = c.define_derived_table(je, min_p=11)
+        c.set_tables(b, e)
+        got = c.eval_primes(ps)
+        res, _ = c.search_range(5, 3000)
+    assert as_pairs(got) == as_pairs(ref) == as_pairs(res)
+    cb = derive.load_json(jb)
+    L, terms = cb.integer_form()
+    ob = C.Congruence("derived", "B", -3, L, terms, cb.cost(), "derived")
+    pick = [p for p in ps if p > 1000][:20]
+    assert [oracle.congruence_residue_exact(p, ob) for p in pick] == [int(r["b"]) for r in got if int(r["p"]) in pick]
+
+
+def test_package_derived_tables_at_scale(ctx):
+    """The shipped derived congruences (hundreds of sums each) reproduce the
+    oracle samples at 1e9 and 1e11 and Tables 2-3."""
+    say("case: package derived tables")
+    g9 = golden_json("window_1e9.json")["rows"][:40]
+    g11 = golden_json("window_1e11.json")["rows"]
+    tb = [(int(p), int(r)) for p, r in read_golden("near_miss_B.txt")][:6]
+    te = [(int(p), int(r)) for p, r in read_golden("near_miss_E.txt")][:6]
+    with wv.Context(0) as c:
+        b, e = c.use_derived_tables(min_p=11)
+        jb, je = wv.derived_table("B"), wv.derived_table("E")
+        assert jb["n"] > 300 and je["n"] > 300
+        got = c.eval_primes([r["p"] for r in g9 + g11])
+        assert as_pairs(got) == [(r["b"], r["e"]) for r in g9 + g11]
+        st = c.stats()
+        assert st["n_sums"] == len(got) * (jb["n"] + je["n"])
+        got = c.eval_primes([p for p, _ in tb] + [p for p, _ in te])
+    sym = [(exact.symmetric(int(r["b"]), int(r["p"])), exact.symmetric(int(r["e"]), int(r["p"]))) for r in got]
+    assert [s[0] for s in sym[:len(tb)]] == [r for _, r in tb]
+    assert [s[1] for s in sym[len(tb):]] == [r for _, r in te]
+
+
+def test_defined_table_fallbacks():
+    """Primes below min_p, and primes dividing the left side (a valid table
+    scaled by 13), take the printed tables; results do not change."""
+    say("case: defined-table fallbacks")
+    jb = _derived("Vandiver", 8)
+    scaled = dict(jb, lhs=str(13 * int(jb["lhs"])), terms=[[str(13 * int(t[0]))] + t[1:] for t in jb["terms"]])
+    ps = oracle.primes(5, 400) + oracle.primes(10 ** 6, 10 ** 6 + 300)
+    with wv.Context(0) as c:
+        ref = c.eval_primes(ps)
+        hi = c.define_derived_table(jb, min_p=10 ** 6)
+        c.set_tables(hi, "EE33")
+        assert as_pairs(c.eval_primes(ps)) == as_pairs(ref)
+        s13 = c.define_derived_table(scaled, min_p=11)
+        c.set_tables(s13, "EE33")
+        assert as_pairs(c.eval_primes(ps)) == as_pairs(ref)
+
+
+def test_define_table_rejects_malformed_input(ctx):
+    say("case: define_table errors")
+    from fractions import Fraction as F
+    good = [(1, F(1, 6), F(1, 5))]
+    bad = [
+        dict(deg=4, lhs=14, terms=good),
+        dict(deg=3, lhs=0, terms=good),
+        dict(deg=3, lhs=14, terms=[]),
+        dict(deg=3, lhs=14, terms=[(1, F(1, 5), F(1, 6))]),          # x >= y
+        dict(deg=3, lhs=14, terms=[(1, F(1, 5), F(1, 5))]),
+        dict(deg=3, lhs=14, terms=[(1, F(1, 2), F(3, 2))]),          # y > 1
+        dict(deg=3, lhs=14, terms=good, min_p=7),
+    ]
+    for kw in bad:
+        with pytest.raises(wv.WvError):
+            ctx.define_table(**kw)
+    with pytest.raises(wv.WvError):
+        ctx.set_tables("EE33", "EE33")                               # wrong side
