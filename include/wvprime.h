@@ -245,7 +245,9 @@ int wv_eval_primes(wv_ctx *ctx, const uint64_t *primes, size_t n, wv_result *out
  * value outside that range yields a result with flags = 0xFFFFFFFF.  The
  * caller keeps both buffers alive until the stream has passed this work.
  * Internal buffers of ctx are in use until then: do not issue another call on
- * ctx before synchronising hip_stream. */
+ * ctx before synchronising hip_stream.  One batch: the padded size times the
+ * sums per prime must not exceed 2^27 (WV_EINVAL otherwise; 2^21 primes with
+ * the printed tables). */
 int wv_eval_primes_async(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
                          wv_result *d_out, void *hip_stream);
 
@@ -256,7 +258,8 @@ int wv_eval_primes_async(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
  * sum of primes[i] and out_e[i*ne + j] the j-th Euler sum, canonical in
  * [0, p); nb and ne are the numbers of sums of the configured congruences
  * (wv_table_info), and slots beyond the congruence used for a prime (p = 5, 7
- * use one-sum root forms) hold 0.  Same validation as wv_eval_primes. */
+ * use one-sum root forms) hold 0.  Same validation as wv_eval_primes; one
+ * batch of at most 2^27 (prime, sum) slots (WV_EINVAL beyond). */
 int wv_eval_sums(wv_ctx *ctx, const uint64_t *primes, size_t n, uint64_t *out_b, uint64_t *out_e);
 
 /* ---- request server ---------------------------------------------------

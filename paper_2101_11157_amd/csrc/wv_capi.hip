@@ -98,15 +98,17 @@ int check_device(wv_ctx *c) {
 // ==========================================================================
 
 int batch_shape(const wv_ctx *c, uint32_t n, uint64_t pmax, BatchShape *sh) {
+    sh->tb = batch_table(c, c->tb, pmax);
+    sh->te = batch_table(c, c->te, pmax);
     sh->n = n;
-    sh->nB = side_slots(c, c->tb);
-    sh->nE = side_slots(c, c->te);
+    sh->nB = side_slots(c, sh->tb);
+    sh->nE = side_slots(c, sh->te);
     sh->nseg = (uint64_t)n * (sh->nB + sh->nE);
     // partial pairs: the plan picks chunk >= total_terms / (cap - nseg), so
     // cap > nseg always; with room for total_terms / chunk_cfg + nseg chunks
     // the configured chunk size is kept.  total_terms <= n (pmax cost + sums).
     const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
-    const double cost = side_cost(c, c->tb) + side_cost(c, c->te);
+    const double cost = side_cost(c, sh->tb) + side_cost(c, sh->te);
     const double t_max = (double)n * ((double)pmax * cost + sh->nB + sh->nE);
     // the adaptive chunk grows with T, so T / chunk is largest at the bound
     const double chunk = chunk_cfg ? (double)chunk_cfg
@@ -141,7 +143,7 @@ int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipS
     uint64_t *toff = as<uint64_t>(c->off);   // prefix of terms, then of chunks
     const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
     WV_HIP(launch_set_u64(st, scal, 8, 0));
-    WV_HIP(launch_plan(st, d_primes, sh.n, c->tb, c->te, table_fallback(c, c->tb), table_fallback(c, c->te), sh.nB,
+    WV_HIP(launch_plan(st, d_primes, sh.n, sh.tb, sh.te, table_fallback(c, sh.tb), table_fallback(c, sh.te), sh.nB,
                        sh.nE, table_store(c), as<PrimeRec>(c->pr), as<SegRec>(c->segs), as<uint64_t>(c->terms),
                        as<uint64_t>(c->coefs), as<uint64_t>(c->lhsmod), 0));
     WV_HIP(launch_scan(st, as<uint64_t>(c->terms), sh.nseg, toff, as<uint64_t>(c->tiles)));
@@ -294,12 +296,14 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
         // with the partial pairs capped, a bigger batch would force chunks
         // longer than its sums
         const double cost = side_cost(c, c->tb) + side_cost(c, c->te);
+        const uint64_t per = (uint64_t)side_slots(c, c->tb) + side_slots(c, c->te);
+        const uint64_t max_np = std::min<uint64_t>(kMaxBatchPrimes, kMaxBatchSlots / per);
         size_t j = i;
         uint64_t np = 0;
         double est = 0.0;
         while (j < descs.size() && j - i < kMaxBatchSegs) {
             const double e = (double)counts[j] * (double)std::min(descs[j].hi, descs[j].L + kSegSpan) * cost;
-            if (np > 0 && (np + counts[j] > kMaxBatchPrimes || est + e > kMaxBatchTerms)) break;
+            if (np > 0 && (np + counts[j] > max_np || est + e > kMaxBatchTerms)) break;
             np += counts[j++];
             est += e;
         }
@@ -474,6 +478,10 @@ TableStore table_store(wv_ctx *c) {
 int table_fallback(const wv_ctx *c, int id) {
     if (id < WV_TABLE_COUNT) return id;
     return c->t_head[id].deg == 3 ? WV_TABLE_BB30 : WV_TABLE_EE33;
+}
+
+int batch_table(const wv_ctx *c, int id, uint64_t pmax) {
+    return pmax <= c->t_head[id].min_p ? table_fallback(c, id) : id;
 }
 
 int side_slots(const wv_ctx *c, int id) {
@@ -810,7 +818,13 @@ int wv_eval_primes(wv_ctx *c, const uint64_t *primes, size_t n, wv_result *out) 
     WV_TRY(ensure(c, c->primes, n * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->results, n * sizeof(wv_result)));
     WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
-    WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)n, pmax + 1, as<wv_result>(c->results)));
+    // batches of at most kMaxBatchSlots (prime, sum) slots, in input order
+    const uint64_t per = (uint64_t)side_slots(c, c->tb) + side_slots(c, c->te);
+    const size_t step = (size_t)std::max<uint64_t>(1, kMaxBatchSlots / per);
+    for (size_t b = 0; b < n; b += step) {
+        const size_t k = std::min(step, n - b);
+        WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes) + b, (uint32_t)k, pmax + 1, as<wv_result>(c->results) + b));
+    }
     WV_HIP(hipMemcpyAsync(out, c->results.ptr, n * sizeof(wv_result), hipMemcpyDeviceToHost, c->stream));
     WV_HIP(hipStreamSynchronize(c->stream));
     return WV_OK;
@@ -830,6 +844,7 @@ int wv_eval_sums(wv_ctx *c, const uint64_t *primes, size_t n, uint64_t *out_b, u
     c->stats = wv_stats{};
     BatchShape sh;
     WV_TRY(batch_shape(c, (uint32_t)n, pmax + 1, &sh));
+    if (sh.nseg > kMaxBatchSlots) return WV_EINVAL;   // one batch only
     WV_TRY(ensure(c, c->primes, n * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->results, std::max(n * sizeof(wv_result), (size_t)sh.nseg * sizeof(uint64_t))));
     WV_HIP(hipMemcpyAsync(c->primes.ptr, primes, n * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
@@ -858,6 +873,7 @@ int wv_eval_primes_async(wv_ctx *c, const uint64_t *d_primes, size_t n, wv_resul
     while (n_pad < n) n_pad <<= 1;
     BatchShape sh;
     WV_TRY(batch_shape(c, (uint32_t)n_pad, WV_P_MAX, &sh));   // the primes are not seen on the host
+    if (sh.nseg > kMaxBatchSlots) return WV_EINVAL;            // one captured batch
     WV_TRY(prepare(c, sh));
     WV_TRY(ensure(c, c->pad_primes, n_pad * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->results, n_pad * sizeof(wv_result)));

@@ -46,11 +46,13 @@ constexpr uint64_t kMaxChunks = 1ull << 27;      // partial pairs held at once (
 constexpr uint64_t kMinChunks = 1ull << 16;
 constexpr size_t kMaxBatchSegs = 64;             // sieve segments per search batch (4 MiB of bitmaps)
 constexpr uint64_t kMaxBatchPrimes = 1ull << 19; // primes per search batch
+constexpr uint64_t kMaxBatchSlots = 1ull << 27;  // (prime, sum) slots per batch (~10 GB of plan records)
 constexpr double kMaxBatchTerms = 70368744177664.0;   // 2^46 terms per search batch (~20 s)
 constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
 constexpr int kDefaultVariant = 7;               // block shape 14/20
 
 struct BatchShape {
+    int tb, te;          // tables of the batch (a defined table's fallback when no prime reaches its min_p)
     uint32_t n;          // primes
     int nB, nE;          // slots per prime on each side
     uint64_t nseg;       // (prime, sum) slots
@@ -129,6 +131,8 @@ int table_add(wv_ctx *c, int deg, const std::vector<uint32_t> &lhs_mag, bool lhs
 TableStore table_store(wv_ctx *c);
 // the table used where `id` does not apply (p < min_p or p | lhs)
 int table_fallback(const wv_ctx *c, int id);
+// the table a batch of primes below pmax uses on the side configured with id
+int batch_table(const wv_ctx *c, int id, uint64_t pmax);
 // slots and cost per p of a side that uses `id` (fallback included)
 int side_slots(const wv_ctx *c, int id);
 double side_cost(const wv_ctx *c, int id);

@@ -517,35 +517,39 @@ constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants
 __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
                                                 uint32_t nseg, const PrimeRec *__restrict__ pr,
                                                 const Pair *__restrict__ partials, Pair *__restrict__ seg_pairs) {
-    const uint32_t j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    // wave-stride loop: one launch covers at most 2^32 work-items, fewer than
+    // 64 per sum when there are more than 2^26 sums
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (j >= nseg) return;   // scalar: the whole wave exits together
-    const uint64_t a = off[j], b = off[j + 1];
-    const Mont m = mont_of(pr[segs[j].prime]);
-    uint64_t c0 = 1, c1 = 0;
-    const uint64_t ff = (a + 63) & ~63ull;   // first 64-aligned window start
-    const uint64_t lf = b & ~63ull;          // end of the last full window
-    if (ff >= lf) {
-        for (uint64_t i = a + lane; i < b; i += 64) {
-            const Pair q = partials[i];
-            pair_mul(c0, c1, q.c0, q.c1, m);
+    for (uint32_t jw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; jw < nseg; jw += nwaves) {
+        const uint32_t j = __builtin_amdgcn_readfirstlane(jw);   // scalar: loop exits are wave-uniform
+        const uint64_t a = off[j], b = off[j + 1];
+        const Mont m = mont_of(pr[segs[j].prime]);
+        uint64_t c0 = 1, c1 = 0;
+        const uint64_t ff = (a + 63) & ~63ull;   // first 64-aligned window start
+        const uint64_t lf = b & ~63ull;          // end of the last full window
+        if (ff >= lf) {
+            for (uint64_t i = a + lane; i < b; i += 64) {
+                const Pair q = partials[i];
+                pair_mul(c0, c1, q.c0, q.c1, m);
+            }
+        } else {
+            for (uint64_t i = a + lane; i < ff; i += 64) {
+                const Pair q = partials[i];
+                pair_mul(c0, c1, q.c0, q.c1, m);
+            }
+            for (uint64_t w = ff + 64ull * lane; w < lf; w += 64ull * 64) {
+                const Pair q = partials[w];
+                pair_mul(c0, c1, q.c0, q.c1, m);
+            }
+            for (uint64_t i = lf + lane; i < b; i += 64) {
+                const Pair q = partials[i];
+                pair_mul(c0, c1, q.c0, q.c1, m);
+            }
         }
-    } else {
-        for (uint64_t i = a + lane; i < ff; i += 64) {
-            const Pair q = partials[i];
-            pair_mul(c0, c1, q.c0, q.c1, m);
-        }
-        for (uint64_t w = ff + 64ull * lane; w < lf; w += 64ull * 64) {
-            const Pair q = partials[w];
-            pair_mul(c0, c1, q.c0, q.c1, m);
-        }
-        for (uint64_t i = lf + lane; i < b; i += 64) {
-            const Pair q = partials[i];
-            pair_mul(c0, c1, q.c0, q.c1, m);
-        }
+        wave_pair_reduce(c0, c1, m);
+        if (lane == 0) seg_pairs[j] = Pair{c0, c1};
     }
-    wave_pair_reduce(c0, c1, m);
-    if (lane == 0) seg_pairs[j] = Pair{c0, c1};
 }
 
 // L^-1 sum_i coef_i c1_i / c0_i mod p for one congruence of n sums; pairs at
@@ -633,6 +637,11 @@ __global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec 
 
 static unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per + (n == 0)); }
 
+// A dispatch holds fewer than 2^32 work-items (the packet's grid size is 32
+// bits): launches of one thread per item refuse larger counts instead of
+// running a truncated grid.
+static bool too_many(uint64_t items) { return items >= (1ull << 32) - 256; }
+
 hipError_t launch_base_sieve(hipStream_t st, uint32_t *out, uint32_t *n_out) {
     hipLaunchKernelGGL(k_base_sieve, dim3(1), dim3(1024), 0, st, out, n_out);
     return hipGetLastError();
@@ -651,6 +660,7 @@ hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, 
 }
 
 hipError_t launch_scan(hipStream_t st, const uint64_t *in, uint64_t n, uint64_t *out, uint64_t *tiles) {
+    if (too_many(n)) return hipErrorInvalidConfiguration;
     const uint64_t nt = std::max<uint64_t>(1, (n + kScanTile - 1) / kScanTile);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(256), 0, st, in, n, out, tiles);
     hipLaunchKernelGGL(k_scan_carry, dim3(1), dim3(1024), 0, st, tiles, nt, out + n);
@@ -664,6 +674,7 @@ hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int t
     hipLaunchKernelGGL(k_plan_primes, dim3(blocks_for(n, 256)), dim3(256), 0, st, primes, n, tb, te, fb, fe, ts, pr,
                        lhsmod);
     const uint64_t nseg = (uint64_t)n * (nB + nE);
+    if (too_many(nseg)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_plan_slots, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, n, nB, nE, ts, pr, segs, terms,
                        coefs, prime_base);
     return hipGetLastError();
@@ -677,6 +688,7 @@ hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64
 
 hipError_t launch_chunk_count(hipStream_t st, const uint64_t *terms, uint64_t nseg, const uint64_t *chunk,
                               uint64_t *cnt) {
+    if (too_many(nseg)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_chunk_count, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg, chunk, cnt);
     return hipGetLastError();
 }
@@ -709,8 +721,9 @@ hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, 
 
 hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
                          const Pair *partials, Pair *seg_pairs) {
-    hipLaunchKernelGGL(k_reduce, dim3(blocks_for((uint64_t)nseg * 64, 256)), dim3(256), 0, st, segs, off, nseg, pr,
-                       partials, seg_pairs);
+    // at most 2^20 workgroups (2^28 work-items; a dispatch holds < 2^32)
+    const unsigned grid = std::min<unsigned>(blocks_for((uint64_t)nseg * 64, 256), 1u << 20);
+    hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, partials, seg_pairs);
     return hipGetLastError();
 }
 
@@ -723,6 +736,7 @@ hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, co
 
 hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec *pr, const Pair *sp, uint64_t nseg,
                              uint64_t *out) {
+    if (too_many(nseg)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_sum_values, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, segs, pr, sp, nseg, out);
     return hipGetLastError();
 }
@@ -734,6 +748,7 @@ hipError_t launch_fold(hipStream_t st, const SegRec *tasks, const uint32_t *targ
 }
 
 hipError_t launch_fill_pairs(hipStream_t st, Pair *p, uint64_t n, uint64_t c0, uint64_t c1) {
+    if (too_many(n)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_fill_pairs, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, c0, c1);
     return hipGetLastError();
 }

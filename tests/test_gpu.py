@@ -796,3 +796,38 @@ def test_define_table_rejects_malformed_input(ctx):
             ctx.define_table(**kw)
     with pytest.raises(wv.WvError):
         ctx.set_tables("EE33", "EE33")                               # wrong side
+
+
+def test_batch_over_2_26_slots_with_defined_tables():
+    """A search batch of more than 2^26 (prime, sum) slots (about 1e5 primes
+    with the shipped ~1100-sum congruences used from p = 11): the per-sum
+    reduction indexes slots beyond 2^26 correctly; results equal the printed
+    tables' (a regression test for a 32-bit thread index)."""
+    lo, hi = 10 ** 6, 10 ** 6 + 1_400_000
+    say(f"case: range [{lo}, {hi}) with derived tables from p = 11")
+    with wv.Context(0) as c:
+        ref, _ = c.search_range(lo, hi)
+        c.use_derived_tables(min_p=11)
+        got, _ = c.search_range(lo, hi)
+        st = c.stats()
+    assert st["n_sums"] > (1 << 26)
+    assert [int(p) for p in got["p"]] == [int(p) for p in ref["p"]]
+    assert as_pairs(got) == as_pairs(ref)
+
+
+def test_batched_windows_with_derived_tables(ctx):
+    """Windows on both sides of the derived tables' 2^30 threshold in one
+    batched call equal the same windows searched alone (the printed tables
+    below 2^30, the derived ones above)."""
+    from paper_2101_11157_amd import workloads
+    wins = workloads.batch_windows(0, 12, len_range=(1e2, 3e3), start_range=(1e8, 5e10))
+    say(f"case: {len(wins)} windows, derived tables")
+    with wv.Context(0) as c:
+        c.use_derived_tables()
+        got = c.search_windows([a for a, _ in wins], [b for _, b in wins])
+        for (a, b), res in zip(wins, got):
+            alone, _ = c.search_range(a, b)
+            assert as_pairs(res) == as_pairs(alone)
+        flat = np.concatenate([g for g in got if len(g)])
+    pick = sorted(random.Random(5).sample(range(len(flat)), 4))
+    check_against_oracle(flat[pick], method="table")
