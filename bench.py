@@ -37,8 +37,9 @@ RENORM = 20         # blocks between table reductions
 
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
-# (profiles/k_sum_window_1e11_14_20.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {("1e11", "printed", 14, 20, 8192): 4285157 + 26352736}
+# (profiles/k_sum_window_1e11_14_20*.md); only valid for that kernel and workload.
+MEASURED_TRAFFIC = {("1e11", "printed", 14, 20, 8192): 4285157 + 26352736,
+                    ("1e11", "derived", 14, 20, 8192): 27225872 + 151601184}
 
 
 def ops_per_term(d, k):
