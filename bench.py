@@ -11,10 +11,10 @@ take the sub-windows before the timed ones, so no step repeats work.
 
 Prints one JSON line.  `roofline` describes the term-sum kernel (the dominant
 kernel), which is bound by vector-ALU issue: the full-rate VALU operations its
-algorithm needs per term (ops_per_term below: Montgomery products, 64-bit
-difference-table additions and the periodic table reductions of the blocked
-loop, as written in the source) times the terms it summed, over its own
-HIP-event time, against the chip's VALU issue rate (256 CUs x 4 SIMDs x 16
+algorithm needs per term (ops_per_term below: double-precision modular
+products, difference-table additions and the periodic table reductions of the
+blocked loop, as written in the source) times the terms it summed, over its
+own HIP-event time, against the chip's VALU issue rate (256 CUs x 4 SIMDs x 16
 lanes x 2.4 GHz).  Register moves the compiler adds are not counted.
 `cpu_baseline` is the plain CPU oracle timed on this host on a bounded sample
 of the same workload.
@@ -32,30 +32,31 @@ PAPER_V100_PRIMES_PER_S = 1.0 / (25.3e-3 + 34.1e-3)   # Section 3 and Section 5 
 PEAK_VALU = 256 * 4 * 16 * 2.4e9                        # full-rate VALU lane operations per second
 OPS_MONT = 12       # one Montgomery product: 8 32x32->64 multiply-adds, 2 low multiplies, 2 64-bit adds
 OPS_ADDM = 3        # one modular addition: add, subtract, select
-OPS_REDUCE = 9      # one table reduction: u64->f64 (3), quotient fma, clamp, f64->u32, q(2^64-p) (2), add
-RENORM = 20         # blocks between table reductions
+OPS_FMUL = 6        # one double-precision modular product: mul, 3 fma, 2 add
+OPS_FRED = 3        # one double-precision reduction: fma, add, fma
+RENORM = 10         # blocks between table reductions
 
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
-# (profiles/k_sum_window_1e11_14_20*.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {("1e11", "printed", 14, 20, 8192): 4285157 + 26352736,
-                    ("1e11", "derived", 14, 20, 8192): 27225872 + 151601184}
+# (profiles/k_sum_window_1e11_*.md); only valid for that kernel and workload.
+MEASURED_TRAFFIC = {}
 
 
 def ops_per_term(d, k):
     """Full-rate VALU operations per term of a sum of s^-d with blocks of k terms."""
-    if k == 1:   # one factor per term: two products, one add, d difference steps
+    if k == 1:   # one factor per term (Montgomery): two products, one add, d difference steps
         return 2 * OPS_MONT + 1 + d * OPS_ADDM
     table = d * k + d * (k - 1)   # difference-table entries of P and Q
-    return (3 * OPS_MONT + 1 + table * (1 + OPS_REDUCE / RENORM)) / k
+    return (3 * OPS_FMUL + 1 + table * (1 + OPS_FRED / RENORM)) / k
 
 
 def muls_per_term(d, k):
-    """int32 multiply instructions (v_mad_u64_u32, v_mul_lo_u32) per term: ten
-    per Montgomery product, two per table-entry reduction."""
+    """Multiply-class instructions per term: 32x32-bit integer multiplies on
+    the k = 1 path (ten per Montgomery product), f64 mul / fma on the blocked
+    path (four per modular product, two per table-entry reduction)."""
     if k == 1:
         return 2 * 10
-    return (3 * 10 + (d * k + d * (k - 1)) * 2 / RENORM) / k
+    return (3 * 4 + (d * k + d * (k - 1)) * 2 / RENORM) / k
 
 
 def sum_kernel_muls(st):
@@ -236,9 +237,9 @@ def main():
             "traffic": MEASURED_TRAFFIC.get((args.config, args.tables, block[0], block[1], W)) if block else None,
         },
     }
-    # the int32-multiply view: the blocked loop needs few multiplies per term,
-    # so this fraction is low although the kernel is bound by VALU issue
-    line["int32_mul"] = {"achieved": mul_rate, "peak": peak, "unit": "Tops/s", "frac": mul_rate / peak}
+    # the multiply view: the blocked loop needs few multiplies per term, so
+    # this fraction is low although the kernel is bound by VALU issue
+    line["multiply_ops"] = {"achieved": mul_rate, "peak": peak, "unit": "Tops/s", "frac": mul_rate / peak}
     if not args.no_cpu_baseline and first_timed:
         sample = first_timed[: max(1, args.cpu_primes)]
         nt = cpu_threads()

@@ -143,7 +143,7 @@ int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
 
 /* Choose the block shape of the term-sum kernel: kb terms per block on the
  * Bernoulli side and ke on the Euler side (compiled shapes: 1/1, 4/4, 8/8,
- * 8/16, 12/12, 12/16, 12/20, 14/20, 16/16; default 14/20).  Each block of k consecutive s is folded
+ * 8/16, 12/16, 14/20, 14/24, 16/16, 16/20, 16/24; default 16/24).  Each block of k consecutive s is folded
  * into the running pair as one factor of eqnCombinePairs whose two members
  * are stepped by finite differences.  Results do not depend on the shape.
  * kb = ke = 0 returns to the default / autotuned choice.

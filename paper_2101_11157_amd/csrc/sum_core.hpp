@@ -1,6 +1,7 @@
 // sum_core.hpp -- the per-lane hot loop of the term-sum kernel and the
 // chunk-to-sum lookup, written so that a plain C++ build can unit-test them.
 #pragma once
+#include <cmath>
 #include <cstdint>
 #include "mont.hpp"
 
@@ -122,6 +123,13 @@ __host__ __device__ __forceinline__ uint64_t opaque(uint64_t x) {
     return x;
 }
 
+__host__ __device__ __forceinline__ double opaque_f(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("" : "+v"(x));
+#endif
+    return x;
+}
+
 template <int DEG, int K>
 __host__ __device__ __forceinline__ void run_chunk_blocked(uint64_t s0, uint64_t n, const Mont &m, uint64_t r2,
                                                            uint64_t one, uint64_t &c0, uint64_t &c1) {
@@ -201,6 +209,125 @@ WV_UNROLL
     }
     c0 = a0;
     c1 = a1;
+}
+
+// ---- the blocked loop in double precision ------------------------------------
+//
+// Residues held as integer-valued doubles, signed and lazily reduced, for p <
+// 2^40.  One modular product of integers a, b is six full-rate f64 operations:
+//   h = ab rounded;  l = fma(a, b, -h) = ab - h exactly (an error-free product);
+//   q = the integer nearest h * (1/p) (fma with 1.5 * 2^52, then subtract it);
+//   r = fma(-q, p, h) + l.
+// With |ab| <= 300 p^2 (the loop's bounds below): h/p < 2^49, so the rounding
+// trick applies; |q - h/p| <= 1/2 + h 2^-53 / p, so h - qp is an integer below
+// p in magnitude and the fma computes it exactly; l is an integer with
+// |l| <= h 2^-53; hence r = ab - qp exactly, r == ab (mod p), and
+// |r| <= p/2 + 2 h 2^-53 <= p/2 + 600 p 2^-13 <= 0.574 p.
+struct Fmod {
+    double p, pinv;   // p, round(1/p)
+};
+
+constexpr double kRound = 6755399441055744.0;   // 1.5 * 2^52: x + kRound - kRound rounds |x| < 2^51
+
+__host__ __device__ __forceinline__ double f_mulmod(double a, double b, const Fmod &f) {
+    const double h = a * b;
+    const double l = fma(a, b, -h);
+    const double q = fma(h, f.pinv, kRound) - kRound;
+    return fma(-q, f.p, h) + l;
+}
+
+// x an integer, |x| < 2^50 -> r == x (mod p), |r| <= p/2 + |x| 2^-53 (< 0.51p), exactly.
+__host__ __device__ __forceinline__ double f_reduce(double x, const Fmod &f) {
+    const double q = fma(x, f.pinv, kRound) - kRound;
+    return fma(-q, f.p, x);
+}
+
+// an integer below 2^50 in magnitude -> its canonical residue in [0, p)
+__host__ __device__ __forceinline__ uint64_t f_canon(double x, const Fmod &f) {
+    const double r = f_reduce(x, f);
+    return (uint64_t)(r < 0.0 ? r + f.p : r);
+}
+
+// Same fold as run_chunk_blocked (P(x), Q(x) of each block of K terms stepped
+// by finite differences; (c0, c1) <- (c0 P, c0 Q + c1 P)), in the double
+// representation above.  The direct values at the first DEG*K + 1 block points
+// are products of s^DEG mod p, their difference table is reduced to
+// (-0.51p, 0.51p), and after n steps every entry is below 0.51p 2^n; the tables
+// are reduced every kRenormF = 10 blocks, so entries stay below 522p < 2^50
+// (exact) and the P, Q entering a product below 261p.  The running pair then
+// stays below (0.574p, 1.148p): |a| |b| <= 1.148 * 261 p^2 < 300 p^2.  Returns
+// plain residues in [0, p): the same ratio c1/c0 as run_chunk.
+constexpr int kRenormF = 10;
+
+template <int DEG>
+__host__ __device__ __forceinline__ double f_pow(double s, const Fmod &f) {
+    const double s2 = f_mulmod(s, s, f);
+    return DEG == 3 ? f_mulmod(s2, s, f) : s2;
+}
+
+template <int DEG, int K>
+__host__ __device__ __forceinline__ void run_chunk_blocked_f64(uint64_t s0, uint64_t n, uint64_t p, uint64_t &c0,
+                                                               uint64_t &c1) {
+    constexpr int DP = DEG * K;
+    constexpr int DQ = DEG * (K - 1);
+    Fmod f;
+    f.p = (double)p;
+    f.pinv = 1.0 / f.p;
+    const uint64_t nb = n / K;
+    double a0 = 1.0, a1 = 0.0;
+    if (nb > 0) {
+        double Pd[DP + 1], Qd[DQ + 1];
+        // direct values P, Q at x = s0 + b K, b = 0..DP
+WV_UNROLL
+        for (int b = 0; b <= DP; b++) {
+            double P = 1.0, Q = 0.0;
+            for (int j = 0; j < K; j++) {
+                const double u = f_pow<DEG>((double)(s0 + (uint64_t)b * K + j), f);
+                Q = f_reduce(f_mulmod(Q, u, f) + P, f);
+                P = f_mulmod(P, u, f);
+            }
+            Pd[b] = P;
+            if (b <= DQ) Qd[b] = Q;
+        }
+        // forward differences at b = 0: entry i becomes Delta^i, reduced
+WV_UNROLL
+        for (int lev = 1; lev <= DP; lev++) {
+WV_UNROLL
+            for (int i = DP; i >= lev; i--) Pd[i] = f_reduce(Pd[i] - Pd[i - 1], f);
+        }
+WV_UNROLL
+        for (int lev = 1; lev <= DQ; lev++) {
+WV_UNROLL
+            for (int i = DQ; i >= lev; i--) Qd[i] = f_reduce(Qd[i] - Qd[i - 1], f);
+        }
+        uint64_t b = 0;
+        for (;;) {
+            const uint64_t steps = nb - b < (uint64_t)kRenormF ? nb - b : (uint64_t)kRenormF;
+            for (uint64_t k = 0; k < steps; k++) {
+                const double n1 = f_mulmod(a0, Qd[0], f) + f_mulmod(a1, Pd[0], f);
+                a0 = f_mulmod(a0, Pd[0], f);
+                a1 = n1;
+WV_UNROLL
+                for (int i = 0; i < DP; i++) Pd[i] = opaque_f(Pd[i] + Pd[i + 1]);
+WV_UNROLL
+                for (int i = 0; i < DQ; i++) Qd[i] = opaque_f(Qd[i] + Qd[i + 1]);
+            }
+            b += steps;
+            if (b >= nb) break;
+WV_UNROLL
+            for (int i = 0; i < DP; i++) Pd[i] = f_reduce(Pd[i], f);
+WV_UNROLL
+            for (int i = 0; i < DQ; i++) Qd[i] = f_reduce(Qd[i], f);
+        }
+    }
+    for (uint64_t t = nb * K; t < n; t++) {
+        const double u = f_pow<DEG>((double)(s0 + t), f);
+        a1 = f_mulmod(a1, u, f) + a0;
+        a0 = f_mulmod(a0, u, f);
+        a1 = f_reduce(a1, f);
+    }
+    c0 = f_canon(a0, f);
+    c1 = f_canon(a1, f);
 }
 
 __device__ __forceinline__ uint32_t find_seg(const uint64_t *__restrict__ off, uint32_t nseg, uint64_t chunk) {

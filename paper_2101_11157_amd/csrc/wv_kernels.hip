@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(256) k_chunk_count(const uint64_t *__restrict_
 template <int DEG, int K>
 __device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont &m, uint64_t r2, uint64_t one,
                                            uint64_t &c0, uint64_t &c1) {
-    if (K > 1 && cnt >= (uint64_t)4 * (DEG * K + 1) * K) run_chunk_blocked<DEG, K>(s0, cnt, m, r2, one, c0, c1);
+    if (K > 1 && cnt >= (uint64_t)4 * (DEG * K + 1) * K) run_chunk_blocked_f64<DEG, K>(s0, cnt, m.p, c0, c1);
     else run_chunk<DEG>(s0, cnt, m, r2, one, c0, c1);
 }
 
@@ -503,9 +503,9 @@ struct SumVariant {
 
 // Compiled block shapes (terms per block, Bernoulli side / Euler side).
 static const SumVariant kSumVariants[] = {
-    {1, 1, k_sum<1, 1>},     {4, 4, k_sum<4, 4>},     {8, 8, k_sum<8, 8>},    {8, 16, k_sum<8, 16>},
-    {12, 12, k_sum<12, 12>}, {12, 16, k_sum<12, 16>}, {12, 20, k_sum<12, 20>}, {14, 20, k_sum<14, 20>},
-    {16, 16, k_sum<16, 16>},
+    {1, 1, k_sum<1, 1>},     {4, 4, k_sum<4, 4>},     {8, 8, k_sum<8, 8>},     {8, 16, k_sum<8, 16>},
+    {12, 16, k_sum<12, 16>}, {14, 20, k_sum<14, 20>}, {14, 24, k_sum<14, 24>}, {16, 16, k_sum<16, 16>},
+    {16, 20, k_sum<16, 20>}, {16, 24, k_sum<16, 24>},
 };
 constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants[0]));
 

@@ -1,6 +1,7 @@
 // Host-side unit test of the device arithmetic (mont.hpp) and of the per-lane
 // hot loop (sum_core.hpp) against unsigned __int128 products and %.
 // Prints "OK <checks>" or the first failure.
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <random>
@@ -155,11 +156,71 @@ int main() {
             run_chunk_blocked<3, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k4")) return 1;
             run_chunk_blocked<3, 8>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k8")) return 1;
             run_chunk_blocked<3, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k16")) return 1;
+            // double-precision blocked loop: plain residues in [0, p), same ratio
+            auto cmpf = [&](uint64_t y0, uint64_t y1, const char *what) {
+                // y1 / y0 == r1 / r0 (mod p)  <=>  y1 r0 == r1 y0
+                if (y0 >= p || y1 >= p || y0 == 0 ||
+                    mulmod(y1, r0 % p, p) != mulmod(r1 % p, y0, p)) {
+                    printf("FAIL %s p=%llu s0=%llu n=%llu\n", what, (unsigned long long)p, (unsigned long long)s0,
+                           (unsigned long long)n);
+                    return false;
+                }
+                checks++;
+                return true;
+            };
+            if (p < (1ull << 40)) {
+                run_chunk_blocked_f64<3, 2>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k2")) return 1;
+                run_chunk_blocked_f64<3, 8>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k8")) return 1;
+                run_chunk_blocked_f64<3, 14>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k14")) return 1;
+            }
             run_chunk<2>(s0, n, m, R2, Rm, r0, r1);
+            if (p < (1ull << 40)) {
+                run_chunk_blocked_f64<2, 4>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E f64 k4")) return 1;
+                run_chunk_blocked_f64<2, 20>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E f64 k20")) return 1;
+            }
             run_chunk_blocked<2, 1>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k1")) return 1;
             run_chunk_blocked<2, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k4")) return 1;
             run_chunk_blocked<2, 8>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k8")) return 1;
             run_chunk_blocked<2, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k16")) return 1;
+        }
+        // f_mulmod / f_reduce: exact at the bounds the loop relies on
+        if (p < (1ull << 40)) {
+            Fmod f;
+            f.p = (double)p;
+            f.pinv = 1.0 / f.p;
+            auto smod = [&](__int128 v) { __int128 r = v % (__int128)p; return (uint64_t)(r < 0 ? r + p : r); };
+            auto chkm = [&](int64_t a, int64_t b) {
+                const double r = f_mulmod((double)a, (double)b, f);
+                const __int128 want = (__int128)a * b;
+                if (r != std::floor(r) || std::fabs(r) > 0.574 * f.p || smod((__int128)(int64_t)r) != smod(want)) {
+                    printf("FAIL f_mulmod p=%llu a=%lld b=%lld r=%.1f\n", (unsigned long long)p, (long long)a,
+                           (long long)b, r);
+                    return false;
+                }
+                checks++;
+                return true;
+            };
+            const int64_t A = (int64_t)(1.148 * (double)p), B = (int64_t)(261.2 * (double)p);
+            const int64_t ea[] = {0, 1, -1, A, -A, (int64_t)p / 2, -(int64_t)p / 2, (int64_t)p - 1};
+            const int64_t eb[] = {0, 1, -1, B, -B, B - 1, (int64_t)p, -(int64_t)p, (int64_t)(0.51 * (double)p)};
+            for (int64_t a : ea)
+                for (int64_t b : eb)
+                    if (!chkm(a, b)) return 1;
+            for (int k = 0; k < 20000; k++) {
+                const int64_t a = (int64_t)(rng() % (2 * (uint64_t)A + 1)) - A;
+                const int64_t b = (int64_t)(rng() % (2 * (uint64_t)B + 1)) - B;
+                if (!chkm(a, b)) return 1;
+            }
+            for (int k = 0; k < 20000; k++) {
+                const int64_t x = (int64_t)(rng() % (1ull << 49)) - (int64_t)(1ull << 48);
+                const double r = f_reduce((double)x, f);
+                if (std::fabs(r) > 0.51 * f.p || smod((__int128)(int64_t)r) != smod(x)) {
+                    printf("FAIL f_reduce p=%llu x=%lld\n", (unsigned long long)p, (long long)x);
+                    return 1;
+                }
+                if (f_canon((double)x, f) != smod(x)) { printf("FAIL f_canon\n"); return 1; }
+                checks += 2;
+            }
         }
         // reduce_f64: x < p 2^24 -> r == x mod p, r < 2p, at quotient boundaries
         {
