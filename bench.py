@@ -39,7 +39,7 @@ RENORM = 10         # blocks between table reductions
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
 # (profiles/k_sum_window_1e11_*.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("1e11", "derived", 16, 24, 8192): 38359002 + 151601184}
 
 
 def ops_per_term(d, k):
