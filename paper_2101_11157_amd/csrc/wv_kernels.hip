@@ -439,8 +439,13 @@ __global__ void __launch_bounds__(256) k_chunk_count(const uint64_t *__restrict_
 template <int DEG, int K>
 __device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont &m, uint64_t r2, uint64_t one,
                                            uint64_t &c0, uint64_t &c1) {
-    if (K > 1 && cnt >= (uint64_t)4 * (DEG * K + 1) * K) run_chunk_blocked_f64<DEG, K>(s0, cnt, m.p, c0, c1);
-    else run_chunk<DEG>(s0, cnt, m, r2, one, c0, c1);
+    if constexpr (K > 1) {
+        if (cnt >= (uint64_t)4 * (DEG * K + 1) * K) {
+            run_chunk_blocked_f64<DEG, K>(s0, cnt, m.p, c0, c1);
+            return;
+        }
+    }
+    run_chunk<DEG>(s0, cnt, m, r2, one, c0, c1);
 }
 
 // Persistent: each wave takes 64 consecutive chunks at a time from `counter`
