@@ -45,7 +45,7 @@ def derived_table(side):
         return json.load(f)
 
 
-def Fraction_(a, b):
+def _frac(a, b):
     from fractions import Fraction
     return Fraction(int(a), int(b))
 
@@ -258,7 +258,7 @@ class Context:
 
     def define_derived_table(self, obj, min_p=DERIVED_MIN_P):
         """Register a congruence written by derive.Congruence.to_json."""
-        terms = [(int(n), Fraction_(xa, xb), Fraction_(ya, yb)) for n, xa, xb, ya, yb in obj["terms"]]
+        terms = [(int(n), _frac(xa, xb), _frac(ya, yb)) for n, xa, xb, ya, yb in obj["terms"]]
         return self.define_table(3 if obj["side"] == "B" else 2, int(obj["lhs"]), terms, min_p)
 
     def use_derived_tables(self, min_p=DERIVED_MIN_P):
