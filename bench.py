@@ -13,7 +13,8 @@ Prints one JSON line.  `roofline` describes the term-sum kernel (the dominant
 kernel), which is bound by vector-ALU issue: the full-rate VALU operations its
 algorithm needs per term (ops_per_term below: double-precision modular
 products, difference-table additions and the periodic table reductions of the
-blocked loop, as written in the source) times the terms it summed, over its
+blocked Taylor-coefficient loop, as written in the source) times the terms it
+summed, over its
 own HIP-event time, against the chip's VALU issue rate (256 CUs x 4 SIMDs x 16
 lanes x 2.4 GHz).  Register moves the compiler adds are not counted.
 `cpu_baseline` is the plain CPU oracle timed on this host on a bounded sample
@@ -34,40 +35,59 @@ OPS_MONT = 12       # one Montgomery product: 8 32x32->64 multiply-adds, 2 low m
 OPS_ADDM = 3        # one modular addition: add, subtract, select
 OPS_FMUL = 6        # one double-precision modular product: mul, 3 fma, 2 add
 OPS_FRED = 3        # one double-precision reduction: fma, add, fma
-RENORM = 10         # blocks between table reductions
+# per block of the Taylor-coefficient loop: modular products, reductions of
+# the g_k entering them, and plain additions (d = 2: P, g0 g2, g1^2 and the
+# three updates of the running pair; d = 3: g0^2, P, g3 g0^2, g0 g1 g2,
+# g1^3 and the three updates)
+BLOCK_FMUL = {2: 6, 3: 10}
+BLOCK_FRED = {2: 3, 3: 4}
+BLOCK_ADD = {2: 3, 3: 5}
 
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
 # (profiles/k_sum_window_1e11_*.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {("1e11", "derived", 16, 24, 8192): 38359002 + 151601184}
+MEASURED_TRAFFIC = {}
 
 
-def ops_per_term(d, k):
+def renorm_period(p):
+    """Blocks between reductions of the difference tables for primes below p."""
+    return 53 - int(p).bit_length()
+
+
+def table_entries(d, k):
+    """Entries of the difference tables of g_0 .. g_d (degrees k .. k - d)."""
+    return (d + 1) * (k + 1) - d * (d + 1) // 2
+
+
+def ops_per_term(d, k, period):
     """Full-rate VALU operations per term of a sum of s^-d with blocks of k terms."""
     if k == 1:   # one factor per term (Montgomery): two products, one add, d difference steps
         return 2 * OPS_MONT + 1 + d * OPS_ADDM
-    table = d * k + d * (k - 1)   # difference-table entries of P and Q
-    return (3 * OPS_FMUL + 1 + table * (1 + OPS_FRED / RENORM)) / k
+    sz = table_entries(d, k)
+    stepped = sz - (d + 1)   # the constant top entries are not stepped
+    per_block = BLOCK_FMUL[d] * OPS_FMUL + BLOCK_FRED[d] * OPS_FRED + BLOCK_ADD[d] + stepped
+    return (per_block + sz * OPS_FRED / period) / k
 
 
-def muls_per_term(d, k):
+def muls_per_term(d, k, period):
     """Multiply-class instructions per term: 32x32-bit integer multiplies on
     the k = 1 path (ten per Montgomery product), f64 mul / fma on the blocked
-    path (four per modular product, two per table-entry reduction)."""
+    path (four per modular product, two per reduction)."""
     if k == 1:
         return 2 * 10
-    return (3 * 4 + (d * k + d * (k - 1)) * 2 / RENORM) / k
+    return (BLOCK_FMUL[d] * 4 + BLOCK_FRED[d] * 2 + table_entries(d, k) * 2 / period) / k
 
 
-def sum_kernel_muls(st):
+def sum_kernel_muls(st, period):
     nb = st["n_terms_b"]
-    return nb * muls_per_term(3, st["block_k_b"]) + (st["n_terms"] - nb) * muls_per_term(2, st["block_k_e"])
+    return (nb * muls_per_term(3, st["block_k_b"], period)
+            + (st["n_terms"] - nb) * muls_per_term(2, st["block_k_e"], period))
 
 
-def sum_kernel_ops(st):
+def sum_kernel_ops(st, period):
     nb = st["n_terms_b"]
     ne = st["n_terms"] - nb
-    return nb * ops_per_term(3, st["block_k_b"]) + ne * ops_per_term(2, st["block_k_e"])
+    return nb * ops_per_term(3, st["block_k_b"], period) + ne * ops_per_term(2, st["block_k_e"], period)
 
 CONFIGS = {
     "1e11": (10 ** 11 - 10 ** 6, 10 ** 11, 8192),
@@ -180,6 +200,7 @@ def main():
     primes = terms = 0
     ops = 0.0
     muls = 0.0
+    period = renorm_period(hi0 - 1)   # exact for every prime of the 1e11 and 1e9 ranges
     block = None
     ms_sum = ms_dev = 0.0
     first_timed = None
@@ -189,8 +210,8 @@ def main():
         st = ctx.stats()
         primes += len(res)
         terms += st["n_terms"]
-        ops += sum_kernel_ops(st)
-        muls += sum_kernel_muls(st)
+        ops += sum_kernel_ops(st, period)
+        muls += sum_kernel_muls(st, period)
         block = [st["block_k_b"], st["block_k_e"]]
         ms_sum += st["ms_sum"]
         ms_dev += st["ms_total"]

@@ -143,9 +143,11 @@ int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
 
 /* Choose the block shape of the term-sum kernel: kb terms per block on the
  * Bernoulli side and ke on the Euler side (compiled shapes: 1/1, 4/4, 8/8,
- * 8/16, 12/16, 14/20, 14/24, 16/16, 16/20, 16/24; default 16/24).  Each block of k consecutive s is folded
- * into the running pair as one factor of eqnCombinePairs whose two members
- * are stepped by finite differences.  Results do not depend on the shape.
+ * 12/16, 16/24, 20/28, 24/24, 24/28, 24/32, 20/32; default 24/32).  Each block
+ * of k consecutive s is folded into the running pair as one factor of
+ * eqnCombinePairs, whose two members come from the Taylor coefficients of
+ * prod_j (x + j) stepped by finite differences.  Results do not depend on the
+ * shape.
  * kb = ke = 0 returns to the default / autotuned choice.
  * Errors: WV_EINVAL for a shape that is not compiled. */
 int wv_set_block(wv_ctx *ctx, int kb, int ke);

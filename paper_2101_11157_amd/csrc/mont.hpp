@@ -13,12 +13,14 @@
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
 #define WV_UNROLL _Pragma("unroll")
+#define WV_NO_UNROLL _Pragma("unroll 1")
 #else
 // Plain C++ build of the same arithmetic, for host-side unit tests.
 #define __host__
 #define __device__
 #define __forceinline__ inline
 #define WV_UNROLL
+#define WV_NO_UNROLL
 #endif
 
 namespace wv {

@@ -236,7 +236,7 @@ __host__ __device__ __forceinline__ double f_mulmod(double a, double b, const Fm
     return fma(-q, f.p, h) + l;
 }
 
-// x an integer, |x| < 2^50 -> r == x (mod p), |r| <= p/2 + |x| 2^-53 (< 0.51p), exactly.
+// x an integer, |x| <= 2^53 -> r == x (mod p), |r| <= p/2 + 2 |x| 2^-53 / p (< 0.51p), exactly.
 __host__ __device__ __forceinline__ double f_reduce(double x, const Fmod &f) {
     const double q = fma(x, f.pinv, kRound) - kRound;
     return fma(-q, f.p, x);
@@ -318,6 +318,124 @@ WV_UNROLL
             for (int i = 0; i < DP; i++) Pd[i] = f_reduce(Pd[i], f);
 WV_UNROLL
             for (int i = 0; i < DQ; i++) Qd[i] = f_reduce(Qd[i], f);
+        }
+    }
+    for (uint64_t t = nb * K; t < n; t++) {
+        const double u = f_pow<DEG>((double)(s0 + t), f);
+        a1 = f_mulmod(a1, u, f) + a0;
+        a0 = f_mulmod(a0, u, f);
+        a1 = f_reduce(a1, f);
+    }
+    c0 = f_canon(a0, f);
+    c1 = f_canon(a1, f);
+}
+
+// ---- blocked loop through the Taylor coefficients of F ------------------------
+//
+// With F(x) = prod_{j<K} (x + j) and g_k(x) = F^(k)(x) / k! (the coefficients
+// of F(x + h) = sum_k g_k h^k), the block factor of run_chunk_blocked is
+//   P = F^d,  Q = P sum_j (x + j)^-d,
+// and the logarithmic derivatives of F give, as polynomial identities,
+//   d = 2:  sum_j (x+j)^-2 = (F'^2 - F F'') / F^2,             Q = g1^2 - 2 g0 g2,
+//   d = 3:  sum_j (x+j)^-3 = (F''' F^2 - 3 F F' F'' + 2 F'^3) / (2 F^3),
+//           Q = 3 g3 g0^2 - 3 g0 g1 g2 + g1^3.
+// So only g_0..g_d (degrees K..K-d in x) are stepped by finite differences
+// with step K: (d+1)K - d(d+1)/2 additions per block instead of d(2K-1), for
+// a few more products per block.  The g_k entering the products are reduced
+// first (|g| < 0.51p), so every product stays within f_mulmod's bounds
+// (|Q| < 4.1p, |a0 Q| < 2.4 p^2).  The tables themselves only need to stay
+// exact integers: every entry is below 0.574p after a reduction and at most
+// doubles per block, so for p < 2^b they are reduced every 53 - b blocks
+// (0.574 2^53 < 2^53; 13 blocks at p < 2^40, 16 at p < 2^37).  Returns plain
+// residues in [0, p) with the same ratio c1/c0 as run_chunk.
+
+template <int DEG, int K>
+__host__ __device__ __forceinline__ void run_chunk_logd(uint64_t s0, uint64_t n, uint64_t p, uint64_t &c0,
+                                                        uint64_t &c1) {
+    // table k holds g_k: K - k + 1 entries from offset k (K + 1) - k (k - 1) / 2
+    static_assert(K >= DEG, "g_DEG must have degree >= 0");
+    constexpr int NT = DEG + 1;
+    constexpr int SZ = NT * (K + 1) - NT * (NT - 1) / 2;
+    Fmod f;
+    f.p = (double)p;
+    f.pinv = 1.0 / f.p;
+    const uint64_t nb = n / K;
+    const uint64_t period = (uint64_t)(53 - (64 - __builtin_clzll(p)));   // blocks between reductions
+    double a0 = 1.0, a1 = 0.0;
+    if (nb > 0) {
+        double G[SZ];
+        // direct values g_k(x) at x = s0 + b K for b = 0..K - k, built in place:
+        // prod_j (x + j + h) mod h^NT, one factor (all points at once) per j.
+        // Table k only needs points the lower tables also hold (b <= K - k <
+        // K - k + 2), so the update g_k <- a g_k + g_{k-1} runs from the top
+        // table down.
+WV_UNROLL
+        for (int i = 0; i < SZ; i++) G[i] = 0.0;
+WV_UNROLL
+        for (int b = 0; b <= K; b++) G[b] = 1.0;
+WV_NO_UNROLL
+        for (int j = 0; j < K; j++) {
+            const double xj = (double)(s0 + (uint64_t)j);
+WV_UNROLL
+            for (int k = NT - 1; k >= 0; k--) {
+                const int off = k * (K + 1) - k * (k - 1) / 2;
+                const int offl = (k - 1) * (K + 1) - (k - 1) * (k - 2) / 2;
+                double a = xj;   // x + j at point b, stepped (no table of constants)
+WV_UNROLL
+                for (int b = 0; b <= K - k; b++) {
+                    const double t = f_mulmod(a, G[off + b], f);
+                    G[off + b] = k == 0 ? t : f_reduce(t + G[(k > 0 ? offl : 0) + b], f);
+                    a = opaque_f(a + (double)K);
+                }
+            }
+        }
+        // forward differences of each table (entry i becomes Delta^i), reduced
+WV_UNROLL
+        for (int k = 0; k < NT; k++) {
+            const int off = k * (K + 1) - k * (k - 1) / 2;
+            const int deg = K - k;
+WV_UNROLL
+            for (int lev = 1; lev <= deg; lev++) {
+WV_UNROLL
+                for (int i = deg; i >= lev; i--) G[off + i] = f_reduce(G[off + i] - G[off + i - 1], f);
+            }
+        }
+        uint64_t b = 0;
+        for (;;) {
+            const uint64_t steps = nb - b < period ? nb - b : period;
+            for (uint64_t t = 0; t < steps; t++) {
+                const double r0 = f_reduce(G[0], f);
+                const double r1 = f_reduce(G[K + 1], f);
+                const double r2 = f_reduce(G[2 * K + 1], f);
+                double P, Q;
+                if (DEG == 2) {
+                    P = f_mulmod(r0, r0, f);
+                    const double u = f_mulmod(r0, r2, f);
+                    Q = f_mulmod(r1, r1, f) - (u + u);
+                } else {
+                    const double r3 = f_reduce(G[3 * K], f);
+                    const double sq = f_mulmod(r0, r0, f);
+                    P = f_mulmod(sq, r0, f);
+                    const double A = f_mulmod(r3, sq, f);
+                    const double C = f_mulmod(f_mulmod(r0, r1, f), r2, f);
+                    const double E = f_mulmod(f_mulmod(r1, r1, f), r1, f);
+                    const double D = A - C;
+                    Q = (D + D + D) + E;
+                }
+                const double n1 = f_mulmod(a0, Q, f) + f_mulmod(a1, P, f);
+                a0 = f_mulmod(a0, P, f);
+                a1 = n1;
+WV_UNROLL
+                for (int k = 0; k < NT; k++) {
+                    const int off = k * (K + 1) - k * (k - 1) / 2;
+WV_UNROLL
+                    for (int i = 0; i < K - k; i++) G[off + i] = opaque_f(G[off + i] + G[off + i + 1]);
+                }
+            }
+            b += steps;
+            if (b >= nb) break;
+WV_UNROLL
+            for (int i = 0; i < SZ; i++) G[i] = f_reduce(G[i], f);
         }
     }
     for (uint64_t t = nb * K; t < n; t++) {

@@ -433,15 +433,16 @@ __global__ void __launch_bounds__(256) k_chunk_count(const uint64_t *__restrict_
 // term-sum kernel
 // --------------------------------------------------------------------------
 
-// Per-lane work of one chunk: the blocked loop with K terms per block when
-// the chunk is long enough to amortise the difference tables, else one term
-// per iteration.
+// Per-lane work of one chunk: the blocked loop with K terms per block (stepped
+// through the Taylor coefficients of prod_j (x + j)) when the chunk is long
+// enough to amortise building the difference tables, else one term per
+// iteration.
 template <int DEG, int K>
 __device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont &m, uint64_t r2, uint64_t one,
                                            uint64_t &c0, uint64_t &c1) {
     if constexpr (K > 1) {
         if (cnt >= (uint64_t)4 * (DEG * K + 1) * K) {
-            run_chunk_blocked_f64<DEG, K>(s0, cnt, m.p, c0, c1);
+            run_chunk_logd<DEG, K>(s0, cnt, m.p, c0, c1);
             return;
         }
     }
@@ -453,8 +454,10 @@ __device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont
 // their butterfly product at partials[first chunk]; any other wave stores one
 // pair per chunk at partials[chunk].  KB / KE: terms per block on the
 // Bernoulli (s^3) and Euler (s^2) sides.
+// Two waves per SIMD (at most 256 registers per lane) keep the VALU fed; the
+// largest block shapes fill that budget with their difference tables.
 template <int KB, int KE>
-__global__ void __launch_bounds__(256) k_sum(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_sum(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
                                              uint32_t nseg, const PrimeRec *__restrict__ pr,
                                              const uint64_t *__restrict__ chunk_ptr, Pair *__restrict__ partials,
                                              unsigned long long *__restrict__ counter, uint64_t end) {
@@ -508,9 +511,9 @@ struct SumVariant {
 
 // Compiled block shapes (terms per block, Bernoulli side / Euler side).
 static const SumVariant kSumVariants[] = {
-    {1, 1, k_sum<1, 1>},     {4, 4, k_sum<4, 4>},     {8, 8, k_sum<8, 8>},     {8, 16, k_sum<8, 16>},
-    {12, 16, k_sum<12, 16>}, {14, 20, k_sum<14, 20>}, {14, 24, k_sum<14, 24>}, {16, 16, k_sum<16, 16>},
-    {16, 20, k_sum<16, 20>}, {16, 24, k_sum<16, 24>},
+    {1, 1, k_sum<1, 1>}, {4, 4, k_sum<4, 4>}, {8, 8, k_sum<8, 8>}, {12, 16, k_sum<12, 16>},
+    {16, 24, k_sum<16, 24>}, {20, 28, k_sum<20, 28>}, {24, 24, k_sum<24, 24>}, {24, 28, k_sum<24, 28>},
+    {24, 32, k_sum<24, 32>}, {20, 32, k_sum<20, 32>},
 };
 constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants[0]));
 

@@ -137,6 +137,7 @@ int main() {
             if (k == 0) n = 0;
             if (k == 1) n = 5;
             if (k == 2) n = 16 * 20 * 3 + 77;   // several reduction periods of the tables
+            if (k == 4) n = 32 * 37 * 2 + 31;   // periods of the Taylor-coefficient tables (53 - b blocks)
             if (k == 3) n = 8 * 20 + 8;         // a period boundary at K = 8
             if (s0 + n > p) n = p - s0;
             uint64_t r0, r1;
@@ -158,8 +159,9 @@ int main() {
             run_chunk_blocked<3, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k16")) return 1;
             // double-precision blocked loop: plain residues in [0, p), same ratio
             auto cmpf = [&](uint64_t y0, uint64_t y1, const char *what) {
-                // y1 / y0 == r1 / r0 (mod p)  <=>  y1 r0 == r1 y0
-                if (y0 >= p || y1 >= p || y0 == 0 ||
+                // y1 / y0 == r1 / r0 (mod p)  <=>  y1 r0 == r1 y0; c0 vanishes for
+                // both or neither (only possible for the composite test moduli)
+                if (y0 >= p || y1 >= p || (y0 == 0) != (r0 % p == 0) ||
                     mulmod(y1, r0 % p, p) != mulmod(r1 % p, y0, p)) {
                     printf("FAIL %s p=%llu s0=%llu n=%llu\n", what, (unsigned long long)p, (unsigned long long)s0,
                            (unsigned long long)n);
@@ -172,11 +174,17 @@ int main() {
                 run_chunk_blocked_f64<3, 2>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k2")) return 1;
                 run_chunk_blocked_f64<3, 8>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k8")) return 1;
                 run_chunk_blocked_f64<3, 14>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k14")) return 1;
+                run_chunk_logd<3, 3>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B logd k3")) return 1;
+                run_chunk_logd<3, 16>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B logd k16")) return 1;
+                run_chunk_logd<3, 24>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B logd k24")) return 1;
             }
             run_chunk<2>(s0, n, m, R2, Rm, r0, r1);
             if (p < (1ull << 40)) {
                 run_chunk_blocked_f64<2, 4>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E f64 k4")) return 1;
                 run_chunk_blocked_f64<2, 20>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E f64 k20")) return 1;
+                run_chunk_logd<2, 2>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E logd k2")) return 1;
+                run_chunk_logd<2, 24>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E logd k24")) return 1;
+                run_chunk_logd<2, 32>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E logd k32")) return 1;
             }
             run_chunk_blocked<2, 1>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k1")) return 1;
             run_chunk_blocked<2, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k4")) return 1;
