@@ -143,7 +143,7 @@ int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
 
 /* Choose the block shape of the term-sum kernel: kb terms per block on the
  * Bernoulli side and ke on the Euler side (compiled shapes: 1/1, 4/4, 8/8,
- * 12/16, 16/24, 20/28, 24/24, 24/28, 24/32, 20/32; default 24/32).  Each block
+ * 12/16, 16/24, 20/28, 24/32, 26/34, 28/32, 28/36; default 28/36).  Each block
  * of k consecutive s is folded into the running pair as one factor of
  * eqnCombinePairs, whose two members come from the Taylor coefficients of
  * prod_j (x + j) stepped by finite differences.  Results do not depend on the

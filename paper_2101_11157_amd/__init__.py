@@ -51,7 +51,7 @@ def _frac(a, b):
 
 
 # compiled block shapes of the term-sum kernel, in the library's order
-BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (12, 16), (16, 24), (20, 28), (24, 24), (24, 28), (24, 32), (20, 32)]
+BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (12, 16), (16, 24), (20, 28), (24, 32), (26, 34), (28, 32), (28, 36)]
 
 # wv_result as a numpy record (32 bytes)
 RESULT_DTYPE = np.dtype([("p", "<u8"), ("b", "<u8"), ("e", "<u8"), ("flags", "<u4"), ("reserved", "<u4")])

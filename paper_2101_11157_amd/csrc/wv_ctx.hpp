@@ -49,7 +49,7 @@ constexpr uint64_t kMaxBatchPrimes = 1ull << 19; // primes per search batch
 constexpr uint64_t kMaxBatchSlots = 1ull << 27;  // (prime, sum) slots per batch (~10 GB of plan records)
 constexpr double kMaxBatchTerms = 70368744177664.0;   // 2^46 terms per search batch (~20 s)
 constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
-constexpr int kDefaultVariant = 8;               // block shape 24/32
+constexpr int kDefaultVariant = 9;               // block shape 28/36
 
 struct BatchShape {
     int tb, te;          // tables of the batch (a defined table's fallback when no prime reaches its min_p)

@@ -63,6 +63,12 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 
 // Butterfly of eqnCombinePairs across the 64 lanes of a wave; every lane
 // ends with the product of all 64 pairs (same prime on all lanes).
+// minimum over the 64 lanes of a fully active wave, as a wave-uniform value
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 __device__ __forceinline__ void wave_pair_reduce(uint64_t &c0, uint64_t &c1, const Mont &m) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -438,11 +444,22 @@ __global__ void __launch_bounds__(256) k_chunk_count(const uint64_t *__restrict_
 // enough to amortise building the difference tables, else one term per
 // iteration.
 template <int DEG, int K>
+__device__ __forceinline__ bool chunk_blocked(uint64_t cnt) {
+    return K > 1 && cnt >= (uint64_t)4 * (DEG * K + 1) * K;
+}
+
+// Blocks between table reductions for p < 2^b (b <= 40): 53 - b.
+__device__ __forceinline__ uint32_t table_period(uint64_t p) { return 53u - (64u - (uint32_t)__clzll(p)); }
+
+// nb_shared / period_shared: blocks and reduction period every lane of the
+// wave shares (wave minima), so those blocks run under scalar loop control.
+template <int DEG, int K>
 __device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont &m, uint64_t r2, uint64_t one,
-                                           uint64_t &c0, uint64_t &c1) {
+                                           uint32_t nb_shared, uint32_t period_shared, uint64_t &c0,
+                                           uint64_t &c1) {
     if constexpr (K > 1) {
-        if (cnt >= (uint64_t)4 * (DEG * K + 1) * K) {
-            run_chunk_logd<DEG, K>(s0, cnt, m.p, c0, c1);
+        if (chunk_blocked<DEG, K>(cnt)) {
+            run_chunk_logd<DEG, K>(s0, cnt, m.p, nb_shared, period_shared, c0, c1);
             return;
         }
     }
@@ -478,16 +495,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         uint64_t c0 = 1, c1 = 0;
         Mont m;
         m.p = 11; m.p0 = 11; m.p1 = 0; m.ninv = neg_inv32(11);
+        uint64_t s0 = 0, cnt = 0, r2 = 0, one = 0;
+        uint32_t deg = 0;
+        // lanes that take no blocked loop do not lower the wave's shared counts
+        uint32_t nb_lane = 0xffffffffu, period_lane = 0xffffffffu;
         if (active) {
             seg = find_seg(off, nseg, chunk);
             const SegRec sr = segs[seg];
             const PrimeRec P = pr[sr.prime];
             m = mont_of(P);
+            r2 = P.r2;
+            one = P.one;
             const uint64_t o = (chunk - off[seg]) * C;
-            const uint64_t s0 = sr.lo + o;
-            const uint64_t cnt = min(C, sr.len - o);
-            if (sr.deg == 3) chunk_pair<3, KB>(s0, cnt, m, P.r2, P.one, c0, c1);
-            else chunk_pair<2, KE>(s0, cnt, m, P.r2, P.one, c0, c1);
+            s0 = sr.lo + o;
+            cnt = min(C, sr.len - o);
+            deg = sr.deg;
+            const bool blk = deg == 3 ? chunk_blocked<3, KB>(cnt) : chunk_blocked<2, KE>(cnt);
+            if (blk) {
+                nb_lane = (uint32_t)min(cnt / (deg == 3 ? KB : KE), (uint64_t)0xfffffffeu);
+                period_lane = table_period(m.p);
+            }
+        }
+        // the whole wave is active here (the loop exit above is wave-uniform)
+        const uint32_t nb_shared = wave_min_u32(nb_lane);
+        const uint32_t period_shared = wave_min_u32(period_lane);
+        if (active) {
+            if (deg == 3) chunk_pair<3, KB>(s0, cnt, m, r2, one, nb_shared, period_shared, c0, c1);
+            else chunk_pair<2, KE>(s0, cnt, m, r2, one, nb_shared, period_shared, c0, c1);
         }
         const uint32_t seg0 = __builtin_amdgcn_readlane(seg, 0);
         const uint32_t segl = __builtin_amdgcn_readlane(seg, 63);
@@ -512,8 +546,8 @@ struct SumVariant {
 // Compiled block shapes (terms per block, Bernoulli side / Euler side).
 static const SumVariant kSumVariants[] = {
     {1, 1, k_sum<1, 1>}, {4, 4, k_sum<4, 4>}, {8, 8, k_sum<8, 8>}, {12, 16, k_sum<12, 16>},
-    {16, 24, k_sum<16, 24>}, {20, 28, k_sum<20, 28>}, {24, 24, k_sum<24, 24>}, {24, 28, k_sum<24, 28>},
-    {24, 32, k_sum<24, 32>}, {20, 32, k_sum<20, 32>},
+    {16, 24, k_sum<16, 24>}, {20, 28, k_sum<20, 28>}, {24, 32, k_sum<24, 32>}, {26, 34, k_sum<26, 34>},
+    {28, 32, k_sum<28, 32>}, {28, 36, k_sum<28, 36>},
 };
 constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants[0]));
 

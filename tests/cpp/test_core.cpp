@@ -136,28 +136,14 @@ int main() {
             uint64_t n = rng() % 700;
             if (k == 0) n = 0;
             if (k == 1) n = 5;
-            if (k == 2) n = 16 * 20 * 3 + 77;   // several reduction periods of the tables
+            if (k == 2) n = 16 * 20 * 3 + 77;   // several reduction periods at p near 2^40
             if (k == 4) n = 32 * 37 * 2 + 31;   // periods of the Taylor-coefficient tables (53 - b blocks)
-            if (k == 3) n = 8 * 20 + 8;         // a period boundary at K = 8
+            if (k == 3) n = 8 * 13 + 8;         // a period boundary at K = 8, p near 2^40
             if (s0 + n > p) n = p - s0;
             uint64_t r0, r1;
-            auto cmp = [&](uint64_t x0, uint64_t x1, const char *what) {
-                if (x0 % p != r0 % p || x1 % p != r1 % p || x0 >= 2 * p || x1 >= 4 * p) {
-                    printf("FAIL %s p=%llu s0=%llu n=%llu\n", what, (unsigned long long)p, (unsigned long long)s0,
-                           (unsigned long long)n);
-                    return false;
-                }
-                checks++;
-                return true;
-            };
             uint64_t x0, x1;
             run_chunk<3>(s0, n, m, R2, Rm, r0, r1);
-            run_chunk_blocked<3, 1>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k1")) return 1;
-            run_chunk_blocked<3, 2>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k2")) return 1;
-            run_chunk_blocked<3, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k4")) return 1;
-            run_chunk_blocked<3, 8>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k8")) return 1;
-            run_chunk_blocked<3, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "B k16")) return 1;
-            // double-precision blocked loop: plain residues in [0, p), same ratio
+            // blocked loop: plain residues in [0, p), the same ratio as run_chunk
             auto cmpf = [&](uint64_t y0, uint64_t y1, const char *what) {
                 // y1 / y0 == r1 / r0 (mod p)  <=>  y1 r0 == r1 y0; c0 vanishes for
                 // both or neither (only possible for the composite test moduli)
@@ -170,26 +156,34 @@ int main() {
                 checks++;
                 return true;
             };
+            // block count / reduction period shared with other lanes: all, some or
+            // none of this lane's blocks, the lane's own period or a shorter one
+            const uint64_t own_period = 53 - (64 - __builtin_clzll(p));
+            const uint64_t psh = k % 2 ? own_period : 7;
+            auto nbsh_of = [&](uint64_t K) { return k % 3 == 0 ? n / K : k % 3 == 1 ? n / K / 3 : 0; };
             if (p < (1ull << 40)) {
-                run_chunk_blocked_f64<3, 2>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k2")) return 1;
-                run_chunk_blocked_f64<3, 8>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k8")) return 1;
-                run_chunk_blocked_f64<3, 14>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B f64 k14")) return 1;
-                run_chunk_logd<3, 3>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B logd k3")) return 1;
-                run_chunk_logd<3, 16>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B logd k16")) return 1;
-                run_chunk_logd<3, 24>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "B logd k24")) return 1;
+                run_chunk_logd<3, 3>(s0, n, p, nbsh_of(3), psh, x0, x1); if (!cmpf(x0, x1, "B logd k3")) return 1;
+                run_chunk_logd<3, 4>(s0, n, p, nbsh_of(4), psh, x0, x1); if (!cmpf(x0, x1, "B logd k4")) return 1;
+                run_chunk_logd<3, 8>(s0, n, p, nbsh_of(8), psh, x0, x1); if (!cmpf(x0, x1, "B logd k8")) return 1;
+                run_chunk_logd<3, 12>(s0, n, p, nbsh_of(12), psh, x0, x1); if (!cmpf(x0, x1, "B logd k12")) return 1;
+                run_chunk_logd<3, 16>(s0, n, p, nbsh_of(16), psh, x0, x1); if (!cmpf(x0, x1, "B logd k16")) return 1;
+                run_chunk_logd<3, 20>(s0, n, p, nbsh_of(20), psh, x0, x1); if (!cmpf(x0, x1, "B logd k20")) return 1;
+                run_chunk_logd<3, 24>(s0, n, p, nbsh_of(24), psh, x0, x1); if (!cmpf(x0, x1, "B logd k24")) return 1;
+                run_chunk_logd<3, 26>(s0, n, p, nbsh_of(26), psh, x0, x1); if (!cmpf(x0, x1, "B logd k26")) return 1;
+                run_chunk_logd<3, 28>(s0, n, p, nbsh_of(28), psh, x0, x1); if (!cmpf(x0, x1, "B logd k28")) return 1;
             }
             run_chunk<2>(s0, n, m, R2, Rm, r0, r1);
             if (p < (1ull << 40)) {
-                run_chunk_blocked_f64<2, 4>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E f64 k4")) return 1;
-                run_chunk_blocked_f64<2, 20>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E f64 k20")) return 1;
-                run_chunk_logd<2, 2>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E logd k2")) return 1;
-                run_chunk_logd<2, 24>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E logd k24")) return 1;
-                run_chunk_logd<2, 32>(s0, n, p, x0, x1); if (!cmpf(x0, x1, "E logd k32")) return 1;
+                run_chunk_logd<2, 2>(s0, n, p, nbsh_of(2), psh, x0, x1); if (!cmpf(x0, x1, "E logd k2")) return 1;
+                run_chunk_logd<2, 4>(s0, n, p, nbsh_of(4), psh, x0, x1); if (!cmpf(x0, x1, "E logd k4")) return 1;
+                run_chunk_logd<2, 8>(s0, n, p, nbsh_of(8), psh, x0, x1); if (!cmpf(x0, x1, "E logd k8")) return 1;
+                run_chunk_logd<2, 16>(s0, n, p, nbsh_of(16), psh, x0, x1); if (!cmpf(x0, x1, "E logd k16")) return 1;
+                run_chunk_logd<2, 24>(s0, n, p, nbsh_of(24), psh, x0, x1); if (!cmpf(x0, x1, "E logd k24")) return 1;
+                run_chunk_logd<2, 28>(s0, n, p, nbsh_of(28), psh, x0, x1); if (!cmpf(x0, x1, "E logd k28")) return 1;
+                run_chunk_logd<2, 32>(s0, n, p, nbsh_of(32), psh, x0, x1); if (!cmpf(x0, x1, "E logd k32")) return 1;
+                run_chunk_logd<2, 34>(s0, n, p, nbsh_of(34), psh, x0, x1); if (!cmpf(x0, x1, "E logd k34")) return 1;
+                run_chunk_logd<2, 36>(s0, n, p, nbsh_of(36), psh, x0, x1); if (!cmpf(x0, x1, "E logd k36")) return 1;
             }
-            run_chunk_blocked<2, 1>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k1")) return 1;
-            run_chunk_blocked<2, 4>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k4")) return 1;
-            run_chunk_blocked<2, 8>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k8")) return 1;
-            run_chunk_blocked<2, 16>(s0, n, m, R2, Rm, x0, x1); if (!cmp(x0, x1, "E k16")) return 1;
         }
         // f_mulmod / f_reduce: exact at the bounds the loop relies on
         if (p < (1ull << 40)) {
@@ -229,41 +223,6 @@ int main() {
                 if (f_canon((double)x, f) != smod(x)) { printf("FAIL f_canon\n"); return 1; }
                 checks += 2;
             }
-        }
-        // reduce_f64: x < p 2^24 -> r == x mod p, r < 2p, at quotient boundaries
-        {
-            const uint64_t negp = 0 - p;
-            const double pinv = 1.0 / (double)p;
-            auto chk = [&](uint64_t x) {
-                const uint64_t r = reduce_f64(x, negp, pinv);
-                if (r % p != x % p || r >= 2 * p) {
-                    printf("FAIL reduce_f64 p=%llu x=%llu r=%llu\n", (unsigned long long)p, (unsigned long long)x,
-                           (unsigned long long)r);
-                    return false;
-                }
-                checks++;
-                return true;
-            };
-            const uint64_t top = (p << 24) - 1;
-            for (uint64_t x : {(uint64_t)0, (uint64_t)1, p - 1, p, p + 1, 2 * p - 1, 2 * p, top, top - p, top / p * p,
-                               top / p * p - 1, (p << 21) - 1, (p << 21), (p << 21) + 1})
-                if (!chk(x)) return 1;
-            for (int k = 0; k < 20000; k++) {
-                const uint64_t q = rng() % ((top / p) + 1);
-                const uint64_t e = rng() % 5;
-                const uint64_t x = q * p + e;
-                if (x <= top && !chk(x)) return 1;
-                if (q > 0 && !chk(q * p - 1 - e)) return 1;
-                if (!chk(rng() % (top + 1))) return 1;
-            }
-        }
-        // addm_n, canon4
-        for (int k = 0; k < 1000; k++) {
-            uint64_t a = rng() % p, b = rng() % p;
-            if (addm_n(a, b, 0 - p) != (uint64_t)(((u128)a + b) % p)) { printf("FAIL addm_n\n"); return 1; }
-            uint64_t x = rng() % (4 * p);
-            if (canon4(x, p) != x % p) { printf("FAIL canon4\n"); return 1; }
-            checks += 2;
         }
     }
     // chunk -> sum lookup skips empty sums
