@@ -135,10 +135,11 @@ int wv_define_table(wv_ctx *ctx, int deg, const char *lhs, size_t n, const char 
                     uint64_t min_p, int *id);
 
 /* Set the number of terms each lane sums per chunk (0 = automatic: about
- * sqrt(2 * 4096 * T / (lanes + sums)) for a batch of T terms, between 2^12
- * and 2^22, which balances the set-up of each chunk against lanes idling
- * behind the short last chunk of each sum and of each lane).  Must be a
- * multiple of 64 when nonzero.  Results do not depend on it. */
+ * sqrt(2 * 4096 * T / lanes) for a batch of T terms, between 2^12 and 2^22,
+ * which balances the set-up of each chunk against lanes idling when the last
+ * chunks finish).  Each sum is cut into chunks of exactly this many terms plus
+ * one shorter tail; the tails of all sums run after the full chunks, longest
+ * first.  Must be a multiple of 64 when nonzero.  Results do not depend on it. */
 int wv_set_chunk_terms(wv_ctx *ctx, uint64_t chunk_terms);
 
 /* Choose the block shape of the term-sum kernel: kb terms per block on the

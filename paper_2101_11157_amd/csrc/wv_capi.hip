@@ -112,8 +112,7 @@ int batch_shape(const wv_ctx *c, uint32_t n, uint64_t pmax, BatchShape *sh) {
     const double t_max = (double)n * ((double)pmax * cost + sh->nB + sh->nE);
     // the adaptive chunk grows with T, so T / chunk is largest at the bound
     const double chunk = chunk_cfg ? (double)chunk_cfg
-                                   : (double)adaptive_chunk((uint64_t)std::min(t_max, 1.8e19),
-                                                            sum_lanes(c) + sh->nseg);
+                                   : (double)adaptive_chunk((uint64_t)std::min(t_max, 1.8e19), sum_lanes(c));
     const double want = t_max / chunk + 2.0 * sh->nseg;
     sh->cap = (uint64_t)std::min<double>(std::max<double>(want, (double)kMinChunks), (double)kMaxChunks);
     sh->cap = std::max<uint64_t>(sh->cap, 2 * sh->nseg);
@@ -133,42 +132,47 @@ int prepare(wv_ctx *c, const BatchShape &sh) {
     WV_TRY(ensure(c, c->seg_pairs, nseg * sizeof(Pair)));
     WV_TRY(ensure(c, c->coefs, nseg * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->lhsmod, 2 * n * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->tails, nseg * sizeof(uint32_t)));
+    WV_TRY(ensure(c, c->tail_hist, 2 * kTailBuckets * sizeof(uint64_t)));
     return WV_OK;
 }
 
-// scal: [0] total terms, [1] chunk size, [2] chunk counter, [3] Bernoulli-side terms,
-//       [4] total chunks
+// scal: [0] total terms, [1..3] chunk layout {chunk size, full chunks, tails},
+//       [4] total chunks, [5] chunk counter, [6] Bernoulli-side terms
+constexpr int kScalTerms = 0, kScalLayout = 1, kScalChunks = 4, kScalCounter = 5, kScalTermsB = 6;
+
 int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st) {
     uint64_t *scal = as<uint64_t>(c->scal);
-    uint64_t *toff = as<uint64_t>(c->off);   // prefix of terms, then of chunks
+    uint64_t *toff = as<uint64_t>(c->off);   // prefix of terms, then of full chunks
     const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
     WV_HIP(launch_set_u64(st, scal, 8, 0));
     WV_HIP(launch_plan(st, d_primes, sh.n, sh.tb, sh.te, table_fallback(c, sh.tb), table_fallback(c, sh.te), sh.nB,
                        sh.nE, table_store(c), as<PrimeRec>(c->pr), as<SegRec>(c->segs), as<uint64_t>(c->terms),
                        as<uint64_t>(c->coefs), as<uint64_t>(c->lhsmod), 0));
     WV_HIP(launch_scan(st, as<uint64_t>(c->terms), sh.nseg, toff, as<uint64_t>(c->tiles)));
-    WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sum_lanes(c), sh.cap, scal + 1));
-    WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + 0, 1));
-    WV_HIP(launch_copy_u64(st, toff + (uint64_t)sh.n * sh.nB, scal + 3, 1));
-    WV_HIP(launch_chunk_count(st, as<uint64_t>(c->terms), sh.nseg, scal + 1, as<uint64_t>(c->cnt)));
-    WV_HIP(launch_scan(st, as<uint64_t>(c->cnt), sh.nseg, toff, as<uint64_t>(c->tiles)));
-    WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + 4, 1));
+    WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sum_lanes(c), sh.cap, scal + kScalLayout));
+    WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + kScalTerms, 1));
+    WV_HIP(launch_copy_u64(st, toff + (uint64_t)sh.n * sh.nB, scal + kScalTermsB, 1));
+    WV_HIP(launch_chunk_layout(st, as<uint64_t>(c->terms), sh.nseg, scal + kScalLayout, as<uint64_t>(c->cnt), toff,
+                               as<uint64_t>(c->tiles), as<unsigned long long>(c->tail_hist), as<uint32_t>(c->tails),
+                               scal + kScalChunks));
     return WV_OK;
 }
 
 int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end) {
     uint64_t *scal = as<uint64_t>(c->scal);
     const int v = c->variant;
-    WV_HIP(launch_set_u64(st, scal + 2, 1, begin));
+    WV_HIP(launch_set_u64(st, scal + kScalCounter, 1, begin));
     WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(c->segs), as<uint64_t>(c->off),
-                      (uint32_t)sh.nseg, as<PrimeRec>(c->pr), scal + 1, as<Pair>(c->partials),
-                      (unsigned long long *)(scal + 2), end));
+                      (uint32_t)sh.nseg, as<PrimeRec>(c->pr), scal + kScalLayout, as<uint32_t>(c->tails),
+                      as<Pair>(c->partials), as<Pair>(c->seg_pairs), (unsigned long long *)(scal + kScalCounter),
+                      end));
     return WV_OK;
 }
 
 int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out) {
     WV_HIP(launch_reduce(st, as<SegRec>(c->segs), as<uint64_t>(c->off), (uint32_t)sh.nseg, as<PrimeRec>(c->pr),
-                         as<Pair>(c->partials), as<Pair>(c->seg_pairs)));
+                         as<Pair>(c->partials), as<uint64_t>(c->scal) + kScalLayout, as<Pair>(c->seg_pairs)));
     WV_HIP(launch_finalize(st, table_store(c), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), as<uint64_t>(c->coefs),
                            as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out));
     return WV_OK;
@@ -197,7 +201,7 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
         uint64_t host[8];
         WV_HIP(hipMemcpyAsync(host, c->scal.ptr, sizeof(host), hipMemcpyDeviceToHost, st));
         WV_HIP(hipStreamSynchronize(st));
-        const uint64_t total = host[4], chunk = host[1];
+        const uint64_t total = host[kScalChunks], chunk = host[kScalLayout];
         const uint64_t per = std::max<uint64_t>(64, (c->launch_terms / std::max<uint64_t>(chunk, 1)) & ~63ull);
         for (uint64_t b = 0; b < total; b += per) {
             const uint64_t e = b + per >= total ? UINT64_MAX : b + per;   // ranges stay 64-aligned
@@ -210,7 +214,7 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
         }
     }
     WV_HIP(launch_reduce(st, as<SegRec>(c->segs), as<uint64_t>(c->off), (uint32_t)sh.nseg, as<PrimeRec>(c->pr),
-                         as<Pair>(c->partials), as<Pair>(c->seg_pairs)));
+                         as<Pair>(c->partials), as<uint64_t>(c->scal) + kScalLayout, as<Pair>(c->seg_pairs)));
     WV_HIP(hipEventRecord(c->ev[EV_RED], st));
     WV_HIP(launch_finalize(st, table_store(c), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), as<uint64_t>(c->coefs),
                            as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out));
@@ -228,10 +232,10 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
     s.ms_total += elapsed(c->ev[EV_PLAN0], c->ev[EV_FINAL]);
     s.n_primes += n;
     s.n_sums += sh.nseg;
-    s.n_chunks += host[4];
-    s.n_terms += host[0];
-    s.n_terms_b += host[3];
-    s.chunk_terms = host[1];
+    s.n_chunks += host[kScalChunks];
+    s.n_terms += host[kScalTerms];
+    s.n_terms_b += host[kScalTermsB];
+    s.chunk_terms = host[kScalLayout];
     s.block_k_b = (uint32_t)sum_variant_kb(c->variant);
     s.block_k_e = (uint32_t)sum_variant_ke(c->variant);
     s.grid = (uint32_t)c->sum_blocks[c->variant];
@@ -596,7 +600,7 @@ int wv_destroy(wv_ctx *c) {
     DevBuf *bufs[] = {&c->base_primes, &c->primes, &c->pr, &c->segs, &c->terms, &c->cnt, &c->off, &c->tiles,
                       &c->scal, &c->partials, &c->seg_pairs, &c->results, &c->seg_counts, &c->seg_bits,
                       &c->seg_off, &c->seg_desc, &c->pad_primes, &c->stats_hist, &c->stats_near, &c->coefs,
-                      &c->lhsmod, &c->tbl_head, &c->tbl_term, &c->tbl_limb};
+                      &c->lhsmod, &c->tbl_head, &c->tbl_term, &c->tbl_limb, &c->tails, &c->tail_hist};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (int i = 0; i < EV_COUNT; i++)

@@ -23,9 +23,10 @@ constexpr int kScanTile = 1024;                // elements per scan workgroup
 constexpr uint64_t kChunkSetup = 4096;         // set-up work of one chunk, in terms
 constexpr uint64_t kChunkMin = 1ull << 12;
 constexpr uint64_t kChunkMax = 1ull << 22;
+constexpr int kTailBuckets = 64;   // length classes of the tail chunks
 
 // Automatic chunk size for T terms: sqrt(2 S T / w), clamped, where w counts
-// the lanes of the grid plus the sums (see k_pick_chunk).
+// the lanes of the grid (see k_pick_chunk).
 __host__ __device__ inline uint64_t adaptive_chunk(uint64_t T, uint64_t w) {
     const double c = sqrt(2.0 * (double)kChunkSetup * (double)T / (double)(w ? w : 1));
     const uint64_t k = (uint64_t)c;
@@ -102,21 +103,29 @@ hipError_t launch_plan(hipStream_t st, const uint64_t *primes, uint32_t n, int t
                        uint64_t *lhsmod, uint32_t prime_base);
 hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64_t nseg, uint64_t chunk_cfg, uint64_t lanes,
                              uint64_t cap, uint64_t *chunk_out);
-hipError_t launch_chunk_count(hipStream_t st, const uint64_t *terms, uint64_t nseg, const uint64_t *chunk,
-                              uint64_t *cnt);
+// Chunk layout (layout = {C, full chunks, tails}; layout[0] set by the pick):
+// cnt[i] = full chunks of sum i, off = their exclusive prefix (off[nseg] =
+// full chunks), tails[0..) = the sums whose length C does not divide, longest
+// tail class first; *total_chunks = full chunks + tails.  hist holds
+// 2 kTailBuckets counters, scan_tiles as for launch_scan.
+hipError_t launch_chunk_layout(hipStream_t st, const uint64_t *terms, uint64_t nseg, uint64_t *layout,
+                               uint64_t *cnt, uint64_t *off, uint64_t *scan_tiles, unsigned long long *hist,
+                               uint32_t *tails, uint64_t *total_chunks);
 hipError_t launch_set_u64(hipStream_t st, uint64_t *dst, int n, uint64_t value);
 hipError_t launch_copy_u64(hipStream_t st, const uint64_t *src, uint64_t *dst, int n);
-// Persistent term sums over the chunks [begin, min(end, total)) of the plan;
-// the counter at *counter must hold `begin` (a multiple of 64).
+// Persistent term sums over the chunks [begin, min(end, total)) of a chunk
+// layout; the counter at *counter must hold `begin` (a multiple of 64).  Full
+// chunks leave pairs in partials, tails in seg_pairs[sum].
 int num_sum_variants();
 int sum_variant_kb(int v);
 int sum_variant_ke(int v);
 hipError_t sum_variant_occupancy(int v, int *blocks_per_cu);
 hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, const uint64_t *off, uint32_t nseg,
-                      const PrimeRec *pr, const uint64_t *chunk, Pair *partials, unsigned long long *counter,
-                      uint64_t end);
+                      const PrimeRec *pr, const uint64_t *layout, const uint32_t *tails, Pair *partials,
+                      Pair *seg_pairs, unsigned long long *counter, uint64_t end);
+// seg_pairs[j] <- the pairs of sum j's full chunks joined with its tail's
 hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
-                         const Pair *partials, Pair *seg_pairs);
+                         const Pair *partials, const uint64_t *layout, Pair *seg_pairs);
 hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *sp, const uint64_t *coefs,
                            const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out);
 hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec *pr, const Pair *sp, uint64_t nseg,

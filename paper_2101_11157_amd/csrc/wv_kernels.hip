@@ -409,16 +409,17 @@ __global__ void __launch_bounds__(256) k_copy_results(const wv_result *__restric
 // Chunk size: at least `chunk_cfg` terms, and large enough that the total
 // number of chunks stays within `max_chunks` (the partial-pair buffer).
 // Terms per lane chunk.  chunk_cfg > 0 is used as given; 0 picks
-// sqrt(2 S T / (lanes + nseg)) (S = kChunkSetup), which minimises the
-// per-chunk set-up of the blocked loop (about S terms of work per chunk) plus
-// the idle lanes behind short chunks (on average half a chunk per sum, at the
-// sum's ragged end, and per lane in the last round), clamped to
-// [kChunkMin, kChunkMax].  Either way at least T / (max_chunks - nseg), so
-// the partial pairs fit, rounded up to a multiple of 64.
+// sqrt(2 S T / lanes) (S = kChunkSetup), which minimises the per-chunk set-up
+// of the blocked loop (about S terms of work per chunk) plus the lanes left
+// idle when the last full chunks finish (about half a chunk per lane; the
+// sums' shorter tail chunks run last, sorted by length, and fill that gap),
+// clamped to [kChunkMin, kChunkMax].  Either way at least
+// T / (max_chunks - nseg), so the partial pairs fit, rounded up to a multiple
+// of 64.
 __global__ void k_pick_chunk(const uint64_t *__restrict__ total_terms, uint64_t nseg, uint64_t chunk_cfg,
                              uint64_t max_chunks, uint64_t lanes, uint64_t *__restrict__ chunk_out) {
     const uint64_t T = *total_terms;
-    uint64_t want = chunk_cfg ? chunk_cfg : adaptive_chunk(T, lanes + nseg);
+    uint64_t want = chunk_cfg ? chunk_cfg : adaptive_chunk(T, lanes);
     uint64_t room = max_chunks > nseg ? max_chunks - nseg : 1;
     uint64_t c = (T + room - 1) / room;
     c = max(c, want);
@@ -426,13 +427,75 @@ __global__ void k_pick_chunk(const uint64_t *__restrict__ total_terms, uint64_t 
     *chunk_out = max(c, (uint64_t)64);
 }
 
-__global__ void __launch_bounds__(256) k_chunk_count(const uint64_t *__restrict__ terms, uint64_t nseg,
-                                                     const uint64_t *__restrict__ chunk,
-                                                     uint64_t *__restrict__ cnt) {
+// Chunk layout of a batch: every sum of len terms gets len / C full chunks of
+// exactly C terms, numbered sum by sum, and, when C does not divide len, one
+// tail chunk of len % C terms.  The tails follow all full chunks, grouped into
+// kTailBuckets classes of length, longest first, so that the 64 chunks a wave
+// takes have (nearly) equal lengths and the shortest work comes last.
+__device__ __forceinline__ uint32_t tail_bucket(uint64_t rem, uint64_t C) {
+    // rem in [1, C): class 0 holds the longest tails
+    return kTailBuckets - 1 - (uint32_t)((rem * kTailBuckets) / C);
+}
+
+// cnt[i] = full chunks of sum i; tail lengths counted per class into hist.
+__global__ void __launch_bounds__(256) k_chunk_split(const uint64_t *__restrict__ terms, uint64_t nseg,
+                                                     const uint64_t *__restrict__ layout, uint64_t *__restrict__ cnt,
+                                                     unsigned long long *__restrict__ hist) {
+    __shared__ uint32_t local[kTailBuckets];
+    if (threadIdx.x < kTailBuckets) local[threadIdx.x] = 0;
+    __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= nseg) return;
-    const uint64_t C = *chunk;
-    cnt[i] = (terms[i] + C - 1) / C;
+    const uint64_t C = layout[0];
+    if (i < nseg) {
+        const uint64_t t = terms[i];
+        cnt[i] = t / C;
+        const uint64_t rem = t % C;
+        if (rem) atomicAdd(&local[tail_bucket(rem, C)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kTailBuckets && local[threadIdx.x])
+        atomicAdd(&hist[threadIdx.x], (unsigned long long)local[threadIdx.x]);
+}
+
+// One thread: first position of each class (cursor), the number of tails
+// (layout[2]) and of all chunks (*total = full + tails).
+__global__ void k_tail_base(const unsigned long long *__restrict__ hist, unsigned long long *__restrict__ cursor,
+                            uint64_t *__restrict__ layout, uint64_t *__restrict__ total) {
+    uint64_t acc = 0;
+    for (int b = 0; b < kTailBuckets; b++) {
+        cursor[b] = acc;
+        acc += hist[b];
+    }
+    layout[2] = acc;
+    *total = layout[1] + acc;
+}
+
+// tails[pos] = i for each sum with a tail, pos within its class's range.
+__global__ void __launch_bounds__(256) k_tail_place(const uint64_t *__restrict__ terms, uint64_t nseg,
+                                                    const uint64_t *__restrict__ layout,
+                                                    unsigned long long *__restrict__ cursor,
+                                                    uint32_t *__restrict__ tails) {
+    __shared__ uint32_t local[kTailBuckets];
+    __shared__ unsigned long long base[kTailBuckets];
+    if (threadIdx.x < kTailBuckets) local[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t C = layout[0];
+    uint32_t b = 0, rank = 0;
+    bool has = false;
+    if (i < nseg) {
+        const uint64_t rem = terms[i] % C;
+        if (rem) {
+            has = true;
+            b = tail_bucket(rem, C);
+            rank = atomicAdd(&local[b], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kTailBuckets && local[threadIdx.x])
+        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], (unsigned long long)local[threadIdx.x]);
+    __syncthreads();
+    if (has) tails[base[b] + rank] = (uint32_t)i;
 }
 
 // --------------------------------------------------------------------------
@@ -467,20 +530,22 @@ __device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont
 }
 
 // Persistent: each wave takes 64 consecutive chunks at a time from `counter`
-// until every chunk is done.  A wave whose chunks all belong to one sum stores
-// their butterfly product at partials[first chunk]; any other wave stores one
-// pair per chunk at partials[chunk].  KB / KE: terms per block on the
-// Bernoulli (s^3) and Euler (s^2) sides.
-// Two waves per SIMD (at most 256 registers per lane) keep the VALU fed; the
-// largest block shapes fill that budget with their difference tables.
+// until every chunk is done.  layout = {C, full chunks F, tails}: chunks below
+// F are full chunks (found through off, the prefix of full chunks per sum),
+// the others are the tails in the order of `tails`.  A wave whose chunks are
+// all full chunks of one sum stores their butterfly product at partials[first
+// chunk]; otherwise each full chunk stores its pair at partials[chunk] and
+// each tail at seg_pairs[sum].  KB / KE: terms per block on the Bernoulli
+// (s^3) and Euler (s^2) sides.
 template <int KB, int KE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_sum(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
-                                             uint32_t nseg, const PrimeRec *__restrict__ pr,
-                                             const uint64_t *__restrict__ chunk_ptr, Pair *__restrict__ partials,
-                                             unsigned long long *__restrict__ counter, uint64_t end) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_sum(
+    const SegRec *__restrict__ segs, const uint64_t *__restrict__ off, uint32_t nseg, const PrimeRec *__restrict__ pr,
+    const uint64_t *__restrict__ layout, const uint32_t *__restrict__ tails, Pair *__restrict__ partials,
+    Pair *__restrict__ seg_pairs, unsigned long long *__restrict__ counter, uint64_t end) {
     // chunks [counter start, min(end, total)); end is a multiple of 64 or past the total
-    const uint64_t total = min(off[nseg], end);
-    const uint64_t C = *chunk_ptr;
+    const uint64_t C = layout[0];
+    const uint64_t F = layout[1];
+    const uint64_t total = min(F + layout[2], end);
     const int lane = threadIdx.x & 63;
     // A wave can take at most total/64 + 1 batches; the bound is a second exit.
     const uint64_t max_iter = total / 64 + 2;
@@ -500,13 +565,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         // lanes that take no blocked loop do not lower the wave's shared counts
         uint32_t nb_lane = 0xffffffffu, period_lane = 0xffffffffu;
         if (active) {
-            seg = find_seg(off, nseg, chunk);
+            uint64_t o;
+            if (chunk < F) {
+                seg = find_seg(off, nseg, chunk);
+                o = (chunk - off[seg]) * C;
+            } else {
+                seg = tails[chunk - F];
+                o = segs[seg].len / C * C;
+            }
             const SegRec sr = segs[seg];
             const PrimeRec P = pr[sr.prime];
             m = mont_of(P);
             r2 = P.r2;
             one = P.one;
-            const uint64_t o = (chunk - off[seg]) * C;
             s0 = sr.lo + o;
             cnt = min(C, sr.len - o);
             deg = sr.deg;
@@ -525,18 +596,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         }
         const uint32_t seg0 = __builtin_amdgcn_readlane(seg, 0);
         const uint32_t segl = __builtin_amdgcn_readlane(seg, 63);
-        const bool uniform = (seg0 == segl) && (base + 63 < total);   // scalar
+        // all 64 chunks full (base + 64 <= F) and of one sum; scalar
+        const bool uniform = (seg0 == segl) && (base + 63 < F);
         if (uniform) {
             wave_pair_reduce(c0, c1, m);
             if (lane == 0) partials[base] = Pair{c0, c1};
         } else if (active) {
-            partials[chunk] = Pair{c0, c1};
+            if (chunk < F) partials[chunk] = Pair{c0, c1};
+            else seg_pairs[seg] = Pair{c0, c1};
         }
     }
 }
 
-typedef void (*SumKernel)(const SegRec *, const uint64_t *, uint32_t, const PrimeRec *, const uint64_t *, Pair *,
-                          unsigned long long *, uint64_t);
+typedef void (*SumKernel)(const SegRec *, const uint64_t *, uint32_t, const PrimeRec *, const uint64_t *,
+                          const uint32_t *, Pair *, Pair *, unsigned long long *, uint64_t);
 
 struct SumVariant {
     int kb, ke;
@@ -555,10 +628,14 @@ constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants
 // per-sum reduction and finalize
 // --------------------------------------------------------------------------
 
-// One wave per (prime, sum): joins the stored pairs of chunks [off[j], off[j+1]).
+// One wave per (prime, sum): joins the stored pairs of its full chunks
+// [off[j], off[j+1]) and, when C does not divide its length, the pair its tail
+// chunk left in seg_pairs[j]; the result replaces seg_pairs[j].
 __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
                                                 uint32_t nseg, const PrimeRec *__restrict__ pr,
-                                                const Pair *__restrict__ partials, Pair *__restrict__ seg_pairs) {
+                                                const Pair *__restrict__ partials,
+                                                const uint64_t *__restrict__ layout, Pair *__restrict__ seg_pairs) {
+    const uint64_t C = layout[0];
     // wave-stride loop: one launch covers at most 2^32 work-items, fewer than
     // 64 per sum when there are more than 2^26 sums
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -566,8 +643,14 @@ __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs,
     for (uint32_t jw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; jw < nseg; jw += nwaves) {
         const uint32_t j = __builtin_amdgcn_readfirstlane(jw);   // scalar: loop exits are wave-uniform
         const uint64_t a = off[j], b = off[j + 1];
-        const Mont m = mont_of(pr[segs[j].prime]);
+        const SegRec sr = segs[j];
+        const Mont m = mont_of(pr[sr.prime]);
         uint64_t c0 = 1, c1 = 0;
+        if (lane == 0 && sr.len % C) {
+            const Pair q = seg_pairs[j];
+            c0 = q.c0;
+            c1 = q.c1;
+        }
         const uint64_t ff = (a + 63) & ~63ull;   // first 64-aligned window start
         const uint64_t lf = b & ~63ull;          // end of the last full window
         if (ff >= lf) {
@@ -728,10 +811,22 @@ hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_count(hipStream_t st, const uint64_t *terms, uint64_t nseg, const uint64_t *chunk,
-                              uint64_t *cnt) {
+hipError_t launch_chunk_layout(hipStream_t st, const uint64_t *terms, uint64_t nseg, uint64_t *layout,
+                               uint64_t *cnt, uint64_t *off, uint64_t *scan_tiles, unsigned long long *hist,
+                               uint32_t *tails, uint64_t *total_chunks) {
     if (too_many(nseg)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_chunk_count, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg, chunk, cnt);
+    unsigned long long *cursor = hist + kTailBuckets;
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(2 * kTailBuckets), 0, st, (uint64_t *)hist, 2 * kTailBuckets,
+                       (uint64_t)0);
+    hipLaunchKernelGGL(k_chunk_split, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg,
+                       (const uint64_t *)layout, cnt, hist);
+    const hipError_t e = launch_scan(st, cnt, nseg, off, scan_tiles);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, st, (const uint64_t *)(off + nseg), layout + 1, 1);
+    hipLaunchKernelGGL(k_tail_base, dim3(1), dim3(1), 0, st, (const unsigned long long *)hist, cursor, layout,
+                       total_chunks);
+    hipLaunchKernelGGL(k_tail_place, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg,
+                       (const uint64_t *)layout, cursor, tails);
     return hipGetLastError();
 }
 
@@ -754,18 +849,18 @@ hipError_t sum_variant_occupancy(int v, int *blocks_per_cu) {
 }
 
 hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, const uint64_t *off, uint32_t nseg,
-                      const PrimeRec *pr, const uint64_t *chunk, Pair *partials, unsigned long long *counter,
-                      uint64_t end) {
-    hipLaunchKernelGGL(kSumVariants[v].fn, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, chunk, partials,
-                       counter, end);
+                      const PrimeRec *pr, const uint64_t *layout, const uint32_t *tails, Pair *partials,
+                      Pair *seg_pairs, unsigned long long *counter, uint64_t end) {
+    hipLaunchKernelGGL(kSumVariants[v].fn, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, layout, tails,
+                       partials, seg_pairs, counter, end);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
-                         const Pair *partials, Pair *seg_pairs) {
+                         const Pair *partials, const uint64_t *layout, Pair *seg_pairs) {
     // at most 2^20 workgroups (2^28 work-items; a dispatch holds < 2^32)
     const unsigned grid = std::min<unsigned>(blocks_for((uint64_t)nseg * 64, 256), 1u << 20);
-    hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, partials, seg_pairs);
+    hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, partials, layout, seg_pairs);
     return hipGetLastError();
 }
 

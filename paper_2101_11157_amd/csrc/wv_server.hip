@@ -62,7 +62,7 @@ struct wv_server {
     uint32_t pool = 1u << 16;
     int tb = 0, te = 0;        // congruences fixed at creation (the pool layout depends on them)
     int nB = 0, nE = 0, NS = 0;
-    DevBuf pr, segs, acc, terms, tmp, tasks, target, toff, tpairs, partials, res, scal, coefs, lhsmod;
+    DevBuf pr, segs, acc, terms, tmp, tasks, target, toff, tpairs, partials, res, scal, coefs, lhsmod, tails;
     std::vector<std::pair<uint32_t, uint32_t>> free_ranges;   // (first slot, count), sorted
     std::deque<Request *> pending;
     std::vector<Request *> active;
@@ -264,30 +264,40 @@ int run_step(wv_server *s) {
         const uint32_t prime = bern ? (uint32_t)(k / s->nB) : (uint32_t)((k - (size_t)t.r->n * s->nB) / s->nE);
         recs[j] = SegRec{t.r->seg_lo[k] + t.r->cursor[k], t.t, t.r->base + prime, bern ? 3u : 2u};
         tgt[j] = (uint32_t)((size_t)t.r->base * s->NS + k);
-        off[j + 1] = off[j] + (t.t + C - 1) / C;
+        off[j + 1] = off[j] + t.t / C;   // full chunks
         terms += t.t;
         (void)nseg_r;
     }
+    // tail chunks (tasks whose length C does not divide), longest first
+    std::vector<uint32_t> tails;
+    for (size_t j = 0; j < nt; j++)
+        if (tasks[j].t % C) tails.push_back((uint32_t)j);
+    std::stable_sort(tails.begin(), tails.end(),
+                     [&](uint32_t a, uint32_t b) { return tasks[a].t % C > tasks[b].t % C; });
     const uint64_t chunks = off[nt];
     WV_TRY(ensure(c, s->tasks, nt * sizeof(SegRec)));
     WV_TRY(ensure(c, s->target, nt * sizeof(uint32_t)));
     WV_TRY(ensure(c, s->toff, (nt + 1) * sizeof(uint64_t)));
     WV_TRY(ensure(c, s->tpairs, nt * sizeof(Pair)));
-    WV_TRY(ensure(c, s->partials, chunks * sizeof(Pair)));
+    WV_TRY(ensure(c, s->partials, std::max<uint64_t>(chunks, 1) * sizeof(Pair)));
+    WV_TRY(ensure(c, s->tails, std::max<size_t>(tails.size(), 1) * sizeof(uint32_t)));
     hipStream_t st = c->stream;
     WV_HIP(hipMemcpyAsync(s->tasks.ptr, recs.data(), nt * sizeof(SegRec), hipMemcpyHostToDevice, st));
     WV_HIP(hipMemcpyAsync(s->target.ptr, tgt.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     WV_HIP(hipMemcpyAsync(s->toff.ptr, off.data(), (nt + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    uint64_t *scal = as<uint64_t>(s->scal);   // [0] chunk size, [1] counter
-    WV_HIP(launch_set_u64(st, scal, 1, C));
-    WV_HIP(launch_set_u64(st, scal + 1, 1, 0));
+    if (!tails.empty())
+        WV_HIP(hipMemcpyAsync(s->tails.ptr, tails.data(), tails.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                              st));
+    const uint64_t layout[4] = {C, chunks, tails.size(), 0};   // chunk layout, then the counter
+    uint64_t *scal = as<uint64_t>(s->scal);
+    WV_HIP(hipMemcpyAsync(scal, layout, sizeof(layout), hipMemcpyHostToDevice, st));
     WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
     const int v = c->variant;
     WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt,
-                      as<PrimeRec>(s->pr), scal, as<Pair>(s->partials), (unsigned long long *)(scal + 1),
-                      UINT64_MAX));
+                      as<PrimeRec>(s->pr), scal, as<uint32_t>(s->tails), as<Pair>(s->partials),
+                      as<Pair>(s->tpairs), (unsigned long long *)(scal + 3), UINT64_MAX));
     WV_HIP(launch_reduce(st, as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt, as<PrimeRec>(s->pr),
-                         as<Pair>(s->partials), as<Pair>(s->tpairs)));
+                         as<Pair>(s->partials), scal, as<Pair>(s->tpairs)));
     WV_HIP(launch_fold(st, as<SegRec>(s->tasks), as<uint32_t>(s->target), as<Pair>(s->tpairs), (uint32_t)nt,
                        as<PrimeRec>(s->pr), as<Pair>(s->acc)));
     WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
@@ -372,7 +382,7 @@ int wv_server_destroy(wv_server *s) {
     if (!s) return WV_OK;
     if (s->c) (void)hipStreamSynchronize(s->c->stream);
     DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->tmp, &s->tasks, &s->target, &s->toff,
-                      &s->tpairs, &s->partials, &s->res, &s->scal, &s->coefs, &s->lhsmod};
+                      &s->tpairs, &s->partials, &s->res, &s->scal, &s->coefs, &s->lhsmod, &s->tails};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &kv : s->all) delete kv.second;

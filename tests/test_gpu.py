@@ -128,7 +128,7 @@ def test_ragged_batches(ctx):
         check_against_oracle(res)
 
 
-@pytest.mark.parametrize("chunk", [64, 192, 4096, 1 << 20])
+@pytest.mark.parametrize("chunk", [64, 192, 4096, 1 << 20, 1 << 30])
 def test_chunk_size_invariance(ctx, chunk):
     say(f"case: chunk {chunk}")
     ps = oracle.primes(10 ** 7, 10 ** 7 + 3000) + [1025793739, 73607557631]
