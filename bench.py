@@ -46,7 +46,15 @@ BLOCK_ADD = {2: 3, 3: 5}
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
 # (profiles/k_sum_window_1e11_*.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("1e11", "derived 687/438", 28, 36, 8192): 88146346 + 205643744}
+
+
+def tables_key(which):
+    """The congruences a traffic figure was measured with (derived: sum counts)."""
+    if which != "derived":
+        return which
+    import paper_2101_11157_amd as wv
+    return f"derived {wv.derived_table('B')['n']}/{wv.derived_table('E')['n']}"
 
 
 def renorm_period(p):
@@ -255,7 +263,8 @@ def main():
             "peak": peak,
             "unit": "Tops/s (full-rate VALU lane ops)",
             "frac": achieved / peak,
-            "traffic": MEASURED_TRAFFIC.get((args.config, args.tables, block[0], block[1], W)) if block else None,
+            "traffic": (MEASURED_TRAFFIC.get((args.config, tables_key(args.tables), block[0], block[1], W))
+                        if block else None),
         },
     }
     # the multiply view: the blocked loop needs few multiplies per term, so

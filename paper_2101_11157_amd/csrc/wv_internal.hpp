@@ -25,6 +25,11 @@ constexpr uint64_t kChunkMin = 1ull << 12;
 constexpr uint64_t kChunkMax = 1ull << 22;
 constexpr int kTailBuckets = 64;   // length classes of the tail chunks
 
+// Length class of a tail of rem in [1, C) terms; class 0 holds the longest.
+__host__ __device__ inline uint32_t tail_bucket(uint64_t rem, uint64_t C) {
+    return kTailBuckets - 1 - (uint32_t)((rem * kTailBuckets) / C);
+}
+
 // Automatic chunk size for T terms: sqrt(2 S T / w), clamped, where w counts
 // the lanes of the grid (see k_pick_chunk).
 __host__ __device__ inline uint64_t adaptive_chunk(uint64_t T, uint64_t w) {

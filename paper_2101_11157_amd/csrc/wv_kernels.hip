@@ -432,11 +432,6 @@ __global__ void k_pick_chunk(const uint64_t *__restrict__ total_terms, uint64_t 
 // tail chunk of len % C terms.  The tails follow all full chunks, grouped into
 // kTailBuckets classes of length, longest first, so that the 64 chunks a wave
 // takes have (nearly) equal lengths and the shortest work comes last.
-__device__ __forceinline__ uint32_t tail_bucket(uint64_t rem, uint64_t C) {
-    // rem in [1, C): class 0 holds the longest tails
-    return kTailBuckets - 1 - (uint32_t)((rem * kTailBuckets) / C);
-}
-
 // cnt[i] = full chunks of sum i; tail lengths counted per class into hist.
 __global__ void __launch_bounds__(256) k_chunk_split(const uint64_t *__restrict__ terms, uint64_t nseg,
                                                      const uint64_t *__restrict__ layout, uint64_t *__restrict__ cnt,

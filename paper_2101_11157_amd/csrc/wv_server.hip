@@ -268,12 +268,16 @@ int run_step(wv_server *s) {
         terms += t.t;
         (void)nseg_r;
     }
-    // tail chunks (tasks whose length C does not divide), longest first
-    std::vector<uint32_t> tails;
+    // tail chunks (tasks whose length C does not divide) by length class,
+    // longest first (counting sort, as the batch plan does on the device)
+    std::vector<uint32_t> cls(nt, kTailBuckets);
+    uint64_t first[kTailBuckets + 1] = {};
     for (size_t j = 0; j < nt; j++)
-        if (tasks[j].t % C) tails.push_back((uint32_t)j);
-    std::stable_sort(tails.begin(), tails.end(),
-                     [&](uint32_t a, uint32_t b) { return tasks[a].t % C > tasks[b].t % C; });
+        if (const uint64_t rem = tasks[j].t % C) first[(cls[j] = tail_bucket(rem, C)) + 1]++;
+    for (int b = 0; b < kTailBuckets; b++) first[b + 1] += first[b];
+    std::vector<uint32_t> tails(first[kTailBuckets]);
+    for (size_t j = 0; j < nt; j++)
+        if (cls[j] < (uint32_t)kTailBuckets) tails[first[cls[j]]++] = (uint32_t)j;
     const uint64_t chunks = off[nt];
     WV_TRY(ensure(c, s->tasks, nt * sizeof(SegRec)));
     WV_TRY(ensure(c, s->target, nt * sizeof(uint32_t)));
