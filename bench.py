@@ -36,17 +36,17 @@ OPS_ADDM = 3        # one modular addition: add, subtract, select
 OPS_FMUL = 6        # one double-precision modular product: mul, 3 fma, 2 add
 OPS_FRED = 3        # one double-precision reduction: fma, add, fma
 # per block of the Taylor-coefficient loop: modular products, reductions of
-# the g_k entering them, and plain additions (d = 2: P, g0 g2, g1^2 and the
-# three updates of the running pair; d = 3: g0^2, P, g3 g0^2, g0 g1 g2,
-# g1^3 and the three updates)
+# the g_k entering them (g0 and g1), and plain additions (d = 2: P, g0 g2,
+# g1^2 and the three updates of the running pair; d = 3: g0^2, P, g3 g0^2,
+# g0 g1 g2, g1^3 and the three updates)
 BLOCK_FMUL = {2: 6, 3: 10}
-BLOCK_FRED = {2: 3, 3: 4}
+BLOCK_FRED = {2: 2, 3: 2}
 BLOCK_ADD = {2: 3, 3: 5}
 
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
 # (profiles/k_sum_window_1e11_*.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {("1e11", "derived 687/438", 28, 36, 8192): 88146346 + 205643744}
+MEASURED_TRAFFIC = {}
 
 
 def tables_key(which):

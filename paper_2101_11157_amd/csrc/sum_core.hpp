@@ -61,11 +61,12 @@ __host__ __device__ __forceinline__ double opaque_f(double x) {
 //   h = ab rounded;  l = fma(a, b, -h) = ab - h exactly (an error-free product);
 //   q = the integer nearest h * (1/p) (fma with 1.5 * 2^52, then subtract it);
 //   r = fma(-q, p, h) + l.
-// With |ab| <= 300 p^2 (every product below stays within it): h/p < 2^49, so the rounding
-// trick applies; |q - h/p| <= 1/2 + h 2^-53 / p, so h - qp is an integer below
-// p in magnitude and the fma computes it exactly; l is an integer with
-// |l| <= h 2^-53; hence r = ab - qp exactly, r == ab (mod p), and
-// |r| <= p/2 + 2 h 2^-53 <= p/2 + 600 p 2^-13 <= 0.574 p.
+// With |ab| < 2^51 p: |h / p| < 2^51, so the rounding trick applies;
+// |q - h/p| <= 1/2 + |h| 2^-53 / p, so h - qp is an integer of magnitude at
+// most p/2 + |h| 2^-53 < p and the fma computes it exactly; l is an integer with
+// |l| <= |h| 2^-53; hence r = ab - qp exactly, r == ab (mod p), and
+// |r| <= p/2 + |ab| 2^-52.  For residues (|ab| <= 300 p^2, p < 2^40) that is
+// below p/2 + 600 p 2^-13 <= 0.574 p.
 struct Fmod {
     double p, pinv;   // p, round(1/p)
 };
@@ -114,14 +115,19 @@ __host__ __device__ __forceinline__ double f_pow(double s, const Fmod &f) {
 // So only g_0..g_d (degrees K..K-d in x) are stepped by finite differences
 // along x = s0, s0 + K, ...: (d+1)K - d(d+1)/2 additions per block, where
 // stepping P and Q themselves (degrees dK and d(K-1)) would take d(2K-1), for
-// a few more products per block.  The g_k entering the products are reduced
-// first (|g| < 0.51p), so every product stays within f_mulmod's bounds
-// (|Q| < 4.1p, |a0 Q| < 2.4 p^2).  The tables themselves only need to stay
-// exact integers.  After a reduction every entry is below 0.51p, and after t
+// a few more products per block.
+//
+// Bounds.  After a reduction every table entry is below 0.51p, and after t
 // blocks entry i is sum_m C(t, m) D_{i+m} < 0.51p 2^t; fresh tables differ only
 // in their value entries (up to 2.3p), which adds less than 1.8p < 0.064p 2^t
-// for t >= 5.  So for p < 2^b (b <= 40) the tables are reduced every 53 - b
-// >= 13 blocks (0.574 2^53 < 2^53; 16 blocks at p < 2^37).  Returns plain
+// for t >= 5: every entry stays below 0.574p 2^t.  For p < 2^b (b <= 40) the
+// tables are reduced every 53 - b >= 13 blocks (16 at p < 2^37), so they stay
+// exact integers (0.574 2^53 < 2^53), and a value entry used in a product (at
+// most 52 - b blocks after a reduction) is below 0.574 2^52.  g0 and g1 are
+// reduced first (|r| < 0.51p); g2 and g3 enter unreduced, each times a reduced
+// operand or a product of two (|x| < 0.574p), so |ab| < 0.33 p 2^52 = 2^50.4 p,
+// inside f_mulmod's exact range (|ab| < 2^51 p), with |result| < 0.83p.  Then
+// |Q| < 5.6p (d = 3) or 2.3p (d = 2), and |a0 Q| < 3.3 p^2.  Returns plain
 // residues in [0, p) with the same ratio c1/c0 as run_chunk.
 //
 // nb_shared, period_shared: a block count and a reduction period that every
@@ -183,16 +189,18 @@ WV_UNROLL
         }
         // one block: fold P, Q into the running pair, step every table once
         auto step = [&]() {
+            // g0 and g1 are squared, so they are reduced; g2 and g3 only meet
+            // reduced partners and enter unreduced
             const double r0 = f_reduce(G[0], f);
             const double r1 = f_reduce(G[K + 1], f);
-            const double r2 = f_reduce(G[2 * K + 1], f);
+            const double r2 = G[2 * K + 1];
             double P, Q;
             if (DEG == 2) {
                 P = f_mulmod(r0, r0, f);
                 const double u = f_mulmod(r0, r2, f);
                 Q = f_mulmod(r1, r1, f) - (u + u);
             } else {
-                const double r3 = f_reduce(G[3 * K], f);
+                const double r3 = G[3 * K];
                 const double sq = f_mulmod(r0, r0, f);
                 P = f_mulmod(sq, r0, f);
                 const double A = f_mulmod(r3, sq, f);

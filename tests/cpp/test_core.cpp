@@ -191,10 +191,11 @@ int main() {
             f.p = (double)p;
             f.pinv = 1.0 / f.p;
             auto smod = [&](__int128 v) { __int128 r = v % (__int128)p; return (uint64_t)(r < 0 ? r + p : r); };
-            auto chkm = [&](int64_t a, int64_t b) {
+            // |r| <= p/2 + |ab| 2^-52 (plus rounding slack) for |ab| < 2^51 p
+            auto chkm = [&](int64_t a, int64_t b, double bound) {
                 const double r = f_mulmod((double)a, (double)b, f);
                 const __int128 want = (__int128)a * b;
-                if (r != std::floor(r) || std::fabs(r) > 0.574 * f.p || smod((__int128)(int64_t)r) != smod(want)) {
+                if (r != std::floor(r) || std::fabs(r) > bound * f.p || smod((__int128)(int64_t)r) != smod(want)) {
                     printf("FAIL f_mulmod p=%llu a=%lld b=%lld r=%.1f\n", (unsigned long long)p, (long long)a,
                            (long long)b, r);
                     return false;
@@ -202,19 +203,36 @@ int main() {
                 checks++;
                 return true;
             };
-            const int64_t A = (int64_t)(1.148 * (double)p), B = (int64_t)(261.2 * (double)p);
+            // residues and running pair: |a| <= 2.3p (unreduced set-up entries,
+            // the pair's c1), |b| <= 5.6p (Q of the s^-3 loop)
+            const int64_t A = (int64_t)(2.3 * (double)p), B = (int64_t)(5.6 * (double)p);
             const int64_t ea[] = {0, 1, -1, A, -A, (int64_t)p / 2, -(int64_t)p / 2, (int64_t)p - 1};
             const int64_t eb[] = {0, 1, -1, B, -B, B - 1, (int64_t)p, -(int64_t)p, (int64_t)(0.51 * (double)p)};
             for (int64_t a : ea)
                 for (int64_t b : eb)
-                    if (!chkm(a, b)) return 1;
+                    if (!chkm(a, b, 0.574)) return 1;
             for (int k = 0; k < 20000; k++) {
                 const int64_t a = (int64_t)(rng() % (2 * (uint64_t)A + 1)) - A;
                 const int64_t b = (int64_t)(rng() % (2 * (uint64_t)B + 1)) - B;
-                if (!chkm(a, b)) return 1;
+                if (!chkm(a, b, 0.574)) return 1;
+            }
+            // a table value entry entering a product unreduced, 53 - bitlen(p)
+            // blocks after a reduction at most (|G| <= 0.574 p 2^(52 - bitlen)),
+            // times a reduced operand (|x| <= 0.574 p): |r| <= 0.83 p
+            const int bl = 64 - __builtin_clzll(p);
+            const int64_t Gm = (int64_t)std::ldexp(0.574 * (double)p, 52 - bl), X = (int64_t)(0.574 * (double)p);
+            const int64_t eg[] = {Gm, -Gm, Gm - 1, Gm / 3, 1};
+            const int64_t ex[] = {X, -X, X - 1, 1, -1, 0};
+            for (int64_t g : eg)
+                for (int64_t x : ex)
+                    if (!chkm(g, x, 0.83)) return 1;
+            for (int k = 0; k < 20000; k++) {
+                const int64_t g = (int64_t)(rng() % (2 * (uint64_t)Gm + 1)) - Gm;
+                const int64_t x = (int64_t)(rng() % (2 * (uint64_t)X + 1)) - X;
+                if (!chkm(g, x, 0.83)) return 1;
             }
             for (int k = 0; k < 20000; k++) {
-                const int64_t x = (int64_t)(rng() % (1ull << 49)) - (int64_t)(1ull << 48);
+                const int64_t x = (int64_t)(rng() % ((1ull << 54) + 1)) - (int64_t)(1ull << 53);
                 const double r = f_reduce((double)x, f);
                 if (std::fabs(r) > 0.51 * f.p || smod((__int128)(int64_t)r) != smod(x)) {
                     printf("FAIL f_reduce p=%llu x=%lld\n", (unsigned long long)p, (long long)x);
