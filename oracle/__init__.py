@@ -11,8 +11,9 @@ Layers (all cite Booker, Hathi, Mossinghoff, Trudgian, arXiv:2101.11157):
                       (Section 1) and Glaisher's congruence (eqnGlaisher).
 * ``congruences``  -- the paper's congruences typed in as data (Sections 2-5).
 * ``wv_oracle.c``  -- C with unsigned __int128 and ``%``: the sums S_l(x,y) of
-                      eqnDefnS, directly or by eqnComputeS, the recurrences mod p,
-                      harmonic sums mod p^2 and a plain sieve.
+                      eqnDefnS, directly or by eqnComputeS, the recurrences mod p
+                      (B_{p-3}, E_{p-3}, and every B_{2k}, E_{2k} with 2k <= p-3 for
+                      irregular pairs), harmonic sums mod p^2 and a plain sieve.
 
 The reference answer for a prime p (``residues``):
 
@@ -82,6 +83,10 @@ def lib():
         L.orc_bernoulli_rec.argtypes = [U64]
         L.orc_euler_rec.restype = U64
         L.orc_euler_rec.argtypes = [U64]
+        L.orc_bernoulli_all.restype = None
+        L.orc_bernoulli_all.argtypes = [U64, P_U64]
+        L.orc_euler_all.restype = None
+        L.orc_euler_all.argtypes = [U64, P_U64]
         L.orc_harmonic2_mod_p2.restype = U64
         L.orc_harmonic2_mod_p2.argtypes = [U64]
         L.orc_harmonic1_mod_p2.restype = U64
@@ -200,6 +205,36 @@ def bernoulli_rec(p):
 def euler_rec(p):
     """E_{p-3} mod p from sec*cos = 1 run in F_p (O(p^2))."""
     return lib().orc_euler_rec(p)
+
+
+def bernoulli_all(p):
+    """[B_2, B_4, ..., B_{p-3}] mod p from the EGF recurrence in F_p (O(p^2))."""
+    n = (p - 3) // 2
+    out = (ctypes.c_uint64 * max(n, 1))()
+    lib().orc_bernoulli_all(p, out)
+    return [int(v) for v in out[:n]]
+
+
+def euler_all(p):
+    """[E_2, E_4, ..., E_{p-3}] mod p from sec*cos = 1 in F_p (O(p^2))."""
+    n = (p - 3) // 2
+    out = (ctypes.c_uint64 * max(n, 1))()
+    lib().orc_euler_all(p, out)
+    return [int(v) for v in out[:n]]
+
+
+def irregular_pairs(p):
+    """Irregular pairs (p, 2k) (p | B_{2k}) and E-irregular pairs (p | E_{2k})
+    with 2 <= 2k <= p - 3 (Section 1): sorted (p, 2k, kind), kind 1 for B,
+    2 for E."""
+    b, e = bernoulli_all(p), euler_all(p)
+    out = []
+    for k in range(1, len(b) + 1):
+        if b[k - 1] == 0:
+            out.append((p, 2 * k, 1))
+        if e[k - 1] == 0:
+            out.append((p, 2 * k, 2))
+    return out
 
 
 def harmonic2_mod_p2(p):

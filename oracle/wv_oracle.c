@@ -23,6 +23,9 @@
  *                         z/(e^z-1) implies (Section 1, Bernoulli EGF)
  *   orc_euler_rec         E_{p-3} mod p from sec z * cos z = 1 (Section 1,
  *                         Euler EGF, secant convention)
+ *   orc_bernoulli_all,    B_{2k} mod p and E_{2k} mod p for every 2k <= p-3
+ *   orc_euler_all         (the same two recurrences, every even index kept;
+ *                         irregular and E-irregular pairs, Section 1)
  *   orc_harmonic2_mod_p2  sum_{0<k<p} k^-2 mod p^2 (Section 1, eqnWolst)
  *   orc_harmonic1_mod_p2  sum_{0<k<p} k^-1 mod p^2 (Section 1, first display)
  *   orc_primes            plain sieve of Eratosthenes on [lo, hi)
@@ -236,6 +239,57 @@ uint64_t orc_euler_rec(uint64_t p) {
     free(E);
     free(row);
     return r;
+}
+
+/* B_{2k} mod p into out[k-1] for k = 1 .. (p-3)/2: the recurrence of
+ * orc_bernoulli_rec, every even index kept.  O(p^2); for small p. */
+void orc_bernoulli_all(uint64_t p, uint64_t *out) {
+    uint64_t n_max = p - 3;
+    uint64_t *B = (uint64_t *)calloc(n_max + 1, sizeof(uint64_t));
+    uint64_t *row = (uint64_t *)calloc(p + 1, sizeof(uint64_t));
+    B[0] = 1;
+    row[0] = 1;
+    uint64_t n_row = 0;
+    for (uint64_t m = 1; m <= n_max; m++) {
+        while (n_row < m + 1) {
+            n_row++;
+            row[n_row] = 1;
+            for (uint64_t j = n_row - 1; j >= 1; j--) row[j] = addmod(row[j], row[j - 1], p);
+        }
+        uint64_t acc = 0;
+        for (uint64_t j = 0; j < m; j++) acc = addmod(acc, mulmod(row[j], B[j], p), p);
+        B[m] = mulmod((p - acc) % p, orc_invmod((m + 1) % p, p), p);
+    }
+    for (uint64_t k = 1; 2 * k <= n_max; k++) out[k - 1] = B[2 * k];
+    free(B);
+    free(row);
+}
+
+/* E_{2k} mod p into out[k-1] for k = 1 .. (p-3)/2: the recurrence of
+ * orc_euler_rec, every even index kept.  O(p^2); for small p. */
+void orc_euler_all(uint64_t p, uint64_t *out) {
+    uint64_t n_max = p - 3;
+    uint64_t *E = (uint64_t *)calloc(n_max + 1, sizeof(uint64_t));
+    uint64_t *row = (uint64_t *)calloc(p + 1, sizeof(uint64_t));
+    E[0] = 1;
+    row[0] = 1;
+    uint64_t n_row = 0;
+    for (uint64_t n = 1; n <= n_max; n++) {
+        while (n_row < n) {
+            n_row++;
+            row[n_row] = 1;
+            for (uint64_t j = n_row - 1; j >= 1; j--) row[j] = addmod(row[j], row[j - 1], p);
+        }
+        uint64_t acc = 0;
+        for (uint64_t j = 1; 2 * j <= n; j++) {
+            uint64_t t = mulmod(row[2 * j], E[n - 2 * j], p);
+            acc = (j & 1) ? submod(acc, t, p) : addmod(acc, t, p);
+        }
+        E[n] = (p - acc) % p;
+    }
+    for (uint64_t k = 1; 2 * k <= n_max; k++) out[k - 1] = E[2 * k];
+    free(E);
+    free(row);
 }
 
 /* sum_{0<k<p} k^-2 mod p^2, one inverse mod p^2 per term (p < 2^31). */

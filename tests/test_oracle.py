@@ -407,3 +407,61 @@ def test_residue_stats_near_misses_from_table_2_and_3():
         cut = sorted(abs(r) for _, r in rows[:4])[2]
         _, _, near = oracle.residue_stats(data, bins=2000, bound=cut)
         assert near == sorted(((p, r, which) for p, r in rows[:4] if abs(r) < cut), key=lambda t: (t[0], t[2]))
+
+
+# ---------------------------------------------------------------------------
+# Every index: irregular and E-irregular pairs (Section 1)
+# ---------------------------------------------------------------------------
+
+
+def test_all_index_recurrences_match_exact_rationals():
+    """B_{2k}, E_{2k} mod p for every 2k <= p - 3 equal the exact EGF
+    coefficients reduced mod p (textbook values, independent of the oracle)."""
+    ps = small_primes(5, 200)
+    B = exact.bernoulli_egf(ps[-1] - 3)
+    E = [int(x) for x in exact.euler_egf(ps[-1] - 3)]
+    for p in ps:
+        want_b = [exact.rational_mod_p(B[2 * k], p) for k in range(1, (p - 3) // 2 + 1)]
+        want_e = [E[2 * k] % p for k in range(1, (p - 3) // 2 + 1)]
+        assert oracle.bernoulli_all(p) == want_b, p
+        assert oracle.euler_all(p) == want_e, p
+
+
+def test_all_index_last_entry_is_the_p_minus_3_residue():
+    for p in small_primes(7, 400):
+        assert oracle.bernoulli_all(p)[-1] == b_rec(p)
+        assert oracle.euler_all(p)[-1] == e_rec(p)
+
+
+def test_smallest_irregular_and_e_irregular_primes():
+    """Section 1: 37 is the smallest irregular prime, 19 the smallest
+    E-irregular one (19 | E_10)."""
+    first_b = next(p for p in small_primes(5, 100) if any(x[2] == 1 for x in oracle.irregular_pairs(p)))
+    first_e = next(p for p in small_primes(5, 100) if any(x[2] == 2 for x in oracle.irregular_pairs(p)))
+    assert first_b == 37 and first_e == 19
+    assert (19, 10, 2) in oracle.irregular_pairs(19)
+
+
+def test_wolstenholme_and_vandiver_primes_are_extremal_pairs():
+    """Section 1: (p, p-3) is an irregular pair at a Wolstenholme prime and an
+    E-irregular pair at a Vandiver prime."""
+    assert (16843, 16840, 1) in oracle.irregular_pairs(16843)
+    for p in (149, 241):
+        assert (p, p - 3, 2) in oracle.irregular_pairs(p)
+
+
+def test_e_index_of_5783_is_five():
+    """Section 1: p = 5783 has index of E-irregularity 5."""
+    assert sum(1 for x in oracle.irregular_pairs(5783) if x[2] == 2) == 5
+
+
+@pytest.mark.slow
+def test_e_irregularity_census_below_10_4():
+    """Section 1: below 10^4 the largest index of E-irregularity is 5,
+    attained by 5783 alone."""
+    from concurrent.futures import ThreadPoolExecutor
+    ps = small_primes(5, 10 ** 4)
+    with ThreadPoolExecutor(8) as ex:
+        idx = dict(zip(ps, ex.map(lambda p: sum(1 for x in oracle.irregular_pairs(p) if x[2] == 2), ps)))
+    top = max(idx.values())
+    assert top == 5 and [p for p, v in idx.items() if v == top] == [5783]
