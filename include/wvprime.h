@@ -221,6 +221,43 @@ int wv_range_stats(wv_ctx *ctx, uint64_t lo, uint64_t hi, uint32_t bins, uint64_
                    uint64_t *hist_b, uint64_t *hist_e, wv_near *near, size_t near_cap, size_t *n_near,
                    uint64_t *n_primes);
 
+/* ---- every index: irregular and E-irregular pairs (Section 1) --------------
+ *
+ * (p, 2k) is an irregular pair when p | B_{2k} and an E-irregular pair when
+ * p | E_{2k} (secant convention), 2 <= 2k <= p - 3.  The residues come from
+ * the paper's congruences for general index: B_{2k} from
+ * C_k(a,b,c) B_{2k} == sum S_{2k-1}(x, y) (Section 2, with C_k(a,b,c) =
+ * (a^{p-2k} + b^{p-2k} - c^{p-2k} - 1) / (4k)) for the family (2, b, b+1)
+ * over sum_{m <= b/2} (m/(b+1), m/b): b = 3, i.e. (1/4, 1/3), and, for the k
+ * where its C_k vanishes mod p, b = 4, 5, ... up to 64; E_{2k} from eqnE1
+ * (Section 5) with the sign read as (-1)^k.  The power sums of every exponent
+ * run on the device: about p^2 / 6 terms per prime. */
+#define WV_IRR_P_MAX (1ULL << 27)
+
+typedef struct {
+    uint64_t p;
+    uint32_t two_k;   /* the index 2k */
+    uint32_t kind;    /* 1: p | B_{2k} (irregular pair); 2: p | E_{2k} (E-irregular pair) */
+} wv_irr_pair;
+
+/* B_{2k} mod p and E_{2k} mod p for 2k = 2, 4, ..., p - 3 of one prime:
+ * b[k-1] = B_{2k} mod p, e[k-1] = E_{2k} mod p in [0, p), k = 1 .. (p-3)/2
+ * (caller-owned arrays of (p - 3) / 2 entries).  b[k-1] = UINT64_MAX marks a
+ * k where every congruence of the chain degenerates.
+ * Errors: WV_EINVAL (NULL), WV_EDOMAIN (p < 5 or p >= WV_IRR_P_MAX),
+ * WV_ENOTPRIME, WV_ENOMEM, WV_EHIP. */
+int wv_bernoulli_euler_all(wv_ctx *ctx, uint64_t p, uint64_t *b, uint64_t *e);
+
+/* All irregular and E-irregular pairs of the primes p in [lo, hi) (p >= 5),
+ * sorted by (p, 2k, kind) into out (caller-owned, cap entries).  *n_out: the
+ * number of pairs; n_primes (optional): primes examined; n_unresolved
+ * (optional): indices whose congruence chain degenerated (not reported as
+ * pairs).  Short buffer: WV_ETRUNC with *n_out set, nothing written.
+ * Errors: WV_EINVAL, WV_EDOMAIN (hi > WV_IRR_P_MAX), WV_ETRUNC, WV_ENOMEM,
+ * WV_EHIP. */
+int wv_irregular_pairs(wv_ctx *ctx, uint64_t lo, uint64_t hi, wv_irr_pair *out, size_t cap, size_t *n_out,
+                       uint64_t *n_primes, uint64_t *n_unresolved);
+
 /* Batched search over nwin windows [lo[w], hi[w]) (may differ in size and
  * position): all windows are sieved together and all their primes go through
  * one plan and one persistent term-sum launch per batch of about 2^19 primes,

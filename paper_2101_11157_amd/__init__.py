@@ -53,6 +53,10 @@ def _frac(a, b):
 # compiled block shapes of the term-sum kernel, in the library's order
 BLOCK_SHAPES = [(1, 1), (4, 4), (8, 8), (12, 16), (16, 24), (20, 28), (24, 32), (26, 34), (28, 32), (28, 36)]
 
+# wv_irr_pair as a numpy record (16 bytes)
+IRR_PAIR_DTYPE = np.dtype([("p", "<u8"), ("two_k", "<u4"), ("kind", "<u4")])
+IRR_P_MAX = 1 << 27
+
 # wv_result as a numpy record (32 bytes)
 RESULT_DTYPE = np.dtype([("p", "<u8"), ("b", "<u8"), ("e", "<u8"), ("flags", "<u4"), ("reserved", "<u4")])
 # wv_near (24 bytes): a prime with a small symmetric residue; which = 1 (B) or 2 (E)
@@ -136,6 +140,8 @@ def lib():
                                                P_U64, P_U64, P_U64, P_U64, U64, ctypes.POINTER(ctypes.c_int)]),
             "wv_range_stats": (ctypes.c_int, [VP, U64, U64, ctypes.c_uint32, U64, P_U64, P_U64, VP, SZ,
                                               ctypes.POINTER(SZ), P_U64]),
+            "wv_bernoulli_euler_all": (ctypes.c_int, [VP, U64, P_U64, P_U64]),
+            "wv_irregular_pairs": (ctypes.c_int, [VP, U64, U64, VP, SZ, ctypes.POINTER(SZ), P_U64, P_U64]),
             "wv_autotune": (ctypes.c_int, [VP, U64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), P_U64, ctypes.POINTER(ctypes.c_double)]),
             "wv_tune_save": (ctypes.c_int, [VP, ctypes.c_char_p]),
@@ -335,6 +341,31 @@ class Context:
                                       ctypes.byref(n_near), ctypes.byref(n_primes))
         _check(st, "wv_range_stats")
         return hb, he, nr[:n_near.value], n_primes.value
+
+    def bernoulli_euler_all(self, p):
+        """(b, e): B_{2k} mod p and E_{2k} mod p for 2k = 2, 4, ..., p - 3
+        (uint64 arrays indexed by k - 1), from the general-index congruences."""
+        n = (int(p) - 3) // 2
+        b = np.zeros(max(n, 1), dtype=np.uint64)
+        e = np.zeros(max(n, 1), dtype=np.uint64)
+        _check(lib().wv_bernoulli_euler_all(self._h, int(p), b.ctypes.data_as(P_U64), e.ctypes.data_as(P_U64)),
+               "wv_bernoulli_euler_all")
+        return b[:n], e[:n]
+
+    def irregular_pairs(self, lo, hi, cap=4096):
+        """Irregular (kind 1) and E-irregular (kind 2) pairs (p, 2k) of the
+        primes in [lo, hi): (IRR_PAIR_DTYPE array sorted by p, 2k, kind,
+        primes examined, unresolved indices)."""
+        out = np.zeros(max(1, cap), dtype=IRR_PAIR_DTYPE)
+        n, n_primes, n_unres = SZ(), U64(), U64()
+        st = lib().wv_irregular_pairs(self._h, int(lo), int(hi), out.ctypes.data_as(VP), cap, ctypes.byref(n),
+                                      ctypes.byref(n_primes), ctypes.byref(n_unres))
+        if st == WV_ETRUNC:
+            out = np.zeros(n.value, dtype=IRR_PAIR_DTYPE)
+            st = lib().wv_irregular_pairs(self._h, int(lo), int(hi), out.ctypes.data_as(VP), n.value,
+                                          ctypes.byref(n), ctypes.byref(n_primes), ctypes.byref(n_unres))
+        _check(st, "wv_irregular_pairs")
+        return out[:n.value], n_primes.value, n_unres.value
 
     def set_progress(self, fn=None, terms_per_launch=0):
         """Callback fn(done, total) between term-sum launches of long calls (None: off)."""

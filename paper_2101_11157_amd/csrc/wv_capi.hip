@@ -600,7 +600,9 @@ int wv_destroy(wv_ctx *c) {
     DevBuf *bufs[] = {&c->base_primes, &c->primes, &c->pr, &c->segs, &c->terms, &c->cnt, &c->off, &c->tiles,
                       &c->scal, &c->partials, &c->seg_pairs, &c->results, &c->seg_counts, &c->seg_bits,
                       &c->seg_off, &c->seg_desc, &c->pad_primes, &c->stats_hist, &c->stats_near, &c->coefs,
-                      &c->lhsmod, &c->tbl_head, &c->tbl_term, &c->tbl_limb, &c->tails, &c->tail_hist};
+                      &c->lhsmod, &c->tbl_head, &c->tbl_term, &c->tbl_limb, &c->tails, &c->tail_hist,
+                      &c->irr_tasks, &c->irr_units, &c->irr_primes, &c->irr_roff, &c->irr_v, &c->irr_fix,
+                      &c->irr_counts, &c->irr_pairs, &c->irr_b, &c->irr_e};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (int i = 0; i < EV_COUNT; i++)

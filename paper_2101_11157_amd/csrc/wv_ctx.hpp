@@ -99,7 +99,8 @@ struct wv_ctx {
     uint64_t gen = 0;                             // bumped on every device reallocation
     wv::DevBuf base_primes, primes, pr, segs, terms, cnt, off, tiles, scal, partials, seg_pairs, results,
         seg_counts, seg_bits, seg_off, seg_desc, pad_primes, stats_hist, stats_near, coefs, lhsmod, tbl_head,
-        tbl_term, tbl_limb, tails, tail_hist;
+        tbl_term, tbl_limb, tails, tail_hist, irr_tasks, irr_units, irr_primes, irr_roff, irr_v, irr_fix,
+        irr_counts, irr_pairs, irr_b, irr_e;
     // congruence registry: the compiled tables (ids < WV_TABLE_COUNT), then
     // those defined at run time; device copy in tbl_* (TableStore)
     std::vector<wv::TableHead> t_head;

@@ -1,0 +1,423 @@
+// wv_irregular.hip -- irregular and E-irregular pairs: B_{2k} mod p and
+// E_{2k} mod p for every 2 <= 2k <= p - 3 (Section 1), from the paper's
+// congruences for general index:
+//
+//   C_k(a,b,c) B_{2k} == sum_i S_{2k-1}(x_i, y_i)   (mod p)     (Section 2:
+//     the family (2, b, b+1) over sum_{m <= b/2} (m/(b+1), m/b): b = 3, i.e.
+//     (1/4, 1/3), for every k, then b = 4, 5, ... where C_k(2,3,4) vanishes),
+//   C_k(a,b,c) = (a^{p-2k} + b^{p-2k} - c^{p-2k} - 1) / (4k),
+//   (-1)^k 4^{2k-1} E_{p-1-2k} == S_{p-1-2k}(0, 1/4)   (mod p)  (eqnE1, sign
+//     read as (-1)^k),
+//
+// with S_l(x, y) = sum_{xp < s < yp} s^l (eqnDefnS) for positive l.  Every k
+// needs its own exponent, so the power sums of each range are computed for all
+// exponents at once: a wave owns 1024 consecutive s (16 per lane), steps
+// x <- x s^2 through the exponents, and the partial sums go through LDS (one
+// transpose per 32 exponents) into exact double-precision totals (integers
+// below 2^53, so the order of the atomic additions does not matter).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "sum_core.hpp"
+#include "wv_ctx.hpp"
+
+namespace wv {
+namespace {
+
+struct IrrTask {          // sum_{lo <= s < hi} s^t for t = t0, t0 + 2, ..., t0 + 2 (nt - 1)
+    uint64_t p, lo, hi;
+    uint64_t out;         // index in V of the first exponent's total
+    uint32_t t0, nt;
+};
+
+struct IrrPrime {         // one prime of a batch
+    uint64_t p;
+    uint64_t vb, ve;      // its Bernoulli (odd t = 2k - 1) and Euler (even t = 2k) totals in V
+    uint64_t res;         // index of its first residue in the b / e output arrays
+    uint32_t nt;          // (p - 3) / 2
+    uint32_t pad;
+};
+
+struct IrrFix {           // a k whose first congruence degenerates (C_k == 0 mod p)
+    uint32_t prime, k;
+};
+
+constexpr int kIrrLaneS = 16;                        // s per lane
+constexpr uint64_t kIrrWaveS = 64 * kIrrLaneS;       // s per wave (one work unit)
+constexpr int kIrrBlock = 32;                        // exponents per transpose
+constexpr int kIrrStride = 65;                       // LDS row stride (doubles)
+constexpr uint64_t kIrrMaxV = 1ull << 27;            // totals per batch (1 GiB)
+constexpr uint64_t kIrrMaxUnits = 1ull << 24;        // waves per launch (2^30 work-items)
+
+__host__ __device__ inline uint64_t floor_div(uint64_t a, uint64_t b) { return a / b; }
+
+// first and one-past-last s of x p < s < y p, x = xa/xb, y = ya/yb (p prime > xb, yb)
+__host__ __device__ inline void open_range(uint64_t p, uint64_t xa, uint64_t xb, uint64_t ya, uint64_t yb,
+                                           uint64_t &lo, uint64_t &hi) {
+    lo = floor_div(xa * p, xb) + 1;
+    hi = ya * p % yb ? floor_div(ya * p, yb) + 1 : ya * p / yb;   // s < y p
+    if (hi < lo) hi = lo;
+}
+
+__device__ inline double fpow_e(double a, uint64_t e, const Fmod &f) {
+    double r = 1.0;
+    while (e) {
+        if (e & 1) r = f_mulmod(r, a, f);
+        a = f_mulmod(a, a, f);
+        e >>= 1;
+    }
+    return r;
+}
+
+__device__ inline uint64_t u_pow(uint64_t a, uint64_t e, const Fmod &f) {
+    return f_canon(fpow_e((double)a, e, f), f);
+}
+
+// C_k(a, b, c) mod p for 1 <= k <= (p - 3) / 2
+__device__ inline uint64_t c_k(uint64_t a, uint64_t b, uint64_t c, uint64_t k, const Fmod &f, uint64_t p) {
+    const uint64_t e = p - 2 * k;
+    double num = fpow_e((double)a, e, f) + fpow_e((double)b, e, f) - fpow_e((double)c, e, f) - 1.0;
+    const uint64_t n = f_canon(f_reduce(num, f), f);
+    const uint64_t inv4k = u_pow((4 * k) % p, p - 2, f);
+    return f_canon(f_mulmod((double)n, (double)inv4k, f), f);
+}
+
+// ---------------------------------------------------------------------------
+// power sums for all exponents
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_irr_sum(const IrrTask *__restrict__ tasks,
+                                                 const uint64_t *__restrict__ unit_off, uint32_t ntask,
+                                                 uint64_t nunits, double *__restrict__ V) {
+    __shared__ double lds[4][kIrrBlock * kIrrStride];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t unit = (uint64_t)blockIdx.x * 4 + wave;   // wave-uniform
+    if (unit >= nunits) return;
+    const uint32_t j = __builtin_amdgcn_readfirstlane(find_seg(unit_off, ntask, unit));
+    const IrrTask T = tasks[j];
+    Fmod f;
+    f.p = (double)T.p;
+    f.pinv = 1.0 / f.p;
+    const uint64_t s0 = T.lo + (unit - unit_off[j]) * kIrrWaveS + lane;
+    double x[kIrrLaneS], sq[kIrrLaneS];
+WV_UNROLL
+    for (int m = 0; m < kIrrLaneS; m++) {
+        const uint64_t s = s0 + 64 * (uint64_t)m;
+        const double sd = (double)s;
+        const double s2 = f_mulmod(sd, sd, f);
+        const bool in = s < T.hi;
+        x[m] = in ? (T.t0 == 1 ? sd : s2) : 0.0;
+        sq[m] = in ? s2 : 0.0;
+    }
+    double *L = lds[wave];
+    for (uint32_t b0 = 0; b0 < T.nt; b0 += kIrrBlock) {
+        for (int e = 0; e < kIrrBlock; e++) {
+            double a = 0.0;
+WV_UNROLL
+            for (int m = 0; m < kIrrLaneS; m++) a += x[m];   // |a| < 16 * 0.574 p, exact
+WV_UNROLL
+            for (int m = 0; m < kIrrLaneS; m++) x[m] = f_mulmod(x[m], sq[m], f);
+            L[e * kIrrStride + lane] = a;
+        }
+        // the wave's own LDS rows: complete its writes before reading across lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lane l and l + 32 each sum half of exponent (l & 31)'s row
+        const int row = lane & 31, half = lane >> 5;
+        double t = 0.0;
+        for (int m = 0; m < 32; m++) t += L[row * kIrrStride + half * 32 + m];
+        t += __shfl_xor(t, 32, 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (half == 0 && b0 + row < T.nt) atomicAdd(&V[T.out + b0 + row], t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// residues from the totals
+// ---------------------------------------------------------------------------
+
+// One thread per (prime, k): b = B_{2k} mod p from (2,3,4) unless its C_k
+// vanishes (then queued for k_irr_fix), e = E_{2k} mod p from eqnE1.  Zero
+// residues are appended to pairs as (p, 2k, kind).
+__global__ void __launch_bounds__(256) k_irr_final(const IrrPrime *__restrict__ pr, const uint64_t *__restrict__ off,
+                                                   uint32_t np, const double *__restrict__ V,
+                                                   uint64_t *__restrict__ b_out, uint64_t *__restrict__ e_out,
+                                                   IrrFix *__restrict__ fix, unsigned long long *__restrict__ counts,
+                                                   wv_irr_pair *__restrict__ pairs, uint64_t pair_cap) {
+    const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= off[np]) return;
+    const uint32_t i = find_seg(off, np, g);
+    const IrrPrime P = pr[i];
+    const uint64_t k = g - off[i] + 1;
+    const uint64_t p = P.p;
+    Fmod f;
+    f.p = (double)p;
+    f.pinv = 1.0 / f.p;
+    // Bernoulli side: odd exponent t = 2k - 1
+    const uint64_t vb = f_canon(V[P.vb + k - 1], f);
+    const uint64_t c = c_k(2, 3, 4, k, f, p);
+    if (c) {
+        const uint64_t b = f_canon(f_mulmod((double)vb, (double)u_pow(c, p - 2, f), f), f);
+        if (b_out) b_out[P.res + k - 1] = b;
+        if (b == 0) {
+            const unsigned long long at = atomicAdd(&counts[1], 1ull);
+            if (at < pair_cap) pairs[at] = wv_irr_pair{p, (uint32_t)(2 * k), 1u};
+        }
+    } else {
+        const unsigned long long at = atomicAdd(&counts[0], 1ull);
+        fix[at] = IrrFix{i, (uint32_t)k};
+    }
+    // Euler side: even exponent t = 2k; eqnE1 with k' = (p - 1 - t) / 2
+    const uint64_t t = 2 * k;
+    const uint64_t kk = (p - 1 - t) / 2;
+    uint64_t e = f_canon(f_mulmod(f_canon(V[P.ve + k - 1], f), (double)u_pow(4, t + 1, f), f), f);
+    if ((kk & 1) && e) e = p - e;
+    if (e_out) e_out[P.res + k - 1] = e;
+    if (e == 0) {
+        const unsigned long long at = atomicAdd(&counts[1], 1ull);
+        if (at < pair_cap) pairs[at] = wv_irr_pair{p, (uint32_t)t, 2u};
+    }
+}
+
+// One wave per queued k: the next members of the family (2, b, b + 1) of
+// Section 2 (C_k(2,b,b+1) B_{2k} == sum_{m=1}^{floor(b/2)} S_{2k-1}(m/(b+1), m/b);
+// b = 5 is eqnVandiver) for b = 4, 5, ..., kIrrMaxB with p not dividing
+// b (b + 1), each sum evaluated directly (one power per s).  At 2k = (p+1)/2
+// every C_k is a sum of Legendre symbols, and the first b with
+// (b/p) != ((b+1)/p) (or b = 3 when (2/p) = -1) resolves it.  A k where all
+// of them degenerate is marked with the residue UINT64_MAX and counted in
+// counts[2].
+constexpr uint64_t kIrrMaxB = 64;
+
+__global__ void __launch_bounds__(256) k_irr_fix(const IrrPrime *__restrict__ pr, const IrrFix *__restrict__ fix,
+                                                 const unsigned long long *__restrict__ nfix_ptr,
+                                                 uint64_t *__restrict__ b_out, unsigned long long *__restrict__ counts,
+                                                 wv_irr_pair *__restrict__ pairs, uint64_t pair_cap) {
+    const uint64_t w = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= *nfix_ptr) return;
+    const IrrFix F = fix[w];
+    const IrrPrime P = pr[F.prime];
+    const uint64_t p = P.p, k = F.k;
+    Fmod f;
+    f.p = (double)p;
+    f.pinv = 1.0 / f.p;
+    uint64_t b = UINT64_MAX;
+    for (uint64_t bb = 4; bb <= kIrrMaxB && b == UINT64_MAX; bb++) {
+        if (bb % p == 0 || (bb + 1) % p == 0) continue;
+        const uint64_t c = c_k(2, bb, bb + 1, k, f, p);
+        if (!c) continue;
+        double acc = 0.0;   // exact: fewer than p terms below 0.574 p in magnitude
+        for (uint64_t m = 1; m <= bb / 2; m++) {
+            uint64_t lo, hi;
+            open_range(p, m, bb + 1, m, bb, lo, hi);
+            for (uint64_t s = lo + lane; s < hi; s += 64) acc += fpow_e((double)s, 2 * k - 1, f);
+        }
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        const uint64_t S = f_canon(f_reduce(acc, f), f);
+        b = f_canon(f_mulmod((double)S, (double)u_pow(c, p - 2, f), f), f);
+    }
+    if (lane != 0) return;
+    if (b_out) b_out[P.res + k - 1] = b;
+    if (b == UINT64_MAX) {
+        atomicAdd(&counts[2], 1ull);
+    } else if (b == 0) {
+        const unsigned long long at = atomicAdd(&counts[1], 1ull);
+        if (at < pair_cap) pairs[at] = wv_irr_pair{p, (uint32_t)(2 * k), 1u};
+    }
+}
+
+__global__ void k_irr_zero(double *__restrict__ v, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) v[i] = 0.0;
+}
+
+unsigned grid_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per + (n == 0)); }
+
+// One batch of primes (all in [5, WV_IRR_P_MAX)): residues into the device
+// arrays b_out / e_out (may be null) at each prime's res offset, zero pairs
+// appended to the device list.  Returns the counters {fixups, pairs, unresolved}.
+int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_t *d_e, uint64_t pair_cap,
+              uint64_t counts_out[3], float *ms_sum, double *pairs_done) {
+    hipStream_t st = c->stream;
+    std::vector<IrrTask> tasks;
+    std::vector<uint64_t> units(1, 0);
+    std::vector<IrrPrime> prs;
+    std::vector<uint64_t> roff(1, 0);
+    uint64_t vn = 0, res = 0;
+    double work = 0.0;
+    for (uint64_t p : ps) {
+        const uint32_t nt = (uint32_t)((p - 3) / 2);
+        IrrPrime P{p, vn, vn + nt, res, nt, 0};
+        uint64_t lo, hi;
+        open_range(p, 1, 4, 1, 3, lo, hi);   // Bernoulli: (1/4, 1/3), odd exponents from 1
+        tasks.push_back(IrrTask{p, lo, hi, vn, 1, nt});
+        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS);
+        work += (double)(hi - lo) * nt;
+        open_range(p, 0, 1, 1, 4, lo, hi);   // Euler: (0, 1/4), even exponents from 2
+        tasks.push_back(IrrTask{p, lo, hi, vn + nt, 2, nt});
+        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS);
+        work += (double)(hi - lo) * nt;
+        vn += 2 * (uint64_t)nt;
+        res += nt;
+        prs.push_back(P);
+        roff.push_back(roff.back() + nt);
+    }
+    const uint64_t nunits = units.back();
+    const uint32_t ntask = (uint32_t)tasks.size(), np = (uint32_t)prs.size();
+    WV_TRY(ensure(c, c->irr_tasks, tasks.size() * sizeof(IrrTask)));
+    WV_TRY(ensure(c, c->irr_units, units.size() * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->irr_primes, prs.size() * sizeof(IrrPrime)));
+    WV_TRY(ensure(c, c->irr_roff, roff.size() * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->irr_v, std::max<uint64_t>(vn, 1) * sizeof(double)));
+    WV_TRY(ensure(c, c->irr_fix, std::max<uint64_t>(res, 1) * sizeof(IrrFix)));
+    WV_TRY(ensure(c, c->irr_counts, 4 * sizeof(unsigned long long)));
+    WV_HIP(hipMemcpyAsync(c->irr_tasks.ptr, tasks.data(), tasks.size() * sizeof(IrrTask), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(c->irr_units.ptr, units.data(), units.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(c->irr_primes.ptr, prs.data(), prs.size() * sizeof(IrrPrime), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(c->irr_roff.ptr, roff.data(), roff.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_irr_zero, dim3(grid_for(vn, 256)), dim3(256), 0, st, as<double>(c->irr_v), vn);
+    WV_HIP(launch_set_u64(st, as<uint64_t>(c->irr_counts), 4, 0));
+    WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
+    hipLaunchKernelGGL(k_irr_sum, dim3(grid_for(nunits, 4)), dim3(256), 0, st, as<IrrTask>(c->irr_tasks),
+                       as<uint64_t>(c->irr_units), ntask, nunits, as<double>(c->irr_v));
+    WV_HIP(hipGetLastError());
+    WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
+    auto *counts = as<unsigned long long>(c->irr_counts);
+    hipLaunchKernelGGL(k_irr_final, dim3(grid_for(res, 256)), dim3(256), 0, st, as<IrrPrime>(c->irr_primes),
+                       as<uint64_t>(c->irr_roff), np, as<double>(c->irr_v), d_b, d_e, as<IrrFix>(c->irr_fix), counts,
+                       as<wv_irr_pair>(c->irr_pairs), pair_cap);
+    WV_HIP(hipGetLastError());
+    unsigned long long host[4];
+    WV_HIP(hipMemcpyAsync(host, counts, sizeof(host), hipMemcpyDeviceToHost, st));
+    WV_HIP(hipStreamSynchronize(st));
+    if (host[0]) {
+        hipLaunchKernelGGL(k_irr_fix, dim3(grid_for(host[0] * 64, 256)), dim3(256), 0, st,
+                           as<IrrPrime>(c->irr_primes), as<IrrFix>(c->irr_fix), counts, d_b, counts,
+                           as<wv_irr_pair>(c->irr_pairs), pair_cap);
+        WV_HIP(hipGetLastError());
+        WV_HIP(hipMemcpyAsync(host, counts, sizeof(host), hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev[EV_SUM0], c->ev[EV_SUM]);
+    *ms_sum += ms;
+    *pairs_done += work;
+    for (int q = 0; q < 3; q++) counts_out[q] = host[q];
+    return WV_OK;
+}
+
+// Batches of consecutive primes within the device budgets.
+template <class F>
+int irr_for_batches(const std::vector<uint64_t> &ps, F &&run) {
+    size_t i = 0;
+    while (i < ps.size()) {
+        std::vector<uint64_t> b;
+        uint64_t vn = 0, units = 0;
+        while (i < ps.size()) {
+            const uint64_t p = ps[i];
+            const uint64_t v = p - 3;   // two totals per k
+            const uint64_t u = 2 * (p / 4 / kIrrWaveS + 2);
+            if (!b.empty() && (vn + v > kIrrMaxV || units + u > kIrrMaxUnits)) break;
+            b.push_back(p);
+            vn += v;
+            units += u;
+            i++;
+        }
+        WV_TRY(run(b));
+    }
+    return WV_OK;
+}
+
+}  // namespace
+}  // namespace wv
+
+using namespace wv;
+
+int wv_bernoulli_euler_all(wv_ctx *c, uint64_t p, uint64_t *b, uint64_t *e) {
+    if (!c || !b || !e) return WV_EINVAL;
+    if (p < 5 || p >= WV_IRR_P_MAX) return WV_EDOMAIN;
+    if (!is_prime_u64(p)) return WV_ENOTPRIME;
+    WV_TRY(check_device(c));
+    c->stats = wv_stats{};
+    const uint64_t nt = (p - 3) / 2;
+    WV_TRY(ensure(c, c->irr_b, nt * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->irr_e, nt * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->irr_pairs, 64 * sizeof(wv_irr_pair)));
+    uint64_t counts[3];
+    float ms = 0.f;
+    double work = 0.0;
+    WV_TRY(irr_batch(c, std::vector<uint64_t>{p}, as<uint64_t>(c->irr_b), as<uint64_t>(c->irr_e), 0, counts, &ms,
+                     &work));
+    WV_HIP(hipMemcpyAsync(b, c->irr_b.ptr, nt * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipMemcpyAsync(e, c->irr_e.ptr, nt * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipStreamSynchronize(c->stream));
+    c->stats.n_primes = 1;
+    c->stats.n_terms = (uint64_t)work;
+    c->stats.ms_sum = ms;
+    return WV_OK;
+}
+
+int wv_irregular_pairs(wv_ctx *c, uint64_t lo, uint64_t hi, wv_irr_pair *out, size_t cap, size_t *n_out,
+                       uint64_t *n_primes, uint64_t *n_unresolved) {
+    if (!c || !n_out || lo > hi || (cap && !out)) return WV_EINVAL;
+    if (hi > WV_IRR_P_MAX) return WV_EDOMAIN;
+    WV_TRY(check_device(c));
+    c->stats = wv_stats{};
+    *n_out = 0;
+    // the primes of [lo, hi), sieved on the device in groups of segments
+    std::vector<SegDesc> d;
+    window_descs(lo, hi, d);
+    std::vector<uint64_t> ps;
+    for (size_t g = 0; g < d.size(); g += kMaxBatchSegs) {
+        const size_t ns = std::min(kMaxBatchSegs, d.size() - g);
+        std::vector<uint32_t> counts(ns);
+        WV_TRY(sieve_count(c, d.data() + g, ns, true, counts.data()));
+        uint64_t np = 0;
+        WV_TRY(compact(c, d.data() + g, ns, counts.data(), &np));
+        const size_t at = ps.size();
+        ps.resize(at + np);
+        if (np) {
+            WV_HIP(hipMemcpyAsync(ps.data() + at, c->primes.ptr, np * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                  c->stream));
+            WV_HIP(hipStreamSynchronize(c->stream));
+        }
+    }
+    std::vector<wv_irr_pair> all;
+    uint64_t unresolved = 0;
+    float ms = 0.f;
+    double work = 0.0;
+    const uint64_t pair_cap = 1ull << 20;
+    WV_TRY(ensure(c, c->irr_pairs, pair_cap * sizeof(wv_irr_pair)));
+    WV_TRY(irr_for_batches(ps, [&](const std::vector<uint64_t> &b) -> int {
+        uint64_t counts[3];
+        WV_TRY(irr_batch(c, b, nullptr, nullptr, pair_cap, counts, &ms, &work));
+        if (counts[1] > pair_cap) return WV_ENOMEM;
+        const size_t at = all.size();
+        all.resize(at + counts[1]);
+        if (counts[1]) {
+            WV_HIP(hipMemcpyAsync(all.data() + at, c->irr_pairs.ptr, counts[1] * sizeof(wv_irr_pair),
+                                  hipMemcpyDeviceToHost, c->stream));
+            WV_HIP(hipStreamSynchronize(c->stream));
+        }
+        unresolved += counts[2];
+        return WV_OK;
+    }));
+    std::sort(all.begin(), all.end(), [](const wv_irr_pair &a, const wv_irr_pair &b) {
+        return a.p != b.p ? a.p < b.p : (a.two_k != b.two_k ? a.two_k < b.two_k : a.kind < b.kind);
+    });
+    c->stats.n_primes = ps.size();
+    c->stats.n_terms = (uint64_t)work;
+    c->stats.ms_sum = ms;
+    if (n_primes) *n_primes = ps.size();
+    if (n_unresolved) *n_unresolved = unresolved;
+    *n_out = all.size();
+    if (all.size() > cap) return WV_ETRUNC;
+    std::copy(all.begin(), all.end(), out);
+    return WV_OK;
+}

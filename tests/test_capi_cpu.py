@@ -86,6 +86,8 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.wv_count_primes(None, 0, 10, None) == wv.WV_EINVAL
     assert lib.wv_eval_primes(None, None, 0, None) == wv.WV_EINVAL
     assert lib.wv_get_stats(None, None) == wv.WV_EINVAL
+    assert lib.wv_bernoulli_euler_all(None, 37, None, None) == wv.WV_EINVAL
+    assert lib.wv_irregular_pairs(None, 5, 100, None, 0, None, None, None) == wv.WV_EINVAL
 
 
 def test_create_reports_missing_device():

@@ -831,3 +831,86 @@ def test_batched_windows_with_derived_tables(ctx):
         flat = np.concatenate([g for g in got if len(g)])
     pick = sorted(random.Random(5).sample(range(len(flat)), 4))
     check_against_oracle(flat[pick], method="table")
+
+
+# ---------------------------------------------------------------------------
+# every index: irregular and E-irregular pairs
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.gpu
+def test_all_index_residues_small_primes(ctx):
+    """B_{2k}, E_{2k} mod p for every 2k <= p - 3 of each prime below 700
+    equal the oracle's recurrences, element by element (p = 5, 7 included:
+    one and two indices; p = 5 needs the second congruence of the chain)."""
+    say("case: every index, primes below 700")
+    for p in oracle.primes(5, 700):
+        b, e = ctx.bernoulli_euler_all(p)
+        assert [int(x) for x in b] == oracle.bernoulli_all(p), p
+        assert [int(x) for x in e] == oracle.euler_all(p), p
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p", [2003, 5783, 16843, 30011])
+def test_all_index_residues_larger_primes(ctx, p):
+    """Several waves per range, many 32-exponent blocks, a ragged last block."""
+    say(f"case: every index, p = {p}")
+    b, e = ctx.bernoulli_euler_all(p)
+    assert [int(x) for x in b] == oracle.bernoulli_all(p)
+    assert [int(x) for x in e] == oracle.euler_all(p)
+
+
+@pytest.mark.gpu
+def test_irregular_pairs_census_matches_oracle(ctx):
+    """Every pair of the primes in [5, 3000), and the paper's statements:
+    37 is the smallest irregular prime, 19 (19 | E_10) the smallest
+    E-irregular one."""
+    say("case: irregular census below 3000")
+    from concurrent.futures import ThreadPoolExecutor
+    got, n_primes, unresolved = ctx.irregular_pairs(5, 3000)
+    ps = oracle.primes(5, 3000)
+    with ThreadPoolExecutor(8) as ex:
+        want = [x for lst in ex.map(oracle.irregular_pairs, ps) for x in lst]
+    assert n_primes == len(ps) and unresolved == 0
+    assert [(int(r["p"]), int(r["two_k"]), int(r["kind"])) for r in got] == sorted(want)
+    assert min(int(r["p"]) for r in got if r["kind"] == 1) == 37
+    assert min(int(r["p"]) for r in got if r["kind"] == 2) == 19
+
+
+@pytest.mark.gpu
+def test_irregular_pairs_paper_primes(ctx):
+    """Section 1: (16843, 16840) is an irregular pair (a Wolstenholme prime),
+    5783 has index of E-irregularity 5, 149 and 241 give E-irregular pairs
+    (p, p - 3) (Vandiver primes)."""
+    say("case: irregular pairs of the paper's primes")
+    got, _, unresolved = ctx.irregular_pairs(16843, 16844)
+    assert unresolved == 0 and (16843, 16840, 1) in [(int(r["p"]), int(r["two_k"]), int(r["kind"])) for r in got]
+    got, _, _ = ctx.irregular_pairs(5783, 5784)
+    assert sum(1 for r in got if r["kind"] == 2) == 5
+    for p in (149, 241):
+        got, _, _ = ctx.irregular_pairs(p, p + 1)
+        assert (p, p - 3, 2) in [(int(r["p"]), int(r["two_k"]), int(r["kind"])) for r in got]
+
+
+@pytest.mark.gpu
+def test_irregular_entry_points_reject_bad_input(ctx):
+    say("case: irregular entry points, bad input")
+    with pytest.raises(wv.WvError) as ei:
+        ctx.bernoulli_euler_all(wv.IRR_P_MAX + 1)
+    assert ei.value.status == wv.WV_EDOMAIN
+    with pytest.raises(wv.WvError) as ei:
+        ctx.bernoulli_euler_all(1001)
+    assert ei.value.status == wv.WV_ENOTPRIME
+    with pytest.raises(wv.WvError) as ei:
+        ctx.bernoulli_euler_all(3)
+    assert ei.value.status == wv.WV_EDOMAIN
+    with pytest.raises(wv.WvError) as ei:
+        ctx.irregular_pairs(5, wv.IRR_P_MAX + 1)
+    assert ei.value.status == wv.WV_EDOMAIN
+    got, n_primes, _ = ctx.irregular_pairs(24, 29)   # no prime
+    assert len(got) == 0 and n_primes == 0
+    # two pairs below 37 (both E-irregular) through a one-entry buffer: the
+    # binding retries after WV_ETRUNC
+    got, n_primes, _ = ctx.irregular_pairs(5, 37, cap=1)
+    assert n_primes == 9
+    assert [(int(r["p"]), int(r["two_k"]), int(r["kind"])) for r in got] == [(19, 10, 2), (31, 22, 2)]
