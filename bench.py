@@ -102,7 +102,7 @@ CONFIGS = {
     "1e9": (10 ** 9, 10 ** 9 + 10 ** 7, 1 << 18),
     "1e5": (5, 10 ** 5, 10 ** 5),
 }
-EXTRA_CONFIGS = ("batch", "serve")
+EXTRA_CONFIGS = ("batch", "serve", "irregular")
 
 
 def use_tables(ctx, which):
@@ -185,6 +185,8 @@ def main():
         return bench_batch(args, wv)
     if args.config == "serve":
         return bench_serve(args, wv)
+    if args.config == "irregular":
+        return bench_irregular(args, wv)
 
     lo0, hi0, wdef = CONFIGS[args.config]
     W = args.window or wdef
@@ -278,6 +280,97 @@ def main():
             "value": v, "unit": "primes/s", "cores": nt, "kind": "oracle",
             "sample": f"{len(sample)} prime(s) of the first timed window ({sample[0]}), "
                       f"eqnBB30+eqnEE33 evaluated plainly, {dt:.1f} s",
+        }
+    print(json.dumps(line), flush=True)
+
+
+# one (s, t) pair of the all-exponent power sums: a modular product (6
+# operations) and an exact addition
+OPS_IRR_PAIR = 7
+
+
+def bench_irregular(args, wv):
+    """Irregular-pair census: every B_{2k} and E_{2k} mod p (2k <= p - 3) of the
+    primes in [2^15, 2^16), a step being the next window of `--window` (default
+    4096) integers; the pairs found are compared with the oracle on the first
+    timed window's smallest prime."""
+    import numpy as np
+    lo0, hi0 = 1 << 15, 1 << 16
+    W = args.window or 4096
+    nwin = args.warmup + args.steps
+    if lo0 + nwin * W > hi0:
+        print(f"bench.py: {nwin} windows of {W} do not fit in [{lo0}, {hi0})", file=sys.stderr)
+        sys.exit(2)
+    wins = [(lo0 + k * W, lo0 + (k + 1) * W) for k in range(nwin)]
+    ctx = wv.Context(0)
+    for k in range(args.warmup):
+        ctx.irregular_pairs(*wins[k])
+        print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
+    primes = npairs = 0
+    pairs_st = 0.0
+    ms_sum = 0.0
+    first = None
+    t0 = time.perf_counter()
+    for k in range(args.warmup, nwin):
+        got, n, unresolved = ctx.irregular_pairs(*wins[k])
+        st = ctx.stats()
+        primes += n
+        npairs += len(got)
+        pairs_st += st["n_terms"]
+        ms_sum += st["ms_sum"]
+        if first is None:
+            first = (wins[k], got)
+        print(f"step {k - args.warmup}: {n} primes, {len(got)} pairs, unresolved {unresolved}, "
+              f"power-sum kernel {st['ms_sum']:.1f} ms", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    value = primes / wall
+    achieved = OPS_IRR_PAIR * pairs_st / (ms_sum * 1e-3) / 1e12
+    line = {
+        "metric": "primes/s with every irregular and E-irregular pair (all 2k <= p-3), p in [2^15, 2^16) (1 GPU)",
+        "value": value,
+        "unit": "primes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"primes in [{lo0}, {hi0}), windows of {W} integers per step",
+            "primes_timed": primes,
+            "pairs_found": npairs,
+            "power_sum_terms": pairs_st,
+            "power_sum_kernel_ms": ms_sum,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_VALU / 1e12,
+            "unit": "Tops/s (full-rate VALU lane ops)",
+            "frac": achieved / (PEAK_VALU / 1e12),
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline and first is not None:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        (wlo, whi), got = first
+        nt = min(cpu_threads(), 16)
+        sample = oracle.primes(wlo, whi)[:nt]
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(nt) as ex:
+            want = [x for lst in ex.map(oracle.irregular_pairs, sample) for x in lst]
+        dt = time.perf_counter() - t1
+        have = [(int(r["p"]), int(r["two_k"]), int(r["kind"])) for r in got if int(r["p"]) <= sample[-1]]
+        line["cpu_baseline"] = {
+            "value": len(sample) / dt, "unit": "primes/s", "cores": len(sample), "kind": "oracle",
+            "sample": f"the {len(sample)} smallest primes of the first timed window ({sample[0]}..{sample[-1]}), "
+                      f"EGF recurrences mod p, one prime per thread, {dt:.1f} s; pairs "
+                      f"{'identical' if have == sorted(want) else 'DIFFERENT'}",
         }
     print(json.dumps(line), flush=True)
 

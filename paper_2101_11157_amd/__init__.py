@@ -352,10 +352,14 @@ class Context:
                "wv_bernoulli_euler_all")
         return b[:n], e[:n]
 
-    def irregular_pairs(self, lo, hi, cap=4096):
+    def irregular_pairs(self, lo, hi, cap=None):
         """Irregular (kind 1) and E-irregular (kind 2) pairs (p, 2k) of the
         primes in [lo, hi): (IRR_PAIR_DTYPE array sorted by p, 2k, kind,
-        primes examined, unresolved indices)."""
+        primes examined, unresolved indices).  The default buffer holds four
+        pairs per expected prime (about one is typical); a short buffer costs
+        a second run."""
+        if cap is None:
+            cap = max(4096, int(4 * (int(hi) - int(lo)) / max(1.0, np.log(max(int(hi), 3)))))
         out = np.zeros(max(1, cap), dtype=IRR_PAIR_DTYPE)
         n, n_primes, n_unres = SZ(), U64(), U64()
         st = lib().wv_irregular_pairs(self._h, int(lo), int(hi), out.ctypes.data_as(VP), cap, ctypes.byref(n),

@@ -11,10 +11,11 @@
 //
 // with S_l(x, y) = sum_{xp < s < yp} s^l (eqnDefnS) for positive l.  Every k
 // needs its own exponent, so the power sums of each range are computed for all
-// exponents at once: a wave owns 1024 consecutive s (16 per lane), steps
-// x <- x s^2 through the exponents, and the partial sums go through LDS (one
-// transpose per 32 exponents) into exact double-precision totals (integers
-// below 2^53, so the order of the atomic additions does not matter).
+// exponents at once: a wave owns 1024 consecutive s (16 per lane) and a block
+// of up to 2048 exponents, steps x <- x s^2 through them, and the partial sums
+// go through LDS (one transpose per 32 exponents) into exact double-precision
+// totals (integers below 2^53, so the order of the atomic additions does not
+// matter).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,6 +48,7 @@ struct IrrFix {           // a k whose first congruence degenerates (C_k == 0 mo
 constexpr int kIrrLaneS = 16;                        // s per lane
 constexpr uint64_t kIrrWaveS = 64 * kIrrLaneS;       // s per wave (one work unit)
 constexpr int kIrrBlock = 32;                        // exponents per transpose
+constexpr uint32_t kIrrUnitT = 2048;                 // exponents per work unit
 constexpr int kIrrStride = 65;                       // LDS row stride (doubles)
 constexpr uint64_t kIrrMaxV = 1ull << 27;            // totals per batch (1 GiB)
 constexpr uint64_t kIrrMaxUnits = 1ull << 24;        // waves per launch (2^30 work-items)
@@ -100,7 +102,12 @@ __global__ void __launch_bounds__(256) k_irr_sum(const IrrTask *__restrict__ tas
     Fmod f;
     f.p = (double)T.p;
     f.pinv = 1.0 / f.p;
-    const uint64_t s0 = T.lo + (unit - unit_off[j]) * kIrrWaveS + lane;
+    // unit = (s chunk, exponent block): 1024 s times at most kIrrUnitT exponents
+    const uint32_t nblk = (T.nt + kIrrUnitT - 1) / kIrrUnitT;
+    const uint64_t u = unit - unit_off[j];
+    const uint32_t e_first = (uint32_t)(u % nblk) * kIrrUnitT;
+    const uint32_t e_end = min(T.nt, e_first + kIrrUnitT);
+    const uint64_t s0 = T.lo + (u / nblk) * kIrrWaveS + lane;
     double x[kIrrLaneS], sq[kIrrLaneS];
 WV_UNROLL
     for (int m = 0; m < kIrrLaneS; m++) {
@@ -108,11 +115,14 @@ WV_UNROLL
         const double sd = (double)s;
         const double s2 = f_mulmod(sd, sd, f);
         const bool in = s < T.hi;
-        x[m] = in ? (T.t0 == 1 ? sd : s2) : 0.0;
+        // s^(t0 + 2 e_first)
+        const double xs = fpow_e(sd, T.t0 + 2 * (uint64_t)e_first, f);
+        x[m] = in ? xs : 0.0;
         sq[m] = in ? s2 : 0.0;
     }
     double *L = lds[wave];
-    for (uint32_t b0 = 0; b0 < T.nt; b0 += kIrrBlock) {
+    for (uint32_t b0 = e_first; b0 < e_end; b0 += kIrrBlock) {
+#pragma unroll 2
         for (int e = 0; e < kIrrBlock; e++) {
             double a = 0.0;
 WV_UNROLL
@@ -133,7 +143,7 @@ WV_UNROLL
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (half == 0 && b0 + row < T.nt) atomicAdd(&V[T.out + b0 + row], t);
+        if (half == 0 && b0 + row < e_end) atomicAdd(&V[T.out + b0 + row], t);
     }
 }
 
@@ -256,12 +266,13 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
         IrrPrime P{p, vn, vn + nt, res, nt, 0};
         uint64_t lo, hi;
         open_range(p, 1, 4, 1, 3, lo, hi);   // Bernoulli: (1/4, 1/3), odd exponents from 1
+        const uint64_t nblk = (nt + kIrrUnitT - 1) / kIrrUnitT;
         tasks.push_back(IrrTask{p, lo, hi, vn, 1, nt});
-        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS);
+        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS * nblk);
         work += (double)(hi - lo) * nt;
         open_range(p, 0, 1, 1, 4, lo, hi);   // Euler: (0, 1/4), even exponents from 2
         tasks.push_back(IrrTask{p, lo, hi, vn + nt, 2, nt});
-        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS);
+        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS * nblk);
         work += (double)(hi - lo) * nt;
         vn += 2 * (uint64_t)nt;
         res += nt;
@@ -322,7 +333,7 @@ int irr_for_batches(const std::vector<uint64_t> &ps, F &&run) {
         while (i < ps.size()) {
             const uint64_t p = ps[i];
             const uint64_t v = p - 3;   // two totals per k
-            const uint64_t u = 2 * (p / 4 / kIrrWaveS + 2);
+            const uint64_t u = 2 * (p / 4 / kIrrWaveS + 2) * ((p / 2) / kIrrUnitT + 1);
             if (!b.empty() && (vn + v > kIrrMaxV || units + u > kIrrMaxUnits)) break;
             b.push_back(p);
             vn += v;
