@@ -284,16 +284,18 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-# one (s, t) pair of the all-exponent power sums: a modular product (6
-# operations) and an exact addition
-OPS_IRR_PAIR = 7
+# one (s, t) pair of the all-exponent power sums on the matrix cores: one f64
+# multiply-add (2 flops) of the power tables s^(t0 + 256 m) and s^(2j)
+FLOPS_IRR_PAIR = 2
+PEAK_MFMA_F64 = 78.6e12                  # dense f64 matrix peak of MI355X
 
 
 def bench_irregular(args, wv):
     """Irregular-pair census: every B_{2k} and E_{2k} mod p (2k <= p - 3) of the
     primes in [2^15, 2^16), a step being the next window of `--window` (default
     4096) integers; the pairs found are compared with the oracle on the first
-    timed window's smallest prime."""
+    timed window's smallest primes.  `roofline` describes the power-sum kernel
+    on the matrix cores (one f64 multiply-add per (s, t) pair)."""
     import numpy as np
     lo0, hi0 = 1 << 15, 1 << 16
     W = args.window or 4096
@@ -325,7 +327,7 @@ def bench_irregular(args, wv):
     wall = time.perf_counter() - t0
     ctx.close()
     value = primes / wall
-    achieved = OPS_IRR_PAIR * pairs_st / (ms_sum * 1e-3) / 1e12
+    achieved = FLOPS_IRR_PAIR * pairs_st / (ms_sum * 1e-3) / 1e12
     line = {
         "metric": "primes/s with every irregular and E-irregular pair (all 2k <= p-3), p in [2^15, 2^16) (1 GPU)",
         "value": value,
@@ -347,11 +349,11 @@ def bench_irregular(args, wv):
             "power_sum_kernel_ms": ms_sum,
         },
         "roofline": {
-            "bound": "alu",
+            "bound": "mfma",
             "achieved": achieved,
-            "peak": PEAK_VALU / 1e12,
-            "unit": "Tops/s (full-rate VALU lane ops)",
-            "frac": achieved / (PEAK_VALU / 1e12),
+            "peak": PEAK_MFMA_F64 / 1e12,
+            "unit": "TFLOP/s (f64 matrix)",
+            "frac": achieved / (PEAK_MFMA_F64 / 1e12),
             "traffic": None,
         },
     }

@@ -248,6 +248,13 @@ typedef struct {
  * WV_ENOTPRIME, WV_ENOMEM, WV_EHIP. */
 int wv_bernoulli_euler_all(wv_ctx *ctx, uint64_t p, uint64_t *b, uint64_t *e);
 
+/* Kernel of the power sums behind wv_bernoulli_euler_all / wv_irregular_pairs:
+ * 0 automatic (matrix cores for batches with every p < 2^21, where a partial
+ * sum of 1024 products stays an exact f64 integer; vector ALU otherwise),
+ * 1 vector ALU always, 2 matrix cores where exact (same as 0).  Results do not
+ * depend on it.  Errors: WV_EINVAL. */
+int wv_set_irregular_path(wv_ctx *ctx, int path);
+
 /* All irregular and E-irregular pairs of the primes p in [lo, hi) (p >= 5),
  * sorted by (p, 2k, kind) into out (caller-owned, cap entries).  *n_out: the
  * number of pairs; n_primes (optional): primes examined; n_unresolved

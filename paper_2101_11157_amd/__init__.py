@@ -141,6 +141,7 @@ def lib():
             "wv_range_stats": (ctypes.c_int, [VP, U64, U64, ctypes.c_uint32, U64, P_U64, P_U64, VP, SZ,
                                               ctypes.POINTER(SZ), P_U64]),
             "wv_bernoulli_euler_all": (ctypes.c_int, [VP, U64, P_U64, P_U64]),
+            "wv_set_irregular_path": (ctypes.c_int, [VP, ctypes.c_int]),
             "wv_irregular_pairs": (ctypes.c_int, [VP, U64, U64, VP, SZ, ctypes.POINTER(SZ), P_U64, P_U64]),
             "wv_autotune": (ctypes.c_int, [VP, U64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), P_U64, ctypes.POINTER(ctypes.c_double)]),
@@ -341,6 +342,11 @@ class Context:
                                       ctypes.byref(n_near), ctypes.byref(n_primes))
         _check(st, "wv_range_stats")
         return hb, he, nr[:n_near.value], n_primes.value
+
+    def set_irregular_path(self, path):
+        """Power-sum kernel of the irregular-pair calls: 0 automatic, 1 vector
+        ALU, 2 matrix cores where exact (p < 2^21)."""
+        _check(lib().wv_set_irregular_path(self._h, int(path)), "wv_set_irregular_path")
 
     def bernoulli_euler_all(self, p):
         """(b, e): B_{2k} mod p and E_{2k} mod p for 2k = 2, 4, ..., p - 3

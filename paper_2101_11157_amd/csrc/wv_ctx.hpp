@@ -111,6 +111,7 @@ struct wv_ctx {
     wv_progress_fn progress = nullptr;
     void *progress_user = nullptr;
     uint64_t launch_terms = 1ull << 44;
+    int irr_path = 0;                             // 0 automatic, 1 vector ALU, 2 matrix cores
     std::vector<wv::GraphEntry> graphs;
     std::vector<wv::TuneEntry> tune;
 };

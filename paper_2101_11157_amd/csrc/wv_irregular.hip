@@ -51,7 +51,7 @@ constexpr int kIrrBlock = 32;                        // exponents per transpose
 constexpr uint32_t kIrrUnitT = 2048;                 // exponents per work unit
 constexpr int kIrrStride = 65;                       // LDS row stride (doubles)
 constexpr uint64_t kIrrMaxV = 1ull << 27;            // totals per batch (1 GiB)
-constexpr uint64_t kIrrMaxUnits = 1ull << 24;        // waves per launch (2^30 work-items)
+constexpr uint64_t kIrrMaxUnits = (1ull << 24) - 64;  // units per launch (fewer than 2^32 work-items)
 
 __host__ __device__ inline uint64_t floor_div(uint64_t a, uint64_t b) { return a / b; }
 
@@ -144,6 +144,100 @@ WV_UNROLL
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (half == 0 && b0 + row < e_end) atomicAdd(&V[T.out + b0 + row], t);
+    }
+}
+
+// The same totals as a dense contraction on the matrix cores, for p < 2^21:
+// with e = 128 m + j, s^(t0 + 2e) = A[m][s] B[s][j], A[m][s] = s^(t0 + 256 m),
+// B[s][j] = s^(2j), so V[m][j] = sum_s A[m][s] B[s][j].  Residues below 0.574p
+// make every product an integer below 0.33 p^2 < 2^41 and a 1024-s partial sum
+// an integer below 2^51, exact in the f64 multiply-adds; each partial is
+// reduced mod p before its atomic addition.  A workgroup takes (task, 64 rows
+// of m, 1024 s): per 32 s it builds A (64 x 32) and B (32 x 128) in LDS, then
+// each wave runs 8 v_mfma_f64_16x16x4 per 4 s (its 16 rows x 128 columns).
+constexpr int kMmaRows = 64;                 // rows of m per workgroup
+constexpr int kMmaKc = 32;                   // s per LDS chunk
+constexpr uint64_t kMmaSb = 1024;            // s per workgroup
+constexpr uint64_t kIrrMmaMaxP = 1ull << 21;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_irr_mma(const IrrTask *__restrict__ tasks,
+                                                 const uint64_t *__restrict__ unit_off, uint32_t ntask,
+                                                 uint64_t nunits, double *__restrict__ V) {
+    __shared__ double As[kMmaRows][kMmaKc + 1];
+    __shared__ double Bs[kMmaKc][128 + 1];
+    const uint64_t unit = blockIdx.x;
+    if (unit >= nunits) return;   // whole workgroup
+    const uint32_t j = find_seg(unit_off, ntask, unit);
+    const IrrTask T = tasks[j];
+    Fmod f;
+    f.p = (double)T.p;
+    f.pinv = 1.0 / f.p;
+    const uint32_t M = (T.nt + 127) / 128;
+    const uint32_t rbs = (M + kMmaRows - 1) / kMmaRows;
+    const uint64_t u = unit - unit_off[j];
+    const uint32_t m0 = (uint32_t)(u % rbs) * kMmaRows;
+    const uint64_t sb0 = T.lo + (u / rbs) * kMmaSb;
+    const uint64_t sb1 = min(T.hi, sb0 + kMmaSb);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const bool wave_live = m0 + 16 * wave < M;   // wave-uniform
+    v4d acc[8];
+WV_UNROLL
+    for (int n = 0; n < 8; n++) acc[n] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (uint64_t c0 = sb0; c0 < sb1; c0 += kMmaKc) {
+        // A[m0 + r][s]: thread -> (s = tid % 32, rows 8 (tid / 32) .. + 8)
+        {
+            const int q = tid & 31, g = tid >> 5;
+            const uint64_t sv = c0 + q;
+            const bool in = sv < sb1;
+            const double sd = (double)sv;
+            double x = fpow_e(sd, T.t0 + 256ull * (m0 + 8 * g), f);
+            const double step = fpow_e(sd, 256, f);
+WV_UNROLL
+            for (int r = 0; r < 8; r++) {
+                As[8 * g + r][q] = in ? x : 0.0;
+                x = f_mulmod(x, step, f);
+            }
+        }
+        // B[s][j]: thread -> (s = tid / 8, j = 16 (tid % 8) .. + 16)
+        {
+            const int q = tid >> 3, g = tid & 7;
+            const uint64_t sv = c0 + q;
+            const bool in = sv < sb1;
+            const double sd = (double)sv;
+            const double s2 = f_mulmod(sd, sd, f);
+            double x = fpow_e(s2, 16 * g, f);
+WV_UNROLL
+            for (int r = 0; r < 16; r++) {
+                Bs[q][16 * g + r] = in ? x : 0.0;
+                x = f_mulmod(x, s2, f);
+            }
+        }
+        __syncthreads();
+        if (wave_live) {
+WV_UNROLL
+            for (int kk = 0; kk < kMmaKc / 4; kk++) {
+                const double a = As[16 * wave + (lane & 15)][4 * kk + (lane >> 4)];
+WV_UNROLL
+                for (int n = 0; n < 8; n++) {
+                    const double b = Bs[4 * kk + (lane >> 4)][16 * n + (lane & 15)];
+                    acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[n], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!wave_live) return;
+    // D[i][c] of tile n: lane = c + 16 (i % 4)... element r of lane l is row l / 16 + 4 r, column l % 16
+WV_UNROLL
+    for (int n = 0; n < 8; n++) {
+WV_UNROLL
+        for (int r = 0; r < 4; r++) {
+            const uint32_t m = m0 + 16 * wave + (lane >> 4) + 4 * r;
+            const uint64_t e = 128ull * m + 16 * n + (lane & 15);
+            if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[n][r], f));
+        }
     }
 }
 
@@ -261,18 +355,27 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
     std::vector<uint64_t> roff(1, 0);
     uint64_t vn = 0, res = 0;
     double work = 0.0;
+    // the matrix-core path while every partial sum stays exact (unless the
+    // vector path is requested)
+    const bool mma = c->irr_path != 1 && *std::max_element(ps.begin(), ps.end()) < kIrrMmaMaxP;
+    auto units_of = [&](uint64_t lo, uint64_t hi, uint64_t nt) -> uint64_t {
+        if (mma) {
+            const uint64_t M = (nt + 127) / 128;
+            return (M + kMmaRows - 1) / kMmaRows * ((hi - lo + kMmaSb - 1) / kMmaSb);
+        }
+        return (hi - lo + kIrrWaveS - 1) / kIrrWaveS * ((nt + kIrrUnitT - 1) / kIrrUnitT);
+    };
     for (uint64_t p : ps) {
         const uint32_t nt = (uint32_t)((p - 3) / 2);
         IrrPrime P{p, vn, vn + nt, res, nt, 0};
         uint64_t lo, hi;
         open_range(p, 1, 4, 1, 3, lo, hi);   // Bernoulli: (1/4, 1/3), odd exponents from 1
-        const uint64_t nblk = (nt + kIrrUnitT - 1) / kIrrUnitT;
         tasks.push_back(IrrTask{p, lo, hi, vn, 1, nt});
-        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS * nblk);
+        units.push_back(units.back() + units_of(lo, hi, nt));
         work += (double)(hi - lo) * nt;
         open_range(p, 0, 1, 1, 4, lo, hi);   // Euler: (0, 1/4), even exponents from 2
         tasks.push_back(IrrTask{p, lo, hi, vn + nt, 2, nt});
-        units.push_back(units.back() + (hi - lo + kIrrWaveS - 1) / kIrrWaveS * nblk);
+        units.push_back(units.back() + units_of(lo, hi, nt));
         work += (double)(hi - lo) * nt;
         vn += 2 * (uint64_t)nt;
         res += nt;
@@ -295,8 +398,14 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
     hipLaunchKernelGGL(k_irr_zero, dim3(grid_for(vn, 256)), dim3(256), 0, st, as<double>(c->irr_v), vn);
     WV_HIP(launch_set_u64(st, as<uint64_t>(c->irr_counts), 4, 0));
     WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
-    hipLaunchKernelGGL(k_irr_sum, dim3(grid_for(nunits, 4)), dim3(256), 0, st, as<IrrTask>(c->irr_tasks),
-                       as<uint64_t>(c->irr_units), ntask, nunits, as<double>(c->irr_v));
+    if (mma) {
+        if (nunits)
+            hipLaunchKernelGGL(k_irr_mma, dim3((unsigned)nunits), dim3(256), 0, st, as<IrrTask>(c->irr_tasks),
+                               as<uint64_t>(c->irr_units), ntask, nunits, as<double>(c->irr_v));
+    } else {
+        hipLaunchKernelGGL(k_irr_sum, dim3(grid_for(nunits, 4)), dim3(256), 0, st, as<IrrTask>(c->irr_tasks),
+                           as<uint64_t>(c->irr_units), ntask, nunits, as<double>(c->irr_v));
+    }
     WV_HIP(hipGetLastError());
     WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
     auto *counts = as<unsigned long long>(c->irr_counts);
@@ -349,6 +458,12 @@ int irr_for_batches(const std::vector<uint64_t> &ps, F &&run) {
 }  // namespace wv
 
 using namespace wv;
+
+int wv_set_irregular_path(wv_ctx *c, int path) {
+    if (!c || path < 0 || path > 2) return WV_EINVAL;
+    c->irr_path = path;
+    return WV_OK;
+}
 
 int wv_bernoulli_euler_all(wv_ctx *c, uint64_t p, uint64_t *b, uint64_t *e) {
     if (!c || !b || !e) return WV_EINVAL;

@@ -838,12 +838,20 @@ def test_batched_windows_with_derived_tables(ctx):
 # ---------------------------------------------------------------------------
 
 
+@pytest.fixture(params=[1, 2], ids=["valu", "mfma"])
+def irr_path(request, ctx):
+    """Both power-sum kernels: vector ALU and matrix cores."""
+    ctx.set_irregular_path(request.param)
+    yield request.param
+    ctx.set_irregular_path(0)
+
+
 @pytest.mark.gpu
-def test_all_index_residues_small_primes(ctx):
+def test_all_index_residues_small_primes(ctx, irr_path):
     """B_{2k}, E_{2k} mod p for every 2k <= p - 3 of each prime below 700
     equal the oracle's recurrences, element by element (p = 5, 7 included:
     one and two indices; p = 5 needs the second congruence of the chain)."""
-    say("case: every index, primes below 700")
+    say(f"case: every index, primes below 700, path {irr_path}")
     for p in oracle.primes(5, 700):
         b, e = ctx.bernoulli_euler_all(p)
         assert [int(x) for x in b] == oracle.bernoulli_all(p), p
@@ -852,12 +860,42 @@ def test_all_index_residues_small_primes(ctx):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("p", [2003, 5783, 16843, 30011])
-def test_all_index_residues_larger_primes(ctx, p):
-    """Several waves per range, many 32-exponent blocks, a ragged last block."""
-    say(f"case: every index, p = {p}")
+def test_all_index_residues_larger_primes(ctx, irr_path, p):
+    """Several units per range, many exponent blocks, ragged last rows and
+    columns (vector: 1024 s x 2048 exponents per wave; matrix: 64 rows of 128
+    exponents x 1024 s per workgroup)."""
+    say(f"case: every index, p = {p}, path {irr_path}")
     b, e = ctx.bernoulli_euler_all(p)
     assert [int(x) for x in b] == oracle.bernoulli_all(p)
     assert [int(x) for x in e] == oracle.euler_all(p)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p", [2097143, 4194301])
+def test_all_index_paths_agree_at_scale(ctx, p):
+    """Just below the matrix-core bound (2^21) and above it: the two kernels
+    agree on every index below 2^21, and a few indices agree with the
+    general-index congruence evaluated plainly on the host."""
+    say(f"case: every index at p = {p}")
+    ctx.set_irregular_path(1)
+    try:
+        bv, ev = ctx.bernoulli_euler_all(p)
+    finally:
+        ctx.set_irregular_path(0)
+    ba, ea = ctx.bernoulli_euler_all(p)   # automatic: matrix cores below 2^21
+    assert np.array_equal(bv, ba) and np.array_equal(ev, ea)
+    assert int(bv.max()) < p and int(ev.max()) < p
+    for k in (1, 2, 1234, (p - 3) // 2):
+        # eqnE1 at exponent t = 2k: E_t = (-1)^{k'} 4^{t+1} S_t(0, 1/4), k' = (p-1-t)/2
+        t = 2 * k
+        S = sum(pow(s, t, p) for s in range(1, p // 4 + 1)) % p
+        want = (-1) ** ((p - 1 - t) // 2) * pow(4, t + 1, p) * S % p
+        assert int(ev[k - 1]) == want, k
+        # (2,3,4) at exponent 2k - 1: C_k B_{2k} = S_{2k-1}(1/4, 1/3)
+        c = (pow(2, p - 2 * k, p) + pow(3, p - 2 * k, p) - pow(4, p - 2 * k, p) - 1) * pow(4 * k, -1, p) % p
+        if c:
+            S = sum(pow(s, 2 * k - 1, p) for s in range(p // 4 + 1, p // 3 + 1)) % p
+            assert int(bv[k - 1]) == S * pow(c, -1, p) % p, k
 
 
 @pytest.mark.gpu
