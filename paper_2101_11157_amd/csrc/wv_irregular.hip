@@ -152,21 +152,26 @@ WV_UNROLL
 // B[s][j] = s^(2j), so V[m][j] = sum_s A[m][s] B[s][j].  Residues below 0.574p
 // make every product an integer below 0.33 p^2 < 2^41 and a 1024-s partial sum
 // an integer below 2^51, exact in the f64 multiply-adds; each partial is
-// reduced mod p before its atomic addition.  A workgroup takes (task, 64 rows
-// of m, 1024 s): per 32 s it builds A (64 x 32) and B (32 x 128) in LDS, then
-// each wave runs 8 v_mfma_f64_16x16x4 per 4 s (its 16 rows x 128 columns).
-constexpr int kMmaRows = 64;                 // rows of m per workgroup
+// reduced mod p before its atomic addition.  A workgroup takes (task, 128
+// rows of m, 1024 s): per 32 s it builds A (128 x 32) and B (32 x 128) in LDS,
+// then each wave runs 16 v_mfma_f64_16x16x4 per 4 s (its 32 rows x 128
+// columns).
+constexpr int kMmaRows = 128;                // rows of m per workgroup (32 per wave)
 constexpr int kMmaKc = 32;                   // s per LDS chunk
 constexpr uint64_t kMmaSb = 1024;            // s per workgroup
 constexpr uint64_t kIrrMmaMaxP = 1ull << 21;
+// LDS row strides (doubles): a wave's fragment reads (16 rows x 4 s of A,
+// 4 s x 16 columns of B) then touch each bank pair at most twice
+constexpr int kMmaAs = kMmaKc + 4;
+constexpr int kMmaBs = 128 + 16;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) k_irr_mma(const IrrTask *__restrict__ tasks,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_irr_mma(const IrrTask *__restrict__ tasks,
                                                  const uint64_t *__restrict__ unit_off, uint32_t ntask,
                                                  uint64_t nunits, double *__restrict__ V) {
-    __shared__ double As[kMmaRows][kMmaKc + 1];
-    __shared__ double Bs[kMmaKc][128 + 1];
+    __shared__ double As[kMmaRows * kMmaAs];
+    __shared__ double Bs[kMmaKc * kMmaBs];
     const uint64_t unit = blockIdx.x;
     if (unit >= nunits) return;   // whole workgroup
     const uint32_t j = find_seg(unit_off, ntask, unit);
@@ -181,22 +186,24 @@ __global__ void __launch_bounds__(256) k_irr_mma(const IrrTask *__restrict__ tas
     const uint64_t sb0 = T.lo + (u / rbs) * kMmaSb;
     const uint64_t sb1 = min(T.hi, sb0 + kMmaSb);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool wave_live = m0 + 16 * wave < M;   // wave-uniform
-    v4d acc[8];
+    const bool live0 = m0 + 32 * wave < M, live1 = m0 + 32 * wave + 16 < M;   // wave-uniform
+    v4d acc[2][8];
 WV_UNROLL
-    for (int n = 0; n < 8; n++) acc[n] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int h = 0; h < 2; h++)
+WV_UNROLL
+        for (int n = 0; n < 8; n++) acc[h][n] = v4d{0.0, 0.0, 0.0, 0.0};
     for (uint64_t c0 = sb0; c0 < sb1; c0 += kMmaKc) {
-        // A[m0 + r][s]: thread -> (s = tid % 32, rows 8 (tid / 32) .. + 8)
+        // A[m0 + r][s]: thread -> (s = tid % 32, rows 16 (tid / 32) .. + 16)
         {
             const int q = tid & 31, g = tid >> 5;
             const uint64_t sv = c0 + q;
             const bool in = sv < sb1;
             const double sd = (double)sv;
-            double x = fpow_e(sd, T.t0 + 256ull * (m0 + 8 * g), f);
+            double x = fpow_e(sd, T.t0 + 256ull * (m0 + 16 * g), f);
             const double step = fpow_e(sd, 256, f);
 WV_UNROLL
-            for (int r = 0; r < 8; r++) {
-                As[8 * g + r][q] = in ? x : 0.0;
+            for (int r = 0; r < 16; r++) {
+                As[(16 * g + r) * kMmaAs + q] = in ? x : 0.0;
                 x = f_mulmod(x, step, f);
             }
         }
@@ -210,33 +217,39 @@ WV_UNROLL
             double x = fpow_e(s2, 16 * g, f);
 WV_UNROLL
             for (int r = 0; r < 16; r++) {
-                Bs[q][16 * g + r] = in ? x : 0.0;
+                Bs[q * kMmaBs + 16 * g + r] = in ? x : 0.0;
                 x = f_mulmod(x, s2, f);
             }
         }
         __syncthreads();
-        if (wave_live) {
+        if (live0) {
 WV_UNROLL
             for (int kk = 0; kk < kMmaKc / 4; kk++) {
-                const double a = As[16 * wave + (lane & 15)][4 * kk + (lane >> 4)];
+                const int k = 4 * kk + (lane >> 4);
+                const double a0 = As[(32 * wave + (lane & 15)) * kMmaAs + k];
+                const double a1 = As[(32 * wave + 16 + (lane & 15)) * kMmaAs + k];
 WV_UNROLL
                 for (int n = 0; n < 8; n++) {
-                    const double b = Bs[4 * kk + (lane >> 4)][16 * n + (lane & 15)];
-                    acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[n], 0, 0, 0);
+                    const double b = Bs[k * kMmaBs + 16 * n + (lane & 15)];
+                    acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][n], 0, 0, 0);
+                    if (live1) acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][n], 0, 0, 0);
                 }
             }
         }
         __syncthreads();
     }
-    if (!wave_live) return;
-    // D[i][c] of tile n: lane = c + 16 (i % 4)... element r of lane l is row l / 16 + 4 r, column l % 16
+    if (!live0) return;
+    // element r of lane l of a 16 x 16 tile is row l / 16 + 4 r, column l % 16
 WV_UNROLL
-    for (int n = 0; n < 8; n++) {
+    for (int h = 0; h < 2; h++) {
 WV_UNROLL
-        for (int r = 0; r < 4; r++) {
-            const uint32_t m = m0 + 16 * wave + (lane >> 4) + 4 * r;
-            const uint64_t e = 128ull * m + 16 * n + (lane & 15);
-            if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[n][r], f));
+        for (int n = 0; n < 8; n++) {
+WV_UNROLL
+            for (int r = 0; r < 4; r++) {
+                const uint32_t m = m0 + 32 * wave + 16 * h + (lane >> 4) + 4 * r;
+                const uint64_t e = 128ull * m + 16 * n + (lane & 15);
+                if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[h][n][r], f));
+            }
         }
     }
 }
