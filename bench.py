@@ -46,7 +46,7 @@ BLOCK_ADD = {2: 3, 3: 5}
 # HBM bytes (read + written) of one term-sum launch on the first timed window,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
 # (profiles/k_sum_window_1e11_*.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("1e11", "derived 1408/1283", 28, 36, 8192): 186358446 + 269036896}
 
 
 def tables_key(which):
