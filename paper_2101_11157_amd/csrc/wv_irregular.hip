@@ -31,6 +31,7 @@ struct IrrTask {          // sum_{lo <= s < hi} s^t for t = t0, t0 + 2, ..., t0 
     uint64_t p, lo, hi;
     uint64_t out;         // index in V of the first exponent's total
     uint32_t t0, nt;
+    uint32_t ct, pad;     // matrix-core path: exponents per row = 16 ct (1 <= ct <= 8)
 };
 
 struct IrrPrime {         // one prime of a batch
@@ -148,8 +149,9 @@ WV_UNROLL
 }
 
 // The same totals as a dense contraction on the matrix cores, for p < 2^21:
-// with e = 128 m + j, s^(t0 + 2e) = A[m][s] B[s][j], A[m][s] = s^(t0 + 256 m),
-// B[s][j] = s^(2j), so V[m][j] = sum_s A[m][s] B[s][j].  Residues below 0.574p
+// with e = N m + j (N = 16 ct exponents per row, ct chosen per task so that
+// the rows fill whole row blocks), s^(t0 + 2e) = A[m][s] B[s][j],
+// A[m][s] = s^(t0 + 2N m), B[s][j] = s^(2j), so V[m][j] = sum_s A[m][s] B[s][j].  Residues below 0.574p
 // make every product an integer below 0.33 p^2 < 2^41 and a 1024-s partial sum
 // an integer below 2^51, exact in the f64 multiply-adds; each partial is
 // reduced mod p before its atomic addition.  A workgroup takes (task, 128
@@ -179,7 +181,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     Fmod f;
     f.p = (double)T.p;
     f.pinv = 1.0 / f.p;
-    const uint32_t M = (T.nt + 127) / 128;
+    const uint32_t ct = T.ct, N = 16 * ct;   // exponents per row
+    const uint32_t M = (T.nt + N - 1) / N;
     const uint32_t rbs = (M + kMmaRows - 1) / kMmaRows;
     const uint64_t u = unit - unit_off[j];
     const uint32_t m0 = (uint32_t)(u % rbs) * kMmaRows;
@@ -199,16 +202,16 @@ WV_UNROLL
             const uint64_t sv = c0 + q;
             const bool in = sv < sb1;
             const double sd = (double)sv;
-            double x = fpow_e(sd, T.t0 + 256ull * (m0 + 16 * g), f);
-            const double step = fpow_e(sd, 256, f);
+            double x = fpow_e(sd, T.t0 + 2ull * N * (m0 + 16 * g), f);
+            const double step = fpow_e(sd, 2 * N, f);
 WV_UNROLL
             for (int r = 0; r < 16; r++) {
                 As[(16 * g + r) * kMmaAs + q] = in ? x : 0.0;
                 x = f_mulmod(x, step, f);
             }
         }
-        // B[s][j]: thread -> (s = tid / 8, j = 16 (tid % 8) .. + 16)
-        {
+        // B[s][j]: thread -> (s = tid / 8, j = 16 (tid % 8) .. + 16), j < N
+        if ((uint32_t)(tid & 7) < ct) {
             const int q = tid >> 3, g = tid & 7;
             const uint64_t sv = c0 + q;
             const bool in = sv < sb1;
@@ -230,6 +233,7 @@ WV_UNROLL
                 const double a1 = As[(32 * wave + 16 + (lane & 15)) * kMmaAs + k];
 WV_UNROLL
                 for (int n = 0; n < 8; n++) {
+                    if ((uint32_t)n >= ct) break;   // wave-uniform
                     const double b = Bs[k * kMmaBs + 16 * n + (lane & 15)];
                     acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][n], 0, 0, 0);
                     if (live1) acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][n], 0, 0, 0);
@@ -247,8 +251,8 @@ WV_UNROLL
 WV_UNROLL
             for (int r = 0; r < 4; r++) {
                 const uint32_t m = m0 + 32 * wave + 16 * h + (lane >> 4) + 4 * r;
-                const uint64_t e = 128ull * m + 16 * n + (lane & 15);
-                if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[h][n][r], f));
+                const uint64_t e = (uint64_t)N * m + 16 * n + (lane & 15);
+                if ((uint32_t)n < ct && m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[h][n][r], f));
             }
         }
     }
@@ -371,9 +375,22 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
     // the matrix-core path while every partial sum stays exact (unless the
     // vector path is requested)
     const bool mma = c->irr_path != 1 && *std::max_element(ps.begin(), ps.end()) < kIrrMmaMaxP;
+    // exponents per row 16 ct: the least work over whole row blocks, each row
+    // costing its N multiply-adds per s plus about 8 for building its A entry
+    // (one modular product), ties to wider rows
+    auto cols_of = [](uint64_t nt) -> uint32_t {
+        uint32_t best = 8;
+        uint64_t best_w = UINT64_MAX;
+        for (uint32_t ct = 8; ct >= 1; ct--) {
+            const uint64_t N = 16 * ct, M = (nt + N - 1) / N;
+            const uint64_t w = (M + kMmaRows - 1) / kMmaRows * kMmaRows * (N + 8);
+            if (w < best_w) best_w = w, best = ct;
+        }
+        return best;
+    };
     auto units_of = [&](uint64_t lo, uint64_t hi, uint64_t nt) -> uint64_t {
         if (mma) {
-            const uint64_t M = (nt + 127) / 128;
+            const uint64_t N = 16 * cols_of(nt), M = (nt + N - 1) / N;
             return (M + kMmaRows - 1) / kMmaRows * ((hi - lo + kMmaSb - 1) / kMmaSb);
         }
         return (hi - lo + kIrrWaveS - 1) / kIrrWaveS * ((nt + kIrrUnitT - 1) / kIrrUnitT);
@@ -383,11 +400,11 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
         IrrPrime P{p, vn, vn + nt, res, nt, 0};
         uint64_t lo, hi;
         open_range(p, 1, 4, 1, 3, lo, hi);   // Bernoulli: (1/4, 1/3), odd exponents from 1
-        tasks.push_back(IrrTask{p, lo, hi, vn, 1, nt});
+        tasks.push_back(IrrTask{p, lo, hi, vn, 1, nt, cols_of(nt), 0});
         units.push_back(units.back() + units_of(lo, hi, nt));
         work += (double)(hi - lo) * nt;
         open_range(p, 0, 1, 1, 4, lo, hi);   // Euler: (0, 1/4), even exponents from 2
-        tasks.push_back(IrrTask{p, lo, hi, vn + nt, 2, nt});
+        tasks.push_back(IrrTask{p, lo, hi, vn + nt, 2, nt, cols_of(nt), 0});
         units.push_back(units.back() + units_of(lo, hi, nt));
         work += (double)(hi - lo) * nt;
         vn += 2 * (uint64_t)nt;
