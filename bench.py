@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--tables", default="derived", choices=["derived", "printed"],
                     help="derived: the package's greedy-derived congruences (Section 2.2) above 2^30, "
                          "printed: eqnBB30 + eqnEE33")
+    ap.add_argument("--irr-path", default="auto", choices=["auto", "valu", "mfma"],
+                    help="irregular: power-sum kernel (auto: matrix cores below 2^21)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-primes", type=int, default=1, help="primes in the oracle sample")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -285,8 +287,11 @@ def main():
 
 
 # one (s, t) pair of the all-exponent power sums on the matrix cores: one f64
-# multiply-add (2 flops) of the power tables s^(t0 + 256 m) and s^(2j)
+# multiply-add (2 flops) of the power tables s^(t0 + 2N m) and s^(2j)
 FLOPS_IRR_PAIR = 2
+# the same pair on the vector ALU: an exact modular product (5 lane operations)
+# and an exact addition (2)
+OPS_IRR_PAIR_VALU = 7
 PEAK_MFMA_F64 = 78.6e12                  # dense f64 matrix peak of MI355X
 
 
@@ -305,6 +310,7 @@ def bench_irregular(args, wv):
         sys.exit(2)
     wins = [(lo0 + k * W, lo0 + (k + 1) * W) for k in range(nwin)]
     ctx = wv.Context(0)
+    ctx.set_irregular_path({"auto": 0, "valu": 1, "mfma": 2}[args.irr_path])
     for k in range(args.warmup):
         ctx.irregular_pairs(*wins[k])
         print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
@@ -357,6 +363,14 @@ def bench_irregular(args, wv):
             "traffic": None,
         },
     }
+    if args.irr_path == "valu":
+        # the vector kernel: one exact modular product and one exact addition
+        # (OPS_IRR_PAIR_VALU lane operations) per (s, t) pair on the VALU
+        ops = OPS_IRR_PAIR_VALU * pairs_st / (ms_sum * 1e-3) / 1e12
+        line["roofline"] = {"bound": "alu", "achieved": ops, "peak": PEAK_VALU / 1e12,
+                            "unit": "Tops/s (full-rate VALU lane ops)", "frac": ops / (PEAK_VALU / 1e12),
+                            "traffic": None}
+        line["config"]["kernel"] = "vector ALU"
     if not args.no_cpu_baseline and first is not None:
         import oracle
         from concurrent.futures import ThreadPoolExecutor

@@ -343,7 +343,10 @@ int wv_server_submit_range(wv_server *srv, uint64_t lo, uint64_t hi, uint64_t *i
 /* A list of primes (validated like wv_eval_primes; at most max_primes). */
 int wv_server_submit_primes(wv_server *srv, const uint64_t *primes, size_t n, uint64_t *id);
 /* Admit what fits, then run one step of work; returns after the step's GPU
- * work.  A failed step (HIP error) restarts every active request from its
+ * work.  Admission takes requests pending for 2 s or more in arrival order,
+ * then the smallest first (a list by its length, a range by its expected
+ * number of primes), and plans at most 2^22 sums per step; a request that
+ * does not fit in the pool waits without blocking others.  A failed step (HIP error) restarts every active request from its
  * plan, so no partial state of the failed step survives. */
 int wv_server_step(wv_server *srv, uint32_t *n_active, uint32_t *n_pending);
 /* Results of a finished request (then forgotten); WV_EBUSY while it runs,

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -433,15 +434,41 @@ int wv_server_submit_primes(wv_server *s, const uint64_t *primes, size_t n, uint
     return WV_OK;
 }
 
+// Sums planned into the pool per step at most (planning copies each sum's
+// record to the host), so that admitting a burst of large requests does not
+// hold back the next step.
+constexpr size_t kAdmitSums = 1u << 22;
+// A request pending longer than this is admitted before smaller ones, in
+// arrival order, so that a stream of small requests cannot starve it.
+constexpr double kAdmitAgeS = 2.0;
+
 int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     if (!s) return WV_EINVAL;
     WV_TRY(check_device(s->c));
-    // admit in arrival order; a request that does not fit yet does not block
-    // smaller ones behind it
+    // admit requests pending for kAdmitAgeS or more in arrival order, then the
+    // smallest first (a prime list by its length, a range by its expected prime
+    // count), arrival order among equals, within the per-step budget of sums;
+    // a request that does not fit in the pool yet does not block those behind it
+    auto size_of = [](const Request *r) -> double {
+        return r->is_range ? (double)(r->hi - r->lo) / std::max(1.0, std::log((double)std::max<uint64_t>(r->hi, 3)))
+                           : (double)r->primes.size();
+    };
+    const double t_old = now_s() - kAdmitAgeS;
+    std::stable_sort(s->pending.begin(), s->pending.end(), [&](const Request *a, const Request *b) {
+        const bool oa = a->t_submit <= t_old, ob = b->t_submit <= t_old;
+        if (oa != ob) return oa;
+        if (oa) return a->t_submit < b->t_submit;
+        return size_of(a) < size_of(b);
+    });
+    size_t admitted_sums = 0;
     std::deque<Request *> waiting;
     while (!s->pending.empty()) {
         Request *r = s->pending.front();
         s->pending.pop_front();
+        if (admitted_sums >= kAdmitSums) {
+            waiting.push_back(r);
+            continue;
+        }
         bool ok = false;
         const int rc = admit(s, r, &ok);
         if (rc != WV_OK) {
@@ -455,6 +482,7 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
             continue;
         }
         if (!ok) waiting.push_back(r);
+        else admitted_sums += (size_t)r->n * s->NS;
     }
     s->pending.swap(waiting);
     int rc = s->active.empty() ? WV_OK : run_step(s);
