@@ -74,6 +74,16 @@ __device__ inline double fpow_e(double a, uint64_t e, const Fmod &f) {
     return r;
 }
 
+// a^e for e < 8 without branches
+__device__ inline double fpow_lt8(double a, uint32_t e, const Fmod &f) {
+    const double a2 = f_mulmod(a, a, f), a4 = f_mulmod(a2, a2, f);
+    double r = (e & 1) ? a : 1.0;
+    const double r2 = f_mulmod(r, a2, f);
+    r = (e & 2) ? r2 : r;
+    const double r4 = f_mulmod(r, a4, f);
+    return (e & 4) ? r4 : r;
+}
+
 __device__ inline uint64_t u_pow(uint64_t a, uint64_t e, const Fmod &f) {
     return f_canon(fpow_e((double)a, e, f), f);
 }
@@ -155,90 +165,127 @@ WV_UNROLL
 // make every product an integer below 0.33 p^2 < 2^41 and a 1024-s partial sum
 // an integer below 2^51, exact in the f64 multiply-adds; each partial is
 // reduced mod p before its atomic addition.  A workgroup takes (task, 128
-// rows of m, 1024 s): per 32 s it builds A (128 x 32) and B (32 x 128) in LDS,
-// then each wave runs 16 v_mfma_f64_16x16x4 per 4 s (its 32 rows x 128
-// columns).
-constexpr int kMmaRows = 128;                // rows of m per workgroup (32 per wave)
+// rows of m, 1024 s) with eight waves in two roles: four producer waves build
+// the A (128 x 32) and transposed B (N x 32) slices of the next 32 s in one
+// LDS buffer while the four consumer waves run v_mfma_f64_16x16x4 on the other
+// (each its 32 rows x N columns, 2 ct operations per 4 s), one barrier per
+// 32 s.  A producer and a consumer wave share each SIMD, so the table
+// arithmetic on the vector ALU overlaps the matrix cores.
+constexpr int kMmaRows = 128;                // rows of m per workgroup (32 per consumer wave)
 constexpr int kMmaKc = 32;                   // s per LDS chunk
 constexpr uint64_t kMmaSb = 1024;            // s per workgroup
 constexpr uint64_t kIrrMmaMaxP = 1ull << 21;
-// LDS row strides (doubles): a wave's fragment reads (16 rows x 4 s of A,
-// 4 s x 16 columns of B) then touch each bank pair at most twice
+constexpr int kMmaThreads = 512;             // 4 consumer + 4 producer waves
+// LDS row stride (doubles) of A and of the transposed B: a wave's fragment
+// reads (16 rows x 4 s) then touch each bank pair at most twice
 constexpr int kMmaAs = kMmaKc + 4;
-constexpr int kMmaBs = 128 + 16;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_irr_mma(const IrrTask *__restrict__ tasks,
-                                                 const uint64_t *__restrict__ unit_off, uint32_t ntask,
-                                                 uint64_t nunits, double *__restrict__ V) {
-    __shared__ double As[kMmaRows * kMmaAs];
-    __shared__ double Bs[kMmaKc * kMmaBs];
-    const uint64_t unit = blockIdx.x;
-    if (unit >= nunits) return;   // whole workgroup
-    const uint32_t j = find_seg(unit_off, ntask, unit);
-    const IrrTask T = tasks[j];
-    Fmod f;
-    f.p = (double)T.p;
-    f.pinv = 1.0 / f.p;
-    const uint32_t ct = T.ct, N = 16 * ct;   // exponents per row
-    const uint32_t M = (T.nt + N - 1) / N;
-    const uint32_t rbs = (M + kMmaRows - 1) / kMmaRows;
-    const uint64_t u = unit - unit_off[j];
-    const uint32_t m0 = (uint32_t)(u % rbs) * kMmaRows;
-    const uint64_t sb0 = T.lo + (u / rbs) * kMmaSb;
-    const uint64_t sb1 = min(T.hi, sb0 + kMmaSb);
+// One 32-s chunk of a consumer wave: its 32 rows (16 when !LIVE1) x 16 CT
+// columns.  CT and LIVE1 are compile-time; the LDS operands of the next 4-s
+// step are read while the matrix operations of the current one run (two
+// register sets, a scheduling fence per step keeps the reads from being
+// hoisted further).
+template <int CT, bool LIVE1>
+__device__ __forceinline__ void mma_chunk(const double *A, const double *B, int wave, int lane, v4d (&acc)[2][8]) {
+    double a0[2], a1[2], b[2][CT];
+    const double *Ar = A + (32 * wave + (lane & 15)) * kMmaAs + (lane >> 4);
+    const double *Br = B + (lane & 15) * kMmaAs + (lane >> 4);
+    auto load = [&](int kk, int slot) {
+        a0[slot] = Ar[4 * kk];
+        a1[slot] = LIVE1 ? Ar[16 * kMmaAs + 4 * kk] : 0.0;
+WV_UNROLL
+        for (int n = 0; n < CT; n++) b[slot][n] = Br[16 * n * kMmaAs + 4 * kk];
+    };
+    load(0, 0);
+WV_UNROLL
+    for (int kk = 0; kk < kMmaKc / 4; kk++) {
+        const int cur = kk & 1;
+        if (kk + 1 < kMmaKc / 4) load(kk + 1, cur ^ 1);
+WV_UNROLL
+        for (int n = 0; n < CT; n++) {
+            acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[cur], b[cur][n], acc[0][n], 0, 0, 0);
+            if (LIVE1) acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[cur], b[cur][n], acc[1][n], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The workgroup's unit (task T, row block rb of M rows, s in [sb0, sb1)) with
+// N = 16 CT exponents per row; CT is compile-time so that each width has its
+// own accumulators and straight-line matrix code.
+template <int CT>
+__device__ __forceinline__ void irr_mma_unit(const IrrTask &T, const Fmod &f, uint32_t rb, uint32_t M, uint64_t sb0,
+                                             uint64_t sb1, double (&As)[2][kMmaRows * kMmaAs],
+                                             double (&Bs)[2][kMmaRows * kMmaAs], double *__restrict__ V) {
+    constexpr uint32_t N = 16 * CT;
+    const uint32_t m0 = rb * kMmaRows;
+    const uint32_t nchunk = (uint32_t)((sb1 - sb0 + kMmaKc - 1) / kMmaKc);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool live0 = m0 + 32 * wave < M, live1 = m0 + 32 * wave + 16 < M;   // wave-uniform
+    const bool producer = tid >= 256;   // wave-uniform
+    const int ptid = tid - 256;
+
+    // tables of chunk c into buffer c & 1: producer thread (q, g) takes
+    // s = sb0 + 32c + q and writes rows 16g .. 16g + 15 of A (A[m][s] =
+    // s^(t0 + 2N(m0 + m))) and of the transposed B (Bt[j][s] = s^(2j); rows
+    // j >= N are written and never read).  Every power comes from s^2, s^16,
+    // s^32, s^(2N) = (s^32)^CT and its squares; the 16 entries of each table
+    // run as two chains of 8, so a thread carries four independent chains.
+    auto produce = [&](uint32_t c) {
+        double *A = As[c & 1];
+        double *Bt = Bs[c & 1];
+        const int q = ptid & 31, g = ptid >> 5;
+        const uint64_t sv = sb0 + (uint64_t)c * kMmaKc + q;
+        const bool in = sv < sb1;
+        const double sd = (double)sv;
+        const double s2 = f_mulmod(sd, sd, f);
+        double s16 = s2;
+WV_UNROLL
+        for (int i = 0; i < 3; i++) s16 = f_mulmod(s16, s16, f);   // s^16
+        const double h = f_mulmod(s16, s16, f);                    // s^32
+        const double step = fpow_e(h, CT, f);                      // s^(2N)
+        double step8 = step;
+WV_UNROLL
+        for (int i = 0; i < 3; i++) step8 = f_mulmod(step8, step8, f);   // s^(16N)
+        const double h16 = f_mulmod(step8, step8, f);                   // s^(32N)
+        double h128 = h16;
+WV_UNROLL
+        for (int i = 0; i < 3; i++) h128 = f_mulmod(h128, h128, f);   // s^(256N)
+        // s^(t0) s^(256N rb) s^(32N g) = s^(t0 + 2N (m0 + 16 g))
+        const double base = f_mulmod(fpow_e(h128, rb, f), fpow_e(sd, T.t0, f), f);
+        double xa0 = f_mulmod(base, fpow_lt8(h16, (uint32_t)g, f), f);
+        double xa1 = f_mulmod(xa0, step8, f);
+        double xb0 = fpow_lt8(h, (uint32_t)g, f);                      // s^(32g)
+        double xb1 = f_mulmod(xb0, s16, f);
+WV_UNROLL
+        for (int r = 0; r < 8; r++) {
+            A[(16 * g + r) * kMmaAs + q] = in ? xa0 : 0.0;
+            A[(16 * g + 8 + r) * kMmaAs + q] = in ? xa1 : 0.0;
+            Bt[(16 * g + r) * kMmaAs + q] = in ? xb0 : 0.0;
+            Bt[(16 * g + 8 + r) * kMmaAs + q] = in ? xb1 : 0.0;
+            xa0 = f_mulmod(xa0, step, f);
+            xa1 = f_mulmod(xa1, step, f);
+            xb0 = f_mulmod(xb0, s2, f);
+            xb1 = f_mulmod(xb1, s2, f);
+        }
+    };
+
+    const bool live0 = !producer && m0 + 32 * wave < M, live1 = !producer && m0 + 32 * wave + 16 < M;   // wave-uniform
     v4d acc[2][8];
 WV_UNROLL
     for (int h = 0; h < 2; h++)
 WV_UNROLL
-        for (int n = 0; n < 8; n++) acc[h][n] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (uint64_t c0 = sb0; c0 < sb1; c0 += kMmaKc) {
-        // A[m0 + r][s]: thread -> (s = tid % 32, rows 16 (tid / 32) .. + 16)
-        {
-            const int q = tid & 31, g = tid >> 5;
-            const uint64_t sv = c0 + q;
-            const bool in = sv < sb1;
-            const double sd = (double)sv;
-            double x = fpow_e(sd, T.t0 + 2ull * N * (m0 + 16 * g), f);
-            const double step = fpow_e(sd, 2 * N, f);
-WV_UNROLL
-            for (int r = 0; r < 16; r++) {
-                As[(16 * g + r) * kMmaAs + q] = in ? x : 0.0;
-                x = f_mulmod(x, step, f);
-            }
-        }
-        // B[s][j]: thread -> (s = tid / 8, j = 16 (tid % 8) .. + 16), j < N
-        if ((uint32_t)(tid & 7) < ct) {
-            const int q = tid >> 3, g = tid & 7;
-            const uint64_t sv = c0 + q;
-            const bool in = sv < sb1;
-            const double sd = (double)sv;
-            const double s2 = f_mulmod(sd, sd, f);
-            double x = fpow_e(s2, 16 * g, f);
-WV_UNROLL
-            for (int r = 0; r < 16; r++) {
-                Bs[q * kMmaBs + 16 * g + r] = in ? x : 0.0;
-                x = f_mulmod(x, s2, f);
-            }
-        }
-        __syncthreads();
-        if (live0) {
-WV_UNROLL
-            for (int kk = 0; kk < kMmaKc / 4; kk++) {
-                const int k = 4 * kk + (lane >> 4);
-                const double a0 = As[(32 * wave + (lane & 15)) * kMmaAs + k];
-                const double a1 = As[(32 * wave + 16 + (lane & 15)) * kMmaAs + k];
-WV_UNROLL
-                for (int n = 0; n < 8; n++) {
-                    if ((uint32_t)n >= ct) break;   // wave-uniform
-                    const double b = Bs[k * kMmaBs + 16 * n + (lane & 15)];
-                    acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][n], 0, 0, 0);
-                    if (live1) acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][n], 0, 0, 0);
-                }
-            }
+        for (int n = 0; n < CT; n++) acc[h][n] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (producer) produce(0);
+    __syncthreads();
+    for (uint32_t c = 0; c < nchunk; c++) {
+        if (producer) {
+            if (c + 1 < nchunk) produce(c + 1);
+        } else if (live1) {
+            mma_chunk<CT, true>(As[c & 1], Bs[c & 1], wave, lane, acc);
+        } else if (live0) {
+            mma_chunk<CT, false>(As[c & 1], Bs[c & 1], wave, lane, acc);
         }
         __syncthreads();
     }
@@ -247,14 +294,45 @@ WV_UNROLL
 WV_UNROLL
     for (int h = 0; h < 2; h++) {
 WV_UNROLL
-        for (int n = 0; n < 8; n++) {
+        for (int n = 0; n < CT; n++) {
 WV_UNROLL
             for (int r = 0; r < 4; r++) {
                 const uint32_t m = m0 + 32 * wave + 16 * h + (lane >> 4) + 4 * r;
                 const uint64_t e = (uint64_t)N * m + 16 * n + (lane & 15);
-                if ((uint32_t)n < ct && m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[h][n][r], f));
+                if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[h][n][r], f));
             }
         }
+    }
+}
+
+__global__ void __launch_bounds__(kMmaThreads) k_irr_mma(const IrrTask *__restrict__ tasks,
+                                                         const uint64_t *__restrict__ unit_off, uint32_t ntask,
+                                                         uint64_t nunits, double *__restrict__ V) {
+    __shared__ double As[2][kMmaRows * kMmaAs];
+    __shared__ double Bs[2][kMmaRows * kMmaAs];
+    const uint64_t unit = blockIdx.x;
+    if (unit >= nunits) return;   // whole workgroup
+    const uint32_t j = find_seg(unit_off, ntask, unit);
+    const IrrTask T = tasks[j];
+    Fmod f;
+    f.p = (double)T.p;
+    f.pinv = 1.0 / f.p;
+    const uint32_t N = 16 * T.ct;   // exponents per row
+    const uint32_t M = (T.nt + N - 1) / N;
+    const uint32_t rbs = (M + kMmaRows - 1) / kMmaRows;
+    const uint64_t u = unit - unit_off[j];
+    const uint32_t rb = (uint32_t)(u % rbs);
+    const uint64_t sb0 = T.lo + (u / rbs) * kMmaSb;
+    const uint64_t sb1 = min(T.hi, sb0 + kMmaSb);
+    switch (T.ct) {   // workgroup-uniform
+        case 1: irr_mma_unit<1>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        case 2: irr_mma_unit<2>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        case 3: irr_mma_unit<3>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        case 4: irr_mma_unit<4>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        case 5: irr_mma_unit<5>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        case 6: irr_mma_unit<6>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        case 7: irr_mma_unit<7>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        default: irr_mma_unit<8>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
     }
 }
 
@@ -430,7 +508,7 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
     WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
     if (mma) {
         if (nunits)
-            hipLaunchKernelGGL(k_irr_mma, dim3((unsigned)nunits), dim3(256), 0, st, as<IrrTask>(c->irr_tasks),
+            hipLaunchKernelGGL(k_irr_mma, dim3((unsigned)nunits), dim3(kMmaThreads), 0, st, as<IrrTask>(c->irr_tasks),
                                as<uint64_t>(c->irr_units), ntask, nunits, as<double>(c->irr_v));
     } else {
         hipLaunchKernelGGL(k_irr_sum, dim3(grid_for(nunits, 4)), dim3(256), 0, st, as<IrrTask>(c->irr_tasks),

@@ -859,11 +859,12 @@ def test_all_index_residues_small_primes(ctx, irr_path):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("p", [2003, 5783, 16843, 30011])
+@pytest.mark.parametrize("p", [2003, 5783, 16843, 30011, 33013])
 def test_all_index_residues_larger_primes(ctx, irr_path, p):
     """Several units per range, many exponent blocks, ragged last rows and
-    columns (vector: 1024 s x 2048 exponents per wave; matrix: 64 rows of 128
-    exponents x 1024 s per workgroup)."""
+    columns (vector: 1024 s x 2048 exponents per wave; matrix: 128 rows of
+    16 ct exponents x 1024 s per workgroup; at 33013, ct = 3 and three row
+    blocks, the last one 88 rows deep)."""
     say(f"case: every index, p = {p}, path {irr_path}")
     b, e = ctx.bernoulli_euler_all(p)
     assert [int(x) for x in b] == oracle.bernoulli_all(p)
