@@ -286,6 +286,21 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def mfma_f64_attained():
+    """f64 matrix flops per second that independent back-to-back
+    v_mfma_f64_16x16x4_f64 operations attain (libwvpeak.so); None if the
+    library is not built."""
+    import ctypes
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2101_11157_amd", "libwvpeak.so")
+    if not os.path.exists(path):
+        return None
+    L = ctypes.CDLL(path)
+    L.wv_peak_mfma_f64.restype = ctypes.c_int
+    L.wv_peak_mfma_f64.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    v = ctypes.c_double(0.0)
+    return v.value if L.wv_peak_mfma_f64(0, ctypes.byref(v)) == 0 else None
+
+
 # one (s, t) pair of the all-exponent power sums on the matrix cores: one f64
 # multiply-add (2 flops) of the power tables s^(t0 + 2N m) and s^(2j)
 FLOPS_IRR_PAIR = 2
@@ -311,6 +326,7 @@ def bench_irregular(args, wv):
     wins = [(lo0 + k * W, lo0 + (k + 1) * W) for k in range(nwin)]
     ctx = wv.Context(0)
     ctx.set_irregular_path({"auto": 0, "valu": 1, "mfma": 2}[args.irr_path])
+    attained = mfma_f64_attained()
     for k in range(args.warmup):
         ctx.irregular_pairs(*wins[k])
         print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
@@ -363,6 +379,11 @@ def bench_irregular(args, wv):
             "traffic": None,
         },
     }
+    if attained:
+        # context for the published peak: what back-to-back independent f64
+        # matrix operations attain on this device
+        line["mfma_f64_attained"] = {"value": attained / 1e12, "unit": "TFLOP/s",
+                                     "frac": achieved / (attained / 1e12)}
     if args.irr_path == "valu":
         # the vector kernel: one exact modular product and one exact addition
         # (OPS_IRR_PAIR_VALU lane operations) per (s, t) pair on the VALU

@@ -1,5 +1,6 @@
-// peak.hip -- instruction-rate microbenchmark for the roofline of the term-sum
-// kernel (libwvpeak.so, C ABI: wv_peak_rates).
+// peak.hip -- instruction-rate microbenchmarks for the rooflines of the
+// term-sum kernel and the matrix-core power sums (libwvpeak.so, C ABI:
+// wv_peak_rates, wv_peak_mfma_f64).
 //
 // Each kernel runs NCHAIN independent dependency chains of one VALU
 // instruction class per lane, so issue rate (not latency) bounds it.  The
@@ -77,6 +78,23 @@ __global__ void __launch_bounds__(256) k_fma64(uint64_t *out, uint32_t a, int it
 
 typedef void (*kfn)(uint64_t *, uint32_t, int);
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4_f64 back to back: NCHAIN independent 16 x 16
+// accumulators per wave, 2048 flops per operation.
+__global__ void __launch_bounds__(256) k_mfma64(double *out, int iters) {
+    v4d acc[NCHAIN];
+    for (int c = 0; c < NCHAIN; c++) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+    const double a = 1.0 + 1e-9 * threadIdx.x, b = 1.0 - 1e-9 * threadIdx.x;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int c = 0; c < NCHAIN; c++) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    }
+    double s = 0;
+    for (int c = 0; c < NCHAIN; c++) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -116,6 +134,36 @@ int wv_peak_rates(int dev, double *rates) {
         const double ops = (double)blocks * threads * iters * UNROLL * NCHAIN;
         rates[k] = ops / (ms * 1e-3);
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    return rc;
+}
+
+// Dense f64 matrix rate attained on device `dev` (flops per second) by
+// independent v_mfma_f64_16x16x4_f64 operations, four waves per SIMD.
+// Returns 0 on success.
+int wv_peak_mfma_f64(int dev, double *flops) {
+    if (!flops) return -1;
+    if (hipSetDevice(dev) != hipSuccess) return -6;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -6;
+    const int blocks = prop.multiProcessorCount * 4;
+    const int threads = 256;
+    const int iters = 8192;
+    double *buf = nullptr;
+    if (hipMalloc(&buf, (size_t)blocks * threads * sizeof(double)) != hipSuccess) return -5;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -6;
+    int rc = 0;
+    hipLaunchKernelGGL(k_mfma64, dim3(blocks), dim3(threads), 0, 0, buf, 64);   // warm-up
+    (void)hipEventRecord(e0, 0);
+    hipLaunchKernelGGL(k_mfma64, dim3(blocks), dim3(threads), 0, 0, buf, iters);
+    (void)hipEventRecord(e1, 0);
+    if (hipEventSynchronize(e1) != hipSuccess) rc = -6;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *flops = (double)blocks * (threads / 64) * iters * NCHAIN * 2048.0 / (ms * 1e-3);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(buf);

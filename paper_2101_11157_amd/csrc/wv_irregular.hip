@@ -163,38 +163,40 @@ WV_UNROLL
 // the rows fill whole row blocks), s^(t0 + 2e) = A[m][s] B[s][j],
 // A[m][s] = s^(t0 + 2N m), B[s][j] = s^(2j), so V[m][j] = sum_s A[m][s] B[s][j].  Residues below 0.574p
 // make every product an integer below 0.33 p^2 < 2^41 and a 1024-s partial sum
-// an integer below 2^51, exact in the f64 multiply-adds; each partial is
-// reduced mod p before its atomic addition.  A workgroup takes (task, 128
-// rows of m, 1024 s) with eight waves in two roles: four producer waves build
-// the A (128 x 32) and transposed B (N x 32) slices of the next 32 s in one
-// LDS buffer while the four consumer waves run v_mfma_f64_16x16x4 on the other
-// (each its 32 rows x N columns, 2 ct operations per 4 s), one barrier per
-// 32 s.  A producer and a consumer wave share each SIMD, so the table
-// arithmetic on the vector ALU overlaps the matrix cores.
-constexpr int kMmaRows = 128;                // rows of m per workgroup (32 per consumer wave)
+// an integer below 2^51, exact in the f64 multiply-adds; the accumulators are
+// reduced mod p after every 1024 s and before their atomic additions.  A
+// workgroup takes (task, 128 rows of m, kMmaSb s) with twelve waves in two roles: four producer waves
+// build the A (128 x 32) and transposed B (N x 32) slices of the next 32 s in
+// one LDS buffer while eight consumer waves run v_mfma_f64_16x16x4 on the
+// other (each its 16 rows x N columns, ct operations per 4 s), one barrier per
+// 32 s.  Each SIMD holds two consumer waves (one issues while the other waits
+// on LDS) and one producer wave, so the table arithmetic on the vector ALU
+// overlaps the matrix cores.
+constexpr int kMmaRows = 128;                // rows of m per workgroup
 constexpr int kMmaKc = 32;                   // s per LDS chunk
 constexpr uint64_t kMmaSb = 1024;            // s per workgroup
+constexpr uint32_t kMmaReduce = 1024 / kMmaKc;   // chunks between reductions of the accumulators
 constexpr uint64_t kIrrMmaMaxP = 1ull << 21;
-constexpr int kMmaThreads = 512;             // 4 consumer + 4 producer waves
+constexpr int kMmaConsumers = 512;           // 8 consumer waves, 16 rows each
+constexpr int kMmaThreads = kMmaConsumers + 256;   // and 4 producer waves
 // LDS row stride (doubles) of A and of the transposed B: a wave's fragment
 // reads (16 rows x 4 s) then touch each bank pair at most twice
 constexpr int kMmaAs = kMmaKc + 4;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// One 32-s chunk of a consumer wave: its 32 rows (16 when !LIVE1) x 16 CT
-// columns.  CT and LIVE1 are compile-time; the LDS operands of the next 4-s
-// step are read while the matrix operations of the current one run (two
-// register sets, a scheduling fence per step keeps the reads from being
-// hoisted further).
-template <int CT, bool LIVE1>
-__device__ __forceinline__ void mma_chunk(const double *A, const double *B, int wave, int lane, v4d (&acc)[2][8]) {
-    double a0[2], a1[2], b[2][CT];
-    const double *Ar = A + (32 * wave + (lane & 15)) * kMmaAs + (lane >> 4);
+// One 32-s chunk of a consumer wave: its 16 rows x 16 CT columns.  CT is
+// compile-time; the LDS operands of the next 4-s step are read while the
+// matrix operations of the current one run (two register sets; the group
+// barriers put the reads (mask 0x100) ahead of the matrix operations (mask
+// 0x8), the fence keeps them from being hoisted further).
+template <int CT>
+__device__ __forceinline__ void mma_chunk(const double *A, const double *B, int wave, int lane, v4d (&acc)[8]) {
+    double a[2], b[2][CT];
+    const double *Ar = A + (16 * wave + (lane & 15)) * kMmaAs + (lane >> 4);
     const double *Br = B + (lane & 15) * kMmaAs + (lane >> 4);
     auto load = [&](int kk, int slot) {
-        a0[slot] = Ar[4 * kk];
-        a1[slot] = LIVE1 ? Ar[16 * kMmaAs + 4 * kk] : 0.0;
+        a[slot] = Ar[4 * kk];
 WV_UNROLL
         for (int n = 0; n < CT; n++) b[slot][n] = Br[16 * n * kMmaAs + 4 * kk];
     };
@@ -204,10 +206,10 @@ WV_UNROLL
         const int cur = kk & 1;
         if (kk + 1 < kMmaKc / 4) load(kk + 1, cur ^ 1);
 WV_UNROLL
-        for (int n = 0; n < CT; n++) {
-            acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[cur], b[cur][n], acc[0][n], 0, 0, 0);
-            if (LIVE1) acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[cur], b[cur][n], acc[1][n], 0, 0, 0);
-        }
+        for (int n = 0; n < CT; n++)
+            acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur], b[cur][n], acc[n], 0, 0, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1 + CT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x8, CT, 0);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -223,8 +225,8 @@ __device__ __forceinline__ void irr_mma_unit(const IrrTask &T, const Fmod &f, ui
     const uint32_t m0 = rb * kMmaRows;
     const uint32_t nchunk = (uint32_t)((sb1 - sb0 + kMmaKc - 1) / kMmaKc);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool producer = tid >= 256;   // wave-uniform
-    const int ptid = tid - 256;
+    const bool producer = tid >= kMmaConsumers;   // wave-uniform
+    const int ptid = tid - kMmaConsumers;
 
     // tables of chunk c into buffer c & 1: producer thread (q, g) takes
     // s = sb0 + 32c + q and writes rows 16g .. 16g + 15 of A (A[m][s] =
@@ -271,36 +273,35 @@ WV_UNROLL
         }
     };
 
-    const bool live0 = !producer && m0 + 32 * wave < M, live1 = !producer && m0 + 32 * wave + 16 < M;   // wave-uniform
-    v4d acc[2][8];
+    const bool live = !producer && m0 + 16 * wave < M;   // wave-uniform
+    v4d acc[8];
 WV_UNROLL
-    for (int h = 0; h < 2; h++)
-WV_UNROLL
-        for (int n = 0; n < CT; n++) acc[h][n] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int n = 0; n < CT; n++) acc[n] = v4d{0.0, 0.0, 0.0, 0.0};
     if (producer) produce(0);
     __syncthreads();
     for (uint32_t c = 0; c < nchunk; c++) {
         if (producer) {
             if (c + 1 < nchunk) produce(c + 1);
-        } else if (live1) {
-            mma_chunk<CT, true>(As[c & 1], Bs[c & 1], wave, lane, acc);
-        } else if (live0) {
-            mma_chunk<CT, false>(As[c & 1], Bs[c & 1], wave, lane, acc);
+        } else if (live) {
+            mma_chunk<CT>(As[c & 1], Bs[c & 1], wave, lane, acc);
+            if (c % kMmaReduce == kMmaReduce - 1) {
+WV_UNROLL
+                for (int n = 0; n < CT; n++)
+WV_UNROLL
+                    for (int r = 0; r < 4; r++) acc[n][r] = f_reduce(acc[n][r], f);
+            }
         }
         __syncthreads();
     }
-    if (!live0) return;
+    if (!live) return;
     // element r of lane l of a 16 x 16 tile is row l / 16 + 4 r, column l % 16
 WV_UNROLL
-    for (int h = 0; h < 2; h++) {
+    for (int n = 0; n < CT; n++) {
 WV_UNROLL
-        for (int n = 0; n < CT; n++) {
-WV_UNROLL
-            for (int r = 0; r < 4; r++) {
-                const uint32_t m = m0 + 32 * wave + 16 * h + (lane >> 4) + 4 * r;
-                const uint64_t e = (uint64_t)N * m + 16 * n + (lane & 15);
-                if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[h][n][r], f));
-            }
+        for (int r = 0; r < 4; r++) {
+            const uint32_t m = m0 + 16 * wave + (lane >> 4) + 4 * r;
+            const uint64_t e = (uint64_t)N * m + 16 * n + (lane & 15);
+            if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[n][r], f));
         }
     }
 }
