@@ -246,9 +246,27 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
 // sieve over segment descriptors
 // ==========================================================================
 
-void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d) {
+void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d, uint64_t piece) {
     if (hi <= lo || hi <= 5) return;
-    for (uint64_t L = lo & ~1ull; L < hi; L += kSegSpan) d.push_back(SegDesc{L, lo, hi});
+    piece = std::max<uint64_t>(piece, 1);
+    for (uint64_t L = lo & ~1ull; L < hi; L += kSegSpan) {
+        if (piece >= kSegSpan) {
+            d.push_back(SegDesc{L, lo, hi});
+            continue;
+        }
+        // the segment's integers in pieces: each piece sieves the whole
+        // segment and keeps the primes of its own sub-range
+        const uint64_t a = std::max(L, lo), b = std::min(L + kSegSpan, hi);
+        for (uint64_t x = a; x < b; x += piece) d.push_back(SegDesc{L, x, std::min(b, x + piece)});
+    }
+}
+
+uint64_t window_piece(const wv_ctx *c, uint64_t hi) {
+    // integers holding about kMaxBatchTerms / 2 terms of work at primes near hi
+    const double cost = side_cost(c, c->tb) + side_cost(c, c->te);
+    const double per_prime = std::max(1.0, (double)hi * cost);
+    const double w = kMaxBatchTerms / 2 / per_prime * std::log(std::max<double>((double)hi, 3.0));
+    return (uint64_t)std::min<double>(std::max(w, 4096.0), (double)kSegSpan);
 }
 
 // Prime counts of descs[0..ns) into counts; with keep_bits the prime bitmaps
@@ -716,7 +734,7 @@ int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t 
     uint64_t pmax = 0;
     for (size_t w = 0; w < nwin; w++) {
         first[w] = d.size();
-        window_descs(lo[w], hi[w], d);
+        window_descs(lo[w], hi[w], d, window_piece(c, hi[w]));
         if (hi[w] > lo[w]) pmax = std::max(pmax, hi[w] - 1);
     }
     first[nwin] = d.size();
@@ -764,7 +782,7 @@ int wv_range_stats(wv_ctx *c, uint64_t lo, uint64_t hi, uint32_t bins, uint64_t 
     if (hi > WV_P_MAX) return WV_EDOMAIN;
     WV_TRY(check_device(c));
     std::vector<SegDesc> d;
-    window_descs(lo, hi, d);
+    window_descs(lo, hi, d, window_piece(c, hi));
     std::vector<uint32_t> counts(d.size());
     if (!d.empty()) WV_TRY(sieve_count(c, d.data(), d.size(), false, counts.data()));
     uint64_t total = 0;

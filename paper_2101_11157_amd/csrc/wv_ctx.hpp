@@ -47,7 +47,7 @@ constexpr uint64_t kMinChunks = 1ull << 16;
 constexpr size_t kMaxBatchSegs = 64;             // sieve segments per search batch (4 MiB of bitmaps)
 constexpr uint64_t kMaxBatchPrimes = 1ull << 19; // primes per search batch
 constexpr uint64_t kMaxBatchSlots = 1ull << 27;  // (prime, sum) slots per batch (~10 GB of plan records)
-constexpr double kMaxBatchTerms = 70368744177664.0;   // 2^46 terms per search batch (~20 s)
+constexpr double kMaxBatchTerms = 17592186044416.0;   // 2^44 terms per search batch (~3 s)
 constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
 constexpr int kDefaultVariant = 9;               // block shape 28/36
 
@@ -149,7 +149,11 @@ int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipS
 int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end);
 int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out);
 int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pmax, wv_result *d_out);
-void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d);
+// the segments of [lo, hi) (kSegSpan integers each), every one cut into
+// sub-ranges of at most `piece` integers
+void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d, uint64_t piece = kSegSpan);
+// sub-range width whose primes near hi hold about half a search batch of work
+uint64_t window_piece(const wv_ctx *c, uint64_t hi);
 int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts);
 int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out);
 // out: host results (may be NULL when sink is set), written contiguously in

@@ -22,7 +22,7 @@ constexpr int kScanTile = 1024;                // elements per scan workgroup
 // share one launch (batched search).
 constexpr uint64_t kChunkSetup = 4096;         // set-up work of one chunk, in terms
 constexpr uint64_t kChunkMin = 1ull << 12;
-constexpr uint64_t kChunkMax = 1ull << 22;
+constexpr uint64_t kChunkMax = 1ull << 19;
 constexpr int kTailBuckets = 64;   // length classes of the tail chunks
 
 // Length class of a tail of rem in [1, C) terms; class 0 holds the longest.
