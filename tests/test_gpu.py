@@ -62,6 +62,22 @@ def test_small_window_all_primes(ctx):
     assert st["n_primes"] == 9590 and st["ms_sum"] > 0
 
 
+def test_wide_window_cut_into_sub_ranges(ctx):
+    """A window at 3e10 holding about three sub-ranges of the size the library
+    cuts windows into there (about half a search batch of work each): every
+    prime once, ascending, and 64 sampled results (first, middle and last
+    included) identical to the same primes evaluated as a list."""
+    lo, hi = 3 * 10 ** 10, 3 * 10 ** 10 + 400_000
+    say(f"case: search_range({lo}, {hi}), cut into sub-ranges")
+    res, hits = ctx.search_range(lo, hi)
+    assert list(res["p"]) == oracle.primes(lo, hi)
+    idx = sorted(set([0, len(res) // 2, len(res) - 1] + random.Random(7).sample(range(len(res)), 61)))
+    alone = ctx.eval_primes(np.array([int(p) for p in res["p"][idx]], dtype=np.uint64))
+    assert as_pairs(res[idx]) == as_pairs(alone)
+    assert [int(f) for f in res["flags"][idx]] == [int(f) for f in alone["flags"]]
+    assert list(hits) == [int(r["p"]) for r in res if int(r["flags"])]
+
+
 def test_paper_tables_2_and_3(ctx):
     """Printed symmetric residues of Tables 2 and 3 (43 primes up to 7.8e10)."""
     say("case: Tables 2 and 3")
