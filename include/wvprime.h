@@ -249,8 +249,9 @@ typedef struct {
 int wv_bernoulli_euler_all(wv_ctx *ctx, uint64_t p, uint64_t *b, uint64_t *e);
 
 /* Kernel of the power sums behind wv_bernoulli_euler_all / wv_irregular_pairs:
- * 0 automatic (matrix cores for batches with every p < 2^21, where a partial
- * sum of 1024 products stays an exact f64 integer; vector ALU otherwise),
+ * 0 automatic (matrix cores for batches with every p < 2^24, where partial
+ * sums of up to 1024 products, reduced mod p before they reach 2^53, stay
+ * exact f64 integers; vector ALU otherwise),
  * 1 vector ALU always, 2 matrix cores where exact (same as 0).  Results do not
  * depend on it.  Errors: WV_EINVAL. */
 int wv_set_irregular_path(wv_ctx *ctx, int path);

@@ -345,7 +345,7 @@ class Context:
 
     def set_irregular_path(self, path):
         """Power-sum kernel of the irregular-pair calls: 0 automatic, 1 vector
-        ALU, 2 matrix cores where exact (p < 2^21)."""
+        ALU, 2 matrix cores where exact (p < 2^24)."""
         _check(lib().wv_set_irregular_path(self._h, int(path)), "wv_set_irregular_path")
 
     def bernoulli_euler_all(self, p):

@@ -158,13 +158,15 @@ WV_UNROLL
     }
 }
 
-// The same totals as a dense contraction on the matrix cores, for p < 2^21:
+// The same totals as a dense contraction on the matrix cores, for p < 2^24:
 // with e = N m + j (N = 16 ct exponents per row, ct chosen per task so that
 // the rows fill whole row blocks), s^(t0 + 2e) = A[m][s] B[s][j],
 // A[m][s] = s^(t0 + 2N m), B[s][j] = s^(2j), so V[m][j] = sum_s A[m][s] B[s][j].  Residues below 0.574p
-// make every product an integer below 0.33 p^2 < 2^41 and a 1024-s partial sum
-// an integer below 2^51, exact in the f64 multiply-adds; the accumulators are
-// reduced mod p after every 1024 s and before their atomic additions.  A
+// make every product an integer below 0.33 p^2 (< 2^46.4), so the f64
+// multiply-adds are exact while a partial sum stays below 2^53: the
+// accumulators are reduced mod p after every `period` chunks of 32 s, the
+// most whose products stay below 2^52 (32 chunks = 1024 s for p < 2^21, one
+// chunk near 2^24), and before their atomic additions.  A
 // workgroup takes (task, 128 rows of m, kMmaSb s) with twelve waves in two roles: four producer waves
 // build the A (128 x 32) and transposed B (N x 32) slices of the next 32 s in
 // one LDS buffer while eight consumer waves run v_mfma_f64_16x16x4 on the
@@ -175,8 +177,8 @@ WV_UNROLL
 constexpr int kMmaRows = 128;                // rows of m per workgroup
 constexpr int kMmaKc = 32;                   // s per LDS chunk
 constexpr uint64_t kMmaSb = 1024;            // s per workgroup
-constexpr uint32_t kMmaReduce = 1024 / kMmaKc;   // chunks between reductions of the accumulators
-constexpr uint64_t kIrrMmaMaxP = 1ull << 21;
+constexpr uint32_t kMmaReduceMax = 1024 / kMmaKc;   // chunks between reductions of the accumulators, at most
+constexpr uint64_t kIrrMmaMaxP = 1ull << 24;
 constexpr int kMmaConsumers = 512;           // 8 consumer waves, 16 rows each
 constexpr int kMmaThreads = kMmaConsumers + 256;   // and 4 producer waves
 // LDS row stride (doubles) of A and of the transposed B: a wave's fragment
@@ -218,8 +220,8 @@ WV_UNROLL
 // N = 16 CT exponents per row; CT is compile-time so that each width has its
 // own accumulators and straight-line matrix code.
 template <int CT>
-__device__ __forceinline__ void irr_mma_unit(const IrrTask &T, const Fmod &f, uint32_t rb, uint32_t M, uint64_t sb0,
-                                             uint64_t sb1, double (&As)[2][kMmaRows * kMmaAs],
+__device__ __forceinline__ void irr_mma_unit(const IrrTask &T, const Fmod &f, uint32_t period, uint32_t rb, uint32_t M,
+                                             uint64_t sb0, uint64_t sb1, double (&As)[2][kMmaRows * kMmaAs],
                                              double (&Bs)[2][kMmaRows * kMmaAs], double *__restrict__ V) {
     constexpr uint32_t N = 16 * CT;
     const uint32_t m0 = rb * kMmaRows;
@@ -284,7 +286,7 @@ WV_UNROLL
             if (c + 1 < nchunk) produce(c + 1);
         } else if (live) {
             mma_chunk<CT>(As[c & 1], Bs[c & 1], wave, lane, acc);
-            if (c % kMmaReduce == kMmaReduce - 1) {
+            if (c % period == period - 1) {
 WV_UNROLL
                 for (int n = 0; n < CT; n++)
 WV_UNROLL
@@ -325,15 +327,18 @@ __global__ void __launch_bounds__(kMmaThreads) k_irr_mma(const IrrTask *__restri
     const uint32_t rb = (uint32_t)(u % rbs);
     const uint64_t sb0 = T.lo + (u / rbs) * kMmaSb;
     const uint64_t sb1 = min(T.hi, sb0 + kMmaSb);
+    // chunks whose products (each below 0.33 p^2) add up to at most 2^52
+    const double chunk_bound = 0.33 * f.p * f.p * kMmaKc;
+    const uint32_t period = (uint32_t)fmax(1.0, fmin((double)kMmaReduceMax, floor(4503599627370496.0 / chunk_bound)));
     switch (T.ct) {   // workgroup-uniform
-        case 1: irr_mma_unit<1>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
-        case 2: irr_mma_unit<2>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
-        case 3: irr_mma_unit<3>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
-        case 4: irr_mma_unit<4>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
-        case 5: irr_mma_unit<5>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
-        case 6: irr_mma_unit<6>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
-        case 7: irr_mma_unit<7>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
-        default: irr_mma_unit<8>(T, f, rb, M, sb0, sb1, As, Bs, V); break;
+        case 1: irr_mma_unit<1>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
+        case 2: irr_mma_unit<2>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
+        case 3: irr_mma_unit<3>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
+        case 4: irr_mma_unit<4>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
+        case 5: irr_mma_unit<5>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
+        case 6: irr_mma_unit<6>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
+        case 7: irr_mma_unit<7>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
+        default: irr_mma_unit<8>(T, f, period, rb, M, sb0, sb1, As, Bs, V); break;
     }
 }
 
