@@ -27,13 +27,23 @@ namespace wv {
 
 int ensure(wv_ctx *c, DevBuf &b, size_t bytes) {
     if (b.cap >= bytes && b.ptr) return WV_OK;
+    const size_t old = b.cap;
     if (b.ptr) {
         WV_HIP(hipFree(b.ptr));
         b.ptr = nullptr;
         b.cap = 0;
     }
-    size_t want = std::max(bytes, (size_t)256);
-    WV_HIP(hipMalloc(&b.ptr, want));
+    const size_t need = std::max(bytes, (size_t)256);
+    // a buffer that grows again gets half as much again (at most twice the
+    // request), so that calls of slowly growing sizes do not reallocate each time
+    size_t want = old ? std::max(need, std::min(old + old / 2, 2 * need)) : need;
+    want = (want + 65535) & ~(size_t)65535;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        want = need;
+        WV_HIP(hipMalloc(&b.ptr, want));
+    }
     b.cap = want;
     c->gen++;   // captured graphs hold the old address
     return WV_OK;
