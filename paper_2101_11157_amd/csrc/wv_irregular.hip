@@ -363,11 +363,14 @@ __global__ void __launch_bounds__(256) k_irr_final(const IrrPrime *__restrict__ 
     Fmod f;
     f.p = (double)p;
     f.pinv = 1.0 / f.p;
-    // Bernoulli side: odd exponent t = 2k - 1
+    // Bernoulli side: odd exponent t = 2k - 1; with x = 2^(p-2k),
+    // 4k C_k(2,3,4) = x + 3^(p-2k) - x^2 - 1 =: n and B_{2k} = S 4k / n
     const uint64_t vb = f_canon(V[P.vb + k - 1], f);
-    const uint64_t c = c_k(2, 3, 4, k, f, p);
+    const double x2 = fpow_e(2.0, p - 2 * k, f);
+    const uint64_t c = f_canon(f_reduce(x2 + fpow_e(3.0, p - 2 * k, f) - f_mulmod(x2, x2, f) - 1.0, f), f);
     if (c) {
-        const uint64_t b = f_canon(f_mulmod((double)vb, (double)u_pow(c, p - 2, f), f), f);
+        const double s4k = f_mulmod((double)vb, (double)((4 * k) % p), f);
+        const uint64_t b = f_canon(f_mulmod(s4k, (double)u_pow(c, p - 2, f), f), f);
         if (b_out) b_out[P.res + k - 1] = b;
         if (b == 0) {
             const unsigned long long at = atomicAdd(&counts[1], 1ull);
@@ -380,7 +383,8 @@ __global__ void __launch_bounds__(256) k_irr_final(const IrrPrime *__restrict__ 
     // Euler side: even exponent t = 2k; eqnE1 with k' = (p - 1 - t) / 2
     const uint64_t t = 2 * k;
     const uint64_t kk = (p - 1 - t) / 2;
-    uint64_t e = f_canon(f_mulmod(f_canon(V[P.ve + k - 1], f), (double)u_pow(4, t + 1, f), f), f);
+    const double pow4 = f_mulmod(4.0, fpow_e(16.0, k, f), f);   // 4^(t+1) = 4 16^k
+    uint64_t e = f_canon(f_mulmod(f_canon(V[P.ve + k - 1], f), pow4, f), f);
     if ((kk & 1) && e) e = p - e;
     if (e_out) e_out[P.res + k - 1] = e;
     if (e == 0) {
