@@ -169,8 +169,8 @@ def main():
                          "traffic that scale the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(primes shard across GPUs with no communication; see the design notes)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported (primes are independent: "
+              "split the range by cost, one process per GPU, and gather the results)", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_bytes:

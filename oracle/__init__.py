@@ -22,8 +22,9 @@ The reference answer for a prime p (``residues``):
   for B and Glaisher's eqnE1 (sign read as (-1)^k) for E;
   ``method="table"``: the printed eqnBB30 / eqnEE33, evaluated plainly.
 
-Readings of the paper that this oracle takes are listed in the repository's
-design notes; the one that changes a formula is the sign of eqnE1.
+Where the paper is ambiguous this oracle takes one reading; the one that
+changes a formula is the sign of eqnE1 (read as (-1)^k, which Table 3's
+printed residues confirm).
 """
 import ctypes
 import os
