@@ -261,15 +261,17 @@ int wv_set_irregular_path(wv_ctx *ctx, int path);
  * number of pairs; n_primes (optional): primes examined; n_unresolved
  * (optional): indices whose congruence chain degenerated (not reported as
  * pairs).  Short buffer: WV_ETRUNC with *n_out set, nothing written.
- * Errors: WV_EINVAL, WV_EDOMAIN (hi > WV_IRR_P_MAX), WV_ETRUNC, WV_ENOMEM,
- * WV_EHIP. */
+ * Errors: WV_EINVAL, WV_EDOMAIN (hi > WV_IRR_P_MAX), WV_ETRUNC, WV_ENOMEM
+ * (also when one batch of primes yields more than 2^20 pairs), WV_EHIP. */
 int wv_irregular_pairs(wv_ctx *ctx, uint64_t lo, uint64_t hi, wv_irr_pair *out, size_t cap, size_t *n_out,
                        uint64_t *n_primes, uint64_t *n_unresolved);
 
 /* Batched search over nwin windows [lo[w], hi[w]) (may differ in size and
  * position): all windows are sieved together and all their primes go through
- * one plan and one persistent term-sum launch per batch of about 2^19 primes,
- * with work split by cost (equal-size chunks of the flat term space).  out
+ * one plan and one persistent term-sum launch per batch (at most 2^19 primes,
+ * 2^27 (prime, sum) slots and about 2^44 terms; a wide window at large p is
+ * cut into sub-ranges that fall into several batches), with work split by
+ * cost (equal-size chunks of the flat term space).  out
  * receives the results window by window, ascending p within a window;
  * win_off (nwin + 1 entries, may be NULL) receives each window's first index
  * and the total.  Short buffer: WV_ETRUNC with *n_out set, nothing written.
