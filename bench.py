@@ -326,7 +326,7 @@ def bench_irregular(args, wv):
     wins = [(lo0 + k * W, lo0 + (k + 1) * W) for k in range(nwin)]
     ctx = wv.Context(0)
     ctx.set_irregular_path({"auto": 0, "valu": 1, "mfma": 2}[args.irr_path])
-    attained = mfma_f64_attained()
+    attained = mfma_f64_attained() if args.irr_path != "valu" else None
     for k in range(args.warmup):
         ctx.irregular_pairs(*wins[k])
         print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
