@@ -38,8 +38,9 @@ def _hipcc(srcs, out, verbose):
 
 
 def build(verbose=False):
-    """Compile csrc/wv_kernels.hip into libwvprime.so and the instruction-rate
-    microbenchmark csrc/peak.hip into libwvpeak.so (both gfx950, in-tree)."""
+    """Compile the HIP sources in SRCS into libwvprime.so and the
+    instruction-rate microbenchmarks csrc/peak.hip into libwvpeak.so (both
+    gfx950, in-tree)."""
     _hipcc(SRCS, LIB, verbose)
     _hipcc([PEAK_SRC], PEAK_LIB, verbose)
     return LIB

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 from fractions import Fraction
 
 import pytest
@@ -135,3 +136,25 @@ def test_device_arithmetic_host_build_sanitized(tmp_path):
         pytest.skip("sanitizer runtime unavailable: " + r.stderr[-200:])
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600)
     assert out.returncode == 0, out.stdout + out.stderr
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says why,
+    before touching any device."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--gpus 2 is not supported" in r.stderr and r.stdout == ""
+
+
+def test_peak_library_exports():
+    """The microbenchmark library behind the rooflines loads and exports its
+    entry points (no device call)."""
+    path = os.path.join(ROOT, "paper_2101_11157_amd", "libwvpeak.so")
+    if not os.path.exists(path):
+        wv_build.build()
+    L = ctypes.CDLL(path)
+    for name in ("wv_peak_count", "wv_peak_rates", "wv_peak_mfma_f64"):
+        assert hasattr(L, name), name
+    L.wv_peak_count.restype = ctypes.c_int
+    assert L.wv_peak_count() == 14
