@@ -40,8 +40,11 @@ extern "C" {
 #define WV_EHIP      -6  /* a HIP runtime call failed (context stays valid)     */
 #define WV_EBUSY     -7  /* a served request has not finished yet               */
 
-/* Largest supported prime bound (exclusive): 2^40.  The sums are computed with
- * 64-bit Montgomery arithmetic whose intermediate bounds assume p < 2^40. */
+/* Largest supported prime bound (exclusive): 2^40.  The long sums run in exact
+ * double-precision modular arithmetic (residues held as integer-valued doubles,
+ * products below 2^51 p) and the short ones, the reductions and the final
+ * combination in 64-bit Montgomery arithmetic; the bounds of both assume
+ * p < 2^40. */
 #define WV_P_MAX (1ULL << 40)
 
 /* Result flags. */
@@ -176,10 +179,19 @@ int wv_tune_save(const wv_ctx *ctx, const char *path);
 int wv_tune_load(wv_ctx *ctx, const char *path);
 
 /* Number of primes p with 5 <= p and lo <= p < hi (segmented sieve on the
- * device).  Errors: WV_EINVAL (n NULL, lo > hi), WV_EDOMAIN (hi > WV_P_MAX). */
+ * device).  The paper's searches run over the primes from 5 upwards (Section 3,
+ * Results: 4,118,054,811 primes in [5, 1e11)); which sieve enumerates them is
+ * not part of the method (the paper uses an external one).  Synchronous.
+ * Errors: WV_EINVAL (n NULL, lo > hi), WV_EDOMAIN (hi > WV_P_MAX). */
 int wv_count_primes(wv_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *n);
 
-/* Every prime p with max(lo,5) <= p < hi: sieve, then residues.  out[0..n)
+/* The search of Sections 3 and 5 over one interval (Theorem 1.1 reports its
+ * hits below 1e11): for every prime p with max(lo,5) <= p < hi, B_{p-3} mod p
+ * and E_{p-3} mod p from the configured congruences (Section 3: eqnBB1 ...
+ * eqnBB30; Section 5: eqnEE3 ... eqnEE33; or defined ones), each sum
+ * S(x, y) of eqnDefnS evaluated as c1/c0 by eqnComputeS and eqnCombinePairs,
+ * and the flags of a Wolstenholme (b = 0) or Vandiver (e = 0) prime.
+ * Sieve, then residues.  out[0..n)
  * receives the results in ascending p, where n = *n_out; if cap < n the call
  * writes nothing, sets *n_out = n and returns WV_ETRUNC.  hits (may be NULL
  * when hit_cap == 0) receives up to hit_cap primes whose flags are nonzero,
@@ -279,20 +291,26 @@ int wv_irregular_pairs(wv_ctx *ctx, uint64_t lo, uint64_t hi, wv_irr_pair *out, 
 int wv_search_windows(wv_ctx *ctx, const uint64_t *lo, const uint64_t *hi, size_t nwin,
                       wv_result *out, size_t cap, size_t *n_out, size_t *win_off);
 
-/* Residues for n given primes (host memory), results in input order.  Each
+/* Residues for n given primes (host memory), results in input order: the
+ * same computation as wv_search_range (Sections 3 and 5, eqnDefnS,
+ * eqnComputeS, eqnCombinePairs) for a caller-chosen list.  Each
  * p must satisfy 5 <= p < WV_P_MAX (else WV_EDOMAIN) and be prime (checked on
  * the host by deterministic Miller-Rabin; else WV_ENOTPRIME).  n == 0 is a
  * no-op. */
 int wv_eval_primes(wv_ctx *ctx, const uint64_t *primes, size_t n, wv_result *out);
 
-/* Device-pointer variant: d_primes and d_out are device memory (e.g. torch
- * tensors) of n entries; the work is enqueued on hip_stream (a hipStream_t;
+/* Device-pointer variant of wv_eval_primes (the same residues: Sections 3
+ * and 5, eqnDefnS, eqnComputeS, eqnCombinePairs): d_primes and d_out are
+ * device memory (e.g. torch tensors) of n entries, d_out in the wv_result
+ * layout; the work is enqueued on hip_stream (a hipStream_t;
  * NULL = the legacy default stream) and the call returns without waiting.
  * The batch is padded to a power of two and the whole sequence of kernels is
  * replayed from a captured HIP graph cached per padded size (captured on the
  * first call of each size, which waits for the context's own stream).
  * The primes are not validated: each must be a prime in [5, WV_P_MAX); a
- * value outside that range yields a result with flags = 0xFFFFFFFF.  The
+ * value outside that range yields a result with flags = 0xFFFFFFFF, and so
+ * does every prime of the call if the term sums report an internal error
+ * (a wave stopped before the work ran out; not expected in a correct run).  The
  * caller keeps both buffers alive until the stream has passed this work.
  * Internal buffers of ctx are in use until then: do not issue another call on
  * ctx before synchronising hip_stream.  One batch: the padded size times the
@@ -300,6 +318,29 @@ int wv_eval_primes(wv_ctx *ctx, const uint64_t *primes, size_t n, wv_result *out
  * the printed tables). */
 int wv_eval_primes_async(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
                          wv_result *d_out, void *hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and the same arguments and results as wv_eval_primes_async, but
+ * the call allocates nothing, captures no graph and never synchronises.
+ * Every intermediate buffer lives in one fixed device array of
+ * WV_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * the process ends (looked up by wv_create); ctx contributes only its
+ * congruence tables and settings.  Limits: n <= WV_STATIC_MAX_PRIMES and n
+ * times the sums per prime <= WV_STATIC_MAX_SLOTS (524288: 8322 primes with
+ * the printed tables, 194 with the package's derived ones); larger calls
+ * return WV_EINVAL before enqueueing anything.  All calls on one GPU share
+ * that GPU's array, which keeps the last call's contents: calls whose work
+ * overlaps on one GPU (other streams, other contexts, other host threads)
+ * race; order them on one stream or synchronise between them.  The words that
+ * must start at zero are cleared by kernels of the call itself.
+ * Errors: WV_EINVAL, WV_EHIP. */
+#define WV_STATIC_MAX_PRIMES 65536ULL
+#define WV_STATIC_MAX_SLOTS (1ULL << 19)
+#define WV_STATIC_MAX_CHUNKS (1ULL << 20)
+#define WV_STATIC_SCRATCH_BYTES (60ULL << 20)
+int wv_eval_primes_static(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
+                          wv_result *d_out, void *hip_stream);
 
 /* Testing aid: the individual sums S_j = sum_{x_j p < s < y_j p} s^-deg mod p
  * (Section 2, eqnDefnS; deg 3 on the Bernoulli side, 2 on the Euler side) of
@@ -326,7 +367,7 @@ int wv_eval_sums(wv_ctx *ctx, const uint64_t *primes, size_t n, uint64_t *out_b,
 typedef struct wv_server wv_server;
 
 typedef struct {
-    uint64_t step_terms;   /* terms of work per step (0: 2^36, ~50 ms at p ~ 1e11) */
+    uint64_t step_terms;   /* terms of work per step (0: 2^36, ~12 ms at p ~ 1e11) */
     uint32_t max_primes;   /* prime slots of the device pool (0: 65536) */
     uint32_t reserved;
 } wv_server_config;
@@ -334,26 +375,35 @@ typedef struct {
 typedef struct {
     uint64_t submitted, completed, pending, active;
     uint64_t primes_done, terms_done, steps, readmits;
-    double p50_ms, p99_ms, mean_ms, max_ms; /* submit-to-completion latency, completed requests */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* submit-to-completion latency, requests completed without error */
     double busy_s;                          /* device time of the steps */
     double wall_s;                          /* since the first submit */
+    uint64_t failed;                        /* requests that ended with an error (counted in completed) */
 } wv_server_stats;
 
 int wv_server_create(wv_ctx *ctx, const wv_server_config *cfg, wv_server **out);
 int wv_server_destroy(wv_server *srv);
-/* Every prime of [lo, hi) (at most 2^26 integers wide). */
+/* Every prime of [lo, hi) (at most 2^26 integers wide).  The primes are counted
+ * on the device at submission: a range holding more primes than the pool
+ * (max_primes) is refused with WV_EINVAL and nothing is queued. */
 int wv_server_submit_range(wv_server *srv, uint64_t lo, uint64_t hi, uint64_t *id);
 /* A list of primes (validated like wv_eval_primes; at most max_primes). */
 int wv_server_submit_primes(wv_server *srv, const uint64_t *primes, size_t n, uint64_t *id);
 /* Admit what fits, then run one step of work; returns after the step's GPU
  * work.  Admission takes requests pending for 2 s or more in arrival order,
- * then the smallest first (a list by its length, a range by its expected
- * number of primes), and plans at most 2^22 sums per step; a request that
- * does not fit in the pool waits without blocking others.  A failed step (HIP error) restarts every active request from its
- * plan, so no partial state of the failed step survives. */
+ * then the smallest first (by number of primes), and plans at most 2^22 sums
+ * per step; a request that does not fit in the pool waits without blocking
+ * others.  A request whose admission fails ends with that error (see
+ * wv_server_result) and frees its pool slots.  A failed step (HIP error, or
+ * term sums that did not cover every chunk) returns its error after
+ * restarting every active request from its plan, so no partial state of the
+ * failed step survives; after 3 consecutive failed steps the active requests
+ * end with the error instead.  The server stays usable either way. */
 int wv_server_step(wv_server *srv, uint32_t *n_active, uint32_t *n_pending);
 /* Results of a finished request (then forgotten); WV_EBUSY while it runs,
- * WV_ETRUNC (with *n_out) if cap is short.  latency_ms: submit to completion. */
+ * WV_ETRUNC (with *n_out) if cap is short.  A request that ended with an error
+ * returns that error once (with *n_out = 0) and is forgotten.
+ * latency_ms: submit to completion. */
 int wv_server_result(wv_server *srv, uint64_t id, wv_result *out, size_t cap, size_t *n_out,
                      double *latency_ms);
 int wv_server_get_stats(const wv_server *srv, wv_server_stats *out);

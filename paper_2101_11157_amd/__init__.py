@@ -86,6 +86,7 @@ class WvServerStats(ctypes.Structure):
         ("steps", ctypes.c_uint64), ("readmits", ctypes.c_uint64),
         ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
         ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("wall_s", ctypes.c_double),
+        ("failed", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -132,6 +133,7 @@ def lib():
                                                ctypes.POINTER(SZ)]),
             "wv_eval_primes": (ctypes.c_int, [VP, P_U64, SZ, VP]),
             "wv_eval_primes_async": (ctypes.c_int, [VP, VP, SZ, VP, VP]),
+            "wv_eval_primes_static": (ctypes.c_int, [VP, VP, SZ, VP, VP]),
             "wv_eval_sums": (ctypes.c_int, [VP, P_U64, SZ, P_U64, P_U64]),
             "wv_search_windows": (ctypes.c_int, [VP, P_U64, P_U64, SZ, VP, SZ, ctypes.POINTER(SZ),
                                                  ctypes.POINTER(SZ)]),
@@ -422,6 +424,12 @@ class Context:
         st = lib().wv_eval_primes_async(self._h, VP(d_primes_ptr), int(n), VP(d_out_ptr),
                                         VP(stream_ptr) if stream_ptr else None)
         _check(st, "wv_eval_primes_async")
+
+    def eval_primes_static(self, d_primes_ptr, n, d_out_ptr, stream_ptr=0):
+        """As eval_primes_async, allocating nothing (the library's fixed scratch array)."""
+        st = lib().wv_eval_primes_static(self._h, VP(d_primes_ptr), int(n), VP(d_out_ptr),
+                                         VP(stream_ptr) if stream_ptr else None)
+        _check(st, "wv_eval_primes_static")
 
     def stats(self):
         s = WvStats()

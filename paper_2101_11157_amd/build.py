@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRCS = [os.path.join(HERE, "csrc", f) for f in ("wv_kernels.hip", "wv_capi.hip", "wv_tune.hip", "wv_server.hip",
-                                                 "wv_irregular.hip")]
+                                                 "wv_irregular.hip", "wv_static.hip")]
 PEAK_SRC = os.path.join(HERE, "csrc", "peak.hip")
 PEAK_LIB = os.path.join(HERE, "libwvpeak.so")
 DEPS = [os.path.join(HERE, "csrc", f) for f in ("mont.hpp", "sum_core.hpp", "wv_tables.hpp", "wv_internal.hpp",

@@ -147,44 +147,54 @@ int prepare(wv_ctx *c, const BatchShape &sh) {
     return WV_OK;
 }
 
-// scal: [0] total terms, [1..3] chunk layout {chunk size, full chunks, tails},
-//       [4] total chunks, [5] chunk counter, [6] Bernoulli-side terms
-constexpr int kScalTerms = 0, kScalLayout = 1, kScalChunks = 4, kScalCounter = 5, kScalTermsB = 6;
+BatchBufs ctx_bufs(wv_ctx *c) {
+    BatchBufs b;
+    b.pr = as<PrimeRec>(c->pr);
+    b.segs = as<SegRec>(c->segs);
+    b.terms = as<uint64_t>(c->terms);
+    b.cnt = as<uint64_t>(c->cnt);
+    b.off = as<uint64_t>(c->off);
+    b.tiles = as<uint64_t>(c->tiles);
+    b.scal = as<uint64_t>(c->scal);
+    b.partials = as<Pair>(c->partials);
+    b.seg_pairs = as<Pair>(c->seg_pairs);
+    b.coefs = as<uint64_t>(c->coefs);
+    b.lhsmod = as<uint64_t>(c->lhsmod);
+    b.tails = as<uint32_t>(c->tails);
+    b.tail_hist = as<unsigned long long>(c->tail_hist);
+    return b;
+}
 
-int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st) {
-    uint64_t *scal = as<uint64_t>(c->scal);
-    uint64_t *toff = as<uint64_t>(c->off);   // prefix of terms, then of full chunks
+int enqueue_plan(wv_ctx *c, const BatchBufs &b, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st) {
+    uint64_t *scal = b.scal;
+    uint64_t *toff = b.off;   // prefix of terms, then of full chunks
     const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
     WV_HIP(launch_set_u64(st, scal, 8, 0));
     WV_HIP(launch_plan(st, d_primes, sh.n, sh.tb, sh.te, table_fallback(c, sh.tb), table_fallback(c, sh.te), sh.nB,
-                       sh.nE, table_store(c), as<PrimeRec>(c->pr), as<SegRec>(c->segs), as<uint64_t>(c->terms),
-                       as<uint64_t>(c->coefs), as<uint64_t>(c->lhsmod), 0));
-    WV_HIP(launch_scan(st, as<uint64_t>(c->terms), sh.nseg, toff, as<uint64_t>(c->tiles)));
+                       sh.nE, table_store(c), b.pr, b.segs, b.terms, b.coefs, b.lhsmod, 0));
+    WV_HIP(launch_scan(st, b.terms, sh.nseg, toff, b.tiles));
     WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sum_lanes(c), sh.cap, scal + kScalLayout));
     WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + kScalTerms, 1));
     WV_HIP(launch_copy_u64(st, toff + (uint64_t)sh.n * sh.nB, scal + kScalTermsB, 1));
-    WV_HIP(launch_chunk_layout(st, as<uint64_t>(c->terms), sh.nseg, scal + kScalLayout, as<uint64_t>(c->cnt), toff,
-                               as<uint64_t>(c->tiles), as<unsigned long long>(c->tail_hist), as<uint32_t>(c->tails),
+    WV_HIP(launch_chunk_layout(st, b.terms, sh.nseg, scal + kScalLayout, b.cnt, toff, b.tiles, b.tail_hist, b.tails,
                                scal + kScalChunks));
     return WV_OK;
 }
 
-int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end) {
-    uint64_t *scal = as<uint64_t>(c->scal);
+int enqueue_sum(wv_ctx *c, const BatchBufs &b, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end) {
+    uint64_t *scal = b.scal;
     const int v = c->variant;
     WV_HIP(launch_set_u64(st, scal + kScalCounter, 1, begin));
-    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(c->segs), as<uint64_t>(c->off),
-                      (uint32_t)sh.nseg, as<PrimeRec>(c->pr), scal + kScalLayout, as<uint32_t>(c->tails),
-                      as<Pair>(c->partials), as<Pair>(c->seg_pairs), (unsigned long long *)(scal + kScalCounter),
-                      end));
+    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], b.segs, b.off, (uint32_t)sh.nseg, b.pr, scal + kScalLayout,
+                      b.tails, b.partials, b.seg_pairs, (unsigned long long *)(scal + kScalCounter), end,
+                      (unsigned long long *)(scal + kScalErr)));
     return WV_OK;
 }
 
-int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out) {
-    WV_HIP(launch_reduce(st, as<SegRec>(c->segs), as<uint64_t>(c->off), (uint32_t)sh.nseg, as<PrimeRec>(c->pr),
-                         as<Pair>(c->partials), as<uint64_t>(c->scal) + kScalLayout, as<Pair>(c->seg_pairs)));
-    WV_HIP(launch_finalize(st, table_store(c), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), as<uint64_t>(c->coefs),
-                           as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out));
+int enqueue_finish(wv_ctx *c, const BatchBufs &b, const BatchShape &sh, hipStream_t st, wv_result *d_out) {
+    WV_HIP(launch_reduce(st, b.segs, b.off, (uint32_t)sh.nseg, b.pr, b.partials, b.scal + kScalLayout, b.seg_pairs));
+    WV_HIP(launch_finalize(st, table_store(c), b.pr, b.seg_pairs, b.coefs, b.lhsmod, sh.n, sh.nB, sh.nE, d_out,
+                           (const unsigned long long *)(b.scal + kScalErr)));
     return WV_OK;
 }
 
@@ -198,12 +208,13 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
     BatchShape sh;
     WV_TRY(batch_shape(c, n, pmax, &sh));
     WV_TRY(prepare(c, sh));
+    const BatchBufs bufs = ctx_bufs(c);
     WV_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
-    WV_TRY(enqueue_plan(c, d_primes, sh, st));
+    WV_TRY(enqueue_plan(c, bufs, d_primes, sh, st));
     WV_HIP(hipEventRecord(c->ev[EV_PLAN], st));
     double ms_sum = 0.0;
     if (!c->progress) {
-        WV_TRY(enqueue_sum(c, sh, st, 0, UINT64_MAX));
+        WV_TRY(enqueue_sum(c, bufs, sh, st, 0, UINT64_MAX));
         WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
         WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
         ms_sum = elapsed(c->ev[EV_PLAN], c->ev[EV_SUM]);
@@ -216,7 +227,7 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
         for (uint64_t b = 0; b < total; b += per) {
             const uint64_t e = b + per >= total ? UINT64_MAX : b + per;   // ranges stay 64-aligned
             WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
-            WV_TRY(enqueue_sum(c, sh, st, b, e));
+            WV_TRY(enqueue_sum(c, bufs, sh, st, b, e));
             WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
             WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
             ms_sum += elapsed(c->ev[EV_SUM0], c->ev[EV_SUM]);
@@ -227,13 +238,15 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
                          as<Pair>(c->partials), as<uint64_t>(c->scal) + kScalLayout, as<Pair>(c->seg_pairs)));
     WV_HIP(hipEventRecord(c->ev[EV_RED], st));
     WV_HIP(launch_finalize(st, table_store(c), as<PrimeRec>(c->pr), as<Pair>(c->seg_pairs), as<uint64_t>(c->coefs),
-                           as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out));
+                           as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out,
+                           (const unsigned long long *)(as<uint64_t>(c->scal) + kScalErr)));
     WV_HIP(hipEventRecord(c->ev[EV_FINAL], st));
     WV_HIP(hipEventSynchronize(c->ev[EV_FINAL]));
     // statistics
     uint64_t host[8];
     WV_HIP(hipMemcpyAsync(host, c->scal.ptr, sizeof(host), hipMemcpyDeviceToHost, st));
     WV_HIP(hipStreamSynchronize(st));
+    if (host[kScalErr]) return WV_EHIP;   // the term sums did not cover every chunk
     wv_stats &s = c->stats;
     s.ms_plan += elapsed(c->ev[EV_PLAN0], c->ev[EV_PLAN]);
     s.ms_sum += ms_sum;
@@ -610,6 +623,12 @@ int wv_create(int hip_device, wv_ctx **out) {
         if (hipMemcpyAsync(&nb, c->scal.ptr, sizeof(nb), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess) { rc = WV_EHIP; break; }
         c->n_base = nb;
+        // the allocation-free entry point's scratch array on this device; a
+        // failed lookup leaves that one entry point returning WV_EHIP
+        if (static_scratch_setup(hip_device, &c->scratch) != WV_OK) {
+            (void)hipGetLastError();
+            c->scratch = nullptr;
+        }
     } while (0);
     if (rc != WV_OK) {
         wv_destroy(c);
@@ -922,9 +941,10 @@ int wv_eval_primes_async(wv_ctx *c, const uint64_t *d_primes, size_t n, wv_resul
         WV_HIP(hipStreamSynchronize(c->stream));
         hipGraph_t graph = nullptr;
         WV_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_plan(c, as<uint64_t>(c->pad_primes), sh, c->stream);
-        if (rc == WV_OK) rc = enqueue_sum(c, sh, c->stream, 0, UINT64_MAX);
-        if (rc == WV_OK) rc = enqueue_finish(c, sh, c->stream, as<wv_result>(c->results));
+        const BatchBufs bufs = ctx_bufs(c);
+        int rc = enqueue_plan(c, bufs, as<uint64_t>(c->pad_primes), sh, c->stream);
+        if (rc == WV_OK) rc = enqueue_sum(c, bufs, sh, c->stream, 0, UINT64_MAX);
+        if (rc == WV_OK) rc = enqueue_finish(c, bufs, sh, c->stream, as<wv_result>(c->results));
         hipError_t e = hipStreamEndCapture(c->stream, &graph);
         if (rc != WV_OK) {
             if (graph) (void)hipGraphDestroy(graph);

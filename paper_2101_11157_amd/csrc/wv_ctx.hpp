@@ -51,6 +51,29 @@ constexpr double kMaxBatchTerms = 17592186044416.0;   // 2^44 terms per search b
 constexpr size_t kSieveLaunch = 1 << 16;         // segments per counting launch
 constexpr int kDefaultVariant = 9;               // block shape 28/36
 
+// scal words of a batch: [0] total terms, [1..3] chunk layout {chunk size,
+// full chunks, tails}, [4] total chunks, [5] chunk counter, [6]
+// Bernoulli-side terms, [7] term-sum error word (nonzero: a wave hit its
+// iteration bound)
+constexpr int kScalTerms = 0, kScalLayout = 1, kScalChunks = 4, kScalCounter = 5, kScalTermsB = 6, kScalErr = 7;
+
+// Device buffers of one batch of primes (plan -> sums -> reduce -> finalize):
+// the context's growable buffers, or a carve-up of a fixed scratch area.
+struct BatchBufs {
+    PrimeRec *pr;               // n
+    SegRec *segs;               // nseg
+    uint64_t *terms, *cnt;      // nseg
+    uint64_t *off;              // nseg + 1
+    uint64_t *tiles;            // ceil(nseg / kScanTile) + 1
+    uint64_t *scal;             // 8
+    Pair *partials;             // cap
+    Pair *seg_pairs;            // nseg
+    uint64_t *coefs;            // nseg
+    uint64_t *lhsmod;           // 2 n
+    uint32_t *tails;            // nseg
+    unsigned long long *tail_hist;   // 2 kTailBuckets
+};
+
 struct BatchShape {
     int tb, te;          // tables of the batch (a defined table's fallback when no prime reaches its min_p)
     uint32_t n;          // primes
@@ -114,6 +137,7 @@ struct wv_ctx {
     int irr_path = 0;                             // 0 automatic, 1 vector ALU, 2 matrix cores
     std::vector<wv::GraphEntry> graphs;
     std::vector<wv::TuneEntry> tune;
+    void *scratch = nullptr;                      // this device's fixed scratch array (wv_eval_primes_static)
 };
 
 namespace wv {
@@ -145,9 +169,14 @@ int check_device(wv_ctx *c);
 // pmax: an upper bound on the batch's primes (sizes the partial-pair buffer)
 int batch_shape(const wv_ctx *c, uint32_t n, uint64_t pmax, BatchShape *sh);
 int prepare(wv_ctx *c, const BatchShape &sh);
-int enqueue_plan(wv_ctx *c, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st);
-int enqueue_sum(wv_ctx *c, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end);
-int enqueue_finish(wv_ctx *c, const BatchShape &sh, hipStream_t st, wv_result *d_out);
+// the context's batch buffers (after prepare)
+BatchBufs ctx_bufs(wv_ctx *c);
+// The three stages of a batch, enqueued on st with buffers b (sized for sh);
+// nothing is allocated, every word that must start at zero is cleared by a
+// kernel, so the sequence can be captured in a graph.
+int enqueue_plan(wv_ctx *c, const BatchBufs &b, const uint64_t *d_primes, const BatchShape &sh, hipStream_t st);
+int enqueue_sum(wv_ctx *c, const BatchBufs &b, const BatchShape &sh, hipStream_t st, uint64_t begin, uint64_t end);
+int enqueue_finish(wv_ctx *c, const BatchBufs &b, const BatchShape &sh, hipStream_t st, wv_result *d_out);
 int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pmax, wv_result *d_out);
 // the segments of [lo, hi) (kSegSpan integers each), every one cut into
 // sub-ranges of at most `piece` integers
@@ -162,5 +191,8 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
 int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts,
                  wv_result *out, StatsSink *sink = nullptr, const uint64_t *dest = nullptr);
 void pick_tuned(wv_ctx *c, uint64_t pmax);
+// device address of the fixed scratch array on `device` (current), looked up
+// once per device (wv_static.hip)
+int static_scratch_setup(int device, void **addr);
 
 }  // namespace wv

@@ -120,19 +120,24 @@ hipError_t launch_set_u64(hipStream_t st, uint64_t *dst, int n, uint64_t value);
 hipError_t launch_copy_u64(hipStream_t st, const uint64_t *src, uint64_t *dst, int n);
 // Persistent term sums over the chunks [begin, min(end, total)) of a chunk
 // layout; the counter at *counter must hold `begin` (a multiple of 64).  Full
-// chunks leave pairs in partials, tails in seg_pairs[sum].
+// chunks leave pairs in partials, tails in seg_pairs[sum].  *err becomes
+// nonzero if a wave stopped at its iteration bound before the chunks ran out
+// (never in a correct run; the caller reports it as a failure).
 int num_sum_variants();
 int sum_variant_kb(int v);
 int sum_variant_ke(int v);
 hipError_t sum_variant_occupancy(int v, int *blocks_per_cu);
 hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, const uint64_t *off, uint32_t nseg,
                       const PrimeRec *pr, const uint64_t *layout, const uint32_t *tails, Pair *partials,
-                      Pair *seg_pairs, unsigned long long *counter, uint64_t end);
+                      Pair *seg_pairs, unsigned long long *counter, uint64_t end, unsigned long long *err);
 // seg_pairs[j] <- the pairs of sum j's full chunks joined with its tail's
 hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
                          const Pair *partials, const uint64_t *layout, Pair *seg_pairs);
+// err (may be null): the term-sum error word; when it is nonzero every result
+// of the batch is marked invalid (flags = 0xFFFFFFFF)
 hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *sp, const uint64_t *coefs,
-                           const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out);
+                           const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out,
+                           const unsigned long long *err);
 hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec *pr, const Pair *sp, uint64_t nseg,
                              uint64_t *out);
 // acc[target[t]] <- acc[target[t]] (x) tp[t] (eqnCombinePairs), t < ntask

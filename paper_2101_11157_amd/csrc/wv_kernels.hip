@@ -531,12 +531,14 @@ __device__ __forceinline__ void chunk_pair(uint64_t s0, uint64_t cnt, const Mont
 // all full chunks of one sum stores their butterfly product at partials[first
 // chunk]; otherwise each full chunk stores its pair at partials[chunk] and
 // each tail at seg_pairs[sum].  KB / KE: terms per block on the Bernoulli
-// (s^3) and Euler (s^2) sides.
+// (s^3) and Euler (s^2) sides.  A wave that leaves through its iteration bound
+// instead of finding the chunks exhausted sets *err (chunks may be missing).
 template <int KB, int KE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_sum(
     const SegRec *__restrict__ segs, const uint64_t *__restrict__ off, uint32_t nseg, const PrimeRec *__restrict__ pr,
     const uint64_t *__restrict__ layout, const uint32_t *__restrict__ tails, Pair *__restrict__ partials,
-    Pair *__restrict__ seg_pairs, unsigned long long *__restrict__ counter, uint64_t end) {
+    Pair *__restrict__ seg_pairs, unsigned long long *__restrict__ counter, uint64_t end,
+    unsigned long long *__restrict__ err) {
     // chunks [counter start, min(end, total)); end is a multiple of 64 or past the total
     const uint64_t C = layout[0];
     const uint64_t F = layout[1];
@@ -544,11 +546,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const int lane = threadIdx.x & 63;
     // A wave can take at most total/64 + 1 batches; the bound is a second exit.
     const uint64_t max_iter = total / 64 + 2;
+    bool drained = false;
     for (uint64_t iter = 0; iter < max_iter; iter++) {
         uint64_t got = 0;
         if (lane == 0) got = atomicAdd(counter, 64ull);
         const uint64_t base = readfirst_u64(got);   // whole wave active: lane 0 is first
-        if (base >= total) break;
+        if (base >= total) {
+            drained = true;
+            break;
+        }
         const uint64_t chunk = base + lane;
         const bool active = chunk < total;
         uint32_t seg = 0xffffffffu;
@@ -601,10 +607,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             else seg_pairs[seg] = Pair{c0, c1};
         }
     }
+    if (!drained && lane == 0) atomicOr(err, 1ull);
 }
 
 typedef void (*SumKernel)(const SegRec *, const uint64_t *, uint32_t, const PrimeRec *, const uint64_t *,
-                          const uint32_t *, Pair *, Pair *, unsigned long long *, uint64_t);
+                          const uint32_t *, Pair *, Pair *, unsigned long long *, uint64_t, unsigned long long *);
 
 struct SumVariant {
     int kb, ke;
@@ -724,16 +731,18 @@ __global__ void __launch_bounds__(256) k_sum_values(const SegRec *__restrict__ s
     out[j] = P.ok ? red1(mmul(q.c1, inv, m), P.p) : 0;
 }
 
+// A prime that the plan rejected, or every prime of a batch whose term sums
+// reported an error (*err != 0; err may be null), gets flags = 0xFFFFFFFF.
 __global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec *__restrict__ pr,
                                                   const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
                                                   const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
-                                                  wv_result *__restrict__ out) {
+                                                  wv_result *__restrict__ out, const unsigned long long *__restrict__ err) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const PrimeRec P = pr[i];
     wv_result r;
     r.reserved = 0;
-    if (!P.ok) {
+    if (!P.ok || (err && *err)) {
         r.p = 0;
         r.b = 0;
         r.e = 0;
@@ -845,9 +854,9 @@ hipError_t sum_variant_occupancy(int v, int *blocks_per_cu) {
 
 hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, const uint64_t *off, uint32_t nseg,
                       const PrimeRec *pr, const uint64_t *layout, const uint32_t *tails, Pair *partials,
-                      Pair *seg_pairs, unsigned long long *counter, uint64_t end) {
+                      Pair *seg_pairs, unsigned long long *counter, uint64_t end, unsigned long long *err) {
     hipLaunchKernelGGL(kSumVariants[v].fn, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, layout, tails,
-                       partials, seg_pairs, counter, end);
+                       partials, seg_pairs, counter, end, err);
     return hipGetLastError();
 }
 
@@ -860,9 +869,10 @@ hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off
 }
 
 hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *sp, const uint64_t *coefs,
-                           const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out) {
+                           const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out,
+                           const unsigned long long *err) {
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, ts, pr, sp, coefs, lhsmod, n, nB, nE,
-                       out);
+                       out, err);
     return hipGetLastError();
 }
 

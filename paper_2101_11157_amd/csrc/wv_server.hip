@@ -47,7 +47,9 @@ struct Request {
     std::vector<uint64_t> primes;
     double t_submit = 0, t_admit = 0, t_done = 0;
     int state = REQ_PENDING;
-    uint32_t n = 0;            // primes
+    int status = WV_OK;        // WV_OK, or the error that ended the request
+    uint64_t n_primes = 0;     // primes of a range (counted at submission) or list length
+    uint32_t n = 0;            // primes in the pool
     uint32_t base = 0;         // first pool slot
     std::vector<uint64_t> seg_lo, seg_len, cursor;
     size_t first_open = 0;     // first sum with work left
@@ -69,7 +71,8 @@ struct wv_server {
     std::vector<Request *> active;
     std::map<uint64_t, Request *> all;
     uint64_t next_id = 1;
-    uint64_t submitted = 0, completed = 0, primes_done = 0, terms_done = 0, steps = 0, readmits = 0;
+    uint64_t submitted = 0, completed = 0, failed = 0, primes_done = 0, terms_done = 0, steps = 0, readmits = 0;
+    int fail_streak = 0;       // consecutive failed steps
     double t_first = 0, busy_s = 0;
     std::vector<double> lat_ms;
     int fault_after = -1;      // host-forced step failure (tests)
@@ -110,7 +113,7 @@ int finish_request(wv_server *s, Request *r) {
                                as<Pair>(s->acc) + (size_t)r->base * s->NS,
                                as<uint64_t>(s->coefs) + (size_t)r->base * s->NS,
                                as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->n, s->nB, s->nE,
-                               as<wv_result>(s->res)));
+                               as<wv_result>(s->res), nullptr));
         r->results.resize(r->n);
         WV_HIP(hipMemcpyAsync(r->results.data(), s->res.ptr, r->n * sizeof(wv_result), hipMemcpyDeviceToHost,
                               c->stream));
@@ -125,51 +128,28 @@ int finish_request(wv_server *s, Request *r) {
     return WV_OK;
 }
 
-// Plans a pending request into the pool.  Returns WV_OK with *admitted false
-// when there is no room yet.
-int admit(wv_server *s, Request *r, bool *admitted) {
+// Ends a request with an error: its pool slots (if any) are freed, it keeps no
+// results, and wv_server_result reports `status`.  Failed requests do not
+// enter the latency statistics.
+void fail_request(wv_server *s, Request *r, int status) {
+    pool_free(s, r->base, r->n);
+    r->n = 0;
+    r->results.clear();
+    r->status = status;
+    r->state = REQ_DONE;
+    r->t_done = now_s();
+    s->completed++;
+    s->failed++;
+}
+
+// Plans the n primes at d_primes into the pool slots [r->base, r->base + n)
+// and reads the per-sum records back.  The caller frees the slots on error.
+int plan_request(wv_server *s, Request *r, const uint64_t *d_primes, uint32_t n) {
     wv_ctx *c = s->c;
-    *admitted = false;
-    const uint64_t *d_primes = nullptr;
-    uint64_t n = 0;
-    if (r->is_range) {
-        std::vector<SegDesc> d;
-        window_descs(r->lo, r->hi, d);
-        std::vector<uint32_t> counts(d.size());
-        // intervals of a request are sieved in one batch of segments
-        if (d.size() > kMaxBatchSegs) return WV_EINVAL;
-        if (!d.empty()) WV_TRY(sieve_count(c, d.data(), d.size(), true, counts.data()));
-        for (uint32_t k : counts) n += k;
-        if (n > s->pool) return WV_ENOMEM;
-        uint32_t base = 0;
-        if (n > 0 && !pool_alloc(s, (uint32_t)n, &base)) return WV_OK;
-        if (n > 0) {
-            uint64_t got = 0;
-            WV_TRY(compact(c, d.data(), d.size(), counts.data(), &got));
-            d_primes = as<uint64_t>(c->primes);
-        }
-        r->base = base;
-    } else {
-        n = r->primes.size();
-        if (n > s->pool) return WV_ENOMEM;
-        uint32_t base = 0;
-        if (n > 0 && !pool_alloc(s, (uint32_t)n, &base)) return WV_OK;
-        if (n > 0) {
-            WV_TRY(ensure(c, s->tmp, n * sizeof(uint64_t)));
-            WV_HIP(hipMemcpyAsync(s->tmp.ptr, r->primes.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                  c->stream));
-            d_primes = as<uint64_t>(s->tmp);
-        }
-        r->base = base;
-    }
-    r->n = (uint32_t)n;
-    r->t_admit = now_s();
-    *admitted = true;
-    if (n == 0) return finish_request(s, r);
     const size_t first = (size_t)r->base * s->NS, nseg = (size_t)n * s->NS;
-    WV_HIP(launch_plan(c->stream, d_primes, (uint32_t)n, s->tb, s->te, table_fallback(c, s->tb),
-                       table_fallback(c, s->te), s->nB, s->nE, table_store(c), as<PrimeRec>(s->pr) + r->base,
-                       as<SegRec>(s->segs) + first, as<uint64_t>(s->terms) + first, as<uint64_t>(s->coefs) + first,
+    WV_HIP(launch_plan(c->stream, d_primes, n, s->tb, s->te, table_fallback(c, s->tb), table_fallback(c, s->te),
+                       s->nB, s->nE, table_store(c), as<PrimeRec>(s->pr) + r->base, as<SegRec>(s->segs) + first,
+                       as<uint64_t>(s->terms) + first, as<uint64_t>(s->coefs) + first,
                        as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->base));
     WV_HIP(launch_fill_pairs(c->stream, as<Pair>(s->acc) + first, nseg, 1, 0));
     std::vector<SegRec> recs(nseg);
@@ -186,12 +166,51 @@ int admit(wv_server *s, Request *r, bool *admitted) {
         r->remaining += recs[k].len;
     }
     r->first_open = 0;
+    return WV_OK;
+}
+
+// Plans a pending request into the pool.  Returns WV_OK with *admitted false
+// when there is no room yet; an error return leaves no pool slot taken.
+int admit(wv_server *s, Request *r, bool *admitted) {
+    wv_ctx *c = s->c;
+    *admitted = false;
+    // submission checked that the request fits in an empty pool
+    const uint64_t n = r->n_primes;
+    if (n > s->pool) return WV_EINVAL;
+    uint32_t base = 0;
+    if (n > 0 && !pool_alloc(s, (uint32_t)n, &base)) return WV_OK;
+    r->base = base;
+    r->n = (uint32_t)n;
+    int rc = WV_OK;
+    const uint64_t *d_primes = nullptr;
+    if (n > 0 && r->is_range) {
+        std::vector<SegDesc> d;
+        window_descs(r->lo, r->hi, d);
+        std::vector<uint32_t> counts(d.size());
+        uint64_t got = 0;
+        rc = sieve_count(c, d.data(), d.size(), true, counts.data());
+        if (rc == WV_OK) rc = compact(c, d.data(), d.size(), counts.data(), &got);
+        if (rc == WV_OK && got != n) rc = WV_EHIP;   // the sieve is deterministic
+        d_primes = as<uint64_t>(c->primes);
+    } else if (n > 0) {
+        rc = ensure(c, s->tmp, n * sizeof(uint64_t));
+        if (rc == WV_OK && hipMemcpyAsync(s->tmp.ptr, r->primes.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                          c->stream) != hipSuccess)
+            rc = WV_EHIP;
+        d_primes = as<uint64_t>(s->tmp);
+    }
+    if (rc == WV_OK && n > 0) rc = plan_request(s, r, d_primes, (uint32_t)n);
+    if (rc != WV_OK) {
+        (void)hipGetLastError();
+        pool_free(s, r->base, r->n);
+        r->n = 0;
+        return rc;
+    }
+    r->t_admit = now_s();
+    *admitted = true;
+    if (n == 0 || r->remaining == 0) return finish_request(s, r);
     r->state = REQ_ACTIVE;
     s->active.push_back(r);
-    if (r->remaining == 0) {
-        s->active.pop_back();
-        return finish_request(s, r);
-    }
     return WV_OK;
 }
 
@@ -293,24 +312,30 @@ int run_step(wv_server *s) {
     if (!tails.empty())
         WV_HIP(hipMemcpyAsync(s->tails.ptr, tails.data(), tails.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                               st));
-    const uint64_t layout[4] = {C, chunks, tails.size(), 0};   // chunk layout, then the counter
+    // chunk layout, the chunk counter, the term-sum error word
+    const uint64_t layout[5] = {C, chunks, tails.size(), 0, 0};
     uint64_t *scal = as<uint64_t>(s->scal);
     WV_HIP(hipMemcpyAsync(scal, layout, sizeof(layout), hipMemcpyHostToDevice, st));
     WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
     const int v = c->variant;
     WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt,
                       as<PrimeRec>(s->pr), scal, as<uint32_t>(s->tails), as<Pair>(s->partials),
-                      as<Pair>(s->tpairs), (unsigned long long *)(scal + 3), UINT64_MAX));
+                      as<Pair>(s->tpairs), (unsigned long long *)(scal + 3), UINT64_MAX,
+                      (unsigned long long *)(scal + 4)));
     WV_HIP(launch_reduce(st, as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt, as<PrimeRec>(s->pr),
                          as<Pair>(s->partials), scal, as<Pair>(s->tpairs)));
     WV_HIP(launch_fold(st, as<SegRec>(s->tasks), as<uint32_t>(s->target), as<Pair>(s->tpairs), (uint32_t)nt,
                        as<PrimeRec>(s->pr), as<Pair>(s->acc)));
     WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
+    uint64_t err = 0;
+    WV_HIP(hipMemcpyAsync(&err, scal + 4, sizeof(err), hipMemcpyDeviceToHost, st));
     WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
+    WV_HIP(hipStreamSynchronize(st));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, c->ev[EV_SUM0], c->ev[EV_SUM]);
     s->busy_s += ms * 1e-3;
     s->steps++;
+    if (err) return WV_EHIP;   // the term sums did not cover every chunk: discard the step
     if (s->fault_after >= 0 && (int64_t)s->steps > s->fault_after) {
         s->fault_after = -1;   // one forced failure: the step's work is discarded
         return WV_EHIP;
@@ -321,15 +346,25 @@ int run_step(wv_server *s) {
         t.r->remaining -= t.t;
     }
     s->terms_done += terms;
+    // finished requests leave the active list one by one, so that an error in
+    // a later finalize leaves only unfinished requests active
     std::vector<Request *> still;
-    for (Request *r : s->active) {
+    int rc = WV_OK;
+    size_t i = 0;
+    for (; i < s->active.size() && rc == WV_OK; i++) {
+        Request *r = s->active[i];
         while (r->first_open < r->seg_len.size() && r->cursor[r->first_open] == r->seg_len[r->first_open])
             r->first_open++;
-        if (r->remaining == 0) WV_TRY(finish_request(s, r));
-        else still.push_back(r);
+        if (r->remaining == 0) {
+            rc = finish_request(s, r);
+            if (rc != WV_OK) still.push_back(r);   // not finished: its sums restart with the others
+        } else {
+            still.push_back(r);
+        }
     }
+    for (; i < s->active.size(); i++) still.push_back(s->active[i]);
     s->active.swap(still);
-    return WV_OK;
+    return rc;
 }
 
 double percentile(std::vector<double> v, double q) {
@@ -399,12 +434,22 @@ int wv_server_submit_range(wv_server *s, uint64_t lo, uint64_t hi, uint64_t *id)
     if (!s || !id || lo > hi) return WV_EINVAL;
     if (hi > WV_P_MAX) return WV_EDOMAIN;
     if (hi - (lo & ~1ull) > kMaxBatchSegs * kSegSpan) return WV_EINVAL;   // one batch of sieve segments
+    WV_TRY(check_device(s->c));
+    // the prime count decides whether the request can ever fit in the pool
+    std::vector<SegDesc> d;
+    window_descs(lo, hi, d);
+    std::vector<uint32_t> counts(d.size());
+    if (!d.empty()) WV_TRY(sieve_count(s->c, d.data(), d.size(), false, counts.data()));
+    uint64_t n = 0;
+    for (uint32_t k : counts) n += k;
+    if (n > s->pool) return WV_EINVAL;
     Request *r = new (std::nothrow) Request();
     if (!r) return WV_ENOMEM;
     r->id = s->next_id++;
     r->is_range = true;
     r->lo = lo;
     r->hi = hi;
+    r->n_primes = n;
     r->t_submit = now_s();
     if (!s->submitted) s->t_first = r->t_submit;
     s->submitted++;
@@ -425,6 +470,7 @@ int wv_server_submit_primes(wv_server *s, const uint64_t *primes, size_t n, uint
     if (!r) return WV_ENOMEM;
     r->id = s->next_id++;
     r->primes.assign(primes, primes + n);
+    r->n_primes = n;
     r->t_submit = now_s();
     if (!s->submitted) s->t_first = r->t_submit;
     s->submitted++;
@@ -441,6 +487,9 @@ constexpr size_t kAdmitSums = 1u << 22;
 // A request pending longer than this is admitted before smaller ones, in
 // arrival order, so that a stream of small requests cannot starve it.
 constexpr double kAdmitAgeS = 2.0;
+// After this many consecutive failed steps the active requests end with the
+// step's error instead of restarting again.
+constexpr int kMaxFailedSteps = 3;
 
 int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     if (!s) return WV_EINVAL;
@@ -449,10 +498,7 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     // smallest first (a prime list by its length, a range by its expected prime
     // count), arrival order among equals, within the per-step budget of sums;
     // a request that does not fit in the pool yet does not block those behind it
-    auto size_of = [](const Request *r) -> double {
-        return r->is_range ? (double)(r->hi - r->lo) / std::max(1.0, std::log((double)std::max<uint64_t>(r->hi, 3)))
-                           : (double)r->primes.size();
-    };
+    auto size_of = [](const Request *r) -> double { return (double)r->n_primes; };
     const double t_old = now_s() - kAdmitAgeS;
     std::stable_sort(s->pending.begin(), s->pending.end(), [&](const Request *a, const Request *b) {
         const bool oa = a->t_submit <= t_old, ob = b->t_submit <= t_old;
@@ -472,13 +518,8 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
         bool ok = false;
         const int rc = admit(s, r, &ok);
         if (rc != WV_OK) {
-            // a request that can never be served completes empty with an error
-            r->state = REQ_DONE;
-            r->t_done = now_s();
-            r->results.clear();
-            r->n = 0;
-            s->completed++;
-            s->lat_ms.push_back((r->t_done - r->t_submit) * 1e3);
+            // the request ends with this error (wv_server_result returns it)
+            fail_request(s, r, rc);
             continue;
         }
         if (!ok) waiting.push_back(r);
@@ -486,7 +527,21 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     }
     s->pending.swap(waiting);
     int rc = s->active.empty() ? WV_OK : run_step(s);
-    if (rc != WV_OK) rc = readmit_all(s);
+    if (rc == WV_OK) {
+        s->fail_streak = 0;
+    } else {
+        (void)hipGetLastError();
+        // the step's partial work is discarded: the active requests restart
+        // from their plans, or end with the error after repeated failures
+        if (++s->fail_streak >= kMaxFailedSteps) {
+            for (Request *r : s->active) fail_request(s, r, rc);
+            s->active.clear();
+            s->fail_streak = 0;
+        } else if (readmit_all(s) != WV_OK) {
+            for (Request *r : s->active) fail_request(s, r, rc);
+            s->active.clear();
+        }
+    }
     if (n_active) *n_active = (uint32_t)s->active.size();
     if (n_pending) *n_pending = (uint32_t)s->pending.size();
     return rc;
@@ -500,6 +555,13 @@ int wv_server_result(wv_server *s, uint64_t id, wv_result *out, size_t cap, size
     if (r->state != REQ_DONE) return WV_EBUSY;
     *n_out = r->results.size();
     if (latency_ms) *latency_ms = (r->t_done - r->t_submit) * 1e3;
+    if (r->status != WV_OK) {
+        // the request ended with an error: report it once, then forget it
+        const int st = r->status;
+        s->all.erase(it);
+        delete r;
+        return st;
+    }
     if (r->results.size() > cap) return WV_ETRUNC;
     if (!r->results.empty()) {
         if (!out) return WV_EINVAL;
@@ -515,6 +577,7 @@ int wv_server_get_stats(const wv_server *s, wv_server_stats *out) {
     memset(out, 0, sizeof(*out));
     out->submitted = s->submitted;
     out->completed = s->completed;
+    out->failed = s->failed;
     out->pending = s->pending.size();
     out->active = s->active.size();
     out->primes_done = s->primes_done;

@@ -558,16 +558,63 @@ def test_batch_windows_seed0_oracle_sample(ctx):
     say(f"case: batch seed 0, {len(rows)} sampled primes")
     res = ctx.eval_primes([r["p"] for r in rows])
     assert as_pairs(res) == [(r["b"], r["e"]) for r in rows]
-    small = [k for k, (a, b) in enumerate(wins) if b < 10 ** 8]
-    say(f"case: batch seed 0, {len(small)} windows below 1e8 batched")
-    assert len(small) >= 8
-    got = ctx.search_windows([wins[k][0] for k in small], [wins[k][1] for k in small])
-    for k, res in zip(small, got):
-        w = g["windows"][k]
-        assert len(res) == w["n_primes"]
+
+
+def test_batch_windows_seed0_full_batch():
+    """The whole batched workload (64 seeded windows, 429,833 primes, about
+    4.3e14 terms with the derived congruences) in one wv_search_windows call,
+    as the bench runs it: every window's prime list has the oracle's count and
+    is ascending, and all 256 stored oracle residues (4 per window) match."""
+    from paper_2101_11157_amd import workloads
+    g = golden_json("batch_seed0.json")
+    wins = workloads.batch_windows(0, 64)
+    say("case: batch seed 0, all 64 windows in one batched call (derived tables)")
+    with wv.Context(0) as c:
+        c.use_derived_tables()
+        last = [0]
+
+        def progress(done, total):
+            if done * 10 >= (last[0] + 1) * total:
+                last[0] = done * 10 // total
+                say(f"  batch progress {done}/{total} chunks")
+
+        c.set_progress(progress)
+        got = c.search_windows([a for a, _ in wins], [b for _, b in wins])
+    n_rows = 0
+    for w, res in zip(g["windows"], got):
+        assert len(res) == w["n_primes"], (w["lo"], w["hi"])
+        ps = res["p"].astype(np.int64)
+        assert np.all(np.diff(ps) > 0) and (len(ps) == 0 or (ps[0] >= w["lo"] and ps[-1] < w["hi"]))
+        assert np.all(res["flags"] != 0xFFFFFFFF)
         by_p = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in res}
         for r in w["rows"]:
             assert by_p[r["p"]] == (r["b"], r["e"]), r["p"]
+            n_rows += 1
+    assert n_rows == 256
+
+
+def test_window_1e11_whole_subwindow_two_table_sets():
+    """The bench's first timed sub-window at the paper's ceiling,
+    [1e11 - 1e6, 1e11 - 1e6 + 8192), in full with two independent congruence
+    sets (the derived 1408/1283-sum tables and the printed eqnBB30 +
+    eqnEE33: different intervals and coefficients): every prime's residues
+    agree, the prime list is the plain sieve's, and the stored oracle values
+    inside the window match."""
+    lo, hi = 10 ** 11 - 10 ** 6, 10 ** 11 - 10 ** 6 + 8192
+    say(f"case: whole window [{lo}, {hi}) with derived and printed tables")
+    with wv.Context(0) as c:
+        printed, _ = c.search_range(lo, hi)
+        c.use_derived_tables()
+        derived, _ = c.search_range(lo, hi)
+    assert [int(p) for p in derived["p"]] == oracle.primes(lo, hi)
+    assert len(derived) > 300
+    assert as_pairs(derived) == as_pairs(printed)
+    g = golden_json("window_1e11.json")
+    by_p = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in derived}
+    inside = [r for r in g["rows"] if r["p"] < hi]
+    assert inside
+    for r in inside:
+        assert by_p[r["p"]] == (r["b"], r["e"]), r["p"]
 
 
 def test_serve_seed0_oracle_sample(ctx):
@@ -606,20 +653,120 @@ def test_serve_seed0_oracle_sample(ctx):
     assert as_pairs(alone) == [(r["b"], r["e"]) for r in rows]
 
 
+def test_serve_seed0_all_requests():
+    """All 128 requests of the serving trace (seed 0, about 8.4e13 terms with
+    the derived congruences) submitted together through the request server:
+    every single prime's residues and every interval's prime count and
+    sampled prime equal the stored oracle values."""
+    from paper_2101_11157_amd import workloads
+    g = golden_json("serve_seed0.json")
+    trace = workloads.serve_trace(0, 128)
+    say("case: serve seed 0, all 128 requests through the server (derived tables)")
+    with wv.Context(0) as c:
+        c.use_derived_tables()
+        with wv.Server(c) as srv:
+            ids = [srv.submit_primes([arg]) if kind == "prime" else srv.submit_range(*arg)
+                   for _, kind, arg in trace]
+            out = {}
+            steps = 0
+            while len(out) < len(ids):
+                for rid in ids:
+                    if rid not in out:
+                        r = srv.result(rid)
+                        if r is not None:
+                            out[rid] = r
+                if len(out) < len(ids):
+                    srv.step()
+                    steps += 1
+                    if steps % 500 == 0:
+                        say(f"  {steps} steps, {len(out)}/{len(ids)} done")
+            st = srv.stats()
+    assert st["failed"] == 0 and st["completed"] == 128
+    for (t, kind, arg), q, rid in zip(trace, g["requests"], ids):
+        got, _ = out[rid]
+        if kind == "range":
+            assert len(got) == q["n_primes"], arg
+        by_p = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in got}
+        for r in q["rows"]:
+            assert by_p[r["p"]] == (r["b"], r["e"]), r["p"]
+
+
 def test_server_restart_after_failed_step(ctx):
-    """A step forced to fail (on the host) restarts the active requests; the
-    results are unchanged."""
+    """A step forced to fail (on the host) reports its error to the caller and
+    restarts the active requests; the results are unchanged."""
     say("case: server fault injection")
     ps1 = oracle.primes(3 * 10 ** 9, 3 * 10 ** 9 + 400)
     with wv.Server(ctx, step_terms=1 << 31) as srv:
         srv.inject_fault(2)
         a = srv.submit_primes(ps1)
         b = srv.submit_range(10 ** 8, 10 ** 8 + 5000)
-        res = drain(srv, [a, b])
+        errors = []
+        out = {}
+        for _ in range(100000):
+            for rid in (a, b):
+                if rid not in out:
+                    r = srv.result(rid)
+                    if r is not None:
+                        out[rid] = r
+            if len(out) == 2:
+                break
+            try:
+                srv.step()
+            except wv.WvError as e:
+                errors.append(e.status)
         st = srv.stats()
-    assert st["readmits"] >= 1
-    assert as_pairs(res[a][0]) == as_pairs(ctx.eval_primes(ps1))
-    assert as_pairs(res[b][0]) == as_pairs(ctx.search_range(10 ** 8, 10 ** 8 + 5000)[0])
+    assert errors == [wv.WV_EHIP]
+    assert st["readmits"] >= 1 and st["failed"] == 0
+    assert as_pairs(out[a][0]) == as_pairs(ctx.eval_primes(ps1))
+    assert as_pairs(out[b][0]) == as_pairs(ctx.search_range(10 ** 8, 10 ** 8 + 5000)[0])
+
+
+def test_server_repeated_failures_end_requests(ctx):
+    """Three failed steps in a row end the active requests with the error
+    (reported once by result, then forgotten) and free their pool slots: a
+    request submitted afterwards is served normally."""
+    say("case: server repeated failures")
+    ps = oracle.primes(10 ** 9, 10 ** 9 + 300)
+    with wv.Server(ctx, step_terms=1 << 28, max_primes=64) as srv:
+        a = srv.submit_primes(ps[:40])
+        raised = 0
+        for k in range(3):
+            srv.inject_fault(0)
+            try:
+                srv.step()
+            except wv.WvError as e:
+                assert e.status == wv.WV_EHIP
+                raised += 1
+        assert raised == 3
+        with pytest.raises(wv.WvError) as ei:
+            srv.result(a)
+        assert ei.value.status == wv.WV_EHIP
+        with pytest.raises(wv.WvError):
+            srv.result(a)                       # forgotten after the report
+        st = srv.stats()
+        assert st["failed"] == 1 and st["active"] == 0
+        b = srv.submit_primes(ps[:60])          # needs the freed slots
+        res = drain(srv, [b])
+    assert as_pairs(res[b][0]) == as_pairs(ctx.eval_primes(ps[:60]))
+
+
+def test_server_range_larger_than_pool_is_refused(ctx):
+    """A range whose prime count exceeds the pool is refused at submission
+    (nothing queued, no silent empty result); one that fits is served."""
+    say("case: server range larger than the pool")
+    lo, hi = 10 ** 8, 10 ** 8 + 20000
+    n = ctx.count_primes(lo, hi)
+    assert n > 700
+    with wv.Server(ctx, step_terms=1 << 30, max_primes=700) as srv:
+        with pytest.raises(wv.WvError) as ei:
+            srv.submit_range(lo, hi)
+        assert ei.value.status == wv.WV_EINVAL
+        assert srv.stats()["submitted"] == 0
+        small = (lo, lo + 9000)
+        assert ctx.count_primes(*small) <= 700
+        b = srv.submit_range(*small)
+        res = drain(srv, [b])
+    assert as_pairs(res[b][0]) == as_pairs(ctx.search_range(*small)[0])
 
 
 def test_server_pool_admission(ctx):
@@ -896,12 +1043,28 @@ def test_all_index_residues_larger_primes(ctx, irr_path, p):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("p", [2097143, 8388593])
+def _power_sum(lo, hi, t, p):
+    """sum_{lo <= s <= hi} s^t mod p on the host (numpy, exact for p < 2^26:
+    products of two residues stay below 2^52)."""
+    assert p < (1 << 26)
+    s = np.arange(lo, hi + 1, dtype=np.uint64) % np.uint64(p)
+    acc = np.ones_like(s)
+    e = t
+    while e:
+        if e & 1:
+            acc = acc * s % np.uint64(p)
+        s = s * s % np.uint64(p)
+        e >>= 1
+    return int(acc.sum(dtype=np.uint64) % np.uint64(p))   # < 2^26 terms below 2^26
+
+
+@pytest.mark.parametrize("p", [2097143, 8388593, 16777213])
 def test_all_index_paths_agree_at_scale(ctx, p):
-    """Below 2^21 (matrix-core partial sums reduced after every 1024 s) and
-    below 2^23 (after every 192 s): the vector and matrix kernels agree on
-    every index, and a few indices agree with the general-index congruence
-    evaluated plainly on the host."""
+    """Below 2^21 (matrix-core partial sums reduced after every 1024 s), below
+    2^23 (after every 192 s) and just below 2^24 (after every 32 s, the
+    tightest exact range of the matrix path): the vector and matrix kernels
+    agree on every index, and a few indices agree with the general-index
+    congruence evaluated plainly on the host."""
     say(f"case: every index at p = {p}")
     ctx.set_irregular_path(1)
     try:
@@ -914,13 +1077,13 @@ def test_all_index_paths_agree_at_scale(ctx, p):
     for k in (1, 2, 1234, (p - 3) // 2):
         # eqnE1 at exponent t = 2k: E_t = (-1)^{k'} 4^{t+1} S_t(0, 1/4), k' = (p-1-t)/2
         t = 2 * k
-        S = sum(pow(s, t, p) for s in range(1, p // 4 + 1)) % p
+        S = _power_sum(1, p // 4, t, p)
         want = (-1) ** ((p - 1 - t) // 2) * pow(4, t + 1, p) * S % p
         assert int(ev[k - 1]) == want, k
         # (2,3,4) at exponent 2k - 1: C_k B_{2k} = S_{2k-1}(1/4, 1/3)
         c = (pow(2, p - 2 * k, p) + pow(3, p - 2 * k, p) - pow(4, p - 2 * k, p) - 1) * pow(4 * k, -1, p) % p
         if c:
-            S = sum(pow(s, 2 * k - 1, p) for s in range(p // 4 + 1, p // 3 + 1)) % p
+            S = _power_sum(p // 4 + 1, p // 3, 2 * k - 1, p)
             assert int(bv[k - 1]) == S * pow(c, -1, p) % p, k
 
 
