@@ -43,10 +43,22 @@ BLOCK_FMUL = {2: 6, 3: 10}
 BLOCK_FRED = {2: 2, 3: 2}
 BLOCK_ADD = {2: 3, 3: 5}
 
-# HBM bytes (read + written) of one term-sum launch on the first timed window,
-# from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of known size
-# (profiles/k_sum_window_1e11_*.md); only valid for that kernel and workload.
-MEASURED_TRAFFIC = {("1e11", "derived 1408/1283", 28, 36, 8192): 186358446 + 269036896}
+# HBM bytes (read + written) of one term-sum launch on the bench's first timed
+# window, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of
+# known size (profiles/k_sum_window_1e11_*.md).  A profile constant: valid only
+# for the kernel source, shape, tables and window it was taken on (keyed by the
+# hash of the kernel sources), reported as null otherwise.
+MEASURED_TRAFFIC = {}
+
+
+def kernel_source_hash():
+    """Short hash of the term-sum kernel's sources (traffic figures are keyed by it)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("wv_kernels.hip", "sum_core.hpp", "mont.hpp"):
+        with open(os.path.join(ROOT, "paper_2101_11157_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
 
 
 def tables_key(which):
@@ -84,6 +96,77 @@ def muls_per_term(d, k, period):
     if k == 1:
         return 2 * 10
     return (BLOCK_FMUL[d] * 4 + BLOCK_FRED[d] * 2 + table_entries(d, k) * 2 / period) / k
+
+
+def blocked_threshold(d, k):
+    """Chunks shorter than this run the one-term (Montgomery) loop (chunk_blocked
+    in the kernel)."""
+    return 4 * (d * k + 1) * k if k > 1 else float("inf")
+
+
+class OpsModel:
+    """VALU operations of the term-sum kernel for a set of primes, from the
+    congruences each prime uses: per prime and side, the terms of the sums
+    long enough for the blocked loop (ops_per_term with that prime's
+    reduction period) and of the shorter ones (the one-term loop).  The term
+    counts are scaled to the kernel's measured totals per side."""
+
+    def __init__(self, tables, kb, ke):
+        import numpy as np
+        import paper_2101_11157_amd as wv
+        self.np = np
+        self.kb, self.ke = kb, ke
+        widths = {}
+        for side, name in (("B", "BB30"), ("E", "EE33")):
+            # interval widths y - x of the congruence's sums (terms ~ width * p)
+            widths[("printed", side)] = sorted(ya / yb - xa / xb for _, xa, xb, ya, yb in wv.table_terms(name))
+            if tables == "derived":
+                terms = wv.derived_table(side)["terms"]
+                widths[("derived", side)] = sorted(int(ya) / int(yb) - int(xa) / int(xb)
+                                                   for _, xa, xb, ya, yb in terms)
+        self.widths = {k: (np.array(v), np.concatenate([[0.0], np.cumsum(v)])) for k, v in widths.items()}
+        self.tables = tables
+        self.min_p = wv.DERIVED_MIN_P
+
+    def _side_terms(self, ps, side, d, k):
+        """(blocked terms, one-term-loop terms) per prime of one side."""
+        np = self.np
+        blk = np.zeros(len(ps))
+        one = np.zeros(len(ps))
+        thr = blocked_threshold(d, k)
+        for kind in ("printed", "derived"):
+            if (kind, side) not in self.widths:
+                continue
+            use = (ps >= self.min_p) if kind == "derived" else (
+                ps < self.min_p if self.tables == "derived" else np.ones(len(ps), bool))
+            if not use.any():
+                continue
+            w, cum = self.widths[(kind, side)]
+            q = ps[use]
+            cut = np.searchsorted(w, thr / q)        # sums narrower than thr / p are short
+            short = cum[cut] * q
+            blk[use] = (cum[-1] * q) - short
+            one[use] = short
+        return blk, one
+
+    def ops(self, primes, n_terms_b, n_terms):
+        """Modelled VALU operations for the primes' term sums, scaled to the
+        measured Bernoulli-side and total term counts."""
+        np = self.np
+        ps = np.asarray(primes, dtype=np.float64)
+        if len(ps) == 0 or n_terms == 0:
+            return 0.0
+        per = np.array([renorm_period(int(p)) for p in primes], dtype=np.float64)
+        total = 0.0
+        for side, d, k, measured in (("B", 3, self.kb, n_terms_b), ("E", 2, self.ke, n_terms - n_terms_b)):
+            blk, one = self._side_terms(ps, side, d, k)
+            est = blk.sum() + one.sum()
+            if est <= 0 or measured <= 0:
+                continue
+            opt_blk = np.array([ops_per_term(d, k, int(t)) for t in per])
+            ops = (blk * opt_blk).sum() + one.sum() * ops_per_term(d, 1, 1)
+            total += ops * (measured / est)
+        return total
 
 
 def sum_kernel_muls(st, period):
@@ -127,16 +210,130 @@ def cpu_threads():
         return os.cpu_count() or 1
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(primes, nthreads):
     """The oracle as it stands: eqnBB30 + eqnEE33 evaluated plainly, one prime
-    at a time with each sum's range split over threads."""
+    at a time with each sum's range split over threads.  Returns (primes/s,
+    seconds, [(b, e)])."""
     import oracle
     oracle.lib()
     t0 = time.perf_counter()
-    for p in primes:
-        oracle.residue_one_parallel(p, method="table", nthreads=nthreads)
+    got = [oracle.residue_one_parallel(p, method="table", nthreads=nthreads) for p in primes]
     dt = time.perf_counter() - t0
-    return len(primes) / dt, dt
+    return len(primes) / dt, dt, got
+
+
+def table_cost(tables):
+    """Terms per unit p of the congruences used at 1e11: (B, E)."""
+    import paper_2101_11157_amd as wv
+    if tables == "derived":
+        jb, je = wv.derived_table("B"), wv.derived_table("E")
+        return jb["cost"][0] / jb["cost"][1], je["cost"][0] / je["cost"][1]
+    return 227 / 6480, 27 / 512
+
+
+def measure_plain(args, wv, wins, lo0, hi0, W):
+    """The headline: consecutive sub-windows through wv_search_range."""
+    ctx = wv.Context(0)
+    if args.chunk:
+        ctx.set_chunk_terms(args.chunk)
+    if args.block:
+        ctx.set_block(*[int(v) for v in args.block.split(",")])
+    tables = use_tables(ctx, args.tables)
+    for k in range(args.warmup):
+        ctx.search_range(*wins[k])
+        print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
+    primes = terms = terms_b = 0
+    muls = 0.0
+    period = renorm_period(hi0 - 1)   # exact for every prime of the 1e11 and 1e9 ranges
+    block = None
+    ms_sum = ms_dev = 0.0
+    timed = []
+    plist = []
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        res, hits = ctx.search_range(*wins[k])
+        st = ctx.stats()
+        primes += len(res)
+        terms += st["n_terms"]
+        terms_b += st["n_terms_b"]
+        muls += sum_kernel_muls(st, period)
+        block = [st["block_k_b"], st["block_k_e"]]
+        ms_sum += st["ms_sum"]
+        ms_dev += st["ms_total"]
+        timed.append(res)
+        plist.extend(int(p) for p in res["p"])
+        print(f"step {k - args.warmup}: {len(res)} primes, {st['n_terms']:.3e} terms, "
+              f"sum kernel {st['ms_sum']:.1f} ms, device {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    ops = OpsModel(args.tables, block[0], block[1]).ops(plist, terms_b, terms) if block else 0.0
+    return dict(tables=tables, primes=primes, terms=terms, terms_b=terms_b, ops=ops, muls=muls, block=block,
+                ms_sum=ms_sum, ms_dev=ms_dev, wall=wall, results=timed)
+
+
+def measure_batch(args, wv, nwin):
+    """The batched workload: `nwin` uneven seeded windows (lengths log-uniform
+    in [1e3, 1e6], starts log-uniform in [1e6, 1e11], numpy default_rng(0)) in
+    one wv_search_windows call."""
+    from paper_2101_11157_amd import workloads
+    wins = workloads.batch_windows(0, nwin)
+    ctx = wv.Context(0)
+    if args.chunk:
+        ctx.set_chunk_terms(args.chunk)
+    tables = use_tables(ctx, args.tables)
+    t_start = time.perf_counter()
+    last = [0.0]
+
+    def progress(done, total):
+        t = time.perf_counter()
+        if t - last[0] > 10 or done == total:
+            last[0] = t
+            print(f"batch progress {done}/{total} chunks at {t - t_start:.1f} s", file=sys.stderr, flush=True)
+
+    ctx.set_progress(progress)
+    t0 = time.perf_counter()
+    res = ctx.search_windows([a for a, _ in wins], [b for _, b in wins])
+    wall = time.perf_counter() - t0
+    st = ctx.stats()
+    primes = sum(len(r) for r in res)
+    plist = [int(p) for r in res for p in r["p"]]
+    ops = OpsModel(args.tables, st["block_k_b"], st["block_k_e"]).ops(plist, st["n_terms_b"], st["n_terms"])
+    ok = None
+    if args.verify:
+        ctx.set_progress(None)
+        order = sorted(range(len(wins)), key=lambda k: wins[k][1] - wins[k][0])[: args.verify]
+        ok = True
+        for k in order:
+            ref, _ = ctx.search_range(*wins[k])
+            same = as_pairs(ref) == as_pairs(res[k])
+            ok = ok and same
+            print(f"verify window {k} {wins[k]}: {len(ref)} primes, {'identical' if same else 'DIFFERENT'}",
+                  file=sys.stderr, flush=True)
+    ctx.close()
+    return dict(workload=f"{len(wins)} seeded windows (default_rng(0)), lengths log-uniform [1e3, 1e6], "
+                         f"starts log-uniform [1e6, 1e11], one wv_search_windows call",
+                tables=tables, primes=primes, terms=st["n_terms"], terms_b=st["n_terms_b"], ops=ops,
+                ms_sum=st["ms_sum"], wall=wall, block=[st["block_k_b"], st["block_k_e"]], verified=ok,
+                n_verified=args.verify)
+
+
+def rate_summary(primes, terms, ops, wall, ms_sum):
+    """primes/s and terms/s over the wall clock, and the term-sum kernel's
+    modelled VALU rate over its own time (frac of the issue peak)."""
+    achieved = ops / (ms_sum * 1e-3) / 1e12 if ms_sum > 0 else 0.0
+    return {"primes_per_s": primes / wall, "terms_per_s": terms / wall, "primes": primes, "terms": terms,
+            "wall_s": wall, "sum_kernel_ms": ms_sum, "valu_tops": achieved, "frac": achieved / (PEAK_VALU / 1e12)}
 
 
 def main():
@@ -161,9 +358,11 @@ def main():
                     help="derived: the package's greedy-derived congruences (Section 2.2) above 2^30, "
                          "printed: eqnBB30 + eqnEE33")
     ap.add_argument("--irr-path", default="auto", choices=["auto", "valu", "mfma"],
-                    help="irregular: power-sum kernel (auto: matrix cores below 2^21)")
+                    help="irregular: power-sum kernel (auto: matrix cores below 2^24)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-primes", type=int, default=1, help="primes in the oracle sample")
+    ap.add_argument("--no-batch", action="store_true", help="1e11: leave the batched workload out of the line")
+    ap.add_argument("--no-serve", action="store_true", help="1e11: leave the served trace out of the line")
+    ap.add_argument("--cpu-primes", type=int, default=4, help="primes in the oracle sample")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one device fill and one copy of this many bytes (torch): kernels of known "
                          "traffic that scale the HBM byte counters of a profiler run")
@@ -199,45 +398,13 @@ def main():
     from paper_2101_11157_amd import workloads
     wins = workloads.bench_windows(nwin, W, lo0, hi0) if args.config != "1e5" else [(lo0, hi0)] * nwin
 
-    ctx = wv.Context(0)
-    if args.chunk:
-        ctx.set_chunk_terms(args.chunk)
-    if args.block:
-        ctx.set_block(*[int(v) for v in args.block.split(",")])
-    tables = use_tables(ctx, args.tables)
-    for k in range(args.warmup):
-        ctx.search_range(*wins[k])
-        print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
-
-    primes = terms = 0
-    ops = 0.0
-    muls = 0.0
-    period = renorm_period(hi0 - 1)   # exact for every prime of the 1e11 and 1e9 ranges
-    block = None
-    ms_sum = ms_dev = 0.0
-    first_timed = None
-    t0 = time.perf_counter()
-    for k in range(args.warmup, nwin):
-        res, hits = ctx.search_range(*wins[k])
-        st = ctx.stats()
-        primes += len(res)
-        terms += st["n_terms"]
-        ops += sum_kernel_ops(st, period)
-        muls += sum_kernel_muls(st, period)
-        block = [st["block_k_b"], st["block_k_e"]]
-        ms_sum += st["ms_sum"]
-        ms_dev += st["ms_total"]
-        if first_timed is None and len(res):
-            first_timed = [int(res["p"][0])]
-        print(f"step {k - args.warmup}: {len(res)} primes, {st['n_terms']:.3e} terms, "
-              f"sum kernel {st['ms_sum']:.1f} ms, device {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t0
-    ctx.close()
-
-    value = primes / wall
-    achieved = ops / (ms_sum * 1e-3) / 1e12
+    m = measure_plain(args, wv, wins, lo0, hi0, W)
+    value = m["primes"] / m["wall"]
+    achieved = m["ops"] / (m["ms_sum"] * 1e-3) / 1e12
     peak = PEAK_VALU / 1e12
-    mul_rate = muls / (ms_sum * 1e-3) / 1e12
+    mul_rate = m["muls"] / (m["ms_sum"] * 1e-3) / 1e12
+    block = m["block"]
+    traffic_key = (args.config, tables_key(args.tables), block[0], block[1], W, kernel_source_hash())
     line = {
         "metric": "primes tested/sec at p~1e11 (1 GPU), both B_{p-3} and E_{p-3} mod p",
         "value": value,
@@ -245,7 +412,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": m["wall"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": value / PAPER_V100_PRIMES_PER_S if args.config == "1e11" else None,
@@ -253,12 +420,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"primes in [{lo0}, {hi0}), sub-windows of {W} integers per step",
-            "tables": tables,
-            "primes_timed": primes,
-            "terms_timed": terms,
-            "terms_per_s": terms / wall,
-            "sum_kernel_ms": ms_sum,
-            "device_ms": ms_dev,
+            "tables": m["tables"],
+            "primes_timed": m["primes"],
+            "terms_timed": m["terms"],
+            "terms_per_s": m["terms"] / m["wall"],
+            "sum_kernel_ms": m["ms_sum"],
+            "device_ms": m["ms_dev"],
             "block": block,
         },
         "roofline": {
@@ -267,21 +434,62 @@ def main():
             "peak": peak,
             "unit": "Tops/s (full-rate VALU lane ops)",
             "frac": achieved / peak,
-            "traffic": (MEASURED_TRAFFIC.get((args.config, tables_key(args.tables), block[0], block[1], W))
-                        if block else None),
+            "traffic": MEASURED_TRAFFIC.get(traffic_key),
+            "traffic_source": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source on this window, scaled "
+                               "by a copy of known size (profile constant)" if traffic_key in MEASURED_TRAFFIC
+                               else "not measured for this kernel source / configuration"),
         },
     }
     # the multiply view: the blocked loop needs few multiplies per term, so
     # this fraction is low although the kernel is bound by VALU issue
     line["multiply_ops"] = {"achieved": mul_rate, "peak": peak, "unit": "Tops/s", "frac": mul_rate / peak}
-    if not args.no_cpu_baseline and first_timed:
-        sample = first_timed[: max(1, args.cpu_primes)]
+
+    if args.config == "1e11" and not args.no_batch:
+        b = measure_batch(args, wv, args.windows)
+        line["batched"] = dict({"workload": b["workload"], "tables": b["tables"], "block": b["block"]},
+                               **rate_summary(b["primes"], b["terms"], b["ops"], b["wall"], b["ms_sum"]))
+    if args.config == "1e11" and not args.no_serve:
+        from paper_2101_11157_amd import workloads as wl
+        trace = wl.serve_trace(0, args.requests, rate=args.rate)
+        ctx = wv.Context(0)
+        use_tables(ctx, args.tables)
+        sv, _ = run_trace(wv, ctx, trace, args.step_terms, args.tables)
+        ctx.close()
+        served = {"workload": f"seeded Poisson trace (default_rng(0)), {len(trace)} requests at {args.rate:g}/s, "
+                              f"70% single primes, 30% intervals of 1e2..1e5, u in [1e8, 1e11]",
+                  "p50_ms": sv["p50_ms"], "p99_ms": sv["p99_ms"], "mean_ms": sv["mean_ms"],
+                  "primes_per_s": sv["value"], "terms_per_s": sv["terms"] / sv["wall_s"],
+                  "capacity_terms_per_s": sv["capacity_terms_per_s"],
+                  "offered_over_capacity": sv["offered_over_capacity"], "primes": sv["primes"],
+                  "terms": sv["terms"], "wall_s": sv["wall_s"], "busy_s": sv["busy_s"], "steps": sv["steps"],
+                  "valu_tops": sv["valu_tops"], "frac": sv["frac"]}
+        line["served"] = served
+    if "batched" in line or "served" in line:
+        # like-for-like: the term-sum kernel's modelled VALU rate (ops per term
+        # differ between the Bernoulli and Euler sides and with p, so terms/s
+        # alone depends on the mix of congruences and primes)
+        line["vs_plain"] = {k: {"frac_ratio": line[k]["frac"] / line["roofline"]["frac"],
+                                "terms_per_s_ratio": line[k]["terms_per_s"] / line["config"]["terms_per_s"]}
+                            for k in ("batched", "served") if k in line}
+
+    if not args.no_cpu_baseline and m["results"]:
+        first = m["results"][0]
+        k = max(1, args.cpu_primes)
+        idx = [int(round(i * (len(first) - 1) / max(1, k - 1))) for i in range(k)] if len(first) > 1 else [0]
+        sample = [int(first["p"][i]) for i in sorted(set(idx))]
+        gpu = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in first}
         nt = cpu_threads()
-        v, dt = cpu_baseline(sample, nt)
+        v, dt, got = cpu_baseline(sample, nt)
+        cb, ce = table_cost(args.tables)
+        match = all(gpu[p] == g for p, g in zip(sample, got))
         line["cpu_baseline"] = {
             "value": v, "unit": "primes/s", "cores": nt, "kind": "oracle",
-            "sample": f"{len(sample)} prime(s) of the first timed window ({sample[0]}), "
-                      f"eqnBB30+eqnEE33 evaluated plainly, {dt:.1f} s",
+            "sample": f"{len(sample)} primes spread over the first timed window ({sample[0]}..{sample[-1]}), "
+                      f"eqnBB30+eqnEE33 evaluated plainly (each sum split over {nt} threads), {dt:.1f} s; "
+                      f"residues {'identical to' if match else 'DIFFERENT from'} the GPU's",
+            "cpu_model": cpu_model(),
+            "residues_match_gpu": match,
+            "terms_per_prime_ratio_oracle_over_gpu": (227 / 6480 + 27 / 512) / (cb + ce),
         }
     print(json.dumps(line), flush=True)
 
@@ -415,51 +623,16 @@ def bench_irregular(args, wv):
 def bench_batch(args, wv):
     """Uneven seeded windows (lengths log-uniform in [1e3, 1e6], starts in
     [1e6, 1e11], numpy default_rng(0)) in one batched call."""
-    from paper_2101_11157_amd import workloads
-    wins = workloads.batch_windows(0, args.windows)
-    ctx = wv.Context(0)
-    if args.chunk:
-        ctx.set_chunk_terms(args.chunk)
-    tables = use_tables(ctx, args.tables)
-    last = [0.0]
-
-    t_start = time.perf_counter()
-
-    def progress(done, total):
-        t = time.perf_counter()
-        if t - last[0] > 10 or done == total:
-            last[0] = t
-            print(f"batch progress {done}/{total} chunks at {t - t_start:.1f} s", file=sys.stderr, flush=True)
-
-    ctx.set_progress(progress)
-    t0 = time.perf_counter()
-    res = ctx.search_windows([a for a, _ in wins], [b for _, b in wins])
-    wall = time.perf_counter() - t0
-    st = ctx.stats()
-    primes = sum(len(r) for r in res)
-    ok = None
-    if args.verify:
-        ctx.set_progress(None)
-        order = sorted(range(len(wins)), key=lambda k: wins[k][1] - wins[k][0])[: args.verify]
-        ok = True
-        for k in order:
-            ref, _ = ctx.search_range(*wins[k])
-            same = as_pairs(ref) == as_pairs(res[k])
-            ok = ok and same
-            print(f"verify window {k} {wins[k]}: {len(ref)} primes, {'identical' if same else 'DIFFERENT'}",
-                  file=sys.stderr, flush=True)
-    ctx.close()
+    b = measure_batch(args, wv, args.windows)
+    r = rate_summary(b["primes"], b["terms"], b["ops"], b["wall"], b["ms_sum"])
     print(json.dumps({
-        "metric": "batched windows: primes tested/sec (1 GPU)", "value": primes / wall, "unit": "primes/s",
-        "config": {"workload": f"{len(wins)} seeded windows (default_rng(0)), lengths log-uniform [1e3, 1e6], "
-                               f"starts log-uniform [1e6, 1e11]", "primes": primes, "terms": st["n_terms"],
-                   "terms_per_s": st["n_terms"] / wall, "sum_kernel_ms": st["ms_sum"], "wall_s": wall,
-                   "block": [st["block_k_b"], st["block_k_e"]], "tables": tables, "verified_windows": args.verify,
-                   "verified_identical": ok},
+        "metric": "batched windows: primes tested/sec (1 GPU)", "value": r["primes_per_s"], "unit": "primes/s",
+        "config": dict({"workload": b["workload"], "tables": b["tables"], "block": b["block"],
+                        "verified_windows": b["n_verified"], "verified_identical": b["verified"]}, **r),
     }), flush=True)
 
 
-def run_trace(wv, ctx, trace, step_terms):
+def run_trace(wv, ctx, trace, step_terms, tables="derived"):
     """Submit each request at its arrival time, step the server, collect
     results; latency is measured from arrival."""
     srv = wv.Server(ctx, step_terms=step_terms)
@@ -497,6 +670,9 @@ def run_trace(wv, ctx, trace, step_terms):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    served = [int(p) for res in out.values() for p in res["p"]]
+    ops = OpsModel(tables, st["block_k_b"], st["block_k_e"]).ops(served, st["terms_done_b"], st["terms_done"])
+    valu = ops / st["sum_s"] / 1e12 if st["sum_s"] > 0 else 0.0
     v = sorted(lat.values())
     pct = lambda q: v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
     span = trace[-1][0] if trace else 0.0
@@ -505,7 +681,8 @@ def run_trace(wv, ctx, trace, step_terms):
     summary = {"value": primes / wall, "p50_ms": pct(0.5), "p99_ms": pct(0.99), "mean_ms": sum(v) / len(v),
                "max_ms": v[-1], "requests": len(trace), "primes": primes, "terms": st["terms_done"],
                "wall_s": wall, "busy_s": st["busy_s"], "steps": st["steps"], "offered_terms_per_s": offered,
-               "capacity_terms_per_s": capacity, "offered_over_capacity": offered / capacity if capacity else None}
+               "capacity_terms_per_s": capacity, "offered_over_capacity": offered / capacity if capacity else None,
+               "sum_kernel_s": st["sum_s"], "valu_tops": valu, "frac": valu / (PEAK_VALU / 1e12)}
     return summary, out
 
 
@@ -518,7 +695,7 @@ def bench_serve(args, wv):
     trace = workloads.serve_trace(0, args.requests, rate=args.rate)
     ctx = wv.Context(0)
     tables = use_tables(ctx, args.tables)
-    main_run, out = run_trace(wv, ctx, trace, args.step_terms)
+    main_run, out = run_trace(wv, ctx, trace, args.step_terms, args.tables)
     ok = None
     if args.verify:
         ok = True
@@ -542,7 +719,7 @@ def bench_serve(args, wv):
         per_req = main_run["terms"] / len(trace)
         rate = args.load * main_run["capacity_terms_per_s"] / per_req
         print(f"supplementary run: {rate:.3f} requests/s ({args.load:g} x capacity)", file=sys.stderr, flush=True)
-        sup, _ = run_trace(wv, ctx, workloads.serve_trace(0, args.requests, rate=rate), args.step_terms)
+        sup, _ = run_trace(wv, ctx, workloads.serve_trace(0, args.requests, rate=rate), args.step_terms, args.tables)
         line["supplementary"] = dict({"rate_per_s": rate, "load": args.load}, **sup)
     ctx.close()
     print(json.dumps(line), flush=True)

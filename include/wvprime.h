@@ -367,7 +367,7 @@ int wv_eval_sums(wv_ctx *ctx, const uint64_t *primes, size_t n, uint64_t *out_b,
 typedef struct wv_server wv_server;
 
 typedef struct {
-    uint64_t step_terms;   /* terms of work per step (0: 2^36, ~12 ms at p ~ 1e11) */
+    uint64_t step_terms;   /* terms of work per step (0: 2^38, ~45 ms at p ~ 1e11) */
     uint32_t max_primes;   /* prime slots of the device pool (0: 65536) */
     uint32_t reserved;
 } wv_server_config;
@@ -379,6 +379,9 @@ typedef struct {
     double busy_s;                          /* device time of the steps */
     double wall_s;                          /* since the first submit */
     uint64_t failed;                        /* requests that ended with an error (counted in completed) */
+    uint64_t terms_done_b;                  /* Bernoulli-side (s^-3) terms of terms_done */
+    double sum_s;                           /* device time of the term-sum kernel launches */
+    uint32_t block_k_b, block_k_e;          /* block shape of the term-sum kernel */
 } wv_server_stats;
 
 int wv_server_create(wv_ctx *ctx, const wv_server_config *cfg, wv_server **out);
@@ -389,16 +392,22 @@ int wv_server_destroy(wv_server *srv);
 int wv_server_submit_range(wv_server *srv, uint64_t lo, uint64_t hi, uint64_t *id);
 /* A list of primes (validated like wv_eval_primes; at most max_primes). */
 int wv_server_submit_primes(wv_server *srv, const uint64_t *primes, size_t n, uint64_t *id);
-/* Admit what fits, then run one step of work; returns after the step's GPU
- * work.  Admission takes requests pending for 2 s or more in arrival order,
+/* Admit what fits, launch the next step of work, then wait for the step the
+ * previous call launched: steps are pipelined two deep, so the caller's work
+ * between calls and the host's planning overlap the device's work.  A
+ * request's results become available in the call that completes its last
+ * step (wv_server_result says WV_EBUSY until then).  A step holds about
+ * step_terms terms (default 2^38, about 45 ms of the whole GPU at p ~ 1e11),
+ * shared fairly among the active requests.  Admission takes requests pending for 2 s or more in arrival order,
  * then the smallest first (by number of primes), and plans at most 2^22 sums
  * per step; a request that does not fit in the pool waits without blocking
  * others.  A request whose admission fails ends with that error (see
  * wv_server_result) and frees its pool slots.  A failed step (HIP error, or
  * term sums that did not cover every chunk) returns its error after
  * restarting every active request from its plan, so no partial state of the
- * failed step survives; after 3 consecutive failed steps the active requests
- * end with the error instead.  The server stays usable either way. */
+ * failed step survives (the step launched after it is discarded too); after
+ * 3 failed steps with no step completed between them the active requests end
+ * with the error instead.  The server stays usable either way. */
 int wv_server_step(wv_server *srv, uint32_t *n_active, uint32_t *n_pending);
 /* Results of a finished request (then forgotten); WV_EBUSY while it runs,
  * WV_ETRUNC (with *n_out) if cap is short.  A request that ended with an error

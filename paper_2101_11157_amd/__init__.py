@@ -86,7 +86,8 @@ class WvServerStats(ctypes.Structure):
         ("steps", ctypes.c_uint64), ("readmits", ctypes.c_uint64),
         ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
         ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("wall_s", ctypes.c_double),
-        ("failed", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64), ("terms_done_b", ctypes.c_uint64), ("sum_s", ctypes.c_double),
+        ("block_k_b", ctypes.c_uint32), ("block_k_e", ctypes.c_uint32),
     ]
 
     def as_dict(self):

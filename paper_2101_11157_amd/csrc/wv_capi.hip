@@ -294,8 +294,8 @@ uint64_t window_piece(const wv_ctx *c, uint64_t hi) {
 
 // Prime counts of descs[0..ns) into counts; with keep_bits the prime bitmaps
 // stay in c->seg_bits for a following compaction (ns <= kMaxBatchSegs).
-int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts) {
-    hipStream_t st = c->stream;
+int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts, hipStream_t st) {
+    if (!st) st = c->stream;
     WV_TRY(ensure(c, c->seg_desc, std::min<size_t>(ns, kSieveLaunch) * sizeof(SegDesc)));
     WV_TRY(ensure(c, c->seg_counts, std::min<size_t>(ns, kSieveLaunch) * sizeof(uint32_t)));
     if (keep_bits) WV_TRY(ensure(c, c->seg_bits, ns * kSegWords * sizeof(uint32_t)));
@@ -311,8 +311,8 @@ int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint
 }
 
 // Primes of descs[0..ns) (bitmaps already in c->seg_bits) into c->primes.
-int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out) {
-    hipStream_t st = c->stream;
+int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out, hipStream_t st) {
+    if (!st) st = c->stream;
     std::vector<uint64_t> offs(ns + 1, 0);
     for (size_t i = 0; i < ns; i++) offs[i + 1] = offs[i] + counts[i];
     *np_out = offs[ns];

@@ -183,8 +183,12 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
 void window_descs(uint64_t lo, uint64_t hi, std::vector<SegDesc> &d, uint64_t piece = kSegSpan);
 // sub-range width whose primes near hi hold about half a search batch of work
 uint64_t window_piece(const wv_ctx *c, uint64_t hi);
-int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts);
-int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out);
+// st: the stream to use (nullptr: the context's); both wait for their own work
+// (compact leaves the compaction enqueued on st)
+int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts,
+                hipStream_t st = nullptr);
+int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out,
+            hipStream_t st = nullptr);
 // out: host results (may be NULL when sink is set), written contiguously in
 // desc order, or, with dest, the primes of descs[k] at out + dest[k];
 // sink: device statistics

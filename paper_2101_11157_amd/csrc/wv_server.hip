@@ -13,6 +13,14 @@
 // results copied out and its slots freed.  New requests join at the next
 // step, so short requests overtake long ones instead of queueing behind them.
 //
+// Steps are pipelined two deep: a call of wv_server_step plans and launches
+// the next step (the host advances the requests' cursors when it plans, so the
+// plan never waits for the device) and then waits for the step launched by the
+// previous call.  The host's work between steps -- planning, the caller's own
+// loop -- overlaps the device's work.  Admission (sieve, plan into the pool)
+// and finalization run on a second stream: they touch pool slots that no step
+// in flight uses.
+//
 // Because the pair product is associative and commutative and all arithmetic
 // is exact, a request's residues do not depend on how its work was cut into
 // tasks or interleaved with other requests.
@@ -51,31 +59,59 @@ struct Request {
     uint64_t n_primes = 0;     // primes of a range (counted at submission) or list length
     uint32_t n = 0;            // primes in the pool
     uint32_t base = 0;         // first pool slot
-    std::vector<uint64_t> seg_lo, seg_len, cursor;
-    size_t first_open = 0;     // first sum with work left
-    uint64_t remaining = 0;    // terms left
+    std::vector<uint64_t> seg_lo, seg_len, cursor;   // cursor: terms handed to launched steps
+    size_t first_open = 0;     // first sum with terms not yet handed out
+    uint64_t remaining = 0;    // terms not yet handed to a launched step
+    uint64_t last_step = 0;    // the last launched step holding terms of this request (0: none)
     std::vector<wv_result> results;
+};
+
+struct Task {
+    Request *r;
+    size_t k;        // sum index within the request
+    uint64_t t;      // terms
+};
+
+// One step's device buffers, the host staging its copies read from (kept
+// until the step completes), its events and its error word.
+struct StepSet {
+    DevBuf tasks, target, toff, tpairs, partials, tails, scal;
+    std::vector<SegRec> recs;
+    std::vector<uint32_t> tgt, tails_h;
+    std::vector<uint64_t> off;
+    uint64_t layout[5] = {};
+    uint64_t *err_host = nullptr;   // pinned: the step's term-sum error word
+    hipEvent_t ev0 = nullptr, ev_sum = nullptr, ev1 = nullptr;
+    bool busy = false;              // launched and not yet completed
+    uint64_t id = 0;                // step number (1, 2, ...)
+    uint64_t terms = 0, terms_b = 0;
 };
 
 }  // namespace
 
 struct wv_server {
     wv_ctx *c = nullptr;
-    uint64_t step_terms = 1ull << 36;
+    uint64_t step_terms = 1ull << 38;
     uint32_t pool = 1u << 16;
     int tb = 0, te = 0;        // congruences fixed at creation (the pool layout depends on them)
     int nB = 0, nE = 0, NS = 0;
-    DevBuf pr, segs, acc, terms, tmp, tasks, target, toff, tpairs, partials, res, scal, coefs, lhsmod, tails;
+    DevBuf pr, segs, acc, terms, tmp, res, coefs, lhsmod;
+    StepSet set[2];
+    int next = 0;              // the set the next launch uses
+    uint64_t launched = 0;     // steps launched
+    hipStream_t aux = nullptr; // admission and finalization
     std::vector<std::pair<uint32_t, uint32_t>> free_ranges;   // (first slot, count), sorted
     std::deque<Request *> pending;
     std::vector<Request *> active;
     std::map<uint64_t, Request *> all;
     uint64_t next_id = 1;
-    uint64_t submitted = 0, completed = 0, failed = 0, primes_done = 0, terms_done = 0, steps = 0, readmits = 0;
-    int fail_streak = 0;       // consecutive failed steps
+    uint64_t submitted = 0, completed = 0, failed = 0, primes_done = 0, terms_done = 0, terms_done_b = 0, steps = 0,
+             readmits = 0;
+    double sum_s = 0;          // device time of the term-sum launches
+    int fail_streak = 0;       // failed steps since the last step that completed
     double t_first = 0, busy_s = 0;
     std::vector<double> lat_ms;
-    int fault_after = -1;      // host-forced step failure (tests)
+    int64_t fault_after = -1;  // host-forced step failure (tests)
 };
 
 namespace {
@@ -106,18 +142,21 @@ void pool_free(wv_server *s, uint32_t base, uint32_t n) {
     s->free_ranges.swap(merged);
 }
 
+// Finalize a request whose steps have all completed: residues from its sums'
+// accumulators (on the auxiliary stream; no step in flight uses its slots),
+// copied out; its slots are freed.
 int finish_request(wv_server *s, Request *r) {
     wv_ctx *c = s->c;
     if (r->n) {
-        WV_HIP(launch_finalize(c->stream, table_store(c), as<PrimeRec>(s->pr) + r->base,
+        WV_HIP(launch_finalize(s->aux, table_store(c), as<PrimeRec>(s->pr) + r->base,
                                as<Pair>(s->acc) + (size_t)r->base * s->NS,
                                as<uint64_t>(s->coefs) + (size_t)r->base * s->NS,
                                as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->n, s->nB, s->nE,
                                as<wv_result>(s->res), nullptr));
         r->results.resize(r->n);
         WV_HIP(hipMemcpyAsync(r->results.data(), s->res.ptr, r->n * sizeof(wv_result), hipMemcpyDeviceToHost,
-                              c->stream));
-        WV_HIP(hipStreamSynchronize(c->stream));
+                              s->aux));
+        WV_HIP(hipStreamSynchronize(s->aux));
     }
     pool_free(s, r->base, r->n);
     r->state = REQ_DONE;
@@ -143,19 +182,20 @@ void fail_request(wv_server *s, Request *r, int status) {
 }
 
 // Plans the n primes at d_primes into the pool slots [r->base, r->base + n)
-// and reads the per-sum records back.  The caller frees the slots on error.
+// and reads the per-sum records back (auxiliary stream).  The caller frees the
+// slots on error.
 int plan_request(wv_server *s, Request *r, const uint64_t *d_primes, uint32_t n) {
     wv_ctx *c = s->c;
     const size_t first = (size_t)r->base * s->NS, nseg = (size_t)n * s->NS;
-    WV_HIP(launch_plan(c->stream, d_primes, n, s->tb, s->te, table_fallback(c, s->tb), table_fallback(c, s->te),
-                       s->nB, s->nE, table_store(c), as<PrimeRec>(s->pr) + r->base, as<SegRec>(s->segs) + first,
+    WV_HIP(launch_plan(s->aux, d_primes, n, s->tb, s->te, table_fallback(c, s->tb), table_fallback(c, s->te), s->nB,
+                       s->nE, table_store(c), as<PrimeRec>(s->pr) + r->base, as<SegRec>(s->segs) + first,
                        as<uint64_t>(s->terms) + first, as<uint64_t>(s->coefs) + first,
                        as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->base));
-    WV_HIP(launch_fill_pairs(c->stream, as<Pair>(s->acc) + first, nseg, 1, 0));
+    WV_HIP(launch_fill_pairs(s->aux, as<Pair>(s->acc) + first, nseg, 1, 0));
     std::vector<SegRec> recs(nseg);
     WV_HIP(hipMemcpyAsync(recs.data(), as<SegRec>(s->segs) + first, nseg * sizeof(SegRec), hipMemcpyDeviceToHost,
-                          c->stream));
-    WV_HIP(hipStreamSynchronize(c->stream));
+                          s->aux));
+    WV_HIP(hipStreamSynchronize(s->aux));
     r->seg_lo.resize(nseg);
     r->seg_len.resize(nseg);
     r->cursor.assign(nseg, 0);
@@ -166,6 +206,7 @@ int plan_request(wv_server *s, Request *r, const uint64_t *d_primes, uint32_t n)
         r->remaining += recs[k].len;
     }
     r->first_open = 0;
+    r->last_step = 0;
     return WV_OK;
 }
 
@@ -188,14 +229,14 @@ int admit(wv_server *s, Request *r, bool *admitted) {
         window_descs(r->lo, r->hi, d);
         std::vector<uint32_t> counts(d.size());
         uint64_t got = 0;
-        rc = sieve_count(c, d.data(), d.size(), true, counts.data());
-        if (rc == WV_OK) rc = compact(c, d.data(), d.size(), counts.data(), &got);
+        rc = sieve_count(c, d.data(), d.size(), true, counts.data(), s->aux);
+        if (rc == WV_OK) rc = compact(c, d.data(), d.size(), counts.data(), &got, s->aux);
         if (rc == WV_OK && got != n) rc = WV_EHIP;   // the sieve is deterministic
         d_primes = as<uint64_t>(c->primes);
     } else if (n > 0) {
         rc = ensure(c, s->tmp, n * sizeof(uint64_t));
         if (rc == WV_OK && hipMemcpyAsync(s->tmp.ptr, r->primes.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                          c->stream) != hipSuccess)
+                                          s->aux) != hipSuccess)
             rc = WV_EHIP;
         d_primes = as<uint64_t>(s->tmp);
     }
@@ -214,12 +255,14 @@ int admit(wv_server *s, Request *r, bool *admitted) {
     return WV_OK;
 }
 
-// Restart every active request from scratch (after a failed step).
+// Restart every active request from scratch (after a failed step; no step is
+// in flight).
 int readmit_all(wv_server *s) {
     for (Request *r : s->active) {
         std::fill(r->cursor.begin(), r->cursor.end(), 0);
         r->first_open = 0;
         r->remaining = 0;
+        r->last_step = 0;
         for (uint64_t l : r->seg_len) r->remaining += l;
         WV_HIP(launch_fill_pairs(s->c->stream, as<Pair>(s->acc) + (size_t)r->base * s->NS, (size_t)r->n * s->NS,
                                  1, 0));
@@ -229,14 +272,13 @@ int readmit_all(wv_server *s) {
     return WV_OK;
 }
 
-struct Task {
-    Request *r;
-    size_t k;        // sum index within the request
-    uint64_t t;      // terms
-};
-
-int run_step(wv_server *s) {
+// Plans the next step on the host -- a fair share of the budget per active
+// request with terms not yet handed out, cut into tasks of whole chunks -- and
+// launches it on the context stream with buffer set `ss`.  The requests'
+// cursors advance now.  *launched is false when no request has terms left.
+int launch_step(wv_server *s, StepSet &ss, bool *launched) {
     wv_ctx *c = s->c;
+    *launched = false;
     const uint64_t C = c->chunk_cfg   ? c->chunk_cfg
                        : c->chunk_auto ? c->chunk_auto
                                        : (adaptive_chunk(s->step_terms, sum_lanes(c)) + 63) & ~63ull;
@@ -271,22 +313,21 @@ int run_step(wv_server *s) {
     }
     if (tasks.empty()) return WV_OK;
     const size_t nt = tasks.size();
-    std::vector<SegRec> recs(nt);
-    std::vector<uint32_t> tgt(nt);
-    std::vector<uint64_t> off(nt + 1, 0);
-    uint64_t terms = 0;
+    ss.recs.resize(nt);
+    ss.tgt.resize(nt);
+    ss.off.assign(nt + 1, 0);
+    uint64_t terms = 0, terms_b = 0;
     for (size_t j = 0; j < nt; j++) {
         const Task &t = tasks[j];
-        const size_t nseg_r = t.r->seg_len.size();
         const size_t k = t.k;
         // slot k of the request: Bernoulli slots (i*nB + j) first, then Euler
         const bool bern = k < (size_t)t.r->n * s->nB;
         const uint32_t prime = bern ? (uint32_t)(k / s->nB) : (uint32_t)((k - (size_t)t.r->n * s->nB) / s->nE);
-        recs[j] = SegRec{t.r->seg_lo[k] + t.r->cursor[k], t.t, t.r->base + prime, bern ? 3u : 2u};
-        tgt[j] = (uint32_t)((size_t)t.r->base * s->NS + k);
-        off[j + 1] = off[j] + t.t / C;   // full chunks
+        ss.recs[j] = SegRec{t.r->seg_lo[k] + t.r->cursor[k], t.t, t.r->base + prime, bern ? 3u : 2u};
+        ss.tgt[j] = (uint32_t)((size_t)t.r->base * s->NS + k);
+        ss.off[j + 1] = ss.off[j] + t.t / C;   // full chunks
         terms += t.t;
-        (void)nseg_r;
+        if (bern) terms_b += t.t;
     }
     // tail chunks (tasks whose length C does not divide) by length class,
     // longest first (counting sort, as the batch plan does on the device)
@@ -295,57 +336,79 @@ int run_step(wv_server *s) {
     for (size_t j = 0; j < nt; j++)
         if (const uint64_t rem = tasks[j].t % C) first[(cls[j] = tail_bucket(rem, C)) + 1]++;
     for (int b = 0; b < kTailBuckets; b++) first[b + 1] += first[b];
-    std::vector<uint32_t> tails(first[kTailBuckets]);
+    ss.tails_h.resize(first[kTailBuckets]);
     for (size_t j = 0; j < nt; j++)
-        if (cls[j] < (uint32_t)kTailBuckets) tails[first[cls[j]]++] = (uint32_t)j;
-    const uint64_t chunks = off[nt];
-    WV_TRY(ensure(c, s->tasks, nt * sizeof(SegRec)));
-    WV_TRY(ensure(c, s->target, nt * sizeof(uint32_t)));
-    WV_TRY(ensure(c, s->toff, (nt + 1) * sizeof(uint64_t)));
-    WV_TRY(ensure(c, s->tpairs, nt * sizeof(Pair)));
-    WV_TRY(ensure(c, s->partials, std::max<uint64_t>(chunks, 1) * sizeof(Pair)));
-    WV_TRY(ensure(c, s->tails, std::max<size_t>(tails.size(), 1) * sizeof(uint32_t)));
+        if (cls[j] < (uint32_t)kTailBuckets) ss.tails_h[first[cls[j]]++] = (uint32_t)j;
+    const uint64_t chunks = ss.off[nt];
+    WV_TRY(ensure(c, ss.tasks, nt * sizeof(SegRec)));
+    WV_TRY(ensure(c, ss.target, nt * sizeof(uint32_t)));
+    WV_TRY(ensure(c, ss.toff, (nt + 1) * sizeof(uint64_t)));
+    WV_TRY(ensure(c, ss.tpairs, nt * sizeof(Pair)));
+    WV_TRY(ensure(c, ss.partials, std::max<uint64_t>(chunks, 1) * sizeof(Pair)));
+    WV_TRY(ensure(c, ss.tails, std::max<size_t>(ss.tails_h.size(), 1) * sizeof(uint32_t)));
     hipStream_t st = c->stream;
-    WV_HIP(hipMemcpyAsync(s->tasks.ptr, recs.data(), nt * sizeof(SegRec), hipMemcpyHostToDevice, st));
-    WV_HIP(hipMemcpyAsync(s->target.ptr, tgt.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    WV_HIP(hipMemcpyAsync(s->toff.ptr, off.data(), (nt + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    if (!tails.empty())
-        WV_HIP(hipMemcpyAsync(s->tails.ptr, tails.data(), tails.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                              st));
+    WV_HIP(hipMemcpyAsync(ss.tasks.ptr, ss.recs.data(), nt * sizeof(SegRec), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(ss.target.ptr, ss.tgt.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    WV_HIP(hipMemcpyAsync(ss.toff.ptr, ss.off.data(), (nt + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    if (!ss.tails_h.empty())
+        WV_HIP(hipMemcpyAsync(ss.tails.ptr, ss.tails_h.data(), ss.tails_h.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, st));
     // chunk layout, the chunk counter, the term-sum error word
-    const uint64_t layout[5] = {C, chunks, tails.size(), 0, 0};
-    uint64_t *scal = as<uint64_t>(s->scal);
-    WV_HIP(hipMemcpyAsync(scal, layout, sizeof(layout), hipMemcpyHostToDevice, st));
-    WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
+    ss.layout[0] = C;
+    ss.layout[1] = chunks;
+    ss.layout[2] = ss.tails_h.size();
+    ss.layout[3] = 0;
+    ss.layout[4] = 0;
+    uint64_t *scal = as<uint64_t>(ss.scal);
+    WV_HIP(hipMemcpyAsync(scal, ss.layout, sizeof(ss.layout), hipMemcpyHostToDevice, st));
+    WV_HIP(hipEventRecord(ss.ev0, st));
     const int v = c->variant;
-    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt,
-                      as<PrimeRec>(s->pr), scal, as<uint32_t>(s->tails), as<Pair>(s->partials),
-                      as<Pair>(s->tpairs), (unsigned long long *)(scal + 3), UINT64_MAX,
-                      (unsigned long long *)(scal + 4)));
-    WV_HIP(launch_reduce(st, as<SegRec>(s->tasks), as<uint64_t>(s->toff), (uint32_t)nt, as<PrimeRec>(s->pr),
-                         as<Pair>(s->partials), scal, as<Pair>(s->tpairs)));
-    WV_HIP(launch_fold(st, as<SegRec>(s->tasks), as<uint32_t>(s->target), as<Pair>(s->tpairs), (uint32_t)nt,
+    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(ss.tasks), as<uint64_t>(ss.toff), (uint32_t)nt,
+                      as<PrimeRec>(s->pr), scal, as<uint32_t>(ss.tails), as<Pair>(ss.partials), as<Pair>(ss.tpairs),
+                      (unsigned long long *)(scal + 3), UINT64_MAX, (unsigned long long *)(scal + 4)));
+    WV_HIP(hipEventRecord(ss.ev_sum, st));
+    WV_HIP(launch_reduce(st, as<SegRec>(ss.tasks), as<uint64_t>(ss.toff), (uint32_t)nt, as<PrimeRec>(s->pr),
+                         as<Pair>(ss.partials), scal, as<Pair>(ss.tpairs)));
+    WV_HIP(launch_fold(st, as<SegRec>(ss.tasks), as<uint32_t>(ss.target), as<Pair>(ss.tpairs), (uint32_t)nt,
                        as<PrimeRec>(s->pr), as<Pair>(s->acc)));
-    WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
-    uint64_t err = 0;
-    WV_HIP(hipMemcpyAsync(&err, scal + 4, sizeof(err), hipMemcpyDeviceToHost, st));
-    WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
-    WV_HIP(hipStreamSynchronize(st));
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, c->ev[EV_SUM0], c->ev[EV_SUM]);
+    WV_HIP(hipMemcpyAsync(ss.err_host, scal + 4, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    WV_HIP(hipEventRecord(ss.ev1, st));
+    // the terms are handed out: advance the cursors
+    ss.id = ++s->launched;
+    for (const Task &t : tasks) {
+        t.r->cursor[t.k] += t.t;
+        t.r->remaining -= t.t;
+        t.r->last_step = ss.id;
+    }
+    for (Request *r : s->active)
+        while (r->first_open < r->seg_len.size() && r->cursor[r->first_open] == r->seg_len[r->first_open])
+            r->first_open++;
+    ss.terms = terms;
+    ss.terms_b = terms_b;
+    ss.busy = true;
+    *launched = true;
+    return WV_OK;
+}
+
+// Waits for the step of buffer set `ss`; on success finalizes every request
+// whose last step it was.
+int complete_step(wv_server *s, StepSet &ss) {
+    WV_HIP(hipEventSynchronize(ss.ev1));
+    ss.busy = false;
+    float ms = 0.f, ms_sum = 0.f;
+    (void)hipEventElapsedTime(&ms, ss.ev0, ss.ev1);
+    (void)hipEventElapsedTime(&ms_sum, ss.ev0, ss.ev_sum);
     s->busy_s += ms * 1e-3;
+    s->sum_s += ms_sum * 1e-3;
     s->steps++;
-    if (err) return WV_EHIP;   // the term sums did not cover every chunk: discard the step
+    if (*ss.err_host) return WV_EHIP;   // the term sums did not cover every chunk: discard the step
     if (s->fault_after >= 0 && (int64_t)s->steps > s->fault_after) {
         s->fault_after = -1;   // one forced failure: the step's work is discarded
         return WV_EHIP;
     }
-    // commit progress
-    for (const Task &t : tasks) {
-        t.r->cursor[t.k] += t.t;
-        t.r->remaining -= t.t;
-    }
-    s->terms_done += terms;
+    s->terms_done += ss.terms;
+    s->terms_done_b += ss.terms_b;
+    s->fail_streak = 0;
     // finished requests leave the active list one by one, so that an error in
     // a later finalize leaves only unfinished requests active
     std::vector<Request *> still;
@@ -353,9 +416,7 @@ int run_step(wv_server *s) {
     size_t i = 0;
     for (; i < s->active.size() && rc == WV_OK; i++) {
         Request *r = s->active[i];
-        while (r->first_open < r->seg_len.size() && r->cursor[r->first_open] == r->seg_len[r->first_open])
-            r->first_open++;
-        if (r->remaining == 0) {
+        if (r->remaining == 0 && r->last_step <= ss.id) {
             rc = finish_request(s, r);
             if (rc != WV_OK) still.push_back(r);   // not finished: its sums restart with the others
         } else {
@@ -402,8 +463,22 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
         (rc = ensure(c, s->terms, nseg * sizeof(uint64_t))) != WV_OK ||
         (rc = ensure(c, s->coefs, nseg * sizeof(uint64_t))) != WV_OK ||
         (rc = ensure(c, s->lhsmod, 2 * (size_t)s->pool * sizeof(uint64_t))) != WV_OK ||
-        (rc = ensure(c, s->res, s->pool * sizeof(wv_result))) != WV_OK ||
-        (rc = ensure(c, s->scal, 8 * sizeof(uint64_t))) != WV_OK) {
+        (rc = ensure(c, s->res, s->pool * sizeof(wv_result))) != WV_OK) {
+        wv_server_destroy(s);
+        return rc;
+    }
+    if (hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) != hipSuccess) rc = WV_EHIP;
+    for (int k = 0; k < 2 && rc == WV_OK; k++) {
+        StepSet &ss = s->set[k];
+        if ((rc = ensure(c, ss.scal, 8 * sizeof(uint64_t))) != WV_OK) break;
+        if (hipHostMalloc((void **)&ss.err_host, sizeof(uint64_t), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreate(&ss.ev0) != hipSuccess || hipEventCreate(&ss.ev_sum) != hipSuccess ||
+            hipEventCreate(&ss.ev1) != hipSuccess)
+            rc = WV_EHIP;
+        else
+            *ss.err_host = 0;
+    }
+    if (rc != WV_OK) {
         wv_server_destroy(s);
         return rc;
     }
@@ -414,17 +489,27 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
 
 int wv_server_inject_fault(wv_server *s, int after_steps) {
     if (!s) return WV_EINVAL;
-    s->fault_after = after_steps < 0 ? -1 : (int)(s->steps + after_steps);
+    s->fault_after = after_steps < 0 ? -1 : (int64_t)(s->steps + after_steps);
     return WV_OK;
 }
 
 int wv_server_destroy(wv_server *s) {
     if (!s) return WV_OK;
     if (s->c) (void)hipStreamSynchronize(s->c->stream);
-    DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->tmp, &s->tasks, &s->target, &s->toff,
-                      &s->tpairs, &s->partials, &s->res, &s->scal, &s->coefs, &s->lhsmod, &s->tails};
+    if (s->aux) (void)hipStreamSynchronize(s->aux);
+    DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->tmp, &s->res, &s->coefs, &s->lhsmod};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
+    for (StepSet &ss : s->set) {
+        DevBuf *sb[] = {&ss.tasks, &ss.target, &ss.toff, &ss.tpairs, &ss.partials, &ss.tails, &ss.scal};
+        for (DevBuf *b : sb)
+            if (b->ptr) (void)hipFree(b->ptr);
+        if (ss.err_host) (void)hipHostFree(ss.err_host);
+        hipEvent_t evs[] = {ss.ev0, ss.ev_sum, ss.ev1};
+        for (hipEvent_t e : evs)
+            if (e) (void)hipEventDestroy(e);
+    }
+    if (s->aux) (void)hipStreamDestroy(s->aux);
     for (auto &kv : s->all) delete kv.second;
     delete s;
     return WV_OK;
@@ -439,7 +524,7 @@ int wv_server_submit_range(wv_server *s, uint64_t lo, uint64_t hi, uint64_t *id)
     std::vector<SegDesc> d;
     window_descs(lo, hi, d);
     std::vector<uint32_t> counts(d.size());
-    if (!d.empty()) WV_TRY(sieve_count(s->c, d.data(), d.size(), false, counts.data()));
+    if (!d.empty()) WV_TRY(sieve_count(s->c, d.data(), d.size(), false, counts.data(), s->aux));
     uint64_t n = 0;
     for (uint32_t k : counts) n += k;
     if (n > s->pool) return WV_EINVAL;
@@ -495,16 +580,15 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     if (!s) return WV_EINVAL;
     WV_TRY(check_device(s->c));
     // admit requests pending for kAdmitAgeS or more in arrival order, then the
-    // smallest first (a prime list by its length, a range by its expected prime
-    // count), arrival order among equals, within the per-step budget of sums;
-    // a request that does not fit in the pool yet does not block those behind it
-    auto size_of = [](const Request *r) -> double { return (double)r->n_primes; };
+    // smallest first (by number of primes), arrival order among equals,
+    // within the per-step budget of sums; a request that does not fit in the
+    // pool yet does not block those behind it
     const double t_old = now_s() - kAdmitAgeS;
     std::stable_sort(s->pending.begin(), s->pending.end(), [&](const Request *a, const Request *b) {
         const bool oa = a->t_submit <= t_old, ob = b->t_submit <= t_old;
         if (oa != ob) return oa;
         if (oa) return a->t_submit < b->t_submit;
-        return size_of(a) < size_of(b);
+        return a->n_primes < b->n_primes;
     });
     size_t admitted_sums = 0;
     std::deque<Request *> waiting;
@@ -526,13 +610,24 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
         else admitted_sums += (size_t)r->n * s->NS;
     }
     s->pending.swap(waiting);
-    int rc = s->active.empty() ? WV_OK : run_step(s);
+    // launch the next step, then wait for the older step in flight (or, when
+    // nothing new was launched, for the one still in flight)
+    StepSet &nx = s->set[s->next];
+    StepSet &older = s->set[1 - s->next];
+    int rc = WV_OK;
+    bool launched = false;
+    if (!nx.busy) rc = launch_step(s, nx, &launched);
     if (rc == WV_OK) {
-        s->fail_streak = 0;
-    } else {
+        if (launched) s->next = 1 - s->next;
+        if (older.busy) rc = complete_step(s, older);
+        else if (!launched && nx.busy) rc = complete_step(s, nx);
+    }
+    if (rc != WV_OK) {
         (void)hipGetLastError();
-        // the step's partial work is discarded: the active requests restart
-        // from their plans, or end with the error after repeated failures
+        // every step in flight is discarded: the active requests restart from
+        // their plans, or end with the error after repeated failures
+        (void)hipStreamSynchronize(s->c->stream);
+        s->set[0].busy = s->set[1].busy = false;
         if (++s->fail_streak >= kMaxFailedSteps) {
             for (Request *r : s->active) fail_request(s, r, rc);
             s->active.clear();
@@ -582,6 +677,10 @@ int wv_server_get_stats(const wv_server *s, wv_server_stats *out) {
     out->active = s->active.size();
     out->primes_done = s->primes_done;
     out->terms_done = s->terms_done;
+    out->terms_done_b = s->terms_done_b;
+    out->sum_s = s->sum_s;
+    out->block_k_b = (uint32_t)sum_variant_kb(s->c->variant);
+    out->block_k_e = (uint32_t)sum_variant_ke(s->c->variant);
     out->steps = s->steps;
     out->readmits = s->readmits;
     out->p50_ms = percentile(s->lat_ms, 0.50);

@@ -564,7 +564,8 @@ def test_batch_windows_seed0_full_batch():
     """The whole batched workload (64 seeded windows, 429,833 primes, about
     4.3e14 terms with the derived congruences) in one wv_search_windows call,
     as the bench runs it: every window's prime list has the oracle's count and
-    is ascending, and all 256 stored oracle residues (4 per window) match."""
+    is ascending, and all 254 stored oracle residues (the first, last and two
+    drawn primes of each window, fewer where they coincide) match."""
     from paper_2101_11157_amd import workloads
     g = golden_json("batch_seed0.json")
     wins = workloads.batch_windows(0, 64)
@@ -590,7 +591,7 @@ def test_batch_windows_seed0_full_batch():
         for r in w["rows"]:
             assert by_p[r["p"]] == (r["b"], r["e"]), r["p"]
             n_rows += 1
-    assert n_rows == 256
+    assert n_rows == sum(len(w["rows"]) for w in g["windows"]) == 254
 
 
 def test_window_1e11_whole_subwindow_two_table_sets():
@@ -722,21 +723,24 @@ def test_server_restart_after_failed_step(ctx):
 
 
 def test_server_repeated_failures_end_requests(ctx):
-    """Three failed steps in a row end the active requests with the error
-    (reported once by result, then forgotten) and free their pool slots: a
-    request submitted afterwards is served normally."""
+    """Three failed steps with none completed between them end the active
+    requests with the error (reported once by result, then forgotten) and free
+    their pool slots: a request submitted afterwards is served normally.  Steps
+    are pipelined, so a step's failure surfaces in the call that completes it."""
     say("case: server repeated failures")
     ps = oracle.primes(10 ** 9, 10 ** 9 + 300)
     with wv.Server(ctx, step_terms=1 << 28, max_primes=64) as srv:
         a = srv.submit_primes(ps[:40])
         raised = 0
-        for k in range(3):
-            srv.inject_fault(0)
+        for _ in range(20):
+            srv.inject_fault(0)                 # the next step to complete fails
             try:
                 srv.step()
             except wv.WvError as e:
                 assert e.status == wv.WV_EHIP
                 raised += 1
+                if raised == 3:
+                    break
         assert raised == 3
         with pytest.raises(wv.WvError) as ei:
             srv.result(a)
