@@ -185,7 +185,39 @@ CONFIGS = {
     "1e9": (10 ** 9, 10 ** 9 + 10 ** 7, 1 << 18),
     "1e5": (5, 10 ** 5, 10 ** 5),
 }
-EXTRA_CONFIGS = ("batch", "serve", "irregular")
+EXTRA_CONFIGS = ("batch", "serve", "irregular", "peak")
+
+PEAK_NAMES = ["v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mul_u32_u24", "v_add_u32", "v_lshl_add_u64",
+              "v_fma_f64", "v_add_co_u32", "v_addc_co_u32", "v_cndmask_b32", "v_cmp_gt_u32", "v_min_u32",
+              "v_mov_b32", "v_sub_u32"]
+
+
+def bench_peak(args):
+    """Instruction rates of the chip (libwvpeak.so): lane operations per second
+    of independent back-to-back VALU instructions of each class, and the f64
+    matrix rate over instruction shape, accumulator chains and waves per SIMD.
+    These are the measured ceilings behind the rooflines: the term-sum kernel
+    issues f64 adds/FMAs and, on the one-term path, 32-bit multiplies."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2101_11157_amd", "libwvpeak.so")
+    L = ctypes.CDLL(path)
+    n = L.wv_peak_count()
+    rates = (ctypes.c_double * n)()
+    rc = L.wv_peak_rates(0, rates)
+    if rc != 0:
+        print(f"bench.py: wv_peak_rates failed ({rc})", file=sys.stderr)
+        sys.exit(1)
+    valu = {PEAK_NAMES[k]: {"lane_ops_per_s": rates[k], "of_full_rate": rates[k] / PEAK_VALU} for k in range(n)}
+    cap = 64
+    rows = (ctypes.c_double * (4 * cap))()
+    L.wv_peak_mfma_f64_sweep.restype = ctypes.c_int
+    m = L.wv_peak_mfma_f64_sweep(0, rows, cap)
+    mfma = [{"instruction": "v_mfma_f64_16x16x4_f64" if rows[4 * i] == 16 else "v_mfma_f64_4x4x4_4b_f64",
+             "chains": int(rows[4 * i + 1]), "waves_per_simd": int(rows[4 * i + 2]),
+             "tflops": rows[4 * i + 3] / 1e12, "of_published_peak": rows[4 * i + 3] / PEAK_MFMA_F64}
+            for i in range(max(m, 0))]
+    print(json.dumps({"metric": "instruction rates (1 GPU)", "full_rate_valu_lane_ops_per_s": PEAK_VALU,
+                      "published_f64_matrix_flops": PEAK_MFMA_F64, "valu": valu, "mfma_f64": mfma}), flush=True)
 
 
 def use_tables(ctx, which):
@@ -388,6 +420,8 @@ def main():
         return bench_serve(args, wv)
     if args.config == "irregular":
         return bench_irregular(args, wv)
+    if args.config == "peak":
+        return bench_peak(args)
 
     lo0, hi0, wdef = CONFIGS[args.config]
     W = args.window or wdef

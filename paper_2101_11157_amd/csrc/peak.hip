@@ -1,6 +1,6 @@
 // peak.hip -- instruction-rate microbenchmarks for the rooflines of the
 // term-sum kernel and the matrix-core power sums (libwvpeak.so, C ABI:
-// wv_peak_rates, wv_peak_mfma_f64).
+// wv_peak_rates, wv_peak_mfma_f64, wv_peak_mfma_f64_sweep).
 //
 // Each kernel runs NCHAIN independent dependency chains of one VALU
 // instruction class per lane, so issue rate (not latency) bounds it.  The
@@ -95,6 +95,47 @@ __global__ void __launch_bounds__(256) k_mfma64(double *out, int iters) {
     out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// The same with a chosen number of accumulator chains and instruction shape:
+// SHAPE 16: v_mfma_f64_16x16x4_f64 (2048 flops, 4 doubles of accumulator per
+// lane); SHAPE 4: v_mfma_f64_4x4x4_4b_f64 (four 4 x 4 x 4 blocks, 512 flops,
+// one double per lane).
+template <int SHAPE, int NCH>
+__global__ void __launch_bounds__(256) k_mfma64_var(double *out, int iters) {
+    const double a = 1.0 + 1e-9 * threadIdx.x, b = 1.0 - 1e-9 * threadIdx.x;
+    double s = 0;
+    if constexpr (SHAPE == 16) {
+        v4d acc[NCH];
+        for (int c = 0; c < NCH; c++) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int c = 0; c < NCH; c++) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        }
+        for (int c = 0; c < NCH; c++) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    } else {
+        double acc[NCH];
+        for (int c = 0; c < NCH; c++) acc[c] = 0.0;
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int c = 0; c < NCH; c++) acc[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, acc[c], 0, 0, 0);
+        }
+        for (int c = 0; c < NCH; c++) s += acc[c];
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+typedef void (*mfn)(double *, int);
+
+struct MfmaVar {
+    int shape, chains;
+    mfn fn;
+};
+
+const MfmaVar kMfmaVars[] = {
+    {16, 2, k_mfma64_var<16, 2>}, {16, 4, k_mfma64_var<16, 4>},  {16, 8, k_mfma64_var<16, 8>},
+    {16, 16, k_mfma64_var<16, 16>}, {4, 4, k_mfma64_var<4, 4>},  {4, 8, k_mfma64_var<4, 8>},
+    {4, 16, k_mfma64_var<4, 16>},
+};
+
 }  // namespace
 
 extern "C" {
@@ -168,6 +209,50 @@ int wv_peak_mfma_f64(int dev, double *flops) {
     (void)hipEventDestroy(e1);
     (void)hipFree(buf);
     return rc;
+}
+
+// Sweep of the attained f64 matrix rate over instruction shape (16: 16x16x4,
+// 4: 4x4x4 with four blocks), independent accumulator chains per wave and
+// waves per SIMD (1, 2, 4, 8).  Writes up to cap rows of four doubles {shape,
+// chains, waves per SIMD, flops per second} to out and returns the number of
+// rows (negative on a HIP error).
+int wv_peak_mfma_f64_sweep(int dev, double *out, int cap) {
+    if (!out || cap < 0) return -1;
+    if (hipSetDevice(dev) != hipSuccess) return -6;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -6;
+    const int threads = 256;   // four waves: one per SIMD of a CU
+    const int iters = 4096;
+    const int wps[] = {1, 2, 4, 8};
+    double *buf = nullptr;
+    if (hipMalloc(&buf, (size_t)prop.multiProcessorCount * 8 * threads * sizeof(double)) != hipSuccess) return -5;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -6;
+    int n = 0, rc = 0;
+    for (const MfmaVar &v : kMfmaVars) {
+        for (int w : wps) {
+            if (n >= cap) break;
+            const int blocks = prop.multiProcessorCount * w;
+            hipLaunchKernelGGL(v.fn, dim3(blocks), dim3(threads), 0, 0, buf, 32);   // warm-up
+            (void)hipEventRecord(e0, 0);
+            hipLaunchKernelGGL(v.fn, dim3(blocks), dim3(threads), 0, 0, buf, iters);
+            (void)hipEventRecord(e1, 0);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = -6; break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double per = v.shape == 16 ? 2048.0 : 512.0;
+            out[4 * n + 0] = v.shape;
+            out[4 * n + 1] = v.chains;
+            out[4 * n + 2] = w;
+            out[4 * n + 3] = (double)blocks * (threads / 64) * iters * v.chains * per / (ms * 1e-3);
+            n++;
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    return rc ? rc : n;
 }
 
 }  // extern "C"
