@@ -241,9 +241,11 @@ int wv_range_stats(wv_ctx *ctx, uint64_t lo, uint64_t hi, uint32_t bins, uint64_
  * C_k(a,b,c) B_{2k} == sum S_{2k-1}(x, y) (Section 2, with C_k(a,b,c) =
  * (a^{p-2k} + b^{p-2k} - c^{p-2k} - 1) / (4k)) for the family (2, b, b+1)
  * over sum_{m <= b/2} (m/(b+1), m/b): b = 3, i.e. (1/4, 1/3), and, for the k
- * where its C_k vanishes mod p, b = 4, 5, ... up to 64; E_{2k} from eqnE1
- * (Section 5) with the sign read as (-1)^k.  The power sums of every exponent
- * run on the device: about p^2 / 6 terms per prime. */
+ * where its C_k vanishes mod p, b = 4, 5, ... up to 64; E_t (t = 2k) from
+ * eqnEMac2 (Section 4: (-1)^k' 4^(k'-1) (9^k' + 1) E_t == 2^t (S_t(0, 1/12)
+ * - S_t(5/12, 1/2)), k' = (p - 1 - t)/2) and, where 9^k' == -1 (mod p), from
+ * eqnE1 with the sign read as (-1)^k'.  The power sums of every exponent run
+ * on the device: about p^2 / 8 terms per prime. */
 #define WV_IRR_P_MAX (1ULL << 27)
 
 typedef struct {

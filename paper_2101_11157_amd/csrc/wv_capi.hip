@@ -143,7 +143,7 @@ int prepare(wv_ctx *c, const BatchShape &sh) {
     WV_TRY(ensure(c, c->coefs, nseg * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->lhsmod, 2 * n * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->tails, nseg * sizeof(uint32_t)));
-    WV_TRY(ensure(c, c->tail_hist, 2 * kTailBuckets * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->tail_hist, 2 * kTailClasses * sizeof(uint64_t)));
     return WV_OK;
 }
 
@@ -176,8 +176,8 @@ int enqueue_plan(wv_ctx *c, const BatchBufs &b, const uint64_t *d_primes, const 
     WV_HIP(launch_pick_chunk(st, toff + sh.nseg, sh.nseg, chunk_cfg, sum_lanes(c), sh.cap, scal + kScalLayout));
     WV_HIP(launch_copy_u64(st, toff + sh.nseg, scal + kScalTerms, 1));
     WV_HIP(launch_copy_u64(st, toff + (uint64_t)sh.n * sh.nB, scal + kScalTermsB, 1));
-    WV_HIP(launch_chunk_layout(st, b.terms, sh.nseg, scal + kScalLayout, b.cnt, toff, b.tiles, b.tail_hist, b.tails,
-                               scal + kScalChunks));
+    WV_HIP(launch_chunk_layout(st, b.terms, sh.nseg, (uint64_t)sh.n * sh.nB, scal + kScalLayout, b.cnt, toff, b.tiles,
+                               b.tail_hist, b.tails, scal + kScalChunks));
     return WV_OK;
 }
 

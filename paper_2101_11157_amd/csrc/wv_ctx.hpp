@@ -71,7 +71,7 @@ struct BatchBufs {
     uint64_t *coefs;            // nseg
     uint64_t *lhsmod;           // 2 n
     uint32_t *tails;            // nseg
-    unsigned long long *tail_hist;   // 2 kTailBuckets
+    unsigned long long *tail_hist;   // 2 kTailClasses
 };
 
 struct BatchShape {

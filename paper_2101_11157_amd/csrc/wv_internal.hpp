@@ -23,11 +23,19 @@ constexpr int kScanTile = 1024;                // elements per scan workgroup
 constexpr uint64_t kChunkSetup = 4096;         // set-up work of one chunk, in terms
 constexpr uint64_t kChunkMin = 1ull << 12;
 constexpr uint64_t kChunkMax = 1ull << 19;
-constexpr int kTailBuckets = 64;   // length classes of the tail chunks
+constexpr int kTailBuckets = 64;                 // length classes of the tail chunks
+constexpr int kTailClasses = 2 * kTailBuckets;   // (length class, side)
 
 // Length class of a tail of rem in [1, C) terms; class 0 holds the longest.
 __host__ __device__ inline uint32_t tail_bucket(uint64_t rem, uint64_t C) {
     return kTailBuckets - 1 - (uint32_t)((rem * kTailBuckets) / C);
+}
+
+// Order of a tail among all tails: by length class, longest first, and
+// within a class the s^-3 sums before the s^-2 sums, so that the 64 tails a
+// wave takes run one code path (a wave holding both sides runs both loops).
+__host__ __device__ inline uint32_t tail_class(uint64_t rem, uint64_t C, uint32_t deg) {
+    return 2 * tail_bucket(rem, C) + (deg == 3 ? 0u : 1u);
 }
 
 // Automatic chunk size for T terms: sqrt(2 S T / w), clamped, where w counts
@@ -111,9 +119,10 @@ hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64
 // Chunk layout (layout = {C, full chunks, tails}; layout[0] set by the pick):
 // cnt[i] = full chunks of sum i, off = their exclusive prefix (off[nseg] =
 // full chunks), tails[0..) = the sums whose length C does not divide, longest
-// tail class first; *total_chunks = full chunks + tails.  hist holds
-// 2 kTailBuckets counters, scan_tiles as for launch_scan.
-hipError_t launch_chunk_layout(hipStream_t st, const uint64_t *terms, uint64_t nseg, uint64_t *layout,
+// tail class first (tail_class: slots below nb_slots are s^-3 sums, the rest
+// s^-2); *total_chunks = full chunks + tails.  hist holds 2 kTailClasses
+// counters, scan_tiles as for launch_scan.
+hipError_t launch_chunk_layout(hipStream_t st, const uint64_t *terms, uint64_t nseg, uint64_t nb_slots, uint64_t *layout,
                                uint64_t *cnt, uint64_t *off, uint64_t *scan_tiles, unsigned long long *hist,
                                uint32_t *tails, uint64_t *total_chunks);
 hipError_t launch_set_u64(hipStream_t st, uint64_t *dst, int n, uint64_t value);

@@ -6,8 +6,10 @@
 //     the family (2, b, b+1) over sum_{m <= b/2} (m/(b+1), m/b): b = 3, i.e.
 //     (1/4, 1/3), for every k, then b = 4, 5, ... where C_k(2,3,4) vanishes),
 //   C_k(a,b,c) = (a^{p-2k} + b^{p-2k} - c^{p-2k} - 1) / (4k),
-//   (-1)^k 4^{2k-1} E_{p-1-2k} == S_{p-1-2k}(0, 1/4)   (mod p)  (eqnE1, sign
-//     read as (-1)^k),
+//   (-1)^k 4^{k-1} (9^k + 1) E_t == 2^t (S_t(0, 1/12) - S_t(5/12, 1/2))
+//     (mod p), t = p - 1 - 2k  (eqnEMac2, Section 4: McIntosh's congruence
+//     with one subdivision), and where 9^k == -1 (mod p)
+//   (-1)^k 4^{2k-1} E_t == S_t(0, 1/4)   (mod p)  (eqnE1, sign read as (-1)^k),
 //
 // with S_l(x, y) = sum_{xp < s < yp} s^l (eqnDefnS) for positive l.  Every k
 // needs its own exponent, so the power sums of each range are computed for all
@@ -27,11 +29,12 @@
 namespace wv {
 namespace {
 
-struct IrrTask {          // sum_{lo <= s < hi} s^t for t = t0, t0 + 2, ..., t0 + 2 (nt - 1)
+struct IrrTask {          // +- sum_{lo <= s < hi} s^t for t = t0, t0 + 2, ..., t0 + 2 (nt - 1)
     uint64_t p, lo, hi;
-    uint64_t out;         // index in V of the first exponent's total
+    uint64_t out;         // index in V of the first exponent's total (tasks may share it)
     uint32_t t0, nt;
-    uint32_t ct, pad;     // matrix-core path: exponents per row = 16 ct (1 <= ct <= 8)
+    uint32_t ct;          // matrix-core path: exponents per row = 16 ct (1 <= ct <= 8)
+    uint32_t neg;         // 1: the sums enter V negated
 };
 
 struct IrrPrime {         // one prime of a batch
@@ -42,8 +45,8 @@ struct IrrPrime {         // one prime of a batch
     uint32_t pad;
 };
 
-struct IrrFix {           // a k whose first congruence degenerates (C_k == 0 mod p)
-    uint32_t prime, k;
+struct IrrFix {           // an index whose first congruence degenerates (its left side is 0 mod p)
+    uint32_t prime, k;    // Bernoulli side: B_{2k}; Euler side: E_{2k}
 };
 
 constexpr int kIrrLaneS = 16;                        // s per lane
@@ -154,7 +157,7 @@ WV_UNROLL
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (half == 0 && b0 + row < e_end) atomicAdd(&V[T.out + b0 + row], t);
+        if (half == 0 && b0 + row < e_end) atomicAdd(&V[T.out + b0 + row], T.neg ? -t : t);
     }
 }
 
@@ -303,7 +306,10 @@ WV_UNROLL
         for (int r = 0; r < 4; r++) {
             const uint32_t m = m0 + 16 * wave + (lane >> 4) + 4 * r;
             const uint64_t e = (uint64_t)N * m + 16 * n + (lane & 15);
-            if (m < M && e < T.nt) atomicAdd(&V[T.out + e], f_reduce(acc[n][r], f));
+            if (m < M && e < T.nt) {
+                const double v = f_reduce(acc[n][r], f);
+                atomicAdd(&V[T.out + e], T.neg ? -v : v);
+            }
         }
     }
 }
@@ -347,12 +353,15 @@ __global__ void __launch_bounds__(kMmaThreads) k_irr_mma(const IrrTask *__restri
 // ---------------------------------------------------------------------------
 
 // One thread per (prime, k): b = B_{2k} mod p from (2,3,4) unless its C_k
-// vanishes (then queued for k_irr_fix), e = E_{2k} mod p from eqnE1.  Zero
-// residues are appended to pairs as (p, 2k, kind).
+// vanishes (then queued for k_irr_fix), e = E_{2k} mod p from eqnEMac2 unless
+// its left side vanishes (then queued for k_irr_fix_e).  Counters: [0] queued
+// Bernoulli indices, [1] pairs, [2] unresolved, [3] queued Euler indices.
+// Zero residues are appended to pairs as (p, 2k, kind).
 __global__ void __launch_bounds__(256) k_irr_final(const IrrPrime *__restrict__ pr, const uint64_t *__restrict__ off,
                                                    uint32_t np, const double *__restrict__ V,
                                                    uint64_t *__restrict__ b_out, uint64_t *__restrict__ e_out,
-                                                   IrrFix *__restrict__ fix, unsigned long long *__restrict__ counts,
+                                                   IrrFix *__restrict__ fix, IrrFix *__restrict__ fix_e,
+                                                   unsigned long long *__restrict__ counts,
                                                    wv_irr_pair *__restrict__ pairs, uint64_t pair_cap) {
     const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= off[np]) return;
@@ -380,13 +389,57 @@ __global__ void __launch_bounds__(256) k_irr_final(const IrrPrime *__restrict__ 
         const unsigned long long at = atomicAdd(&counts[0], 1ull);
         fix[at] = IrrFix{i, (uint32_t)k};
     }
-    // Euler side: even exponent t = 2k; eqnE1 with k' = (p - 1 - t) / 2
+    // Euler side: even exponent t = 2k, left-side index k' = (p - 1 - t) / 2.
+    // eqnEMac2: (-1)^k' 4^(k'-1) (9^k' + 1) E_t == 2^t T, T = S_t(0, 1/12) -
+    // S_t(5/12, 1/2) (the totals); by Fermat 4^(k'-1) = 2^(-2-t) and 9^k' =
+    // 3^(-t), so E_t = (-1)^k' 4^(t+1) 3^t T / (3^t + 1), queued for eqnE1
+    // where 3^t == -1.
     const uint64_t t = 2 * k;
     const uint64_t kk = (p - 1 - t) / 2;
-    const double pow4 = f_mulmod(4.0, fpow_e(16.0, k, f), f);   // 4^(t+1) = 4 16^k
-    uint64_t e = f_canon(f_mulmod(f_canon(V[P.ve + k - 1], f), pow4, f), f);
+    const double pow3 = fpow_e(3.0, t, f);
+    const uint64_t w = f_canon(pow3 + 1.0, f);
+    if (w) {
+        const double pow4 = f_mulmod(4.0, fpow_e(16.0, k, f), f);   // 4^(t+1) = 4 16^k
+        const double num = f_mulmod(f_mulmod((double)f_canon(V[P.ve + k - 1], f), pow4, f), pow3, f);
+        uint64_t e = f_canon(f_mulmod(num, (double)u_pow(w, p - 2, f), f), f);
+        if ((kk & 1) && e) e = p - e;
+        if (e_out) e_out[P.res + k - 1] = e;
+        if (e == 0) {
+            const unsigned long long at = atomicAdd(&counts[1], 1ull);
+            if (at < pair_cap) pairs[at] = wv_irr_pair{p, (uint32_t)t, 2u};
+        }
+    } else {
+        const unsigned long long at = atomicAdd(&counts[3], 1ull);
+        fix_e[at] = IrrFix{i, (uint32_t)k};
+    }
+}
+
+// One wave per queued Euler index: eqnE1, (-1)^k' 4^(2k'-1) E_t == S_t(0,
+// 1/4) with t = 2k and k' = (p - 1 - t) / 2, the sum evaluated directly (one
+// power per s); 4^-(2k'-1) = 4^(t+1) by Fermat.
+__global__ void __launch_bounds__(256) k_irr_fix_e(const IrrPrime *__restrict__ pr, const IrrFix *__restrict__ fix,
+                                                   const unsigned long long *__restrict__ nfix_ptr,
+                                                   uint64_t *__restrict__ e_out, unsigned long long *__restrict__ counts,
+                                                   wv_irr_pair *__restrict__ pairs, uint64_t pair_cap) {
+    const uint64_t w = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= *nfix_ptr) return;
+    const IrrFix F = fix[w];
+    const IrrPrime P = pr[F.prime];
+    const uint64_t p = P.p, t = 2 * (uint64_t)F.k, kk = (p - 1 - t) / 2;
+    Fmod f;
+    f.p = (double)p;
+    f.pinv = 1.0 / f.p;
+    uint64_t lo, hi;
+    open_range(p, 0, 1, 1, 4, lo, hi);
+    double acc = 0.0;   // exact: fewer than p terms below 0.574 p in magnitude
+    for (uint64_t s = lo + lane; s < hi; s += 64) acc += fpow_e((double)s, t, f);
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane != 0) return;
+    const double pow4 = f_mulmod(4.0, fpow_e(16.0, F.k, f), f);
+    uint64_t e = f_canon(f_mulmod((double)f_canon(f_reduce(acc, f), f), pow4, f), f);
     if ((kk & 1) && e) e = p - e;
-    if (e_out) e_out[P.res + k - 1] = e;
+    if (e_out) e_out[P.res + F.k - 1] = e;
     if (e == 0) {
         const unsigned long long at = atomicAdd(&counts[1], 1ull);
         if (at < pair_cap) pairs[at] = wv_irr_pair{p, (uint32_t)t, 2u};
@@ -488,11 +541,17 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
         IrrPrime P{p, vn, vn + nt, res, nt, 0};
         uint64_t lo, hi;
         open_range(p, 1, 4, 1, 3, lo, hi);   // Bernoulli: (1/4, 1/3), odd exponents from 1
-        tasks.push_back(IrrTask{p, lo, hi, vn, 1, nt, cols_of(nt), 0});
+        tasks.push_back(IrrTask{p, lo, hi, vn, 1, nt, cols_of(nt), 0});   // Bernoulli: +S(1/4, 1/3)
         units.push_back(units.back() + units_of(lo, hi, nt));
         work += (double)(hi - lo) * nt;
-        open_range(p, 0, 1, 1, 4, lo, hi);   // Euler: (0, 1/4), even exponents from 2
+        // Euler (eqnEMac2): S(0, 1/12) - S(5/12, 1/2) into the same totals,
+        // even exponents from 2
+        open_range(p, 0, 1, 1, 12, lo, hi);
         tasks.push_back(IrrTask{p, lo, hi, vn + nt, 2, nt, cols_of(nt), 0});
+        units.push_back(units.back() + units_of(lo, hi, nt));
+        work += (double)(hi - lo) * nt;
+        open_range(p, 5, 12, 1, 2, lo, hi);
+        tasks.push_back(IrrTask{p, lo, hi, vn + nt, 2, nt, cols_of(nt), 1});
         units.push_back(units.back() + units_of(lo, hi, nt));
         work += (double)(hi - lo) * nt;
         vn += 2 * (uint64_t)nt;
@@ -507,7 +566,7 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
     WV_TRY(ensure(c, c->irr_primes, prs.size() * sizeof(IrrPrime)));
     WV_TRY(ensure(c, c->irr_roff, roff.size() * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->irr_v, std::max<uint64_t>(vn, 1) * sizeof(double)));
-    WV_TRY(ensure(c, c->irr_fix, std::max<uint64_t>(res, 1) * sizeof(IrrFix)));
+    WV_TRY(ensure(c, c->irr_fix, 2 * std::max<uint64_t>(res, 1) * sizeof(IrrFix)));   // both sides' queues
     WV_TRY(ensure(c, c->irr_counts, 4 * sizeof(unsigned long long)));
     WV_HIP(hipMemcpyAsync(c->irr_tasks.ptr, tasks.data(), tasks.size() * sizeof(IrrTask), hipMemcpyHostToDevice, st));
     WV_HIP(hipMemcpyAsync(c->irr_units.ptr, units.data(), units.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
@@ -527,17 +586,23 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
     WV_HIP(hipGetLastError());
     WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
     auto *counts = as<unsigned long long>(c->irr_counts);
+    IrrFix *fix_b = as<IrrFix>(c->irr_fix), *fix_e = fix_b + std::max<uint64_t>(res, 1);
     hipLaunchKernelGGL(k_irr_final, dim3(grid_for(res, 256)), dim3(256), 0, st, as<IrrPrime>(c->irr_primes),
-                       as<uint64_t>(c->irr_roff), np, as<double>(c->irr_v), d_b, d_e, as<IrrFix>(c->irr_fix), counts,
+                       as<uint64_t>(c->irr_roff), np, as<double>(c->irr_v), d_b, d_e, fix_b, fix_e, counts,
                        as<wv_irr_pair>(c->irr_pairs), pair_cap);
     WV_HIP(hipGetLastError());
     unsigned long long host[4];
     WV_HIP(hipMemcpyAsync(host, counts, sizeof(host), hipMemcpyDeviceToHost, st));
     WV_HIP(hipStreamSynchronize(st));
-    if (host[0]) {
-        hipLaunchKernelGGL(k_irr_fix, dim3(grid_for(host[0] * 64, 256)), dim3(256), 0, st,
-                           as<IrrPrime>(c->irr_primes), as<IrrFix>(c->irr_fix), counts, d_b, counts,
-                           as<wv_irr_pair>(c->irr_pairs), pair_cap);
+    if (host[0] || host[3]) {
+        if (host[0])
+            hipLaunchKernelGGL(k_irr_fix, dim3(grid_for(host[0] * 64, 256)), dim3(256), 0, st,
+                               as<IrrPrime>(c->irr_primes), fix_b, counts, d_b, counts,
+                               as<wv_irr_pair>(c->irr_pairs), pair_cap);
+        if (host[3])
+            hipLaunchKernelGGL(k_irr_fix_e, dim3(grid_for(host[3] * 64, 256)), dim3(256), 0, st,
+                               as<IrrPrime>(c->irr_primes), fix_e, counts + 3, d_e, counts,
+                               as<wv_irr_pair>(c->irr_pairs), pair_cap);
         WV_HIP(hipGetLastError());
         WV_HIP(hipMemcpyAsync(host, counts, sizeof(host), hipMemcpyDeviceToHost, st));
         WV_HIP(hipStreamSynchronize(st));
@@ -560,7 +625,8 @@ int irr_for_batches(const std::vector<uint64_t> &ps, F &&run) {
         while (i < ps.size()) {
             const uint64_t p = ps[i];
             const uint64_t v = p - 3;   // two totals per k
-            const uint64_t u = 2 * (p / 4 / kIrrWaveS + 2) * ((p / 2) / kIrrUnitT + 1);
+            // three tasks of at most p/12 s each (a bound for either kernel's units)
+            const uint64_t u = 3 * (p / 12 / kIrrWaveS + 2) * ((p / 2) / kIrrUnitT + 1);
             if (!b.empty() && (vn + v > kIrrMaxV || units + u > kIrrMaxUnits)) break;
             b.push_back(p);
             vn += v;

@@ -430,14 +430,15 @@ __global__ void k_pick_chunk(const uint64_t *__restrict__ total_terms, uint64_t 
 // Chunk layout of a batch: every sum of len terms gets len / C full chunks of
 // exactly C terms, numbered sum by sum, and, when C does not divide len, one
 // tail chunk of len % C terms.  The tails follow all full chunks, grouped into
-// kTailBuckets classes of length, longest first, so that the 64 chunks a wave
-// takes have (nearly) equal lengths and the shortest work comes last.
-// cnt[i] = full chunks of sum i; tail lengths counted per class into hist.
+// kTailClasses classes (tail_class: length, longest first, then side), so that
+// the 64 chunks a wave takes have (nearly) equal lengths and one side, and the
+// shortest work comes last.  Slots below nb_slots are s^-3 sums.
+// cnt[i] = full chunks of sum i; tail counts per class into hist.
 __global__ void __launch_bounds__(256) k_chunk_split(const uint64_t *__restrict__ terms, uint64_t nseg,
-                                                     const uint64_t *__restrict__ layout, uint64_t *__restrict__ cnt,
-                                                     unsigned long long *__restrict__ hist) {
-    __shared__ uint32_t local[kTailBuckets];
-    if (threadIdx.x < kTailBuckets) local[threadIdx.x] = 0;
+                                                     uint64_t nb_slots, const uint64_t *__restrict__ layout,
+                                                     uint64_t *__restrict__ cnt, unsigned long long *__restrict__ hist) {
+    __shared__ uint32_t local[kTailClasses];
+    if (threadIdx.x < kTailClasses) local[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t C = layout[0];
@@ -445,10 +446,10 @@ __global__ void __launch_bounds__(256) k_chunk_split(const uint64_t *__restrict_
         const uint64_t t = terms[i];
         cnt[i] = t / C;
         const uint64_t rem = t % C;
-        if (rem) atomicAdd(&local[tail_bucket(rem, C)], 1u);
+        if (rem) atomicAdd(&local[tail_class(rem, C, i < nb_slots ? 3u : 2u)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kTailBuckets && local[threadIdx.x])
+    if (threadIdx.x < kTailClasses && local[threadIdx.x])
         atomicAdd(&hist[threadIdx.x], (unsigned long long)local[threadIdx.x]);
 }
 
@@ -457,7 +458,7 @@ __global__ void __launch_bounds__(256) k_chunk_split(const uint64_t *__restrict_
 __global__ void k_tail_base(const unsigned long long *__restrict__ hist, unsigned long long *__restrict__ cursor,
                             uint64_t *__restrict__ layout, uint64_t *__restrict__ total) {
     uint64_t acc = 0;
-    for (int b = 0; b < kTailBuckets; b++) {
+    for (int b = 0; b < kTailClasses; b++) {
         cursor[b] = acc;
         acc += hist[b];
     }
@@ -467,12 +468,12 @@ __global__ void k_tail_base(const unsigned long long *__restrict__ hist, unsigne
 
 // tails[pos] = i for each sum with a tail, pos within its class's range.
 __global__ void __launch_bounds__(256) k_tail_place(const uint64_t *__restrict__ terms, uint64_t nseg,
-                                                    const uint64_t *__restrict__ layout,
+                                                    uint64_t nb_slots, const uint64_t *__restrict__ layout,
                                                     unsigned long long *__restrict__ cursor,
                                                     uint32_t *__restrict__ tails) {
-    __shared__ uint32_t local[kTailBuckets];
-    __shared__ unsigned long long base[kTailBuckets];
-    if (threadIdx.x < kTailBuckets) local[threadIdx.x] = 0;
+    __shared__ uint32_t local[kTailClasses];
+    __shared__ unsigned long long base[kTailClasses];
+    if (threadIdx.x < kTailClasses) local[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t C = layout[0];
@@ -482,12 +483,12 @@ __global__ void __launch_bounds__(256) k_tail_place(const uint64_t *__restrict__
         const uint64_t rem = terms[i] % C;
         if (rem) {
             has = true;
-            b = tail_bucket(rem, C);
+            b = tail_class(rem, C, i < nb_slots ? 3u : 2u);
             rank = atomicAdd(&local[b], 1u);
         }
     }
     __syncthreads();
-    if (threadIdx.x < kTailBuckets && local[threadIdx.x])
+    if (threadIdx.x < kTailClasses && local[threadIdx.x])
         base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], (unsigned long long)local[threadIdx.x]);
     __syncthreads();
     if (has) tails[base[b] + rank] = (uint32_t)i;
@@ -680,18 +681,28 @@ __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs,
 }
 
 // L^-1 sum_i coef_i c1_i / c0_i mod p for one congruence of n sums; pairs at
-// sp[first + j], coefficients mod p at coef[first + j], L mod p in lhs.
-// Running fraction N/D in Montgomery values.
+// sp[first + j], coefficients mod p at coef[first + j], L mod p in lhs.  The
+// 64 lanes of the calling wave each fold every 64th sum into a running
+// fraction N/D (Montgomery values; any common factor of N and D is
+// harmless), the fractions are added across the wave by a butterfly
+// (N1/D1 + N2/D2 = (N1 D2 + N2 D1) / (D1 D2)), and every lane ends with the
+// residue.  The whole wave must be active.
 __device__ uint64_t combine_residue(int n, const Pair *__restrict__ sp, const uint64_t *__restrict__ coef,
-                                    size_t first, uint64_t lhs, const Mont &m, uint64_t r2, uint64_t one) {
+                                    size_t first, uint64_t lhs, const Mont &m, uint64_t r2, uint64_t one, int lane) {
     const uint64_t p = m.p;
     uint64_t N = 0, D = one;
-    for (int j = 0; j < n; j++) {
+    for (int j = lane; j < n; j += 64) {
         const Pair q = sp[first + j];
         const uint64_t cR = to_mont(coef[first + j], r2, m);
         const uint64_t num = mmul(mmul(cR, q.c1, m), D, m);       // coef c1 D / R
         N = mmul(N, q.c0, m) + num;                                 // (N c0 + coef c1 D) / R
         D = mmul(D, q.c0, m);                                       // D c0 / R
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t N2 = shfl_xor_u64(N, off), D2 = shfl_xor_u64(D, off);
+        N = mmul(N, D2, m) + mmul(N2, D, m);
+        D = mmul(D, D2, m);
     }
     const uint64_t LR = to_mont(lhs, r2, m);
     const uint64_t X = mmul(D, LR, m);                              // D L
@@ -731,14 +742,16 @@ __global__ void __launch_bounds__(256) k_sum_values(const SegRec *__restrict__ s
     out[j] = P.ok ? red1(mmul(q.c1, inv, m), P.p) : 0;
 }
 
-// A prime that the plan rejected, or every prime of a batch whose term sums
-// reported an error (*err != 0; err may be null), gets flags = 0xFFFFFFFF.
+// One wave per prime.  A prime that the plan rejected, or every prime of a
+// batch whose term sums reported an error (*err != 0; err may be null), gets
+// flags = 0xFFFFFFFF.
 __global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec *__restrict__ pr,
                                                   const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
                                                   const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
                                                   wv_result *__restrict__ out, const unsigned long long *__restrict__ err) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const uint32_t i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;   // whole wave
     const PrimeRec P = pr[i];
     wv_result r;
     r.reserved = 0;
@@ -747,16 +760,16 @@ __global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec 
         r.b = 0;
         r.e = 0;
         r.flags = 0xFFFFFFFFu;
-        out[i] = r;
+        if (lane == 0) out[i] = r;
         return;
     }
     const Mont m = mont_of(P);
     r.p = P.p;
-    r.b = combine_residue(ts.head[P.tb].n, sp, coefs, (size_t)i * nB, lhsmod[2 * (size_t)i], m, P.r2, P.one);
+    r.b = combine_residue(ts.head[P.tb].n, sp, coefs, (size_t)i * nB, lhsmod[2 * (size_t)i], m, P.r2, P.one, lane);
     r.e = combine_residue(ts.head[P.te].n, sp, coefs, (size_t)n * nB + (size_t)i * nE, lhsmod[2 * (size_t)i + 1], m,
-                          P.r2, P.one);
+                          P.r2, P.one, lane);
     r.flags = (r.b == 0 ? WV_FLAG_WOLSTENHOLME : 0u) | (r.e == 0 ? WV_FLAG_VANDIVER : 0u);
-    out[i] = r;
+    if (lane == 0) out[i] = r;
 }
 
 
@@ -815,21 +828,21 @@ hipError_t launch_pick_chunk(hipStream_t st, const uint64_t *total_terms, uint64
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_layout(hipStream_t st, const uint64_t *terms, uint64_t nseg, uint64_t *layout,
+hipError_t launch_chunk_layout(hipStream_t st, const uint64_t *terms, uint64_t nseg, uint64_t nb_slots, uint64_t *layout,
                                uint64_t *cnt, uint64_t *off, uint64_t *scan_tiles, unsigned long long *hist,
                                uint32_t *tails, uint64_t *total_chunks) {
     if (too_many(nseg)) return hipErrorInvalidConfiguration;
-    unsigned long long *cursor = hist + kTailBuckets;
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(2 * kTailBuckets), 0, st, (uint64_t *)hist, 2 * kTailBuckets,
+    unsigned long long *cursor = hist + kTailClasses;
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(2 * kTailClasses), 0, st, (uint64_t *)hist, 2 * kTailClasses,
                        (uint64_t)0);
-    hipLaunchKernelGGL(k_chunk_split, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg,
+    hipLaunchKernelGGL(k_chunk_split, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg, nb_slots,
                        (const uint64_t *)layout, cnt, hist);
     const hipError_t e = launch_scan(st, cnt, nseg, off, scan_tiles);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, st, (const uint64_t *)(off + nseg), layout + 1, 1);
     hipLaunchKernelGGL(k_tail_base, dim3(1), dim3(1), 0, st, (const unsigned long long *)hist, cursor, layout,
                        total_chunks);
-    hipLaunchKernelGGL(k_tail_place, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg,
+    hipLaunchKernelGGL(k_tail_place, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg, nb_slots,
                        (const uint64_t *)layout, cursor, tails);
     return hipGetLastError();
 }
@@ -871,8 +884,9 @@ hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off
 hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *sp, const uint64_t *coefs,
                            const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out,
                            const unsigned long long *err) {
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, ts, pr, sp, coefs, lhsmod, n, nB, nE,
-                       out, err);
+    if (too_many((uint64_t)n * 64)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for((uint64_t)n * 64, 256)), dim3(256), 0, st, ts, pr, sp, coefs, lhsmod,
+                       n, nB, nE, out, err);
     return hipGetLastError();
 }
 

@@ -330,15 +330,16 @@ int launch_step(wv_server *s, StepSet &ss, bool *launched) {
         if (bern) terms_b += t.t;
     }
     // tail chunks (tasks whose length C does not divide) by length class,
-    // longest first (counting sort, as the batch plan does on the device)
-    std::vector<uint32_t> cls(nt, kTailBuckets);
-    uint64_t first[kTailBuckets + 1] = {};
+    // longest first, each class's s^-3 tasks before its s^-2 ones (counting
+    // sort, as the batch plan does on the device)
+    std::vector<uint32_t> cls(nt, kTailClasses);
+    uint64_t first[kTailClasses + 1] = {};
     for (size_t j = 0; j < nt; j++)
-        if (const uint64_t rem = tasks[j].t % C) first[(cls[j] = tail_bucket(rem, C)) + 1]++;
-    for (int b = 0; b < kTailBuckets; b++) first[b + 1] += first[b];
-    ss.tails_h.resize(first[kTailBuckets]);
+        if (const uint64_t rem = tasks[j].t % C) first[(cls[j] = tail_class(rem, C, ss.recs[j].deg)) + 1]++;
+    for (int b = 0; b < kTailClasses; b++) first[b + 1] += first[b];
+    ss.tails_h.resize(first[kTailClasses]);
     for (size_t j = 0; j < nt; j++)
-        if (cls[j] < (uint32_t)kTailBuckets) ss.tails_h[first[cls[j]]++] = (uint32_t)j;
+        if (cls[j] < (uint32_t)kTailClasses) ss.tails_h[first[cls[j]]++] = (uint32_t)j;
     const uint64_t chunks = ss.off[nt];
     WV_TRY(ensure(c, ss.tasks, nt * sizeof(SegRec)));
     WV_TRY(ensure(c, ss.target, nt * sizeof(uint32_t)));

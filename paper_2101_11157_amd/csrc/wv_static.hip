@@ -35,7 +35,7 @@ constexpr size_t kOffCoefs = align256(kOffSegPairs + WV_STATIC_MAX_SLOTS * sizeo
 constexpr size_t kOffLhs = align256(kOffCoefs + WV_STATIC_MAX_SLOTS * sizeof(uint64_t));
 constexpr size_t kOffTails = align256(kOffLhs + 2 * WV_STATIC_MAX_PRIMES * sizeof(uint64_t));
 constexpr size_t kOffHist = align256(kOffTails + WV_STATIC_MAX_SLOTS * sizeof(uint32_t));
-constexpr size_t kScratchBytes = align256(kOffHist + 2 * kTailBuckets * sizeof(uint64_t));
+constexpr size_t kScratchBytes = align256(kOffHist + 2 * kTailClasses * sizeof(uint64_t));
 static_assert(kScratchBytes <= WV_STATIC_SCRATCH_BYTES, "scratch layout exceeds the documented size");
 static_assert(WV_STATIC_MAX_CHUNKS >= 2 * WV_STATIC_MAX_SLOTS, "partial pairs must exceed twice the slots");
 

@@ -188,3 +188,195 @@ def test_greedy_euler_search_matches_section_4():
     (about 4 minutes)."""
     _, best, _ = D.greedy(D.Congruence.start("EMac2"), D=8, rounds=100)
     assert best.n_sums() == 438 and best.cost() < 1 / Q(304, 10)
+
+
+# ---------------------------------------------------------------------------
+# congruences for every index (coefficients sum_n m_n n^t, Sections 2 and 4)
+# ---------------------------------------------------------------------------
+
+GENERAL_SIZES = {   # (sums, cost) stated in Sections 2.1 and 4 / Table 1
+    "B2": (2, Q(1, 15)), "B6": (6, Q(5, 96)), "B9": (9, Q(1, 20)), "B16": (16, Q(1, 24)), "B22": (22, Q(3, 80)),
+    "B30": (30, Q(227, 6480)), "E3": (3, Q(3, 16)), "E5": (5, Q(9, 64)), "E9": (9, Q(43, 384)),
+    "E16": (16, Q(205, 2304)), "E24": (24, Q(115, 1536)), "E33": (33, Q(27, 512)),
+}
+
+
+def poly(*pairs):
+    return D.Poly({n: m for n, m in pairs})
+
+
+# eqnB9 and eqnE9 as printed in Sections 2.1 and 4 (t = 2k - 1, resp. p - 1 - 2k)
+PRINTED_B9 = [
+    (poly((3, 1), (6, 1)), Q(1, 18), Q(11, 180)),
+    (poly((3, 1), (6, 1), (10, -1)), Q(11, 180), Q(1, 15)),
+    (poly((6, -1), (10, 1), (12, -1)), Q(2, 15), Q(5, 36)),
+    (poly((6, 1), (12, 1)), Q(7, 36), Q(1, 5)),
+    (poly((10, -1)), Q(47, 180), Q(4, 15)),
+    (poly((2, -1), (6, -1), (12, -1)), Q(3, 10), Q(11, 36)),
+    (poly((10, 1)), Q(1, 3), Q(61, 180)),
+    (poly((6, 1), (12, 1)), Q(13, 36), Q(11, 30)),
+    (poly((10, -1)), Q(83, 180), Q(7, 15)),
+]
+PRINTED_E9 = [
+    (poly((32, 1)), Q(0), Q(1, 128)),
+    (poly((6, 1)), Q(1, 8), Q(7, 48)),
+    (poly((6, 1)), Q(3, 16), Q(5, 24)),
+    (poly((2, 1), (4, 1)), Q(7, 16), Q(11, 24)),
+    (poly((2, 1), (4, 1), (6, 1)), Q(11, 24), Q(15, 32)),
+    (poly((2, 1), (4, 1), (6, 1), (8, 1)), Q(15, 32), Q(23, 48)),
+    (poly((2, 1), (4, 1), (8, 1)), Q(23, 48), Q(31, 64)),
+    (poly((2, 1), (4, 1), (8, 1), (16, 1)), Q(31, 64), Q(63, 128)),
+    (poly((2, 1), (4, 1), (8, 1), (16, 1), (32, 1)), Q(63, 128), Q(1, 2)),
+]
+
+
+def test_general_recipes_sizes_and_costs():
+    """Every general-index recipe of Sections 2.1 and 4 gives the stated
+    number of sums and cost."""
+    for name, (m, cost) in GENERAL_SIZES.items():
+        c = D.general(name)
+        assert (c.n_sums(), c.cost()) == (m, cost), name
+
+
+def test_general_b9_and_e9_equal_the_printed_forms():
+    """The replayed recipes equal eqnB9 (from eqnB2: the reading recorded in
+    derive.GENERAL_RECIPES) and eqnE9 term by term, coefficients as
+    polynomials in the powers n^t."""
+    for name, printed in (("B9", PRINTED_B9), ("E9", PRINTED_E9)):
+        got = [(str(c), x, y) for c, x, y in D.general(name).pieces()]
+        assert got == [(str(c), x, y) for c, x, y in printed], name
+
+
+# left sides at the index p - 3 (Section 3: k = (p-3)/2, so C_k(a,b,c) =
+# (c^3 - a^3 - b^3 + 1)/6; Section 5: k = 1)
+LHS_AT_P3 = {"C256": 14, "E1": -4, "MacE": -10}
+
+
+@pytest.mark.parametrize("name,table", [("B2", "BB2"), ("B6", "BB6"), ("B9", "BB9"), ("B16", "BB16"),
+                                        ("B22", "BB22"), ("B30", "BB30"), ("E3", "EE3"), ("E5", "EE5"),
+                                        ("E9", "EE9"), ("E16", "EE16"), ("E24", "EE24"), ("E33", "EE33")])
+def test_general_forms_specialise_to_the_printed_tables(name, table):
+    """At the index p - 3 (n^t -> n^-3 on the Bernoulli side, n^-2 on the
+    Euler side) each general congruence is the printed specialised table of
+    Sections 3 and 5 (eqnBB2 ... eqnBB30, eqnEE3 ... eqnEE33)."""
+    g = D.general(name)
+    sp = g.specialise()
+    sp.lhs = Q(LHS_AT_P3[g.lhs])
+    assert_same(sp, getattr(C, table))
+
+
+def _lhs_values(kind, p, ks):
+    """Left sides of the general congruences mod p for indices k."""
+    out = []
+    for k in ks:
+        if kind == "C256":
+            e = p - 2 * k
+            v = (pow(2, e, p) + pow(5, e, p) - pow(6, e, p) - 1) * pow(4 * k, -1, p)
+        elif kind == "C346":
+            e = p - 2 * k
+            v = (pow(3, e, p) + pow(4, e, p) - pow(6, e, p) - 1) * pow(4 * k, -1, p)
+        elif kind == "C234":
+            e = p - 2 * k
+            v = (pow(2, e, p) + pow(3, e, p) - pow(4, e, p) - 1) * pow(4 * k, -1, p)
+        elif kind == "E1":
+            v = (-1) ** k * pow(4, 2 * k - 1, p)
+        elif kind == "MacE":
+            v = (-1) ** k * pow(4, k - 1, p) * (pow(9, k, p) + 1)
+        out.append(v % p)
+    return out
+
+
+def _exponent_tables(p, side):
+    """Exponents ts of one side (B: t = 2k - 1, E: t = p - 1 - 2k, k = 1 ..
+    (p-3)/2), prefix sums over s <= p/2 of s^t (rows), and n^t for any base."""
+    import numpy as np
+    half = p // 2
+    s = np.arange(1, half + 1, dtype=np.int64)
+    ks = np.arange(1, (p - 3) // 2 + 1, dtype=np.int64)
+    ts = 2 * ks - 1 if side == "B" else p - 1 - 2 * ks
+    order = np.argsort(ts)
+    pw = np.ones_like(s)
+    rows = np.zeros((len(ts), half), dtype=np.int64)
+    t_cur = 0
+    for i in order:
+        while t_cur < ts[i]:
+            pw = pw * s % p
+            t_cur += 1
+        rows[i] = pw
+    cum = np.concatenate([np.zeros((len(ts), 1), dtype=np.int64), np.cumsum(rows, axis=1) % p], axis=1)
+    cache = {}
+
+    def powers(n):   # n^t mod p for t in ts (ts sorted one way or the other: step by n^2)
+        if n not in cache:
+            t0 = int(ts.min())
+            v = np.zeros(len(ts), dtype=np.int64)
+            cur, n2 = pow(n, t0, p), n * n % p
+            for i in order:
+                v[i] = cur
+                cur = cur * n2 % p
+            cache[n] = v
+        return cache[n]
+
+    return [int(k) for k in ks], ts, cum, powers
+
+
+def general_residues(cong, p, tables=None):
+    """X mod p for every index of a general congruence, evaluated plainly
+    (numpy, all exponents at once): {index: residue} with index 2k (B_{2k},
+    exponent t = 2k - 1) or t (E_t, t = p - 1 - 2k), skipping the k whose left
+    side vanishes.  tables: _exponent_tables(p, side), reused across calls."""
+    import numpy as np
+    ks, ts, cum, powers = tables or _exponent_tables(p, cong.side)
+    v = np.zeros(len(ts), dtype=np.int64)
+    for c, x, y in cong.pieces():
+        lo = x.numerator * p // x.denominator + 1
+        hi = (y.numerator * p - 1) // y.denominator
+        if hi < lo:
+            continue
+        S = (cum[:, hi] - cum[:, lo - 1]) % p
+        coef = np.zeros(len(ts), dtype=np.int64)
+        for n, m in c.m.items():
+            mm = m.numerator * pow(m.denominator, -1, p) % p
+            coef = (coef + mm * powers(n)) % p
+        v = (v + coef * S) % p
+    lhs = _lhs_values(cong.lhs, p, ks)
+    out = {}
+    for k, t, L, val in zip(ks, ts, lhs, v):
+        if L:
+            out[2 * k if cong.side == "B" else int(t)] = int(val) * pow(L, -1, p) % p
+    return out
+
+
+def test_general_congruences_hold_for_every_index():
+    """Every general-index congruence (the starts eqnVandiver, eqnSV, eqnV12,
+    eqnE1 with the sign (-1)^k, eqnEMac2 and every recipe) gives B_{2k} and
+    E_{2k} mod p equal to the recurrences for every index 2 <= 2k <= p - 3
+    where its left side is nonzero, at every prime 7 <= p < 2000."""
+    congs = {n: D.general(n) for n in list(D.GENERAL_STARTS) + list(D.GENERAL_RECIPES)}
+    checked = 0
+    for p in oracle.primes(7, 2000):
+        bern = oracle.bernoulli_all(p)
+        eul = oracle.euler_all(p)
+        tables = {side: _exponent_tables(p, side) for side in "BE"}
+        for name, cong in congs.items():
+            got = general_residues(cong, p, tables[cong.side])
+            ref = bern if cong.side == "B" else eul
+            for idx, v in got.items():
+                assert v == ref[idx // 2 - 1], (name, p, idx)
+                checked += 1
+    assert checked > 2_000_000
+
+
+def test_general_mutation_is_caught():
+    """A wrong base or sign in one coefficient of eqnB30 breaks the check
+    above at many indices (the evaluation is not vacuous)."""
+    g = D.general("B30")
+    c, x, y = g.pieces()[5]
+    bad = g.copy()
+    bad.add(x, y, -c)
+    bad.add(x, y, c.times_power(2))         # 2^t times the coefficient
+    p = 1009
+    ref = oracle.bernoulli_all(p)
+    got = general_residues(bad, p)
+    wrong = sum(1 for idx, v in got.items() if v != ref[idx // 2 - 1])
+    assert wrong > len(got) // 2
