@@ -207,6 +207,24 @@ def table_terms(name_or_id):
     return out
 
 
+def prime_count_bound(lo, hi):
+    """An upper bound on the number of primes in [lo, hi), for sizing output
+    buffers: the odd numbers there, pi(x) < 1.25506 x / log x (Rosser and
+    Schoenfeld) for the count below hi, and pi(x + y) - pi(x) <= 2 y / log y
+    (Montgomery and Vaughan) for an interval of length y > 1."""
+    import math
+    lo, hi = int(lo), int(hi)
+    if hi <= lo:
+        return 0
+    y = hi - lo
+    bound = y // 2 + 2
+    if hi > 17:
+        bound = min(bound, int(1.25506 * hi / math.log(hi)) + 2)
+    if y > 1:
+        bound = min(bound, int(2 * y / math.log(y)) + 2)
+    return bound
+
+
 def symmetric(r, p):
     """Representative of r mod p in (-p/2, p/2]."""
     r = int(r) % int(p)
@@ -292,16 +310,23 @@ class Context:
         return n.value
 
     def search_range(self, lo, hi, cap=None, hit_cap=1024):
-        """Results (numpy RESULT_DTYPE, ascending p) and the hit list for [lo, hi)."""
+        """Results (numpy RESULT_DTYPE, ascending p) and the hit list for [lo, hi).
+        The output buffer is sized from an upper bound on the number of primes
+        (a short buffer costs a second call, which the library reports with
+        WV_ETRUNC before doing any work)."""
         if cap is None:
-            cap = self.count_primes(lo, hi)
-        out = np.zeros(max(1, cap), dtype=RESULT_DTYPE)
-        hits = np.zeros(max(1, hit_cap), dtype=np.uint64)
-        n_out, n_hits = SZ(), SZ()
-        st = lib().wv_search_range(self._h, int(lo), int(hi), out.ctypes.data_as(VP), cap, ctypes.byref(n_out),
-                                   hits.ctypes.data_as(P_U64), hit_cap, ctypes.byref(n_hits))
-        _check(st, "wv_search_range")
-        return out[:n_out.value], hits[:min(n_hits.value, hit_cap)]
+            cap = prime_count_bound(lo, hi)
+        while True:
+            out = np.zeros(max(1, cap), dtype=RESULT_DTYPE)
+            hits = np.zeros(max(1, hit_cap), dtype=np.uint64)
+            n_out, n_hits = SZ(), SZ()
+            st = lib().wv_search_range(self._h, int(lo), int(hi), out.ctypes.data_as(VP), cap, ctypes.byref(n_out),
+                                       hits.ctypes.data_as(P_U64), hit_cap, ctypes.byref(n_hits))
+            if st == WV_ETRUNC and n_out.value > cap:
+                cap = n_out.value
+                continue
+            _check(st, "wv_search_range")
+            return out[:n_out.value], hits[:min(n_hits.value, hit_cap)]
 
     def eval_primes(self, primes):
         """Results (numpy RESULT_DTYPE) for the given primes, input order."""

@@ -430,13 +430,18 @@ def beam_search(start, D=6, rounds=16, beam=8, max_m=None, log=None):
     """Section 2.1's exhaustive strategy with restarts, as a beam over the
     number of sums: each round applies every single subdivision (d <= D) to
     every congruence kept, merges congruences that coincide, and keeps the
-    `beam` cheapest for each number of sums m (at most max_m).  Returns
-    {m: (cost, congruence)}, the cheapest seen per m."""
+    `beam` cheapest for each number of sums m (at most max_m).  `start` is a
+    congruence or a list of them (restart points).  Returns {m: (cost,
+    congruence)}, the cheapest seen per m."""
     def key(c):
         return tuple((c2, x, y) for c2, x, y in c.pieces())
 
-    best = {start.n_sums(): (start.cost(), start)}
-    frontier = [start]
+    starts = start if isinstance(start, (list, tuple)) else [start]
+    best = {}
+    for c in starts:
+        if c.n_sums() not in best or c.cost() < best[c.n_sums()][0]:
+            best[c.n_sums()] = (c.cost(), c)
+    frontier = list(starts)
     for r in range(1, rounds + 1):
         seen = {}
         for cong in frontier:

@@ -380,3 +380,35 @@ def test_general_mutation_is_caught():
     got = general_residues(bad, p)
     wrong = sum(1 for idx, v in got.items() if v != ref[idx // 2 - 1])
     assert wrong > len(got) // 2
+
+
+TABLE_1 = {2: Q(15), 3: Q(15), 4: Q(120, 7), 5: Q(240, 13), 6: Q(96, 5), 7: Q(960, 49), 8: Q(1920, 97),
+           9: Q(20), 10: Q(1200, 59), 11: Q(360, 17), 12: Q(108, 5), 13: Q(45, 2), 14: Q(1080, 47),
+           15: Q(540, 23), 16: Q(24), 17: Q(1080, 43), 18: Q(180, 7), 19: Q(180, 7), 20: Q(810, 31),
+           21: Q(1080, 41), 22: Q(80, 3), 23: Q(3240, 121), 24: Q(1620, 59)}
+
+
+def test_table_1_up_to_24_sums():
+    """Table 1 (Section 2.1) for m = 2..24: the exhaustive strategy with
+    restarts, as a beam over the number of sums (single subdivisions with
+    d <= 6, the 12 cheapest congruences kept per m, 8 rounds) started from
+    eqnVandiver and restarted from eqnB9 and eqnB16 (themselves built from
+    eqnVandiver by the recipes of Section 2.1), reaches every printed r_m, and
+    at m = 11, 12, 22, 23 cheaper ones, which are valid congruences."""
+    starts = [D.Congruence.start("Vandiver")]
+    for name in ("B9", "B16"):
+        sp = D.general(name).specialise()
+        sp.lhs = Q(LHS_AT_P3["C256"])
+        starts.append(sp)
+    best = D.beam_search(starts, D=6, rounds=8, beam=12, max_m=26)
+    r = {m: 1 / cost for m, (cost, _) in best.items()}
+    for m, want in TABLE_1.items():
+        assert r[m] >= want, (m, r[m], want)
+    better = [m for m in TABLE_1 if r[m] > TABLE_1[m]]
+    assert better == [11, 12, 22, 23]
+    assert r[22] == 27 and r[23] == 27
+    for m in better:
+        cong = _as_oracle_congruence(best[m][1], f"beam-{m}")
+        ps = [p for p in oracle.primes(11, 1200) if cong.lhs % p]
+        got = [oracle.congruence_residue_exact(p, cong) for p in ps]
+        assert got == [oracle.bernoulli_rec(p) for p in ps], m
