@@ -391,6 +391,70 @@ def general(name):
     return c
 
 
+# ---------------------------------------------------------------------------
+# transformation graphs (Section 7)
+# ---------------------------------------------------------------------------
+
+def parse_transformations(text):
+    """Tokens of a transformation string in depth-first order: ('t', d) for
+    tau_d (subdivision into d terms), ('s', f) for sigma_f (separation at the
+    fraction f of the interval), ('r',) for rho (reflection), ('i',) for iota
+    (a leaf).  Written as e.g. "t3 s1/2 i i r i"."""
+    out = []
+    for tok in text.split():
+        if tok == "i":
+            out.append(("i",))
+        elif tok == "r":
+            out.append(("r",))
+        elif tok[0] == "t":
+            out.append(("t", int(tok[1:])))
+        elif tok[0] == "s":
+            out.append(("s", Q(tok[1:])))
+        else:
+            raise ValueError(f"unknown transformation {tok!r}")
+    return out
+
+
+def apply_transformation_trees(side, lhs, terms, trees):
+    """A derived congruence from a transformation graph (Section 7): the
+    starting congruence's terms [(c, x, y)] with one tree per term, each tree
+    a token list in depth-first order (parse_transformations).  Every node
+    transforms its term: tau_d into its d images (x+i)/d, (y+i)/d with the
+    coefficient times d^t, sigma_f into (x, x + f(y-x)) and (x + f(y-x), y),
+    rho into (1-y, 1-x) with the coefficient times (-1)^t; the leaves (iota)
+    are added up.  Coefficients are general-index (Poly).  Returns (the
+    congruence, number of leaves)."""
+    out = Congruence(side, lhs, general=True)
+    refl = SIDES[side][1]
+    leaves = 0
+    for (c, x, y), toks in zip(terms, trees):
+        pos = 0
+
+        def visit(c, x, y):
+            nonlocal pos, leaves
+            tok = toks[pos]
+            pos += 1
+            if tok[0] == "i":
+                leaves += 1
+                out.add(x, y, c)
+            elif tok[0] == "r":
+                visit(refl * c, 1 - y, 1 - x)
+            elif tok[0] == "s":
+                z = x + tok[1] * (y - x)
+                visit(c, x, z)
+                visit(c, z, y)
+            else:
+                d = tok[1]
+                w = c.times_power(d)
+                for i in range(d):
+                    visit(w, (x + i) / d, (y + i) / d)
+
+        visit(Poly.of(c), Q(x), Q(y))
+        if pos != len(toks):
+            raise ValueError("tokens left over after the tree")
+    return out, leaves
+
+
 def load_json(obj):
     """A Congruence from to_json output."""
     c = Congruence(obj["side"], int(obj["lhs"]))

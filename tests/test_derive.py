@@ -412,3 +412,27 @@ def test_table_1_up_to_24_sums():
         ps = [p for p in oracle.primes(11, 1200) if cong.lhs % p]
         got = [oracle.congruence_residue_exact(p, cong) for p in ps]
         assert got == [oracle.bernoulli_rec(p) for p in ps], m
+
+
+def test_transformation_graph_of_b9():
+    """Section 7: the depth-first string printed for the transformation graph
+    of eqnB9 (one tree per term of eqnTW1 with b = 5, i.e. eqnVandiver),
+    evaluated node by node (tau_d: d images times d^t, sigma_f: split, rho:
+    reflection times (-1)^t, iota: leaf), gives eqnB9 term by term; its 18
+    leaves (T' = 18; 6 and 12 per tree) merge into T = 9 sums, within the
+    bound of Proposition propproportion (b = 5, beta = 2, N = 12, eps = 1/20).
+    Its second tree starts with tau_2 on S(1/3, 2/5): the step that makes
+    eqnB2 (reading of eqnB9's recipe)."""
+    tree1 = D.parse_transformations("t3 s1/2 i i t2 i r i r t2 i r i")
+    tree2 = D.parse_transformations("t2 t3 s1/2 i i t2 i r i r t2 i r i r s1/6 i t5 i i i r i r i")
+    side, lhs, terms = D.GENERAL_STARTS["Vandiver"]
+    cong, leaves = D.apply_transformation_trees(side, lhs, terms, [tree1, tree2])
+    assert [(str(c), x, y) for c, x, y in cong.pieces()] == [(str(c), x, y) for c, x, y in PRINTED_B9]
+    T, Tp = cong.n_sums(), leaves
+    assert (T, Tp) == (9, 18)
+    assert [sum(1 for t in tr if t == ("i",)) for tr in (tree1, tree2)] == [6, 12]
+    b, beta, N, eps = 5, 2, 12, cong.cost()
+    bound = N * eps * b * (b + 1) / max(beta - 1 + N, beta * (beta - 1) / (2 * eps * b * (b + 1)) + N)
+    assert eps == Q(1, 20) and Q(T, Tp) <= bound
+    with pytest.raises(ValueError):
+        D.apply_transformation_trees(side, lhs, terms, [tree1 + [("i",)], tree2])
