@@ -358,14 +358,18 @@ int wv_eval_sums(wv_ctx *ctx, const uint64_t *primes, size_t n, uint64_t *out_b,
 /* ---- request server ---------------------------------------------------
  * Continuous batching of mixed requests (prime lists and intervals) on one
  * context.  Admitted requests keep their primes, per-sum plans and running
- * pairs (c0, c1) in a device pool; each step cuts `step_terms` terms of work
- * into contiguous pieces of sums, shared fairly among the active requests,
- * runs them through the term-sum kernels and folds every piece into its sum
- * with eqnCombinePairs (Section 3).  Requests that arrive while others run
- * join at the next step; results do not depend on the interleaving (exact
- * arithmetic, associative product).  The server uses the context's stream and
- * buffers: do not call other entry points on the context between steps except
- * wv_get_stats.  The congruences are those set on the context at creation. */
+ * pairs (c0, c1) in a device pool; each step takes whole primes of the active
+ * requests, about `step_terms` terms in all (an even share per request, the
+ * rest to the smallest remaining work first, at least one prime), runs every
+ * sum of those primes through the term-sum kernels and folds it into its
+ * pair with eqnCombinePairs (Section 3).  Requests that arrive while others
+ * run join at the next step; results do not depend on the interleaving (exact
+ * arithmetic, associative product).  All device work goes on the context's
+ * stream in call order (admission between steps); the host keeps no per-sum
+ * state and copies from pinned staging.  Do not call other entry points on
+ * the context between steps except wv_get_stats.  The congruences are those
+ * set on the context at creation; the pool holds max_primes times their
+ * sums, fewer than 2^32 (else WV_EINVAL). */
 typedef struct wv_server wv_server;
 
 typedef struct {
@@ -389,21 +393,24 @@ typedef struct {
 int wv_server_create(wv_ctx *ctx, const wv_server_config *cfg, wv_server **out);
 int wv_server_destroy(wv_server *srv);
 /* Every prime of [lo, hi) (at most 2^26 integers wide).  The primes are counted
- * on the device at submission: a range holding more primes than the pool
- * (max_primes) is refused with WV_EINVAL and nothing is queued. */
+ * on the host at submission (a segmented sieve, no device work): a range
+ * holding more primes than the pool (max_primes) is refused with WV_EINVAL and
+ * nothing is queued.  At admission the device sieves the range again; a count
+ * that disagrees ends the request with WV_EHIP. */
 int wv_server_submit_range(wv_server *srv, uint64_t lo, uint64_t hi, uint64_t *id);
 /* A list of primes (validated like wv_eval_primes; at most max_primes). */
 int wv_server_submit_primes(wv_server *srv, const uint64_t *primes, size_t n, uint64_t *id);
 /* Admit what fits, launch the next step of work, then wait for the step the
  * previous call launched: steps are pipelined two deep, so the caller's work
  * between calls and the host's planning overlap the device's work.  A
- * request's results become available in the call that completes its last
- * step (wv_server_result says WV_EBUSY until then).  A step holds about
- * step_terms terms (default 2^38, about 45 ms of the whole GPU at p ~ 1e11),
- * shared fairly among the active requests.  Admission takes requests pending for 2 s or more in arrival order,
- * then the smallest first (by number of primes), and plans at most 2^22 sums
- * per step; a request that does not fit in the pool waits without blocking
- * others.  A request whose admission fails ends with that error (see
+ * request is finalized at the end of the step that holds its last primes and
+ * its results become available in the call that completes that step
+ * (wv_server_result says WV_EBUSY until then).  A step holds about
+ * step_terms terms (default 2^38, about 45 ms of the whole GPU at p ~ 1e11)
+ * and at most 2^22 sums.  Admission takes requests pending for 2 s or more in
+ * arrival order, then the smallest first (by number of primes), and plans at
+ * most 2^24 sums per call; a request that does not fit in the pool waits
+ * without blocking others.  A request whose admission fails ends with that error (see
  * wv_server_result) and frees its pool slots.  A failed step (HIP error, or
  * term sums that did not cover every chunk) returns its error after
  * restarting every active request from its plan, so no partial state of the

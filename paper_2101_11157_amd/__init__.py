@@ -313,8 +313,10 @@ class Context:
         """Results (numpy RESULT_DTYPE, ascending p) and the hit list for [lo, hi).
         The output buffer is sized from an upper bound on the number of primes
         (a short buffer costs a second call, which the library reports with
-        WV_ETRUNC before doing any work)."""
-        if cap is None:
+        WV_ETRUNC before doing any work).  An explicit `cap` that is too short
+        raises WvError(WV_ETRUNC)."""
+        auto = cap is None
+        if auto:
             cap = prime_count_bound(lo, hi)
         while True:
             out = np.zeros(max(1, cap), dtype=RESULT_DTYPE)
@@ -322,7 +324,7 @@ class Context:
             n_out, n_hits = SZ(), SZ()
             st = lib().wv_search_range(self._h, int(lo), int(hi), out.ctypes.data_as(VP), cap, ctypes.byref(n_out),
                                        hits.ctypes.data_as(P_U64), hit_cap, ctypes.byref(n_hits))
-            if st == WV_ETRUNC and n_out.value > cap:
+            if auto and st == WV_ETRUNC and n_out.value > cap:
                 cap = n_out.value
                 continue
             _check(st, "wv_search_range")

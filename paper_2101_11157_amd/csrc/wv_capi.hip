@@ -322,7 +322,7 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
     WV_HIP(hipMemcpyAsync(c->seg_desc.ptr, descs, ns * sizeof(SegDesc), hipMemcpyHostToDevice, st));
     WV_HIP(hipMemcpyAsync(c->seg_off.ptr, offs.data(), (ns + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     WV_HIP(launch_seg_compact(st, as<SegDesc>(c->seg_desc), (unsigned)ns, as<uint32_t>(c->seg_bits),
-                              as<uint64_t>(c->seg_off), as<uint64_t>(c->primes)));
+                              as<uint64_t>(c->seg_off), as<uint64_t>(c->primes), offs[ns]));
     return WV_OK;
 }
 

@@ -70,6 +70,21 @@ struct Pair {
     uint64_t c0, c1;
 };
 
+// Request server: a step takes whole primes of the pool, span by span.  Span:
+// primes [i0, i0 + cnt) of the request planned at pool sums seg0.. (its n
+// primes laid out as a batch: B sums of prime i at i*nB + j, E sums at
+// n*nB + i*nE + j), numbered q0.. among the step's primes.
+struct StepSpan {
+    uint64_t seg0;
+    uint32_t nreq, i0, q0, cnt;
+};
+
+// A request finalized at the end of a step: pool slots [base, base + n), its
+// results at out[out0 .. out0 + n).
+struct FinReq {
+    uint32_t base, n, out0, pad;
+};
+
 // A congruence  lhs * X_{p-3} == sum_i coef_i S(x_i, y_i)  (mod p) in device
 // memory (compiled tables and tables defined at run time alike).  Integers of
 // any size are little-endian base-2^32 limbs of the magnitude plus a sign.
@@ -101,8 +116,14 @@ struct TableStore {
 hipError_t launch_base_sieve(hipStream_t st, uint32_t *out, uint32_t *n_out);
 hipError_t launch_seg_sieve(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bp, uint32_t n_bp,
                             uint32_t *bits_out, uint32_t *counts);
+// primes of segment i at out[off[i] ..], written only below out[limit]
 hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bits,
-                              const uint64_t *off, uint64_t *out);
+                              const uint64_t *off, uint64_t *out, uint64_t limit);
+// off[0..ns] = exclusive prefix of counts[0..ns) (ns <= 1024); if the total is
+// not `expect`, every off[i] = expect (a compaction then writes nothing) and
+// primes[0..expect) = 0 (primes the plan rejects)
+hipError_t launch_seg_offsets(hipStream_t st, const uint32_t *counts, unsigned ns, uint64_t expect, uint64_t *off,
+                              uint64_t *primes);
 // exclusive scan of n values into out[0..n], out[n] = total; tiles holds
 // ceil(n / kScanTile) entries
 hipError_t launch_scan(hipStream_t st, const uint64_t *in, uint64_t n, uint64_t *out, uint64_t *tiles);
@@ -153,6 +174,16 @@ hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec 
 hipError_t launch_fold(hipStream_t st, const SegRec *tasks, const uint32_t *target, const Pair *tp, uint32_t ntask,
                        const PrimeRec *pr, Pair *acc);
 hipError_t launch_fill_pairs(hipStream_t st, Pair *p, uint64_t n, uint64_t c0, uint64_t c1);
+// The tasks of a request-server step: nq whole primes over nsp spans, B tasks
+// of all of them first, then E tasks; tasks[t] = segs[g], terms[t] = its
+// length, target[t] = g (its pool index).
+hipError_t launch_step_expand(hipStream_t st, const StepSpan *sp, uint32_t nsp, uint32_t nq, int nB, int nE,
+                              const SegRec *segs, SegRec *tasks, uint64_t *terms, uint32_t *target);
+// k_finalize for several requests of the pool at once (FinReq list, `total`
+// primes): pool arrays pr, acc, coefs, lhsmod with nB + nE sums per prime
+hipError_t launch_finalize_multi(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *acc,
+                                 const uint64_t *coefs, const uint64_t *lhsmod, const FinReq *fr, uint32_t nfr,
+                                 uint32_t total, int nB, int nE, wv_result *out, const unsigned long long *err);
 // out[i] = i < n ? src[i] : 0  (zero marks a padding slot the plan rejects)
 hipError_t launch_copy_pad(hipStream_t st, const uint64_t *src, uint64_t n, uint64_t *dst, uint64_t n_pad);
 hipError_t launch_copy_results(hipStream_t st, const wv_result *src, uint64_t n, wv_result *dst);

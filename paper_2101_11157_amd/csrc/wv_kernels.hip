@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(1024) k_seg_sieve(const SegDesc *__restrict__ 
 __global__ void __launch_bounds__(1024) k_seg_compact(const SegDesc *__restrict__ desc,
                                                       const uint32_t *__restrict__ bits_in,
                                                       const uint64_t *__restrict__ off,
-                                                      uint64_t *__restrict__ out) {
+                                                      uint64_t *__restrict__ out, uint64_t limit) {
     __shared__ uint32_t scan[1024];
     const int tid = threadIdx.x;
     const uint32_t *bits = bits_in + (size_t)blockIdx.x * kSegWords;
@@ -230,9 +230,31 @@ __global__ void __launch_bounds__(1024) k_seg_compact(const SegDesc *__restrict_
         while (v) {
             int b = __ffs(v) - 1;
             v &= v - 1;
-            out[pos++] = L + 2ull * (uint64_t)(w * 32 + b) + 1ull;
+            if (pos < limit) out[pos] = L + 2ull * (uint64_t)(w * 32 + b) + 1ull;
+            pos++;
         }
     }
+}
+
+// Exclusive prefix of ns <= 1024 segment counts (one workgroup).  A total
+// other than `expect` (the count the caller sized the output for) leaves every
+// offset at `expect`, so the compaction writes nothing, and zeroes the output.
+__global__ void __launch_bounds__(256) k_seg_offsets(const uint32_t *__restrict__ counts, uint32_t ns, uint64_t expect,
+                                                     uint64_t *__restrict__ off, uint64_t *__restrict__ primes) {
+    __shared__ uint64_t total;
+    if (threadIdx.x == 0) {
+        uint64_t a = 0;
+        for (uint32_t i = 0; i < ns; i++) {
+            off[i] = a;
+            a += counts[i];
+        }
+        off[ns] = a;
+        total = a;
+    }
+    __syncthreads();
+    if (total == expect) return;
+    for (uint32_t i = threadIdx.x; i <= ns; i += 256) off[i] = expect;
+    for (uint64_t i = threadIdx.x; i < expect; i += 256) primes[i] = 0;
 }
 
 // --------------------------------------------------------------------------
@@ -745,13 +767,11 @@ __global__ void __launch_bounds__(256) k_sum_values(const SegRec *__restrict__ s
 // One wave per prime.  A prime that the plan rejected, or every prime of a
 // batch whose term sums reported an error (*err != 0; err may be null), gets
 // flags = 0xFFFFFFFF.
-__global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec *__restrict__ pr,
-                                                  const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
-                                                  const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
-                                                  wv_result *__restrict__ out, const unsigned long long *__restrict__ err) {
-    const uint32_t i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= n) return;   // whole wave
+// Prime i of a batch of n (one wave; every lane returns the result).
+__device__ inline wv_result finalize_prime(const TableStore &ts, const PrimeRec *__restrict__ pr,
+                                           const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
+                                           const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE, uint32_t i,
+                                           const unsigned long long *__restrict__ err, int lane) {
     const PrimeRec P = pr[i];
     wv_result r;
     r.reserved = 0;
@@ -760,8 +780,7 @@ __global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec 
         r.b = 0;
         r.e = 0;
         r.flags = 0xFFFFFFFFu;
-        if (lane == 0) out[i] = r;
-        return;
+        return r;
     }
     const Mont m = mont_of(P);
     r.p = P.p;
@@ -769,7 +788,73 @@ __global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec 
     r.e = combine_residue(ts.head[P.te].n, sp, coefs, (size_t)n * nB + (size_t)i * nE, lhsmod[2 * (size_t)i + 1], m,
                           P.r2, P.one, lane);
     r.flags = (r.b == 0 ? WV_FLAG_WOLSTENHOLME : 0u) | (r.e == 0 ? WV_FLAG_VANDIVER : 0u);
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec *__restrict__ pr,
+                                                  const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
+                                                  const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
+                                                  wv_result *__restrict__ out, const unsigned long long *__restrict__ err) {
+    const uint32_t i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;   // whole wave
+    const wv_result r = finalize_prime(ts, pr, sp, coefs, lhsmod, n, nB, nE, i, err, lane);
     if (lane == 0) out[i] = r;
+}
+
+// One wave per prime of several pool requests (fr[k]: slots [base, base + n),
+// results at out[out0 ..]; out0 ascending from 0, `total` primes in all).
+__global__ void __launch_bounds__(256) k_finalize_multi(TableStore ts, const PrimeRec *__restrict__ pr,
+                                                        const Pair *__restrict__ acc,
+                                                        const uint64_t *__restrict__ coefs,
+                                                        const uint64_t *__restrict__ lhsmod,
+                                                        const FinReq *__restrict__ fr, uint32_t nfr, uint32_t total,
+                                                        int nB, int nE, wv_result *__restrict__ out,
+                                                        const unsigned long long *__restrict__ err) {
+    const uint32_t w = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= total) return;   // whole wave
+    uint32_t a = 0, b = nfr;  // the last request with out0 <= w
+    while (b - a > 1) {
+        const uint32_t m = (a + b) >> 1;
+        if (fr[m].out0 <= w) a = m;
+        else b = m;
+    }
+    const FinReq f = fr[a];
+    const size_t per = (size_t)nB + nE;
+    const wv_result r = finalize_prime(ts, pr + f.base, acc + (size_t)f.base * per, coefs + (size_t)f.base * per,
+                                       lhsmod + 2 * (size_t)f.base, f.n, nB, nE, w - f.out0, err, lane);
+    if (lane == 0) out[w] = r;
+}
+
+// Tasks of a request-server step (one thread each): B tasks of the step's nq
+// primes first, then E tasks; prime q of the step lies in the last span whose
+// q0 <= q.
+__global__ void __launch_bounds__(256) k_step_expand(const StepSpan *__restrict__ sp, uint32_t nsp, uint32_t nq,
+                                                     int nB, int nE, const SegRec *__restrict__ segs,
+                                                     SegRec *__restrict__ tasks, uint64_t *__restrict__ terms,
+                                                     uint32_t *__restrict__ target) {
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t nbt = (uint64_t)nq * nB;
+    if (t >= nbt + (uint64_t)nq * nE) return;
+    const bool bern = t < nbt;
+    const uint64_t k = bern ? t : t - nbt;
+    const uint64_t per = bern ? (uint64_t)nB : (uint64_t)nE;
+    const uint32_t q = (uint32_t)(k / per);
+    const uint64_t j = k % per;
+    uint32_t a = 0, b = nsp;
+    while (b - a > 1) {
+        const uint32_t m = (a + b) >> 1;
+        if (sp[m].q0 <= q) a = m;
+        else b = m;
+    }
+    const StepSpan s = sp[a];
+    const uint64_t i = (uint64_t)s.i0 + (q - s.q0);
+    const uint64_t g = s.seg0 + (bern ? i * nB + j : (uint64_t)s.nreq * nB + i * nE + j);
+    const SegRec r = segs[g];
+    tasks[t] = r;
+    terms[t] = r.len;
+    target[t] = (uint32_t)g;
 }
 
 
@@ -796,8 +881,15 @@ hipError_t launch_seg_sieve(hipStream_t st, const SegDesc *desc, unsigned ns, co
 }
 
 hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bits,
-                              const uint64_t *off, uint64_t *out) {
-    hipLaunchKernelGGL(k_seg_compact, dim3(ns), dim3(1024), 0, st, desc, bits, off, out);
+                              const uint64_t *off, uint64_t *out, uint64_t limit) {
+    hipLaunchKernelGGL(k_seg_compact, dim3(ns), dim3(1024), 0, st, desc, bits, off, out, limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_offsets(hipStream_t st, const uint32_t *counts, unsigned ns, uint64_t expect, uint64_t *off,
+                              uint64_t *primes) {
+    if (ns > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_seg_offsets, dim3(1), dim3(256), 0, st, counts, ns, expect, off, primes);
     return hipGetLastError();
 }
 
@@ -900,6 +992,24 @@ hipError_t launch_sum_values(hipStream_t st, const SegRec *segs, const PrimeRec 
 hipError_t launch_fold(hipStream_t st, const SegRec *tasks, const uint32_t *target, const Pair *tp, uint32_t ntask,
                        const PrimeRec *pr, Pair *acc) {
     hipLaunchKernelGGL(k_fold, dim3(blocks_for(ntask, 256)), dim3(256), 0, st, tasks, target, tp, ntask, pr, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_expand(hipStream_t st, const StepSpan *sp, uint32_t nsp, uint32_t nq, int nB, int nE,
+                              const SegRec *segs, SegRec *tasks, uint64_t *terms, uint32_t *target) {
+    const uint64_t nt = (uint64_t)nq * (nB + nE);
+    if (too_many(nt) || nsp == 0) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_step_expand, dim3(blocks_for(nt, 256)), dim3(256), 0, st, sp, nsp, nq, nB, nE, segs, tasks,
+                       terms, target);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_multi(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *acc,
+                                 const uint64_t *coefs, const uint64_t *lhsmod, const FinReq *fr, uint32_t nfr,
+                                 uint32_t total, int nB, int nE, wv_result *out, const unsigned long long *err) {
+    if (too_many((uint64_t)total * 64) || nfr == 0) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_finalize_multi, dim3(blocks_for((uint64_t)total * 64, 256)), dim3(256), 0, st, ts, pr, acc,
+                       coefs, lhsmod, fr, nfr, total, nB, nE, out, err);
     return hipGetLastError();
 }
 

@@ -1,34 +1,38 @@
-// wv_server.hip -- request server with continuous batching at chunk
+// wv_server.hip -- request server with continuous batching at prime
 // granularity (the serving loop of the residue search).
 //
 // Requests (a prime list, or every prime of an interval) are admitted into a
 // device pool of prime slots when a contiguous range of slots is free: their
 // primes are planned into the pool (PrimeRec, one SegRec per (prime, sum)) and
 // each sum gets an accumulator pair (c0, c1) = (1, 0) on the device.  Every
-// step then cuts a budget of terms into tasks -- contiguous ranges of one sum
-// -- shared fairly among the active requests, runs them through the same
-// term-sum and reduction kernels as a batch, and folds each task's pair into
-// its sum's accumulator with eqnCombinePairs (Section 3).  A request whose
-// sums are all complete is finalized (Sections 3 and 5 congruences), its
-// results copied out and its slots freed.  New requests join at the next
-// step, so short requests overtake long ones instead of queueing behind them.
+// step takes whole primes of the active requests -- a fair share of a budget
+// of terms each, smallest remaining work first -- expands them into tasks (one
+// per sum) on the device, runs them through the same term-sum and reduction
+// kernels as a batch, and folds each task's pair into its sum's accumulator
+// with eqnCombinePairs (Section 3).  A request whose last primes a step holds
+// is finalized at the end of that step (Sections 3 and 5 congruences), its
+// results copied out with the step's and its slots freed when the step
+// completes.  New requests join at the next step, so short requests overtake
+// long ones instead of queueing behind them.
 //
-// Steps are pipelined two deep: a call of wv_server_step plans and launches
-// the next step (the host advances the requests' cursors when it plans, so the
-// plan never waits for the device) and then waits for the step launched by the
-// previous call.  The host's work between steps -- planning, the caller's own
-// loop -- overlaps the device's work.  Admission (sieve, plan into the pool)
-// and finalization run on a second stream: they touch pool slots that no step
-// in flight uses.
+// Everything the server enqueues goes on the context stream, in order:
+// admission work (sieve, compaction, plan into the pool) runs between steps,
+// and the host never waits for the device except for the oldest step in
+// flight.  A call of wv_server_step admits what fits, launches the next step
+// and then waits for the step launched by the previous call, so one step is
+// always queued behind the running one while the host plans.  The host keeps
+// no per-sum state: a request is its pool slots and the number of its primes
+// handed out.  Host-to-device copies come from pinned staging buffers, so no
+// copy waits for the device.
 //
 // Because the pair product is associative and commutative and all arithmetic
 // is exact, a request's residues do not depend on how its work was cut into
-// tasks or interleaved with other requests.
+// steps or interleaved with other requests.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cmath>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <deque>
@@ -57,34 +61,53 @@ struct Request {
     int state = REQ_PENDING;
     int status = WV_OK;        // WV_OK, or the error that ended the request
     uint64_t n_primes = 0;     // primes of a range (counted at submission) or list length
+    uint64_t pmax = 0;         // an upper bound on its primes
     uint32_t n = 0;            // primes in the pool
     uint32_t base = 0;         // first pool slot
-    std::vector<uint64_t> seg_lo, seg_len, cursor;   // cursor: terms handed to launched steps
-    size_t first_open = 0;     // first sum with terms not yet handed out
-    uint64_t remaining = 0;    // terms not yet handed to a launched step
-    uint64_t last_step = 0;    // the last launched step holding terms of this request (0: none)
+    uint32_t next = 0;         // primes handed to launched steps
+    double tpp = 0;            // estimated terms per prime
     std::vector<wv_result> results;
 };
 
-struct Task {
-    Request *r;
-    size_t k;        // sum index within the request
-    uint64_t t;      // terms
-};
+// Pinned host memory that grows (only while no queued copy reads it).
+template <class T>
+int pinned_reserve(T *&p, size_t &cap, size_t n) {
+    if (n <= cap) return WV_OK;
+    const size_t want = std::max<size_t>(n, cap + cap / 2);
+    T *q = nullptr;
+    if (hipHostMalloc((void **)&q, want * sizeof(T), hipHostMallocDefault) != hipSuccess) return WV_ENOMEM;
+    if (p) (void)hipHostFree(p);
+    p = q;
+    cap = want;
+    return WV_OK;
+}
 
-// One step's device buffers, the host staging its copies read from (kept
-// until the step completes), its events and its error word.
+// One step's device buffers, its pinned staging (reused once the step has
+// completed), its events and the requests it finalizes.
 struct StepSet {
-    DevBuf tasks, target, toff, tpairs, partials, tails, scal;
-    std::vector<SegRec> recs;
-    std::vector<uint32_t> tgt, tails_h;
-    std::vector<uint64_t> off;
-    uint64_t layout[5] = {};
-    uint64_t *err_host = nullptr;   // pinned: the step's term-sum error word
-    hipEvent_t ev0 = nullptr, ev_sum = nullptr, ev1 = nullptr;
+    DevBuf spans, tasks, terms, cnt, off, tiles, target, tpairs, partials, tails, hist, scal, fin, res;
+    StepSpan *spans_h = nullptr;
+    size_t spans_cap = 0;
+    FinReq *fin_h = nullptr;
+    size_t fin_cap = 0;
+    wv_result *res_h = nullptr;
+    size_t res_cap = 0;
+    uint64_t *scal_h = nullptr;     // pinned: the step's scalars (kScal* words) once it has run
+    hipEvent_t ev0 = nullptr, ev_sum0 = nullptr, ev_sum = nullptr, ev1 = nullptr;
     bool busy = false;              // launched and not yet completed
     uint64_t id = 0;                // step number (1, 2, ...)
-    uint64_t terms = 0, terms_b = 0;
+    std::vector<Request *> finishing;   // requests finalized at the end of this step
+    std::vector<uint32_t> fin_out;      // their first result in res
+};
+
+// Pinned staging of the host-to-device copies one call enqueues; the two
+// halves alternate between calls, and a half is refilled only after the
+// copies of its previous call have run (its event).
+struct Upload {
+    char *h = nullptr;
+    size_t cap = 0, used = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
 };
 
 }  // namespace
@@ -95,15 +118,19 @@ struct wv_server {
     uint32_t pool = 1u << 16;
     int tb = 0, te = 0;        // congruences fixed at creation (the pool layout depends on them)
     int nB = 0, nE = 0, NS = 0;
-    DevBuf pr, segs, acc, terms, tmp, res, coefs, lhsmod;
+    DevBuf pr, segs, acc, terms, coefs, lhsmod, plist;   // pool (plist: each slot's prime)
+    DevBuf sdesc, scount, sbits, soff;                    // sieve of one range admission
     StepSet set[2];
     int next = 0;              // the set the next launch uses
     uint64_t launched = 0;     // steps launched
-    hipStream_t aux = nullptr; // admission and finalization
+    Upload up[2];
+    int up_cur = 0;
     std::vector<std::pair<uint32_t, uint32_t>> free_ranges;   // (first slot, count), sorted
     std::deque<Request *> pending;
     std::vector<Request *> active;
     std::map<uint64_t, Request *> all;
+    std::vector<uint32_t> base_primes;   // odd primes up to base_limit for the host-side prime count
+    uint64_t base_limit = 0;
     uint64_t next_id = 1;
     uint64_t submitted = 0, completed = 0, failed = 0, primes_done = 0, terms_done = 0, terms_done_b = 0, steps = 0,
              readmits = 0;
@@ -115,6 +142,11 @@ struct wv_server {
 };
 
 namespace {
+
+// Tasks per step at most (whole primes of nB + nE sums each).
+constexpr uint64_t kMaxStepTasks = 1ull << 22;
+// Upload staging per half at creation (it grows for larger prime lists).
+constexpr size_t kUploadBytes = 1u << 20;
 
 bool pool_alloc(wv_server *s, uint32_t n, uint32_t *base) {
     for (size_t i = 0; i < s->free_ranges.size(); i++) {
@@ -142,27 +174,74 @@ void pool_free(wv_server *s, uint32_t base, uint32_t n) {
     s->free_ranges.swap(merged);
 }
 
-// Finalize a request whose steps have all completed: residues from its sums'
-// accumulators (on the auxiliary stream; no step in flight uses its slots),
-// copied out; its slots are freed.
-int finish_request(wv_server *s, Request *r) {
-    wv_ctx *c = s->c;
-    if (r->n) {
-        WV_HIP(launch_finalize(s->aux, table_store(c), as<PrimeRec>(s->pr) + r->base,
-                               as<Pair>(s->acc) + (size_t)r->base * s->NS,
-                               as<uint64_t>(s->coefs) + (size_t)r->base * s->NS,
-                               as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->n, s->nB, s->nE,
-                               as<wv_result>(s->res), nullptr));
-        r->results.resize(r->n);
-        WV_HIP(hipMemcpyAsync(r->results.data(), s->res.ptr, r->n * sizeof(wv_result), hipMemcpyDeviceToHost,
-                              s->aux));
-        WV_HIP(hipStreamSynchronize(s->aux));
+// Primes p with max(lo, 5) <= p < hi (the device sieve's convention), by a
+// segmented sieve of the odd numbers on the host.
+uint64_t count_primes_host(std::vector<uint32_t> &base, uint64_t &limit, uint64_t lo, uint64_t hi) {
+    lo = std::max<uint64_t>(lo, 5);
+    if (hi <= lo) return 0;
+    uint64_t r = (uint64_t)std::sqrt((double)hi);
+    while (r * r > hi) r--;
+    while ((r + 1) * (r + 1) <= hi) r++;
+    if (r > limit) {
+        // odd primes up to r (r <= 2^20 for hi <= 2^40), then a sentinel whose
+        // square exceeds every hi
+        std::vector<uint8_t> comp(r + 1, 0);
+        base.clear();
+        for (uint64_t q = 3; q <= r; q += 2) {
+            if (comp[q]) continue;
+            base.push_back((uint32_t)q);
+            for (uint64_t x = q * q; x <= r; x += 2 * q) comp[x] = 1;
+        }
+        base.push_back(UINT32_MAX);
+        limit = r;
     }
-    pool_free(s, r->base, r->n);
+    constexpr uint64_t kOdd = 1u << 20;   // odd numbers per block
+    std::vector<uint8_t> comp(kOdd);
+    uint64_t count = 0;
+    for (uint64_t a = lo | 1; a < hi; a += 2 * kOdd) {
+        const uint64_t b = std::min<uint64_t>(hi, a + 2 * kOdd);
+        const uint64_t m = (b - a + 1) / 2;   // odd numbers a, a + 2, ... below b
+        std::fill(comp.begin(), comp.begin() + m, 0);
+        for (uint32_t q : base) {
+            const uint64_t qq = (uint64_t)q * q;
+            if (qq >= b) break;
+            uint64_t x = std::max(qq, (a + q - 1) / q * q);
+            if (!(x & 1)) x += q;
+            for (; x < b; x += 2ull * q) comp[(x - a) / 2] = 1;
+        }
+        for (uint64_t i = 0; i < m; i++) count += !comp[i];
+    }
+    return count;
+}
+
+// Estimated terms per prime of size p (the congruence that applies at p).
+double terms_per_prime(const wv_server *s, uint64_t p) {
+    const wv_ctx *c = s->c;
+    return (double)p * (c->t_cost[batch_table(c, s->tb, p)] + c->t_cost[batch_table(c, s->te, p)]) + s->NS;
+}
+
+// Stage n bytes for a host-to-device copy into the current upload half.
+int stage_upload(wv_server *s, const void *src, size_t n, void *dst) {
+    Upload &u = s->up[s->up_cur];
+    if (u.used + n > u.cap) {
+        if (u.used) return WV_EBUSY;   // full: the caller retries in a later call
+        // nothing of this half is in flight (its event was waited for)
+        char *h = nullptr;
+        if (hipHostMalloc((void **)&h, n, hipHostMallocDefault) != hipSuccess) return WV_ENOMEM;
+        (void)hipHostFree(u.h);
+        u.h = h;
+        u.cap = n;
+    }
+    memcpy(u.h + u.used, src, n);
+    WV_HIP(hipMemcpyAsync(dst, u.h + u.used, n, hipMemcpyHostToDevice, s->c->stream));
+    u.used = (u.used + n + 255) & ~(size_t)255;
+    return WV_OK;
+}
+
+int finish_empty(wv_server *s, Request *r) {
     r->state = REQ_DONE;
     r->t_done = now_s();
     s->completed++;
-    s->primes_done += r->n;
     s->lat_ms.push_back((r->t_done - r->t_submit) * 1e3);
     return WV_OK;
 }
@@ -181,252 +260,253 @@ void fail_request(wv_server *s, Request *r, int status) {
     s->failed++;
 }
 
-// Plans the n primes at d_primes into the pool slots [r->base, r->base + n)
-// and reads the per-sum records back (auxiliary stream).  The caller frees the
-// slots on error.
-int plan_request(wv_server *s, Request *r, const uint64_t *d_primes, uint32_t n) {
-    wv_ctx *c = s->c;
-    const size_t first = (size_t)r->base * s->NS, nseg = (size_t)n * s->NS;
-    WV_HIP(launch_plan(s->aux, d_primes, n, s->tb, s->te, table_fallback(c, s->tb), table_fallback(c, s->te), s->nB,
-                       s->nE, table_store(c), as<PrimeRec>(s->pr) + r->base, as<SegRec>(s->segs) + first,
-                       as<uint64_t>(s->terms) + first, as<uint64_t>(s->coefs) + first,
-                       as<uint64_t>(s->lhsmod) + 2 * (size_t)r->base, r->base));
-    WV_HIP(launch_fill_pairs(s->aux, as<Pair>(s->acc) + first, nseg, 1, 0));
-    std::vector<SegRec> recs(nseg);
-    WV_HIP(hipMemcpyAsync(recs.data(), as<SegRec>(s->segs) + first, nseg * sizeof(SegRec), hipMemcpyDeviceToHost,
-                          s->aux));
-    WV_HIP(hipStreamSynchronize(s->aux));
-    r->seg_lo.resize(nseg);
-    r->seg_len.resize(nseg);
-    r->cursor.assign(nseg, 0);
-    r->remaining = 0;
-    for (size_t k = 0; k < nseg; k++) {
-        r->seg_lo[k] = recs[k].lo;
-        r->seg_len[k] = recs[k].len;
-        r->remaining += recs[k].len;
-    }
-    r->first_open = 0;
-    r->last_step = 0;
-    return WV_OK;
-}
-
-// Plans a pending request into the pool.  Returns WV_OK with *admitted false
-// when there is no room yet; an error return leaves no pool slot taken.
+// Plans a pending request into the pool (enqueued on the context stream).
+// Sets *admitted false when there is no room yet (slots, or staging for its
+// copies); an error return leaves no pool slot taken.
 int admit(wv_server *s, Request *r, bool *admitted) {
     wv_ctx *c = s->c;
+    hipStream_t st = c->stream;
     *admitted = false;
-    // submission checked that the request fits in an empty pool
-    const uint64_t n = r->n_primes;
-    if (n > s->pool) return WV_EINVAL;
+    const uint64_t n = r->n_primes;   // submission checked n <= pool
+    if (n == 0) {
+        *admitted = true;
+        r->t_admit = now_s();
+        return finish_empty(s, r);
+    }
     uint32_t base = 0;
-    if (n > 0 && !pool_alloc(s, (uint32_t)n, &base)) return WV_OK;
+    if (!pool_alloc(s, (uint32_t)n, &base)) return WV_OK;
     r->base = base;
     r->n = (uint32_t)n;
+    uint64_t *dp = as<uint64_t>(s->plist) + base;
     int rc = WV_OK;
-    const uint64_t *d_primes = nullptr;
-    if (n > 0 && r->is_range) {
+    if (r->is_range) {
         std::vector<SegDesc> d;
-        window_descs(r->lo, r->hi, d);
-        std::vector<uint32_t> counts(d.size());
-        uint64_t got = 0;
-        rc = sieve_count(c, d.data(), d.size(), true, counts.data(), s->aux);
-        if (rc == WV_OK) rc = compact(c, d.data(), d.size(), counts.data(), &got, s->aux);
-        if (rc == WV_OK && got != n) rc = WV_EHIP;   // the sieve is deterministic
-        d_primes = as<uint64_t>(c->primes);
-    } else if (n > 0) {
-        rc = ensure(c, s->tmp, n * sizeof(uint64_t));
-        if (rc == WV_OK && hipMemcpyAsync(s->tmp.ptr, r->primes.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                          s->aux) != hipSuccess)
+        window_descs(r->lo, r->hi, d);   // at most kMaxBatchSegs (checked at submission)
+        rc = stage_upload(s, d.data(), d.size() * sizeof(SegDesc), s->sdesc.ptr);
+        if (rc == WV_OK && (launch_seg_sieve(st, as<SegDesc>(s->sdesc), (unsigned)d.size(), as<uint32_t>(c->base_primes),
+                                             c->n_base, as<uint32_t>(s->sbits), as<uint32_t>(s->scount)) != hipSuccess ||
+                            launch_seg_offsets(st, as<uint32_t>(s->scount), (unsigned)d.size(), n, as<uint64_t>(s->soff),
+                                               dp) != hipSuccess ||
+                            launch_seg_compact(st, as<SegDesc>(s->sdesc), (unsigned)d.size(), as<uint32_t>(s->sbits),
+                                               as<uint64_t>(s->soff), dp, n) != hipSuccess))
             rc = WV_EHIP;
-        d_primes = as<uint64_t>(s->tmp);
+    } else {
+        rc = stage_upload(s, r->primes.data(), n * sizeof(uint64_t), dp);
     }
-    if (rc == WV_OK && n > 0) rc = plan_request(s, r, d_primes, (uint32_t)n);
+    if (rc == WV_OK) {
+        const size_t first = (size_t)base * s->NS, nseg = (size_t)n * s->NS;
+        if (launch_plan(st, dp, (uint32_t)n, s->tb, s->te, table_fallback(c, s->tb), table_fallback(c, s->te), s->nB,
+                        s->nE, table_store(c), as<PrimeRec>(s->pr) + base, as<SegRec>(s->segs) + first,
+                        as<uint64_t>(s->terms) + first, as<uint64_t>(s->coefs) + first,
+                        as<uint64_t>(s->lhsmod) + 2 * (size_t)base, base) != hipSuccess ||
+            launch_fill_pairs(st, as<Pair>(s->acc) + first, nseg, 1, 0) != hipSuccess)
+            rc = WV_EHIP;
+    }
     if (rc != WV_OK) {
         (void)hipGetLastError();
         pool_free(s, r->base, r->n);
         r->n = 0;
-        return rc;
+        return rc == WV_EBUSY ? WV_OK : rc;   // no staging room: stays pending
     }
     r->t_admit = now_s();
-    *admitted = true;
-    if (n == 0 || r->remaining == 0) return finish_request(s, r);
+    r->next = 0;
+    r->tpp = terms_per_prime(s, r->pmax);
     r->state = REQ_ACTIVE;
     s->active.push_back(r);
+    *admitted = true;
     return WV_OK;
 }
 
-// Restart every active request from scratch (after a failed step; no step is
+// Restart every active request from its plan (after a failed step; nothing is
 // in flight).
 int readmit_all(wv_server *s) {
     for (Request *r : s->active) {
-        std::fill(r->cursor.begin(), r->cursor.end(), 0);
-        r->first_open = 0;
-        r->remaining = 0;
-        r->last_step = 0;
-        for (uint64_t l : r->seg_len) r->remaining += l;
-        WV_HIP(launch_fill_pairs(s->c->stream, as<Pair>(s->acc) + (size_t)r->base * s->NS, (size_t)r->n * s->NS,
-                                 1, 0));
+        r->next = 0;
+        WV_HIP(launch_fill_pairs(s->c->stream, as<Pair>(s->acc) + (size_t)r->base * s->NS, (size_t)r->n * s->NS, 1, 0));
         s->readmits++;
     }
     WV_HIP(hipStreamSynchronize(s->c->stream));
     return WV_OK;
 }
 
-// Plans the next step on the host -- a fair share of the budget per active
-// request with terms not yet handed out, cut into tasks of whole chunks -- and
-// launches it on the context stream with buffer set `ss`.  The requests'
-// cursors advance now.  *launched is false when no request has terms left.
+// Chooses the next step's primes on the host -- an even share of the budget
+// for every active request with primes left, then what is left of the budget
+// to the smallest remaining work first, at least one prime per step -- and
+// launches the step on the context stream with buffer set `ss`.  The requests'
+// counters advance now.  *launched is false when no request has primes left.
 int launch_step(wv_server *s, StepSet &ss, bool *launched) {
     wv_ctx *c = s->c;
     *launched = false;
-    const uint64_t C = c->chunk_cfg   ? c->chunk_cfg
-                       : c->chunk_auto ? c->chunk_auto
-                                       : (adaptive_chunk(s->step_terms, sum_lanes(c)) + 63) & ~63ull;
-    // fair share of the step budget, leftovers to whoever still has work
-    std::vector<uint64_t> allow(s->active.size(), 0);
-    uint64_t budget = s->step_terms;
-    for (int pass = 0; pass < 2 && budget > 0; pass++) {
-        size_t want = 0;
-        for (size_t i = 0; i < s->active.size(); i++)
-            if (s->active[i]->remaining > allow[i]) want++;
-        if (!want) break;
-        const uint64_t share = std::max<uint64_t>(C, budget / want);
-        for (size_t i = 0; i < s->active.size() && budget > 0; i++) {
-            const uint64_t left = s->active[i]->remaining - allow[i];
-            if (!left) continue;
-            const uint64_t g = std::min(std::min(left, share), budget);
-            allow[i] += g;
-            budget -= g;
+    std::vector<Request *> cand;
+    for (Request *r : s->active)
+        if (r->next < r->n) cand.push_back(r);
+    if (cand.empty()) return WV_OK;
+    std::stable_sort(cand.begin(), cand.end(), [](const Request *a, const Request *b) {
+        return (a->n - a->next) * a->tpp < (b->n - b->next) * b->tpp;
+    });
+    const uint64_t max_q = std::max<uint64_t>(1, kMaxStepTasks / (uint64_t)s->NS);
+    std::vector<uint32_t> give(cand.size(), 0);
+    double budget = (double)s->step_terms;
+    uint64_t nq = 0;
+    const double even = budget / cand.size();
+    for (size_t k = 0; k < cand.size(); k++) {
+        const Request *r = cand[k];
+        const uint64_t g = std::min<uint64_t>({(uint64_t)(r->n - r->next), (uint64_t)(even / r->tpp), max_q - nq});
+        give[k] = (uint32_t)g;
+        nq += g;
+        budget -= g * r->tpp;
+    }
+    for (size_t k = 0; k < cand.size() && nq < max_q; k++) {
+        const Request *r = cand[k];
+        const uint64_t left = r->n - r->next - give[k];
+        if (!left) continue;
+        if (budget < r->tpp && nq > 0) break;
+        const uint64_t g = std::min<uint64_t>({left, std::max<uint64_t>(1, (uint64_t)(budget / r->tpp)), max_q - nq});
+        give[k] += (uint32_t)g;
+        nq += g;
+        budget -= g * r->tpp;
+    }
+    // spans in candidate order; requests whose last primes this step holds
+    // are finalized at its end
+    std::vector<StepSpan> spans;
+    std::vector<FinReq> fins;
+    ss.finishing.clear();
+    ss.fin_out.clear();
+    uint32_t q0 = 0, nres = 0;
+    double t_est = 0;
+    for (size_t k = 0; k < cand.size(); k++) {
+        if (!give[k]) continue;
+        Request *r = cand[k];
+        spans.push_back(StepSpan{(uint64_t)r->base * s->NS, r->n, r->next, q0, give[k]});
+        q0 += give[k];
+        t_est += give[k] * r->tpp;
+        if (r->next + give[k] == r->n) {
+            fins.push_back(FinReq{r->base, r->n, nres, 0});
+            ss.finishing.push_back(r);
+            ss.fin_out.push_back(nres);
+            nres += r->n;
         }
     }
-    std::vector<Task> tasks;
-    for (size_t i = 0; i < s->active.size(); i++) {
-        Request *r = s->active[i];
-        uint64_t a = allow[i];
-        for (size_t k = r->first_open; k < r->seg_len.size() && a > 0; k++) {
-            const uint64_t left = r->seg_len[k] - r->cursor[k];
-            if (!left) continue;
-            uint64_t t = std::min(left, ((a + C - 1) / C) * C);
-            tasks.push_back(Task{r, k, t});
-            a -= std::min(a, t);
-        }
-    }
-    if (tasks.empty()) return WV_OK;
-    const size_t nt = tasks.size();
-    ss.recs.resize(nt);
-    ss.tgt.resize(nt);
-    ss.off.assign(nt + 1, 0);
-    uint64_t terms = 0, terms_b = 0;
-    for (size_t j = 0; j < nt; j++) {
-        const Task &t = tasks[j];
-        const size_t k = t.k;
-        // slot k of the request: Bernoulli slots (i*nB + j) first, then Euler
-        const bool bern = k < (size_t)t.r->n * s->nB;
-        const uint32_t prime = bern ? (uint32_t)(k / s->nB) : (uint32_t)((k - (size_t)t.r->n * s->nB) / s->nE);
-        ss.recs[j] = SegRec{t.r->seg_lo[k] + t.r->cursor[k], t.t, t.r->base + prime, bern ? 3u : 2u};
-        ss.tgt[j] = (uint32_t)((size_t)t.r->base * s->NS + k);
-        ss.off[j + 1] = ss.off[j] + t.t / C;   // full chunks
-        terms += t.t;
-        if (bern) terms_b += t.t;
-    }
-    // tail chunks (tasks whose length C does not divide) by length class,
-    // longest first, each class's s^-3 tasks before its s^-2 ones (counting
-    // sort, as the batch plan does on the device)
-    std::vector<uint32_t> cls(nt, kTailClasses);
-    uint64_t first[kTailClasses + 1] = {};
-    for (size_t j = 0; j < nt; j++)
-        if (const uint64_t rem = tasks[j].t % C) first[(cls[j] = tail_class(rem, C, ss.recs[j].deg)) + 1]++;
-    for (int b = 0; b < kTailClasses; b++) first[b + 1] += first[b];
-    ss.tails_h.resize(first[kTailClasses]);
-    for (size_t j = 0; j < nt; j++)
-        if (cls[j] < (uint32_t)kTailClasses) ss.tails_h[first[cls[j]]++] = (uint32_t)j;
-    const uint64_t chunks = ss.off[nt];
+    const uint64_t nt = nq * (uint64_t)s->NS, nbt = nq * (uint64_t)s->nB;
+    // partial pairs: room for the estimated terms at the configured (or
+    // adaptive) chunk and for every task's tail; the device picks a chunk
+    // size that fits whatever the terms turn out to be
+    const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    const double chunk = chunk_cfg ? (double)chunk_cfg
+                                   : (double)adaptive_chunk((uint64_t)std::min(t_est, 1.8e19), sum_lanes(c));
+    const uint64_t cap = std::max<uint64_t>(
+        2 * nt, (uint64_t)std::min<double>(std::max<double>(t_est / chunk + 2.0 * nt, (double)kMinChunks),
+                                           (double)kMaxChunks));
+    WV_TRY(ensure(c, ss.spans, spans.size() * sizeof(StepSpan)));
     WV_TRY(ensure(c, ss.tasks, nt * sizeof(SegRec)));
+    WV_TRY(ensure(c, ss.terms, nt * sizeof(uint64_t)));
+    WV_TRY(ensure(c, ss.cnt, nt * sizeof(uint64_t)));
+    WV_TRY(ensure(c, ss.off, (nt + 1) * sizeof(uint64_t)));
+    WV_TRY(ensure(c, ss.tiles, ((nt + kScanTile - 1) / kScanTile + 1) * sizeof(uint64_t)));
     WV_TRY(ensure(c, ss.target, nt * sizeof(uint32_t)));
-    WV_TRY(ensure(c, ss.toff, (nt + 1) * sizeof(uint64_t)));
     WV_TRY(ensure(c, ss.tpairs, nt * sizeof(Pair)));
-    WV_TRY(ensure(c, ss.partials, std::max<uint64_t>(chunks, 1) * sizeof(Pair)));
-    WV_TRY(ensure(c, ss.tails, std::max<size_t>(ss.tails_h.size(), 1) * sizeof(uint32_t)));
+    WV_TRY(ensure(c, ss.tails, nt * sizeof(uint32_t)));
+    WV_TRY(ensure(c, ss.hist, 2 * kTailClasses * sizeof(uint64_t)));
+    WV_TRY(ensure(c, ss.partials, cap * sizeof(Pair)));
+    WV_TRY(ensure(c, ss.fin, std::max<size_t>(fins.size(), 1) * sizeof(FinReq)));
+    WV_TRY(ensure(c, ss.res, std::max<size_t>(nres, 1) * sizeof(wv_result)));
+    WV_TRY(pinned_reserve(ss.spans_h, ss.spans_cap, spans.size()));
+    WV_TRY(pinned_reserve(ss.fin_h, ss.fin_cap, std::max<size_t>(fins.size(), 1)));
+    WV_TRY(pinned_reserve(ss.res_h, ss.res_cap, std::max<size_t>(nres, 1)));
+    memcpy(ss.spans_h, spans.data(), spans.size() * sizeof(StepSpan));
+    if (!fins.empty()) memcpy(ss.fin_h, fins.data(), fins.size() * sizeof(FinReq));
+
     hipStream_t st = c->stream;
-    WV_HIP(hipMemcpyAsync(ss.tasks.ptr, ss.recs.data(), nt * sizeof(SegRec), hipMemcpyHostToDevice, st));
-    WV_HIP(hipMemcpyAsync(ss.target.ptr, ss.tgt.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    WV_HIP(hipMemcpyAsync(ss.toff.ptr, ss.off.data(), (nt + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    if (!ss.tails_h.empty())
-        WV_HIP(hipMemcpyAsync(ss.tails.ptr, ss.tails_h.data(), ss.tails_h.size() * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, st));
-    // chunk layout, the chunk counter, the term-sum error word
-    ss.layout[0] = C;
-    ss.layout[1] = chunks;
-    ss.layout[2] = ss.tails_h.size();
-    ss.layout[3] = 0;
-    ss.layout[4] = 0;
     uint64_t *scal = as<uint64_t>(ss.scal);
-    WV_HIP(hipMemcpyAsync(scal, ss.layout, sizeof(ss.layout), hipMemcpyHostToDevice, st));
+    uint64_t *off = as<uint64_t>(ss.off);
     WV_HIP(hipEventRecord(ss.ev0, st));
+    WV_HIP(hipMemcpyAsync(ss.spans.ptr, ss.spans_h, spans.size() * sizeof(StepSpan), hipMemcpyHostToDevice, st));
+    if (!fins.empty())
+        WV_HIP(hipMemcpyAsync(ss.fin.ptr, ss.fin_h, fins.size() * sizeof(FinReq), hipMemcpyHostToDevice, st));
+    WV_HIP(launch_set_u64(st, scal, 8, 0));
+    WV_HIP(launch_step_expand(st, as<StepSpan>(ss.spans), (uint32_t)spans.size(), (uint32_t)nq, s->nB, s->nE,
+                              as<SegRec>(s->segs), as<SegRec>(ss.tasks), as<uint64_t>(ss.terms),
+                              as<uint32_t>(ss.target)));
+    WV_HIP(launch_scan(st, as<uint64_t>(ss.terms), nt, off, as<uint64_t>(ss.tiles)));
+    WV_HIP(launch_pick_chunk(st, off + nt, nt, chunk_cfg, sum_lanes(c), cap, scal + kScalLayout));
+    WV_HIP(launch_copy_u64(st, off + nt, scal + kScalTerms, 1));
+    WV_HIP(launch_copy_u64(st, off + nbt, scal + kScalTermsB, 1));
+    WV_HIP(launch_chunk_layout(st, as<uint64_t>(ss.terms), nt, nbt, scal + kScalLayout, as<uint64_t>(ss.cnt), off,
+                               as<uint64_t>(ss.tiles), as<unsigned long long>(ss.hist), as<uint32_t>(ss.tails),
+                               scal + kScalChunks));
+    WV_HIP(hipEventRecord(ss.ev_sum0, st));
     const int v = c->variant;
-    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(ss.tasks), as<uint64_t>(ss.toff), (uint32_t)nt,
-                      as<PrimeRec>(s->pr), scal, as<uint32_t>(ss.tails), as<Pair>(ss.partials), as<Pair>(ss.tpairs),
-                      (unsigned long long *)(scal + 3), UINT64_MAX, (unsigned long long *)(scal + 4)));
+    WV_HIP(launch_sum(st, v, (unsigned)c->sum_blocks[v], as<SegRec>(ss.tasks), off, (uint32_t)nt, as<PrimeRec>(s->pr),
+                      scal + kScalLayout, as<uint32_t>(ss.tails), as<Pair>(ss.partials), as<Pair>(ss.tpairs),
+                      (unsigned long long *)(scal + kScalCounter), UINT64_MAX,
+                      (unsigned long long *)(scal + kScalErr)));
     WV_HIP(hipEventRecord(ss.ev_sum, st));
-    WV_HIP(launch_reduce(st, as<SegRec>(ss.tasks), as<uint64_t>(ss.toff), (uint32_t)nt, as<PrimeRec>(s->pr),
-                         as<Pair>(ss.partials), scal, as<Pair>(ss.tpairs)));
+    WV_HIP(launch_reduce(st, as<SegRec>(ss.tasks), off, (uint32_t)nt, as<PrimeRec>(s->pr), as<Pair>(ss.partials),
+                         scal + kScalLayout, as<Pair>(ss.tpairs)));
     WV_HIP(launch_fold(st, as<SegRec>(ss.tasks), as<uint32_t>(ss.target), as<Pair>(ss.tpairs), (uint32_t)nt,
                        as<PrimeRec>(s->pr), as<Pair>(s->acc)));
-    WV_HIP(hipMemcpyAsync(ss.err_host, scal + 4, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    WV_HIP(hipEventRecord(ss.ev1, st));
-    // the terms are handed out: advance the cursors
-    ss.id = ++s->launched;
-    for (const Task &t : tasks) {
-        t.r->cursor[t.k] += t.t;
-        t.r->remaining -= t.t;
-        t.r->last_step = ss.id;
+    if (!fins.empty()) {
+        WV_HIP(launch_finalize_multi(st, table_store(c), as<PrimeRec>(s->pr), as<Pair>(s->acc),
+                                     as<uint64_t>(s->coefs), as<uint64_t>(s->lhsmod), as<FinReq>(ss.fin),
+                                     (uint32_t)fins.size(), nres, s->nB, s->nE, as<wv_result>(ss.res),
+                                     (const unsigned long long *)(scal + kScalErr)));
+        WV_HIP(hipMemcpyAsync(ss.res_h, ss.res.ptr, (size_t)nres * sizeof(wv_result), hipMemcpyDeviceToHost, st));
     }
-    for (Request *r : s->active)
-        while (r->first_open < r->seg_len.size() && r->cursor[r->first_open] == r->seg_len[r->first_open])
-            r->first_open++;
-    ss.terms = terms;
-    ss.terms_b = terms_b;
+    WV_HIP(hipMemcpyAsync(ss.scal_h, scal, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    WV_HIP(hipEventRecord(ss.ev1, st));
+    // the primes are handed out
+    ss.id = ++s->launched;
+    for (size_t k = 0; k < cand.size(); k++) cand[k]->next += give[k];
     ss.busy = true;
     *launched = true;
     return WV_OK;
 }
 
-// Waits for the step of buffer set `ss`; on success finalizes every request
-// whose last step it was.
+// Waits for the step of buffer set `ss`; on success completes every request
+// it finalized.
 int complete_step(wv_server *s, StepSet &ss) {
     WV_HIP(hipEventSynchronize(ss.ev1));
     ss.busy = false;
     float ms = 0.f, ms_sum = 0.f;
     (void)hipEventElapsedTime(&ms, ss.ev0, ss.ev1);
-    (void)hipEventElapsedTime(&ms_sum, ss.ev0, ss.ev_sum);
+    (void)hipEventElapsedTime(&ms_sum, ss.ev_sum0, ss.ev_sum);
     s->busy_s += ms * 1e-3;
     s->sum_s += ms_sum * 1e-3;
     s->steps++;
-    if (*ss.err_host) return WV_EHIP;   // the term sums did not cover every chunk: discard the step
+    if (ss.scal_h[kScalErr]) return WV_EHIP;   // the term sums did not cover every chunk: discard the step
     if (s->fault_after >= 0 && (int64_t)s->steps > s->fault_after) {
         s->fault_after = -1;   // one forced failure: the step's work is discarded
         return WV_EHIP;
     }
-    s->terms_done += ss.terms;
-    s->terms_done_b += ss.terms_b;
+    s->terms_done += ss.scal_h[kScalTerms];
+    s->terms_done_b += ss.scal_h[kScalTermsB];
     s->fail_streak = 0;
-    // finished requests leave the active list one by one, so that an error in
-    // a later finalize leaves only unfinished requests active
-    std::vector<Request *> still;
-    int rc = WV_OK;
-    size_t i = 0;
-    for (; i < s->active.size() && rc == WV_OK; i++) {
-        Request *r = s->active[i];
-        if (r->remaining == 0 && r->last_step <= ss.id) {
-            rc = finish_request(s, r);
-            if (rc != WV_OK) still.push_back(r);   // not finished: its sums restart with the others
-        } else {
-            still.push_back(r);
+    if (ss.finishing.empty()) return WV_OK;
+    for (size_t k = 0; k < ss.finishing.size(); k++) {
+        Request *r = ss.finishing[k];
+        const wv_result *res = ss.res_h + ss.fin_out[k];
+        bool bad = false;
+        for (uint32_t i = 0; i < r->n; i++) bad |= res[i].flags == 0xFFFFFFFFu;
+        if (bad) {
+            // every prime of a request is valid (checked at submission, or
+            // from the sieve): a rejected one means the admission went wrong
+            fail_request(s, r, WV_EHIP);
+            continue;
         }
+        r->results.assign(res, res + r->n);
+        pool_free(s, r->base, r->n);
+        r->state = REQ_DONE;
+        r->t_done = now_s();
+        s->completed++;
+        s->primes_done += r->n;
+        s->lat_ms.push_back((r->t_done - r->t_submit) * 1e3);
     }
-    for (; i < s->active.size(); i++) still.push_back(s->active[i]);
+    std::vector<Request *> still;
+    for (Request *r : s->active)
+        if (r->state == REQ_ACTIVE) still.push_back(r);
     s->active.swap(still);
-    return rc;
+    ss.finishing.clear();
+    return WV_OK;
 }
 
 double percentile(std::vector<double> v, double q) {
@@ -457,6 +537,10 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
     s->nE = side_slots(c, c->te);
     s->NS = s->nB + s->nE;
     const size_t nseg = (size_t)s->pool * s->NS;
+    if (nseg >= (1ull << 32)) {   // pool indices of the step tasks are 32-bit
+        delete s;
+        return WV_EINVAL;
+    }
     int rc = WV_OK;
     if ((rc = ensure(c, s->pr, s->pool * sizeof(PrimeRec))) != WV_OK ||
         (rc = ensure(c, s->segs, nseg * sizeof(SegRec))) != WV_OK ||
@@ -464,20 +548,28 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
         (rc = ensure(c, s->terms, nseg * sizeof(uint64_t))) != WV_OK ||
         (rc = ensure(c, s->coefs, nseg * sizeof(uint64_t))) != WV_OK ||
         (rc = ensure(c, s->lhsmod, 2 * (size_t)s->pool * sizeof(uint64_t))) != WV_OK ||
-        (rc = ensure(c, s->res, s->pool * sizeof(wv_result))) != WV_OK) {
+        (rc = ensure(c, s->plist, s->pool * sizeof(uint64_t))) != WV_OK ||
+        (rc = ensure(c, s->sdesc, kMaxBatchSegs * sizeof(SegDesc))) != WV_OK ||
+        (rc = ensure(c, s->scount, kMaxBatchSegs * sizeof(uint32_t))) != WV_OK ||
+        (rc = ensure(c, s->sbits, kMaxBatchSegs * kSegWords * sizeof(uint32_t))) != WV_OK ||
+        (rc = ensure(c, s->soff, (kMaxBatchSegs + 1) * sizeof(uint64_t))) != WV_OK) {
         wv_server_destroy(s);
         return rc;
     }
-    if (hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) != hipSuccess) rc = WV_EHIP;
     for (int k = 0; k < 2 && rc == WV_OK; k++) {
         StepSet &ss = s->set[k];
         if ((rc = ensure(c, ss.scal, 8 * sizeof(uint64_t))) != WV_OK) break;
-        if (hipHostMalloc((void **)&ss.err_host, sizeof(uint64_t), hipHostMallocDefault) != hipSuccess ||
-            hipEventCreate(&ss.ev0) != hipSuccess || hipEventCreate(&ss.ev_sum) != hipSuccess ||
-            hipEventCreate(&ss.ev1) != hipSuccess)
+        if (hipHostMalloc((void **)&ss.scal_h, 8 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreate(&ss.ev0) != hipSuccess || hipEventCreate(&ss.ev_sum0) != hipSuccess ||
+            hipEventCreate(&ss.ev_sum) != hipSuccess || hipEventCreate(&ss.ev1) != hipSuccess)
             rc = WV_EHIP;
         else
-            *ss.err_host = 0;
+            memset(ss.scal_h, 0, 8 * sizeof(uint64_t));
+        Upload &u = s->up[k];
+        if (rc == WV_OK && (hipHostMalloc((void **)&u.h, kUploadBytes, hipHostMallocDefault) != hipSuccess ||
+                            hipEventCreate(&u.ev) != hipSuccess))
+            rc = WV_EHIP;
+        if (rc == WV_OK) u.cap = kUploadBytes;
     }
     if (rc != WV_OK) {
         wv_server_destroy(s);
@@ -497,20 +589,26 @@ int wv_server_inject_fault(wv_server *s, int after_steps) {
 int wv_server_destroy(wv_server *s) {
     if (!s) return WV_OK;
     if (s->c) (void)hipStreamSynchronize(s->c->stream);
-    if (s->aux) (void)hipStreamSynchronize(s->aux);
-    DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->tmp, &s->res, &s->coefs, &s->lhsmod};
+    DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->coefs, &s->lhsmod, &s->plist,
+                      &s->sdesc, &s->scount, &s->sbits, &s->soff};
     for (DevBuf *b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     for (StepSet &ss : s->set) {
-        DevBuf *sb[] = {&ss.tasks, &ss.target, &ss.toff, &ss.tpairs, &ss.partials, &ss.tails, &ss.scal};
+        DevBuf *sb[] = {&ss.spans, &ss.tasks, &ss.terms, &ss.cnt, &ss.off, &ss.tiles, &ss.target,
+                        &ss.tpairs, &ss.partials, &ss.tails, &ss.hist, &ss.scal, &ss.fin, &ss.res};
         for (DevBuf *b : sb)
             if (b->ptr) (void)hipFree(b->ptr);
-        if (ss.err_host) (void)hipHostFree(ss.err_host);
-        hipEvent_t evs[] = {ss.ev0, ss.ev_sum, ss.ev1};
+        void *hb[] = {ss.spans_h, ss.fin_h, ss.res_h, ss.scal_h};
+        for (void *h : hb)
+            if (h) (void)hipHostFree(h);
+        hipEvent_t evs[] = {ss.ev0, ss.ev_sum0, ss.ev_sum, ss.ev1};
         for (hipEvent_t e : evs)
             if (e) (void)hipEventDestroy(e);
     }
-    if (s->aux) (void)hipStreamDestroy(s->aux);
+    for (Upload &u : s->up) {
+        if (u.h) (void)hipHostFree(u.h);
+        if (u.ev) (void)hipEventDestroy(u.ev);
+    }
     for (auto &kv : s->all) delete kv.second;
     delete s;
     return WV_OK;
@@ -520,14 +618,8 @@ int wv_server_submit_range(wv_server *s, uint64_t lo, uint64_t hi, uint64_t *id)
     if (!s || !id || lo > hi) return WV_EINVAL;
     if (hi > WV_P_MAX) return WV_EDOMAIN;
     if (hi - (lo & ~1ull) > kMaxBatchSegs * kSegSpan) return WV_EINVAL;   // one batch of sieve segments
-    WV_TRY(check_device(s->c));
     // the prime count decides whether the request can ever fit in the pool
-    std::vector<SegDesc> d;
-    window_descs(lo, hi, d);
-    std::vector<uint32_t> counts(d.size());
-    if (!d.empty()) WV_TRY(sieve_count(s->c, d.data(), d.size(), false, counts.data(), s->aux));
-    uint64_t n = 0;
-    for (uint32_t k : counts) n += k;
+    const uint64_t n = count_primes_host(s->base_primes, s->base_limit, lo, hi);
     if (n > s->pool) return WV_EINVAL;
     Request *r = new (std::nothrow) Request();
     if (!r) return WV_ENOMEM;
@@ -536,6 +628,7 @@ int wv_server_submit_range(wv_server *s, uint64_t lo, uint64_t hi, uint64_t *id)
     r->lo = lo;
     r->hi = hi;
     r->n_primes = n;
+    r->pmax = hi;
     r->t_submit = now_s();
     if (!s->submitted) s->t_first = r->t_submit;
     s->submitted++;
@@ -548,15 +641,18 @@ int wv_server_submit_range(wv_server *s, uint64_t lo, uint64_t hi, uint64_t *id)
 int wv_server_submit_primes(wv_server *s, const uint64_t *primes, size_t n, uint64_t *id) {
     if (!s || !id || (n && !primes)) return WV_EINVAL;
     if (n > s->pool) return WV_EINVAL;
+    uint64_t pmax = 0;
     for (size_t i = 0; i < n; i++) {
         if (primes[i] < 5 || primes[i] >= WV_P_MAX) return WV_EDOMAIN;
         if (!is_prime_u64(primes[i])) return WV_ENOTPRIME;
+        pmax = std::max(pmax, primes[i]);
     }
     Request *r = new (std::nothrow) Request();
     if (!r) return WV_ENOMEM;
     r->id = s->next_id++;
     r->primes.assign(primes, primes + n);
     r->n_primes = n;
+    r->pmax = pmax;
     r->t_submit = now_s();
     if (!s->submitted) s->t_first = r->t_submit;
     s->submitted++;
@@ -566,10 +662,9 @@ int wv_server_submit_primes(wv_server *s, const uint64_t *primes, size_t n, uint
     return WV_OK;
 }
 
-// Sums planned into the pool per step at most (planning copies each sum's
-// record to the host), so that admitting a burst of large requests does not
-// hold back the next step.
-constexpr size_t kAdmitSums = 1u << 22;
+// Sums planned into the pool per call at most, so that admitting a burst of
+// large requests does not hold back the next step.
+constexpr size_t kAdmitSums = 1u << 24;
 // A request pending longer than this is admitted before smaller ones, in
 // arrival order, so that a stream of small requests cannot starve it.
 constexpr double kAdmitAgeS = 2.0;
@@ -580,9 +675,15 @@ constexpr int kMaxFailedSteps = 3;
 int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     if (!s) return WV_EINVAL;
     WV_TRY(check_device(s->c));
+    // this call's upload staging: the copies its previous use enqueued have
+    // run once the step launched after them completed (a call ago)
+    Upload &u = s->up[s->up_cur];
+    if (u.pending) WV_HIP(hipEventSynchronize(u.ev));
+    u.pending = false;
+    u.used = 0;
     // admit requests pending for kAdmitAgeS or more in arrival order, then the
     // smallest first (by number of primes), arrival order among equals,
-    // within the per-step budget of sums; a request that does not fit in the
+    // within the per-call budget of sums; a request that does not fit in the
     // pool yet does not block those behind it
     const double t_old = now_s() - kAdmitAgeS;
     std::stable_sort(s->pending.begin(), s->pending.end(), [&](const Request *a, const Request *b) {
@@ -611,6 +712,11 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
         else admitted_sums += (size_t)r->n * s->NS;
     }
     s->pending.swap(waiting);
+    if (u.used) {
+        WV_HIP(hipEventRecord(u.ev, s->c->stream));
+        u.pending = true;
+        s->up_cur ^= 1;
+    }
     // launch the next step, then wait for the older step in flight (or, when
     // nothing new was launched, for the one still in flight)
     StepSet &nx = s->set[s->next];
@@ -628,7 +734,10 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
         // every step in flight is discarded: the active requests restart from
         // their plans, or end with the error after repeated failures
         (void)hipStreamSynchronize(s->c->stream);
-        s->set[0].busy = s->set[1].busy = false;
+        for (StepSet &ss : s->set) {
+            ss.busy = false;
+            ss.finishing.clear();
+        }
         if (++s->fail_streak >= kMaxFailedSteps) {
             for (Request *r : s->active) fail_request(s, r, rc);
             s->active.clear();

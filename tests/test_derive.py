@@ -121,6 +121,26 @@ def test_greedy_search_lowers_cost_and_cost_after_is_exact():
             assert cur.cost_after(x, y, d) == cur.copy().subdivide(x, y, d).cost()
 
 
+def test_greedy_progress_follows_the_figure_fit():
+    """Section 6 (figure of the greedy progress): from eqnB2 with lambda = 1
+    and D = 8, the congruence of m sums after each round costs p / r with r
+    within 1.5 % of the paper's fitted curve 8.68 + 4.49 log m for every round
+    that reaches m >= 40 in the first 40 rounds (the fit is of the paper's own
+    run; a wrong cost, a missed candidate or a wrong d range moves r off it)."""
+    import math
+    start = D.Congruence.start("Vandiver").subdivide(Q(1, 3), Q(2, 5), 2)
+    pts = []
+    D.greedy(start, D=8, rounds=40, log=lambda k, c: pts.append((c.n_sums(), 1 / c.cost())))
+    assert pts[9] == (43, pts[9][1]) and abs(float(pts[9][1]) - 25.548) < 1e-3
+    checked = 0
+    for m, r in pts:
+        if m >= 40:
+            fit = 8.68 + 4.49 * math.log(m)
+            assert abs(float(r) - fit) / fit < 0.015, (m, float(r), fit)
+            checked += 1
+    assert checked >= 30
+
+
 def _as_oracle_congruence(cong, name):
     L, terms = cong.integer_form()
     kind, ell = ("B", -3) if cong.side == "B" else ("E", -2)
