@@ -291,7 +291,6 @@ def measure_plain(args, wv, wins, lo0, hi0, W):
     block = None
     ms_sum = ms_dev = 0.0
     timed = []
-    plist = []
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
         res, hits = ctx.search_range(*wins[k])
@@ -304,11 +303,11 @@ def measure_plain(args, wv, wins, lo0, hi0, W):
         ms_sum += st["ms_sum"]
         ms_dev += st["ms_total"]
         timed.append(res)
-        plist.extend(int(p) for p in res["p"])
         print(f"step {k - args.warmup}: {len(res)} primes, {st['n_terms']:.3e} terms, "
               f"sum kernel {st['ms_sum']:.1f} ms, device {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     ctx.close()
+    plist = [int(p) for res in timed for p in res["p"]]   # bookkeeping outside the timed region
     ops = OpsModel(args.tables, block[0], block[1]).ops(plist, terms_b, terms) if block else 0.0
     return dict(tables=tables, primes=primes, terms=terms, terms_b=terms_b, ops=ops, muls=muls, block=block,
                 ms_sum=ms_sum, ms_dev=ms_dev, wall=wall, results=timed)

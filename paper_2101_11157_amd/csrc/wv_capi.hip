@@ -214,10 +214,9 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
     WV_HIP(hipEventRecord(c->ev[EV_PLAN], st));
     double ms_sum = 0.0;
     if (!c->progress) {
+        // one launch; its time is read after the batch's single wait below
         WV_TRY(enqueue_sum(c, bufs, sh, st, 0, UINT64_MAX));
         WV_HIP(hipEventRecord(c->ev[EV_SUM], st));
-        WV_HIP(hipEventSynchronize(c->ev[EV_SUM]));
-        ms_sum = elapsed(c->ev[EV_PLAN], c->ev[EV_SUM]);
     } else {
         uint64_t host[8];
         WV_HIP(hipMemcpyAsync(host, c->scal.ptr, sizeof(host), hipMemcpyDeviceToHost, st));
@@ -241,12 +240,12 @@ int run_batch_sync(wv_ctx *c, const uint64_t *d_primes, uint32_t n, uint64_t pma
                            as<uint64_t>(c->lhsmod), sh.n, sh.nB, sh.nE, d_out,
                            (const unsigned long long *)(as<uint64_t>(c->scal) + kScalErr)));
     WV_HIP(hipEventRecord(c->ev[EV_FINAL], st));
-    WV_HIP(hipEventSynchronize(c->ev[EV_FINAL]));
-    // statistics
+    // statistics (the batch's one wait)
     uint64_t host[8];
     WV_HIP(hipMemcpyAsync(host, c->scal.ptr, sizeof(host), hipMemcpyDeviceToHost, st));
     WV_HIP(hipStreamSynchronize(st));
     if (host[kScalErr]) return WV_EHIP;   // the term sums did not cover every chunk
+    if (!c->progress) ms_sum = elapsed(c->ev[EV_PLAN], c->ev[EV_SUM]);
     wv_stats &s = c->stats;
     s.ms_plan += elapsed(c->ev[EV_PLAN0], c->ev[EV_PLAN]);
     s.ms_sum += ms_sum;
@@ -331,7 +330,7 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
 // about kMaxBatchPrimes primes; each batch is one plan and one persistent
 // term-sum launch (or one split launch sequence under a progress callback).
 int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts, wv_result *out,
-                 StatsSink *sink, const uint64_t *dest) {
+                 StatsSink *sink, const uint64_t *dest, bool bits_ready) {
     std::vector<wv_result> staging;
     hipStream_t st = c->stream;
     size_t i = 0, written = 0;
@@ -357,19 +356,21 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
             continue;
         }
         WV_HIP(hipEventRecord(c->ev[EV_START], st));
-        std::vector<uint32_t> again(j - i);
-        WV_TRY(sieve_count(c, descs.data() + i, j - i, true, again.data()));
-        for (size_t k = 0; k < again.size(); k++)
-            if (again[k] != counts[i + k]) return WV_EHIP;   // the sieve is deterministic
+        if (!(bits_ready && i == 0 && j == descs.size())) {
+            // the bitmaps of this batch's segments (the counting pass kept none)
+            std::vector<uint32_t> again(j - i);
+            WV_TRY(sieve_count(c, descs.data() + i, j - i, true, again.data()));
+            for (size_t k = 0; k < again.size(); k++)
+                if (again[k] != counts[i + k]) return WV_EHIP;   // the sieve is deterministic
+        }
         uint64_t got = 0;
         WV_TRY(compact(c, descs.data() + i, j - i, counts.data() + i, &got));
         WV_HIP(hipEventRecord(c->ev[EV_SIEVE], st));
-        WV_HIP(hipEventSynchronize(c->ev[EV_SIEVE]));
-        c->stats.ms_sieve += elapsed(c->ev[EV_START], c->ev[EV_SIEVE]);
         WV_TRY(ensure(c, c->results, got * sizeof(wv_result)));
         uint64_t pmax = 0;
         for (size_t k = i; k < j; k++) pmax = std::max(pmax, std::min(descs[k].hi, descs[k].L + kSegSpan));
         WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)got, pmax, as<wv_result>(c->results)));
+        c->stats.ms_sieve += elapsed(c->ev[EV_START], c->ev[EV_SIEVE]);   // both recorded before its wait
         if (out && !dest)
             WV_HIP(hipMemcpyAsync(out + written, c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
         if (out && dest) {
@@ -768,7 +769,9 @@ int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t 
     }
     first[nwin] = d.size();
     std::vector<uint32_t> counts(d.size());
-    if (!d.empty()) WV_TRY(sieve_count(c, d.data(), d.size(), false, counts.data()));
+    // a single batch's worth of segments keeps its bitmaps from this count
+    const bool keep = d.size() <= kMaxBatchSegs;
+    if (!d.empty()) WV_TRY(sieve_count(c, d.data(), d.size(), keep, counts.data()));
     uint64_t total = 0;
     for (size_t w = 0; w < nwin; w++) {
         if (win_off) win_off[w] = (size_t)total;
@@ -796,12 +799,14 @@ int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t 
     std::vector<SegDesc> ds(d.size());
     std::vector<uint32_t> cs(d.size());
     std::vector<uint64_t> dst(d.size());
+    bool same_order = true;
     for (size_t k = 0; k < ord.size(); k++) {
         ds[k] = d[ord[k]];
         cs[k] = counts[ord[k]];
         dst[k] = dest[ord[k]];
+        same_order &= ord[k] == k;
     }
-    return search_descs(c, ds, cs, out, nullptr, dst.data());
+    return search_descs(c, ds, cs, out, nullptr, dst.data(), keep && same_order);
 }
 
 int wv_range_stats(wv_ctx *c, uint64_t lo, uint64_t hi, uint32_t bins, uint64_t near_bound, uint64_t *hist_b,

@@ -191,9 +191,10 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
             hipStream_t st = nullptr);
 // out: host results (may be NULL when sink is set), written contiguously in
 // desc order, or, with dest, the primes of descs[k] at out + dest[k];
-// sink: device statistics
+// sink: device statistics; bits_ready: the counting pass kept the bitmaps of
+// every descriptor, in this order, in c->seg_bits
 int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts,
-                 wv_result *out, StatsSink *sink = nullptr, const uint64_t *dest = nullptr);
+                 wv_result *out, StatsSink *sink = nullptr, const uint64_t *dest = nullptr, bool bits_ready = false);
 void pick_tuned(wv_ctx *c, uint64_t pmax);
 // device address of the fixed scratch array on `device` (current), looked up
 // once per device (wv_static.hip)

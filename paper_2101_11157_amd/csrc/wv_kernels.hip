@@ -153,26 +153,30 @@ __global__ void __launch_bounds__(1024) k_seg_sieve(const SegDesc *__restrict__ 
     const uint64_t H = min(L + kSegSpan, hi);
     for (int w = tid; w < kSegWords; w += 1024) bits[w] = 0;
     __syncthreads();
+    // only [max(lo, L + 1), H) is kept (the count masks the rest): composites
+    // are marked there, bits i < i_end hold n = L + 2i + 1 up to H
+    const uint64_t first = max(lo, L + 1);
+    const uint64_t i_end = min((uint64_t)kSegBits, (H - L + 1) >> 1);
     // primes below 2048 (the first 308 odd ones): all threads stride one prime
     const uint32_t n_coop = min(n_bp, 308u);
     for (uint32_t k = 0; k < n_coop; k++) {
         const uint64_t q = bp[k];
         if (q * q >= H) break;
-        uint64_t x = max(q * q, L + 1);
+        uint64_t x = max(q * q, first);
         uint64_t m0 = ((x + q - 1) / q) * q;
         if (!(m0 & 1)) m0 += q;
         const uint64_t i0 = (m0 - L - 1) >> 1;
-        for (uint64_t i = i0 + (uint64_t)tid * q; i < (uint64_t)kSegBits; i += 1024 * q)
+        for (uint64_t i = i0 + (uint64_t)tid * q; i < i_end; i += 1024 * q)
             atomicOr(&bits[i >> 5], 1u << (i & 31));
     }
     // larger primes: one prime per thread
     for (uint32_t k = n_coop + tid; k < n_bp; k += 1024) {
         const uint64_t q = bp[k];
         if (q * q >= H) break;
-        uint64_t x = max(q * q, L + 1);
+        uint64_t x = max(q * q, first);
         uint64_t m0 = ((x + q - 1) / q) * q;
         if (!(m0 & 1)) m0 += q;
-        for (uint64_t i = (m0 - L - 1) >> 1; i < (uint64_t)kSegBits; i += q)
+        for (uint64_t i = (m0 - L - 1) >> 1; i < i_end; i += q)
             atomicOr(&bits[i >> 5], 1u << (i & 31));
     }
     __syncthreads();
@@ -653,52 +657,86 @@ constexpr int kNumSumVariants = (int)(sizeof(kSumVariants) / sizeof(kSumVariants
 // per-sum reduction and finalize
 // --------------------------------------------------------------------------
 
-// One wave per (prime, sum): joins the stored pairs of its full chunks
+// Sums with at most this many full chunks are joined by one lane each.
+constexpr uint64_t kReduceLaneChunks = 16;
+
+// Every (prime, sum) j: joins the stored pairs of its full chunks
 // [off[j], off[j+1]) and, when C does not divide its length, the pair its tail
-// chunk left in seg_pairs[j]; the result replaces seg_pairs[j].
+// chunk left in seg_pairs[j]; the result replaces seg_pairs[j].  A wave takes
+// 64 consecutive sums: a lane joins its own sum when it has few full chunks,
+// and the wave joins each of the others together (lanes stride its chunks,
+// then a butterfly).
 __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs, const uint64_t *__restrict__ off,
                                                 uint32_t nseg, const PrimeRec *__restrict__ pr,
                                                 const Pair *__restrict__ partials,
                                                 const uint64_t *__restrict__ layout, Pair *__restrict__ seg_pairs) {
     const uint64_t C = layout[0];
-    // wave-stride loop: one launch covers at most 2^32 work-items, fewer than
-    // 64 per sum when there are more than 2^26 sums
+    // wave-stride loop over groups of 64 sums (one launch covers at most 2^32
+    // work-items)
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t ngroups = (nseg + 63) >> 6;
     const int lane = threadIdx.x & 63;
-    for (uint32_t jw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; jw < nseg; jw += nwaves) {
-        const uint32_t j = __builtin_amdgcn_readfirstlane(jw);   // scalar: loop exits are wave-uniform
-        const uint64_t a = off[j], b = off[j + 1];
-        const SegRec sr = segs[j];
-        const Mont m = mont_of(pr[sr.prime]);
-        uint64_t c0 = 1, c1 = 0;
-        if (lane == 0 && sr.len % C) {
-            const Pair q = seg_pairs[j];
-            c0 = q.c0;
-            c1 = q.c1;
-        }
-        const uint64_t ff = (a + 63) & ~63ull;   // first 64-aligned window start
-        const uint64_t lf = b & ~63ull;          // end of the last full window
-        if (ff >= lf) {
-            for (uint64_t i = a + lane; i < b; i += 64) {
-                const Pair q = partials[i];
-                pair_mul(c0, c1, q.c0, q.c1, m);
-            }
-        } else {
-            for (uint64_t i = a + lane; i < ff; i += 64) {
-                const Pair q = partials[i];
-                pair_mul(c0, c1, q.c0, q.c1, m);
-            }
-            for (uint64_t w = ff + 64ull * lane; w < lf; w += 64ull * 64) {
-                const Pair q = partials[w];
-                pair_mul(c0, c1, q.c0, q.c1, m);
-            }
-            for (uint64_t i = lf + lane; i < b; i += 64) {
-                const Pair q = partials[i];
-                pair_mul(c0, c1, q.c0, q.c1, m);
+    for (uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; gw < ngroups; gw += nwaves) {
+        const uint32_t g = __builtin_amdgcn_readfirstlane(gw);   // scalar: loop exits are wave-uniform
+        const uint32_t j = g * 64 + lane;
+        bool big = false;
+        if (j < nseg) {
+            const uint64_t a = off[j], b = off[j + 1];
+            big = b - a > kReduceLaneChunks;
+            if (!big) {
+                const SegRec sr = segs[j];
+                const Mont m = mont_of(pr[sr.prime]);
+                uint64_t c0 = 1, c1 = 0;
+                if (sr.len % C) {
+                    const Pair q = seg_pairs[j];
+                    c0 = q.c0;
+                    c1 = q.c1;
+                }
+                for (uint64_t i = a; i < b; i++) {
+                    const Pair q = partials[i];
+                    pair_mul(c0, c1, q.c0, q.c1, m);
+                }
+                seg_pairs[j] = Pair{c0, c1};
             }
         }
-        wave_pair_reduce(c0, c1, m);
-        if (lane == 0) seg_pairs[j] = Pair{c0, c1};
+        uint64_t todo = __ballot(big);
+        while (todo) {
+            const int l = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t k = g * 64 + l;   // wave-uniform
+            const uint64_t a = off[k], b = off[k + 1];
+            const SegRec sr = segs[k];
+            const Mont m = mont_of(pr[sr.prime]);
+            uint64_t c0 = 1, c1 = 0;
+            if (lane == 0 && sr.len % C) {
+                const Pair q = seg_pairs[k];
+                c0 = q.c0;
+                c1 = q.c1;
+            }
+            const uint64_t ff = (a + 63) & ~63ull;   // first 64-aligned window start
+            const uint64_t lf = b & ~63ull;          // end of the last full window
+            if (ff >= lf) {
+                for (uint64_t i = a + lane; i < b; i += 64) {
+                    const Pair q = partials[i];
+                    pair_mul(c0, c1, q.c0, q.c1, m);
+                }
+            } else {
+                for (uint64_t i = a + lane; i < ff; i += 64) {
+                    const Pair q = partials[i];
+                    pair_mul(c0, c1, q.c0, q.c1, m);
+                }
+                for (uint64_t w = ff + 64ull * lane; w < lf; w += 64ull * 64) {
+                    const Pair q = partials[w];
+                    pair_mul(c0, c1, q.c0, q.c1, m);
+                }
+                for (uint64_t i = lf + lane; i < b; i += 64) {
+                    const Pair q = partials[i];
+                    pair_mul(c0, c1, q.c0, q.c1, m);
+                }
+            }
+            wave_pair_reduce(c0, c1, m);
+            if (lane == 0) seg_pairs[k] = Pair{c0, c1};
+        }
     }
 }
 
@@ -967,8 +1005,9 @@ hipError_t launch_sum(hipStream_t st, int v, unsigned grid, const SegRec *segs, 
 
 hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off, uint32_t nseg, const PrimeRec *pr,
                          const Pair *partials, const uint64_t *layout, Pair *seg_pairs) {
-    // at most 2^20 workgroups (2^28 work-items; a dispatch holds < 2^32)
-    const unsigned grid = std::min<unsigned>(blocks_for((uint64_t)nseg * 64, 256), 1u << 20);
+    // a wave per 64 sums, at most 2^20 workgroups (2^28 work-items; a
+    // dispatch holds < 2^32)
+    const unsigned grid = std::min<unsigned>(blocks_for((uint64_t)nseg, 256), 1u << 20);
     hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, st, segs, off, nseg, pr, partials, layout, seg_pairs);
     return hipGetLastError();
 }

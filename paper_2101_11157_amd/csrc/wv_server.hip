@@ -15,15 +15,20 @@
 // completes.  New requests join at the next step, so short requests overtake
 // long ones instead of queueing behind them.
 //
-// Everything the server enqueues goes on the context stream, in order:
-// admission work (sieve, compaction, plan into the pool) runs between steps,
-// and the host never waits for the device except for the oldest step in
-// flight.  A call of wv_server_step admits what fits, launches the next step
-// and then waits for the step launched by the previous call, so one step is
-// always queued behind the running one while the host plans.  The host keeps
-// no per-sum state: a request is its pool slots and the number of its primes
-// handed out.  Host-to-device copies come from pinned staging buffers, so no
-// copy waits for the device.
+// Steps alternate between two streams (the context's and the server's own),
+// one per set of step buffers, so that the next step's term sums take over
+// the compute units as the running step's last waves finish instead of after
+// them.  A call of wv_server_step admits what fits (sieve, compaction, plan
+// into the pool, on the stream of the step it launches next), launches that
+// step and then waits for the step launched by the previous call; the host
+// never waits for the device otherwise.  Events order what crosses the
+// streams: a step waits for the admissions enqueued on the other stream, and
+// a step that finalizes a request waits for the other stream's last fold
+// before its finalize (every sum is folded by exactly one step, so the folds
+// themselves never touch the same pair).  The host keeps no per-sum state: a
+// request is its pool slots and the number of its primes handed out.
+// Host-to-device copies come from pinned staging buffers, so no copy waits
+// for the device.
 //
 // Because the pair product is associative and commutative and all arithmetic
 // is exact, a request's residues do not depend on how its work was cut into
@@ -114,6 +119,10 @@ struct Upload {
 
 struct wv_server {
     wv_ctx *c = nullptr;
+    hipStream_t own = nullptr;  // the second stream (set 1's); set 0 uses the context's
+    hipEvent_t ev_adm[2] = {}, ev_fold[2] = {}, ev_ref = nullptr;
+    bool adm_pending[2] = {}, adm_recorded[2] = {}, fold_recorded[2] = {};
+    double busy_end_ms = 0, sum_end_ms = 0;   // ends of the device intervals counted so far (from ev_ref)
     uint64_t step_terms = 1ull << 38;
     uint32_t pool = 1u << 16;
     int tb = 0, te = 0;        // congruences fixed at creation (the pool layout depends on them)
@@ -142,6 +151,8 @@ struct wv_server {
 };
 
 namespace {
+
+hipStream_t stream_of(const wv_server *s, int k) { return k == 0 ? s->c->stream : s->own; }
 
 // Tasks per step at most (whole primes of nB + nE sums each).
 constexpr uint64_t kMaxStepTasks = 1ull << 22;
@@ -221,7 +232,7 @@ double terms_per_prime(const wv_server *s, uint64_t p) {
 }
 
 // Stage n bytes for a host-to-device copy into the current upload half.
-int stage_upload(wv_server *s, const void *src, size_t n, void *dst) {
+int stage_upload(wv_server *s, const void *src, size_t n, void *dst, hipStream_t st) {
     Upload &u = s->up[s->up_cur];
     if (u.used + n > u.cap) {
         if (u.used) return WV_EBUSY;   // full: the caller retries in a later call
@@ -233,7 +244,7 @@ int stage_upload(wv_server *s, const void *src, size_t n, void *dst) {
         u.cap = n;
     }
     memcpy(u.h + u.used, src, n);
-    WV_HIP(hipMemcpyAsync(dst, u.h + u.used, n, hipMemcpyHostToDevice, s->c->stream));
+    WV_HIP(hipMemcpyAsync(dst, u.h + u.used, n, hipMemcpyHostToDevice, st));
     u.used = (u.used + n + 255) & ~(size_t)255;
     return WV_OK;
 }
@@ -260,12 +271,11 @@ void fail_request(wv_server *s, Request *r, int status) {
     s->failed++;
 }
 
-// Plans a pending request into the pool (enqueued on the context stream).
-// Sets *admitted false when there is no room yet (slots, or staging for its
-// copies); an error return leaves no pool slot taken.
-int admit(wv_server *s, Request *r, bool *admitted) {
+// Plans a pending request into the pool (enqueued on st).  Sets *admitted
+// false when there is no room yet (slots, or staging for its copies); an
+// error return leaves no pool slot taken.
+int admit(wv_server *s, Request *r, bool *admitted, hipStream_t st) {
     wv_ctx *c = s->c;
-    hipStream_t st = c->stream;
     *admitted = false;
     const uint64_t n = r->n_primes;   // submission checked n <= pool
     if (n == 0) {
@@ -282,7 +292,7 @@ int admit(wv_server *s, Request *r, bool *admitted) {
     if (r->is_range) {
         std::vector<SegDesc> d;
         window_descs(r->lo, r->hi, d);   // at most kMaxBatchSegs (checked at submission)
-        rc = stage_upload(s, d.data(), d.size() * sizeof(SegDesc), s->sdesc.ptr);
+        rc = stage_upload(s, d.data(), d.size() * sizeof(SegDesc), s->sdesc.ptr, st);
         if (rc == WV_OK && (launch_seg_sieve(st, as<SegDesc>(s->sdesc), (unsigned)d.size(), as<uint32_t>(c->base_primes),
                                              c->n_base, as<uint32_t>(s->sbits), as<uint32_t>(s->scount)) != hipSuccess ||
                             launch_seg_offsets(st, as<uint32_t>(s->scount), (unsigned)d.size(), n, as<uint64_t>(s->soff),
@@ -291,7 +301,7 @@ int admit(wv_server *s, Request *r, bool *admitted) {
                                                as<uint64_t>(s->soff), dp, n) != hipSuccess))
             rc = WV_EHIP;
     } else {
-        rc = stage_upload(s, r->primes.data(), n * sizeof(uint64_t), dp);
+        rc = stage_upload(s, r->primes.data(), n * sizeof(uint64_t), dp, st);
     }
     if (rc == WV_OK) {
         const size_t first = (size_t)base * s->NS, nseg = (size_t)n * s->NS;
@@ -318,7 +328,7 @@ int admit(wv_server *s, Request *r, bool *admitted) {
 }
 
 // Restart every active request from its plan (after a failed step; nothing is
-// in flight).
+// in flight on either stream).
 int readmit_all(wv_server *s) {
     for (Request *r : s->active) {
         r->next = 0;
@@ -332,9 +342,10 @@ int readmit_all(wv_server *s) {
 // Chooses the next step's primes on the host -- an even share of the budget
 // for every active request with primes left, then what is left of the budget
 // to the smallest remaining work first, at least one prime per step -- and
-// launches the step on the context stream with buffer set `ss`.  The requests'
-// counters advance now.  *launched is false when no request has primes left.
-int launch_step(wv_server *s, StepSet &ss, bool *launched) {
+// launches the step with buffer set k on its stream.  The requests' counters
+// advance now.  *launched is false when no request has primes left.
+int launch_step(wv_server *s, int sk, bool *launched) {
+    StepSet &ss = s->set[sk];
     wv_ctx *c = s->c;
     *launched = false;
     std::vector<Request *> cand;
@@ -416,9 +427,14 @@ int launch_step(wv_server *s, StepSet &ss, bool *launched) {
     memcpy(ss.spans_h, spans.data(), spans.size() * sizeof(StepSpan));
     if (!fins.empty()) memcpy(ss.fin_h, fins.data(), fins.size() * sizeof(FinReq));
 
-    hipStream_t st = c->stream;
+    hipStream_t st = stream_of(s, sk);
     uint64_t *scal = as<uint64_t>(ss.scal);
     uint64_t *off = as<uint64_t>(ss.off);
+    // admissions enqueued on the other stream come first
+    if (s->adm_pending[1 - sk]) {
+        WV_HIP(hipStreamWaitEvent(st, s->ev_adm[1 - sk], 0));
+        s->adm_pending[1 - sk] = false;
+    }
     WV_HIP(hipEventRecord(ss.ev0, st));
     WV_HIP(hipMemcpyAsync(ss.spans.ptr, ss.spans_h, spans.size() * sizeof(StepSpan), hipMemcpyHostToDevice, st));
     if (!fins.empty())
@@ -445,7 +461,12 @@ int launch_step(wv_server *s, StepSet &ss, bool *launched) {
                          scal + kScalLayout, as<Pair>(ss.tpairs)));
     WV_HIP(launch_fold(st, as<SegRec>(ss.tasks), as<uint32_t>(ss.target), as<Pair>(ss.tpairs), (uint32_t)nt,
                        as<PrimeRec>(s->pr), as<Pair>(s->acc)));
+    WV_HIP(hipEventRecord(s->ev_fold[sk], st));
+    s->fold_recorded[sk] = true;
     if (!fins.empty()) {
+        // the finalized requests' earlier primes may have been folded by the
+        // other stream's step
+        if (s->fold_recorded[1 - sk]) WV_HIP(hipStreamWaitEvent(st, s->ev_fold[1 - sk], 0));
         WV_HIP(launch_finalize_multi(st, table_store(c), as<PrimeRec>(s->pr), as<Pair>(s->acc),
                                      as<uint64_t>(s->coefs), as<uint64_t>(s->lhsmod), as<FinReq>(ss.fin),
                                      (uint32_t)fins.size(), nres, s->nB, s->nE, as<wv_result>(ss.res),
@@ -467,11 +488,17 @@ int launch_step(wv_server *s, StepSet &ss, bool *launched) {
 int complete_step(wv_server *s, StepSet &ss) {
     WV_HIP(hipEventSynchronize(ss.ev1));
     ss.busy = false;
-    float ms = 0.f, ms_sum = 0.f;
-    (void)hipEventElapsedTime(&ms, ss.ev0, ss.ev1);
-    (void)hipEventElapsedTime(&ms_sum, ss.ev_sum0, ss.ev_sum);
-    s->busy_s += ms * 1e-3;
-    s->sum_s += ms_sum * 1e-3;
+    // device time: the union of the steps' intervals (consecutive steps on the
+    // two streams overlap), measured from the reference event
+    float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+    (void)hipEventElapsedTime(&a0, s->ev_ref, ss.ev0);
+    (void)hipEventElapsedTime(&a1, s->ev_ref, ss.ev1);
+    (void)hipEventElapsedTime(&b0, s->ev_ref, ss.ev_sum0);
+    (void)hipEventElapsedTime(&b1, s->ev_ref, ss.ev_sum);
+    s->busy_s += std::max(0.0, a1 - std::max<double>(a0, s->busy_end_ms)) * 1e-3;
+    s->busy_end_ms = std::max<double>(s->busy_end_ms, a1);
+    s->sum_s += std::max(0.0, b1 - std::max<double>(b0, s->sum_end_ms)) * 1e-3;
+    s->sum_end_ms = std::max<double>(s->sum_end_ms, b1);
     s->steps++;
     if (ss.scal_h[kScalErr]) return WV_EHIP;   // the term sums did not cover every chunk: discard the step
     if (s->fault_after >= 0 && (int64_t)s->steps > s->fault_after) {
@@ -556,6 +583,13 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
         wv_server_destroy(s);
         return rc;
     }
+    if (hipStreamCreateWithFlags(&s->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&s->ev_ref) != hipSuccess || hipEventRecord(s->ev_ref, c->stream) != hipSuccess)
+        rc = WV_EHIP;
+    for (int k = 0; k < 2 && rc == WV_OK; k++)
+        if (hipEventCreateWithFlags(&s->ev_adm[k], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s->ev_fold[k], hipEventDisableTiming) != hipSuccess)
+            rc = WV_EHIP;
     for (int k = 0; k < 2 && rc == WV_OK; k++) {
         StepSet &ss = s->set[k];
         if ((rc = ensure(c, ss.scal, 8 * sizeof(uint64_t))) != WV_OK) break;
@@ -589,6 +623,7 @@ int wv_server_inject_fault(wv_server *s, int after_steps) {
 int wv_server_destroy(wv_server *s) {
     if (!s) return WV_OK;
     if (s->c) (void)hipStreamSynchronize(s->c->stream);
+    if (s->own) (void)hipStreamSynchronize(s->own);
     DevBuf *bufs[] = {&s->pr, &s->segs, &s->acc, &s->terms, &s->coefs, &s->lhsmod, &s->plist,
                       &s->sdesc, &s->scount, &s->sbits, &s->soff};
     for (DevBuf *b : bufs)
@@ -609,6 +644,10 @@ int wv_server_destroy(wv_server *s) {
         if (u.h) (void)hipHostFree(u.h);
         if (u.ev) (void)hipEventDestroy(u.ev);
     }
+    hipEvent_t sev[] = {s->ev_adm[0], s->ev_adm[1], s->ev_fold[0], s->ev_fold[1], s->ev_ref};
+    for (hipEvent_t e : sev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->own) (void)hipStreamDestroy(s->own);
     for (auto &kv : s->all) delete kv.second;
     delete s;
     return WV_OK;
@@ -694,6 +733,11 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     });
     size_t admitted_sums = 0;
     std::deque<Request *> waiting;
+    const hipStream_t ast = stream_of(s, s->next);   // the stream of the step launched next
+    bool enqueued = false;
+    // admissions share the sieve buffers: the other stream's come first
+    if (!s->pending.empty() && s->adm_recorded[1 - s->next])
+        WV_HIP(hipStreamWaitEvent(ast, s->ev_adm[1 - s->next], 0));
     while (!s->pending.empty()) {
         Request *r = s->pending.front();
         s->pending.pop_front();
@@ -702,20 +746,29 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
             continue;
         }
         bool ok = false;
-        const int rc = admit(s, r, &ok);
+        const int rc = admit(s, r, &ok, ast);
         if (rc != WV_OK) {
             // the request ends with this error (wv_server_result returns it)
             fail_request(s, r, rc);
             continue;
         }
-        if (!ok) waiting.push_back(r);
-        else admitted_sums += (size_t)r->n * s->NS;
+        if (!ok) {
+            waiting.push_back(r);
+        } else {
+            admitted_sums += (size_t)r->n * s->NS;
+            enqueued |= r->n > 0;
+        }
     }
     s->pending.swap(waiting);
     if (u.used) {
-        WV_HIP(hipEventRecord(u.ev, s->c->stream));
+        WV_HIP(hipEventRecord(u.ev, ast));
         u.pending = true;
         s->up_cur ^= 1;
+    }
+    if (enqueued) {
+        WV_HIP(hipEventRecord(s->ev_adm[s->next], ast));
+        s->adm_pending[s->next] = true;
+        s->adm_recorded[s->next] = true;
     }
     // launch the next step, then wait for the older step in flight (or, when
     // nothing new was launched, for the one still in flight)
@@ -723,7 +776,7 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
     StepSet &older = s->set[1 - s->next];
     int rc = WV_OK;
     bool launched = false;
-    if (!nx.busy) rc = launch_step(s, nx, &launched);
+    if (!nx.busy) rc = launch_step(s, s->next, &launched);
     if (rc == WV_OK) {
         if (launched) s->next = 1 - s->next;
         if (older.busy) rc = complete_step(s, older);
@@ -734,6 +787,7 @@ int wv_server_step(wv_server *s, uint32_t *n_active, uint32_t *n_pending) {
         // every step in flight is discarded: the active requests restart from
         // their plans, or end with the error after repeated failures
         (void)hipStreamSynchronize(s->c->stream);
+        (void)hipStreamSynchronize(s->own);
         for (StepSet &ss : s->set) {
             ss.busy = false;
             ss.finishing.clear();

@@ -597,7 +597,7 @@ def test_batch_windows_seed0_full_batch():
 def test_window_1e11_whole_subwindow_two_table_sets():
     """The bench's first timed sub-window at the paper's ceiling,
     [1e11 - 1e6, 1e11 - 1e6 + 8192), in full with two independent congruence
-    sets (the derived 1408/1283-sum tables and the printed eqnBB30 +
+    sets (the derived tables of thousands of sums and the printed eqnBB30 +
     eqnEE33: different intervals and coefficients): every prime's residues
     agree, the prime list is the plain sieve's, and the stored oracle values
     inside the window match."""

@@ -100,10 +100,14 @@ def test_static_entry_matches_async_entry():
             want = oracle.residues(pick, method="table")
             by_p = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in s2}
             assert [by_p[p] for p in pick] == want
-            # derived congruences near 1e11: 2691 sums per prime, the fixed
-            # partial-pair area forces chunks longer than the automatic size
+            # derived congruences near 1e11 (thousands of sums per prime): as
+            # many primes as the fixed slot area holds, whose partial-pair
+            # area forces chunks longer than the automatic size
             ctx.use_derived_tables()
-            ps3 = oracle.primes(10 ** 11 - 10 ** 6, 10 ** 11 - 10 ** 6 + 3600)
+            per = sum(len(wv.derived_table(side)["terms"]) for side in "BE")
+            room = (1 << 19) // per
+            ps3 = oracle.primes(10 ** 11 - 10 ** 6, 10 ** 11 - 10 ** 6 + 3600)[:room]
+            assert len(ps3) >= 40
             say(f"case: static entry, call 3: {len(ps3)} primes near 1e11 (derived tables)")
             s3, a3 = run_both(ctx, hip, st.value, ps3)
             assert same(s3, a3)
@@ -111,7 +115,7 @@ def test_static_entry_matches_async_entry():
             # limits: refused before anything is enqueued
             d = hip.malloc(8 * 256)
             with pytest.raises(wv.WvError) as ei:
-                ctx.eval_primes_static(d, 200, d, st.value)   # 200 x 2691 slots > 2^19
+                ctx.eval_primes_static(d, room + 1, d, st.value)   # more slots than 2^19
             assert ei.value.status == wv.WV_EINVAL
             with pytest.raises(wv.WvError) as ei:
                 ctx.eval_primes_static(d, (1 << 16) + 1, d, st.value)
