@@ -48,7 +48,9 @@ BLOCK_ADD = {2: 3, 3: 5}
 # known size (profiles/k_sum_window_1e11_*.md).  A profile constant: valid only
 # for the kernel source, shape, tables and window it was taken on (keyed by the
 # hash of the kernel sources), reported as null otherwise.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("1e11", "derived 3798/3626", 28, 36, 8192, "02921c460da7"): 895347639,
+}
 
 
 def kernel_source_hash():

@@ -310,7 +310,8 @@ int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint
 }
 
 // Primes of descs[0..ns) (bitmaps already in c->seg_bits) into c->primes.
-int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out, hipStream_t st) {
+int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out, hipStream_t st,
+            bool descs_ready) {
     if (!st) st = c->stream;
     std::vector<uint64_t> offs(ns + 1, 0);
     for (size_t i = 0; i < ns; i++) offs[i + 1] = offs[i] + counts[i];
@@ -318,10 +319,27 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
     if (offs[ns] == 0) return WV_OK;
     WV_TRY(ensure(c, c->seg_off, (ns + 1) * sizeof(uint64_t)));
     WV_TRY(ensure(c, c->primes, offs[ns] * sizeof(uint64_t)));
-    WV_HIP(hipMemcpyAsync(c->seg_desc.ptr, descs, ns * sizeof(SegDesc), hipMemcpyHostToDevice, st));
+    if (!descs_ready)
+        WV_HIP(hipMemcpyAsync(c->seg_desc.ptr, descs, ns * sizeof(SegDesc), hipMemcpyHostToDevice, st));
     WV_HIP(hipMemcpyAsync(c->seg_off.ptr, offs.data(), (ns + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     WV_HIP(launch_seg_compact(st, as<SegDesc>(c->seg_desc), (unsigned)ns, as<uint32_t>(c->seg_bits),
                               as<uint64_t>(c->seg_off), as<uint64_t>(c->primes), offs[ns]));
+    return WV_OK;
+}
+
+int results_to_host(wv_ctx *c, const wv_result *d, size_t n, wv_result *out) {
+    if (n == 0) return WV_OK;
+    if (n > c->pin_res_cap) {
+        const size_t want = std::max(n, c->pin_res_cap + c->pin_res_cap / 2);
+        wv_result *h = nullptr;
+        if (hipHostMalloc((void **)&h, want * sizeof(wv_result), hipHostMallocDefault) != hipSuccess) return WV_ENOMEM;
+        if (c->pin_res) (void)hipHostFree(c->pin_res);
+        c->pin_res = h;
+        c->pin_res_cap = want;
+    }
+    WV_HIP(hipMemcpyAsync(c->pin_res, d, n * sizeof(wv_result), hipMemcpyDeviceToHost, c->stream));
+    WV_HIP(hipStreamSynchronize(c->stream));
+    std::memcpy(out, c->pin_res, n * sizeof(wv_result));
     return WV_OK;
 }
 
@@ -356,7 +374,8 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
             continue;
         }
         WV_HIP(hipEventRecord(c->ev[EV_START], st));
-        if (!(bits_ready && i == 0 && j == descs.size())) {
+        const bool whole = bits_ready && i == 0 && j == descs.size();
+        if (!whole) {
             // the bitmaps of this batch's segments (the counting pass kept none)
             std::vector<uint32_t> again(j - i);
             WV_TRY(sieve_count(c, descs.data() + i, j - i, true, again.data()));
@@ -364,19 +383,19 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
                 if (again[k] != counts[i + k]) return WV_EHIP;   // the sieve is deterministic
         }
         uint64_t got = 0;
-        WV_TRY(compact(c, descs.data() + i, j - i, counts.data() + i, &got));
+        // the counting pass (or the re-sieve just above) left these
+        // descriptors in c->seg_desc when they fit one launch
+        WV_TRY(compact(c, descs.data() + i, j - i, counts.data() + i, &got, nullptr, j - i <= kSieveLaunch));
         WV_HIP(hipEventRecord(c->ev[EV_SIEVE], st));
         WV_TRY(ensure(c, c->results, got * sizeof(wv_result)));
         uint64_t pmax = 0;
         for (size_t k = i; k < j; k++) pmax = std::max(pmax, std::min(descs[k].hi, descs[k].L + kSegSpan));
         WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes), (uint32_t)got, pmax, as<wv_result>(c->results)));
         c->stats.ms_sieve += elapsed(c->ev[EV_START], c->ev[EV_SIEVE]);   // both recorded before its wait
-        if (out && !dest)
-            WV_HIP(hipMemcpyAsync(out + written, c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
+        if (out && !dest) WV_TRY(results_to_host(c, as<wv_result>(c->results), got, out + written));
         if (out && dest) {
             staging.resize(got);
-            WV_HIP(hipMemcpyAsync(staging.data(), c->results.ptr, got * sizeof(wv_result), hipMemcpyDeviceToHost, st));
-            WV_HIP(hipStreamSynchronize(st));
+            WV_TRY(results_to_host(c, as<wv_result>(c->results), got, staging.data()));
             uint64_t o = 0;
             for (size_t k = i; k < j; k++) {
                 std::memcpy(out + dest[k], staging.data() + o, counts[k] * sizeof(wv_result));
@@ -655,6 +674,7 @@ int wv_destroy(wv_ctx *c) {
         if (b->ptr) (void)hipFree(b->ptr);
     for (int i = 0; i < EV_COUNT; i++)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->pin_res) (void)hipHostFree(c->pin_res);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return WV_OK;
@@ -883,9 +903,7 @@ int wv_eval_primes(wv_ctx *c, const uint64_t *primes, size_t n, wv_result *out) 
         const size_t k = std::min(step, n - b);
         WV_TRY(run_batch_sync(c, as<uint64_t>(c->primes) + b, (uint32_t)k, pmax + 1, as<wv_result>(c->results) + b));
     }
-    WV_HIP(hipMemcpyAsync(out, c->results.ptr, n * sizeof(wv_result), hipMemcpyDeviceToHost, c->stream));
-    WV_HIP(hipStreamSynchronize(c->stream));
-    return WV_OK;
+    return results_to_host(c, as<wv_result>(c->results), n, out);
 }
 
 int wv_eval_sums(wv_ctx *c, const uint64_t *primes, size_t n, uint64_t *out_b, uint64_t *out_e) {

@@ -138,6 +138,8 @@ struct wv_ctx {
     std::vector<wv::GraphEntry> graphs;
     std::vector<wv::TuneEntry> tune;
     void *scratch = nullptr;                      // this device's fixed scratch array (wv_eval_primes_static)
+    wv_result *pin_res = nullptr;                 // pinned staging of results copied to the caller
+    size_t pin_res_cap = 0;
 };
 
 namespace wv {
@@ -187,8 +189,9 @@ uint64_t window_piece(const wv_ctx *c, uint64_t hi);
 // (compact leaves the compaction enqueued on st)
 int sieve_count(wv_ctx *c, const SegDesc *descs, size_t ns, bool keep_bits, uint32_t *counts,
                 hipStream_t st = nullptr);
+// descs_ready: c->seg_desc already holds descs[0..ns) (the sieve uploaded them)
 int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, uint64_t *np_out,
-            hipStream_t st = nullptr);
+            hipStream_t st = nullptr, bool descs_ready = false);
 // out: host results (may be NULL when sink is set), written contiguously in
 // desc order, or, with dest, the primes of descs[k] at out + dest[k];
 // sink: device statistics; bits_ready: the counting pass kept the bitmaps of
@@ -196,6 +199,10 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
 int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector<uint32_t> &counts,
                  wv_result *out, StatsSink *sink = nullptr, const uint64_t *dest = nullptr, bool bits_ready = false);
 void pick_tuned(wv_ctx *c, uint64_t pmax);
+// n results from the device to host memory `out` through the pinned staging
+// buffer (a pageable copy costs several times more); waits on the context
+// stream
+int results_to_host(wv_ctx *c, const wv_result *d, size_t n, wv_result *out);
 // device address of the fixed scratch array on `device` (current), looked up
 // once per device (wv_static.hip)
 int static_scratch_setup(int device, void **addr);
