@@ -191,8 +191,11 @@ int wv_count_primes(wv_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *n);
  * eqnBB30; Section 5: eqnEE3 ... eqnEE33; or defined ones), each sum
  * S(x, y) of eqnDefnS evaluated as c1/c0 by eqnComputeS and eqnCombinePairs,
  * and the flags of a Wolstenholme (b = 0) or Vandiver (e = 0) prime.
- * Sieve, then residues.  out[0..n)
- * receives the results in ascending p, where n = *n_out; if cap < n the call
+ * Sieve, then residues; a small interval (at most 64 sieve segments, an upper
+ * bound on its prime count no larger than cap, little work) runs as one
+ * replayed HIP graph sized by that bound, with the count taken on the device.
+ * out[0..n) receives the results in ascending p, where n = *n_out; if cap < n
+ * the call
  * writes nothing, sets *n_out = n and returns WV_ETRUNC.  hits (may be NULL
  * when hit_cap == 0) receives up to hit_cap primes whose flags are nonzero,
  * ascending; *n_hits (may be NULL) receives their total number.  All buffers
@@ -330,7 +333,7 @@ int wv_eval_primes_async(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
  * the process ends (looked up by wv_create); ctx contributes only its
  * congruence tables and settings.  Limits: n <= WV_STATIC_MAX_PRIMES and n
  * times the sums per prime <= WV_STATIC_MAX_SLOTS (524288: 8322 primes with
- * the printed tables, 194 with the package's derived ones); larger calls
+ * the printed tables, 70 with the package's derived ones); larger calls
  * return WV_EINVAL before enqueueing anything.  All calls on one GPU share
  * that GPU's array, which keeps the last call's contents: calls whose work
  * overlaps on one GPU (other streams, other contexts, other host threads)

@@ -327,16 +327,20 @@ int compact(wv_ctx *c, const SegDesc *descs, size_t ns, const uint32_t *counts, 
     return WV_OK;
 }
 
+int pin_res_reserve(wv_ctx *c, size_t n) {
+    if (n <= c->pin_res_cap) return WV_OK;
+    const size_t want = std::max(n, c->pin_res_cap + c->pin_res_cap / 2);
+    wv_result *h = nullptr;
+    if (hipHostMalloc((void **)&h, want * sizeof(wv_result), hipHostMallocDefault) != hipSuccess) return WV_ENOMEM;
+    if (c->pin_res) (void)hipHostFree(c->pin_res);
+    c->pin_res = h;
+    c->pin_res_cap = want;
+    return WV_OK;
+}
+
 int results_to_host(wv_ctx *c, const wv_result *d, size_t n, wv_result *out) {
     if (n == 0) return WV_OK;
-    if (n > c->pin_res_cap) {
-        const size_t want = std::max(n, c->pin_res_cap + c->pin_res_cap / 2);
-        wv_result *h = nullptr;
-        if (hipHostMalloc((void **)&h, want * sizeof(wv_result), hipHostMallocDefault) != hipSuccess) return WV_ENOMEM;
-        if (c->pin_res) (void)hipHostFree(c->pin_res);
-        c->pin_res = h;
-        c->pin_res_cap = want;
-    }
+    WV_TRY(pin_res_reserve(c, n));
     WV_HIP(hipMemcpyAsync(c->pin_res, d, n * sizeof(wv_result), hipMemcpyDeviceToHost, c->stream));
     WV_HIP(hipStreamSynchronize(c->stream));
     std::memcpy(out, c->pin_res, n * sizeof(wv_result));
@@ -566,6 +570,110 @@ void pick_tuned(wv_ctx *c, uint64_t pmax) {
         }
 }
 
+// An upper bound on the primes p with max(lo, 5) <= p < hi: the odd numbers
+// there, pi(x) < 1.25506 x / log x (Rosser and Schoenfeld) below hi, and
+// pi(x + y) - pi(x) <= 2 y / log y (Montgomery and Vaughan) for y > 1.
+uint64_t prime_count_bound(uint64_t lo, uint64_t hi) {
+    if (hi <= lo) return 0;
+    const uint64_t y = hi - lo;
+    uint64_t b = y / 2 + 2;
+    if (hi > 17) b = std::min<uint64_t>(b, (uint64_t)(1.25506 * (double)hi / std::log((double)hi)) + 2);
+    if (y > 1) b = std::min<uint64_t>(b, (uint64_t)(2.0 * (double)y / std::log((double)y)) + 2);
+    return b;
+}
+
+// A single-batch search replayed from one captured graph: sieve -> segment
+// offsets -> compaction -> plan -> term sums -> reduce -> finalize, sized by
+// an upper bound on the prime count (rounded up to a multiple of 1024; the
+// padding slots hold 0, which the plan rejects and which cost no term work).
+// The device counts the primes; the count, the batch's scalars and the
+// results come back after the call's one wait.  d: the segments (at most
+// kMaxBatchSegs), in ascending order, so the compacted primes ascend.
+int search_graph(wv_ctx *c, const std::vector<SegDesc> &d, uint64_t n_bound, uint64_t pmax, wv_result *out,
+                 size_t *n_out) {
+    hipStream_t st = c->stream;
+    const uint64_t ns = d.size();
+    const uint64_t n_pad = (n_bound + 1023) & ~1023ull;
+    BatchShape sh;
+    WV_TRY(batch_shape(c, (uint32_t)n_pad, pmax, &sh));
+    if (sh.nseg > kMaxBatchSlots) return WV_EINVAL;
+    WV_TRY(prepare(c, sh));
+    WV_TRY(ensure(c, c->seg_desc, ns * sizeof(SegDesc)));
+    WV_TRY(ensure(c, c->seg_counts, ns * sizeof(uint32_t)));
+    WV_TRY(ensure(c, c->seg_bits, ns * kSegWords * sizeof(uint32_t)));
+    WV_TRY(ensure(c, c->seg_off, (ns + 1) * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->pad_primes, n_pad * sizeof(uint64_t)));
+    WV_TRY(ensure(c, c->results, n_pad * sizeof(wv_result)));
+    WV_TRY(pin_res_reserve(c, n_pad));
+    const uint64_t chunk = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    hipGraphExec_t exec = nullptr;
+    for (GraphEntry &g : c->graphs)
+        if (g.ns == ns && g.n_pad == n_pad && g.gen == c->gen && g.variant == c->variant && g.tb == c->tb &&
+            g.te == c->te && g.chunk == chunk && g.tbl_b == sh.tb && g.tbl_e == sh.te)
+            exec = g.exec;
+    if (!exec) {
+        WV_HIP(hipStreamSynchronize(st));   // the capture stream must be idle
+        hipGraph_t graph = nullptr;
+        WV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const BatchBufs bufs = ctx_bufs(c);
+        uint64_t *primes = as<uint64_t>(c->pad_primes);
+        int rc = WV_OK;
+        if (launch_seg_sieve(st, as<SegDesc>(c->seg_desc), (unsigned)ns, as<uint32_t>(c->base_primes), c->n_base,
+                             as<uint32_t>(c->seg_bits), as<uint32_t>(c->seg_counts)) != hipSuccess ||
+            launch_copy_pad(st, primes, 0, primes, n_pad) != hipSuccess ||   // every slot 0 (padding)
+            launch_seg_offsets(st, as<uint32_t>(c->seg_counts), (unsigned)ns, UINT64_MAX, as<uint64_t>(c->seg_off),
+                               primes) != hipSuccess ||
+            launch_seg_compact(st, as<SegDesc>(c->seg_desc), (unsigned)ns, as<uint32_t>(c->seg_bits),
+                               as<uint64_t>(c->seg_off), primes, n_pad) != hipSuccess)
+            rc = WV_EHIP;
+        if (rc == WV_OK) rc = enqueue_plan(c, bufs, primes, sh, st);
+        if (rc == WV_OK) rc = enqueue_sum(c, bufs, sh, st, 0, UINT64_MAX);
+        if (rc == WV_OK) rc = enqueue_finish(c, bufs, sh, st, as<wv_result>(c->results));
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (rc != WV_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        WV_HIP(e);
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        WV_HIP(e);
+        GraphEntry g{n_pad, c->gen, c->variant, c->tb, c->te, chunk, exec};
+        g.ns = ns;
+        g.tbl_b = sh.tb;
+        g.tbl_e = sh.te;
+        c->graphs.push_back(g);
+    }
+    WV_HIP(hipMemcpyAsync(c->seg_desc.ptr, d.data(), ns * sizeof(SegDesc), hipMemcpyHostToDevice, st));
+    WV_HIP(hipEventRecord(c->ev[EV_PLAN0], st));
+    WV_HIP(hipGraphLaunch(exec, st));
+    WV_HIP(hipEventRecord(c->ev[EV_FINAL], st));
+    uint64_t host[9];
+    WV_HIP(hipMemcpyAsync(c->pin_res, c->results.ptr, n_pad * sizeof(wv_result), hipMemcpyDeviceToHost, st));
+    WV_HIP(hipMemcpyAsync(host, c->scal.ptr, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    WV_HIP(hipMemcpyAsync(host + 8, as<uint64_t>(c->seg_off) + ns, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    WV_HIP(hipStreamSynchronize(st));
+    if (host[kScalErr]) return WV_EHIP;   // the term sums did not cover every chunk
+    const uint64_t n = host[8];
+    if (n > n_pad) return WV_EHIP;        // cannot happen: the bound holds
+    std::memcpy(out, c->pin_res, n * sizeof(wv_result));
+    *n_out = (size_t)n;
+    wv_stats &s = c->stats;
+    const double ms = elapsed(c->ev[EV_PLAN0], c->ev[EV_FINAL]);
+    s.ms_total += ms;
+    s.ms_sum += ms;   // one graph: the phases are not timed apart
+    s.n_primes += n;
+    s.n_sums += n * (sh.nB + sh.nE);
+    s.n_chunks += host[kScalChunks];
+    s.n_terms += host[kScalTerms];
+    s.n_terms_b += host[kScalTermsB];
+    s.chunk_terms = host[kScalLayout];
+    s.block_k_b = (uint32_t)sum_variant_kb(c->variant);
+    s.block_k_e = (uint32_t)sum_variant_ke(c->variant);
+    s.grid = (uint32_t)c->sum_blocks[c->variant];
+    return WV_OK;
+}
+
 }  // namespace wv
 
 // ==========================================================================
@@ -788,6 +896,23 @@ int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t 
         if (hi[w] > lo[w]) pmax = std::max(pmax, hi[w] - 1);
     }
     first[nwin] = d.size();
+    // a small single-window search: one graph, sized by the prime-count bound
+    if (nwin == 1 && out && !d.empty() && d.size() <= kMaxBatchSegs && !c->progress) {
+        const uint64_t bound = prime_count_bound(std::max<uint64_t>(lo[0], 5), hi[0]);
+        const double work = (double)bound * (double)pmax * (side_cost(c, c->tb) + side_cost(c, c->te));
+        if (bound <= cap && bound <= kMaxBatchPrimes && work <= kGraphSearchTerms) {
+            c->stats = wv_stats{};
+            pick_tuned(c, pmax);
+            size_t n = 0;
+            WV_TRY(search_graph(c, d, bound, pmax + 1, out, &n));
+            *n_out = n;
+            if (win_off) {
+                win_off[0] = 0;
+                win_off[1] = n;
+            }
+            return WV_OK;
+        }
+    }
     std::vector<uint32_t> counts(d.size());
     // a single batch's worth of segments keeps its bitmaps from this count
     const bool keep = d.size() <= kMaxBatchSegs;
@@ -956,8 +1081,8 @@ int wv_eval_primes_async(wv_ctx *c, const uint64_t *d_primes, size_t n, wv_resul
     hipGraphExec_t exec = nullptr;
     const uint64_t chunk = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
     for (GraphEntry &g : c->graphs)
-        if (g.n_pad == n_pad && g.gen == c->gen && g.variant == c->variant && g.tb == c->tb && g.te == c->te &&
-            g.chunk == chunk)
+        if (g.ns == 0 && g.n_pad == n_pad && g.gen == c->gen && g.variant == c->variant && g.tb == c->tb &&
+            g.te == c->te && g.chunk == chunk)
             exec = g.exec;
     if (!exec) {
         // the capture stream must be idle: earlier work on it may still run

@@ -87,6 +87,8 @@ struct GraphEntry {
     int variant, tb, te;
     uint64_t chunk;
     hipGraphExec_t exec;
+    uint64_t ns = 0;       // search graphs: sieve segments (0: the eval graph)
+    int tbl_b = -1, tbl_e = -1;   // search graphs: the batch's table choice
 };
 
 // Per-batch consumer of device results that never go to the host: residue
@@ -203,6 +205,14 @@ void pick_tuned(wv_ctx *c, uint64_t pmax);
 // buffer (a pageable copy costs several times more); waits on the context
 // stream
 int results_to_host(wv_ctx *c, const wv_result *d, size_t n, wv_result *out);
+int pin_res_reserve(wv_ctx *c, size_t n);
+// an upper bound on the primes in [lo, hi) (lo >= 5)
+uint64_t prime_count_bound(uint64_t lo, uint64_t hi);
+// Work (terms, estimated from the prime-count bound) below which a
+// single-window search runs as one replayed graph (a few ms of the GPU).
+constexpr double kGraphSearchTerms = 17179869184.0;
+int search_graph(wv_ctx *c, const std::vector<SegDesc> &d, uint64_t n_bound, uint64_t pmax, wv_result *out,
+                 size_t *n_out);
 // device address of the fixed scratch array on `device` (current), looked up
 // once per device (wv_static.hip)
 int static_scratch_setup(int device, void **addr);

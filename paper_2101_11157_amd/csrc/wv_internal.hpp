@@ -119,9 +119,10 @@ hipError_t launch_seg_sieve(hipStream_t st, const SegDesc *desc, unsigned ns, co
 // primes of segment i at out[off[i] ..], written only below out[limit]
 hipError_t launch_seg_compact(hipStream_t st, const SegDesc *desc, unsigned ns, const uint32_t *bits,
                               const uint64_t *off, uint64_t *out, uint64_t limit);
-// off[0..ns] = exclusive prefix of counts[0..ns) (ns <= 1024); if the total is
-// not `expect`, every off[i] = expect (a compaction then writes nothing) and
-// primes[0..expect) = 0 (primes the plan rejects)
+// off[0..ns] = exclusive prefix of counts[0..ns) (ns <= 1024); unless expect
+// is UINT64_MAX, a total other than `expect` sets every off[i] = expect (a
+// compaction then writes nothing) and primes[0..expect) = 0 (primes the plan
+// rejects)
 hipError_t launch_seg_offsets(hipStream_t st, const uint32_t *counts, unsigned ns, uint64_t expect, uint64_t *off,
                               uint64_t *primes);
 // exclusive scan of n values into out[0..n], out[n] = total; tiles holds

@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) k_seg_offsets(const uint32_t *__restrict_
         total = a;
     }
     __syncthreads();
-    if (total == expect) return;
+    if (expect == UINT64_MAX || total == expect) return;   // UINT64_MAX: no count to check
     for (uint32_t i = threadIdx.x; i <= ns; i += 256) off[i] = expect;
     for (uint64_t i = threadIdx.x; i < expect; i += 256) primes[i] = 0;
 }

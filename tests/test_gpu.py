@@ -105,6 +105,36 @@ def test_theorem_1_1_hits(ctx):
             assert not f & wv.WV_FLAG_VANDIVER, p
 
 
+def test_small_search_graph_replays(ctx):
+    """A small single-window search runs as one replayed graph sized by a
+    prime-count bound: [5, 1e5) replayed three times with other work on the
+    context between the replays (an evaluation, a search that captures a graph
+    of another size, a search on the counted path) gives the oracle's primes
+    and residues every time."""
+    say("case: search graph replays")
+    ps = oracle.primes(5, 10 ** 5)
+    first, hits = ctx.search_range(5, 10 ** 5)
+    assert [int(p) for p in first["p"]] == ps
+    assert ctx.stats()["n_primes"] == len(ps) and ctx.stats()["n_terms"] > 0
+    sample = ps[::97]
+    by_p = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in first}
+    assert [by_p[p] for p in sample] == oracle.residues(sample)
+    assert sorted(int(h) for h in hits) == [149, 241, 16843]   # E_{p-3} == 0 at 149, 241; B_{p-3} == 0 at 16843
+    other_lo, other_hi = 10 ** 6, 10 ** 6 + 3000
+    big_lo, big_hi = 10 ** 9, 10 ** 9 + 2 ** 18        # enough work for the counted path
+    for k in range(3):
+        ev = ctx.eval_primes(oracle.primes(10 ** 6, 10 ** 6 + 300))
+        assert np.all(ev["flags"] != 0xFFFFFFFF)
+        other, _ = ctx.search_range(other_lo, other_hi)
+        assert [int(p) for p in other["p"]] == oracle.primes(other_lo, other_hi)
+        if k == 1:
+            big, _ = ctx.search_range(big_lo, big_hi)
+            assert len(big) == ctx.count_primes(big_lo, big_hi)
+        again, _ = ctx.search_range(5, 10 ** 5)
+        assert as_pairs(again) == as_pairs(first), k
+        assert [int(p) for p in again["p"]] == ps
+
+
 def test_smallest_primes_and_edges(ctx):
     say("case: p = 5 .. 101 and argument edges")
     ps = oracle.primes(5, 102)
