@@ -184,6 +184,7 @@ constexpr uint32_t kMmaReduceMax = 1024 / kMmaKc;   // chunks between reductions
 constexpr uint64_t kIrrMmaMaxP = 1ull << 24;
 constexpr int kMmaConsumers = 512;           // 8 consumer waves, 16 rows each
 constexpr int kMmaThreads = kMmaConsumers + 256;   // and 4 producer waves
+constexpr uint64_t kMmaMaxGrid = 1ull << 22;       // workgroups per launch (2^22 x 768 < 2^32 work-items)
 // LDS row stride (doubles) of A and of the transposed B: a wave's fragment
 // reads (16 rows x 4 s) then touch each bank pair at most twice
 constexpr int kMmaAs = kMmaKc + 4;
@@ -316,10 +317,10 @@ WV_UNROLL
 
 __global__ void __launch_bounds__(kMmaThreads) k_irr_mma(const IrrTask *__restrict__ tasks,
                                                          const uint64_t *__restrict__ unit_off, uint32_t ntask,
-                                                         uint64_t nunits, double *__restrict__ V) {
+                                                         uint64_t nunits, uint64_t unit_base, double *__restrict__ V) {
     __shared__ double As[2][kMmaRows * kMmaAs];
     __shared__ double Bs[2][kMmaRows * kMmaAs];
-    const uint64_t unit = blockIdx.x;
+    const uint64_t unit = unit_base + blockIdx.x;
     if (unit >= nunits) return;   // whole workgroup
     const uint32_t j = find_seg(unit_off, ntask, unit);
     const IrrTask T = tasks[j];
@@ -576,9 +577,12 @@ int irr_batch(wv_ctx *c, const std::vector<uint64_t> &ps, uint64_t *d_b, uint64_
     WV_HIP(launch_set_u64(st, as<uint64_t>(c->irr_counts), 4, 0));
     WV_HIP(hipEventRecord(c->ev[EV_SUM0], st));
     if (mma) {
-        if (nunits)
-            hipLaunchKernelGGL(k_irr_mma, dim3((unsigned)nunits), dim3(kMmaThreads), 0, st, as<IrrTask>(c->irr_tasks),
-                               as<uint64_t>(c->irr_units), ntask, nunits, as<double>(c->irr_v));
+        // one workgroup per unit, in launches of fewer than 2^32 work-items
+        for (uint64_t u0 = 0; u0 < nunits; u0 += kMmaMaxGrid) {
+            const uint64_t g = std::min<uint64_t>(kMmaMaxGrid, nunits - u0);
+            hipLaunchKernelGGL(k_irr_mma, dim3((unsigned)g), dim3(kMmaThreads), 0, st, as<IrrTask>(c->irr_tasks),
+                               as<uint64_t>(c->irr_units), ntask, nunits, u0, as<double>(c->irr_v));
+        }
     } else {
         hipLaunchKernelGGL(k_irr_sum, dim3(grid_for(nunits, 4)), dim3(256), 0, st, as<IrrTask>(c->irr_tasks),
                            as<uint64_t>(c->irr_units), ntask, nunits, as<double>(c->irr_v));

@@ -402,9 +402,13 @@ int launch_step(wv_server *s, int sk, bool *launched) {
     // partial pairs: room for the estimated terms at the configured (or
     // adaptive) chunk and for every task's tail; the device picks a chunk
     // size that fits whatever the terms turn out to be
-    const uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
-    const double chunk = chunk_cfg ? (double)chunk_cfg
-                                   : (double)adaptive_chunk((uint64_t)std::min(t_est, 1.8e19), sum_lanes(c));
+    // consecutive steps overlap on the two streams, so a step's ragged end
+    // costs little: its chunks are sized as for a launch four times its work
+    // (fewer chunk set-ups); a configured or tuned size is kept
+    uint64_t chunk_cfg = c->chunk_cfg ? c->chunk_cfg : c->chunk_auto;
+    if (!chunk_cfg)
+        chunk_cfg = (adaptive_chunk((uint64_t)std::min(4.0 * t_est, 1.8e19), sum_lanes(c)) + 63) & ~63ull;
+    const double chunk = (double)chunk_cfg;
     const uint64_t cap = std::max<uint64_t>(
         2 * nt, (uint64_t)std::min<double>(std::max<double>(t_est / chunk + 2.0 * nt, (double)kMinChunks),
                                            (double)kMaxChunks));
