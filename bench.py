@@ -103,7 +103,7 @@ def muls_per_term(d, k, period):
 def blocked_threshold(d, k):
     """Chunks shorter than this run the one-term (Montgomery) loop (chunk_blocked
     in the kernel)."""
-    return 4 * (d * k + 1) * k if k > 1 else float("inf")
+    return 8 * (d + 1) * k if k > 1 else float("inf")
 
 
 class OpsModel:
@@ -229,7 +229,7 @@ def use_tables(ctx, which):
         ctx.use_derived_tables()
         jb, je = wv.derived_table("B"), wv.derived_table("E")
         return (f"derived: {jb['n']}-sum B (cost {jb['cost'][0]}/{jb['cost'][1]}) and {je['n']}-sum E "
-                f"(cost {je['cost'][0]}/{je['cost'][1]}) for p >= 2^30, eqnBB30+eqnEE33 below")
+                f"(cost {je['cost'][0]}/{je['cost'][1]}) for p >= 3*2^29, eqnBB30+eqnEE33 below")
     return "eqnBB30+eqnEE33"
 
 
@@ -388,7 +388,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="terms per lane chunk (0: automatic)")
     ap.add_argument("--block", default="", help="term-sum block shape KB,KE (default: the library's)")
     ap.add_argument("--tables", default="derived", choices=["derived", "printed"],
-                    help="derived: the package's greedy-derived congruences (Section 2.2) above 2^30, "
+                    help="derived: the package's greedy-derived congruences (Section 2.2) above 3*2^29, "
                          "printed: eqnBB30 + eqnEE33")
     ap.add_argument("--irr-path", default="auto", choices=["auto", "valu", "mfma"],
                     help="irregular: power-sum kernel (auto: matrix cores below 2^24)")

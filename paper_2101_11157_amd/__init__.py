@@ -35,7 +35,7 @@ TABLE_NAMES = ["BB1", "BB2", "BB6", "BB9", "BB16", "BB22", "BB30",
 TABLE_ID = {n: i for i, n in enumerate(TABLE_NAMES)}
 # derived congruences shipped with the package (tables/make_tables.py)
 DERIVED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tables")
-DERIVED_MIN_P = 1 << 30     # below this the printed tables' fewer, longer sums are cheaper overall
+DERIVED_MIN_P = 3 << 29     # about 2^30.6: below this the printed tables' fewer, longer sums are cheaper overall
 
 
 def derived_table(side):

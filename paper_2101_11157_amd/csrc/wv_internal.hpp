@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -27,8 +28,14 @@ constexpr int kTailBuckets = 64;                 // length classes of the tail c
 constexpr int kTailClasses = 2 * kTailBuckets;   // (length class, side)
 
 // Length class of a tail of rem in [1, C) terms; class 0 holds the longest.
+// Classes are geometric, eight per octave below C (lengths within a class
+// differ by at most 9 %), so that the 64 tails of a wave have nearly equal
+// lengths also when the sums are much shorter than a chunk; tails below
+// C / 2^8 share the last class.
+constexpr int kTailPerOctave = 8;
 __host__ __device__ inline uint32_t tail_bucket(uint64_t rem, uint64_t C) {
-    return kTailBuckets - 1 - (uint32_t)((rem * kTailBuckets) / C);
+    const double x = log2((double)C / (double)rem) * kTailPerOctave;   // > 0 for rem < C
+    return x >= kTailBuckets - 1 ? (uint32_t)(kTailBuckets - 1) : (uint32_t)x;
 }
 
 // Order of a tail among all tails: by length class, longest first, and

@@ -527,10 +527,13 @@ __global__ void __launch_bounds__(256) k_tail_place(const uint64_t *__restrict__
 // Per-lane work of one chunk: the blocked loop with K terms per block (stepped
 // through the Taylor coefficients of prod_j (x + j)) when the chunk is long
 // enough to amortise building the difference tables, else one term per
-// iteration.
+// iteration.  Building the tables costs about 6 K (DEG + 1) (K + 1)
+// operations (25,000 at K = 28 on the s^-3 side); a block then costs about 6.5
+// per term against about 43 for the one-term Montgomery loop, so the blocked
+// loop wins from roughly 700 terms: it is taken from 8 K (DEG + 1).
 template <int DEG, int K>
 __device__ __forceinline__ bool chunk_blocked(uint64_t cnt) {
-    return K > 1 && cnt >= (uint64_t)4 * (DEG * K + 1) * K;
+    return K > 1 && cnt >= (uint64_t)8 * (DEG + 1) * K;
 }
 
 // Blocks between table reductions for p < 2^b (b <= 40): 53 - b.

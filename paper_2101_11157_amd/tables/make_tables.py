@@ -10,11 +10,12 @@ ties broken by piece order, then d), run by paper_2101_11157_amd.derive:
   cost p/30.47; the search keeps lowering the cost after that).
 
 More rounds trade more sums for fewer terms; at p near 1e11 a sum holds
-about half a million terms, so its fixed cost (a chunk set-up and a
-reduction) is small and the cheapest congruence wins.  800 rounds give 3798
-sums at cost p/50.73 (B) and 3626 sums at p/47.03 (E) and take about an hour
-per side; the search is deterministic, and continuing a saved congruence
-gives the same result as running the rounds in one go.
+about 350,000 terms, so its fixed cost (a chunk set-up and a reduction) is
+small and the cheapest congruence wins.  1200 rounds give 5849 sums at cost
+p/53.79 (B) and 5545 sums at p/50.18 (E) and take about two and a half hours
+per side (800 rounds: 3798 sums at p/50.73 and 3626 at p/47.03); the search
+is deterministic, and continuing a saved congruence gives the same result as
+running the rounds in one go.
 
 Usage: python -m paper_2101_11157_amd.tables.make_tables [B|E ...]
 """
@@ -28,8 +29,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from paper_2101_11157_amd import derive  # noqa: E402
 
-ROUNDS_B = 800
-ROUNDS_E = 800
+ROUNDS_B = 1200
+ROUNDS_E = 1200
 PLAN = {"B": ("Vandiver", ROUNDS_B), "E": ("EMac2", ROUNDS_E)}
 
 

@@ -1017,9 +1017,9 @@ def test_batch_over_2_26_slots_with_defined_tables():
 
 
 def test_batched_windows_with_derived_tables(ctx):
-    """Windows on both sides of the derived tables' 2^30 threshold in one
-    batched call equal the same windows searched alone (the printed tables
-    below 2^30, the derived ones above)."""
+    """Windows on both sides of the derived tables' threshold (3 * 2^29) in
+    one batched call equal the same windows searched alone (the printed tables
+    below it, the derived ones above)."""
     from paper_2101_11157_amd import workloads
     wins = workloads.batch_windows(0, 12, len_range=(1e2, 3e3), start_range=(1e8, 5e10))
     say(f"case: {len(wins)} windows, derived tables")
