@@ -596,7 +596,7 @@ int search_graph(wv_ctx *c, const std::vector<SegDesc> &d, uint64_t n_bound, uin
     const uint64_t n_pad = (n_bound + 1023) & ~1023ull;
     BatchShape sh;
     WV_TRY(batch_shape(c, (uint32_t)n_pad, pmax, &sh));
-    if (sh.nseg > kMaxBatchSlots) return WV_EINVAL;
+    if (sh.nseg > kMaxBatchSlots) return kGraphNotTaken;   // more than one batch: the counted path
     WV_TRY(prepare(c, sh));
     WV_TRY(ensure(c, c->seg_desc, ns * sizeof(SegDesc)));
     WV_TRY(ensure(c, c->seg_counts, ns * sizeof(uint32_t)));
@@ -904,13 +904,16 @@ int wv_search_windows(wv_ctx *c, const uint64_t *lo, const uint64_t *hi, size_t 
             c->stats = wv_stats{};
             pick_tuned(c, pmax);
             size_t n = 0;
-            WV_TRY(search_graph(c, d, bound, pmax + 1, out, &n));
-            *n_out = n;
-            if (win_off) {
-                win_off[0] = 0;
-                win_off[1] = n;
+            const int rc = search_graph(c, d, bound, pmax + 1, out, &n);
+            if (rc != kGraphNotTaken) {
+                if (rc != WV_OK) return rc;
+                *n_out = n;
+                if (win_off) {
+                    win_off[0] = 0;
+                    win_off[1] = n;
+                }
+                return WV_OK;
             }
-            return WV_OK;
         }
     }
     std::vector<uint32_t> counts(d.size());

@@ -211,6 +211,9 @@ uint64_t prime_count_bound(uint64_t lo, uint64_t hi);
 // Work (terms, estimated from the prime-count bound) below which a
 // single-window search runs as one replayed graph (a few ms of the GPU).
 constexpr double kGraphSearchTerms = 17179869184.0;
+// Returns kGraphNotTaken (and does nothing) when the batch would exceed one
+// batch's slots; the caller then takes the counted path.
+constexpr int kGraphNotTaken = 1;
 int search_graph(wv_ctx *c, const std::vector<SegDesc> &d, uint64_t n_bound, uint64_t pmax, wv_result *out,
                  size_t *n_out);
 // device address of the fixed scratch array on `device` (current), looked up
