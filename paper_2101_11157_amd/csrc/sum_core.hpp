@@ -147,7 +147,15 @@ __host__ __device__ __forceinline__ void run_chunk_logd(uint64_t s0, uint64_t n,
     f.pinv = 1.0 / f.p;
     const uint64_t nb = n / K;
     const uint64_t period = (uint64_t)(53 - (64 - __builtin_clzll(p)));   // blocks between reductions
+    // The terms after the last full block go first (the pair product
+    // commutes), so that s0 and n are dead while the tables are live.
     double a0 = 1.0, a1 = 0.0;
+    for (uint64_t t = nb * K; t < n; t++) {
+        const double u = f_pow<DEG>((double)(s0 + t), f);
+        a1 = f_mulmod(a1, u, f) + a0;
+        a0 = f_mulmod(a0, u, f);
+        a1 = f_reduce(a1, f);
+    }
     if (nb > 0) {
         double G[SZ];
         // direct values g_k(x) at x = s0 + b K for b = 0..K - k, built in place:
@@ -243,14 +251,19 @@ WV_UNROLL
             renorm();
         }
     }
-    for (uint64_t t = nb * K; t < n; t++) {
-        const double u = f_pow<DEG>((double)(s0 + t), f);
-        a1 = f_mulmod(a1, u, f) + a0;
-        a0 = f_mulmod(a0, u, f);
-        a1 = f_reduce(a1, f);
-    }
     c0 = f_canon(a0, f);
     c1 = f_canon(a1, f);
+}
+
+// floor(len / C) for len < 2^53 and 1 <= C < 2^53, given invC = 1/C rounded
+// to double: len and len * invC carry relative errors of at most 2^-53 each,
+// so the product is within len/C * 2^-52 < 2 of len/C and its integer part is
+// off by at most one, which the two comparisons correct.
+__host__ __device__ __forceinline__ uint64_t full_chunks(uint64_t len, uint64_t C, double invC) {
+    uint64_t q = (uint64_t)((double)len * invC);
+    if (q * C > len) q--;
+    else if ((q + 1) * C <= len) q++;
+    return q;
 }
 
 __device__ __forceinline__ uint32_t find_seg(const uint64_t *__restrict__ off, uint32_t nseg, uint64_t chunk) {

@@ -61,21 +61,62 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Butterfly of eqnCombinePairs across the 64 lanes of a wave; every lane
-// ends with the product of all 64 pairs (same prime on all lanes).
+// v of lane (lane ^ X) within the same 32-lane half (0 < X < 32): ds_swizzle
+// in bit-mask mode (offset = and-mask 0x1f | or-mask 0 << 5 | xor-mask X << 10).
+// The pattern is an immediate, so unlike ds_bpermute no per-lane address
+// register is held; the persistent sum kernel would otherwise keep those
+// addresses live across its loop and spill them.
+template <int X>
+__device__ __forceinline__ uint32_t swz_xor(uint32_t v) {
+    static_assert(X > 0 && X < 32, "swizzle reaches within a 32-lane half");
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1f | (X << 10));
+}
+
+template <int X>
+__device__ __forceinline__ uint64_t swz_xor_u64(uint64_t v) {
+    return ((uint64_t)swz_xor<X>((uint32_t)(v >> 32)) << 32) | swz_xor<X>((uint32_t)v);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // minimum over the 64 lanes of a fully active wave, as a wave-uniform value
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
+    v = min(v, swz_xor<16>(v));
+    v = min(v, swz_xor<8>(v));
+    v = min(v, swz_xor<4>(v));
+    v = min(v, swz_xor<2>(v));
+    v = min(v, swz_xor<1>(v));
+    // readlane returns int: compare as unsigned (0xffffffff is the largest value)
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    return a < b ? a : b;
+}
+
+// Butterfly of eqnCombinePairs across the 64 lanes of a fully active wave
+// (same prime on all lanes): each 32-lane half by swizzles, then the two
+// halves through scalar reads; every lane ends with the product of all 64
+// pairs.
+template <int X>
+__device__ __forceinline__ void pair_swz_step(uint64_t &c0, uint64_t &c1, const Mont &m) {
+    const uint64_t d0 = swz_xor_u64<X>(c0);
+    const uint64_t d1 = swz_xor_u64<X>(c1);
+    pair_mul(c0, c1, d0, d1, m);
 }
 
 __device__ __forceinline__ void wave_pair_reduce(uint64_t &c0, uint64_t &c1, const Mont &m) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        uint64_t d0 = shfl_xor_u64(c0, off);
-        uint64_t d1 = shfl_xor_u64(c1, off);
-        pair_mul(c0, c1, d0, d1, m);
-    }
+    pair_swz_step<16>(c0, c1, m);
+    pair_swz_step<8>(c0, c1, m);
+    pair_swz_step<4>(c0, c1, m);
+    pair_swz_step<2>(c0, c1, m);
+    pair_swz_step<1>(c0, c1, m);
+    const uint64_t d0 = readlane_u64(c0, 32), d1 = readlane_u64(c1, 32);
+    c0 = readlane_u64(c0, 0);
+    c1 = readlane_u64(c1, 0);
+    pair_mul(c0, c1, d0, d1, m);
 }
 
 // --------------------------------------------------------------------------
@@ -574,6 +615,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const uint64_t F = layout[1];
     const uint64_t total = min(F + layout[2], end);
     const int lane = threadIdx.x & 63;
+    // 1/C, wave-uniform: kept in scalar registers, not vector ones
+    const double invC = __longlong_as_double((long long)readfirst_u64((uint64_t)__double_as_longlong(1.0 / (double)C)));
     // A wave can take at most total/64 + 1 batches; the bound is a second exit.
     const uint64_t max_iter = total / 64 + 2;
     bool drained = false;
@@ -602,7 +645,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                 o = (chunk - off[seg]) * C;
             } else {
                 seg = tails[chunk - F];
-                o = segs[seg].len / C * C;
+                o = full_chunks(segs[seg].len, C, invC) * C;
             }
             const SegRec sr = segs[seg];
             const PrimeRec P = pr[sr.prime];
@@ -621,20 +664,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         // the whole wave is active here (the loop exit above is wave-uniform)
         const uint32_t nb_shared = wave_min_u32(nb_lane);
         const uint32_t period_shared = wave_min_u32(period_lane);
-        if (active) {
-            if (deg == 3) chunk_pair<3, KB>(s0, cnt, m, r2, one, nb_shared, period_shared, c0, c1);
-            else chunk_pair<2, KE>(s0, cnt, m, r2, one, nb_shared, period_shared, c0, c1);
-        }
         const uint32_t seg0 = __builtin_amdgcn_readlane(seg, 0);
         const uint32_t segl = __builtin_amdgcn_readlane(seg, 63);
         // all 64 chunks full (base + 64 <= F) and of one sum; scalar
         const bool uniform = (seg0 == segl) && (base + 63 < F);
+        // where this lane's pair goes when the wave does not join them: only
+        // this address stays live across the sums (the chunk and sum indices
+        // do not), which keeps the chunk set-up's registers out of scratch
+        Pair *dst = nullptr;
+        if (active && !uniform) dst = chunk < F ? partials + chunk : seg_pairs + seg;
+        if (active) {
+            if (deg == 3) chunk_pair<3, KB>(s0, cnt, m, r2, one, nb_shared, period_shared, c0, c1);
+            else chunk_pair<2, KE>(s0, cnt, m, r2, one, nb_shared, period_shared, c0, c1);
+        }
         if (uniform) {
-            wave_pair_reduce(c0, c1, m);
+            // one prime for the whole wave: its constants are loaded again
+            // (scalar) rather than kept in vector registers across the sums
+            const Mont mu = mont_of(pr[segs[seg0].prime]);
+            wave_pair_reduce(c0, c1, mu);
             if (lane == 0) partials[base] = Pair{c0, c1};
-        } else if (active) {
-            if (chunk < F) partials[chunk] = Pair{c0, c1};
-            else seg_pairs[seg] = Pair{c0, c1};
+        } else if (dst) {
+            *dst = Pair{c0, c1};
         }
     }
     if (!drained && lane == 0) atomicOr(err, 1ull);

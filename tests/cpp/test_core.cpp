@@ -251,6 +251,30 @@ int main() {
             if (find_seg(off, 7, c) != want[c]) { printf("FAIL find_seg %llu\n", (unsigned long long)c); return 1; }
         checks += 8;
     }
+    // floor(len / C) through a rounded reciprocal: multiples of C, their
+    // neighbours and random lengths up to 2^41, chunk sizes from 64 to 2^32
+    {
+        std::vector<uint64_t> cs = {1, 3, 64, 192, 4096, 65536, 680000, 680064, (1ull << 20) + 64, (1ull << 32)};
+        for (int i = 0; i < 200; i++) cs.push_back(((rng() % (1ull << 26)) + 1) * 64);
+        for (uint64_t C : cs) {
+            const double inv = 1.0 / (double)C;
+            auto one = [&](uint64_t len) {
+                if (full_chunks(len, C, inv) != len / C) {
+                    printf("FAIL full_chunks len=%llu C=%llu\n", (unsigned long long)len, (unsigned long long)C);
+                    return false;
+                }
+                checks++;
+                return true;
+            };
+            for (int i = 0; i < 200; i++) {
+                const uint64_t k = (uint64_t)(rng() % ((1ull << 41) / C + 1));
+                for (uint64_t len : {k * C, k * C + 1, k * C + C - 1, k ? k * C - 1 : 0, (uint64_t)(rng() % (1ull << 41))})
+                    if (!one(len)) return 1;
+            }
+            for (uint64_t len : {(1ull << 40) - 1, (1ull << 40), (1ull << 41) - 1})
+                if (!one(len)) return 1;
+        }
+    }
     printf("OK %ld\n", checks);
     return 0;
 }
