@@ -63,12 +63,21 @@ def kernel_source_hash():
     return h.hexdigest()[:12]
 
 
-def tables_key(which):
-    """The congruences a traffic figure was measured with (derived: sum counts)."""
+def rung_at(side, p):
+    """The shipped derived congruence (a rung of the ladder) that serves prime
+    p, or None where the printed table does."""
+    import paper_2101_11157_amd as wv
+    use = [r for r in wv.derived_ladder(side) if p >= r["min_p"]]
+    return use[-1] if use else None
+
+
+def tables_key(which, p=10 ** 11 - 1):
+    """The congruences a traffic figure was measured with (derived: the sum
+    counts of the rungs serving p)."""
     if which != "derived":
         return which
-    import paper_2101_11157_amd as wv
-    return f"derived {wv.derived_table('B')['n']}/{wv.derived_table('E')['n']}"
+    rb, re_ = rung_at("B", p), rung_at("E", p)
+    return f"derived {rb['n'] if rb else 30}/{re_['n'] if re_ else 33}"
 
 
 def renorm_period(p):
@@ -108,7 +117,8 @@ def blocked_threshold(d, k):
 
 class OpsModel:
     """VALU operations of the term-sum kernel for a set of primes, from the
-    congruences each prime uses: per prime and side, the terms of the sums
+    congruences each prime uses (the rung of the derived ladder its size
+    selects, or eqnBB30 / eqnEE33): per prime and side, the terms of the sums
     long enough for the blocked loop (ops_per_term with that prime's
     reduction period) and of the shorter ones (the one-term loop).  The term
     counts are scaled to the kernel's measured totals per side."""
@@ -118,17 +128,18 @@ class OpsModel:
         import paper_2101_11157_amd as wv
         self.np = np
         self.kb, self.ke = kb, ke
-        widths = {}
+        self.widths = {}     # (side, rounds or None) -> (sorted widths, prefix sums)
+        self.rungs = {}      # side -> [(min_p, rounds)] ascending
         for side, name in (("B", "BB30"), ("E", "EE33")):
-            # interval widths y - x of the congruence's sums (terms ~ width * p)
-            widths[("printed", side)] = sorted(ya / yb - xa / xb for _, xa, xb, ya, yb in wv.table_terms(name))
+            w = sorted(ya / yb - xa / xb for _, xa, xb, ya, yb in wv.table_terms(name))
+            self.widths[(side, None)] = (np.array(w), np.concatenate([[0.0], np.cumsum(w)]))
+            self.rungs[side] = []
             if tables == "derived":
-                terms = wv.derived_table(side)["terms"]
-                widths[("derived", side)] = sorted(int(ya) / int(yb) - int(xa) / int(xb)
-                                                   for _, xa, xb, ya, yb in terms)
-        self.widths = {k: (np.array(v), np.concatenate([[0.0], np.cumsum(v)])) for k, v in widths.items()}
-        self.tables = tables
-        self.min_p = wv.DERIVED_MIN_P
+                for r in wv.derived_ladder(side):
+                    terms = wv.derived_table(side, r["rounds"])["terms"]
+                    w = sorted(int(ya) / int(yb) - int(xa) / int(xb) for _, xa, xb, ya, yb in terms)
+                    self.widths[(side, r["rounds"])] = (np.array(w), np.concatenate([[0.0], np.cumsum(w)]))
+                    self.rungs[side].append((r["min_p"], r["rounds"]))
 
     def _side_terms(self, ps, side, d, k):
         """(blocked terms, one-term-loop terms) per prime of one side."""
@@ -136,14 +147,12 @@ class OpsModel:
         blk = np.zeros(len(ps))
         one = np.zeros(len(ps))
         thr = blocked_threshold(d, k)
-        for kind in ("printed", "derived"):
-            if (kind, side) not in self.widths:
-                continue
-            use = (ps >= self.min_p) if kind == "derived" else (
-                ps < self.min_p if self.tables == "derived" else np.ones(len(ps), bool))
-            if not use.any():
-                continue
-            w, cum = self.widths[(kind, side)]
+        mins = np.array([m for m, _ in self.rungs[side]], dtype=np.float64)
+        pick = np.searchsorted(mins, ps, side="right") - 1     # -1: the printed table
+        for j in np.unique(pick):
+            key = (side, None if j < 0 else self.rungs[side][j][1])
+            use = pick == j
+            w, cum = self.widths[key]
             q = ps[use]
             cut = np.searchsorted(w, thr / q)        # sums narrower than thr / p are short
             short = cum[cut] * q
@@ -169,7 +178,6 @@ class OpsModel:
             ops = (blk * opt_blk).sum() + one.sum() * ops_per_term(d, 1, 1)
             total += ops * (measured / est)
         return total
-
 
 def sum_kernel_muls(st, period):
     nb = st["n_terms_b"]
@@ -222,14 +230,19 @@ def bench_peak(args):
                       "published_f64_matrix_flops": PEAK_MFMA_F64, "valu": valu, "mfma_f64": mfma}), flush=True)
 
 
-def use_tables(ctx, which):
-    """Select the congruences; returns their description."""
+def use_tables(ctx, which, p=10 ** 11 - 1):
+    """Select the congruences; returns their description (at prime size p)."""
     if which == "derived":
         import paper_2101_11157_amd as wv
         ctx.use_derived_tables()
-        jb, je = wv.derived_table("B"), wv.derived_table("E")
-        return (f"derived: {jb['n']}-sum B (cost {jb['cost'][0]}/{jb['cost'][1]}) and {je['n']}-sum E "
-                f"(cost {je['cost'][0]}/{je['cost'][1]}) for p >= 3*2^29, eqnBB30+eqnEE33 below")
+        parts = []
+        for side in "BE":
+            lad = wv.derived_ladder(side)
+            r = rung_at(side, p)
+            at = (f"{r['n']}-sum {side} of {r['rounds']} rounds (cost {r['cost'][0]}/{r['cost'][1]})" if r
+                  else f"eqnBB30/eqnEE33 for {side}")
+            parts.append(f"{side}: {len(lad)} rungs from p >= {lad[0]['min_p']}, here the {at}")
+        return "derived ladders (greedy, Section 2.2; eqnBB30+eqnEE33 below the lowest rung): " + "; ".join(parts)
     return "eqnBB30+eqnEE33"
 
 
@@ -267,12 +280,12 @@ def cpu_baseline(primes, nthreads):
     return len(primes) / dt, dt, got
 
 
-def table_cost(tables):
-    """Terms per unit p of the congruences used at 1e11: (B, E)."""
-    import paper_2101_11157_amd as wv
+def table_cost(tables, p=10 ** 11 - 1):
+    """Terms per unit p of the congruences used at prime size p: (B, E)."""
     if tables == "derived":
-        jb, je = wv.derived_table("B"), wv.derived_table("E")
-        return jb["cost"][0] / jb["cost"][1], je["cost"][0] / je["cost"][1]
+        rb, re_ = rung_at("B", p), rung_at("E", p)
+        return (rb["cost"][0] / rb["cost"][1] if rb else 227 / 6480,
+                re_["cost"][0] / re_["cost"][1] if re_ else 27 / 512)
     return 227 / 6480, 27 / 512
 
 
@@ -283,7 +296,7 @@ def measure_plain(args, wv, wins, lo0, hi0, W):
         ctx.set_chunk_terms(args.chunk)
     if args.block:
         ctx.set_block(*[int(v) for v in args.block.split(",")])
-    tables = use_tables(ctx, args.tables)
+    tables = use_tables(ctx, args.tables, hi0 - 1)
     for k in range(args.warmup):
         ctx.search_range(*wins[k])
         print(f"warmup {k}: window {wins[k]}", file=sys.stderr, flush=True)
@@ -358,7 +371,47 @@ def measure_batch(args, wv, nwin):
                          f"starts log-uniform [1e6, 1e11], one wv_search_windows call",
                 tables=tables, primes=primes, terms=st["n_terms"], terms_b=st["n_terms_b"], ops=ops,
                 ms_sum=st["ms_sum"], wall=wall, block=[st["block_k_b"], st["block_k_e"]], verified=ok,
-                n_verified=args.verify)
+                n_verified=args.verify, wins=wins, results=res)
+
+
+def per_window_plain(args, wv, wins, batched):
+    """The plain per-window path on the same windows: one wv_search_range call
+    per window, in order, on a fresh context with the same congruences;
+    returns (primes/s over the wall clock, results identical to the batched
+    call's)."""
+    ctx = wv.Context(0)
+    use_tables(ctx, args.tables)
+    same = True
+    primes = 0
+    t0 = time.perf_counter()
+    for k, (a, b) in enumerate(wins):
+        res, _ = ctx.search_range(a, b)
+        primes += len(res)
+        same = same and as_pairs(res) == as_pairs(batched[k])
+    wall = time.perf_counter() - t0
+    ctx.close()
+    print(f"per-window plain path: {len(wins)} windows, {primes} primes in {wall:.1f} s", file=sys.stderr, flush=True)
+    return primes / wall, wall, same
+
+
+def requests_alone(args, wv, trace, served):
+    """The requests of a serving trace through the plain path one at a time
+    (wv_eval_primes for a single prime, wv_search_range for an interval), all
+    available at once; returns (primes/s over the wall clock, every result
+    identical to the served one)."""
+    ctx = wv.Context(0)
+    use_tables(ctx, args.tables)
+    same = True
+    primes = 0
+    t0 = time.perf_counter()
+    for k, (_, kind, arg) in enumerate(trace):
+        res = ctx.eval_primes([arg]) if kind == "prime" else ctx.search_range(*arg)[0]
+        primes += len(res)
+        same = same and as_pairs(res) == as_pairs(served[k])
+    wall = time.perf_counter() - t0
+    ctx.close()
+    print(f"requests alone: {len(trace)} requests, {primes} primes in {wall:.1f} s", file=sys.stderr, flush=True)
+    return primes / wall, wall, same
 
 
 def rate_summary(primes, terms, ops, wall, ms_sum):
@@ -388,13 +441,15 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="terms per lane chunk (0: automatic)")
     ap.add_argument("--block", default="", help="term-sum block shape KB,KE (default: the library's)")
     ap.add_argument("--tables", default="derived", choices=["derived", "printed"],
-                    help="derived: the package's greedy-derived congruences (Section 2.2) above 3*2^29, "
+                    help="derived: the package's ladders of greedy-derived congruences (Section 2.2), "
                          "printed: eqnBB30 + eqnEE33")
     ap.add_argument("--irr-path", default="auto", choices=["auto", "valu", "mfma"],
                     help="irregular: power-sum kernel (auto: matrix cores below 2^24)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="1e11: leave the batched workload out of the line")
     ap.add_argument("--no-serve", action="store_true", help="1e11: leave the served trace out of the line")
+    ap.add_argument("--no-same-work", action="store_true",
+                    help="1e11: skip the plain path on the batched windows and the served requests")
     ap.add_argument("--cpu-primes", type=int, default=4, help="primes in the oracle sample")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one device fill and one copy of this many bytes (torch): kernels of known "
@@ -439,7 +494,7 @@ def main():
     peak = PEAK_VALU / 1e12
     mul_rate = m["muls"] / (m["ms_sum"] * 1e-3) / 1e12
     block = m["block"]
-    traffic_key = (args.config, tables_key(args.tables), block[0], block[1], W, kernel_source_hash())
+    traffic_key = (args.config, tables_key(args.tables, hi0 - 1), block[0], block[1], W, kernel_source_hash())
     line = {
         "metric": "primes tested/sec at p~1e11 (1 GPU), both B_{p-3} and E_{p-3} mod p",
         "value": value,
@@ -483,12 +538,18 @@ def main():
         b = measure_batch(args, wv, args.windows)
         line["batched"] = dict({"workload": b["workload"], "tables": b["tables"], "block": b["block"]},
                                **rate_summary(b["primes"], b["terms"], b["ops"], b["wall"], b["ms_sum"]))
+        if not args.no_same_work:
+            v, w, same = per_window_plain(args, wv, b["wins"], b["results"])
+            line["batched"]["per_window_plain"] = {
+                "primes_per_s": v, "wall_s": w, "identical_results": same,
+                "batched_over_per_window": line["batched"]["primes_per_s"] / v,
+                "how": "the same 64 windows, one wv_search_range call each, in order"}
     if args.config == "1e11" and not args.no_serve:
         from paper_2101_11157_amd import workloads as wl
         trace = wl.serve_trace(0, args.requests, rate=args.rate)
         ctx = wv.Context(0)
         use_tables(ctx, args.tables)
-        sv, _ = run_trace(wv, ctx, trace, args.step_terms, args.tables)
+        sv, sv_out = run_trace(wv, ctx, trace, args.step_terms, args.tables)
         ctx.close()
         served = {"workload": f"seeded Poisson trace (default_rng(0)), {len(trace)} requests at {args.rate:g}/s, "
                               f"70% single primes, 30% intervals of 1e2..1e5, u in [1e8, 1e11]",
@@ -498,11 +559,20 @@ def main():
                   "offered_over_capacity": sv["offered_over_capacity"], "primes": sv["primes"],
                   "terms": sv["terms"], "wall_s": sv["wall_s"], "busy_s": sv["busy_s"], "steps": sv["steps"],
                   "valu_tops": sv["valu_tops"], "frac": sv["frac"]}
+        if not args.no_same_work:
+            v, w, same = requests_alone(args, wv, trace, sv_out)
+            served["alone_plain"] = {
+                "primes_per_s": v, "wall_s": w, "identical_results": same,
+                "served_over_alone": sv["value"] / v,
+                "how": "the same 128 requests through the plain path one at a time, all available at once"}
         line["served"] = served
     if "batched" in line or "served" in line:
-        # like-for-like: the term-sum kernel's modelled VALU rate (ops per term
-        # differ between the Bernoulli and Euler sides and with p, so terms/s
-        # alone depends on the mix of congruences and primes)
+        # against the headline window (other primes and congruences): the
+        # term-sum kernel's modelled VALU rate and terms/s (ops per term differ
+        # between the Bernoulli and Euler sides and with p, and each rung of the
+        # derived ladder trades terms for sums, so terms/s depends on the mix);
+        # the same work through the plain path is in per_window_plain /
+        # alone_plain above
         line["vs_plain"] = {k: {"frac_ratio": line[k]["frac"] / line["roofline"]["frac"],
                                 "terms_per_s_ratio": line[k]["terms_per_s"] / line["config"]["terms_per_s"]}
                             for k in ("batched", "served") if k in line}
@@ -515,7 +585,7 @@ def main():
         gpu = {int(r["p"]): (int(r["b"]), int(r["e"])) for r in first}
         nt = cpu_threads()
         v, dt, got = cpu_baseline(sample, nt)
-        cb, ce = table_cost(args.tables)
+        cb, ce = table_cost(args.tables, hi0 - 1)
         match = all(gpu[p] == g for p, g in zip(sample, got))
         line["cpu_baseline"] = {
             "value": v, "unit": "primes/s", "cores": nt, "kind": "oracle",

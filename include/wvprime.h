@@ -137,6 +137,19 @@ int wv_define_table(wv_ctx *ctx, int deg, const char *lhs, size_t n, const char 
                     const uint64_t *xa, const uint64_t *xb, const uint64_t *ya, const uint64_t *yb,
                     uint64_t min_p, int *id);
 
+/* Name the table that serves the primes a defined table `id` does not (those
+ * below its min_p, or dividing its left side): `below` is a compiled table of
+ * the same degree (not a root form) or a defined one with a smaller min_p, so
+ * that every chain ends at a compiled table.  The default is eqnBB30 /
+ * eqnEE33.  A chain of congruences from one greedy search (Section 2.2: more
+ * rounds give more, shorter sums of fewer terms in total) lets each prime use
+ * the one whose work, terms plus a fixed cost per sum, is least at its size;
+ * the residues do not depend on the choice.  A batch allows for the most sums
+ * per prime of any table on the chain.  Errors: WV_EINVAL (an id out of
+ * range, a compiled `id`, another degree, a root form, or a defined `below`
+ * whose min_p is not smaller), WV_EHIP. */
+int wv_set_table_below(wv_ctx *ctx, int id, int below);
+
 /* Set the number of terms each lane sums per chunk (0 = automatic: about
  * sqrt(2 * 4096 * T / lanes) for a batch of T terms, between 2^12 and 2^22,
  * which balances the set-up of each chunk against lanes idling when the last
@@ -377,7 +390,8 @@ typedef struct wv_server wv_server;
 
 typedef struct {
     uint64_t step_terms;   /* terms of work per step (0: 2^38, ~45 ms at p ~ 1e11) */
-    uint32_t max_primes;   /* prime slots of the device pool (0: 65536) */
+    uint32_t max_primes;   /* prime slots of the device pool (0: 65536, or fewer so that the pool
+                              holds at most 2^30 (prime, sum) slots, at least 1024 primes) */
     uint32_t reserved;
 } wv_server_config;
 

@@ -33,16 +33,38 @@ WV_FLAG_VANDIVER = 2
 TABLE_NAMES = ["BB1", "BB2", "BB6", "BB9", "BB16", "BB22", "BB30",
                "EE3", "EE5", "EE9", "EE16", "EE24", "EE33", "V12", "E1"]
 TABLE_ID = {n: i for i, n in enumerate(TABLE_NAMES)}
-# derived congruences shipped with the package (tables/make_tables.py)
+# derived congruences shipped with the package (tables/make_tables.py): for
+# each side a ladder of congruences from one greedy search, each serving the
+# primes from its min_p up to the next one's (tables/ladder.json)
 DERIVED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tables")
-DERIVED_MIN_P = 3 << 29     # about 2^30.6: below this the printed tables' fewer, longer sums are cheaper overall
 
 
-def derived_table(side):
-    """The JSON congruence of tables/derived_<side>.json (side 'B' or 'E')."""
+def _load_table(name):
+    import gzip
     import json
-    with open(os.path.join(DERIVED_DIR, f"derived_{side}.json")) as f:
+    path = os.path.join(DERIVED_DIR, name)
+    with (gzip.open(path, "rt") if name.endswith(".gz") else open(path)) as f:
         return json.load(f)
+
+
+def derived_ladder(side):
+    """[{"rounds", "min_p", "file", "n", "cost"}] of the shipped congruences of
+    one side ('B' or 'E'), ascending in min_p (and so in rounds)."""
+    return _load_table("ladder.json")[side]
+
+
+def derived_min_p():
+    """Smallest prime any shipped derived congruence serves (below it: the
+    printed eqnBB30 / eqnEE33)."""
+    return min(r["min_p"] for side in "BE" for r in derived_ladder(side))
+
+
+def derived_table(side, rounds=None):
+    """The JSON congruence of one rung of the ladder (default: the top one,
+    the most rounds, used for the largest primes)."""
+    rungs = derived_ladder(side)
+    r = rungs[-1] if rounds is None else next(r for r in rungs if r["rounds"] == rounds)
+    return _load_table(r["file"])
 
 
 def _frac(a, b):
@@ -141,6 +163,7 @@ def lib():
             "wv_set_progress": (ctypes.c_int, [VP, PROGRESS_FN, VP, U64]),
             "wv_define_table": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_char_p, SZ, ctypes.POINTER(ctypes.c_char_p),
                                                P_U64, P_U64, P_U64, P_U64, U64, ctypes.POINTER(ctypes.c_int)]),
+            "wv_set_table_below": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int]),
             "wv_range_stats": (ctypes.c_int, [VP, U64, U64, ctypes.c_uint32, U64, P_U64, P_U64, VP, SZ,
                                               ctypes.POINTER(SZ), P_U64]),
             "wv_bernoulli_euler_all": (ctypes.c_int, [VP, U64, P_U64, P_U64]),
@@ -284,17 +307,39 @@ class Context:
                                      int(min_p), ctypes.byref(out)), "wv_define_table")
         return out.value
 
-    def define_derived_table(self, obj, min_p=DERIVED_MIN_P):
-        """Register a congruence written by derive.Congruence.to_json."""
+    def define_derived_table(self, obj, min_p=None):
+        """Register a congruence written by derive.Congruence.to_json (for
+        primes >= min_p; default: the smallest prime the shipped ladder serves)."""
         terms = [(int(n), _frac(xa, xb), _frac(ya, yb)) for n, xa, xb, ya, yb in obj["terms"]]
-        return self.define_table(3 if obj["side"] == "B" else 2, int(obj["lhs"]), terms, min_p)
+        return self.define_table(3 if obj["side"] == "B" else 2, int(obj["lhs"]), terms,
+                                 derived_min_p() if min_p is None else min_p)
 
-    def use_derived_tables(self, min_p=DERIVED_MIN_P):
-        """Define the package's derived congruences (tables/*.json, built by
-        tables/make_tables.py with the greedy search of Section 2.2) and use
-        them for primes >= min_p; returns (b_id, e_id)."""
-        b = self.define_derived_table(derived_table("B"), min_p)
-        e = self.define_derived_table(derived_table("E"), min_p)
+    def set_table_below(self, table, below):
+        """Primes a defined table does not serve (below its min_p, or dividing
+        its left side) use `below` (a name or id)."""
+        below = TABLE_ID[below] if isinstance(below, str) else int(below)
+        _check(lib().wv_set_table_below(self._h, int(table), below), "wv_set_table_below")
+
+    def use_derived_tables(self, min_p=None, top=None):
+        """Define the shipped ladders of derived congruences (tables/ladder.json,
+        built by tables/make_tables.py with the greedy search of Section 2.2)
+        and use them: each rung serves the primes from its min_p up to the next
+        rung's, the lowest from min_p when given (else its own), and the
+        printed eqnBB30 / eqnEE33 the primes below.  top: use only the rungs
+        of at most this many rounds.  Returns (b_id, e_id) of the top rungs."""
+        ids = []
+        for side in "BE":
+            rungs = [r for r in derived_ladder(side) if top is None or r["rounds"] <= top]
+            if not rungs:
+                raise ValueError(f"no shipped {side} congruence of at most {top} rounds")
+            below = "BB30" if side == "B" else "EE33"
+            for k, r in enumerate(rungs):
+                lo = r["min_p"] if (k > 0 or min_p is None) else int(min_p)
+                t = self.define_derived_table(_load_table(r["file"]), lo)
+                self.set_table_below(t, below)
+                below = t
+            ids.append(below)
+        b, e = ids
         self.set_tables(b, e)
         return b, e
 

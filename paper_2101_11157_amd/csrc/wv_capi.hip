@@ -361,17 +361,23 @@ int search_descs(wv_ctx *c, const std::vector<SegDesc> &descs, const std::vector
         // about kMaxBatchTerms terms (bounded by count * largest p * cost):
         // with the partial pairs capped, a bigger batch would force chunks
         // longer than its sums
-        const double cost = side_cost(c, c->tb) + side_cost(c, c->te);
-        const uint64_t per = (uint64_t)side_slots(c, c->tb) + side_slots(c, c->te);
-        const uint64_t max_np = std::min<uint64_t>(kMaxBatchPrimes, kMaxBatchSlots / per);
+        // (slots per prime: those of the tables a batch up to its largest
+        // prime can pick; work: each piece at the cost of the table serving
+        // its top)
         size_t j = i;
-        uint64_t np = 0;
+        uint64_t np = 0, pm = 0;
         double est = 0.0;
         while (j < descs.size() && j - i < kMaxBatchSegs) {
-            const double e = (double)counts[j] * (double)std::min(descs[j].hi, descs[j].L + kSegSpan) * cost;
+            const uint64_t top = std::min(descs[j].hi, descs[j].L + kSegSpan);
+            const uint64_t pm_j = std::max(pm, top);
+            const uint64_t per = (uint64_t)side_slots(c, batch_table(c, c->tb, pm_j)) +
+                                 side_slots(c, batch_table(c, c->te, pm_j));
+            const uint64_t max_np = std::min<uint64_t>(kMaxBatchPrimes, kMaxBatchSlots / per);
+            const double e = (double)counts[j] * (double)top * (prime_cost(c, c->tb, top) + prime_cost(c, c->te, top));
             if (np > 0 && (np + counts[j] > max_np || est + e > kMaxBatchTerms)) break;
             np += counts[j++];
             est += e;
+            pm = pm_j;
         }
         if (np == 0) {
             i = j;
@@ -491,6 +497,9 @@ int table_add(wv_ctx *c, int deg, const std::vector<uint32_t> &lhs_mag, bool lhs
     h.lhs_nlimb = (uint16_t)lhs_mag.size();
     h.lhs_neg = lhs_neg ? 1 : 0;
     h.min_p = min_p;
+    // compiled tables serve every prime; a defined one hands the others to the
+    // printed table of its degree until wv_set_table_below says otherwise
+    h.below = c->t_head.size() < (size_t)WV_TABLE_COUNT ? -1 : (deg == 3 ? WV_TABLE_BB30 : WV_TABLE_EE33);
     c->t_limb.insert(c->t_limb.end(), lhs_mag.begin(), lhs_mag.end());
     double cost = 0.0;
     for (size_t i = 0; i < coef_mag.size(); i++) {
@@ -549,15 +558,39 @@ int table_fallback(const wv_ctx *c, int id) {
     return c->t_head[id].deg == 3 ? WV_TABLE_BB30 : WV_TABLE_EE33;
 }
 
+// The table a batch whose largest prime is pmax starts from: defined tables
+// whose min_p no prime of the batch reaches hand over to the one below.
 int batch_table(const wv_ctx *c, int id, uint64_t pmax) {
-    return pmax <= c->t_head[id].min_p ? table_fallback(c, id) : id;
+    while (id >= WV_TABLE_COUNT && pmax <= c->t_head[id].min_p) id = c->t_head[id].below;
+    return id;
 }
 
+// Sums per prime and cost per unit p a batch must allow for: the largest over
+// the tables the plan can pick from id down (the chain and its end).
 int side_slots(const wv_ctx *c, int id) {
-    return std::max({c->t_head[id].n, c->t_head[table_fallback(c, id)].n, 1});
+    int n = std::max(c->t_head[table_fallback(c, id)].n, 1);
+    for (int t = id;; t = c->t_head[t].below) {
+        n = std::max(n, c->t_head[t].n);
+        if (t < WV_TABLE_COUNT) break;
+    }
+    return n;
 }
 
-double side_cost(const wv_ctx *c, int id) { return std::max(c->t_cost[id], c->t_cost[table_fallback(c, id)]); }
+// Terms per unit p of the table that serves a prime of size p (the chain's
+// min_p only; an estimate of work, not a choice of table).
+double prime_cost(const wv_ctx *c, int id, uint64_t p) {
+    while (id >= WV_TABLE_COUNT && p < c->t_head[id].min_p) id = c->t_head[id].below;
+    return c->t_cost[id];
+}
+
+double side_cost(const wv_ctx *c, int id) {
+    double v = c->t_cost[table_fallback(c, id)];
+    for (int t = id;; t = c->t_head[t].below) {
+        v = std::max(v, c->t_cost[t]);
+        if (t < WV_TABLE_COUNT) break;
+    }
+    return v;
+}
 
 void pick_tuned(wv_ctx *c, uint64_t pmax) {
     if (c->shape_forced || pmax < 2) return;
@@ -811,6 +844,21 @@ int wv_define_table(wv_ctx *c, int deg, const char *lhs, size_t n, const char *c
     WV_TRY(check_device(c));
     WV_TRY(table_add(c, deg, lmag, lneg, mag, neg, xa, xb, ya, yb, min_p, id));
     c->gen++;   // captured graphs hold the old table ids' shapes
+    return WV_OK;
+}
+
+int wv_set_table_below(wv_ctx *c, int id, int below) {
+    if (!c) return WV_EINVAL;
+    const int nt = (int)c->t_head.size();
+    if (id < WV_TABLE_COUNT || id >= nt || below < 0 || below >= nt) return WV_EINVAL;
+    if (c->t_head[below].deg != c->t_head[id].deg) return WV_EINVAL;
+    if (below == WV_TABLE_V12 || below == WV_TABLE_E1) return WV_EINVAL;
+    // a defined table below must start lower, so every chain ends at a compiled table
+    if (below >= WV_TABLE_COUNT && c->t_head[below].min_p >= c->t_head[id].min_p) return WV_EINVAL;
+    WV_TRY(check_device(c));
+    c->t_head[id].below = below;
+    WV_TRY(upload_tables(c));
+    c->gen++;   // captured graphs were sized for the old chain
     return WV_OK;
 }
 

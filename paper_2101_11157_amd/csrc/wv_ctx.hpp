@@ -149,7 +149,7 @@ namespace wv {
 // lanes of the persistent term-sum grid of the current block shape
 inline uint64_t sum_lanes(const wv_ctx *c) { return (uint64_t)c->sum_blocks[c->variant] * 256; }
 
-constexpr int kMaxDefinedTables = 64;
+constexpr int kMaxDefinedTables = kMaxTableChain;
 constexpr size_t kMaxTableTerms = 1 << 16;
 
 // table registry (wv_capi.hip)
@@ -159,13 +159,17 @@ int table_add(wv_ctx *c, int deg, const std::vector<uint32_t> &lhs_mag, bool lhs
               const uint64_t *xa, const uint64_t *xb, const uint64_t *ya, const uint64_t *yb, uint64_t min_p,
               int *id);
 TableStore table_store(wv_ctx *c);
-// the table used where `id` does not apply (p < min_p or p | lhs)
+// the printed table of id's degree (the last resort of the device's choice)
 int table_fallback(const wv_ctx *c, int id);
-// the table a batch of primes below pmax uses on the side configured with id
+// the table a batch of primes below pmax starts from on the side configured
+// with id (defined tables hand the primes below their min_p down their chain)
 int batch_table(const wv_ctx *c, int id, uint64_t pmax);
-// slots and cost per p of a side that uses `id` (fallback included)
+// slots and cost per p a side that starts from `id` must allow for: the
+// largest over its chain of tables
 int side_slots(const wv_ctx *c, int id);
 double side_cost(const wv_ctx *c, int id);
+// cost per p of the table of id's chain that serves a prime of size p
+double prime_cost(const wv_ctx *c, int id, uint64_t p);
 
 int ensure(wv_ctx *c, DevBuf &b, size_t bytes);
 bool is_prime_u64(uint64_t n);

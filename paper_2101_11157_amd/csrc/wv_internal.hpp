@@ -17,6 +17,7 @@ constexpr int kSegBits = 1 << (kSegLog - 1);   // odd integers per segment
 constexpr int kSegWords = kSegBits / 32;       // 16384 words = 64 KiB of LDS
 constexpr uint32_t kBaseLimit = 1u << 20;      // base primes below 2^20 cover p < 2^40
 constexpr int kScanTile = 1024;                // elements per scan workgroup
+constexpr int kMaxTableChain = 64;              // defined tables per context (and so per chain)
 
 // One sieve segment: the 2^20 integers [L, L + 2^20) (L even), of which the
 // window [lo, hi) keeps the primes p >= 5.  Segments of several windows can
@@ -107,7 +108,7 @@ struct TableHead {      // 32 bytes
     uint32_t term_off, lhs_off;
     uint16_t lhs_nlimb;
     int16_t lhs_neg;
-    uint32_t pad;
+    int32_t below;             // defined tables: the table for the other primes (-1 for compiled ones)
     uint64_t min_p;            // used for p >= min_p (and p not dividing lhs)
 };
 

@@ -376,15 +376,21 @@ __device__ uint64_t limbs_mod(const uint32_t *__restrict__ limb, uint32_t off, i
 }
 
 // Table of one side for prime p: the configured one where it applies, else
-// the fallback; the root forms for p = 5 and 7 (readings of the paper: the
-// specialised tables need p >= 11).
+// the table it names for the primes it does not serve (a chain of defined
+// tables with falling min_p that ends at a compiled table; fb if a chain were
+// ever longer than the registry); the root forms for p = 5 and 7 (readings of
+// the paper: the specialised tables need p >= 11).
 __device__ int pick_table(TableStore ts, int side, uint64_t p, int cfg, int fb) {
     if (side == 0 && p == 5) return WV_TABLE_BB1;
     if (side == 0 && p == 7) return WV_TABLE_V12;
     if (side == 1 && p < 11) return WV_TABLE_E1;
-    const TableHead h = ts.head[cfg];
-    if (p < h.min_p || limbs_mod(ts.limb, h.lhs_off, h.lhs_nlimb, false, p) == 0) return fb;
-    return cfg;
+    int t = cfg;
+    for (int hop = 0; hop <= kMaxTableChain && t >= WV_TABLE_COUNT; hop++) {
+        const TableHead h = ts.head[t];
+        if (p >= h.min_p && limbs_mod(ts.limb, h.lhs_off, h.lhs_nlimb, false, p) != 0) return t;
+        t = h.below;
+    }
+    return t >= WV_TABLE_COUNT ? fb : t;
 }
 
 // One thread per prime: PrimeRec, the table of each side and the residues of

@@ -561,12 +561,15 @@ int wv_server_create(wv_ctx *c, const wv_server_config *cfg, wv_server **out) {
     if (!s) return WV_ENOMEM;
     s->c = c;
     if (cfg && cfg->step_terms) s->step_terms = cfg->step_terms;
-    if (cfg && cfg->max_primes) s->pool = cfg->max_primes;
     s->tb = c->tb;
     s->te = c->te;
     s->nB = side_slots(c, c->tb);
     s->nE = side_slots(c, c->te);
     s->NS = s->nB + s->nE;
+    // default pool: 65536 primes, fewer where the congruences have so many
+    // sums that this would pass 2^30 slots (56 bytes of device state each)
+    if (cfg && cfg->max_primes) s->pool = cfg->max_primes;
+    else s->pool = (uint32_t)std::min<uint64_t>(s->pool, std::max<uint64_t>(1024, (1ull << 30) / s->NS));
     const size_t nseg = (size_t)s->pool * s->NS;
     if (nseg >= (1ull << 32)) {   // pool indices of the step tasks are 32-bit
         delete s;

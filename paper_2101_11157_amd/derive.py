@@ -532,15 +532,33 @@ def beam_search(start, D=6, rounds=16, beam=8, max_m=None, log=None):
     return best
 
 
-def greedy(start, D=8, rounds=100, lam=1, log=None):
+def greedy(start, D=8, rounds=100, lam=1, log=None, cached=True):
     """Section 2.2: each round tries every sequence of lam subdivisions with
     d <= D and moves to a cheapest result (first in piece order, then d, on
-    ties); returns (final congruence, cheapest congruence seen, its round)."""
+    ties); returns (final congruence, cheapest congruence seen, its round).
+
+    With lam = 1 and cached=True the change of cost of each candidate is kept
+    from round to round and recomputed only for the pieces whose value, or
+    the value on one of whose images, the last subdivision changed (the
+    choices, and so the result, are those of the plain scan, cached=False)."""
     cur = start.copy()
     best, best_round = cur.copy(), 0
+    cache = {}   # (x, y) -> (coefficient, least cost_delta(x, y, d) over d = 2..D, first such d)
     for r in range(1, rounds + 1):
         choice = None
-        if lam == 1:
+        if lam == 1 and cached:
+            kept = {}
+            for c, x, y in cur.pieces():
+                ent = cache.get((x, y))
+                if ent is None or ent[0] != c:
+                    deltas = [cur.cost_delta(x, y, d) for d in range(2, D + 1)]
+                    k = min(range(len(deltas)), key=deltas.__getitem__)   # first smallest d
+                    ent = (c, deltas[k], k + 2)
+                kept[(x, y)] = ent
+                if choice is None or ent[1] < choice[0]:
+                    choice = (ent[1], [(x, y, ent[2])])
+            cache = kept
+        elif lam == 1:
             # the round's candidates differ only in their change of cost
             base = cur.cost()
             for c, x, y in cur.pieces():
@@ -559,11 +577,49 @@ def greedy(start, D=8, rounds=100, lam=1, log=None):
             break
         for x, y, d in choice[1]:
             cur.subdivide(x, y, d)
+            if lam == 1 and cached:
+                _drop_touched(cache, cur, _changed(cur, x, y, d), D)
         if cur.cost() < best.cost():
             best, best_round = cur.copy(), r
         if log:
             log(r, cur)
     return cur, best, best_round
+
+
+def _changed(cong, x, y, d):
+    """Intervals of [0, 1/2] where subdivide(x, y, d) changed the coefficient
+    function: the piece and its d images, reflected below 1/2."""
+    out = [(x, y)]
+    for i in range(d):
+        a, b = (x + i) / d, (y + i) / d
+        if b <= HALF:
+            out.append((a, b))
+        elif a >= HALF:
+            out.append((1 - b, 1 - a))
+        else:
+            out.append((a, HALF))
+            out.append((1 - b, HALF))
+    return out
+
+
+def _drop_touched(cache, cong, changed, D):
+    """Remove the cached candidates whose images by some d <= D meet a changed
+    interval.  An image ((x+i)/d, (y+i)/d) lies in (0, 1); it meets a changed
+    interval (a, b) of [0, 1/2] directly or through the reflection t -> 1 - t,
+    i.e. the piece (x, y) meets (d a - i, d b - i) or (d (1 - b) - i, d (1 - a) - i)."""
+    bp, cf = cong.bp, cong.cf
+    for a, b in changed:
+        for ta, tb in ((a, b), (1 - b, 1 - a)):
+            for d in range(2, D + 1):
+                for i in range(d):
+                    u, v = ta * d - i, tb * d - i
+                    if v <= 0 or u >= HALF:
+                        continue
+                    j = max(bisect_right(bp, u) - 1, 0)
+                    while j < len(cf) and bp[j] < v:
+                        if cf[j] != 0 and bp[j + 1] > u:
+                            cache.pop((bp[j], bp[j + 1]), None)
+                        j += 1
 
 
 def _sequences(cong, D, lam):

@@ -178,27 +178,60 @@ def test_json_round_trip():
     assert again.integer_form() == best.integer_form() and again.cost() == best.cost()
 
 
-@pytest.mark.parametrize("side", ["B", "E"])
-def test_shipped_derived_tables(side):
-    """The congruences the package ships (tables/make_tables.py) are valid:
-    the oracle evaluates them plainly and gets the recurrence residues for all
-    11 <= p < 600 and the root forms' residues near 1e6.  The Euler one is the
-    paper's 100-round greedy search from eqnEMac2: 438 sums, cost below p/30.4
-    (end of Section 4)."""
+def _rungs():
     import paper_2101_11157_amd as wv
-    obj = wv.derived_table(side)
+    return [(side, r["rounds"]) for side in "BE" for r in wv.derived_ladder(side)]
+
+
+@pytest.mark.parametrize("side,rounds", _rungs())
+def test_shipped_derived_tables(side, rounds):
+    """Every congruence the package ships (tables/make_tables.py: one rung of
+    a ladder from the greedy search of Section 2.2) is valid: the oracle
+    evaluates it plainly and gets the recurrence residues for 11 <= p < 600
+    (every such prime for the smaller rungs, a spread of them for the larger
+    ones) and the root forms' residues near 1e6; its cost and sum count are
+    the ones the ladder records, and it is cheaper than eqnBB30 / eqnEE33."""
+    import paper_2101_11157_amd as wv
+    rung = next(r for r in wv.derived_ladder(side) if r["rounds"] == rounds)
+    obj = wv.derived_table(side, rounds)
     cong = D.load_json(obj)
-    assert cong.n_sums() == obj["n"] and cong.cost() == Q(*obj["cost"])
+    assert cong.n_sums() == obj["n"] == rung["n"] and cong.cost() == Q(*obj["cost"]) == Q(*rung["cost"])
     printed = C.BB30 if side == "B" else C.EE33
-    assert cong.cost() < printed.cost and obj["n"] > 300
-    oc = _as_oracle_congruence(cong, f"shipped-{side}")
+    assert cong.cost() < printed.cost
+    oc = _as_oracle_congruence(cong, f"shipped-{side}-{rounds}")
     ps = [p for p in oracle.primes(11, 600) if oc.lhs % p]
+    if obj["n"] > 3000:
+        ps = ps[::7] + ps[-3:]
     got = [oracle.congruence_residue_exact(p, oc) for p in ps]
     want = [oracle.bernoulli_rec(p) if side == "B" else oracle.euler_rec(p) for p in ps]
     assert got == want
-    big = oracle.primes(10 ** 6, 10 ** 6 + 200)[:6]
+    big = oracle.primes(10 ** 6, 10 ** 6 + 200)[:3 if obj["n"] > 3000 else 6]
     root = C.SV if side == "B" else C.E1
     assert [oracle.congruence_residue_exact(p, oc) for p in big] == oracle.congruence_residues(big, root)
+
+
+@pytest.mark.parametrize("side", ["B", "E"])
+def test_shipped_ladder_is_consistent(side):
+    """The ladder: rungs in ascending rounds with more sums, lower cost and
+    rising min_p; each min_p is where the rung's modelled work (cost * p +
+    beta * sums) falls below the rung under it (eqnBB30 / eqnEE33 for the
+    lowest), so between two thresholds the rung in use is the cheapest of the
+    ladder at both ends."""
+    import paper_2101_11157_amd as wv
+    doc = wv._load_table("ladder.json")
+    beta = doc["beta"]
+    rungs = doc[side]
+    assert len(rungs) >= 3
+    n0, c0 = (30, Q(227, 6480)) if side == "B" else (33, Q(27, 512))
+    prev = None
+    for r in rungs:
+        n, c = r["n"], Q(*r["cost"])
+        assert n > n0 and c < c0 and r["min_p"] >= 11
+        assert c * r["min_p"] + beta * n <= c0 * r["min_p"] + beta * n0
+        assert c * (r["min_p"] - 1) + beta * n > c0 * (r["min_p"] - 1) + beta * n0 or r["min_p"] == 11
+        if prev is not None:
+            assert r["rounds"] > prev["rounds"] and r["min_p"] > prev["min_p"]
+        prev, n0, c0 = r, n, c
 
 
 @pytest.mark.slow

@@ -941,8 +941,9 @@ def test_defined_tables_all_small_primes():
 
 
 def test_package_derived_tables_at_scale(ctx):
-    """The shipped derived congruences (hundreds of sums each) reproduce the
-    oracle samples at 1e9 and 1e11 and Tables 2-3."""
+    """The shipped derived congruences (a ladder of rungs of hundreds to tens
+    of thousands of sums, each from its min_p, the lowest from p = 11)
+    reproduce the oracle samples at 1e9 and 1e11 and Tables 2-3."""
     say("case: package derived tables")
     g9 = golden_json("window_1e9.json")["rows"][:40]
     g11 = golden_json("window_1e11.json")["rows"]
@@ -955,7 +956,10 @@ def test_package_derived_tables_at_scale(ctx):
         got = c.eval_primes([r["p"] for r in g9 + g11])
         assert as_pairs(got) == [(r["b"], r["e"]) for r in g9 + g11]
         st = c.stats()
-        assert st["n_sums"] == len(got) * (jb["n"] + je["n"])
+        # slots per prime: the largest rung any prime of the batch can select
+        pmax = max(int(p) for p in got["p"])
+        per = sum(max(r["n"] for r in wv.derived_ladder(side) if r["min_p"] < pmax) for side in "BE")
+        assert st["n_sums"] == len(got) * per
         got = c.eval_primes([p for p, _ in tb] + [p for p, _ in te])
     sym = [(exact.symmetric(int(r["b"]), int(r["p"])), exact.symmetric(int(r["e"]), int(r["p"]))) for r in got]
     assert [s[0] for s in sym[:len(tb)]] == [r for _, r in tb]
@@ -977,6 +981,80 @@ def test_defined_table_fallbacks():
         s13 = c.define_derived_table(scaled, min_p=11)
         c.set_tables(s13, "EE33")
         assert as_pairs(c.eval_primes(ps)) == as_pairs(ref)
+
+
+def _open_interval_terms(p, ends):
+    """Integers s with x p < s < y p summed over the sums (eqnDefnS); ends:
+    (xa, xb, ya, yb) per sum."""
+    return sum(max(0, -(-ya * p // yb) - (xa * p // xb) - 1) for xa, xb, ya, yb in ends)
+
+
+@functools.lru_cache(maxsize=None)
+def _ends(side, rounds):
+    if rounds is None:
+        from oracle import congruences as C
+        t = C.BB30 if side == "B" else C.EE33
+        return tuple((x.numerator, x.denominator, y.numerator, y.denominator) for _, x, y in t.terms)
+    obj = wv.derived_table(side, rounds)
+    return tuple((int(xa), int(xb), int(ya), int(yb)) for _, xa, xb, ya, yb in obj["terms"])
+
+
+def test_derived_ladder_matches_printed_tables():
+    """The shipped ladders (a rung per range of p, chained with
+    wv_set_table_below): primes on every rung, from below the lowest threshold
+    to 1e11, searched and evaluated in mixed batches, give the residues of the
+    printed eqnBB30 / eqnEE33 (independent intervals and coefficients); each
+    prime's work is that of the rung its size selects."""
+    rungs = {side: wv.derived_ladder(side) for side in "BE"}
+    marks = sorted({r["min_p"] for side in "BE" for r in rungs[side]} | {10 ** 11 - 10 ** 6})
+    ps = []
+    for m in marks:
+        ps += oracle.primes(max(11, m - 400), m + 400)[:6]      # both sides of each threshold
+    say(f"case: derived ladder, {len(ps)} primes around {len(marks)} thresholds")
+    with wv.Context(0) as c:
+        ref = c.eval_primes(ps)
+        b, e = c.use_derived_tables()
+        got = c.eval_primes(ps)
+        st = c.stats()
+        # the terms summed are those of the rung (or printed table) each prime selects
+        def terms(p, side):
+            use = [r for r in rungs[side] if p >= r["min_p"]]
+            return _open_interval_terms(p, _ends(side, use[-1]["rounds"] if use else None))
+        assert st["n_terms"] == sum(terms(p, "B") + terms(p, "E") for p in ps)
+        # a window that straddles a threshold, searched in one call
+        m = rungs["B"][len(rungs["B"]) // 2]["min_p"]
+        win, _ = c.search_range(m - 3000, m + 3000)
+    assert as_pairs(got) == as_pairs(ref)
+    c2 = wv.Context(0)
+    try:
+        ref_win, _ = c2.search_range(m - 3000, m + 3000)
+    finally:
+        c2.close()
+    assert as_pairs(win) == as_pairs(ref_win)
+
+
+def test_set_table_below_rejects_bad_chains(ctx):
+    say("case: set_table_below errors")
+    from fractions import Fraction as F
+    jb = _derived("Vandiver", 8)
+    with wv.Context(0) as c:
+        lo = c.define_derived_table(jb, min_p=11)
+        hi = c.define_derived_table(jb, min_p=10 ** 6)
+        e = c.define_derived_table(_derived("EMac2", 8), min_p=11)
+        c.set_table_below(hi, lo)                     # a smaller min_p: fine
+        for t, below in [(hi, e),                     # another degree
+                         (lo, hi),                    # min_p not smaller (would cycle)
+                         (lo, lo),
+                         ("BB30", lo),                # a compiled table has no chain
+                         (hi, "V12"),                 # a root form
+                         (hi, 999)]:
+            with pytest.raises(wv.WvError):
+                c.set_table_below(wv.TABLE_ID[t] if isinstance(t, str) else t, below)
+        c.set_tables(hi, "EE33")
+        ps = oracle.primes(11, 2000) + oracle.primes(10 ** 6, 10 ** 6 + 200)
+        got = c.eval_primes(ps)
+    assert as_pairs(got) == as_pairs(ctx.eval_primes(ps))
+    assert as_pairs(got)[:40] == [tuple(x) for x in oracle.residues(ps[:40])]
 
 
 def test_define_table_rejects_malformed_input(ctx):
@@ -1001,25 +1079,32 @@ def test_define_table_rejects_malformed_input(ctx):
 
 def test_batch_over_2_26_slots_with_defined_tables():
     """A search batch of more than 2^26 (prime, sum) slots (about 1e5 primes
-    with the shipped ~1100-sum congruences used from p = 11): the per-sum
-    reduction indexes slots beyond 2^26 correctly; results equal the printed
-    tables' (a regression test for a 32-bit thread index)."""
+    with shipped congruences of 600 to 1000 sums in all, used from p = 11):
+    the per-sum reduction indexes slots beyond 2^26 correctly; results equal
+    the printed tables' (a regression test for a 32-bit thread index)."""
     lo, hi = 10 ** 6, 10 ** 6 + 1_400_000
-    say(f"case: range [{lo}, {hi}) with derived tables from p = 11")
+    rb = max((r for r in wv.derived_ladder("B") if r["n"] <= 500), key=lambda r: r["n"])
+    re_ = max((r for r in wv.derived_ladder("E") if r["n"] <= 500), key=lambda r: r["n"])
+    per = rb["n"] + re_["n"]
+    assert 600 <= per <= 1000
+    say(f"case: range [{lo}, {hi}) with derived tables of {per} sums from p = 11")
     with wv.Context(0) as c:
         ref, _ = c.search_range(lo, hi)
-        c.use_derived_tables(min_p=11)
+        b = c.define_derived_table(wv.derived_table("B", rb["rounds"]), min_p=11)
+        e = c.define_derived_table(wv.derived_table("E", re_["rounds"]), min_p=11)
+        c.set_tables(b, e)
         got, _ = c.search_range(lo, hi)
         st = c.stats()
-    assert st["n_sums"] > (1 << 26)
+    # one batch: fewer than 2^27 slots in all, more than 2^26
+    assert (1 << 26) < st["n_sums"] == len(got) * per < (1 << 27)
     assert [int(p) for p in got["p"]] == [int(p) for p in ref["p"]]
     assert as_pairs(got) == as_pairs(ref)
 
 
 def test_batched_windows_with_derived_tables(ctx):
-    """Windows on both sides of the derived tables' threshold (3 * 2^29) in
+    """Windows on both sides of several thresholds of the derived ladders in
     one batched call equal the same windows searched alone (the printed tables
-    below it, the derived ones above)."""
+    below the lowest threshold, above it the rung each prime's size selects)."""
     from paper_2101_11157_amd import workloads
     wins = workloads.batch_windows(0, 12, len_range=(1e2, 3e3), start_range=(1e8, 5e10))
     say(f"case: {len(wins)} windows, derived tables")

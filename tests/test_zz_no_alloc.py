@@ -103,8 +103,11 @@ def test_static_entry_matches_async_entry():
             # derived congruences near 1e11 (thousands of sums per prime): as
             # many primes as the fixed slot area holds, whose partial-pair
             # area forces chunks longer than the automatic size
-            ctx.use_derived_tables()
-            per = sum(len(wv.derived_table(side)["terms"]) for side in "BE")
+            # the largest rungs of the ladder that leave room for 40 primes
+            cap = min(max(r["rounds"] for r in wv.derived_ladder(side) if r["n"] <= (1 << 19) // 80)
+                      for side in "BE")
+            ctx.use_derived_tables(top=cap)
+            per = sum(max(r["n"] for r in wv.derived_ladder(side) if r["rounds"] <= cap) for side in "BE")
             room = (1 << 19) // per
             ps3 = oracle.primes(10 ** 11 - 10 ** 6, 10 ** 11 - 10 ** 6 + 3600)[:room]
             assert len(ps3) >= 40
