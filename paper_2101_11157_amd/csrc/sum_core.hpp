@@ -266,6 +266,38 @@ __host__ __device__ __forceinline__ uint64_t full_chunks(uint64_t len, uint64_t 
     return q;
 }
 
+// floor(x / b) for b >= 1 and a quotient below 2^52, from `est`, a double
+// within a few units of x / b: two exact 128-bit comparisons move it onto the
+// quotient (software 128-bit division is a long call on the GPU; these are a
+// few multiplies).
+__host__ __device__ __forceinline__ uint64_t quot_from_estimate(unsigned __int128 x, uint64_t b, double est) {
+    uint64_t q = est > 0.0 ? (uint64_t)est : 0;
+    while ((unsigned __int128)q * b > x) q--;
+    while ((unsigned __int128)(q + 1) * b <= x) q++;
+    return q;
+}
+
+// floor(a p / b) for a, b < 2^63 and a p / b < 2^52 (the endpoints of the
+// open intervals of eqnDefnS): the double estimate a * p / b carries a
+// relative error of at most 5 * 2^-53, under one unit.
+__host__ __device__ __forceinline__ uint64_t floor_mul_div(uint64_t a, uint64_t p, uint64_t b) {
+    return quot_from_estimate((unsigned __int128)a * p, b, (double)a * (double)p / (double)b);
+}
+
+// floor((a p - 1) / b) for a >= 1, as floor_mul_div.
+__host__ __device__ __forceinline__ uint64_t floor_mul_minus1_div(uint64_t a, uint64_t p, uint64_t b) {
+    return quot_from_estimate((unsigned __int128)a * p - 1, b, (double)a * (double)p / (double)b);
+}
+
+// (r 2^32 + limb) mod p for r < p < 2^40: one step of reducing an integer
+// given as base-2^32 limbs, most significant first.  The quotient is below
+// 2^32 and its double estimate is within one unit.
+__host__ __device__ __forceinline__ uint64_t shift_in_limb(uint64_t r, uint32_t limb, uint64_t p) {
+    const unsigned __int128 x = ((unsigned __int128)r << 32) | limb;
+    const uint64_t q = quot_from_estimate(x, p, ((double)r * 4294967296.0 + (double)limb) / (double)p);
+    return (uint64_t)(x - (unsigned __int128)q * p);
+}
+
 __device__ __forceinline__ uint32_t find_seg(const uint64_t *__restrict__ off, uint32_t nseg, uint64_t chunk) {
     // largest j in [0, nseg) with off[j] <= chunk
     uint32_t lo = 0, hi = nseg;   // invariant: off[lo] <= chunk < off[hi] (off[nseg] = total)

@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) k_scan_add(uint64_t *__restrict__ out, ui
 // significant first) mod p, canonical.
 __device__ uint64_t limbs_mod(const uint32_t *__restrict__ limb, uint32_t off, int nlimb, bool neg, uint64_t p) {
     uint64_t r = 0;
-    for (int k = nlimb - 1; k >= 0; k--) r = (uint64_t)((((unsigned __int128)r << 32) | limb[off + k]) % p);
+    for (int k = nlimb - 1; k >= 0; k--) r = shift_in_limb(r, limb[off + k], p);
     return neg && r ? p - r : r;
 }
 
@@ -435,8 +435,10 @@ __global__ void __launch_bounds__(256) k_plan_slots(uint32_t n, int nB, int nE, 
     const int side = slot < nb_slots ? 0 : 1;
     const uint64_t k = side == 0 ? slot : slot - nb_slots;
     const int per = side == 0 ? nB : nE;
-    const uint32_t i = (uint32_t)(k / per);
-    const int j = (int)(k % per);
+    // k < 2^32: a batch holds at most 2^27 slots and the server's pool fewer
+    // than 2^32 (both checked by the host), so 32-bit division will do
+    const uint32_t i = (uint32_t)k / (uint32_t)per;
+    const int j = (int)((uint32_t)k - i * (uint32_t)per);
     const PrimeRec r = pr[i];
     const TableHead h = ts.head[side == 0 ? r.tb : r.te];
     SegRec s;
@@ -448,8 +450,8 @@ __global__ void __launch_bounds__(256) k_plan_slots(uint32_t n, int nB, int nE, 
     if (r.ok && j < h.n) {
         const TableTerm d = ts.term[h.term_off + j];
         const uint64_t p = r.p;
-        const uint64_t lo = (uint64_t)((unsigned __int128)d.xa * p / d.xb) + 1;
-        const uint64_t hi = (uint64_t)(((unsigned __int128)d.ya * p - 1) / d.yb);
+        const uint64_t lo = floor_mul_div(d.xa, p, d.xb) + 1;
+        const uint64_t hi = floor_mul_minus1_div(d.ya, p, d.yb);
         s.lo = lo;
         s.len = hi >= lo ? hi - lo + 1 : 0;
         c = limbs_mod(ts.limb, d.limb_off, d.nlimb, d.neg != 0, p);
@@ -506,6 +508,36 @@ __global__ void k_pick_chunk(const uint64_t *__restrict__ total_terms, uint64_t 
 // kTailClasses classes (tail_class: length, longest first, then side), so that
 // the 64 chunks a wave takes have (nearly) equal lengths and one side, and the
 // shortest work comes last.  Slots below nb_slots are s^-3 sums.
+//
+// A workgroup takes kLayoutTile consecutive sums and counts its tails per
+// class in LDS; one lane per distinct class of a wave adds the wave's count
+// (most tails of a batch fall in a few classes, so per-lane atomics would
+// queue on one address), and the workgroup adds its counts to the global
+// ones once per class.
+constexpr int kLayoutItems = 16;
+constexpr uint64_t kLayoutTile = 256ull * kLayoutItems;
+
+// Adds, for every distinct key among the lanes with `has`, the number of
+// such lanes holding it to ctr[key]; returns this lane's rank among them
+// (the counter's old value plus the lanes below it with the same key).
+// Called by the whole wave.
+__device__ __forceinline__ uint32_t wave_rank_add(uint32_t *ctr, uint32_t key, bool has) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(has);
+    uint32_t rank = 0;
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+        const uint64_t m = __ballot(has && key == k);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&ctr[k], (uint32_t)__popcll(m));
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+        if (has && key == k) rank = base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+        pending &= ~m;
+    }
+    return rank;
+}
+
 // cnt[i] = full chunks of sum i; tail counts per class into hist.
 __global__ void __launch_bounds__(256) k_chunk_split(const uint64_t *__restrict__ terms, uint64_t nseg,
                                                      uint64_t nb_slots, const uint64_t *__restrict__ layout,
@@ -513,13 +545,24 @@ __global__ void __launch_bounds__(256) k_chunk_split(const uint64_t *__restrict_
     __shared__ uint32_t local[kTailClasses];
     if (threadIdx.x < kTailClasses) local[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t C = layout[0];
-    if (i < nseg) {
-        const uint64_t t = terms[i];
-        cnt[i] = t / C;
-        const uint64_t rem = t % C;
-        if (rem) atomicAdd(&local[tail_class(rem, C, i < nb_slots ? 3u : 2u)], 1u);
+    const double invC = 1.0 / (double)C;
+    const uint64_t first = (uint64_t)blockIdx.x * kLayoutTile;
+    for (int it = 0; it < kLayoutItems; it++) {
+        const uint64_t i = first + (uint64_t)it * 256 + threadIdx.x;
+        uint32_t cls = 0;
+        bool has = false;
+        if (i < nseg) {
+            const uint64_t t = terms[i];
+            const uint64_t q = full_chunks(t, C, invC);
+            cnt[i] = q;
+            const uint64_t rem = t - q * C;
+            if (rem) {
+                has = true;
+                cls = tail_class(rem, C, i < nb_slots ? 3u : 2u);
+            }
+        }
+        (void)wave_rank_add(local, cls, has);
     }
     __syncthreads();
     if (threadIdx.x < kTailClasses && local[threadIdx.x])
@@ -539,7 +582,9 @@ __global__ void k_tail_base(const unsigned long long *__restrict__ hist, unsigne
     *total = layout[1] + acc;
 }
 
-// tails[pos] = i for each sum with a tail, pos within its class's range.
+// tails[pos] = i for each sum with a tail, pos within its class's range: the
+// workgroup counts its tails per class, reserves that many places of each
+// class at once, then hands them out.
 __global__ void __launch_bounds__(256) k_tail_place(const uint64_t *__restrict__ terms, uint64_t nseg,
                                                     uint64_t nb_slots, const uint64_t *__restrict__ layout,
                                                     unsigned long long *__restrict__ cursor,
@@ -548,23 +593,38 @@ __global__ void __launch_bounds__(256) k_tail_place(const uint64_t *__restrict__
     __shared__ unsigned long long base[kTailClasses];
     if (threadIdx.x < kTailClasses) local[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t C = layout[0];
-    uint32_t b = 0, rank = 0;
-    bool has = false;
-    if (i < nseg) {
-        const uint64_t rem = terms[i] % C;
-        if (rem) {
-            has = true;
-            b = tail_class(rem, C, i < nb_slots ? 3u : 2u);
-            rank = atomicAdd(&local[b], 1u);
+    const double invC = 1.0 / (double)C;
+    const uint64_t first = (uint64_t)blockIdx.x * kLayoutTile;
+    uint32_t cls[kLayoutItems];
+    uint32_t has_mask = 0;
+WV_UNROLL
+    for (int it = 0; it < kLayoutItems; it++) {
+        const uint64_t i = first + (uint64_t)it * 256 + threadIdx.x;
+        cls[it] = 0;
+        if (i < nseg) {
+            const uint64_t t = terms[i];
+            const uint64_t rem = t - full_chunks(t, C, invC) * C;
+            if (rem) {
+                has_mask |= 1u << it;
+                cls[it] = tail_class(rem, C, i < nb_slots ? 3u : 2u);
+            }
         }
+        (void)wave_rank_add(local, cls[it], (has_mask >> it) & 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kTailClasses && local[threadIdx.x])
-        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], (unsigned long long)local[threadIdx.x]);
+    if (threadIdx.x < kTailClasses) {
+        const uint32_t n = local[threadIdx.x];
+        base[threadIdx.x] = n ? atomicAdd(&cursor[threadIdx.x], (unsigned long long)n) : 0ull;
+        local[threadIdx.x] = 0;
+    }
     __syncthreads();
-    if (has) tails[base[b] + rank] = (uint32_t)i;
+WV_UNROLL
+    for (int it = 0; it < kLayoutItems; it++) {
+        const bool has = (has_mask >> it) & 1u;
+        const uint32_t r = wave_rank_add(local, cls[it], has);
+        if (has) tails[base[cls[it]] + r] = (uint32_t)(first + (uint64_t)it * 256 + threadIdx.x);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -730,6 +790,7 @@ __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs,
                                                 const Pair *__restrict__ partials,
                                                 const uint64_t *__restrict__ layout, Pair *__restrict__ seg_pairs) {
     const uint64_t C = layout[0];
+    const double invC = 1.0 / (double)C;
     // wave-stride loop over groups of 64 sums (one launch covers at most 2^32
     // work-items)
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -746,7 +807,7 @@ __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs,
                 const SegRec sr = segs[j];
                 const Mont m = mont_of(pr[sr.prime]);
                 uint64_t c0 = 1, c1 = 0;
-                if (sr.len % C) {
+                if (sr.len != full_chunks(sr.len, C, invC) * C) {
                     const Pair q = seg_pairs[j];
                     c0 = q.c0;
                     c1 = q.c1;
@@ -767,7 +828,7 @@ __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs,
             const SegRec sr = segs[k];
             const Mont m = mont_of(pr[sr.prime]);
             uint64_t c0 = 1, c1 = 0;
-            if (lane == 0 && sr.len % C) {
+            if (lane == 0 && sr.len != full_chunks(sr.len, C, invC) * C) {
                 const Pair q = seg_pairs[k];
                 c0 = q.c0;
                 c1 = q.c1;
@@ -1024,14 +1085,14 @@ hipError_t launch_chunk_layout(hipStream_t st, const uint64_t *terms, uint64_t n
     unsigned long long *cursor = hist + kTailClasses;
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(2 * kTailClasses), 0, st, (uint64_t *)hist, 2 * kTailClasses,
                        (uint64_t)0);
-    hipLaunchKernelGGL(k_chunk_split, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg, nb_slots,
+    hipLaunchKernelGGL(k_chunk_split, dim3(blocks_for(nseg, kLayoutTile)), dim3(256), 0, st, terms, nseg, nb_slots,
                        (const uint64_t *)layout, cnt, hist);
     const hipError_t e = launch_scan(st, cnt, nseg, off, scan_tiles);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, st, (const uint64_t *)(off + nseg), layout + 1, 1);
     hipLaunchKernelGGL(k_tail_base, dim3(1), dim3(1), 0, st, (const unsigned long long *)hist, cursor, layout,
                        total_chunks);
-    hipLaunchKernelGGL(k_tail_place, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, terms, nseg, nb_slots,
+    hipLaunchKernelGGL(k_tail_place, dim3(blocks_for(nseg, kLayoutTile)), dim3(256), 0, st, terms, nseg, nb_slots,
                        (const uint64_t *)layout, cursor, tails);
     return hipGetLastError();
 }

@@ -275,6 +275,49 @@ int main() {
                 if (!one(len)) return 1;
         }
     }
+    // the plan's interval endpoints and limb reductions against 128-bit / and %
+    {
+        std::vector<uint64_t> qs = {11, 13, 1000003, 99999999977ull, 100000000003ull, (1ull << 40) - 87,
+                                    (1ull << 40) - 1, (1ull << 39) + 1, (1ull << 32) + 15};
+        for (int i = 0; i < 200; i++) qs.push_back((rng() % ((1ull << 40) - 11)) | 1ull);
+        std::vector<std::pair<uint64_t, uint64_t>> fr = {{0, 1}, {1, 2}, {1, 3}, {2, 5}, {1, 1}, {491, 960400},
+                                                         {127, 246960}, {9887, 19208000}, {1, 1920},
+                                                         {(1ull << 62) - 1, (1ull << 62)}, {1, (1ull << 63) - 1},
+                                                         {(1ull << 63) - 2, (1ull << 63) - 1}};
+        for (int i = 0; i < 300; i++) {
+            const uint64_t b = (rng() >> (rng() % 63)) | 1ull;
+            fr.push_back({rng() % (b + 1), b});
+        }
+        for (uint64_t p : qs) {
+            for (auto [a, b] : fr) {
+                const uint64_t want = (uint64_t)((u128)a * p / b);
+                if (floor_mul_div(a, p, b) != want) {
+                    printf("FAIL floor_mul_div a=%llu p=%llu b=%llu\n", (unsigned long long)a, (unsigned long long)p,
+                           (unsigned long long)b);
+                    return 1;
+                }
+                if (a >= 1) {
+                    const uint64_t want1 = (uint64_t)(((u128)a * p - 1) / b);
+                    if (floor_mul_minus1_div(a, p, b) != want1) {
+                        printf("FAIL floor_mul_minus1_div a=%llu p=%llu b=%llu\n", (unsigned long long)a,
+                               (unsigned long long)p, (unsigned long long)b);
+                        return 1;
+                    }
+                }
+                checks += 2;
+            }
+            for (uint64_t r : {(uint64_t)0, (uint64_t)1, p - 1, p / 2, rng() % p})
+                for (uint32_t limb : {0u, 1u, 0xFFFFFFFFu, (uint32_t)rng()}) {
+                    const uint64_t want = (uint64_t)((((u128)r << 32) | limb) % p);
+                    if (shift_in_limb(r, limb, p) != want) {
+                        printf("FAIL shift_in_limb r=%llu limb=%u p=%llu\n", (unsigned long long)r, limb,
+                               (unsigned long long)p);
+                        return 1;
+                    }
+                    checks++;
+                }
+        }
+    }
     printf("OK %ld\n", checks);
     return 0;
 }
