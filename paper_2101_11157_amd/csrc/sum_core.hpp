@@ -117,10 +117,9 @@ __host__ __device__ __forceinline__ double f_pow(double s, const Fmod &f) {
 // stepping P and Q themselves (degrees dK and d(K-1)) would take d(2K-1), for
 // a few more products per block.
 //
-// Bounds.  After a reduction every table entry is below 0.51p, and after t
-// blocks entry i is sum_m C(t, m) D_{i+m} < 0.51p 2^t; fresh tables differ only
-// in their value entries (up to 2.3p), which adds less than 1.8p < 0.064p 2^t
-// for t >= 5: every entry stays below 0.574p 2^t.  For p < 2^b (b <= 40) the
+// Bounds.  After a reduction (and in fresh tables) every table entry is
+// below 0.51p, and after t blocks entry i is sum_m C(t, m) D_{i+m} < 0.51p
+// 2^t < 0.574p 2^t.  For p < 2^b (b <= 40) the
 // tables are reduced every 53 - b >= 13 blocks (16 at p < 2^37), so they stay
 // exact integers (0.574 2^53 < 2^53), and a value entry used in a product (at
 // most 52 - b blocks after a reduction) is below 0.574 2^52.  g0 and g1 are
@@ -158,41 +157,46 @@ __host__ __device__ __forceinline__ void run_chunk_logd(uint64_t s0, uint64_t n,
     }
     if (nb > 0) {
         double G[SZ];
-        // direct values g_k(x) at x = s0 + b K for b = 0..K - k, built in place:
-        // prod_j (x + j + h) mod h^NT, one factor (all points at once) per j.
-        // Table k only needs points the lower tables also hold (b <= K - k <
-        // K - k + 2), so the update g_k <- a g_k + g_{k-1} runs from the top
-        // table down.  Left unreduced, |g_k| <= 0.574 (k + 1) p (a product
-        // plus the entry below), so |a g_k| < 2.4 p^2 stays in f_mulmod's range.
+        // The difference tables straight from the product.  With x = s0 + K t,
+        //   F(x + h) = prod_{j<K} (a_j + K t + h),  a_j = s0 + j,
+        // written as sum_{m,k} c_{m,k} C(t, m) h^k (k <= DEG, binomial
+        // coefficients of t) has c_{m,k} = Delta^m g_k(s0) (Newton's forward
+        // formula, step 1 in t): entry m of table k.  One more factor uses
+        // (a + K t) C(t, m) = (a + K m) C(t, m) + K (m + 1) C(t, m + 1), so
+        //   c_{m,k} <- (a + K m) c_{m,k} + K m c_{m-1,k} + c_{m,k-1}.
+        // Tables from the top down and entries from the highest down read
+        // only old values.  After J factors c_{m,k} = 0 for m > J - k, so
+        // each factor updates only the blocks of four entries that can be
+        // nonzero (a wave-uniform test).  Every entry stays reduced: a_j c is
+        // one exact modular product (|a_j c| < 2^41 p), and K m |c_{m,k}| and
+        // K m |c_{m-1,k}| are below 2^9 p each, so the sum is an exact integer
+        // below 2^53 and leaves f_reduce below 0.51 p.  About (DEG + 1) K^2 / 2 updates of 12 operations, against
+        // (DEG + 1) K^2 products for the values at K + 1 points and the
+        // differencing after them.
 WV_UNROLL
         for (int i = 0; i < SZ; i++) G[i] = 0.0;
-WV_UNROLL
-        for (int b = 0; b <= K; b++) G[b] = 1.0;
+        G[0] = 1.0;
 WV_NO_UNROLL
         for (int j = 0; j < K; j++) {
-            const double xj = (double)(s0 + (uint64_t)j);
+            const double aj = (double)(s0 + (uint64_t)j);
 WV_UNROLL
             for (int k = NT - 1; k >= 0; k--) {
                 const int off = k * (K + 1) - k * (k - 1) / 2;
                 const int offl = (k - 1) * (K + 1) - (k - 1) * (k - 2) / 2;
-                double a = xj;   // x + j at point b, stepped (no table of constants)
 WV_UNROLL
-                for (int b = 0; b <= K - k; b++) {
-                    const double t = f_mulmod(a, G[off + b], f);
-                    G[off + b] = k == 0 ? t : t + G[(k > 0 ? offl : 0) + b];
-                    a = opaque_f(a + (double)K);
+                for (int mb = (K - k) / 4; mb >= 0; mb--) {
+                    if (4 * mb > j + 1 - k) continue;   // entries still zero
+WV_UNROLL
+                    for (int m = (4 * mb + 3 < K - k ? 4 * mb + 3 : K - k); m >= 4 * mb; m--) {
+                        // (a_j + K m) c as a_j c (one product) plus K m c (exact):
+                        // a single per-lane multiplier instead of one per m
+                        const double km = (double)(K * m);
+                        double r = fma(G[off + m], km, f_mulmod(G[off + m], aj, f));
+                        if (m > 0) r = fma(G[off + m - 1], km, r);
+                        if (k > 0) r += G[(k > 0 ? offl : 0) + m];
+                        G[off + m] = f_reduce(r, f);
+                    }
                 }
-            }
-        }
-        // forward differences of each table (entry i becomes Delta^i), reduced
-WV_UNROLL
-        for (int k = 0; k < NT; k++) {
-            const int off = k * (K + 1) - k * (k - 1) / 2;
-            const int deg = K - k;
-WV_UNROLL
-            for (int lev = 1; lev <= deg; lev++) {
-WV_UNROLL
-                for (int i = deg; i >= lev; i--) G[off + i] = f_reduce(G[off + i] - G[off + i - 1], f);
             }
         }
         // one block: fold P, Q into the running pair, step every table once
