@@ -275,6 +275,41 @@ int main() {
                 if (!one(len)) return 1;
         }
     }
+    // f_mulmod_add at the edges of its range: |ab| < 2^51 p, |e| < 2^50
+    {
+        std::vector<uint64_t> qs = {11, 13, 53, 1000003, 99999999977ull, (1ull << 40) - 87, (1ull << 39) + 1};
+        for (int i = 0; i < 40; i++) qs.push_back((rng() % ((1ull << 40) - 11)) | 1ull);
+        for (uint64_t p : qs) {
+            Fmod f;
+            f.p = (double)p;
+            f.pinv = 1.0 / f.p;
+            const int64_t E = (int64_t)(1ull << 50) - 1;
+            const int64_t A = (int64_t)(0.51 * (double)p);               // a reduced entry
+            const int64_t B = (int64_t)std::min<uint64_t>((1ull << 41) - 1, (uint64_t)(((u128)1 << 51) * p / (A + 1) - 1));
+            auto chk = [&](int64_t a, int64_t b, int64_t e) {
+                const double r = f_mulmod_add((double)a, (double)b, (double)e, f);
+                const __int128 want = ((__int128)a * b + e) % (__int128)p;
+                const __int128 got = (__int128)(int64_t)r % (__int128)p;
+                if (std::fabs(r) >= 0.51 * f.p || r != std::floor(r) || (got - want) % (__int128)p != 0) {
+                    printf("FAIL f_mulmod_add p=%llu a=%lld b=%lld e=%lld\n", (unsigned long long)p, (long long)a,
+                           (long long)b, (long long)e);
+                    return false;
+                }
+                checks++;
+                return true;
+            };
+            for (int64_t a : {A, -A, (int64_t)1, (int64_t)0})
+                for (int64_t b : {B, -B, B - 1, (int64_t)1})
+                    for (int64_t e : {E, -E, (int64_t)0, (int64_t)p, -(int64_t)p})
+                        if (!chk(a, b, e)) return 1;
+            for (int i = 0; i < 20000; i++) {
+                const int64_t a = (int64_t)(rng() % (2 * (uint64_t)A + 1)) - A;
+                const int64_t b = (int64_t)(rng() % (2 * (uint64_t)B + 1)) - B;
+                const int64_t e = (int64_t)(rng() % (2 * (uint64_t)E + 1)) - E;
+                if (!chk(a, b, e)) return 1;
+            }
+        }
+    }
     // the plan's interval endpoints and limb reductions against 128-bit / and %
     {
         std::vector<uint64_t> qs = {11, 13, 1000003, 99999999977ull, 100000000003ull, (1ull << 40) - 87,
