@@ -11,12 +11,14 @@ take the sub-windows before the timed ones, so no step repeats work.
 
 Prints one JSON line.  `roofline` describes the term-sum kernel (the dominant
 kernel), which is bound by vector-ALU issue: the full-rate VALU operations its
-algorithm needs per term (ops_per_term below: double-precision modular
-products, difference-table additions and the periodic table reductions of the
-blocked Taylor-coefficient loop, as written in the source) times the terms it
-summed, over its
-own HIP-event time, against the chip's VALU issue rate (256 CUs x 4 SIMDs x 16
-lanes x 2.4 GHz).  Register moves the compiler adds are not counted.
+algorithm needs (ops_per_term below: double-precision modular products,
+difference-table additions and the periodic table reductions of the blocked
+Taylor-coefficient loop, times the terms it summed; plus setup_ops_per_chunk
+for every blocked chunk: building its difference tables and folding the terms
+after its last full block; both as written in the source), over its own
+HIP-event time, against the chip's VALU issue rate (256 CUs x 4 SIMDs x 16
+lanes x 2.4 GHz).  `frac_terms_only` leaves the set-up out.  Register moves
+the compiler adds are not counted.
 `cpu_baseline` is the plain CPU oracle timed on this host on a bounded sample
 of the same workload.
 """
@@ -100,6 +102,27 @@ def ops_per_term(d, k, period):
     return (per_block + sz * OPS_FRED / period) / k
 
 
+def setup_ops_per_chunk(d, k):
+    """Full-rate VALU operations of one blocked chunk's set-up, as written in
+    csrc/sum_core.hpp: the terms after the last full block folded one by one
+    ((k - 1) / 2 on average: s^d by modular products, the pair update, a
+    reduction), the tables cleared, one update per coefficient that can be
+    nonzero (blocks of four) after each of the k factors (f_mulmod_add plus
+    two exact multiply-adds, none for m = 0), the factor's own value, and the
+    two canonical residues at the end."""
+    nt = d + 1
+    upd = 0
+    for j in range(k):
+        for kk in range(nt):
+            for mb in range((k - kk) // 4 + 1):
+                if 4 * mb > j + 1 - kk:
+                    continue
+                for m in range(min(4 * mb + 3, k - kk), 4 * mb - 1, -1):
+                    upd += 8 + (2 if m > 0 else 0)
+    tail_term = (d - 1) * OPS_FMUL + 2 * OPS_FMUL + 1 + OPS_FRED
+    return (k - 1) / 2 * tail_term + table_entries(d, k) + upd + 2 * k + 2 * 5
+
+
 def muls_per_term(d, k, period):
     """Multiply-class instructions per term: 32x32-bit integer multiplies on
     the k = 1 path (ten per Montgomery product), f64 mul / fma on the blocked
@@ -160,9 +183,24 @@ class OpsModel:
             one[use] = short
         return blk, one
 
-    def ops(self, primes, n_terms_b, n_terms):
+    def _long_sums(self, ps, side, d, k):
+        """Sums per prime long enough for the blocked loop."""
+        np = self.np
+        out = np.zeros(len(ps))
+        thr = blocked_threshold(d, k)
+        mins = np.array([m for m, _ in self.rungs[side]], dtype=np.float64)
+        pick = np.searchsorted(mins, ps, side="right") - 1
+        for j in np.unique(pick):
+            w, _ = self.widths[(side, None if j < 0 else self.rungs[side][j][1])]
+            use = pick == j
+            out[use] = len(w) - np.searchsorted(w, thr / ps[use])
+        return out
+
+    def ops(self, primes, n_terms_b, n_terms, chunk=0):
         """Modelled VALU operations for the primes' term sums, scaled to the
-        measured Bernoulli-side and total term counts."""
+        measured Bernoulli-side and total term counts; with the chunk size,
+        also the set-up of every blocked chunk (about one per long sum plus
+        one per `chunk` blocked terms; setup_ops_per_chunk)."""
         np = self.np
         ps = np.asarray(primes, dtype=np.float64)
         if len(ps) == 0 or n_terms == 0:
@@ -177,6 +215,9 @@ class OpsModel:
             opt_blk = np.array([ops_per_term(d, k, int(t)) for t in per])
             ops = (blk * opt_blk).sum() + one.sum() * ops_per_term(d, 1, 1)
             total += ops * (measured / est)
+            if chunk and k > 1:
+                chunks = self._long_sums(ps, side, d, k).sum() + blk.sum() * (measured / est) / chunk
+                total += chunks * setup_ops_per_chunk(d, k)
         return total
 
 def sum_kernel_muls(st, period):
@@ -306,6 +347,7 @@ def measure_plain(args, wv, wins, lo0, hi0, W):
     block = None
     ms_sum = ms_dev = 0.0
     timed = []
+    steps_st = []
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
         res, hits = ctx.search_range(*wins[k])
@@ -318,14 +360,22 @@ def measure_plain(args, wv, wins, lo0, hi0, W):
         ms_sum += st["ms_sum"]
         ms_dev += st["ms_total"]
         timed.append(res)
+        steps_st.append((st["n_terms_b"], st["n_terms"], st["chunk_terms"]))
         print(f"step {k - args.warmup}: {len(res)} primes, {st['n_terms']:.3e} terms, "
               f"sum kernel {st['ms_sum']:.1f} ms, device {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     ctx.close()
-    plist = [int(p) for res in timed for p in res["p"]]   # bookkeeping outside the timed region
-    ops = OpsModel(args.tables, block[0], block[1]).ops(plist, terms_b, terms) if block else 0.0
-    return dict(tables=tables, primes=primes, terms=terms, terms_b=terms_b, ops=ops, muls=muls, block=block,
-                ms_sum=ms_sum, ms_dev=ms_dev, wall=wall, results=timed)
+    # bookkeeping outside the timed region: the modelled operations of each
+    # step's launch, with and without the chunks' set-up
+    ops = ops_terms = 0.0
+    if block:
+        om = OpsModel(args.tables, block[0], block[1])
+        for res, (nb, nt, C) in zip(timed, steps_st):
+            plist = [int(p) for p in res["p"]]
+            ops += om.ops(plist, nb, nt, chunk=C)
+            ops_terms += om.ops(plist, nb, nt)
+    return dict(tables=tables, primes=primes, terms=terms, terms_b=terms_b, ops=ops, ops_terms=ops_terms, muls=muls,
+                block=block, ms_sum=ms_sum, ms_dev=ms_dev, wall=wall, results=timed)
 
 
 def measure_batch(args, wv, nwin):
@@ -354,7 +404,8 @@ def measure_batch(args, wv, nwin):
     st = ctx.stats()
     primes = sum(len(r) for r in res)
     plist = [int(p) for r in res for p in r["p"]]
-    ops = OpsModel(args.tables, st["block_k_b"], st["block_k_e"]).ops(plist, st["n_terms_b"], st["n_terms"])
+    ops = OpsModel(args.tables, st["block_k_b"], st["block_k_e"]).ops(plist, st["n_terms_b"], st["n_terms"],
+                                                                       chunk=st["chunk_terms"])
     ok = None
     if args.verify:
         ctx.set_progress(None)
@@ -491,6 +542,7 @@ def main():
     m = measure_plain(args, wv, wins, lo0, hi0, W)
     value = m["primes"] / m["wall"]
     achieved = m["ops"] / (m["ms_sum"] * 1e-3) / 1e12
+    achieved_terms = m["ops_terms"] / (m["ms_sum"] * 1e-3) / 1e12
     peak = PEAK_VALU / 1e12
     mul_rate = m["muls"] / (m["ms_sum"] * 1e-3) / 1e12
     block = m["block"]
@@ -524,6 +576,8 @@ def main():
             "peak": peak,
             "unit": "Tops/s (full-rate VALU lane ops)",
             "frac": achieved / peak,
+            "achieved_terms_only": achieved_terms,
+            "frac_terms_only": achieved_terms / peak,
             "traffic": MEASURED_TRAFFIC.get(traffic_key),
             "traffic_source": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source on this window, scaled "
                                "by a copy of known size (profile constant)" if traffic_key in MEASURED_TRAFFIC
@@ -776,7 +830,10 @@ def run_trace(wv, ctx, trace, step_terms, tables="derived"):
     st = srv.stats()
     srv.close()
     served = [int(p) for res in out.values() for p in res["p"]]
-    ops = OpsModel(tables, st["block_k_b"], st["block_k_e"]).ops(served, st["terms_done_b"], st["terms_done"])
+    # the server's steps pick their own chunk sizes; at these sizes nearly
+    # every sum is one chunk whatever the size, so a nominal 2^18 stands in
+    ops = OpsModel(tables, st["block_k_b"], st["block_k_e"]).ops(served, st["terms_done_b"], st["terms_done"],
+                                                                 chunk=1 << 18)
     valu = ops / st["sum_s"] / 1e12 if st["sum_s"] > 0 else 0.0
     v = sorted(lat.values())
     pct = lambda q: v[min(len(v) - 1, int(round(q * (len(v) - 1))))]

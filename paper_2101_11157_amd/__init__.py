@@ -330,6 +330,9 @@ class Context:
         ids = []
         for side in "BE":
             rungs = [r for r in derived_ladder(side) if top is None or r["rounds"] <= top]
+            if min_p is not None:
+                # rungs that would serve only primes below min_p are left out
+                rungs = [r for k, r in enumerate(rungs) if k + 1 == len(rungs) or rungs[k + 1]["min_p"] > int(min_p)]
             if not rungs:
                 raise ValueError(f"no shipped {side} congruence of at most {top} rounds")
             below = "BB30" if side == "B" else "EE33"

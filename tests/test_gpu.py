@@ -1025,6 +1025,10 @@ def test_derived_ladder_matches_printed_tables():
         m = rungs["B"][len(rungs["B"]) // 2]["min_p"]
         win, _ = c.search_range(m - 3000, m + 3000)
     assert as_pairs(got) == as_pairs(ref)
+    # the ladders from a larger min_p (rungs below it left out)
+    with wv.Context(0) as c:
+        c.use_derived_tables(min_p=10 ** 10)
+        assert as_pairs(c.eval_primes(ps)) == as_pairs(ref)
     c2 = wv.Context(0)
     try:
         ref_win, _ = c2.search_range(m - 3000, m + 3000)
