@@ -346,7 +346,8 @@ int wv_eval_primes_async(wv_ctx *ctx, const uint64_t *d_primes, size_t n,
  * the process ends (looked up by wv_create); ctx contributes only its
  * congruence tables and settings.  Limits: n <= WV_STATIC_MAX_PRIMES and n
  * times the sums per prime <= WV_STATIC_MAX_SLOTS (524288: 8322 primes with
- * the printed tables, 46 with the package's derived ones); larger calls
+ * the printed tables, 8 with the top rungs of the package's derived ladders,
+ * whose lower rungs fit more); larger calls
  * return WV_EINVAL before enqueueing anything.  All calls on one GPU share
  * that GPU's array, which keeps the last call's contents: calls whose work
  * overlaps on one GPU (other streams, other contexts, other host threads)

@@ -326,7 +326,9 @@ class Context:
         and use them: each rung serves the primes from its min_p up to the next
         rung's, the lowest from min_p when given (else its own), and the
         printed eqnBB30 / eqnEE33 the primes below.  top: use only the rungs
-        of at most this many rounds.  Returns (b_id, e_id) of the top rungs."""
+        of at most this many rounds.  Each rung is one defined table of the
+        context's 64 (about 30 in all).  Returns (b_id, e_id) of the top
+        rungs."""
         ids = []
         for side in "BE":
             rungs = [r for r in derived_ladder(side) if top is None or r["rounds"] <= top]

@@ -8,9 +8,10 @@ the paper's 546-sum Bernoulli congruence) and eqnEMac2 (E; the paper reports
 reproduces).  More rounds give more, shorter sums and fewer terms in total.
 On the GPU a prime's work is its terms plus a fixed cost per sum (the set-up
 of a chunk's difference tables, its reduction and its share of the last,
-ragged chunks), measured as about BETA = 8000 terms per sum (greedy tables of
-1200 to 2000 rounds at 3e9, 1e10 and 1e11), so the best number of rounds
-grows with p.  For each target p in TARGETS the search keeps the round whose
+ragged chunks), measured as about BETA = 6000 terms per sum (a least-squares
+fit of time per prime against terms and sums, four congruence pairs of 4548
+to 44,484 sums at each of 3e9, 1e10 and 1e11: 6193, 5682 and 6018 terms),
+so the best number of rounds grows with p.  For each target p in TARGETS the search keeps the round whose
 congruence minimises cost * p + BETA * sums; the distinct rounds found are the
 rungs of the ladder, and each rung serves the primes from the point where its
 work falls below the next smaller rung's (the lowest: below eqnBB30 /
@@ -40,9 +41,9 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from paper_2101_11157_amd import derive  # noqa: E402
 
-ROUNDS = {"B": 4500, "E": 4500}
+ROUNDS = {"B": 6000, "E": 6000}
 START = {"B": "Vandiver", "E": "EMac2"}
-BETA = 8000                                        # terms of work per sum (measured)
+BETA = 6000                                        # terms of work per sum (measured)
 TARGETS = [int(2 ** (k / 2)) for k in range(56, 77)]   # 2^28 .. 2^38, factor sqrt(2)
 MIN_SPAN = 1.4                                         # narrowest range of p a rung serves
 # eqnBB30 / eqnEE33 (Sections 3 and 5): sums, cost per unit p

@@ -84,6 +84,7 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.wv_create(0, None) == wv.WV_EINVAL
     assert lib.wv_destroy(None) == wv.WV_OK
     assert lib.wv_set_tables(None, 6, 12) == wv.WV_EINVAL
+    assert lib.wv_set_table_below(None, 15, 6) == wv.WV_EINVAL
     assert lib.wv_count_primes(None, 0, 10, None) == wv.WV_EINVAL
     assert lib.wv_eval_primes(None, None, 0, None) == wv.WV_EINVAL
     assert lib.wv_get_stats(None, None) == wv.WV_EINVAL
