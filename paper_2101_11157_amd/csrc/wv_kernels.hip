@@ -860,18 +860,19 @@ __global__ void __launch_bounds__(256) k_reduce(const SegRec *__restrict__ segs,
     }
 }
 
-// L^-1 sum_i coef_i c1_i / c0_i mod p for one congruence of n sums; pairs at
-// sp[first + j], coefficients mod p at coef[first + j], L mod p in lhs.  The
-// 64 lanes of the calling wave each fold every 64th sum into a running
-// fraction N/D (Montgomery values; any common factor of N and D is
-// harmless), the fractions are added across the wave by a butterfly
-// (N1/D1 + N2/D2 = (N1 D2 + N2 D1) / (D1 D2)), and every lane ends with the
-// residue.  The whole wave must be active.
-__device__ uint64_t combine_residue(int n, const Pair *__restrict__ sp, const uint64_t *__restrict__ coef,
-                                    size_t first, uint64_t lhs, const Mont &m, uint64_t r2, uint64_t one, int lane) {
-    const uint64_t p = m.p;
-    uint64_t N = 0, D = one;
-    for (int j = lane; j < n; j += 64) {
+// The fraction N/D = sum_j coef_j c1_j / c0_j (Montgomery values; any common
+// factor of N and D is harmless) over the sums j = j0, j0 + stride, ... of a
+// congruence of n sums, for a wave whose lanes start at consecutive j0: each
+// lane folds its sums into a running fraction, and a butterfly adds the
+// lanes' fractions (N1/D1 + N2/D2 = (N1 D2 + N2 D1) / (D1 D2)), so every lane
+// ends with the wave's.  Pairs at sp[first + j], coefficients mod p at
+// coef[first + j].  The whole wave must be active.
+__device__ void fraction_part(int n, const Pair *__restrict__ sp, const uint64_t *__restrict__ coef, size_t first,
+                              const Mont &m, uint64_t r2, uint64_t one, int j0, int stride, uint64_t &N,
+                              uint64_t &D) {
+    N = 0;
+    D = one;
+    for (int j = j0; j < n; j += stride) {
         const Pair q = sp[first + j];
         const uint64_t cR = to_mont(coef[first + j], r2, m);
         const uint64_t num = mmul(mmul(cR, q.c1, m), D, m);       // coef c1 D / R
@@ -884,11 +885,30 @@ __device__ uint64_t combine_residue(int n, const Pair *__restrict__ sp, const ui
         N = mmul(N, D2, m) + mmul(N2, D, m);
         D = mmul(D, D2, m);
     }
+}
+
+// N / (D L) mod p, canonical (N, D Montgomery values, L the left side mod p).
+__device__ uint64_t fraction_residue(uint64_t N, uint64_t D, uint64_t lhs, const Mont &m, uint64_t r2, uint64_t one) {
+    const uint64_t p = m.p;
     const uint64_t LR = to_mont(lhs, r2, m);
     const uint64_t X = mmul(D, LR, m);                              // D L
     const uint64_t XR = mmul(X, r2, m);                             // D L R
     const uint64_t inv = mpow(XR, p - 2, one, m);                   // (D L)^-1 R
     return red1(mmul(N, inv, m), p);                                // N / (D L)
+}
+
+// L^-1 sum_i coef_i c1_i / c0_i mod p for one congruence of n sums; pairs at
+// sp[first + j], coefficients mod p at coef[first + j], L mod p in lhs.  The
+// 64 lanes of the calling wave each fold every 64th sum into a running
+// fraction N/D (Montgomery values; any common factor of N and D is
+// harmless), the fractions are added across the wave by a butterfly
+// (N1/D1 + N2/D2 = (N1 D2 + N2 D1) / (D1 D2)), and every lane ends with the
+// residue.  The whole wave must be active.
+__device__ uint64_t combine_residue(int n, const Pair *__restrict__ sp, const uint64_t *__restrict__ coef,
+                                    size_t first, uint64_t lhs, const Mont &m, uint64_t r2, uint64_t one, int lane) {
+    uint64_t N, D;
+    fraction_part(n, sp, coef, first, m, r2, one, lane, 64, N, D);
+    return fraction_residue(N, D, lhs, m, r2, one);
 }
 
 // acc[target[t]] <- acc[target[t]] * tp[t] in F_p[z]/(z^2) (eqnCombinePairs),
@@ -949,15 +969,53 @@ __device__ inline wv_result finalize_prime(const TableStore &ts, const PrimeRec 
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_finalize(TableStore ts, const PrimeRec *__restrict__ pr,
-                                                  const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
-                                                  const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
-                                                  wv_result *__restrict__ out, const unsigned long long *__restrict__ err) {
-    const uint32_t i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= n) return;   // whole wave
-    const wv_result r = finalize_prime(ts, pr, sp, coefs, lhsmod, n, nB, nE, i, err, lane);
-    if (lane == 0) out[i] = r;
+// One workgroup of four waves per prime: waves 0 and 1 take the Bernoulli
+// side's sums (every other group of 64), waves 2 and 3 the Euler side's; the
+// two halves of each side are joined through LDS and the residue taken by
+// the side's first wave.  Four times the parallelism of one wave per prime,
+// which left the fraction loop waiting on its loads.
+__global__ void __launch_bounds__(256) k_finalize_wg(TableStore ts, const PrimeRec *__restrict__ pr,
+                                                     const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
+                                                     const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
+                                                     wv_result *__restrict__ out,
+                                                     const unsigned long long *__restrict__ err) {
+    __shared__ uint64_t part[4][2];
+    __shared__ uint64_t res[2];
+    const uint32_t i = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const PrimeRec P = pr[i];
+    const bool bad = !P.ok || (err && *err);   // the same for the whole workgroup
+    if (bad) {
+        if (threadIdx.x == 0) out[i] = wv_result{0, 0, 0, 0xFFFFFFFFu, 0};
+        return;
+    }
+    const Mont m = mont_of(P);
+    const int side = wave >> 1, half = wave & 1;
+    const int ns = ts.head[side == 0 ? P.tb : P.te].n;
+    const size_t first = side == 0 ? (size_t)i * nB : (size_t)n * nB + (size_t)i * nE;
+    uint64_t N, D;
+    fraction_part(ns, sp, coefs, first, m, P.r2, P.one, half * 64 + lane, 128, N, D);
+    if (lane == 0) {
+        part[wave][0] = N;
+        part[wave][1] = D;
+    }
+    __syncthreads();
+    if (half == 0) {
+        const uint64_t N2 = part[wave + 1][0], D2 = part[wave + 1][1];
+        const uint64_t Nt = mmul(N, D2, m) + mmul(N2, D, m), Dt = mmul(D, D2, m);
+        const uint64_t r = fraction_residue(Nt, Dt, lhsmod[2 * (size_t)i + side], m, P.r2, P.one);
+        if (lane == 0) res[side] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        wv_result r;
+        r.p = P.p;
+        r.b = res[0];
+        r.e = res[1];
+        r.flags = (r.b == 0 ? WV_FLAG_WOLSTENHOLME : 0u) | (r.e == 0 ? WV_FLAG_VANDIVER : 0u);
+        r.reserved = 0;
+        out[i] = r;
+    }
 }
 
 // One wave per prime of several pool requests (fr[k]: slots [base, base + n),
@@ -1135,9 +1193,9 @@ hipError_t launch_reduce(hipStream_t st, const SegRec *segs, const uint64_t *off
 hipError_t launch_finalize(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *sp, const uint64_t *coefs,
                            const uint64_t *lhsmod, uint32_t n, int nB, int nE, wv_result *out,
                            const unsigned long long *err) {
-    if (too_many((uint64_t)n * 64)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for((uint64_t)n * 64, 256)), dim3(256), 0, st, ts, pr, sp, coefs, lhsmod,
-                       n, nB, nE, out, err);
+    if (n == 0) return hipSuccess;
+    if (too_many((uint64_t)n * 256)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_finalize_wg, dim3(n), dim3(256), 0, st, ts, pr, sp, coefs, lhsmod, n, nB, nE, out, err);
     return hipGetLastError();
 }
 
