@@ -303,9 +303,11 @@ def test_known_wolstenholme_and_vandiver_primes():
     assert [p for p, (_, e) in zip(ps, res) if e == 0] == [149, 241]
 
 
-def _near_miss(name, cong, limit, slow):
+def _near_miss(name, cong, limit, slow, ends_only=False):
     rows = [(int(p), int(r)) for p, r in read_golden(name)]
-    rows = [(p, r) for p, r in rows if (p >= limit) == slow]
+    rows = sorted((p, r) for p, r in rows if (p >= limit) == slow)
+    if ends_only:
+        rows = [rows[0], rows[-1]]
     for p, r in rows:
         got = oracle.congruence_residue(p, cong, nthreads=oracle.max_threads())
         assert exact.symmetric(got, p) == r, (p, r, got)
@@ -317,6 +319,15 @@ def test_table2_near_misses():
 
 def test_table3_near_misses():
     _near_miss("near_miss_E.txt", C.EE33, 1.2e10, slow=False)
+
+
+def test_tables_2_and_3_largest_printed_primes():
+    """The smallest and the largest printed prime of each table above the
+    default range (up to 7.76e10, Tables 2 and 3): the oracle's plain
+    eqnBB30 / eqnEE33 gives the printed symmetric residues; the slow tests
+    below check every printed prime up there."""
+    _near_miss("near_miss_B.txt", C.BB30, 1.6e10, slow=True, ends_only=True)
+    _near_miss("near_miss_E.txt", C.EE33, 1.2e10, slow=True, ends_only=True)
 
 
 @pytest.mark.slow
