@@ -425,6 +425,35 @@ def measure_batch(args, wv, nwin):
                 n_verified=args.verify, wins=wins, results=res)
 
 
+def same_windows_batched(args, wv, wins):
+    """The same sub-windows of the headline range through the plain path (one
+    wv_search_range call each, in order) and through one wv_search_windows
+    call, on one context with the same congruences; primes/s of both over
+    the wall clock and whether every result is identical."""
+    if not wins:
+        return None
+    ctx = wv.Context(0)
+    use_tables(ctx, args.tables)
+    # warm-up, not timed: the batched call sizes the context's device buffers
+    # (a few GB of plan records) for both paths
+    ctx.search_windows([a for a, _ in wins], [b for _, b in wins])
+    t0 = time.perf_counter()
+    plain = [ctx.search_range(a, b)[0] for a, b in wins]
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batched = ctx.search_windows([a for a, _ in wins], [b for _, b in wins])
+    t_batch = time.perf_counter() - t0
+    ctx.close()
+    n = sum(len(r) for r in plain)
+    same = all(as_pairs(x) == as_pairs(y) for x, y in zip(plain, batched))
+    print(f"same windows at 1e11: {len(wins)} windows, {n} primes, plain {t_plain:.3f} s, batched {t_batch:.3f} s",
+          file=sys.stderr, flush=True)
+    return {"workload": f"{len(wins)} consecutive sub-windows of {wins[0][1] - wins[0][0]} integers after the timed "
+                        f"ones ({wins[0][0]}..{wins[-1][1]})",
+            "primes": n, "plain_primes_per_s": n / t_plain, "batched_primes_per_s": n / t_batch,
+            "batched_over_plain": t_plain / t_batch, "identical_results": same}
+
+
 def per_window_plain(args, wv, wins, batched):
     """The plain per-window path on the same windows: one wv_search_range call
     per window, in order, on a fresh context with the same congruences;
@@ -541,6 +570,10 @@ def main():
 
     m = measure_plain(args, wv, wins, lo0, hi0, W)
     value = m["primes"] / m["wall"]
+    # the next 8 sub-windows (work the timed steps did not do) for the
+    # batched-against-plain comparison at the headline's size
+    wins_extra = (workloads.bench_windows(nwin + 8, W, lo0, hi0)[nwin:]
+                  if args.config == "1e11" and lo0 + (nwin + 8) * W <= hi0 else [])
     achieved = m["ops"] / (m["ms_sum"] * 1e-3) / 1e12
     achieved_terms = m["ops_terms"] / (m["ms_sum"] * 1e-3) / 1e12
     peak = PEAK_VALU / 1e12
@@ -588,6 +621,8 @@ def main():
     # this fraction is low although the kernel is bound by VALU issue
     line["multiply_ops"] = {"achieved": mul_rate, "peak": peak, "unit": "Tops/s", "frac": mul_rate / peak}
 
+    if args.config == "1e11" and not args.no_batch and not args.no_same_work:
+        line["batched_1e11"] = same_windows_batched(args, wv, wins_extra)
     if args.config == "1e11" and not args.no_batch:
         b = measure_batch(args, wv, args.windows)
         line["batched"] = dict({"workload": b["workload"], "tables": b["tables"], "block": b["block"]},
