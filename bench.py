@@ -51,7 +51,7 @@ BLOCK_ADD = {2: 3, 3: 5}
 # for the kernel source, shape, tables and window it was taken on (keyed by the
 # hash of the kernel sources), reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("1e11", "derived 31184/30413", 28, 36, 8192, "72036aae1568"): 3861220184,
+    ("1e11", "derived 31184/30413", 28, 36, 8192, "a23d13af47cd"): 3861060498,
 }
 
 
