@@ -856,8 +856,13 @@ int wv_set_table_below(wv_ctx *c, int id, int below) {
     // a defined table below must start lower, so every chain ends at a compiled table
     if (below >= WV_TABLE_COUNT && c->t_head[below].min_p >= c->t_head[id].min_p) return WV_EINVAL;
     WV_TRY(check_device(c));
+    const int32_t old = c->t_head[id].below;
     c->t_head[id].below = below;
-    WV_TRY(upload_tables(c));
+    const int rc = upload_tables(c);
+    if (rc != WV_OK) {
+        c->t_head[id].below = old;   // the device copy may be partial: the next upload restores it
+        return rc;
+    }
     c->gen++;   // captured graphs were sized for the old chain
     return WV_OK;
 }
