@@ -517,8 +517,17 @@ int table_add(wv_ctx *c, int deg, const std::vector<uint32_t> &lhs_mag, bool lhs
     }
     c->t_head.push_back(h);
     c->t_cost.push_back(cost);
+    const int rc = upload_tables(c);
+    if (rc != WV_OK) {
+        // leave the registry as it was (the next upload rewrites the device copy)
+        c->t_head.pop_back();
+        c->t_cost.pop_back();
+        c->t_term.resize(h.term_off);
+        c->t_limb.resize(h.lhs_off);
+        return rc;
+    }
     *id = (int)c->t_head.size() - 1;
-    return upload_tables(c);
+    return WV_OK;
 }
 
 // The compiled tables, from wv_tables.hpp, become registry entries 0..WV_TABLE_COUNT-1.
