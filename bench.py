@@ -38,12 +38,15 @@ OPS_ADDM = 3        # one modular addition: add, subtract, select
 OPS_FMUL = 6        # one double-precision modular product: mul, 3 fma, 2 add
 OPS_FRED = 3        # one double-precision reduction: fma, add, fma
 # per block of the Taylor-coefficient loop: modular products, reductions of
-# the g_k entering them (g0 and g1), and plain additions (d = 2: P, g0 g2,
-# g1^2 and the three updates of the running pair; d = 3: g0^2, P, g3 g0^2,
-# g0 g1 g2, g1^3 and the three updates)
-BLOCK_FMUL = {2: 6, 3: 10}
+# the g_k entering them (g0 and g1), and plain additions or exact
+# multiply-adds (d = 2: P = g0^2, g0 g2, g1^2, Q = g1^2 - 2 g0 g2 and the three
+# products of the running pair's update, plus its one addition; d = 3:
+# g0^2, P, g0^2 g3, g0 g2, g1^2, g1 (g1^2 - 3 g0 g2), Q as a multiply-add,
+# and the update)
+BLOCK_FMUL = {2: 6, 3: 9}
 BLOCK_FRED = {2: 2, 3: 2}
-BLOCK_ADD = {2: 3, 3: 5}
+BLOCK_ADD = {2: 2, 3: 3}
+BLOCK_XFMA = {2: 1, 3: 2}   # of BLOCK_ADD, the exact multiply-adds forming Q
 
 # HBM bytes (read + written) of one term-sum launch on the bench's first timed
 # window, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of
@@ -51,7 +54,7 @@ BLOCK_ADD = {2: 3, 3: 5}
 # for the kernel source, shape, tables and window it was taken on (keyed by the
 # hash of the kernel sources), reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("1e11", "derived 31184/30413", 28, 36, 8192, "a23d13af47cd"): 3861060498,
+    ("1e11", "derived 31184/30413", 28, 36, 8192, "ed13e8016360"): 3787720043,
 }
 
 
@@ -129,7 +132,7 @@ def muls_per_term(d, k, period):
     path (four per modular product, two per reduction)."""
     if k == 1:
         return 2 * 10
-    return (BLOCK_FMUL[d] * 4 + BLOCK_FRED[d] * 2 + table_entries(d, k) * 2 / period) / k
+    return (BLOCK_FMUL[d] * 4 + BLOCK_FRED[d] * 2 + BLOCK_XFMA[d] + table_entries(d, k) * 2 / period) / k
 
 
 def blocked_threshold(d, k):

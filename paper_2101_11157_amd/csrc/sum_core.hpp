@@ -123,7 +123,7 @@ __host__ __device__ __forceinline__ double f_pow(double s, const Fmod &f) {
 // polynomial identities:
 //   d = 2:  sum_j (x+j)^-2 = (F'^2 - F F'') / F^2,             Q = g1^2 - 2 g0 g2,
 //   d = 3:  sum_j (x+j)^-3 = (F''' F^2 - 3 F F' F'' + 2 F'^3) / (2 F^3),
-//           Q = 3 g3 g0^2 - 3 g0 g1 g2 + g1^3.
+//           Q = 3 g3 g0^2 - 3 g0 g1 g2 + g1^3 = 3 g0^2 g3 + g1 (g1^2 - 3 g0 g2).
 // So only g_0..g_d (degrees K..K-d in x) are stepped by finite differences
 // along x = s0, s0 + K, ...: (d+1)K - d(d+1)/2 additions per block, where
 // stepping P and Q themselves (degrees dK and d(K-1)) would take d(2K-1), for
@@ -137,9 +137,11 @@ __host__ __device__ __forceinline__ double f_pow(double s, const Fmod &f) {
 // most 52 - b blocks after a reduction) is below 0.574 2^52.  g0 and g1 are
 // reduced first (|r| < 0.51p); g2 and g3 enter unreduced, each times a reduced
 // operand or a product of two (|x| < 0.574p), so |ab| < 0.33 p 2^52 = 2^50.4 p,
-// inside f_mulmod's exact range (|ab| < 2^51 p), with |result| < 0.83p.  Then
-// |Q| < 5.6p (d = 3) or 2.3p (d = 2), and |a0 Q| < 3.3 p^2.  Returns plain
-// residues in [0, p) with the same ratio c1/c0 as run_chunk.
+// inside f_mulmod's exact range (|ab| < 2^51 p), with |result| < 0.83p.  For
+// d = 3, g1^2 - 3 g0 g2 is an exact integer below 3.1p, times g1 below 1.6p^2;
+// then |Q| < 3.0p (d = 3) or 2.3p (d = 2) (the multiply-adds are exact), and
+// |a0 Q| < 1.8 p^2.  Returns plain residues in [0, p) with the same ratio
+// c1/c0 as run_chunk.
 //
 // nb_shared, period_shared: a block count and a reduction period that every
 // lane of the calling wave shares, at most this lane's n / K and 53 - b (the
@@ -220,18 +222,19 @@ WV_UNROLL
             const double r2 = G[2 * K + 1];
             double P, Q;
             if (DEG == 2) {
+                // Q = g1^2 - 2 g0 g2
                 P = f_mulmod(r0, r0, f);
                 const double u = f_mulmod(r0, r2, f);
-                Q = f_mulmod(r1, r1, f) - (u + u);
+                Q = fma(u, -2.0, f_mulmod(r1, r1, f));
             } else {
+                // Q = 3 g0^2 g3 + g1 (g1^2 - 3 g0 g2): six products for P and Q
                 const double r3 = G[3 * K];
                 const double sq = f_mulmod(r0, r0, f);
                 P = f_mulmod(sq, r0, f);
                 const double A = f_mulmod(r3, sq, f);
-                const double C = f_mulmod(f_mulmod(r0, r1, f), r2, f);
-                const double E = f_mulmod(f_mulmod(r1, r1, f), r1, f);
-                const double D = A - C;
-                Q = (D + D + D) + E;
+                const double t = f_mulmod(r0, r2, f);
+                const double u = fma(t, -3.0, f_mulmod(r1, r1, f));
+                Q = fma(A, 3.0, f_mulmod(r1, u, f));
             }
             const double n1 = f_mulmod(a0, Q, f) + f_mulmod(a1, P, f);
             a0 = f_mulmod(a0, P, f);
