@@ -39,14 +39,14 @@ OPS_FMUL = 6        # one double-precision modular product: mul, 3 fma, 2 add
 OPS_FRED = 3        # one double-precision reduction: fma, add, fma
 # per block of the Taylor-coefficient loop: modular products, reductions of
 # the g_k entering them (g0 and g1), and plain additions or exact
-# multiply-adds (d = 2: P = g0^2, g0 g2, g1^2, Q = g1^2 - 2 g0 g2 and the three
-# products of the running pair's update, plus its one addition; d = 3:
-# g0^2, P, g0^2 g3, g0 g2, g1^2, g1 (g1^2 - 3 g0 g2), Q as a multiply-add,
-# and the update)
+# multiply-adds (d = 2: P = g0^2, g0 g2, g1^2, Q = g1^2 - 2 g0 g2 by two
+# additions and the three products of the running pair's update, plus its one
+# addition; d = 3: g0^2, P, g0^2 g3, g0 g2, g1^2, g1 (g1^2 - 3 g0 g2), Q, the
+# two differences as multiply-adds, and the update)
 BLOCK_FMUL = {2: 6, 3: 9}
 BLOCK_FRED = {2: 2, 3: 2}
-BLOCK_ADD = {2: 2, 3: 3}
-BLOCK_XFMA = {2: 1, 3: 2}   # of BLOCK_ADD, the exact multiply-adds forming Q
+BLOCK_ADD = {2: 3, 3: 3}
+BLOCK_XFMA = {2: 0, 3: 2}   # of BLOCK_ADD, the exact multiply-adds forming Q
 
 # HBM bytes (read + written) of one term-sum launch on the bench's first timed
 # window, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy of
