@@ -154,8 +154,12 @@ namespace {
 
 hipStream_t stream_of(const wv_server *s, int k) { return k == 0 ? s->c->stream : s->own; }
 
-// Tasks per step at most (whole primes of nB + nE sums each).
-constexpr uint64_t kMaxStepTasks = 1ull << 22;
+// Tasks per step at most (whole primes of nB + nE sums each): with the
+// derived ladders' 61,597 sums per prime near 1e11, 136 primes, so that the
+// configured step_terms (2^38 by default, about 88 such primes) sets the
+// step, not this cap (at 2^22 it did: 68 primes, 2 % less throughput on the
+// serving trace for half the median latency).
+constexpr uint64_t kMaxStepTasks = 1ull << 23;
 // Upload staging per half at creation (it grows for larger prime lists).
 constexpr size_t kUploadBytes = 1u << 20;
 
