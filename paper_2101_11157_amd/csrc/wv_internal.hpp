@@ -188,8 +188,9 @@ hipError_t launch_fill_pairs(hipStream_t st, Pair *p, uint64_t n, uint64_t c0, u
 // length, target[t] = g (its pool index).
 hipError_t launch_step_expand(hipStream_t st, const StepSpan *sp, uint32_t nsp, uint32_t nq, int nB, int nE,
                               const SegRec *segs, SegRec *tasks, uint64_t *terms, uint32_t *target);
-// k_finalize for several requests of the pool at once (FinReq list, `total`
-// primes): pool arrays pr, acc, coefs, lhsmod with nB + nE sums per prime
+// Finalize (a workgroup per prime) for several requests of the pool at once
+// (FinReq list, `total` primes): pool arrays pr, acc, coefs, lhsmod with
+// nB + nE sums per prime
 hipError_t launch_finalize_multi(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *acc,
                                  const uint64_t *coefs, const uint64_t *lhsmod, const FinReq *fr, uint32_t nfr,
                                  uint32_t total, int nB, int nE, wv_result *out, const unsigned long long *err);

@@ -897,20 +897,6 @@ __device__ uint64_t fraction_residue(uint64_t N, uint64_t D, uint64_t lhs, const
     return red1(mmul(N, inv, m), p);                                // N / (D L)
 }
 
-// L^-1 sum_i coef_i c1_i / c0_i mod p for one congruence of n sums; pairs at
-// sp[first + j], coefficients mod p at coef[first + j], L mod p in lhs.  The
-// 64 lanes of the calling wave each fold every 64th sum into a running
-// fraction N/D (Montgomery values; any common factor of N and D is
-// harmless), the fractions are added across the wave by a butterfly
-// (N1/D1 + N2/D2 = (N1 D2 + N2 D1) / (D1 D2)), and every lane ends with the
-// residue.  The whole wave must be active.
-__device__ uint64_t combine_residue(int n, const Pair *__restrict__ sp, const uint64_t *__restrict__ coef,
-                                    size_t first, uint64_t lhs, const Mont &m, uint64_t r2, uint64_t one, int lane) {
-    uint64_t N, D;
-    fraction_part(n, sp, coef, first, m, r2, one, lane, 64, N, D);
-    return fraction_residue(N, D, lhs, m, r2, one);
-}
-
 // acc[target[t]] <- acc[target[t]] * tp[t] in F_p[z]/(z^2) (eqnCombinePairs),
 // one thread per task; each target appears at most once per launch.
 __global__ void __launch_bounds__(256) k_fold(const SegRec *__restrict__ tasks, const uint32_t *__restrict__ target,
@@ -942,51 +928,25 @@ __global__ void __launch_bounds__(256) k_sum_values(const SegRec *__restrict__ s
     out[j] = P.ok ? red1(mmul(q.c1, inv, m), P.p) : 0;
 }
 
-// One wave per prime.  A prime that the plan rejected, or every prime of a
-// batch whose term sums reported an error (*err != 0; err may be null), gets
-// flags = 0xFFFFFFFF.
-// Prime i of a batch of n (one wave; every lane returns the result).
-__device__ inline wv_result finalize_prime(const TableStore &ts, const PrimeRec *__restrict__ pr,
-                                           const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
-                                           const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE, uint32_t i,
-                                           const unsigned long long *__restrict__ err, int lane) {
-    const PrimeRec P = pr[i];
-    wv_result r;
-    r.reserved = 0;
-    if (!P.ok || (err && *err)) {
-        r.p = 0;
-        r.b = 0;
-        r.e = 0;
-        r.flags = 0xFFFFFFFFu;
-        return r;
-    }
-    const Mont m = mont_of(P);
-    r.p = P.p;
-    r.b = combine_residue(ts.head[P.tb].n, sp, coefs, (size_t)i * nB, lhsmod[2 * (size_t)i], m, P.r2, P.one, lane);
-    r.e = combine_residue(ts.head[P.te].n, sp, coefs, (size_t)n * nB + (size_t)i * nE, lhsmod[2 * (size_t)i + 1], m,
-                          P.r2, P.one, lane);
-    r.flags = (r.b == 0 ? WV_FLAG_WOLSTENHOLME : 0u) | (r.e == 0 ? WV_FLAG_VANDIVER : 0u);
-    return r;
-}
-
-// One workgroup of four waves per prime: waves 0 and 1 take the Bernoulli
-// side's sums (every other group of 64), waves 2 and 3 the Euler side's; the
-// two halves of each side are joined through LDS and the residue taken by
-// the side's first wave.  Four times the parallelism of one wave per prime,
-// which left the fraction loop waiting on its loads.
-__global__ void __launch_bounds__(256) k_finalize_wg(TableStore ts, const PrimeRec *__restrict__ pr,
-                                                     const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
-                                                     const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
-                                                     wv_result *__restrict__ out,
-                                                     const unsigned long long *__restrict__ err) {
+// The residues and flags of prime i by a workgroup of four waves: waves 0
+// and 1 take the Bernoulli side's sums (every other group of 64), waves 2
+// and 3 the Euler side's; the two halves of each side are joined through LDS
+// and the residue taken by the side's first wave.  Four times the
+// parallelism of one wave per prime, which left the fraction loop waiting on
+// its loads.  A prime that the plan rejected, or every prime of a batch whose
+// term sums reported an error (*err), gets p = 0 and flags 0xFFFFFFFF.
+// Called by the whole workgroup; writes *out.
+__device__ void finalize_prime_wg(const TableStore &ts, const PrimeRec *__restrict__ pr,
+                                  const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
+                                  const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE, uint32_t i,
+                                  const unsigned long long *__restrict__ err, wv_result *__restrict__ out) {
     __shared__ uint64_t part[4][2];
     __shared__ uint64_t res[2];
-    const uint32_t i = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const PrimeRec P = pr[i];
     const bool bad = !P.ok || (err && *err);   // the same for the whole workgroup
     if (bad) {
-        if (threadIdx.x == 0) out[i] = wv_result{0, 0, 0, 0xFFFFFFFFu, 0};
+        if (threadIdx.x == 0) *out = wv_result{0, 0, 0, 0xFFFFFFFFu, 0};
         return;
     }
     const Mont m = mont_of(P);
@@ -1014,12 +974,22 @@ __global__ void __launch_bounds__(256) k_finalize_wg(TableStore ts, const PrimeR
         r.e = res[1];
         r.flags = (r.b == 0 ? WV_FLAG_WOLSTENHOLME : 0u) | (r.e == 0 ? WV_FLAG_VANDIVER : 0u);
         r.reserved = 0;
-        out[i] = r;
+        *out = r;
     }
 }
 
-// One wave per prime of several pool requests (fr[k]: slots [base, base + n),
-// results at out[out0 ..]; out0 ascending from 0, `total` primes in all).
+// One workgroup per prime of a batch.
+__global__ void __launch_bounds__(256) k_finalize_wg(TableStore ts, const PrimeRec *__restrict__ pr,
+                                                     const Pair *__restrict__ sp, const uint64_t *__restrict__ coefs,
+                                                     const uint64_t *__restrict__ lhsmod, uint32_t n, int nB, int nE,
+                                                     wv_result *__restrict__ out,
+                                                     const unsigned long long *__restrict__ err) {
+    finalize_prime_wg(ts, pr, sp, coefs, lhsmod, n, nB, nE, blockIdx.x, err, out + blockIdx.x);
+}
+
+// One workgroup per prime of several pool requests (fr[k]: slots [base, base
+// + n), results at out[out0 ..]; out0 ascending from 0, `total` primes in
+// all).
 __global__ void __launch_bounds__(256) k_finalize_multi(TableStore ts, const PrimeRec *__restrict__ pr,
                                                         const Pair *__restrict__ acc,
                                                         const uint64_t *__restrict__ coefs,
@@ -1027,9 +997,7 @@ __global__ void __launch_bounds__(256) k_finalize_multi(TableStore ts, const Pri
                                                         const FinReq *__restrict__ fr, uint32_t nfr, uint32_t total,
                                                         int nB, int nE, wv_result *__restrict__ out,
                                                         const unsigned long long *__restrict__ err) {
-    const uint32_t w = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
-    if (w >= total) return;   // whole wave
+    const uint32_t w = blockIdx.x;
     uint32_t a = 0, b = nfr;  // the last request with out0 <= w
     while (b - a > 1) {
         const uint32_t m = (a + b) >> 1;
@@ -1038,9 +1006,8 @@ __global__ void __launch_bounds__(256) k_finalize_multi(TableStore ts, const Pri
     }
     const FinReq f = fr[a];
     const size_t per = (size_t)nB + nE;
-    const wv_result r = finalize_prime(ts, pr + f.base, acc + (size_t)f.base * per, coefs + (size_t)f.base * per,
-                                       lhsmod + 2 * (size_t)f.base, f.n, nB, nE, w - f.out0, err, lane);
-    if (lane == 0) out[w] = r;
+    finalize_prime_wg(ts, pr + f.base, acc + (size_t)f.base * per, coefs + (size_t)f.base * per,
+                      lhsmod + 2 * (size_t)f.base, f.n, nB, nE, w - f.out0, err, out + w);
 }
 
 // Tasks of a request-server step (one thread each): B tasks of the step's nq
@@ -1224,9 +1191,10 @@ hipError_t launch_step_expand(hipStream_t st, const StepSpan *sp, uint32_t nsp, 
 hipError_t launch_finalize_multi(hipStream_t st, TableStore ts, const PrimeRec *pr, const Pair *acc,
                                  const uint64_t *coefs, const uint64_t *lhsmod, const FinReq *fr, uint32_t nfr,
                                  uint32_t total, int nB, int nE, wv_result *out, const unsigned long long *err) {
-    if (too_many((uint64_t)total * 64) || nfr == 0) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_finalize_multi, dim3(blocks_for((uint64_t)total * 64, 256)), dim3(256), 0, st, ts, pr, acc,
-                       coefs, lhsmod, fr, nfr, total, nB, nE, out, err);
+    if (too_many((uint64_t)total * 256) || nfr == 0) return hipErrorInvalidConfiguration;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_multi, dim3(total), dim3(256), 0, st, ts, pr, acc, coefs, lhsmod, fr, nfr, total, nB,
+                       nE, out, err);
     return hipGetLastError();
 }
 
