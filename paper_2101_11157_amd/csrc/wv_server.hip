@@ -158,7 +158,8 @@ hipStream_t stream_of(const wv_server *s, int k) { return k == 0 ? s->c->stream 
 // derived ladders' 61,597 sums per prime near 1e11, 136 primes, so that the
 // configured step_terms (2^38 by default, about 88 such primes) sets the
 // step, not this cap (at 2^22 it did: 68 primes, 2 % less throughput on the
-// serving trace for half the median latency).
+// serving trace for a third less median latency).  Half of it while a
+// request with little work left is active (launch_step).
 constexpr uint64_t kMaxStepTasks = 1ull << 23;
 // Upload staging per half at creation (it grows for larger prime lists).
 constexpr size_t kUploadBytes = 1u << 20;
@@ -359,7 +360,14 @@ int launch_step(wv_server *s, int sk, bool *launched) {
     std::stable_sort(cand.begin(), cand.end(), [](const Request *a, const Request *b) {
         return (a->n - a->next) * a->tpp < (b->n - b->next) * b->tpp;
     });
-    const uint64_t max_q = std::max<uint64_t>(1, kMaxStepTasks / (uint64_t)s->NS);
+    // While a request with little work left is among them (a single prime,
+    // a short interval: at most an eighth of the step budget), steps take
+    // half the task cap, so that it completes sooner; otherwise the full cap
+    // lets the term budget set the step.
+    const Request *least = cand.front();
+    const bool small_left = (double)(least->n - least->next) * least->tpp * 8.0 <= (double)s->step_terms;
+    const uint64_t task_cap = small_left ? kMaxStepTasks / 2 : kMaxStepTasks;
+    const uint64_t max_q = std::max<uint64_t>(1, task_cap / (uint64_t)s->NS);
     std::vector<uint32_t> give(cand.size(), 0);
     double budget = (double)s->step_terms;
     uint64_t nq = 0;
