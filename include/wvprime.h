@@ -425,7 +425,9 @@ int wv_server_submit_primes(wv_server *srv, const uint64_t *primes, size_t n, ui
  * its results become available in the call that completes that step
  * (wv_server_result says WV_EBUSY until then).  A step holds about
  * step_terms terms (default 2^38, about 45 ms of the whole GPU at p ~ 1e11)
- * and at most 2^22 sums.  Admission takes requests pending for 2 s or more in
+ * and at most 2^23 sums (2^22 while a request with at most an eighth of
+ * step_terms left is active, so that it completes in a short step).
+ * Admission takes requests pending for 2 s or more in
  * arrival order, then the smallest first (by number of primes), and plans at
  * most 2^24 sums per call; a request that does not fit in the pool waits
  * without blocking others.  A request whose admission fails ends with that error (see
