@@ -45,6 +45,7 @@
 #include <new>
 #include <vector>
 
+#include "step_share.hpp"
 #include "wv_ctx.hpp"
 
 using namespace wv;
@@ -154,13 +155,6 @@ namespace {
 
 hipStream_t stream_of(const wv_server *s, int k) { return k == 0 ? s->c->stream : s->own; }
 
-// Tasks per step at most (whole primes of nB + nE sums each): with the
-// derived ladders' 61,597 sums per prime near 1e11, 136 primes, so that the
-// configured step_terms (2^38 by default, about 88 such primes) sets the
-// step, not this cap (at 2^22 it did: 68 primes, 2 % less throughput on the
-// serving trace for a third less median latency).  Half of it while a
-// request with little work left is active (launch_step).
-constexpr uint64_t kMaxStepTasks = 1ull << 23;
 // Upload staging per half at creation (it grows for larger prime lists).
 constexpr size_t kUploadBytes = 1u << 20;
 
@@ -344,11 +338,12 @@ int readmit_all(wv_server *s) {
     return WV_OK;
 }
 
-// Chooses the next step's primes on the host -- an even share of the budget
-// for every active request with primes left, then what is left of the budget
-// to the smallest remaining work first, at least one prime per step -- and
-// launches the step with buffer set k on its stream.  The requests' counters
-// advance now.  *launched is false when no request has primes left.
+// Chooses the next step's primes on the host (step_share: an even share of
+// the budget for every active request with primes left, then what is left of
+// the budget to the smallest remaining work first, at least one prime per
+// step) and launches the step with buffer set k on its stream.  The
+// requests' counters advance now.  *launched is false when no request has
+// primes left.
 int launch_step(wv_server *s, int sk, bool *launched) {
     StepSet &ss = s->set[sk];
     wv_ctx *c = s->c;
@@ -360,35 +355,10 @@ int launch_step(wv_server *s, int sk, bool *launched) {
     std::stable_sort(cand.begin(), cand.end(), [](const Request *a, const Request *b) {
         return (a->n - a->next) * a->tpp < (b->n - b->next) * b->tpp;
     });
-    // While a request with little work left is among them (a single prime,
-    // a short interval: at most an eighth of the step budget), steps take
-    // half the task cap, so that it completes sooner; otherwise the full cap
-    // lets the term budget set the step.
-    const Request *least = cand.front();
-    const bool small_left = (double)(least->n - least->next) * least->tpp * 8.0 <= (double)s->step_terms;
-    const uint64_t task_cap = small_left ? kMaxStepTasks / 2 : kMaxStepTasks;
-    const uint64_t max_q = std::max<uint64_t>(1, task_cap / (uint64_t)s->NS);
+    std::vector<ShareReq> share(cand.size());
+    for (size_t k = 0; k < cand.size(); k++) share[k] = ShareReq{(uint64_t)(cand[k]->n - cand[k]->next), cand[k]->tpp};
     std::vector<uint32_t> give(cand.size(), 0);
-    double budget = (double)s->step_terms;
-    uint64_t nq = 0;
-    const double even = budget / cand.size();
-    for (size_t k = 0; k < cand.size(); k++) {
-        const Request *r = cand[k];
-        const uint64_t g = std::min<uint64_t>({(uint64_t)(r->n - r->next), (uint64_t)(even / r->tpp), max_q - nq});
-        give[k] = (uint32_t)g;
-        nq += g;
-        budget -= g * r->tpp;
-    }
-    for (size_t k = 0; k < cand.size() && nq < max_q; k++) {
-        const Request *r = cand[k];
-        const uint64_t left = r->n - r->next - give[k];
-        if (!left) continue;
-        if (budget < r->tpp && nq > 0) break;
-        const uint64_t g = std::min<uint64_t>({left, std::max<uint64_t>(1, (uint64_t)(budget / r->tpp)), max_q - nq});
-        give[k] += (uint32_t)g;
-        nq += g;
-        budget -= g * r->tpp;
-    }
+    const uint64_t nq = step_share(share.data(), share.size(), (double)s->step_terms, (uint64_t)s->NS, give.data());
     // spans in candidate order; requests whose last primes this step holds
     // are finalized at its end
     std::vector<StepSpan> spans;

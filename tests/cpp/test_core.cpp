@@ -7,6 +7,7 @@
 #include <random>
 #include <vector>
 #include "mont.hpp"
+#include "step_share.hpp"
 #include "sum_core.hpp"
 
 using u128 = unsigned __int128;
@@ -352,6 +353,67 @@ int main() {
                     checks++;
                 }
         }
+    }
+    // Server step composition: the cap, the budget, the even share, at least
+    // one prime, and no prime left out that the budget and the cap allow.
+    {
+        std::uniform_real_distribution<double> lg(0.0, 1.0);
+        auto fail = [](const char *what, int t) {
+            printf("FAIL step_share %s case %d\n", what, t);
+            return 1;
+        };
+        for (int t = 0; t < 20000; t++) {
+            const size_t n = 1 + rng() % 40;
+            const double step_terms = std::ldexp(1.0, 20 + (int)(rng() % 21));
+            const uint64_t ns_choice[] = {1, 12, 61597, (1ull << 23) + 5, 1 + rng() % 100000};
+            const uint64_t NS = ns_choice[rng() % 5];
+            std::vector<ShareReq> c(n);
+            for (auto &r : c) {
+                r.left = (rng() % 3 == 0) ? 1 : 1 + rng() % ((rng() % 2) ? 100 : 65536);
+                r.tpp = std::pow(10.0, 3.0 + 8.0 * lg(rng));
+            }
+            std::sort(c.begin(), c.end(),
+                      [](const ShareReq &a, const ShareReq &b) { return (double)a.left * a.tpp < (double)b.left * b.tpp; });
+            std::vector<uint32_t> give(n, 0xDEADu);
+            const uint64_t nq = step_share(c.data(), n, step_terms, NS, give.data());
+            const uint64_t cap = ((double)c[0].left * c[0].tpp * 8.0 <= step_terms) ? (1ull << 22) : (1ull << 23);
+            const uint64_t max_q = std::max<uint64_t>(1, cap / NS);
+            uint64_t sum = 0;
+            double terms = 0;
+            for (size_t k = 0; k < n; k++) {
+                if (give[k] > c[k].left) return fail("more than left", t);
+                sum += give[k];
+                terms += give[k] * c[k].tpp;
+            }
+            if (sum != nq) return fail("count", t);
+            if (nq < 1 || nq > max_q) return fail("cap", t);
+            if (nq > 1 && terms > step_terms * (1 + 1e-9)) return fail("budget", t);
+            if (nq < max_q) {
+                for (size_t k = 0; k < n; k++) {
+                    const uint64_t even = (uint64_t)(step_terms / (double)n / c[k].tpp);
+                    if (give[k] < std::min<uint64_t>(c[k].left, even)) return fail("even share", t);
+                }
+                for (size_t k = 0; k < n; k++)
+                    if (give[k] < c[k].left) {
+                        if (step_terms - terms >= c[k].tpp * (1 + 1e-9)) return fail("left out", t);
+                        break;
+                    }
+            }
+            checks += 5;
+        }
+        // a single prime near 1e11 beside a long interval: the cap halves
+        // (68 primes of 61,597 sums), and without it the step reaches 136
+        std::vector<ShareReq> c = {{1, 4.9e9}, {40000, 4.9e9}};
+        std::vector<uint32_t> give(2);
+        if (step_max_primes(c[0], std::ldexp(1.0, 38), 61597) != 68) return fail("small cap", -1);
+        if (step_max_primes(c[1], std::ldexp(1.0, 38), 61597) != 136) return fail("full cap", -1);
+        const uint64_t nq = step_share(c.data(), 2, std::ldexp(1.0, 45), 61597, give.data());
+        if (nq != 68 || give[0] != 1 || give[1] != 67) return fail("fixed case", -1);
+        // one prime over the whole budget still makes a step of one prime
+        std::vector<ShareReq> big = {{3, 1e12}};
+        if (step_share(big.data(), 1, std::ldexp(1.0, 38), 61597, give.data()) != 1 || give[0] != 1)
+            return fail("oversized prime", -1);
+        checks += 6;
     }
     printf("OK %ld\n", checks);
     return 0;
